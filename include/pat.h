@@ -1,0 +1,153 @@
+/*
+ * pat.h -- C-ABI of the MI355X (gfx950) photoacoustic-tomography operator library.
+ *
+ * The library evaluates the forward operator A of eq. (3) (Sec. 2.1): the 2D
+ * wave initial-value problem of eq. (1) with constant speed of sound c, zero
+ * initial velocity and initial pressure f, observed as the boundary traces of
+ * eq. (2) at detectors on a circle of radius R (or an arc of it, the limited
+ * view of Sec. 2.1), and its exact discrete adjoint A* (the plain matrix
+ * transpose), which the gradient-based reconstructions of eq. (4) and eq. (5)
+ * call once per iteration (Sec. 2.2).  The discretisation is the "polar grid
+ * in the spectral domain" of Sec. 2.4.1:
+ *
+ *   F(n,l) = h^2 sum m_ij f_ij exp(-i lam_n (x_j cos psi_l + y_i sin psi_l))   (polar pixel spectrum)
+ *   F_k(n) = angular Fourier coefficients of F(n, .), |k| <= K
+ *   b_k(n) = i^k J_k(lam_n R) W_n F_k(n),  W_n = lam_n dlam / (2 pi)
+ *   B_k(j) = sum_n b_k(n) cos(c lam_n t_j)
+ *   g(d,j) = Re sum_k e^{i k theta_d} B_k(j) + kappa h^2 sum m f,  kappa = dlam^2/(24 pi)
+ *
+ * with lam_n = n dlam (n = 1..n_lam), dlam = pi/(M c dt), M the smallest
+ * 2^a 3^b >= sigma_t T, lam_{n_lam} <= pi/h, pixel centres x_j = -1 + (j+1/2) h,
+ * h = 2/N, mask m_ij = [x_j^2 + y_i^2 < rho_s^2], detectors
+ * theta_d = theta_c - alpha/2 + (d+1/2) alpha/D, times t_j = j dt (j = 1..T).
+ *
+ * Layouts (all row-major, FP32, caller-owned device memory):
+ *   image f : [batch][N][N]   row i is y_i (increasing), column j is x_j
+ *   data  g : [batch][D][T]   detector-major, column j-1 is t_j
+ *
+ * Execution model: every compute call is asynchronous and stream-ordered on
+ * the HIP stream passed in (`stream`, a hipStream_t; NULL = default stream).
+ * No call allocates, frees or synchronises.  All argument checks run on the
+ * host before anything is enqueued, so an error return means nothing was
+ * launched.  Plans own their device tables; the caller owns every tensor and
+ * the workspace.  A plan may be used concurrently from several streams only
+ * with distinct workspaces.
+ */
+#ifndef PAT_H
+#define PAT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define PAT_OK               0
+#define PAT_ERR_ARG         -1   /* bad argument: null pointer, size out of range, batch > capacity */
+#define PAT_ERR_UNSUPPORTED -2   /* geometry outside what the kernels handle (LDS or size limits) */
+#define PAT_ERR_WORKSPACE   -3   /* workspace missing or smaller than pat_workspace_size()       */
+#define PAT_ERR_HIP         -4   /* a HIP runtime call failed (launch, copy, event)               */
+#define PAT_ERR_ALLOC       -5   /* device allocation failed while building a plan                */
+
+typedef struct pat_plan pat_plan;
+
+/* Geometry and discretisation of one operator (eq. (1)-(3), Sec. 2.1 and 2.4.1). */
+typedef struct {
+    int    n;                 /* grid side N >= 16; cell-centred pixels on [-1,1]^2, h = 2/N         */
+    double support_r;         /* rho_s in (0, det_r]: pixels with x^2+y^2 >= rho_s^2 are zero (1.0) */
+    double det_r;             /* R > 0: detector circle radius (1.0)                                  */
+    int    n_det;             /* D >= 1                                                               */
+    double arc_center;        /* theta_c [rad] (-pi/2: the array at the bottom)                       */
+    double arc_span;          /* alpha in (0, 2 pi]; 2 pi = full circle                               */
+    int    n_t;               /* T >= 1; t_j = j * dt for j = 1..T                                    */
+    double dt;                /* > 0                                                                  */
+    double c;                 /* constant speed of sound > 0                                          */
+    double lambda_oversample; /* sigma_t >= 1 (2.0); radial frequency step dlam = pi/(M c dt)         */
+    int    em_correction;     /* 1: add the rank-1 endpoint term kappa*h^2*sum(m f) (default 1)       */
+    int    max_batch;         /* capacity of the batch dimension (>= 1); sizes pat_workspace_size     */
+} pat_plan_desc;
+
+/* What a plan derived (pat_plan_query). */
+typedef struct {
+    int    M;                 /* length of the radial/temporal cosine grid                            */
+    double dlam;              /* radial frequency step                                                */
+    int    n_lam;             /* number of radial frequencies lam_n = n*dlam, n = 1..n_lam            */
+    int    K;                 /* highest angular mode, ceil(z + 10 z^(1/3)), z = lam_max R            */
+    int    n_psi;             /* uniform angular grid size (smallest 2^a3^b >= 2K+2, multiple of 4)    */
+    double kappa;             /* endpoint-term coefficient dlam^2/(24 pi), 0 if disabled              */
+    int    n_grid;            /* oversampled spectral grid side used for the polar interpolation      */
+    int    n_points;          /* polar points evaluated per image (half plane, per-ring angular grids) */
+    int    len_czt;           /* FFT length of the detector-angle chirp-z transform                   */
+    size_t workspace_per_instance; /* workspace bytes per batch instance                              */
+    size_t table_bytes;       /* device bytes held by the plan's tables                               */
+} pat_plan_info;
+
+/* Build a plan: derive sizes, compute every table in FP64 on the host, upload
+ * them as FP32 device tables (hipMalloc; freed by pat_plan_destroy).  The
+ * current HIP device at creation is the plan's device.  Returns PAT_OK and
+ * sets *out, or an error code and leaves *out untouched. */
+int  pat_plan_create(const pat_plan_desc* desc, pat_plan** out);
+int  pat_plan_query(const pat_plan* plan, pat_plan_info* out);
+void pat_plan_destroy(pat_plan* plan);
+
+/* Workspace bytes a forward or adjoint call needs for `batch` instances
+ * (0 if plan is NULL or batch < 1).  The workspace is scratch only: its
+ * contents on entry are ignored and on exit are unspecified. */
+size_t pat_workspace_size(const pat_plan* plan, int batch);
+
+/* g = A f for `batch` images (1 <= batch <= max_batch).
+ * f: device [batch][N][N] FP32 (read); g: device [batch][D][T] FP32 (written).
+ * ws: device workspace of at least pat_workspace_size(plan, batch) bytes.
+ * Errors: PAT_ERR_ARG (null pointer, batch out of range), PAT_ERR_WORKSPACE,
+ * PAT_ERR_HIP (launch failure). */
+int  pat_forward(const pat_plan* plan, const float* f, float* g, int batch,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* f = A* g (exact transpose of pat_forward under the plain Euclidean inner
+ * products of R^{N x N} and R^{D x T}; this is the gradient of 0.5||A f - g||^2
+ * with respect to f at residual g, Sec. 2.2).
+ * g: device [batch][D][T] FP32 (read); f: device [batch][N][N] FP32 (written).
+ * Same workspace and error rules as pat_forward. */
+int  pat_adjoint(const pat_plan* plan, const float* g, float* f, int batch,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* Smoothed isotropic total variation of eq. (4)/(5) (Sec. 2.1, 2.2):
+ *   TV_eps(f) = sum_{i,j} sqrt((f_{i,j+1}-f_{i,j})^2 + (f_{i+1,j}-f_{i,j})^2 + eps^2)
+ * with forward differences and zero difference across the last row/column
+ * (Neumann boundary).  Writes grad = d TV_eps / d f ([batch][N][N]) and, if
+ * tv is not NULL, tv[b] = TV_eps(f_b) ([batch], FP32).
+ * Errors: PAT_ERR_ARG (null f/grad, n < 2, batch < 1, eps <= 0), PAT_ERR_HIP. */
+int  pat_tv_grad(const float* f, float* grad, float* tv, int n, int batch, float eps,
+                 void* stream);
+
+/* One projected-gradient step of eq. (4) with smoothed TV, fused:
+ *   f <- max(f - tau * (adj + lambda * tvgrad), 0)     (elementwise, in place on f)
+ * f, adj, tvgrad: device [count] FP32.  Errors: PAT_ERR_ARG, PAT_ERR_HIP. */
+int  pat_pgd_update(float* f, const float* adj, const float* tvgrad, long count,
+                    float tau, float lambda, void* stream);
+
+/* Residual r = A f - g_meas computed in place on `g` (g holds A f on entry),
+ * and, if sq is not NULL, sq[b] = 0.5 * ||r_b||^2 per instance (FP32).
+ * g, g_meas: device [batch][count_per] FP32.  Errors: PAT_ERR_ARG, PAT_ERR_HIP. */
+int  pat_residual(float* g, const float* g_meas, float* sq, long count_per, int batch,
+                  void* stream);
+
+/* Host-only helpers (no GPU needed).
+ * pat_plan_derive: the sizes pat_plan_create would derive for `desc`, without
+ * building tables (fields M, dlam, n_lam, K, n_psi, kappa, n_grid, len_czt are
+ * set, the rest are 0).  Same error codes as pat_plan_create's checks.
+ * pat_bessel_jn_table: out[k] = J_k(x) for k = 0..kmax in FP64 by Miller's
+ * backward recurrence (the routine behind the plan's radial weights
+ * i^k J_k(lam_n R) of the mode form).  PAT_ERR_ARG on kmax < 0, NULL out or
+ * non-finite x. */
+int  pat_plan_derive(const pat_plan_desc* desc, pat_plan_info* out);
+int  pat_bessel_jn_table(int kmax, double x, double* out);
+
+/* Human-readable text of a status code (static storage). */
+const char* pat_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

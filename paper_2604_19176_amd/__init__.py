@@ -1,0 +1,187 @@
+"""MI355X (gfx950) library for the circular-geometry PAT operator pair.
+
+The forward operator A maps an initial pressure image f (eq. (1), Sec. 2.1) to
+the pressure traces g at detectors on a circle or arc (eq. (2)); A* is its
+exact discrete transpose, the operator the gradients of eq. (4) and eq. (5)
+need (Sec. 2.2).  All computation runs in the HIP kernels of libpat.so; this
+package only marshals torch tensors (device memory and streams) into the C-ABI.
+
+    plan = PatPlan(geometry, max_batch=B)        # tables built once (FP64 on the host)
+    g = plan.forward(f)                           # f: (B, N, N) or (N, N) float32 on the GPU
+    f_adj = plan.adjoint(g)
+    g = pat_operator(plan, f)                     # autograd: backward runs A*
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (PatError, pat_plan_desc, pat_status_string, pat_plan_create, pat_plan_query,  # noqa: F401
+                   pat_plan_destroy, pat_workspace_size, pat_forward, pat_adjoint, pat_tv_grad,
+                   pat_pgd_update, pat_residual, pat_plan_derive, pat_bessel_jn_table)
+
+__all__ = ["PatPlan", "pat_operator", "PatOperatorFn", "tv_grad", "pgd_update", "residual", "PatError",
+           "desc_from_geometry", "library_path"]
+
+
+def library_path() -> str:
+    return _lib.LIB_PATH
+
+
+def desc_from_geometry(geom, max_batch: int = 1) -> pat_plan_desc:
+    """pat_plan_desc from any object with the Geometry fields."""
+    return pat_plan_desc(int(geom.n), float(geom.support_r), float(geom.det_r), int(geom.n_det),
+                         float(geom.arc_center), float(geom.arc_span), int(geom.n_t), float(geom.dt),
+                         float(geom.c), float(geom.lambda_oversample), int(geom.em_correction),
+                         int(max_batch))
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_tensor(t, name, shape_tail, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a GPU tensor (got device %s)" % (name, t.device))
+    if device is not None and t.device != device:
+        raise ValueError("%s is on %s but the plan lives on %s" % (name, t.device, device))
+    if t.dtype != torch.float32:
+        raise TypeError("%s must be float32 (got %s)" % (name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if tuple(t.shape[-len(shape_tail):]) != tuple(shape_tail) or t.dim() not in (len(shape_tail),
+                                                                                  len(shape_tail) + 1):
+        raise ValueError("%s must have shape %s or (batch,) + %s, got %s"
+                         % (name, tuple(shape_tail), tuple(shape_tail), tuple(t.shape)))
+    return 1 if t.dim() == len(shape_tail) else int(t.shape[0])
+
+
+class PatPlan:
+    """A plan for one geometry: device tables plus a workspace for up to
+    `max_batch` images, on the current CUDA/HIP device."""
+
+    def __init__(self, geom, max_batch: int = 1, device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("PatPlan needs a GPU: torch.cuda.is_available() is False")
+        _lib.load()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        self.geom = geom
+        self.max_batch = int(max_batch)
+        with torch.cuda.device(self.device):
+            self.handle = pat_plan_create(desc_from_geometry(geom, max_batch))
+        self.info = pat_plan_query(self.handle)
+        self._ws = None
+
+    # -- sizes ------------------------------------------------------------------
+    @property
+    def image_shape(self):
+        return (self.geom.n, self.geom.n)
+
+    @property
+    def data_shape(self):
+        return (self.geom.n_det, self.geom.n_t)
+
+    def workspace_bytes(self, batch: int) -> int:
+        return pat_workspace_size(self.handle, batch)
+
+    def workspace(self, batch: int):
+        need = self.workspace_bytes(batch)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(max(need, self.workspace_bytes(self.max_batch)), dtype=torch.uint8,
+                                   device=self.device)
+        return self._ws
+
+    # -- operators ----------------------------------------------------------------
+    def forward(self, f, out=None):
+        """g = A f.  f: (N, N) or (B, N, N) float32 contiguous on the plan's GPU."""
+        B = _check_tensor(f, "f", self.image_shape, self.device)
+        shape = self.data_shape if f.dim() == 2 else (B,) + self.data_shape
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=self.device)
+        else:
+            _check_tensor(out, "out", self.data_shape, self.device)
+        ws = self.workspace(B)
+        pat_forward(self.handle, f.data_ptr(), out.data_ptr(), B, ws.data_ptr(), ws.numel(),
+                    _stream(self.device))
+        return out
+
+    def adjoint(self, g, out=None):
+        """f = A* g.  g: (D, T) or (B, D, T) float32 contiguous on the plan's GPU."""
+        B = _check_tensor(g, "g", self.data_shape, self.device)
+        shape = self.image_shape if g.dim() == 2 else (B,) + self.image_shape
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=self.device)
+        else:
+            _check_tensor(out, "out", self.image_shape, self.device)
+        ws = self.workspace(B)
+        pat_adjoint(self.handle, g.data_ptr(), out.data_ptr(), B, ws.data_ptr(), ws.numel(),
+                    _stream(self.device))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            pat_plan_destroy(self.handle)
+            self.handle = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PatOperatorFn(torch.autograd.Function):
+    """A as an autograd Function: forward runs pat_forward, backward runs
+    pat_adjoint on the incoming gradient (the gradient of <A f, w> is A* w)."""
+
+    @staticmethod
+    def forward(ctx, f, plan):
+        ctx.plan = plan
+        return plan.forward(f.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_g):
+        return ctx.plan.adjoint(grad_g.contiguous()), None
+
+
+def pat_operator(plan: PatPlan, f):
+    """Differentiable g = A f (backward = A* on the GPU)."""
+    return PatOperatorFn.apply(f, plan)
+
+
+def tv_grad(f, eps: float = 1e-3, with_value: bool = False):
+    """Gradient (and optionally the value per image) of the smoothed TV of eq. (4)."""
+    if f.dim() == 2:
+        n, B = f.shape[-1], 1
+    else:
+        n, B = f.shape[-1], f.shape[0]
+    _check_tensor(f, "f", (n, n), f.device)
+    grad = torch.empty_like(f)
+    tv = torch.empty(B, dtype=torch.float32, device=f.device) if with_value else None
+    pat_tv_grad(f.data_ptr(), grad.data_ptr(), tv.data_ptr() if tv is not None else None, n, B, eps,
+                _stream(f.device))
+    return (grad, tv) if with_value else grad
+
+
+def pgd_update(f, adj, tvg, tau: float, lam: float):
+    """In place: f <- max(f - tau (adj + lam tvg), 0)."""
+    pat_pgd_update(f.data_ptr(), adj.data_ptr(), tvg.data_ptr() if tvg is not None else None, f.numel(),
+                   tau, lam, _stream(f.device))
+    return f
+
+
+def residual(g, g_meas, with_value: bool = False):
+    """In place: g <- g - g_meas; optionally 0.5 ||r||^2 per instance."""
+    B = g.shape[0] if g.dim() == 3 else 1
+    per = g.numel() // B
+    sq = torch.empty(B, dtype=torch.float32, device=g.device) if with_value else None
+    pat_residual(g.data_ptr(), g_meas.data_ptr(), sq.data_ptr() if sq is not None else None, per, B,
+                 _stream(g.device))
+    return (g, sq) if with_value else g
+

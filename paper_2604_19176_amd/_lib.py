@@ -1,0 +1,150 @@
+"""ctypes binding of libpat.so (include/pat.h).  Argument marshalling only.
+
+Every function here has the name of the C entry point it calls.  The library
+is the in-tree build (paper_2604_19176_amd/libpat.so); if it is missing the
+import fails loudly -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpat.so")
+HEADER = os.path.join(HERE, "..", "include", "pat.h")
+
+PAT_OK = 0
+PAT_ERR_ARG = -1
+PAT_ERR_UNSUPPORTED = -2
+PAT_ERR_WORKSPACE = -3
+PAT_ERR_HIP = -4
+PAT_ERR_ALLOC = -5
+
+
+class PatError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s failed: %s (%d)" % (where, pat_status_string(status), status))
+
+
+class pat_plan_desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("support_r", ctypes.c_double), ("det_r", ctypes.c_double),
+                ("n_det", ctypes.c_int), ("arc_center", ctypes.c_double), ("arc_span", ctypes.c_double),
+                ("n_t", ctypes.c_int), ("dt", ctypes.c_double), ("c", ctypes.c_double),
+                ("lambda_oversample", ctypes.c_double), ("em_correction", ctypes.c_int),
+                ("max_batch", ctypes.c_int)]
+
+
+class pat_plan_info(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int), ("dlam", ctypes.c_double), ("n_lam", ctypes.c_int),
+                ("K", ctypes.c_int), ("n_psi", ctypes.c_int), ("kappa", ctypes.c_double),
+                ("n_grid", ctypes.c_int), ("n_points", ctypes.c_int), ("len_czt", ctypes.c_int),
+                ("workspace_per_instance", ctypes.c_size_t), ("table_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def load():
+    """Load libpat.so once; raise ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libpat.so not built at %s; run __graft_entry__.build() or "
+                          "python paper_2604_19176_amd/build.py" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, sz, ci, cf, cl = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_float, ctypes.c_long
+    P = ctypes.POINTER
+    sig = {
+        "pat_plan_create": (ci, [P(pat_plan_desc), P(vp)]),
+        "pat_plan_query": (ci, [vp, P(pat_plan_info)]),
+        "pat_plan_destroy": (None, [vp]),
+        "pat_workspace_size": (sz, [vp, ci]),
+        "pat_forward": (ci, [vp, vp, vp, ci, vp, sz, vp]),
+        "pat_adjoint": (ci, [vp, vp, vp, ci, vp, sz, vp]),
+        "pat_tv_grad": (ci, [vp, vp, vp, ci, ci, cf, vp]),
+        "pat_pgd_update": (ci, [vp, vp, vp, cl, cf, cf, vp]),
+        "pat_residual": (ci, [vp, vp, vp, cl, ci, vp]),
+        "pat_plan_derive": (ci, [P(pat_plan_desc), P(pat_plan_info)]),
+        "pat_bessel_jn_table": (ci, [ci, ctypes.c_double, P(ctypes.c_double)]),
+        "pat_status_string": (ctypes.c_char_p, [ci]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def declared_functions():
+    """Names of the functions include/pat.h declares (for the export test)."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pat_[a-z0-9_]+)\s*\(", text)))
+
+
+def _check(rc, where):
+    if rc != PAT_OK:
+        raise PatError(rc, where)
+
+
+# -- thin wrappers with the C names -------------------------------------------
+
+def pat_status_string(status: int) -> str:
+    return load().pat_status_string(int(status)).decode()
+
+
+def pat_plan_derive(desc: pat_plan_desc) -> pat_plan_info:
+    info = pat_plan_info()
+    _check(load().pat_plan_derive(ctypes.byref(desc), ctypes.byref(info)), "pat_plan_derive")
+    return info
+
+
+def pat_bessel_jn_table(kmax: int, x: float):
+    out = (ctypes.c_double * (kmax + 1))()
+    _check(load().pat_bessel_jn_table(int(kmax), float(x), out), "pat_bessel_jn_table")
+    return list(out)
+
+
+def pat_plan_create(desc: pat_plan_desc) -> int:
+    h = ctypes.c_void_p()
+    _check(load().pat_plan_create(ctypes.byref(desc), ctypes.byref(h)), "pat_plan_create")
+    return h.value
+
+
+def pat_plan_query(plan: int) -> pat_plan_info:
+    info = pat_plan_info()
+    _check(load().pat_plan_query(plan, ctypes.byref(info)), "pat_plan_query")
+    return info
+
+
+def pat_plan_destroy(plan: int) -> None:
+    load().pat_plan_destroy(plan)
+
+
+def pat_workspace_size(plan: int, batch: int) -> int:
+    return int(load().pat_workspace_size(plan, int(batch)))
+
+
+def pat_forward(plan, f_ptr, g_ptr, batch, ws_ptr, ws_bytes, stream) -> None:
+    _check(load().pat_forward(plan, f_ptr, g_ptr, int(batch), ws_ptr, int(ws_bytes), stream), "pat_forward")
+
+
+def pat_adjoint(plan, g_ptr, f_ptr, batch, ws_ptr, ws_bytes, stream) -> None:
+    _check(load().pat_adjoint(plan, g_ptr, f_ptr, int(batch), ws_ptr, int(ws_bytes), stream), "pat_adjoint")
+
+
+def pat_tv_grad(f_ptr, grad_ptr, tv_ptr, n, batch, eps, stream) -> None:
+    _check(load().pat_tv_grad(f_ptr, grad_ptr, tv_ptr, int(n), int(batch), float(eps), stream), "pat_tv_grad")
+
+
+def pat_pgd_update(f_ptr, adj_ptr, tvg_ptr, count, tau, lam, stream) -> None:
+    _check(load().pat_pgd_update(f_ptr, adj_ptr, tvg_ptr, int(count), float(tau), float(lam), stream),
+           "pat_pgd_update")
+
+
+def pat_residual(g_ptr, gm_ptr, sq_ptr, count_per, batch, stream) -> None:
+    _check(load().pat_residual(g_ptr, gm_ptr, sq_ptr, int(count_per), int(batch), stream), "pat_residual")

@@ -1,0 +1,116 @@
+// pat_internal.hpp -- plan layout shared by the host plan builder and the gfx950 kernels.
+//
+// A plan's device tables are FP32 (or int) copies of quantities computed in FP64
+// on the host at plan creation.  Kernels receive a PlanDev by value.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pat {
+
+// ES ("exponential of semicircle") interpolation kernel of the polar
+// interpolation: phi(t) = exp(beta (sqrt(1 - (2t/w)^2) - 1)) for |t| <= w/2.
+constexpr int kEsWidth = 8;
+constexpr double kEsBeta = 2.30 * kEsWidth;
+
+constexpr int kMaxStages = 24;
+
+// One complex FFT length n = 2^a 3^b: Stockham stages of radix 4, 2 or 3.
+struct FftDev {
+    int n;
+    int nst;
+    int tw;                        // offset of this length's twiddles e^{-2 pi i e/n}, e = 0..n-1
+    int pad;
+    unsigned char rad[kMaxStages];
+};
+
+struct PlanDev {
+    // sizes
+    int N;         // image side
+    int Ng;        // oversampled spectral grid side (even, 2^a3^b >= 2N)
+    int Hy;        // stored half-spectrum rows: m_y = -4 .. Ng/2+4  (Ng/2 + 9 rows)
+    int nlam;      // radial frequencies
+    int K;         // highest angular mode
+    int Kp;        // K + 1 (row stride of mode arrays)
+    int M;         // cosine grid: FFT length 2M
+    int T;         // time samples
+    int D;         // detectors
+    int L;         // chirp-z FFT length
+    int npts;      // half-plane polar points (sum over rings of Npsi(n)/2)
+    int NB;        // interpolation bands (rows of footprint bases): Ng/2 + 2
+    float kappa;   // endpoint term coefficient
+    float h2;      // h^2
+    // image-side tables
+    const float* deap;      // [N]: h / phihat(k - N/2), k = 0..N-1 (one factor per axis)
+    const int2* mask_rows;  // [N]: row i keeps columns jlo <= j < jhi
+    // polar points, ring order (ring n = 1..nlam occupies [ring_off[n-1], ring_off[n]))
+    const float4* pt_geo;   // (bx mod Ng as int bits, r0 = by + 4 as int bits, fx, fy)
+    const float2* pt_phase; // e^{-i pi (s_x + s_y)/Ng}  (half-pixel shift of cell-centred pixels)
+    const int* ring_off;    // [nlam + 1]
+    const int* ring_K;      // [nlam]   K_n: modes kept on ring n
+    const int* ring_fft;    // [nlam]   FFT descriptor of Npsi(n)
+    const int* ring_joff;   // [nlam]   offset of ring n in Jw
+    const float* Jw;        // ragged: J_k(lam_n R) W_n / Npsi(n), k = 0..K_n
+    const int* mode_nmin;   // [Kp]     first (0-based) ring with K_n >= k
+    // polar points, band order (sorted by (r0, bx)) for the deterministic spread
+    const int* perm;        // [npts]   ring-order index -> band-order slot
+    const float4* bpt_geo;  // [npts]   same fields as pt_geo, band order
+    const int* band_ptr;    // [NB][Ng + 1] CSR: first band-order slot with (r0, bx' >= bx)
+    // chirp-z synthesis over detector angles
+    const float2* czt_pre;  // [Kp]  c_k e^{i k theta_0} w^{k^2}, c_0 = 1, c_k = 2
+    const float2* czt_post; // [D]   w^{d^2}
+    const float2* czt_vhat; // [L]   FFT_L of the chirp filter w^{-m^2}, divided by L
+    // FFTs
+    const FftDev* ffts;
+    const float2* tw;
+    int fft_grid;  // length Ng
+    int fft_dct;   // length 2M
+    int fft_czt;   // length L
+    int pad0;
+};
+
+// Launch shapes chosen at plan creation (the autotuner may overwrite them).
+struct LaunchCfg {
+    int col_np;      // packed column pairs per column-pass workgroup
+    int row_rpb;     // rows per row-pass workgroup
+    int dct_mt;      // modes per DCT workgroup
+    int czt_tt;      // time samples per chirp-z workgroup
+    int czt_par;     // chirp-z FFTs in flight per workgroup
+    int spr_cb;      // spread: columns per workgroup (multiple of 64)
+    int spr_th;      // spread: rows per workgroup
+    int spr_cap;     // spread: points staged in LDS per chunk
+};
+
+// Per-instance workspace layout (byte offsets; all 256-byte aligned).
+struct WsLayout {
+    size_t x1;       // [Hy][N]   float2   column-pass output / row-pass-adjoint output
+    size_t grid;     // [Hy][Ng]  float2   spectrum / spread target
+    size_t modes;    // [nlam][Kp] float2  ring output / DCT-adjoint output
+    size_t tmodes;   // [T][Kp]   float2   DCT output / chirp-z-adjoint output
+    size_t polar;    // [npts]    float2   spread input (band order)
+    size_t red;      // small FP32 partial sums (mass / data sum)
+    int n_red;       // number of partial sums
+    size_t bytes;    // total per instance
+};
+
+}  // namespace pat
+
+struct pat_plan {
+    pat::PlanDev dev;
+    pat::LaunchCfg cfg;
+    pat::WsLayout ws;
+    int device;
+    int max_batch;
+    int n_psi_uniform;
+    int M;
+    double dlam;
+    double kappa;
+    int n_psi_max;
+    size_t table_bytes;
+    void* table_mem;        // one device allocation holding every table
+    int n_col_tiles;        // column-pass tiles (mass partials)
+    int n_time_tiles;       // chirp-z tiles (data-sum partials)
+    int thr_col, thr_row, thr_ring, thr_dct, thr_czt;  // workgroup sizes of the FFT kernels
+};

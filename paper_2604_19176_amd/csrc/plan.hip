@@ -1,0 +1,596 @@
+// plan.hip -- host-side plan construction: sizes, FP64 tables, device upload.
+//
+// Everything here runs once per plan on the host in FP64; kernels only read
+// the resulting FP32/int tables.
+#include "fft.hpp"
+#include "pat_internal.hpp"
+#include "../../include/pat.h"
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+namespace pat {
+
+using cd = std::complex<double>;
+static const double PI = 3.14159265358979323846264338327950288;
+
+// smallest 2^a 3^b >= x (optionally even / divisible by 4)
+long smooth23(double x, int multiple_of)
+{
+    long best = -1;
+    for (long p2 = 1; p2 < (1L << 40); p2 *= 2) {
+        long p = p2;
+        while ((double)p < x) p *= 3;
+        if (p % multiple_of == 0 && (best < 0 || p < best)) best = p;
+        if ((double)p2 >= x && p2 % multiple_of == 0) break;
+    }
+    return best;
+}
+
+// Radix plan for n = 2^a 3^b: radix-4 stages first, then one radix-2, then radix-3.
+static int radix_plan(long n, unsigned char* rad)
+{
+    int ns = 0;
+    while (n % 4 == 0) { rad[ns++] = 4; n /= 4; }
+    while (n % 2 == 0) { rad[ns++] = 2; n /= 2; }
+    while (n % 3 == 0) { rad[ns++] = 3; n /= 3; }
+    return n == 1 ? ns : -1;
+}
+
+// FP64 Stockham FFT on the host (same decomposition as the device FFT), sign -1.
+static void host_fft(std::vector<cd>& x)
+{
+    const long n = (long)x.size();
+    unsigned char rad[kMaxStages];
+    int ns = radix_plan(n, rad);
+    std::vector<cd> y(n);
+    long Ns = 1;
+    for (int s = 0; s < ns; ++s) {
+        const int R = rad[s];
+        const long nb = n / R;
+        for (long j = 0; j < nb; ++j) {
+            long k = j % Ns;
+            cd v[4];
+            for (int r = 0; r < R; ++r) {
+                double ang = -2.0 * PI * (double)(k * r) / (double)(Ns * R);
+                v[r] = x[j + r * nb] * cd(std::cos(ang), std::sin(ang));
+            }
+            cd o[4];
+            for (int a = 0; a < R; ++a) {
+                o[a] = 0;
+                for (int r = 0; r < R; ++r) {
+                    double ang = -2.0 * PI * (double)((a * r) % R) / R;
+                    o[a] += v[r] * cd(std::cos(ang), std::sin(ang));
+                }
+            }
+            long base = (j - k) * R + k;
+            for (int a = 0; a < R; ++a) y[base + a * Ns] = o[a];
+        }
+        x.swap(y);
+        Ns *= R;
+    }
+}
+
+// J_k(x) for k = 0..kmax by Miller's backward recurrence with the normalisation
+// J_0 + 2 sum J_{2k} = 1, rescaled against overflow.  FP64.
+void bessel_jn_table(int kmax, double x, double* out)
+{
+    if (x == 0.0) {
+        for (int k = 0; k <= kmax; ++k) out[k] = (k == 0) ? 1.0 : 0.0;
+        return;
+    }
+    const double ax = std::fabs(x);
+    int start = (int)std::max<double>(kmax, ax) + 40 + (int)(12.0 * std::cbrt(ax));
+    if (start % 2) ++start;
+    std::vector<double> j(start + 2, 0.0);
+    double jp1 = 0.0, jk = 1e-300, norm = 0.0;
+    for (int k = start; k >= 0; --k) {
+        j[k] = jk;
+        if (k % 2 == 0) norm += (k == 0 ? 1.0 : 2.0) * jk;
+        double jm1 = 2.0 * k / ax * jk - jp1;
+        jp1 = jk;
+        jk = jm1;
+        if (std::fabs(jk) > 1e250) {
+            for (int q = k; q <= start; ++q) j[q] *= 1e-250;
+            norm *= 1e-250;
+            jp1 *= 1e-250;
+            jk *= 1e-250;
+        }
+    }
+    for (int k = 0; k <= kmax; ++k) {
+        double v = j[k] / norm;
+        if (x < 0 && (k % 2)) v = -v;
+        out[k] = v;
+    }
+}
+
+static double es_phi(double t)
+{
+    double z = 2.0 * t / kEsWidth;
+    double q = 1.0 - z * z;
+    return q >= 0 ? std::exp(kEsBeta * (std::sqrt(q) - 1.0)) : 0.0;
+}
+
+// phihat(k) = int_{-w/2}^{w/2} phi(t) cos(2 pi k t / Ng) dt by Gauss-Legendre (FP64).
+static std::vector<double> es_hat(int N, int Ng)
+{
+    const int Q = 256;  // nodes per half interval
+    std::vector<double> xs(Q), ws(Q);
+    for (int i = 0; i < Q; ++i) {  // Newton on Legendre P_Q
+        double x = std::cos(PI * (i + 0.75) / (Q + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1, p1 = x;
+            for (int k = 2; k <= Q; ++k) { double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k; p0 = p1; p1 = p2; }
+            double dp = Q * (x * p1 - p0) / (x * x - 1);
+            double dx = p1 / dp;
+            x -= dx;
+            if (std::fabs(dx) < 1e-16) break;
+        }
+        double p0 = 1, p1 = x;
+        for (int k = 2; k <= Q; ++k) { double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k; p0 = p1; p1 = p2; }
+        double dp = Q * (x * p1 - p0) / (x * x - 1);
+        xs[i] = x;
+        ws[i] = 2.0 / ((1 - x * x) * dp * dp);
+    }
+    const double half = 0.5 * kEsWidth;
+    std::vector<double> out(N);
+    for (int j = 0; j < N; ++j) {
+        double k = j - N / 2;
+        double acc = 0.0;
+        for (int side = 0; side < 2; ++side) {  // [-w/2, 0] and [0, w/2]
+            double a = side ? 0.0 : -half, b = side ? half : 0.0;
+            for (int i = 0; i < Q; ++i) {
+                double t = 0.5 * (a + b) + 0.5 * (b - a) * xs[i];
+                acc += 0.5 * (b - a) * ws[i] * es_phi(t) * std::cos(2 * PI * k * t / Ng);
+            }
+        }
+        out[j] = acc;
+    }
+    return out;
+}
+
+struct Derived {
+    int M, n_lam, K, n_psi, Ng, L;
+    double h, dlam, kappa;
+};
+
+static int derive(const pat_plan_desc* d, Derived* o)
+{
+    if (!d || !o) return PAT_ERR_ARG;
+    if (d->n < 4 || d->n_det < 1 || d->n_t < 1 || d->max_batch < 1) return PAT_ERR_ARG;
+    if (!(d->dt > 0) || !(d->c > 0) || !(d->det_r > 0) || !(d->support_r > 0)) return PAT_ERR_ARG;
+    if (!(d->arc_span > 0) || d->arc_span > 2 * PI + 1e-12) return PAT_ERR_ARG;
+    if (!(d->lambda_oversample >= 1.0) || !std::isfinite(d->arc_center)) return PAT_ERR_ARG;
+    if (d->support_r > d->det_r) return PAT_ERR_ARG;
+    o->h = 2.0 / d->n;
+    o->M = (int)smooth23(d->lambda_oversample * d->n_t, 1);
+    o->dlam = PI / (o->M * d->c * d->dt);
+    o->n_lam = (int)std::floor(o->M * d->c * d->dt / o->h + 1e-9);  // lam_max <= pi/h
+    if (o->n_lam < 1) return PAT_ERR_ARG;
+    double z = o->n_lam * o->dlam * d->det_r;
+    o->K = (int)std::ceil(z + 10.0 * std::cbrt(z) - 1e-9);
+    o->n_psi = (int)smooth23(2.0 * o->K + 2, 4);
+    o->kappa = d->em_correction ? o->dlam * o->dlam / (24.0 * PI) : 0.0;
+    o->Ng = (int)smooth23(2.0 * d->n, 2);
+    o->L = (int)smooth23((double)o->K + d->n_det, 1);
+    // limits of the kernels: every FFT length must fit the LDS plans
+    if (d->n < 16 || o->Ng > 8192 || 2L * o->M > 8192 || o->L > 8192 || o->n_psi > 8192)
+        return PAT_ERR_UNSUPPORTED;
+    if (o->n_lam >= 2 * o->M) return PAT_ERR_UNSUPPORTED;  // cosine grid index n < 2M
+    return PAT_OK;
+}
+
+}  // namespace pat
+
+using namespace pat;
+
+// ----------------------------------------------------------------------------
+
+namespace {
+
+struct TableBuilder {
+    std::vector<unsigned char> host;
+    size_t add(const void* p, size_t bytes)
+    {
+        size_t off = (host.size() + 255) & ~(size_t)255;
+        host.resize(off + bytes);
+        if (bytes) std::memcpy(host.data() + off, p, bytes);
+        return off;
+    }
+    template <class T>
+    size_t add(const std::vector<T>& v) { return add(v.data(), v.size() * sizeof(T)); }
+};
+
+struct FftSet {
+    std::vector<FftDev> descs;
+    std::vector<float2> tw;
+    int get(long n)
+    {
+        for (size_t i = 0; i < descs.size(); ++i)
+            if (descs[i].n == n) return (int)i;
+        FftDev d;
+        std::memset(&d, 0, sizeof(d));
+        d.n = (int)n;
+        d.nst = radix_plan(n, d.rad);
+        d.tw = (int)tw.size();
+        for (long e = 0; e < n; ++e) {
+            double a = -2.0 * PI * (double)e / (double)n;
+            tw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+        }
+        descs.push_back(d);
+        return (int)descs.size() - 1;
+    }
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+namespace pat {
+
+static int fft_threads(int nseq, const FftDev& fd)
+{
+    const int need = (nseq * fft_max_butterflies(fd) + 7) / 8;  // 8 butterflies per thread per stage
+    int t = ((need + 63) / 64) * 64;
+    return std::max(128, std::min(512, t));
+}
+
+// Launch shapes: LDS per workgroup <= 64 KB and every FFT stage fits
+// 512 threads x 8 butterflies.
+int choose_launch(pat_plan* p, const std::vector<FftDev>& fd, int max_ring_bf)
+{
+    const PlanDev& d = p->dev;
+    LaunchCfg& c = p->cfg;
+    const size_t kLds = 64 * 1024;
+    const int kBf = 512 * 8;
+    const FftDev& fg = fd[d.fft_grid];
+    const FftDev& fm = fd[d.fft_dct];
+    const FftDev& fc = fd[d.fft_czt];
+    auto pick = [&](int maxn, size_t bytes_each, int bf_each) {
+        int v = maxn;
+        while (v > 1 && (v * bytes_each > kLds || v * bf_each > kBf)) --v;
+        return (v * bytes_each <= kLds && v * bf_each <= kBf) ? v : 0;
+    };
+    c.col_np = pick(8, sizeof(float2) * d.Ng, fft_max_butterflies(fg));
+    c.row_rpb = pick(8, sizeof(float2) * d.Ng, fft_max_butterflies(fg));
+    c.dct_mt = pick(8, sizeof(float2) * 2 * d.M, fft_max_butterflies(fm));
+    c.czt_tt = 16;
+    while (c.czt_tt > 1 && (size_t)d.D * c.czt_tt * 4 > kLds / 2) c.czt_tt /= 2;
+    {
+        size_t rest = kLds - (size_t)d.D * c.czt_tt * 4;
+        int v = 4;
+        while (v > 1 && ((size_t)v * sizeof(float2) * d.L > rest || v * fft_max_butterflies(fc) > kBf)) --v;
+        c.czt_par = ((size_t)v * sizeof(float2) * d.L <= rest && v * fft_max_butterflies(fc) <= kBf) ? v : 0;
+    }
+    c.spr_cb = 64;
+    c.spr_th = 32;
+    c.spr_cap = 256;
+    if (!c.col_np || !c.row_rpb || !c.dct_mt || !c.czt_par) return PAT_ERR_UNSUPPORTED;
+    if ((size_t)p->n_psi_max * sizeof(float2) > kLds || max_ring_bf > kBf) return PAT_ERR_UNSUPPORTED;
+    p->thr_col = fft_threads(c.col_np, fg);
+    p->thr_row = fft_threads(c.row_rpb, fg);
+    p->thr_dct = fft_threads(c.dct_mt, fm);
+    p->thr_czt = fft_threads(c.czt_par, fc);
+    {
+        const int need = (max_ring_bf + 7) / 8;
+        p->thr_ring = std::max(128, std::min(512, ((need + 63) / 64) * 64));
+    }
+    return PAT_OK;
+}
+
+void layout_workspace(pat_plan* p)
+{
+    const PlanDev& d = p->dev;
+    WsLayout& w = p->ws;
+    size_t o = 0;
+    w.x1 = o;     o += align256(sizeof(float2) * (size_t)d.Hy * d.N);
+    w.grid = o;   o += align256(sizeof(float2) * (size_t)d.Hy * d.Ng);
+    w.modes = o;  o += align256(sizeof(float2) * (size_t)d.nlam * d.Kp);
+    w.tmodes = o; o += align256(sizeof(float2) * (size_t)d.T * d.Kp);
+    w.polar = o;  o += align256(sizeof(float2) * (size_t)d.npts);
+    p->n_col_tiles = (d.N + 2 * p->cfg.col_np - 1) / (2 * p->cfg.col_np);
+    p->n_time_tiles = (d.T + p->cfg.czt_tt - 1) / p->cfg.czt_tt;
+    w.n_red = std::max(p->n_col_tiles, p->n_time_tiles);
+    w.red = o;    o += align256(sizeof(float) * (size_t)w.n_red);
+    w.bytes = o;
+}
+
+}  // namespace pat
+
+extern "C" int pat_plan_derive(const pat_plan_desc* desc, pat_plan_info* out)
+{
+    Derived dv;
+    int rc = derive(desc, &dv);
+    if (rc != PAT_OK) return rc;
+    if (!out) return PAT_ERR_ARG;
+    std::memset(out, 0, sizeof(*out));
+    out->M = dv.M;
+    out->dlam = dv.dlam;
+    out->n_lam = dv.n_lam;
+    out->K = dv.K;
+    out->n_psi = dv.n_psi;
+    out->kappa = dv.kappa;
+    out->n_grid = dv.Ng;
+    out->len_czt = dv.L;
+    return PAT_OK;
+}
+
+extern "C" int pat_bessel_jn_table(int kmax, double x, double* out)
+{
+    if (kmax < 0 || !out || !std::isfinite(x)) return PAT_ERR_ARG;
+    bessel_jn_table(kmax, x, out);
+    return PAT_OK;
+}
+
+// Host part of plan creation; fills every table into `tb` and the PlanDev
+// offsets (as byte offsets stored in the pointer fields, relocated later).
+static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* p, TableBuilder& tb)
+{
+    PlanDev& d = p->dev;
+    const int N = desc->n, Ng = dv.Ng, nlam = dv.n_lam, K = dv.K, D = desc->n_det, T = desc->n_t;
+    const double h = dv.h, R = desc->det_r;
+    d.N = N; d.Ng = Ng; d.Hy = Ng / 2 + 9; d.nlam = nlam; d.K = K; d.Kp = K + 1; d.M = dv.M;
+    d.T = T; d.D = D; d.L = dv.L; d.NB = Ng / 2 + 2;
+    d.kappa = (float)dv.kappa;
+    d.h2 = (float)(h * h);
+
+    FftSet ffts;
+    d.fft_grid = ffts.get(Ng);
+    d.fft_dct = ffts.get(2L * dv.M);
+    d.fft_czt = ffts.get(dv.L);
+
+    // --- image-side tables -------------------------------------------------
+    std::vector<double> ph = es_hat(N, Ng);
+    std::vector<float> deap(N);
+    for (int j = 0; j < N; ++j) {
+        if (!(ph[j] > 1e-300)) return PAT_ERR_UNSUPPORTED;
+        deap[j] = (float)(h / ph[j]);
+    }
+    std::vector<int2> mask(N);
+    const double rs2 = desc->support_r * desc->support_r;
+    for (int i = 0; i < N; ++i) {
+        double y = -1.0 + (i + 0.5) * h;
+        int lo = N, hi = 0;
+        for (int j = 0; j < N; ++j) {
+            double x = -1.0 + (j + 0.5) * h;
+            if (x * x + y * y < rs2) { lo = std::min(lo, j); hi = std::max(hi, j + 1); }
+        }
+        if (lo >= hi) { lo = 0; hi = 0; }
+        mask[i] = make_int2(lo, hi);
+    }
+
+    // --- rings: per-ring mode cut-off and angular grid ----------------------
+    std::vector<int> ringK(nlam), ringN(nlam), ringOff(nlam + 1), ringFft(nlam), ringJoff(nlam);
+    std::vector<double> rho(nlam);
+    int npts = 0, joff = 0, npsi_max = 0;
+    for (int n = 1; n <= nlam; ++n) {
+        double lam = n * dv.dlam, x = lam * R;
+        int kn = (int)std::ceil(x + 10.0 * std::cbrt(x) - 1e-9);
+        kn = std::min(K, std::max(kn, 1));
+        int np = (int)smooth23(2.0 * kn + 2, 2);
+        ringK[n - 1] = kn;
+        ringN[n - 1] = np;
+        ringOff[n - 1] = npts;
+        ringJoff[n - 1] = joff;
+        ringFft[n - 1] = ffts.get(np);
+        rho[n - 1] = lam * h * Ng / (2.0 * PI);
+        npts += np / 2;
+        joff += kn + 1;
+        npsi_max = std::max(npsi_max, np);
+    }
+    ringOff[nlam] = npts;
+    d.npts = npts;
+    p->n_psi_max = npsi_max;
+    std::vector<int> nmin(K + 1, nlam);
+    for (int k = 0; k <= K; ++k)
+        for (int n = 0; n < nlam; ++n)
+            if (ringK[n] >= k) { nmin[k] = n; break; }
+
+    // radial weights J_k(lam_n R) W_n / Npsi(n)
+    std::vector<float> Jw(joff);
+    {
+        std::vector<double> jt(K + 1);
+        for (int n = 1; n <= nlam; ++n) {
+            double lam = n * dv.dlam;
+            double W = lam * dv.dlam / (2.0 * PI);
+            bessel_jn_table(ringK[n - 1], lam * R, jt.data());
+            for (int k = 0; k <= ringK[n - 1]; ++k)
+                Jw[ringJoff[n - 1] + k] = (float)(jt[k] * W / ringN[n - 1]);
+        }
+    }
+
+    // --- polar points (ring order), footprint bases and phases -------------
+    std::vector<float4> geo(npts);
+    std::vector<float2> phase(npts);
+    std::vector<int> r0s(npts), bxs(npts);
+    for (int n = 0; n < nlam; ++n) {
+        const int np = ringN[n];
+        for (int l = 0; l < np / 2; ++l) {
+            double psi = 2.0 * PI * l / np;
+            double sx = rho[n] * std::cos(psi), sy = rho[n] * std::sin(psi);
+            double flx = std::floor(sx), fly = std::floor(sy);
+            long bx = (long)flx - 3, by = (long)fly - 3;
+            int r0 = (int)(by + 4);
+            if (r0 < 0 || r0 + 7 >= d.Hy) return PAT_ERR_UNSUPPORTED;
+            int bxm = (int)(((bx % Ng) + Ng) % Ng);
+            int q = ringOff[n] + l;
+            float4 gq;
+            int ibx = bxm, ir0 = r0;
+            std::memcpy(&gq.x, &ibx, 4);
+            std::memcpy(&gq.y, &ir0, 4);
+            gq.z = (float)(sx - flx);
+            gq.w = (float)(sy - fly);
+            geo[q] = gq;
+            double a = -PI * (sx + sy) / Ng;
+            phase[q] = make_float2((float)std::cos(a), (float)std::sin(a));
+            r0s[q] = r0;
+            bxs[q] = bxm;
+        }
+    }
+    // band order: stable sort by (r0, bx)
+    std::vector<int> order(npts);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return r0s[a] != r0s[b] ? r0s[a] < r0s[b] : bxs[a] < bxs[b];
+    });
+    std::vector<int> perm(npts);
+    std::vector<float4> bgeo(npts);
+    for (int s = 0; s < npts; ++s) { perm[order[s]] = s; bgeo[s] = geo[order[s]]; }
+    const int NB = d.NB;
+    std::vector<int> bptr((size_t)NB * (Ng + 1));
+    {
+        // counts per (r0, bx) then exclusive scan in (r0, bx) order
+        std::vector<int> cnt((size_t)NB * Ng, 0);
+        for (int q = 0; q < npts; ++q) cnt[(size_t)r0s[q] * Ng + bxs[q]]++;
+        int run = 0;
+        for (int r = 0; r < NB; ++r) {
+            for (int b = 0; b < Ng; ++b) {
+                bptr[(size_t)r * (Ng + 1) + b] = run;
+                run += cnt[(size_t)r * Ng + b];
+            }
+            bptr[(size_t)r * (Ng + 1) + Ng] = run;
+        }
+    }
+
+    // --- chirp-z tables over detector angles --------------------------------
+    const double dth = desc->arc_span / D;
+    const double th0 = desc->arc_center - 0.5 * desc->arc_span + 0.5 * dth;
+    const int L = dv.L;
+    auto wpow = [&](long m) {  // w^{m^2}, w = e^{i dth/2}; reduce the phase mod 2 pi in FP64
+        double a = std::fmod(0.5 * dth * (double)m * (double)m, 2.0 * PI);
+        return cd(std::cos(a), std::sin(a));
+    };
+    std::vector<float2> pre(K + 1), post(D), vhat(L);
+    for (int k = 0; k <= K; ++k) {
+        double a = std::fmod(k * th0, 2.0 * PI);
+        cd v = (k == 0 ? 1.0 : 2.0) * cd(std::cos(a), std::sin(a)) * wpow(k);
+        pre[k] = make_float2((float)v.real(), (float)v.imag());
+    }
+    for (int q = 0; q < D; ++q) {
+        cd v = wpow(q);
+        post[q] = make_float2((float)v.real(), (float)v.imag());
+    }
+    {
+        std::vector<cd> v(L, cd(0, 0));
+        for (long m = -K; m <= D - 1; ++m) v[((m % L) + L) % L] = std::conj(wpow(m));
+        host_fft(v);
+        for (int q = 0; q < L; ++q) vhat[q] = make_float2((float)(v[q].real() / L), (float)(v[q].imag() / L));
+    }
+
+    {
+        int max_ring_bf = 0;
+        for (int n = 0; n < nlam; ++n) max_ring_bf = std::max(max_ring_bf, fft_max_butterflies(ffts.descs[ringFft[n]]));
+        int rc = choose_launch(p, ffts.descs, max_ring_bf);
+        if (rc != PAT_OK) return rc;
+    }
+
+    // --- pack ---------------------------------------------------------------
+    size_t o_deap = tb.add(deap), o_mask = tb.add(mask);
+    size_t o_geo = tb.add(geo), o_phase = tb.add(phase);
+    size_t o_roff = tb.add(ringOff), o_rk = tb.add(ringK), o_rfft = tb.add(ringFft), o_rj = tb.add(ringJoff);
+    size_t o_jw = tb.add(Jw), o_nmin = tb.add(nmin);
+    size_t o_perm = tb.add(perm), o_bgeo = tb.add(bgeo), o_bptr = tb.add(bptr);
+    size_t o_pre = tb.add(pre), o_post = tb.add(post), o_vhat = tb.add(vhat);
+    size_t o_ffts = tb.add(ffts.descs), o_tw = tb.add(ffts.tw);
+    // store offsets in the pointer fields; relocated after the upload
+    auto off = [](size_t o) { return (const void*)(uintptr_t)o; };
+    d.deap = (const float*)off(o_deap);
+    d.mask_rows = (const int2*)off(o_mask);
+    d.pt_geo = (const float4*)off(o_geo);
+    d.pt_phase = (const float2*)off(o_phase);
+    d.ring_off = (const int*)off(o_roff);
+    d.ring_K = (const int*)off(o_rk);
+    d.ring_fft = (const int*)off(o_rfft);
+    d.ring_joff = (const int*)off(o_rj);
+    d.Jw = (const float*)off(o_jw);
+    d.mode_nmin = (const int*)off(o_nmin);
+    d.perm = (const int*)off(o_perm);
+    d.bpt_geo = (const float4*)off(o_bgeo);
+    d.band_ptr = (const int*)off(o_bptr);
+    d.czt_pre = (const float2*)off(o_pre);
+    d.czt_post = (const float2*)off(o_post);
+    d.czt_vhat = (const float2*)off(o_vhat);
+    d.ffts = (const FftDev*)off(o_ffts);
+    d.tw = (const float2*)off(o_tw);
+    return PAT_OK;
+}
+
+extern "C" int pat_plan_create(const pat_plan_desc* desc, pat_plan** out)
+{
+    if (!desc || !out) return PAT_ERR_ARG;
+    Derived dv;
+    int rc = derive(desc, &dv);
+    if (rc != PAT_OK) return rc;
+    pat_plan* p = new (std::nothrow) pat_plan;
+    if (!p) return PAT_ERR_ALLOC;
+    std::memset(p, 0, sizeof(*p));
+    TableBuilder tb;
+    rc = build_tables(desc, dv, p, tb);
+    if (rc != PAT_OK) { delete p; return rc; }
+    if (hipGetDevice(&p->device) != hipSuccess) { delete p; return PAT_ERR_HIP; }
+    void* mem = nullptr;
+    if (hipMalloc(&mem, tb.host.size()) != hipSuccess) { delete p; return PAT_ERR_ALLOC; }
+    if (hipMemcpy(mem, tb.host.data(), tb.host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(mem);
+        delete p;
+        return PAT_ERR_HIP;
+    }
+    p->table_mem = mem;
+    p->table_bytes = tb.host.size();
+    // relocate
+    char* base = (char*)mem;
+    PlanDev& d = p->dev;
+    auto rel = [&](auto& ptr) { ptr = (std::remove_reference_t<decltype(ptr)>)(base + (uintptr_t)ptr); };
+    rel(d.deap); rel(d.mask_rows); rel(d.pt_geo); rel(d.pt_phase); rel(d.ring_off); rel(d.ring_K);
+    rel(d.ring_fft); rel(d.ring_joff); rel(d.Jw); rel(d.mode_nmin); rel(d.perm); rel(d.bpt_geo);
+    rel(d.band_ptr); rel(d.czt_pre); rel(d.czt_post); rel(d.czt_vhat); rel(d.ffts); rel(d.tw);
+    p->max_batch = desc->max_batch;
+    p->n_psi_uniform = dv.n_psi;
+    p->M = dv.M;
+    p->dlam = dv.dlam;
+    p->kappa = dv.kappa;
+    layout_workspace(p);
+    *out = p;
+    return PAT_OK;
+}
+
+extern "C" int pat_plan_query(const pat_plan* p, pat_plan_info* out)
+{
+    if (!p || !out) return PAT_ERR_ARG;
+    std::memset(out, 0, sizeof(*out));
+    out->M = p->M;
+    out->dlam = p->dlam;
+    out->n_lam = p->dev.nlam;
+    out->K = p->dev.K;
+    out->n_psi = p->n_psi_uniform;
+    out->kappa = p->kappa;
+    out->n_grid = p->dev.Ng;
+    out->n_points = p->dev.npts;
+    out->len_czt = p->dev.L;
+    out->workspace_per_instance = p->ws.bytes;
+    out->table_bytes = p->table_bytes;
+    return PAT_OK;
+}
+
+extern "C" void pat_plan_destroy(pat_plan* p)
+{
+    if (!p) return;
+    if (p->table_mem) {
+        int cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess) cur = p->device;
+        (void)hipSetDevice(p->device);
+        (void)hipFree(p->table_mem);
+        (void)hipSetDevice(cur);
+    }
+    delete p;
+}
+
+extern "C" size_t pat_workspace_size(const pat_plan* p, int batch)
+{
+    if (!p || batch < 1) return 0;
+    return p->ws.bytes * (size_t)batch;
+}

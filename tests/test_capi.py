@@ -1,0 +1,118 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library must load and export every function include/pat.h declares; the
+host-only routines (size derivation, Bessel table, status strings) and the
+argument checks that run before any launch are exercised here.
+"""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+from scipy import special
+
+from pat_inputs import Geometry, config_geometry
+
+
+@pytest.fixture(scope="module")
+def patlib():
+    from paper_2604_19176_amd import _lib
+    return _lib
+
+
+def test_every_declared_symbol_is_exported(patlib):
+    lib = patlib.load()
+    names = patlib.declared_functions()
+    assert "pat_forward" in names and "pat_adjoint" in names and "pat_plan_create" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, "gradcheck", 5])
+def test_derived_sizes_match_oracle(patlib, oracle_mod, cfg):
+    """The plan's size rules (implemented separately from the oracle's) agree."""
+    import paper_2604_19176_amd as pat
+    geom = config_geometry(cfg)
+    info = pat.pat_plan_derive(pat.desc_from_geometry(geom))
+    ref = oracle_mod.sizes(geom)
+    assert (info.M, info.n_lam, info.K, info.n_psi) == (ref["M"], ref["n_lam"], ref["K"], ref["n_psi"])
+    assert info.dlam == pytest.approx(ref["dlam"], rel=1e-15)
+    assert info.kappa == pytest.approx(ref["kappa"], rel=1e-15)
+    assert info.n_grid >= 2 * geom.n and info.n_grid % 2 == 0
+    assert info.len_czt >= info.K + geom.n_det
+
+
+def test_derived_sizes_random_geometries(patlib, oracle_mod):
+    import paper_2604_19176_amd as pat
+    rng = np.random.default_rng(3)
+    for _ in range(40):
+        n = int(rng.integers(16, 300))
+        t = int(rng.integers(8, 900))
+        geom = Geometry(n=n, n_det=int(rng.integers(1, 400)), n_t=t, dt=float(rng.uniform(0.5, 3.0)) / t,
+                        arc_span=float(rng.uniform(0.1, 2 * math.pi)), c=float(rng.uniform(0.5, 2.0)),
+                        lambda_oversample=float(rng.choice([1.0, 1.5, 2.0, 3.0])))
+        try:
+            ref = oracle_mod.sizes(geom)
+        except ValueError:
+            continue
+        try:
+            info = pat.pat_plan_derive(pat.desc_from_geometry(geom))
+        except pat.PatError as e:
+            assert e.status == pat._lib.PAT_ERR_UNSUPPORTED  # valid but beyond the kernels' limits
+            continue
+        assert (info.M, info.n_lam, info.K, info.n_psi) == (ref["M"], ref["n_lam"], ref["K"], ref["n_psi"])
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=8), -2),                  # below the smallest supported grid
+    (dict(arc_span=7.0), -1),
+    (dict(arc_span=0.0), -1),
+    (dict(dt=-1.0), -1),
+    (dict(c=0.0), -1),
+    (dict(support_r=1.2), -1),        # support outside the detector circle
+    (dict(n_det=0), -1),
+    (dict(lambda_oversample=0.5), -1),
+    (dict(n_t=1, dt=1e-4), -1),       # no radial frequency below pi/h
+    (dict(n_t=4096, dt=2 / 4096), -2),  # cosine FFT longer than the LDS plans
+])
+def test_plan_argument_errors(patlib, kw, status):
+    import paper_2604_19176_amd as pat
+    base = dict(n=32, n_det=16, n_t=64, dt=2 / 64)
+    base.update(kw)
+    geom = Geometry(**base)
+    with pytest.raises(pat.PatError) as ei:
+        pat.pat_plan_derive(pat.desc_from_geometry(geom))
+    assert ei.value.status == status
+
+
+def test_bessel_table_matches_scipy(patlib):
+    import paper_2604_19176_amd as pat
+    for x in [1e-3, 0.785, 7.0, 99.5, 402.12, 1608.5]:
+        kmax = int(math.ceil(x + 10 * x ** (1 / 3))) + 3
+        got = np.array(pat.pat_bessel_jn_table(kmax, x))
+        ref = special.jv(np.arange(kmax + 1), x)
+        assert np.abs(got - ref).max() < 1e-13, x
+
+
+def test_status_strings(patlib):
+    import paper_2604_19176_amd as pat
+    assert pat.pat_status_string(0) == "ok"
+    for s in (-1, -2, -3, -4, -5):
+        assert pat.pat_status_string(s) not in ("ok", "unknown status")
+    assert pat.pat_status_string(7) == "unknown status"
+
+
+def test_calls_reject_null_arguments_before_launch(patlib):
+    """Host checks return PAT_ERR_ARG without touching a GPU."""
+    lib = patlib.load()
+    one = ctypes.c_void_p(1)
+    assert lib.pat_forward(None, one, one, 1, one, 0, None) == -1
+    assert lib.pat_adjoint(None, one, one, 1, one, 0, None) == -1
+    assert lib.pat_tv_grad(None, one, None, 16, 1, 1e-3, None) == -1
+    assert lib.pat_tv_grad(one, one, None, 1, 1, 1e-3, None) == -1
+    assert lib.pat_tv_grad(one, one, None, 16, 1, 0.0, None) == -1
+    assert lib.pat_pgd_update(None, one, None, 10, 0.1, 0.1, None) == -1
+    assert lib.pat_residual(one, None, None, 10, 1, None) == -1
+    assert lib.pat_workspace_size(None, 1) == 0
+    assert lib.pat_plan_query(None, None) == -1
+    lib.pat_plan_destroy(None)  # no-op
