@@ -78,7 +78,9 @@ typedef struct {
     double kappa;             /* endpoint-term coefficient dlam^2/(24 pi), 0 if disabled              */
     int    n_grid;            /* oversampled spectral grid side used for the polar interpolation      */
     int    n_points;          /* polar points evaluated per image (half plane, per-ring angular grids) */
-    int    len_czt;           /* FFT length of the detector-angle chirp-z transform                   */
+    int    len_czt;           /* FFT length of the synthesis over detector angles: P when the detector
+                                 pitch is 2 pi / P (P = 2^a 3^b >= D), else the chirp-z length >= K + D */
+    int    n_ring_modes;      /* sum over radial frequencies of the angular modes kept (K_n + 1)       */
     size_t workspace_per_instance; /* workspace bytes per batch instance                              */
     size_t table_bytes;       /* device bytes held by the plan's tables                               */
 } pat_plan_info;
@@ -132,6 +134,19 @@ int  pat_pgd_update(float* f, const float* adj, const float* tvgrad, long count,
  * g, g_meas: device [batch][count_per] FP32.  Errors: PAT_ERR_ARG, PAT_ERR_HIP. */
 int  pat_residual(float* g, const float* g_meas, float* sq, long count_per, int batch,
                   void* stream);
+
+/* Per-kernel timing.  pat_profile_enable(plan, 1) creates HIP events; from
+ * then on every pat_forward / pat_adjoint call on `plan` records an event
+ * before and after each of its kernels on the call's stream (a few
+ * microseconds of overhead; 0 disables and frees the events).
+ * pat_profile_read waits for the last call of direction `which` (0 = forward,
+ * 1 = adjoint) to finish and writes its kernel durations in milliseconds to
+ * ms[0..*count-1], in launch order (forward: column pass, row pass, ring
+ * (interpolation, angular FFT, weights, detector synthesis), cosine transform;
+ * adjoint: cosine transform, ring, spread, row pass, column pass).  Errors: PAT_ERR_ARG (NULL, profiling off,
+ * max_kernels too small), PAT_ERR_HIP. */
+int  pat_profile_enable(pat_plan* plan, int enable);
+int  pat_profile_read(const pat_plan* plan, int which, float* ms, int max_kernels, int* count);
 
 /* Host-only helpers (no GPU needed).
  * pat_plan_derive: the sizes pat_plan_create would derive for `desc`, without

@@ -20,7 +20,8 @@ import torch
 from . import _lib
 from ._lib import (PatError, pat_plan_desc, pat_status_string, pat_plan_create, pat_plan_query,  # noqa: F401
                    pat_plan_destroy, pat_workspace_size, pat_forward, pat_adjoint, pat_tv_grad,
-                   pat_pgd_update, pat_residual, pat_plan_derive, pat_bessel_jn_table)
+                   pat_pgd_update, pat_residual, pat_plan_derive, pat_bessel_jn_table,
+                   pat_profile_enable, pat_profile_read)
 
 __all__ = ["PatPlan", "pat_operator", "PatOperatorFn", "tv_grad", "pgd_update", "residual", "PatError",
            "desc_from_geometry", "library_path"]

@@ -40,6 +40,7 @@ class pat_plan_info(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int), ("dlam", ctypes.c_double), ("n_lam", ctypes.c_int),
                 ("K", ctypes.c_int), ("n_psi", ctypes.c_int), ("kappa", ctypes.c_double),
                 ("n_grid", ctypes.c_int), ("n_points", ctypes.c_int), ("len_czt", ctypes.c_int),
+                ("n_ring_modes", ctypes.c_int),
                 ("workspace_per_instance", ctypes.c_size_t), ("table_bytes", ctypes.c_size_t)]
 
 
@@ -67,6 +68,8 @@ def load():
         "pat_tv_grad": (ci, [vp, vp, vp, ci, ci, cf, vp]),
         "pat_pgd_update": (ci, [vp, vp, vp, cl, cf, cf, vp]),
         "pat_residual": (ci, [vp, vp, vp, cl, ci, vp]),
+        "pat_profile_enable": (ci, [vp, ci]),
+        "pat_profile_read": (ci, [vp, ci, P(ctypes.c_float), ci, P(ci)]),
         "pat_plan_derive": (ci, [P(pat_plan_desc), P(pat_plan_info)]),
         "pat_bessel_jn_table": (ci, [ci, ctypes.c_double, P(ctypes.c_double)]),
         "pat_status_string": (ctypes.c_char_p, [ci]),
@@ -135,6 +138,17 @@ def pat_forward(plan, f_ptr, g_ptr, batch, ws_ptr, ws_bytes, stream) -> None:
 
 def pat_adjoint(plan, g_ptr, f_ptr, batch, ws_ptr, ws_bytes, stream) -> None:
     _check(load().pat_adjoint(plan, g_ptr, f_ptr, int(batch), ws_ptr, int(ws_bytes), stream), "pat_adjoint")
+
+
+def pat_profile_enable(plan, enable: bool) -> None:
+    _check(load().pat_profile_enable(plan, 1 if enable else 0), "pat_profile_enable")
+
+
+def pat_profile_read(plan, which: int):
+    ms = (ctypes.c_float * 8)()
+    cnt = ctypes.c_int()
+    _check(load().pat_profile_read(plan, int(which), ms, 8, ctypes.byref(cnt)), "pat_profile_read")
+    return [float(ms[i]) for i in range(cnt.value)]
 
 
 def pat_tv_grad(f_ptr, grad_ptr, tv_ptr, n, batch, eps, stream) -> None:

@@ -11,9 +11,19 @@
 
 using namespace pat;
 
+static size_t twb(int n) { return sizeof(float2) * (size_t)tw_lds_slots(n); }
+
+static unsigned xcd_grid(int items) { return (unsigned)(((items + kXcds - 1) / kXcds) * kXcds); }
+
 static int check_launch()
 {
     return hipGetLastError() == hipSuccess ? PAT_OK : PAT_ERR_HIP;
+}
+
+// Per-kernel timing: event q is recorded before launch q, event q+1 after it.
+static inline void prof_mark(const pat_plan* p, int dir, int q, hipStream_t st)
+{
+    if (p->prof) (void)hipEventRecord(p->ev[dir][q], st);
 }
 
 static int validate(const pat_plan* p, const void* in, const void* out, int batch, const void* ws,
@@ -35,37 +45,24 @@ extern "C" int pat_forward(const pat_plan* p, const float* f, float* g, int batc
     const PlanDev& d = p->dev;
     const LaunchCfg& c = p->cfg;
     const InstPtrs wsp{(char*)ws, p->ws.bytes};
-    // column pass
-    {
-        dim3 grid(p->n_col_tiles, batch);
-        hipLaunchKernelGGL(k_colpass_fwd, grid, dim3(p->thr_col), sizeof(float2) * c.col_np * d.Ng, st, d, p->ws,
-                           f, wsp, c.col_np);
-        if ((rc = check_launch())) return rc;
-    }
-    {
-        dim3 grid((d.Hy + c.row_rpb - 1) / c.row_rpb, batch);
-        hipLaunchKernelGGL(k_rowpass_fwd, grid, dim3(p->thr_row), sizeof(float2) * c.row_rpb * d.Ng, st, d, p->ws,
-                           wsp, c.row_rpb);
-        if ((rc = check_launch())) return rc;
-    }
-    {
-        dim3 grid(d.nlam, batch);
-        hipLaunchKernelGGL(k_ring_fwd, grid, dim3(p->thr_ring), sizeof(float2) * p->n_psi_max, st, d, p->ws, wsp);
-        if ((rc = check_launch())) return rc;
-    }
-    {
-        dim3 grid((d.Kp + c.dct_mt - 1) / c.dct_mt, batch);
-        hipLaunchKernelGGL(k_dct, grid, dim3(p->thr_dct), sizeof(float2) * c.dct_mt * 2 * d.M, st, d, p->ws, wsp,
-                           c.dct_mt, 0);
-        if ((rc = check_launch())) return rc;
-    }
-    {
-        dim3 grid(p->n_time_tiles, batch);
-        size_t lds = sizeof(float2) * c.czt_par * d.L + sizeof(float) * d.D * c.czt_tt;
-        hipLaunchKernelGGL(k_czt_fwd, grid, dim3(p->thr_czt), lds, st, d, p->ws, wsp, g, c.czt_tt, c.czt_par,
-                           p->n_col_tiles);
-        if ((rc = check_launch())) return rc;
-    }
+    prof_mark(p, 0, 0, st);
+    hipLaunchKernelGGL(k_colpass_fwd, dim3(p->n_col_tiles, batch), dim3(p->thr_col), sizeof(float2) * c.col_np * d.Ng + twb(d.Ng),
+                       st, d, p->ws, f, wsp, c.col_np);
+    if ((rc = check_launch())) return rc;
+    prof_mark(p, 0, 1, st);
+    hipLaunchKernelGGL(k_rowpass_fwd, dim3((d.Hy + c.row_rpb - 1) / c.row_rpb, batch), dim3(p->thr_row),
+                       sizeof(float2) * c.row_rpb * d.Ng + twb(d.Ng), st, d, p->ws, wsp, c.row_rpb);
+    if ((rc = check_launch())) return rc;
+    prof_mark(p, 0, 2, st);
+    hipLaunchKernelGGL(k_ring_fwd, dim3(xcd_grid((d.nlam + c.ring_rt - 1) / c.ring_rt * batch)), dim3(p->thr_ring),
+                       p->lds_ring, st, d, p->ws, wsp, c.ring_rt, batch);
+    if ((rc = check_launch())) return rc;
+    prof_mark(p, 0, 3, st);
+    hipLaunchKernelGGL(k_dct_det, dim3(xcd_grid(p->n_pair_tiles * batch)), dim3(p->thr_dct),
+                       sizeof(float2) * c.dct_dp * 2 * d.M + twb(2 * d.M), st, d, p->ws, wsp, g, (const float*)nullptr, c.dct_dp, 0,
+                       p->n_col_tiles, batch);
+    if ((rc = check_launch())) return rc;
+    prof_mark(p, 0, 4, st);
     return PAT_OK;
 }
 
@@ -78,41 +75,28 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
     const PlanDev& d = p->dev;
     const LaunchCfg& c = p->cfg;
     const InstPtrs wsp{(char*)ws, p->ws.bytes};
-    {
-        dim3 grid(p->n_time_tiles, batch);
-        size_t lds = sizeof(float2) * c.czt_par * d.L + sizeof(float) * d.D * c.czt_tt;
-        hipLaunchKernelGGL(k_czt_adj, grid, dim3(p->thr_czt), lds, st, d, p->ws, wsp, g, c.czt_tt, c.czt_par);
-        if ((rc = check_launch())) return rc;
-    }
-    {
-        dim3 grid((d.Kp + c.dct_mt - 1) / c.dct_mt, batch);
-        hipLaunchKernelGGL(k_dct, grid, dim3(p->thr_dct), sizeof(float2) * c.dct_mt * 2 * d.M, st, d, p->ws, wsp,
-                           c.dct_mt, 1);
-        if ((rc = check_launch())) return rc;
-    }
-    {
-        dim3 grid(d.nlam, batch);
-        hipLaunchKernelGGL(k_ring_adj, grid, dim3(p->thr_ring), sizeof(float2) * p->n_psi_max, st, d, p->ws, wsp);
-        if ((rc = check_launch())) return rc;
-    }
-    {
-        dim3 grid((d.Ng + c.spr_cb - 1) / c.spr_cb, (d.Hy + c.spr_th - 1) / c.spr_th, batch);
-        size_t lds = sizeof(float) * 19 * c.spr_cap;
-        hipLaunchKernelGGL(k_spread, grid, dim3(c.spr_cb), lds, st, d, p->ws, wsp, c.spr_th, c.spr_cap);
-        if ((rc = check_launch())) return rc;
-    }
-    {
-        dim3 grid((d.Hy + c.row_rpb - 1) / c.row_rpb, batch);
-        hipLaunchKernelGGL(k_rowpass_adj, grid, dim3(p->thr_row), sizeof(float2) * c.row_rpb * d.Ng, st, d, p->ws,
-                           wsp, c.row_rpb);
-        if ((rc = check_launch())) return rc;
-    }
-    {
-        dim3 grid(p->n_col_tiles, batch);
-        hipLaunchKernelGGL(k_colpass_adj, grid, dim3(p->thr_col), sizeof(float2) * c.col_np * d.Ng, st, d, p->ws,
-                           wsp, f, c.col_np, p->n_time_tiles);
-        if ((rc = check_launch())) return rc;
-    }
+    prof_mark(p, 1, 0, st);
+    hipLaunchKernelGGL(k_dct_det, dim3(xcd_grid(p->n_pair_tiles * batch)), dim3(p->thr_dct),
+                       sizeof(float2) * c.dct_dp * 2 * d.M + twb(2 * d.M), st, d, p->ws, wsp, (float*)nullptr, g, c.dct_dp, 1, 0,
+                       batch);
+    if ((rc = check_launch())) return rc;
+    prof_mark(p, 1, 1, st);
+    hipLaunchKernelGGL(k_ring_adj, dim3(xcd_grid((d.nlam + c.ring_rt - 1) / c.ring_rt * batch)), dim3(p->thr_ring),
+                       p->lds_ring, st, d, p->ws, wsp, c.ring_rt, batch);
+    if ((rc = check_launch())) return rc;
+    prof_mark(p, 1, 2, st);
+    hipLaunchKernelGGL(k_spread, dim3((d.Ng + c.spr_cb - 1) / c.spr_cb, (d.Hy + c.spr_th - 1) / c.spr_th, batch),
+                       dim3(c.spr_cb), sizeof(float) * 19 * c.spr_cap, st, d, p->ws, wsp, c.spr_th, c.spr_cap);
+    if ((rc = check_launch())) return rc;
+    prof_mark(p, 1, 3, st);
+    hipLaunchKernelGGL(k_rowpass_adj, dim3((d.Hy + c.row_rpb - 1) / c.row_rpb, batch), dim3(p->thr_row),
+                       sizeof(float2) * c.row_rpb * d.Ng + twb(d.Ng), st, d, p->ws, wsp, c.row_rpb);
+    if ((rc = check_launch())) return rc;
+    prof_mark(p, 1, 4, st);
+    hipLaunchKernelGGL(k_colpass_adj, dim3(p->n_col_tiles, batch), dim3(p->thr_col), sizeof(float2) * c.col_np * d.Ng + twb(d.Ng),
+                       st, d, p->ws, wsp, f, c.col_np, p->n_pair_tiles);
+    if ((rc = check_launch())) return rc;
+    prof_mark(p, 1, 5, st);
     return PAT_OK;
 }
 
@@ -149,6 +133,37 @@ extern "C" int pat_residual(float* g, const float* g_meas, float* sq, long count
     if (rc || !sq) return rc;
     hipLaunchKernelGGL(k_half_sq, dim3(batch), dim3(1024), 0, st, g, sq, count_per);
     return check_launch();
+}
+
+extern "C" int pat_profile_enable(pat_plan* p, int enable)
+{
+    if (!p) return PAT_ERR_ARG;
+    if (enable && !p->prof) {
+        for (int dir = 0; dir < 2; ++dir)
+            for (int q = 0; q < 8; ++q)
+                if (hipEventCreate(&p->ev[dir][q]) != hipSuccess) return PAT_ERR_HIP;
+        p->ev_count[0] = 5;  // 4 forward kernels
+        p->ev_count[1] = 6;  // 5 adjoint kernels
+        p->prof = 1;
+    } else if (!enable && p->prof) {
+        for (int dir = 0; dir < 2; ++dir)
+            for (int q = 0; q < 8; ++q) (void)hipEventDestroy(p->ev[dir][q]);
+        p->prof = 0;
+    }
+    return PAT_OK;
+}
+
+extern "C" int pat_profile_read(const pat_plan* p, int which, float* ms, int max_kernels, int* count)
+{
+    if (!p || !ms || !count || (which != 0 && which != 1)) return PAT_ERR_ARG;
+    if (!p->prof) return PAT_ERR_ARG;
+    const int nk = p->ev_count[which] - 1;
+    if (max_kernels < nk) return PAT_ERR_ARG;
+    if (hipEventSynchronize(p->ev[which][nk]) != hipSuccess) return PAT_ERR_HIP;
+    for (int q = 0; q < nk; ++q)
+        if (hipEventElapsedTime(&ms[q], p->ev[which][q], p->ev[which][q + 1]) != hipSuccess) return PAT_ERR_HIP;
+    *count = nk;
+    return PAT_OK;
 }
 
 extern "C" const char* pat_status_string(int s)

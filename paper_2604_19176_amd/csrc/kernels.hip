@@ -20,7 +20,21 @@
 
 namespace pat {
 
-constexpr int kMaxB = 8;  // butterflies per thread per FFT stage
+constexpr int kMaxB = 4;  // butterflies per thread per FFT stage (workgroups of up to 1024 threads)
+
+// XCD-aware work mapping.  The hardware hands workgroup w to XCD (w mod 8);
+// remap so that XCD x owns the contiguous item range [start(x), start(x+1))
+// of the U work items (instance-major), keeping one instance's intermediates
+// in one XCD's L2.  Returns -1 for the padding workgroups of the last round.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_item(int w, int U)
+{
+    const int x = w % kXcds, q = w / kXcds;
+    const int Q = U / kXcds, Rm = U - Q * kXcds;
+    const int cnt = Q + (x < Rm ? 1 : 0);
+    if (q >= cnt) return -1;
+    return x * Q + min(x, Rm) + q;
+}
 
 __device__ __forceinline__ float es_weight(float t)
 {
@@ -60,11 +74,11 @@ struct InstPtrs {
 // ---------------------------------------------------------------------------
 // forward: column pass (FFT along y of real columns, packed in pairs)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(512) void k_colpass_fwd(PlanDev d, WsLayout L, const float* __restrict__ f,
+__global__ __launch_bounds__(1024) void k_colpass_fwd(PlanDev d, WsLayout L, const float* __restrict__ f,
                                                      InstPtrs wsp, int NP)
 {
     extern __shared__ float2 sm[];
-    __shared__ float red_s[512];
+    __shared__ float red_s[1024];
     const int b = blockIdx.y;
     const int N = d.N, Ng = d.Ng, CT = 2 * NP;
     const float* fb = f + (size_t)b * N * N;
@@ -72,6 +86,7 @@ __global__ __launch_bounds__(512) void k_colpass_fwd(PlanDev d, WsLayout L, cons
     float2* X1 = (float2*)(wb + L.x1);
     float* red = (float*)(wb + L.red);
     const int j0 = blockIdx.x * CT;
+    const TwLds tw = tw_lds_build(sm + NP * Ng, d.ffts[d.fft_grid], d.tw);
     for (int e = threadIdx.x; e < NP * Ng; e += blockDim.x) sm[e] = make_float2(0.f, 0.f);
     __syncthreads();
     float msum = 0.f;
@@ -94,7 +109,7 @@ __global__ __launch_bounds__(512) void k_colpass_fwd(PlanDev d, WsLayout L, cons
     const float tot = block_sum(msum, red_s);
     if (threadIdx.x == 0) red[blockIdx.x] = tot * d.h2;
     __syncthreads();
-    fft_lds<kMaxB>(sm, Ng, NP, d.ffts[d.fft_grid], d.tw, false);
+    fft_lds<kMaxB>(sm, Ng, NP, d.ffts[d.fft_grid], tw, false);
     for (int e = threadIdx.x; e < d.Hy * CT; e += blockDim.x) {
         const int r = e / CT, jj = e - r * CT, j = j0 + jj;
         if (j >= N) continue;
@@ -115,7 +130,7 @@ __global__ __launch_bounds__(512) void k_colpass_fwd(PlanDev d, WsLayout L, cons
 // ---------------------------------------------------------------------------
 // forward: row pass (FFT along x)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(512) void k_rowpass_fwd(PlanDev d, WsLayout L, InstPtrs wsp, int RPB)
+__global__ __launch_bounds__(1024) void k_rowpass_fwd(PlanDev d, WsLayout L, InstPtrs wsp, int RPB)
 {
     extern __shared__ float2 sm[];
     const int b = blockIdx.y;
@@ -125,6 +140,7 @@ __global__ __launch_bounds__(512) void k_rowpass_fwd(PlanDev d, WsLayout L, Inst
     float2* G = (float2*)(wb + L.grid);
     const int r0 = blockIdx.x * RPB;
     const int nr = min(RPB, d.Hy - r0);
+    const TwLds tw = tw_lds_build(sm + RPB * Ng, d.ffts[d.fft_grid], d.tw);
     for (int e = threadIdx.x; e < nr * Ng; e += blockDim.x) sm[e] = make_float2(0.f, 0.f);
     __syncthreads();
     for (int e = threadIdx.x; e < nr * N; e += blockDim.x) {
@@ -134,240 +150,253 @@ __global__ __launch_bounds__(512) void k_rowpass_fwd(PlanDev d, WsLayout L, Inst
         sm[rr * Ng + pos] = X1[(size_t)(r0 + rr) * N + j];
     }
     __syncthreads();
-    fft_lds<kMaxB>(sm, Ng, nr, d.ffts[d.fft_grid], d.tw, false);
+    fft_lds<kMaxB>(sm, Ng, nr, d.ffts[d.fft_grid], tw, false);
     for (int e = threadIdx.x; e < nr * Ng; e += blockDim.x) G[(size_t)r0 * Ng + e] = sm[e];
 }
 
 // ---------------------------------------------------------------------------
-// forward: ring kernel (interpolation + angular FFT + radial weight)
+// Ring kernels.  One workgroup handles RT consecutive radial frequencies
+// (rings) of one instance, one ring after another:
+//   forward: ES interpolation of the half spectrum at the ring's half-plane
+//            points, completion F(l + Npsi/2) = conj F(l), angular FFT,
+//            a_k = c_k e^{i k theta_0} i^k J_k(lam_n R) W_n F_k / Npsi (k <= K_n),
+//            synthesis over detectors h(d) = Re sum_k a_k e^{i k d dtheta}
+//            (one inverse FFT of length P after folding k mod P when
+//            dtheta = 2 pi / P, else Bluestein with two FFTs of length L),
+//            -> hT[d][n]  (real; the cosine transform over n follows)
+//   adjoint: the exact transpose, ending with the Hermitian fold and the
+//            conjugate half-pixel phase -> H (band order) for the spread.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(512) void k_ring_fwd(PlanDev d, WsLayout L, InstPtrs wsp)
+__device__ __forceinline__ float2 mul_ipow(float2 v, int k)  // v * i^k
+{
+    switch (k & 3) {
+        case 0: return v;
+        case 1: return make_float2(-v.y, v.x);
+        case 2: return make_float2(-v.x, -v.y);
+        default: return make_float2(v.y, -v.x);
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_ring_fwd(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
 {
     extern __shared__ float2 sm[];
-    const int b = blockIdx.y, n = blockIdx.x;
+    const int ntile = (d.nlam + RT - 1) / RT;
+    const int item = xcd_item(blockIdx.x, ntile * batch);
+    if (item < 0) return;
+    const int b = item / ntile, tile = item - b * ntile;
     char* wb = wsp.ws + (size_t)b * wsp.stride;
     const float2* __restrict__ G = (const float2*)(wb + L.grid);
-    float2* bm = (float2*)(wb + L.modes);
-    const int Ng = d.Ng;
-    const int off = d.ring_off[n], P = d.ring_off[n + 1] - off;
-    for (int l = threadIdx.x; l < P; l += blockDim.x) {
-        const float4 gq = d.pt_geo[off + l];
-        const int bx = fbits(gq.x), r0 = fbits(gq.y);
-        float wx[8], wy[8];
-        es_weights8(gq.z, wx);
-        es_weights8(gq.w, wy);
-        int cols[8];
-#pragma unroll
-        for (int dx = 0; dx < 8; ++dx) {
-            int c = bx + dx;
-            cols[dx] = c >= Ng ? c - Ng : c;
-        }
-        float2 acc = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int dy = 0; dy < 8; ++dy) {
-            const float2* row = G + (size_t)(r0 + dy) * Ng;
-            float2 ra = make_float2(0.f, 0.f);
+    float* hT = (float*)(wb + L.hdet);
+    const int Ng = d.Ng, D = d.D, S = d.syn_len;
+    float2* sa = sm;                          // [npsi_max]
+    float2* sb = sm + d.npsi_max;             // [S]
+    float* ot = (float*)(sb + S);             // [D][RT]
+    float2* twr_s = (float2*)(ot + ((D * RT + 1) & ~1));  // ring-length twiddles (rebuilt per ring)
+    float2* tws_s = twr_s + tw_lds_slots(d.npsi_max);
+    const int n0 = tile * RT;
+    const int nr = min(RT, d.nlam - n0);
+    const FftDev& fsyn = d.ffts[d.fft_syn];
+    const TwLds tws = tw_lds_build(tws_s, fsyn, d.tw);
+    for (int r = 0; r < nr; ++r) {
+        const int n = n0 + r;
+        const int off = d.ring_off[n], P = d.ring_off[n + 1] - off;
+        const TwLds twr = tw_lds_build(twr_s, d.ffts[d.ring_fft[n]], d.tw);
+        for (int l = threadIdx.x; l < P; l += blockDim.x) {
+            const float4 gq = d.pt_geo[off + l];
+            const int bx = fbits(gq.x), r0 = fbits(gq.y);
+            float wx[8], wy[8];
+            es_weights8(gq.z, wx);
+            es_weights8(gq.w, wy);
+            int cols[8];
 #pragma unroll
             for (int dx = 0; dx < 8; ++dx) {
-                const float2 gv = row[cols[dx]];
-                ra.x += wx[dx] * gv.x;
-                ra.y += wx[dx] * gv.y;
+                int c = bx + dx;
+                cols[dx] = c >= Ng ? c - Ng : c;
             }
-            acc.x += wy[dy] * ra.x;
-            acc.y += wy[dy] * ra.y;
+            float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int dy = 0; dy < 8; ++dy) {
+                const float2* row = G + (size_t)(r0 + dy) * Ng;
+                float2 ra = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int dx = 0; dx < 8; ++dx) {
+                    const float2 gv = row[cols[dx]];
+                    ra.x += wx[dx] * gv.x;
+                    ra.y += wx[dx] * gv.y;
+                }
+                acc.x += wy[dy] * ra.x;
+                acc.y += wy[dy] * ra.y;
+            }
+            const float2 F = cmul(acc, d.pt_phase[off + l]);
+            sa[l] = F;
+            sa[l + P] = cconj(F);
         }
-        const float2 F = cmul(acc, d.pt_phase[off + l]);
-        sm[l] = F;
-        sm[l + P] = cconj(F);
+        __syncthreads();
+        fft_lds<kMaxB>(sa, 2 * P, 1, d.ffts[d.ring_fft[n]], twr, false);
+        const int Kn = d.ring_K[n], jo = d.ring_joff[n];
+        if (d.fold_P) {
+            const int Pf = d.fold_P;
+            for (int s = threadIdx.x; s < Pf; s += blockDim.x) {
+                float2 acc = make_float2(0.f, 0.f);
+                for (int k = s; k <= Kn; k += Pf)
+                    acc = cadd(acc, cmul(d.syn_pre[k], mul_ipow(cscale(sa[k], d.Jw[jo + k]), k)));
+                sb[s] = acc;
+            }
+            __syncthreads();
+            fft_lds<kMaxB>(sb, Pf, 1, fsyn, tws, true);
+            for (int q = threadIdx.x; q < D; q += blockDim.x) ot[q * RT + r] = sb[q].x;
+        } else {
+            for (int q = threadIdx.x; q < S; q += blockDim.x)
+                sb[q] = q <= Kn ? cmul(d.syn_pre[q], mul_ipow(cscale(sa[q], d.Jw[jo + q]), q)) : make_float2(0.f, 0.f);
+            __syncthreads();
+            fft_lds<kMaxB>(sb, S, 1, fsyn, tws, false);
+            for (int q = threadIdx.x; q < S; q += blockDim.x) sb[q] = cmul(sb[q], d.czt_vhat[q]);
+            __syncthreads();
+            fft_lds<kMaxB>(sb, S, 1, fsyn, tws, true);
+            for (int q = threadIdx.x; q < D; q += blockDim.x) {
+                const float2 v = sb[q], w = d.czt_post[q];
+                ot[q * RT + r] = w.x * v.x - w.y * v.y;
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    fft_lds<kMaxB>(sm, 2 * P, 1, d.ffts[d.ring_fft[n]], d.tw, false);
-    const int Kn = d.ring_K[n], jo = d.ring_joff[n];
-    for (int k = threadIdx.x; k <= Kn; k += blockDim.x) {
-        const float2 v = cscale(sm[k], d.Jw[jo + k]);
-        float2 o;
-        switch (k & 3) {  // multiply by i^k
-            case 0: o = v; break;
-            case 1: o = make_float2(-v.y, v.x); break;
-            case 2: o = make_float2(-v.x, -v.y); break;
-            default: o = make_float2(v.y, -v.x); break;
-        }
-        bm[(size_t)n * d.Kp + k] = o;
+    for (int e = threadIdx.x; e < D * nr; e += blockDim.x) {
+        const int q = e / nr, r = e - q * nr;
+        hT[(size_t)q * d.nlam + n0 + r] = ot[q * RT + r];
     }
 }
 
-// ---------------------------------------------------------------------------
-// cosine transform per mode (shared by forward and adjoint)
-//   forward (adj = 0): in = b [nlam][Kp] (row n-1 = lam_n), out = Bt [T][Kp]
-//   adjoint (adj = 1): in = Bt [T][Kp], out = b [nlam][Kp]
-// out(q) = sum_p in(p) cos(pi p q / M) = (X[q] + X[2M - q]) / 2, X = FFT_2M(in).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(512) void k_dct(PlanDev d, WsLayout L, InstPtrs wsp, int MT, int adj)
+__global__ __launch_bounds__(1024) void k_ring_adj(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
 {
     extern __shared__ float2 sm[];
-    const int b = blockIdx.y;
-    const int twoM = 2 * d.M, Kp = d.Kp;
+    const int ntile = (d.nlam + RT - 1) / RT;
+    const int item = xcd_item(blockIdx.x, ntile * batch);
+    if (item < 0) return;
+    const int b = item / ntile, tile = item - b * ntile;
     char* wb = wsp.ws + (size_t)b * wsp.stride;
-    const float2* in = (const float2*)(wb + (adj ? L.tmodes : L.modes));
-    float2* out = (float2*)(wb + (adj ? L.modes : L.tmodes));
-    const int nin = adj ? d.T : d.nlam;
-    const int nout = adj ? d.nlam : d.T;
-    const int k0 = blockIdx.x * MT;
-    const int mt = min(MT, Kp - k0);
-    for (int e = threadIdx.x; e < mt * twoM; e += blockDim.x) sm[e] = make_float2(0.f, 0.f);
-    __syncthreads();
-    for (int e = threadIdx.x; e < nin * mt; e += blockDim.x) {
-        const int p = e / mt, kk = e - p * mt, k = k0 + kk;   // p = row index (0-based), lambda/t index p+1
-        const bool keep = adj ? true : (p >= d.mode_nmin[k]);
-        if (keep) sm[kk * twoM + p + 1] = in[(size_t)p * Kp + k];
+    const float* hT = (const float*)(wb + L.hdet);
+    float2* H = (float2*)(wb + L.polar);
+    const int D = d.D, S = d.syn_len;
+    float2* sa = sm;
+    float2* sb = sm + d.npsi_max;
+    float* it = (float*)(sb + S);             // [D][RT]
+    float2* twr_s = (float2*)(it + ((D * RT + 1) & ~1));
+    float2* tws_s = twr_s + tw_lds_slots(d.npsi_max);
+    const int n0 = tile * RT;
+    const int nr = min(RT, d.nlam - n0);
+    const FftDev& fsyn = d.ffts[d.fft_syn];
+    const TwLds tws = tw_lds_build(tws_s, fsyn, d.tw);
+    for (int e = threadIdx.x; e < D * nr; e += blockDim.x) {
+        const int q = e / nr, r = e - q * nr;
+        it[q * RT + r] = hT[(size_t)q * d.nlam + n0 + r];
     }
     __syncthreads();
-    fft_lds<kMaxB>(sm, twoM, mt, d.ffts[d.fft_dct], d.tw, false);
-    for (int e = threadIdx.x; e < nout * mt; e += blockDim.x) {
-        const int q = e / mt, kk = e - q * mt, k = k0 + kk;
-        if (adj && q < d.mode_nmin[k]) continue;
-        const int s = q + 1;
-        const float2 a = sm[kk * twoM + s], c = sm[kk * twoM + (twoM - s)];
-        out[(size_t)q * Kp + k] = make_float2(0.5f * (a.x + c.x), 0.5f * (a.y + c.y));
+    for (int r = 0; r < nr; ++r) {
+        const int n = n0 + r;
+        const int off = d.ring_off[n], P = d.ring_off[n + 1] - off, np = 2 * P;
+        const int Kn = d.ring_K[n], jo = d.ring_joff[n];
+        const TwLds twr = tw_lds_build(twr_s, d.ffts[d.ring_fft[n]], d.tw);
+        if (d.fold_P) {
+            const int Pf = d.fold_P;
+            for (int s = threadIdx.x; s < Pf; s += blockDim.x)
+                sb[s] = make_float2(s < D ? it[s * RT + r] : 0.f, 0.f);
+            __syncthreads();
+            fft_lds<kMaxB>(sb, Pf, 1, fsyn, tws, false);
+            for (int k = threadIdx.x; k < np; k += blockDim.x) {
+                float2 o = make_float2(0.f, 0.f);
+                if (k <= Kn) {
+                    int s = k;
+                    while (s >= Pf) s -= Pf;
+                    // conj(pre0_k i^k) Jw_k * y~_{k mod P}
+                    o = cscale(mul_ipow(cmulc(sb[s], d.syn_pre[k]), (4 - (k & 3)) & 3), d.Jw[jo + k]);
+                }
+                sa[k] = o;
+            }
+        } else {
+            for (int q = threadIdx.x; q < S; q += blockDim.x)
+                sb[q] = q < D ? cmulc(make_float2(it[q * RT + r], 0.f), d.czt_post[q]) : make_float2(0.f, 0.f);
+            __syncthreads();
+            fft_lds<kMaxB>(sb, S, 1, fsyn, tws, false);
+            for (int q = threadIdx.x; q < S; q += blockDim.x) sb[q] = cmulc(sb[q], d.czt_vhat[q]);
+            __syncthreads();
+            fft_lds<kMaxB>(sb, S, 1, fsyn, tws, true);
+            for (int k = threadIdx.x; k < np; k += blockDim.x) {
+                float2 o = make_float2(0.f, 0.f);
+                if (k <= Kn) o = cscale(mul_ipow(cmulc(sb[k], d.syn_pre[k]), (4 - (k & 3)) & 3), d.Jw[jo + k]);
+                sa[k] = o;
+            }
+        }
+        __syncthreads();
+        fft_lds<kMaxB>(sa, np, 1, d.ffts[d.ring_fft[n]], twr, true);
+        for (int l = threadIdx.x; l < P; l += blockDim.x) {
+            const float2 a = sa[l], c = sa[l + P];
+            const float2 hh = make_float2(a.x + c.x, a.y - c.y);  // F~(l) + conj F~(l + P)
+            H[d.perm[off + l]] = cmulc(hh, d.pt_phase[off + l]);
+        }
+        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// forward: chirp-z synthesis over detector angles, per time sample
+// Cosine transform over radial frequencies, per detector, two detectors packed
+// as the real and imaginary parts of one complex sequence (the transform is
+// real):  out(q) = sum_p in(p) cos(pi p q / M) = (X[q] + X[2M - q]) / 2 with
+// X = FFT_2M of the zero-padded input (p, q >= 1).
+//   forward: hT [D][nlam] -> g [D][T] (+ kappa * mass)
+//   adjoint: g [D][T] -> hT [D][nlam] (+ per-workgroup partial sums of g)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(512) void k_czt_fwd(PlanDev d, WsLayout L, InstPtrs wsp, float* __restrict__ g,
-                                                 int TT, int PAR, int n_mass)
+__global__ __launch_bounds__(1024) void k_dct_det(PlanDev d, WsLayout L, InstPtrs wsp, float* __restrict__ gout,
+                                                  const float* __restrict__ gin, int DP, int adj, int n_mass, int batch)
 {
     extern __shared__ float2 sm[];
+    __shared__ float red_s[1024];
     __shared__ float mass_s;
-    const int b = blockIdx.y;
-    const int Ln = d.L, Kp = d.Kp, D = d.D, T = d.T;
+    const int ntile = ((d.D + 1) / 2 + DP - 1) / DP;
+    const int item = xcd_item(blockIdx.x, ntile * batch);
+    if (item < 0) return;
+    const int b = item / ntile, tile = item - b * ntile;
+    const int twoM = 2 * d.M, D = d.D, T = d.T, NL = d.nlam;
     char* wb = wsp.ws + (size_t)b * wsp.stride;
-    const float2* Bt = (const float2*)(wb + L.tmodes);
-    const float* red = (const float*)(wb + L.red);
-    float* ot = (float*)(sm + PAR * Ln);  // [D][TT]
-    float* gb = g + (size_t)b * D * T;
-    if (threadIdx.x == 0) {
+    float* hT = (float*)(wb + L.hdet);
+    float* red = (float*)(wb + L.red);
+    const int p0 = tile * DP;                        // first detector pair
+    const int np = min(DP, (D + 1) / 2 - p0);
+    const int nin = adj ? T : NL;
+    const int nout = adj ? NL : T;
+    const float* src = adj ? gin + (size_t)b * D * T : hT;
+    const int sld = adj ? T : NL;
+    if (!adj && threadIdx.x == 0) {
         float m = 0.f;
         for (int t = 0; t < n_mass; ++t) m += red[t];
         mass_s = m;
     }
-    const int j0 = blockIdx.x * TT;
-    const int nt = min(TT, T - j0);
-    const FftDev& fd = d.ffts[d.fft_czt];
-    for (int jb = 0; jb < nt; jb += PAR) {
-        const int np = min(PAR, nt - jb);
-        for (int e = threadIdx.x; e < np * Ln; e += blockDim.x) {
-            const int p = e / Ln, q = e - p * Ln;
-            float2 v = make_float2(0.f, 0.f);
-            if (q < Kp) v = cmul(d.czt_pre[q], Bt[(size_t)(j0 + jb + p) * Kp + q]);
-            sm[e] = v;
-        }
-        __syncthreads();
-        fft_lds<kMaxB>(sm, Ln, np, fd, d.tw, false);
-        for (int e = threadIdx.x; e < np * Ln; e += blockDim.x) {
-            const int q = e % Ln;
-            sm[e] = cmul(sm[e], d.czt_vhat[q]);
-        }
-        __syncthreads();
-        fft_lds<kMaxB>(sm, Ln, np, fd, d.tw, true);
-        const float km = d.kappa * mass_s;
-        for (int e = threadIdx.x; e < np * D; e += blockDim.x) {
-            const int p = e / D, q = e - p * D;
-            const float2 s = sm[p * Ln + q], w = d.czt_post[q];
-            ot[q * TT + jb + p] = (w.x * s.x - w.y * s.y) + km;
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < D * nt; e += blockDim.x) {
-        const int q = e / nt, tt = e - q * nt;
-        gb[(size_t)q * T + j0 + tt] = ot[q * TT + tt];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// adjoint: chirp-z transpose, detectors -> modes, per time sample
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(512) void k_czt_adj(PlanDev d, WsLayout L, InstPtrs wsp, const float* __restrict__ g,
-                                                 int TT, int PAR)
-{
-    extern __shared__ float2 sm[];
-    __shared__ float red_s[512];
-    const int b = blockIdx.y;
-    const int Ln = d.L, Kp = d.Kp, D = d.D, T = d.T;
-    char* wb = wsp.ws + (size_t)b * wsp.stride;
-    float2* Bt = (float2*)(wb + L.tmodes);
-    float* red = (float*)(wb + L.red);
-    float* it = (float*)(sm + PAR * Ln);  // [D][TT]
-    const float* gb = g + (size_t)b * D * T;
-    const int j0 = blockIdx.x * TT;
-    const int nt = min(TT, T - j0);
+    const TwLds tw = tw_lds_build(sm + DP * twoM, d.ffts[d.fft_dct], d.tw);
+    for (int e = threadIdx.x; e < np * twoM; e += blockDim.x) sm[e] = make_float2(0.f, 0.f);
+    __syncthreads();
     float ls = 0.f;
-    for (int e = threadIdx.x; e < D * nt; e += blockDim.x) {
-        const int q = e / nt, tt = e - q * nt;
-        const float v = gb[(size_t)q * T + j0 + tt];
-        it[q * TT + tt] = v;
-        ls += v;
+    for (int e = threadIdx.x; e < np * nin; e += blockDim.x) {
+        const int p = e / nin, q = e - p * nin;
+        const int d0 = 2 * (p0 + p);
+        const float re = src[(size_t)d0 * sld + q];
+        const float im = (d0 + 1 < D) ? src[(size_t)(d0 + 1) * sld + q] : 0.f;
+        ls += re + im;
+        sm[p * twoM + q + 1] = make_float2(re, im);
     }
-    const float tot = block_sum(ls, red_s);
-    if (threadIdx.x == 0) red[blockIdx.x] = tot;
-    __syncthreads();
-    const FftDev& fd = d.ffts[d.fft_czt];
-    for (int jb = 0; jb < nt; jb += PAR) {
-        const int np = min(PAR, nt - jb);
-        for (int e = threadIdx.x; e < np * Ln; e += blockDim.x) {
-            const int p = e / Ln, q = e - p * Ln;
-            float2 v = make_float2(0.f, 0.f);
-            if (q < D) v = cmulc(make_float2(it[q * TT + jb + p], 0.f), d.czt_post[q]);
-            sm[e] = v;
-        }
-        __syncthreads();
-        fft_lds<kMaxB>(sm, Ln, np, fd, d.tw, false);
-        for (int e = threadIdx.x; e < np * Ln; e += blockDim.x) {
-            const int q = e % Ln;
-            sm[e] = cmulc(sm[e], d.czt_vhat[q]);
-        }
-        __syncthreads();
-        fft_lds<kMaxB>(sm, Ln, np, fd, d.tw, true);
-        for (int e = threadIdx.x; e < np * Kp; e += blockDim.x) {
-            const int p = e / Kp, k = e - p * Kp;
-            Bt[(size_t)(j0 + jb + p) * Kp + k] = cmulc(sm[p * Ln + k], d.czt_pre[k]);
-        }
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------
-// adjoint: ring kernel (conjugate weight, inverse angular FFT, fold, phase)
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(512) void k_ring_adj(PlanDev d, WsLayout L, InstPtrs wsp)
-{
-    extern __shared__ float2 sm[];
-    const int b = blockIdx.y, n = blockIdx.x;
-    char* wb = wsp.ws + (size_t)b * wsp.stride;
-    const float2* bm = (const float2*)(wb + L.modes);
-    float2* H = (float2*)(wb + L.polar);
-    const int off = d.ring_off[n], P = d.ring_off[n + 1] - off, np = 2 * P;
-    const int Kn = d.ring_K[n], jo = d.ring_joff[n];
-    for (int e = threadIdx.x; e < np; e += blockDim.x) {
-        float2 o = make_float2(0.f, 0.f);
-        if (e <= Kn) {
-            const float2 v = cscale(bm[(size_t)n * d.Kp + e], d.Jw[jo + e]);
-            switch (e & 3) {  // multiply by (-i)^k
-                case 0: o = v; break;
-                case 1: o = make_float2(v.y, -v.x); break;
-                case 2: o = make_float2(-v.x, -v.y); break;
-                default: o = make_float2(-v.y, v.x); break;
-            }
-        }
-        sm[e] = o;
+    if (adj) {
+        const float tot = block_sum(ls, red_s);
+        if (threadIdx.x == 0) red[tile] = tot;
     }
     __syncthreads();
-    fft_lds<kMaxB>(sm, np, 1, d.ffts[d.ring_fft[n]], d.tw, true);
-    for (int l = threadIdx.x; l < P; l += blockDim.x) {
-        const float2 a = sm[l], c = sm[l + P];
-        const float2 hh = make_float2(a.x + c.x, a.y - c.y);  // F~(l) + conj F~(l + P)
-        H[d.perm[off + l]] = cmulc(hh, d.pt_phase[off + l]);
+    fft_lds<kMaxB>(sm, twoM, np, d.ffts[d.fft_dct], tw, false);
+    const float add = adj ? 0.f : d.kappa * mass_s;
+    float* dst = adj ? hT : gout + (size_t)b * D * T;
+    const int dld = adj ? NL : T;
+    for (int e = threadIdx.x; e < np * nout; e += blockDim.x) {
+        const int p = e / nout, q = e - p * nout;
+        const int d0 = 2 * (p0 + p);
+        const float2 a = sm[p * twoM + q + 1], c = sm[p * twoM + twoM - q - 1];
+        dst[(size_t)d0 * dld + q] = 0.5f * (a.x + c.x) + add;
+        if (d0 + 1 < D) dst[(size_t)(d0 + 1) * dld + q] = 0.5f * (a.y + c.y) + add;
     }
 }
 
@@ -466,7 +495,7 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev d, WsLayout L, InstPtrs 
 // ---------------------------------------------------------------------------
 // adjoint: row pass (inverse FFT along x, crop to the N image columns)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(512) void k_rowpass_adj(PlanDev d, WsLayout L, InstPtrs wsp, int RPB)
+__global__ __launch_bounds__(1024) void k_rowpass_adj(PlanDev d, WsLayout L, InstPtrs wsp, int RPB)
 {
     extern __shared__ float2 sm[];
     const int b = blockIdx.y;
@@ -476,9 +505,10 @@ __global__ __launch_bounds__(512) void k_rowpass_adj(PlanDev d, WsLayout L, Inst
     float2* X1 = (float2*)(wb + L.x1);
     const int r0 = blockIdx.x * RPB;
     const int nr = min(RPB, d.Hy - r0);
+    const TwLds tw = tw_lds_build(sm + RPB * Ng, d.ffts[d.fft_grid], d.tw);
     for (int e = threadIdx.x; e < nr * Ng; e += blockDim.x) sm[e] = Gt[(size_t)r0 * Ng + e];
     __syncthreads();
-    fft_lds<kMaxB>(sm, Ng, nr, d.ffts[d.fft_grid], d.tw, true);
+    fft_lds<kMaxB>(sm, Ng, nr, d.ffts[d.fft_grid], tw, true);
     for (int e = threadIdx.x; e < nr * N; e += blockDim.x) {
         const int rr = e / N, j = e - rr * N;
         int pos = j - N / 2;
@@ -491,7 +521,7 @@ __global__ __launch_bounds__(512) void k_rowpass_adj(PlanDev d, WsLayout L, Inst
 // adjoint: column pass (Hermitian symmetrisation, inverse FFT along y, real
 // parts of two columns packed as one complex transform, crop, deapodise, mask)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(512) void k_colpass_adj(PlanDev d, WsLayout L, InstPtrs wsp, float* __restrict__ f,
+__global__ __launch_bounds__(1024) void k_colpass_adj(PlanDev d, WsLayout L, InstPtrs wsp, float* __restrict__ f,
                                                      int NP, int n_sum)
 {
     extern __shared__ float2 sm[];
@@ -509,6 +539,7 @@ __global__ __launch_bounds__(512) void k_colpass_adj(PlanDev d, WsLayout L, Inst
     }
     const int j0 = blockIdx.x * CT;
     const int top = Ng / 2 + 4;
+    const TwLds tw = tw_lds_build(sm + NP * Ng, d.ffts[d.fft_grid], d.tw);
     for (int e = threadIdx.x; e < NP * Ng; e += blockDim.x) {
         const int p = e / Ng, q = e - p * Ng;
         const int ja = j0 + 2 * p, jb = ja + 1;
@@ -531,7 +562,7 @@ __global__ __launch_bounds__(512) void k_colpass_adj(PlanDev d, WsLayout L, Inst
         sm[e] = make_float2(ha.x - hb.y, ha.y + hb.x);
     }
     __syncthreads();
-    fft_lds<kMaxB>(sm, Ng, NP, d.ffts[d.fft_grid], d.tw, true);
+    fft_lds<kMaxB>(sm, Ng, NP, d.ffts[d.fft_grid], tw, true);
     const float kt = d.kappa * d.h2 * gsum_s;
     for (int e = threadIdx.x; e < N * CT; e += blockDim.x) {
         const int i = e / CT, jj = e - i * CT, j = j0 + jj;

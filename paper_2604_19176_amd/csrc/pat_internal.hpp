@@ -53,21 +53,23 @@ struct PlanDev {
     const int* ring_fft;    // [nlam]   FFT descriptor of Npsi(n)
     const int* ring_joff;   // [nlam]   offset of ring n in Jw
     const float* Jw;        // ragged: J_k(lam_n R) W_n / Npsi(n), k = 0..K_n
-    const int* mode_nmin;   // [Kp]     first (0-based) ring with K_n >= k
     // polar points, band order (sorted by (r0, bx)) for the deterministic spread
     const int* perm;        // [npts]   ring-order index -> band-order slot
     const float4* bpt_geo;  // [npts]   same fields as pt_geo, band order
     const int* band_ptr;    // [NB][Ng + 1] CSR: first band-order slot with (r0, bx' >= bx)
-    // chirp-z synthesis over detector angles
-    const float2* czt_pre;  // [Kp]  c_k e^{i k theta_0} w^{k^2}, c_0 = 1, c_k = 2
-    const float2* czt_post; // [D]   w^{d^2}
-    const float2* czt_vhat; // [L]   FFT_L of the chirp filter w^{-m^2}, divided by L
+    // synthesis over detector angles theta_d = theta_0 + d dtheta
+    int fold_P;             // P if dtheta = 2 pi / P (P = 2^a3^b >= D): fold k mod P, one FFT; else 0
+    int syn_len;            // P (fold) or the chirp-z FFT length L >= K + D (Bluestein)
+    const float2* syn_pre;  // [Kp]  c_k e^{i k theta_0} (fold) or c_k e^{i k theta_0} w^{k^2} (Bluestein); c_0 = 1, c_k = 2
+    const float2* czt_post; // [D]   w^{d^2}, w = e^{i dtheta/2} (Bluestein only)
+    const float2* czt_vhat; // [L]   FFT_L of the chirp filter w^{-m^2}, divided by L (Bluestein only)
+    int npsi_max;           // largest per-ring angular grid
     // FFTs
     const FftDev* ffts;
     const float2* tw;
     int fft_grid;  // length Ng
     int fft_dct;   // length 2M
-    int fft_czt;   // length L
+    int fft_syn;   // length syn_len
     int pad0;
 };
 
@@ -75,9 +77,8 @@ struct PlanDev {
 struct LaunchCfg {
     int col_np;      // packed column pairs per column-pass workgroup
     int row_rpb;     // rows per row-pass workgroup
-    int dct_mt;      // modes per DCT workgroup
-    int czt_tt;      // time samples per chirp-z workgroup
-    int czt_par;     // chirp-z FFTs in flight per workgroup
+    int ring_rt;     // rings per ring-kernel workgroup
+    int dct_dp;      // detector pairs per cosine-transform workgroup
     int spr_cb;      // spread: columns per workgroup (multiple of 64)
     int spr_th;      // spread: rows per workgroup
     int spr_cap;     // spread: points staged in LDS per chunk
@@ -87,8 +88,7 @@ struct LaunchCfg {
 struct WsLayout {
     size_t x1;       // [Hy][N]   float2   column-pass output / row-pass-adjoint output
     size_t grid;     // [Hy][Ng]  float2   spectrum / spread target
-    size_t modes;    // [nlam][Kp] float2  ring output / DCT-adjoint output
-    size_t tmodes;   // [T][Kp]   float2   DCT output / chirp-z-adjoint output
+    size_t hdet;     // [D][nlam] float    ring output (synthesised at the detectors) / cosine-adjoint output
     size_t polar;    // [npts]    float2   spread input (band order)
     size_t red;      // small FP32 partial sums (mass / data sum)
     int n_red;       // number of partial sums
@@ -108,9 +108,15 @@ struct pat_plan {
     double dlam;
     double kappa;
     int n_psi_max;
+    int n_ring_modes;
     size_t table_bytes;
     void* table_mem;        // one device allocation holding every table
     int n_col_tiles;        // column-pass tiles (mass partials)
-    int n_time_tiles;       // chirp-z tiles (data-sum partials)
-    int thr_col, thr_row, thr_ring, thr_dct, thr_czt;  // workgroup sizes of the FFT kernels
+    int n_pair_tiles;       // cosine-transform tiles (data-sum partials)
+    int thr_col, thr_row, thr_ring, thr_dct;  // workgroup sizes of the FFT kernels
+    size_t lds_ring;        // dynamic LDS of the ring kernels
+    // optional per-kernel timing (pat_profile_enable): events around each launch
+    int prof;
+    hipEvent_t ev[2][8];
+    int ev_count[2];
 };

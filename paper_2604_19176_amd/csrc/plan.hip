@@ -31,12 +31,19 @@ long smooth23(double x, int multiple_of)
     return best;
 }
 
-// Radix plan for n = 2^a 3^b: radix-4 stages first, then one radix-2, then radix-3.
+// Radix plan for n = 2^a 3^b: radix-8 stages, then 4 x 4 / 4 / 2 for the rest of
+// the power of two (a radix-2 stage only when a = 1), then radix-3 stages.
 static int radix_plan(long n, unsigned char* rad)
 {
+    int a = 0;
+    while (n % 2 == 0) { ++a; n /= 2; }
     int ns = 0;
-    while (n % 4 == 0) { rad[ns++] = 4; n /= 4; }
-    while (n % 2 == 0) { rad[ns++] = 2; n /= 2; }
+    int q = a / 3, r = a % 3;
+    if (r == 1 && q >= 1) { q -= 1; r = 4; }  // 2^(3q+1) = 8^(q-1) * 4 * 4
+    for (int i = 0; i < q; ++i) rad[ns++] = 8;
+    if (r == 4) { rad[ns++] = 4; rad[ns++] = 4; }
+    else if (r == 2) rad[ns++] = 4;
+    else if (r == 1) rad[ns++] = 2;
     while (n % 3 == 0) { rad[ns++] = 3; n /= 3; }
     return n == 1 ? ns : -1;
 }
@@ -54,12 +61,12 @@ static void host_fft(std::vector<cd>& x)
         const long nb = n / R;
         for (long j = 0; j < nb; ++j) {
             long k = j % Ns;
-            cd v[4];
+            cd v[8];
             for (int r = 0; r < R; ++r) {
                 double ang = -2.0 * PI * (double)(k * r) / (double)(Ns * R);
                 v[r] = x[j + r * nb] * cd(std::cos(ang), std::sin(ang));
             }
-            cd o[4];
+            cd o[8];
             for (int a = 0; a < R; ++a) {
                 o[a] = 0;
                 for (int r = 0; r < R; ++r) {
@@ -154,7 +161,7 @@ static std::vector<double> es_hat(int N, int Ng)
 }
 
 struct Derived {
-    int M, n_lam, K, n_psi, Ng, L;
+    int M, n_lam, K, n_psi, Ng, L, P;
     double h, dlam, kappa;
 };
 
@@ -177,8 +184,14 @@ static int derive(const pat_plan_desc* d, Derived* o)
     o->kappa = d->em_correction ? o->dlam * o->dlam / (24.0 * PI) : 0.0;
     o->Ng = (int)smooth23(2.0 * d->n, 2);
     o->L = (int)smooth23((double)o->K + d->n_det, 1);
+    {   // detector pitch dtheta = 2 pi / P with P = 2^a 3^b >= D: synthesis by one FFT of length P
+        double Pd = 2.0 * PI * d->n_det / d->arc_span;
+        long Pi = std::lround(Pd);
+        o->P = (std::fabs(Pd - (double)Pi) < 1e-9 * Pd && Pi >= d->n_det && smooth23((double)Pi, 1) == Pi &&
+                Pi <= 8192) ? (int)Pi : 0;
+    }
     // limits of the kernels: every FFT length must fit the LDS plans
-    if (d->n < 16 || o->Ng > 8192 || 2L * o->M > 8192 || o->L > 8192 || o->n_psi > 8192)
+    if (d->n < 16 || o->Ng > 8192 || 2L * o->M > 8192 || (!o->P && o->L > 8192) || o->n_psi > 8192)
         return PAT_ERR_UNSUPPORTED;
     if (o->n_lam >= 2 * o->M) return PAT_ERR_UNSUPPORTED;  // cosine grid index n < 2M
     return PAT_OK;
@@ -232,53 +245,50 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 namespace pat {
 
+// Threads for `nseq` sequences of one length: tps per sequence (4 butterflies
+// per thread per stage, rounded to 32); at least 128 threads in total.
 static int fft_threads(int nseq, const FftDev& fd)
 {
-    const int need = (nseq * fft_max_butterflies(fd) + 7) / 8;  // 8 butterflies per thread per stage
-    int t = ((need + 63) / 64) * 64;
-    return std::max(128, std::min(512, t));
+    int tps = fft_min_tps(fd, 4);
+    tps = ((tps + 31) / 32) * 32;
+    while (nseq * tps < 128) tps += 32;
+    return nseq * tps;
 }
 
 // Launch shapes: LDS per workgroup <= 64 KB and every FFT stage fits
-// 512 threads x 8 butterflies.
+// 1024 threads x 4 butterflies.
 int choose_launch(pat_plan* p, const std::vector<FftDev>& fd, int max_ring_bf)
 {
     const PlanDev& d = p->dev;
     LaunchCfg& c = p->cfg;
     const size_t kLds = 64 * 1024;
-    const int kBf = 512 * 8;
     const FftDev& fg = fd[d.fft_grid];
     const FftDev& fm = fd[d.fft_dct];
-    const FftDev& fc = fd[d.fft_czt];
-    auto pick = [&](int maxn, size_t bytes_each, int bf_each) {
+    const FftDev& fs = fd[d.fft_syn];
+    auto pick = [&](int maxn, size_t bytes_each, const FftDev& f, size_t fixed) {
+        const int tps = (fft_min_tps(f, 4) + 31) / 32 * 32;
         int v = maxn;
-        while (v > 1 && (v * bytes_each > kLds || v * bf_each > kBf)) --v;
-        return (v * bytes_each <= kLds && v * bf_each <= kBf) ? v : 0;
+        while (v > 1 && (v * bytes_each + fixed > kLds || v * tps > 1024)) --v;
+        return (v * bytes_each + fixed <= kLds && v * tps <= 1024) ? v : 0;
     };
-    c.col_np = pick(8, sizeof(float2) * d.Ng, fft_max_butterflies(fg));
-    c.row_rpb = pick(8, sizeof(float2) * d.Ng, fft_max_butterflies(fg));
-    c.dct_mt = pick(8, sizeof(float2) * 2 * d.M, fft_max_butterflies(fm));
-    c.czt_tt = 16;
-    while (c.czt_tt > 1 && (size_t)d.D * c.czt_tt * 4 > kLds / 2) c.czt_tt /= 2;
-    {
-        size_t rest = kLds - (size_t)d.D * c.czt_tt * 4;
-        int v = 4;
-        while (v > 1 && ((size_t)v * sizeof(float2) * d.L > rest || v * fft_max_butterflies(fc) > kBf)) --v;
-        c.czt_par = ((size_t)v * sizeof(float2) * d.L <= rest && v * fft_max_butterflies(fc) <= kBf) ? v : 0;
-    }
+    auto twb = [](int n) { return sizeof(float2) * (size_t)tw_lds_slots(n); };
+    c.col_np = pick(8, sizeof(float2) * d.Ng, fg, twb(d.Ng));
+    c.row_rpb = pick(8, sizeof(float2) * d.Ng, fg, twb(d.Ng));
+    c.dct_dp = pick(4, sizeof(float2) * 2 * d.M, fm, twb(2 * d.M));
+    // ring kernels: angular FFT buffer + synthesis buffer + [D][RT] detector tile + twiddles
+    const size_t base = sizeof(float2) * ((size_t)d.npsi_max + d.syn_len) + twb(d.npsi_max) + twb(d.syn_len);
+    c.ring_rt = 1;
+    p->lds_ring = base + (((size_t)d.D * c.ring_rt + 1) & ~(size_t)1) * 4;
     c.spr_cb = 64;
     c.spr_th = 32;
     c.spr_cap = 256;
-    if (!c.col_np || !c.row_rpb || !c.dct_mt || !c.czt_par) return PAT_ERR_UNSUPPORTED;
-    if ((size_t)p->n_psi_max * sizeof(float2) > kLds || max_ring_bf > kBf) return PAT_ERR_UNSUPPORTED;
+    if (!c.col_np || !c.row_rpb || !c.dct_dp || p->lds_ring > kLds) return PAT_ERR_UNSUPPORTED;
+    const int ring_tps = std::max(max_ring_bf, fft_min_tps(fs, 4));
     p->thr_col = fft_threads(c.col_np, fg);
     p->thr_row = fft_threads(c.row_rpb, fg);
-    p->thr_dct = fft_threads(c.dct_mt, fm);
-    p->thr_czt = fft_threads(c.czt_par, fc);
-    {
-        const int need = (max_ring_bf + 7) / 8;
-        p->thr_ring = std::max(128, std::min(512, ((need + 63) / 64) * 64));
-    }
+    p->thr_dct = fft_threads(c.dct_dp, fm);
+    p->thr_ring = std::max(256, ((ring_tps + 63) / 64) * 64);
+    if (p->thr_ring > 1024) return PAT_ERR_UNSUPPORTED;
     return PAT_OK;
 }
 
@@ -289,12 +299,11 @@ void layout_workspace(pat_plan* p)
     size_t o = 0;
     w.x1 = o;     o += align256(sizeof(float2) * (size_t)d.Hy * d.N);
     w.grid = o;   o += align256(sizeof(float2) * (size_t)d.Hy * d.Ng);
-    w.modes = o;  o += align256(sizeof(float2) * (size_t)d.nlam * d.Kp);
-    w.tmodes = o; o += align256(sizeof(float2) * (size_t)d.T * d.Kp);
+    w.hdet = o;   o += align256(sizeof(float) * (size_t)d.D * d.nlam);
     w.polar = o;  o += align256(sizeof(float2) * (size_t)d.npts);
     p->n_col_tiles = (d.N + 2 * p->cfg.col_np - 1) / (2 * p->cfg.col_np);
-    p->n_time_tiles = (d.T + p->cfg.czt_tt - 1) / p->cfg.czt_tt;
-    w.n_red = std::max(p->n_col_tiles, p->n_time_tiles);
+    p->n_pair_tiles = ((d.D + 1) / 2 + p->cfg.dct_dp - 1) / p->cfg.dct_dp;
+    w.n_red = std::max(p->n_col_tiles, p->n_pair_tiles);
     w.red = o;    o += align256(sizeof(float) * (size_t)w.n_red);
     w.bytes = o;
 }
@@ -315,7 +324,7 @@ extern "C" int pat_plan_derive(const pat_plan_desc* desc, pat_plan_info* out)
     out->n_psi = dv.n_psi;
     out->kappa = dv.kappa;
     out->n_grid = dv.Ng;
-    out->len_czt = dv.L;
+    out->len_czt = dv.P ? dv.P : dv.L;
     return PAT_OK;
 }
 
@@ -334,14 +343,16 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     const int N = desc->n, Ng = dv.Ng, nlam = dv.n_lam, K = dv.K, D = desc->n_det, T = desc->n_t;
     const double h = dv.h, R = desc->det_r;
     d.N = N; d.Ng = Ng; d.Hy = Ng / 2 + 9; d.nlam = nlam; d.K = K; d.Kp = K + 1; d.M = dv.M;
-    d.T = T; d.D = D; d.L = dv.L; d.NB = Ng / 2 + 2;
+    d.T = T; d.D = D; d.L = dv.P ? 0 : dv.L; d.NB = Ng / 2 + 2;
     d.kappa = (float)dv.kappa;
     d.h2 = (float)(h * h);
 
     FftSet ffts;
     d.fft_grid = ffts.get(Ng);
     d.fft_dct = ffts.get(2L * dv.M);
-    d.fft_czt = ffts.get(dv.L);
+    d.fold_P = dv.P;
+    d.syn_len = dv.P ? dv.P : dv.L;
+    d.fft_syn = ffts.get(d.syn_len);
 
     // --- image-side tables -------------------------------------------------
     std::vector<double> ph = es_hat(N, Ng);
@@ -383,12 +394,10 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
         npsi_max = std::max(npsi_max, np);
     }
     ringOff[nlam] = npts;
+    p->n_ring_modes = joff;
+    d.npsi_max = npsi_max;
     d.npts = npts;
     p->n_psi_max = npsi_max;
-    std::vector<int> nmin(K + 1, nlam);
-    for (int k = 0; k <= K; ++k)
-        for (int n = 0; n < nlam; ++n)
-            if (ringK[n] >= k) { nmin[k] = n; break; }
 
     // radial weights J_k(lam_n R) W_n / Npsi(n)
     std::vector<float> Jw(joff);
@@ -456,25 +465,28 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
         }
     }
 
-    // --- chirp-z tables over detector angles --------------------------------
+    // --- synthesis over detector angles --------------------------------------
     const double dth = desc->arc_span / D;
     const double th0 = desc->arc_center - 0.5 * desc->arc_span + 0.5 * dth;
-    const int L = dv.L;
-    auto wpow = [&](long m) {  // w^{m^2}, w = e^{i dth/2}; reduce the phase mod 2 pi in FP64
+    auto wpow = [&](long m) {  // w^{m^2}, w = e^{i dth/2}; phase reduced mod 2 pi in FP64
         double a = std::fmod(0.5 * dth * (double)m * (double)m, 2.0 * PI);
         return cd(std::cos(a), std::sin(a));
     };
-    std::vector<float2> pre(K + 1), post(D), vhat(L);
+    std::vector<float2> pre(K + 1), post, vhat;
     for (int k = 0; k <= K; ++k) {
         double a = std::fmod(k * th0, 2.0 * PI);
-        cd v = (k == 0 ? 1.0 : 2.0) * cd(std::cos(a), std::sin(a)) * wpow(k);
+        cd v = (k == 0 ? 1.0 : 2.0) * cd(std::cos(a), std::sin(a));
+        if (!dv.P) v *= wpow(k);
         pre[k] = make_float2((float)v.real(), (float)v.imag());
     }
-    for (int q = 0; q < D; ++q) {
-        cd v = wpow(q);
-        post[q] = make_float2((float)v.real(), (float)v.imag());
-    }
-    {
+    if (!dv.P) {
+        const int L = dv.L;
+        post.resize(D);
+        vhat.resize(L);
+        for (int q = 0; q < D; ++q) {
+            cd v = wpow(q);
+            post[q] = make_float2((float)v.real(), (float)v.imag());
+        }
         std::vector<cd> v(L, cd(0, 0));
         for (long m = -K; m <= D - 1; ++m) v[((m % L) + L) % L] = std::conj(wpow(m));
         host_fft(v);
@@ -483,7 +495,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
 
     {
         int max_ring_bf = 0;
-        for (int n = 0; n < nlam; ++n) max_ring_bf = std::max(max_ring_bf, fft_max_butterflies(ffts.descs[ringFft[n]]));
+        for (int n = 0; n < nlam; ++n) max_ring_bf = std::max(max_ring_bf, fft_min_tps(ffts.descs[ringFft[n]], 4));
         int rc = choose_launch(p, ffts.descs, max_ring_bf);
         if (rc != PAT_OK) return rc;
     }
@@ -492,7 +504,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     size_t o_deap = tb.add(deap), o_mask = tb.add(mask);
     size_t o_geo = tb.add(geo), o_phase = tb.add(phase);
     size_t o_roff = tb.add(ringOff), o_rk = tb.add(ringK), o_rfft = tb.add(ringFft), o_rj = tb.add(ringJoff);
-    size_t o_jw = tb.add(Jw), o_nmin = tb.add(nmin);
+    size_t o_jw = tb.add(Jw);
     size_t o_perm = tb.add(perm), o_bgeo = tb.add(bgeo), o_bptr = tb.add(bptr);
     size_t o_pre = tb.add(pre), o_post = tb.add(post), o_vhat = tb.add(vhat);
     size_t o_ffts = tb.add(ffts.descs), o_tw = tb.add(ffts.tw);
@@ -507,11 +519,10 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     d.ring_fft = (const int*)off(o_rfft);
     d.ring_joff = (const int*)off(o_rj);
     d.Jw = (const float*)off(o_jw);
-    d.mode_nmin = (const int*)off(o_nmin);
     d.perm = (const int*)off(o_perm);
     d.bpt_geo = (const float4*)off(o_bgeo);
     d.band_ptr = (const int*)off(o_bptr);
-    d.czt_pre = (const float2*)off(o_pre);
+    d.syn_pre = (const float2*)off(o_pre);
     d.czt_post = (const float2*)off(o_post);
     d.czt_vhat = (const float2*)off(o_vhat);
     d.ffts = (const FftDev*)off(o_ffts);
@@ -546,8 +557,8 @@ extern "C" int pat_plan_create(const pat_plan_desc* desc, pat_plan** out)
     PlanDev& d = p->dev;
     auto rel = [&](auto& ptr) { ptr = (std::remove_reference_t<decltype(ptr)>)(base + (uintptr_t)ptr); };
     rel(d.deap); rel(d.mask_rows); rel(d.pt_geo); rel(d.pt_phase); rel(d.ring_off); rel(d.ring_K);
-    rel(d.ring_fft); rel(d.ring_joff); rel(d.Jw); rel(d.mode_nmin); rel(d.perm); rel(d.bpt_geo);
-    rel(d.band_ptr); rel(d.czt_pre); rel(d.czt_post); rel(d.czt_vhat); rel(d.ffts); rel(d.tw);
+    rel(d.ring_fft); rel(d.ring_joff); rel(d.Jw); rel(d.perm); rel(d.bpt_geo);
+    rel(d.band_ptr); rel(d.syn_pre); rel(d.czt_post); rel(d.czt_vhat); rel(d.ffts); rel(d.tw);
     p->max_batch = desc->max_batch;
     p->n_psi_uniform = dv.n_psi;
     p->M = dv.M;
@@ -570,15 +581,19 @@ extern "C" int pat_plan_query(const pat_plan* p, pat_plan_info* out)
     out->kappa = p->kappa;
     out->n_grid = p->dev.Ng;
     out->n_points = p->dev.npts;
-    out->len_czt = p->dev.L;
+    out->len_czt = p->dev.syn_len;
+    out->n_ring_modes = p->n_ring_modes;
     out->workspace_per_instance = p->ws.bytes;
     out->table_bytes = p->table_bytes;
     return PAT_OK;
 }
 
+extern "C" int pat_profile_enable(pat_plan* p, int enable);
+
 extern "C" void pat_plan_destroy(pat_plan* p)
 {
     if (!p) return;
+    (void)pat_profile_enable(p, 0);
     if (p->table_mem) {
         int cur = 0;
         if (hipGetDevice(&cur) != hipSuccess) cur = p->device;

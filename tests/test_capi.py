@@ -39,7 +39,11 @@ def test_derived_sizes_match_oracle(patlib, oracle_mod, cfg):
     assert info.dlam == pytest.approx(ref["dlam"], rel=1e-15)
     assert info.kappa == pytest.approx(ref["kappa"], rel=1e-15)
     assert info.n_grid >= 2 * geom.n and info.n_grid % 2 == 0
-    assert info.len_czt >= info.K + geom.n_det
+    pitch_turns = geom.n_det * 2 * math.pi / geom.arc_span   # 2 pi / dtheta
+    if abs(pitch_turns - round(pitch_turns)) < 1e-9 * pitch_turns and info.len_czt == round(pitch_turns):
+        assert info.len_czt >= geom.n_det            # one FFT of length P after folding modes mod P
+    else:
+        assert info.len_czt >= info.K + geom.n_det   # Bluestein chirp-z
 
 
 def test_derived_sizes_random_geometries(patlib, oracle_mod):
