@@ -27,7 +27,7 @@ if ROOT not in sys.path:
 
 METRIC = "A+A* operator pairs/sec at 256² FP32 (rel L2 ≤1e-5 vs FP64); batched vs single"
 HBM_PEAK_GBS = 8000.0
-FWD_NAMES = ["colpass_fwd", "rowpass_fwd", "ring_fwd", "dct_fwd"]
+FWD_NAMES = ["colpass_fwd", "rowpass_fwd", "gather", "ring_fwd", "dct_fwd"]
 ADJ_NAMES = ["dct_adj", "ring_adj", "spread", "rowpass_adj", "colpass_adj"]
 
 
@@ -43,7 +43,8 @@ def algorithmic_bytes(info, geom):
     return {
         "colpass_fwd": 4 * N * N + c8 * Hy * N,
         "rowpass_fwd": c8 * Hy * N + c8 * Hy * Ng,
-        "ring_fwd": c8 * Hy * Ng + 24 * P + 4 * D * NL,
+        "gather": c8 * Hy * Ng + 24 * P + c8 * P,
+        "ring_fwd": c8 * P + 4 * D * NL,
         "dct_fwd": 4 * D * NL + 4 * D * T,
         "dct_adj": 4 * D * T + 4 * D * NL,
         "ring_adj": 4 * D * NL + 12 * P + c8 * P,

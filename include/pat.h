@@ -141,8 +141,8 @@ int  pat_residual(float* g, const float* g_meas, float* sq, long count_per, int 
  * microseconds of overhead; 0 disables and frees the events).
  * pat_profile_read waits for the last call of direction `which` (0 = forward,
  * 1 = adjoint) to finish and writes its kernel durations in milliseconds to
- * ms[0..*count-1], in launch order (forward: column pass, row pass, ring
- * (interpolation, angular FFT, weights, detector synthesis), cosine transform;
+ * ms[0..*count-1], in launch order (forward: column pass, row pass, polar
+ * interpolation, ring (angular FFT, weights, detector synthesis), cosine transform;
  * adjoint: cosine transform, ring, spread, row pass, column pass).  Errors: PAT_ERR_ARG (NULL, profiling off,
  * max_kernels too small), PAT_ERR_HIP. */
 int  pat_profile_enable(pat_plan* plan, int enable);

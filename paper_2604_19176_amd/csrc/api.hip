@@ -54,15 +54,25 @@ extern "C" int pat_forward(const pat_plan* p, const float* f, float* g, int batc
                        sizeof(float2) * c.row_rpb * d.Ng + twb(d.Ng), st, d, p->ws, wsp, c.row_rpb);
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, 2, st);
+    {
+        int cb = c.gat_cb, th = c.gat_th;
+        const long wide = (long)((d.Ng + 255) / 256) * ((d.NB + 31) / 32) * batch;
+        if (wide >= 512) { cb = 256; th = 32; }
+        const int items = ((d.Ng + cb - 1) / cb) * ((d.NB + th - 1) / th) * batch;
+        hipLaunchKernelGGL(k_gather, dim3(xcd_grid(items)), dim3(cb), sizeof(float2) * 8 * (cb + 7), st, d, p->ws, wsp,
+                           th, batch);
+    }
+    if ((rc = check_launch())) return rc;
+    prof_mark(p, 0, 3, st);
     hipLaunchKernelGGL(k_ring_fwd, dim3(xcd_grid((d.nlam + c.ring_rt - 1) / c.ring_rt * batch)), dim3(p->thr_ring),
                        p->lds_ring, st, d, p->ws, wsp, c.ring_rt, batch);
     if ((rc = check_launch())) return rc;
-    prof_mark(p, 0, 3, st);
+    prof_mark(p, 0, 4, st);
     hipLaunchKernelGGL(k_dct_det, dim3(xcd_grid(p->n_pair_tiles * batch)), dim3(p->thr_dct),
                        sizeof(float2) * c.dct_dp * 2 * d.M + twb(2 * d.M), st, d, p->ws, wsp, g, (const float*)nullptr, c.dct_dp, 0,
                        p->n_col_tiles, batch);
     if ((rc = check_launch())) return rc;
-    prof_mark(p, 0, 4, st);
+    prof_mark(p, 0, 5, st);
     return PAT_OK;
 }
 
@@ -85,8 +95,15 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
                        p->lds_ring, st, d, p->ws, wsp, c.ring_rt, batch);
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 2, st);
-    hipLaunchKernelGGL(k_spread, dim3((d.Ng + c.spr_cb - 1) / c.spr_cb, (d.Hy + c.spr_th - 1) / c.spr_th, batch),
-                       dim3(c.spr_cb), sizeof(float) * 19 * c.spr_cap, st, d, p->ws, wsp, c.spr_th, c.spr_cap);
+    {
+        // wide tiles amortise the per-band weight evaluation; narrow ones keep small batches parallel
+        int cb = c.spr_cb, th = c.spr_th;
+        const long wide = (long)((d.Ng + 255) / 256) * ((d.Hy + 15) / 16) * batch;
+        if (wide >= 1024) { cb = 256; th = 16; }
+        const int items = ((d.Ng + cb - 1) / cb) * ((d.Hy + th - 1) / th) * batch;
+        hipLaunchKernelGGL(k_spread, dim3(xcd_grid(items)), dim3(cb), sizeof(float) * 19 * 2 * cb, st, d, p->ws, wsp,
+                           th, 2 * cb, batch);
+    }
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 3, st);
     hipLaunchKernelGGL(k_rowpass_adj, dim3((d.Hy + c.row_rpb - 1) / c.row_rpb, batch), dim3(p->thr_row),
@@ -142,7 +159,7 @@ extern "C" int pat_profile_enable(pat_plan* p, int enable)
         for (int dir = 0; dir < 2; ++dir)
             for (int q = 0; q < 8; ++q)
                 if (hipEventCreate(&p->ev[dir][q]) != hipSuccess) return PAT_ERR_HIP;
-        p->ev_count[0] = 5;  // 4 forward kernels
+        p->ev_count[0] = 6;  // 5 forward kernels
         p->ev_count[1] = 6;  // 5 adjoint kernels
         p->prof = 1;
     } else if (!enable && p->prof) {

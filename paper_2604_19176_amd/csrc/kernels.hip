@@ -157,8 +157,8 @@ __global__ __launch_bounds__(1024) void k_rowpass_fwd(PlanDev d, WsLayout L, Ins
 // ---------------------------------------------------------------------------
 // Ring kernels.  One workgroup handles RT consecutive radial frequencies
 // (rings) of one instance, one ring after another:
-//   forward: ES interpolation of the half spectrum at the ring's half-plane
-//            points, completion F(l + Npsi/2) = conj F(l), angular FFT,
+//   forward: the ring's interpolated half-plane values (k_gather), completion
+//            F(l + Npsi/2) = conj F(l), angular FFT,
 //            a_k = c_k e^{i k theta_0} i^k J_k(lam_n R) W_n F_k / Npsi (k <= K_n),
 //            synthesis over detectors h(d) = Re sum_k a_k e^{i k d dtheta}
 //            (one inverse FFT of length P after folding k mod P when
@@ -167,6 +167,75 @@ __global__ __launch_bounds__(1024) void k_rowpass_fwd(PlanDev d, WsLayout L, Ins
 //   adjoint: the exact transpose, ending with the Hermitian fold and the
 //            conjugate half-pixel phase -> H (band order) for the spread.
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// forward: ES interpolation of the half spectrum at the half-plane polar
+// points, in band order (points sorted by footprint base row r0, then by
+// base column bx).  A workgroup owns the points with r0 in [R0, R0 + TH) and
+// bx in [C0, C0 + CB); it keeps the 8 spectrum rows r0 .. r0 + 7 of columns
+// C0 .. C0 + CB + 6 in an LDS ring buffer (one coalesced row load per band)
+// and each thread interpolates one point from LDS.  Output Fb[slot] (band
+// order) times the half-pixel phase.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gather(PlanDev d, WsLayout L, InstPtrs wsp, int TH, int batch)
+{
+    extern __shared__ float2 win[];  // [8][W]
+    const int Ng = d.Ng, NB = d.NB, Hy = d.Hy;
+    const int CB = blockDim.x, W = CB + 7;
+    const int ncb = (Ng + CB - 1) / CB, nrb = (NB + TH - 1) / TH;
+    const int item = xcd_item(blockIdx.x, ncb * nrb * batch);
+    if (item < 0) return;
+    const int b = item / (ncb * nrb);
+    const int rbk = (item - b * ncb * nrb) / ncb, cbk = item - b * ncb * nrb - rbk * ncb;
+    const int C0 = cbk * CB, R0 = rbk * TH;
+    const int rend = min(R0 + TH, NB);
+    const int cend = min(C0 + CB, Ng);
+    char* wb = wsp.ws + (size_t)b * wsp.stride;
+    const float2* __restrict__ G = (const float2*)(wb + L.grid);
+    float2* Fb = (float2*)(wb + L.polar);
+    // rows R0 .. R0 + 6 of the window
+    for (int e = threadIdx.x; e < 7 * W; e += CB) {
+        const int rr = e / W, cc = e - rr * W;
+        const int r = R0 + rr;
+        const int c = (C0 + cc) % Ng;  // the window may wrap around the periodic grid
+        win[(r & 7) * W + cc] = r < Hy ? G[(size_t)r * Ng + c] : make_float2(0.f, 0.f);
+    }
+    for (int rb = R0; rb < rend; ++rb) {
+        {
+            const int r = rb + 7;  // <= NB - 1 + 7 = Hy - 1
+            for (int cc = threadIdx.x; cc < W; cc += CB) {
+                const int c = (C0 + cc) % Ng;
+                win[(r & 7) * W + cc] = G[(size_t)r * Ng + c];
+            }
+        }
+        __syncthreads();
+        const int* bp = d.band_ptr + (size_t)rb * (Ng + 1);
+        const int lo = bp[C0], hi = bp[cend];
+        for (int s = lo + threadIdx.x; s < hi; s += CB) {
+            const float4 gq = d.bpt_geo[s];
+            const int c0 = fbits(gq.x) - C0;
+            float wx[8], wy[8];
+            es_weights8(gq.z, wx);
+            es_weights8(gq.w, wy);
+            float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int dy = 0; dy < 8; ++dy) {
+                const float2* row = win + ((rb + dy) & 7) * W + c0;
+                float2 ra = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int dx = 0; dx < 8; ++dx) {
+                    const float2 gv = row[dx];
+                    ra.x += wx[dx] * gv.x;
+                    ra.y += wx[dx] * gv.y;
+                }
+                acc.x += wy[dy] * ra.x;
+                acc.y += wy[dy] * ra.y;
+            }
+            Fb[s] = cmul(acc, d.bpt_phase[s]);
+        }
+        __syncthreads();
+    }
+}
+
 __device__ __forceinline__ float2 mul_ipow(float2 v, int k)  // v * i^k
 {
     switch (k & 3) {
@@ -185,9 +254,9 @@ __global__ __launch_bounds__(1024) void k_ring_fwd(PlanDev d, WsLayout L, InstPt
     if (item < 0) return;
     const int b = item / ntile, tile = item - b * ntile;
     char* wb = wsp.ws + (size_t)b * wsp.stride;
-    const float2* __restrict__ G = (const float2*)(wb + L.grid);
+    const float2* __restrict__ Fp = (const float2*)(wb + L.polar);
     float* hT = (float*)(wb + L.hdet);
-    const int Ng = d.Ng, D = d.D, S = d.syn_len;
+    const int D = d.D, S = d.syn_len;
     float2* sa = sm;                          // [npsi_max]
     float2* sb = sm + d.npsi_max;             // [S]
     float* ot = (float*)(sb + S);             // [D][RT]
@@ -202,32 +271,7 @@ __global__ __launch_bounds__(1024) void k_ring_fwd(PlanDev d, WsLayout L, InstPt
         const int off = d.ring_off[n], P = d.ring_off[n + 1] - off;
         const TwLds twr = tw_lds_build(twr_s, d.ffts[d.ring_fft[n]], d.tw);
         for (int l = threadIdx.x; l < P; l += blockDim.x) {
-            const float4 gq = d.pt_geo[off + l];
-            const int bx = fbits(gq.x), r0 = fbits(gq.y);
-            float wx[8], wy[8];
-            es_weights8(gq.z, wx);
-            es_weights8(gq.w, wy);
-            int cols[8];
-#pragma unroll
-            for (int dx = 0; dx < 8; ++dx) {
-                int c = bx + dx;
-                cols[dx] = c >= Ng ? c - Ng : c;
-            }
-            float2 acc = make_float2(0.f, 0.f);
-#pragma unroll
-            for (int dy = 0; dy < 8; ++dy) {
-                const float2* row = G + (size_t)(r0 + dy) * Ng;
-                float2 ra = make_float2(0.f, 0.f);
-#pragma unroll
-                for (int dx = 0; dx < 8; ++dx) {
-                    const float2 gv = row[cols[dx]];
-                    ra.x += wx[dx] * gv.x;
-                    ra.y += wx[dx] * gv.y;
-                }
-                acc.x += wy[dy] * ra.x;
-                acc.y += wy[dy] * ra.y;
-            }
-            const float2 F = cmul(acc, d.pt_phase[off + l]);
+            const float2 F = Fp[d.perm[off + l]];
             sa[l] = F;
             sa[l + P] = cconj(F);
         }
@@ -404,13 +448,86 @@ __global__ __launch_bounds__(1024) void k_dct_det(PlanDev d, WsLayout L, InstPtr
 // adjoint: deterministic spread of the polar half-plane values onto G~ [Hy][Ng]
 // One lane owns one column; bands (footprint base rows) are swept in order and
 // an 8-row register window accumulates; band points are staged in LDS with
-// their ES weights.  Every output is a fixed-order sum.
+// their ES weights.  Every output is a fixed-order sum.  The next band's
+// ranges and first points are fetched into registers while the current band
+// is processed.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_spread(PlanDev d, WsLayout L, InstPtrs wsp, int TH, int CAP)
+struct BandMeta {
+    int aLo, nA, bLo, ntot, lo, hi;
+};
+
+__device__ __forceinline__ BandMeta band_meta(const PlanDev& d, int rb, int C0, int mx, bool active)
+{
+    const int Ng = d.Ng;
+    const int* bp = d.band_ptr + (size_t)rb * (Ng + 1);
+    const int lo_col = C0 - 7, hi_col = min(C0 + (int)blockDim.x, Ng);
+    BandMeta m;
+    m.aLo = lo_col < 0 ? bp[Ng + lo_col] : 0;
+    const int aHi = lo_col < 0 ? bp[Ng] : 0;
+    m.bLo = bp[max(lo_col, 0)];
+    const int bHi = bp[hi_col];
+    m.nA = aHi - m.aLo;
+    m.ntot = m.nA + (bHi - m.bLo);
+    m.lo = m.hi = 0;
+    if (active) {
+        const int c = mx - 7;
+        m.lo = c < 0 ? (bp[Ng + c] - m.aLo) : (m.nA + bp[c] - m.bLo);
+        m.hi = m.nA + bp[mx + 1] - m.bLo;
+    }
+    return m;
+}
+
+__device__ __forceinline__ int band_slot(const BandMeta& m, int idx)
+{
+    return idx < m.nA ? m.aLo + idx : m.bLo + (idx - m.nA);
+}
+
+__device__ __forceinline__ void spread_stage(float* wxs, float* wys, float2* hs, int* bxs, int e, float4 gq, float2 h)
+{
+    float w[8];
+    es_weights8(gq.z, w);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) wxs[e * 8 + k] = w[k];
+    es_weights8(gq.w, w);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) wys[e * 8 + k] = w[k];
+    hs[e] = h;
+    bxs[e] = fbits(gq.x);
+}
+
+__device__ __forceinline__ void spread_visit(const float* wxs, const float* wys, const float2* hs, const int* bxs,
+                                             int s0, int s1, int c0, int mx, int Ng, float2 (&acc)[8])
+{
+    for (int s = s0; s < s1; ++s) {
+        const int e = s - c0;
+        int dx = mx - bxs[e];
+        if (dx < 0) dx += Ng;
+        const float w = wxs[e * 8 + dx];
+        const float2 t = cscale(hs[e], w);
+        const float4 wa = *(const float4*)&wys[e * 8];
+        const float4 wb4 = *(const float4*)&wys[e * 8 + 4];
+        acc[0].x += wa.x * t.x; acc[0].y += wa.x * t.y;
+        acc[1].x += wa.y * t.x; acc[1].y += wa.y * t.y;
+        acc[2].x += wa.z * t.x; acc[2].y += wa.z * t.y;
+        acc[3].x += wa.w * t.x; acc[3].y += wa.w * t.y;
+        acc[4].x += wb4.x * t.x; acc[4].y += wb4.x * t.y;
+        acc[5].x += wb4.y * t.x; acc[5].y += wb4.y * t.y;
+        acc[6].x += wb4.z * t.x; acc[6].y += wb4.z * t.y;
+        acc[7].x += wb4.w * t.x; acc[7].y += wb4.w * t.y;
+    }
+}
+
+// CAP must be 2 * blockDim.x (two staged points per thread per chunk).
+__global__ __launch_bounds__(256) void k_spread(PlanDev d, WsLayout L, InstPtrs wsp, int TH, int CAP, int batch)
 {
     extern __shared__ float sf[];
-    const int b = blockIdx.z;
     const int Ng = d.Ng, NB = d.NB, Hy = d.Hy;
+    const int CB = blockDim.x;
+    const int ncb = (Ng + CB - 1) / CB, nrb = (Hy + TH - 1) / TH;
+    const int item = xcd_item(blockIdx.x, ncb * nrb * batch);
+    if (item < 0) return;
+    const int b = item / (ncb * nrb);
+    const int rb_ = (item - b * ncb * nrb) / ncb, cb_ = item - b * ncb * nrb - rb_ * ncb;
     char* wb = wsp.ws + (size_t)b * wsp.stride;
     const float2* __restrict__ H = (const float2*)(wb + L.polar);
     float2* Gt = (float2*)(wb + L.grid);
@@ -418,8 +535,7 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev d, WsLayout L, InstPtrs 
     float* wys = sf + CAP * 8;             // [CAP][8]
     float2* hs = (float2*)(sf + CAP * 16); // [CAP]
     int* bxs = (int*)(sf + CAP * 18);      // [CAP]
-    const int CB = blockDim.x;
-    const int C0 = blockIdx.x * CB, R0 = blockIdx.y * TH;
+    const int C0 = cb_ * CB, R0 = rb_ * TH;
     const int mx = C0 + threadIdx.x;
     const bool active = mx < Ng;
     const int rend = min(R0 + TH, Hy);
@@ -427,55 +543,40 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev d, WsLayout L, InstPtrs 
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc[k] = make_float2(0.f, 0.f);
     const int band_lo = max(0, R0 - 7), band_hi = min(NB - 1, rend - 1);
-    const int lo_col = C0 - 7;
-    const int hi_col = min(C0 + CB, Ng);  // exclusive
+    const int e0 = threadIdx.x, e1 = threadIdx.x + CB;
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    BandMeta nm;
+    float4 ng0 = zero4, ng1 = zero4;
+    float2 nh0 = make_float2(0.f, 0.f), nh1 = nh0;
+    if (band_lo <= band_hi) {
+        nm = band_meta(d, band_lo, C0, mx, active);
+        if (e0 < nm.ntot) { const int sl = band_slot(nm, e0); ng0 = d.bpt_geo[sl]; nh0 = H[sl]; }
+        if (e1 < nm.ntot) { const int sl = band_slot(nm, e1); ng1 = d.bpt_geo[sl]; nh1 = H[sl]; }
+    }
     for (int rb = band_lo; rb <= band_hi; ++rb) {
-        const int* bp = d.band_ptr + (size_t)rb * (Ng + 1);
-        const int aLo = lo_col < 0 ? bp[Ng + lo_col] : 0;
-        const int aHi = lo_col < 0 ? bp[Ng] : 0;
-        const int bLo = bp[max(lo_col, 0)], bHi = bp[hi_col];
-        const int nA = aHi - aLo, ntot = nA + (bHi - bLo);
-        int lo = 0, hi = 0;
-        if (active) {
-            const int c = mx - 7;
-            lo = c < 0 ? (bp[Ng + c] - aLo) : (nA + bp[c] - bLo);
-            hi = nA + bp[mx + 1] - bLo;
+        const BandMeta m = nm;
+        const float4 g0 = ng0, g1 = ng1;
+        const float2 h0 = nh0, h1 = nh1;
+        if (rb < band_hi) {  // prefetch the next band
+            nm = band_meta(d, rb + 1, C0, mx, active);
+            if (e0 < nm.ntot) { const int sl = band_slot(nm, e0); ng0 = d.bpt_geo[sl]; nh0 = H[sl]; }
+            if (e1 < nm.ntot) { const int sl = band_slot(nm, e1); ng1 = d.bpt_geo[sl]; nh1 = H[sl]; }
         }
-        for (int c0 = 0; c0 < ntot; c0 += CAP) {
-            const int cn = min(CAP, ntot - c0);
-            for (int e = threadIdx.x; e < cn; e += blockDim.x) {
-                const int idx = c0 + e;
-                const int slot = idx < nA ? aLo + idx : bLo + (idx - nA);
-                const float4 gq = d.bpt_geo[slot];
-                float w[8];
-                es_weights8(gq.z, w);
-#pragma unroll
-                for (int k = 0; k < 8; ++k) wxs[e * 8 + k] = w[k];
-                es_weights8(gq.w, w);
-#pragma unroll
-                for (int k = 0; k < 8; ++k) wys[e * 8 + k] = w[k];
-                hs[e] = H[slot];
-                bxs[e] = fbits(gq.x);
+        // chunk 0 from registers
+        if (e0 < m.ntot) spread_stage(wxs, wys, hs, bxs, e0, g0, h0);
+        if (e1 < m.ntot) spread_stage(wxs, wys, hs, bxs, e1, g1, h1);
+        __syncthreads();
+        spread_visit(wxs, wys, hs, bxs, m.lo, min(m.hi, CAP), 0, mx, Ng, acc);
+        __syncthreads();
+        // further chunks (dense bands only)
+        for (int c0 = CAP; c0 < m.ntot; c0 += CAP) {
+            const int cn = min(CAP, m.ntot - c0);
+            for (int e = threadIdx.x; e < cn; e += CB) {
+                const int sl = band_slot(m, c0 + e);
+                spread_stage(wxs, wys, hs, bxs, e, d.bpt_geo[sl], H[sl]);
             }
             __syncthreads();
-            const int s0 = max(lo, c0), s1 = min(hi, c0 + cn);
-            for (int s = s0; s < s1; ++s) {
-                const int e = s - c0;
-                int dx = mx - bxs[e];
-                if (dx < 0) dx += Ng;
-                const float w = wxs[e * 8 + dx];
-                const float2 t = cscale(hs[e], w);
-                const float4 wa = *(const float4*)&wys[e * 8];
-                const float4 wb4 = *(const float4*)&wys[e * 8 + 4];
-                acc[0].x += wa.x * t.x; acc[0].y += wa.x * t.y;
-                acc[1].x += wa.y * t.x; acc[1].y += wa.y * t.y;
-                acc[2].x += wa.z * t.x; acc[2].y += wa.z * t.y;
-                acc[3].x += wa.w * t.x; acc[3].y += wa.w * t.y;
-                acc[4].x += wb4.x * t.x; acc[4].y += wb4.x * t.y;
-                acc[5].x += wb4.y * t.x; acc[5].y += wb4.y * t.y;
-                acc[6].x += wb4.z * t.x; acc[6].y += wb4.z * t.y;
-                acc[7].x += wb4.w * t.x; acc[7].y += wb4.w * t.y;
-            }
+            spread_visit(wxs, wys, hs, bxs, max(m.lo, c0), min(m.hi, c0 + cn), c0, mx, Ng, acc);
             __syncthreads();
         }
         // row rb is complete

@@ -56,6 +56,7 @@ struct PlanDev {
     // polar points, band order (sorted by (r0, bx)) for the deterministic spread
     const int* perm;        // [npts]   ring-order index -> band-order slot
     const float4* bpt_geo;  // [npts]   same fields as pt_geo, band order
+    const float2* bpt_phase;// [npts]   pt_phase in band order
     const int* band_ptr;    // [NB][Ng + 1] CSR: first band-order slot with (r0, bx' >= bx)
     // synthesis over detector angles theta_d = theta_0 + d dtheta
     int fold_P;             // P if dtheta = 2 pi / P (P = 2^a3^b >= D): fold k mod P, one FFT; else 0
@@ -79,6 +80,8 @@ struct LaunchCfg {
     int row_rpb;     // rows per row-pass workgroup
     int ring_rt;     // rings per ring-kernel workgroup
     int dct_dp;      // detector pairs per cosine-transform workgroup
+    int gat_cb;      // interpolation: columns per workgroup (multiple of 64)
+    int gat_th;      // interpolation: bands per workgroup
     int spr_cb;      // spread: columns per workgroup (multiple of 64)
     int spr_th;      // spread: rows per workgroup
     int spr_cap;     // spread: points staged in LDS per chunk

@@ -279,9 +279,11 @@ int choose_launch(pat_plan* p, const std::vector<FftDev>& fd, int max_ring_bf)
     const size_t base = sizeof(float2) * ((size_t)d.npsi_max + d.syn_len) + twb(d.npsi_max) + twb(d.syn_len);
     c.ring_rt = 1;
     p->lds_ring = base + (((size_t)d.D * c.ring_rt + 1) & ~(size_t)1) * 4;
+    c.gat_cb = 64;
+    c.gat_th = 16;
     c.spr_cb = 64;
     c.spr_th = 32;
-    c.spr_cap = 256;
+    c.spr_cap = 128;
     if (!c.col_np || !c.row_rpb || !c.dct_dp || p->lds_ring > kLds) return PAT_ERR_UNSUPPORTED;
     const int ring_tps = std::max(max_ring_bf, fft_min_tps(fs, 4));
     p->thr_col = fft_threads(c.col_np, fg);
@@ -448,7 +450,8 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     });
     std::vector<int> perm(npts);
     std::vector<float4> bgeo(npts);
-    for (int s = 0; s < npts; ++s) { perm[order[s]] = s; bgeo[s] = geo[order[s]]; }
+    std::vector<float2> bphase(npts);
+    for (int s = 0; s < npts; ++s) { perm[order[s]] = s; bgeo[s] = geo[order[s]]; bphase[s] = phase[order[s]]; }
     const int NB = d.NB;
     std::vector<int> bptr((size_t)NB * (Ng + 1));
     {
@@ -505,7 +508,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     size_t o_geo = tb.add(geo), o_phase = tb.add(phase);
     size_t o_roff = tb.add(ringOff), o_rk = tb.add(ringK), o_rfft = tb.add(ringFft), o_rj = tb.add(ringJoff);
     size_t o_jw = tb.add(Jw);
-    size_t o_perm = tb.add(perm), o_bgeo = tb.add(bgeo), o_bptr = tb.add(bptr);
+    size_t o_perm = tb.add(perm), o_bgeo = tb.add(bgeo), o_bph = tb.add(bphase), o_bptr = tb.add(bptr);
     size_t o_pre = tb.add(pre), o_post = tb.add(post), o_vhat = tb.add(vhat);
     size_t o_ffts = tb.add(ffts.descs), o_tw = tb.add(ffts.tw);
     // store offsets in the pointer fields; relocated after the upload
@@ -521,6 +524,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     d.Jw = (const float*)off(o_jw);
     d.perm = (const int*)off(o_perm);
     d.bpt_geo = (const float4*)off(o_bgeo);
+    d.bpt_phase = (const float2*)off(o_bph);
     d.band_ptr = (const int*)off(o_bptr);
     d.syn_pre = (const float2*)off(o_pre);
     d.czt_post = (const float2*)off(o_post);
@@ -557,7 +561,7 @@ extern "C" int pat_plan_create(const pat_plan_desc* desc, pat_plan** out)
     PlanDev& d = p->dev;
     auto rel = [&](auto& ptr) { ptr = (std::remove_reference_t<decltype(ptr)>)(base + (uintptr_t)ptr); };
     rel(d.deap); rel(d.mask_rows); rel(d.pt_geo); rel(d.pt_phase); rel(d.ring_off); rel(d.ring_K);
-    rel(d.ring_fft); rel(d.ring_joff); rel(d.Jw); rel(d.perm); rel(d.bpt_geo);
+    rel(d.ring_fft); rel(d.ring_joff); rel(d.Jw); rel(d.perm); rel(d.bpt_geo); rel(d.bpt_phase);
     rel(d.band_ptr); rel(d.syn_pre); rel(d.czt_post); rel(d.czt_vhat); rel(d.ffts); rel(d.tw);
     p->max_batch = desc->max_batch;
     p->n_psi_uniform = dv.n_psi;
