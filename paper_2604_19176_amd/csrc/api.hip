@@ -30,6 +30,7 @@ static int validate(const pat_plan* p, const void* in, const void* out, int batc
                     size_t ws_bytes)
 {
     if (!p || !in || !out) return PAT_ERR_ARG;
+    if (p->thr_col <= 0 || p->thr_row <= 0 || p->thr_dct <= 0 || p->thr_ring <= 0) return PAT_ERR_ARG;
     if (batch < 1 || batch > p->max_batch) return PAT_ERR_ARG;
     if (!ws || ((uintptr_t)ws & 255)) return PAT_ERR_WORKSPACE;
     if (ws_bytes < pat_workspace_size(p, batch)) return PAT_ERR_WORKSPACE;
@@ -64,8 +65,10 @@ extern "C" int pat_forward(const pat_plan* p, const float* f, float* g, int batc
     }
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, 3, st);
-    hipLaunchKernelGGL(k_ring_fwd, dim3(xcd_grid((d.nlam + c.ring_rt - 1) / c.ring_rt * batch)), dim3(p->thr_ring),
-                       p->lds_ring, st, d, p->ws, wsp, c.ring_rt, batch);
+    {
+        const dim3 grid(xcd_grid((d.nlam + c.ring_rt - 1) / c.ring_rt * batch)), blk(p->thr_ring);
+        hipLaunchKernelGGL(k_ring_fwd<4>, grid, blk, p->lds_ring, st, d, p->ws, wsp, c.ring_rt, batch);
+    }
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, 4, st);
     hipLaunchKernelGGL(k_dct_det, dim3(xcd_grid(p->n_pair_tiles * batch)), dim3(p->thr_dct),
@@ -91,8 +94,10 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
                        batch);
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 1, st);
-    hipLaunchKernelGGL(k_ring_adj, dim3(xcd_grid((d.nlam + c.ring_rt - 1) / c.ring_rt * batch)), dim3(p->thr_ring),
-                       p->lds_ring, st, d, p->ws, wsp, c.ring_rt, batch);
+    {
+        const dim3 grid(xcd_grid((d.nlam + c.ring_rt - 1) / c.ring_rt * batch)), blk(p->thr_ring);
+        hipLaunchKernelGGL(k_ring_adj<4>, grid, blk, p->lds_ring, st, d, p->ws, wsp, c.ring_rt, batch);
+    }
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 2, st);
     {

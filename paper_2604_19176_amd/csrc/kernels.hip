@@ -246,6 +246,42 @@ __device__ __forceinline__ float2 mul_ipow(float2 v, int k)  // v * i^k
     }
 }
 
+// Unpack one bin of a real length-2H DFT from Z = FFT_H(z), z(t) = q(2t) + i q(2t+1):
+//   Q_k = (Z_k + conj Z_{H-k}) / 2 - (i/2) w_{2H}^k (Z_k - conj Z_{H-k}),  0 <= k < H.
+__device__ __forceinline__ float2 real_unpack(const float2* Z, int H, int k, float2 wk)
+{
+    const float2 zk = Z[k];
+    const float2 zc = cconj(Z[k == 0 ? 0 : H - k]);
+    const float2 sm = cadd(zk, zc), df = csub(zk, zc);
+    const float2 t = cmul(wk, df);
+    return make_float2(0.5f * (sm.x + t.y), 0.5f * (sm.y - t.x));
+}
+
+// Layout of the ring kernels' dynamic LDS (float2 slots unless noted).
+struct RingLds {
+    float2 *sa, *sy, *sc, *twPs, *twNs, *twAs, *twBs;
+    float* tile;  // [D][RT] floats
+};
+
+__device__ __forceinline__ RingLds ring_lds(float2* sm, const PlanDev& d, int RT)
+{
+    RingLds r;
+    const int Pmax = d.npsi_max / 2;
+    const int S = d.syn_len;
+    const int B2 = S > Pmax ? S : Pmax;
+    const int B3 = d.syn_half ? S / 2 : 0;
+    r.sa = sm;
+    r.sy = r.sa + Pmax;
+    r.sc = r.sy + B2;
+    r.tile = (float*)(r.sc + B3);
+    r.twPs = (float2*)(r.tile + ((d.D * RT + 1) & ~1));
+    r.twNs = r.twPs + tw_lds_slots(Pmax);
+    r.twAs = r.twNs + tw_lds_slots(d.npsi_max);
+    r.twBs = r.twAs + tw_lds_slots(S);
+    return r;
+}
+
+template <int RB>
 __global__ __launch_bounds__(1024) void k_ring_fwd(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
 {
     extern __shared__ float2 sm[];
@@ -257,48 +293,78 @@ __global__ __launch_bounds__(1024) void k_ring_fwd(PlanDev d, WsLayout L, InstPt
     const float2* __restrict__ Fp = (const float2*)(wb + L.polar);
     float* hT = (float*)(wb + L.hdet);
     const int D = d.D, S = d.syn_len;
-    float2* sa = sm;                          // [npsi_max]
-    float2* sb = sm + d.npsi_max;             // [S]
-    float* ot = (float*)(sb + S);             // [D][RT]
-    float2* twr_s = (float2*)(ot + ((D * RT + 1) & ~1));  // ring-length twiddles (rebuilt per ring)
-    float2* tws_s = twr_s + tw_lds_slots(d.npsi_max);
+    const RingLds R = ring_lds(sm, d, RT);
+    float* ot = R.tile;
     const int n0 = tile * RT;
     const int nr = min(RT, d.nlam - n0);
-    const FftDev& fsyn = d.ffts[d.fft_syn];
-    const TwLds tws = tw_lds_build(tws_s, fsyn, d.tw);
+    // synthesis tables: fold with even P -> FFT of P/2 (twB) + twiddles of P (twA); else FFT of S (twA)
+    const TwLds twA = tw_lds_build(R.twAs, d.ffts[d.fft_syn], d.tw);
+    const TwLds twB = d.syn_half ? tw_lds_build(R.twBs, d.ffts[d.fft_synh], d.tw) : twA;
     for (int r = 0; r < nr; ++r) {
         const int n = n0 + r;
         const int off = d.ring_off[n], P = d.ring_off[n + 1] - off;
-        const TwLds twr = tw_lds_build(twr_s, d.ffts[d.ring_fft[n]], d.tw);
-        for (int l = threadIdx.x; l < P; l += blockDim.x) {
-            const float2 F = Fp[d.perm[off + l]];
-            sa[l] = F;
-            sa[l + P] = cconj(F);
+        const TwLds twP = tw_lds_build(R.twPs, d.ffts[d.ring_fft[n]], d.tw);   // FFT of length P
+        const TwLds twN = tw_lds_build(R.twNs, d.ffts[d.ring_twn[n]], d.tw);   // w_{2P}^k
+        // q(m) = Re F + Im F (m < P), Re F - Im F (m >= P) is real; pack z(t) = q(2t) + i q(2t+1)
+        for (int t = threadIdx.x; t < P; t += blockDim.x) {
+            float qv[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int m = 2 * t + u;
+                const bool lo = m < P;
+                const float2 F = Fp[d.perm[off + (lo ? m : m - P)]];
+                qv[u] = lo ? F.x + F.y : F.x - F.y;
+            }
+            R.sa[t] = make_float2(qv[0], qv[1]);
         }
         __syncthreads();
-        fft_lds<kMaxB>(sa, 2 * P, 1, d.ffts[d.ring_fft[n]], twr, false);
+        fft_lds<RB>(R.sa, P, 1, d.ffts[d.ring_fft[n]], twP, false);
         const int Kn = d.ring_K[n], jo = d.ring_joff[n];
+        // a_k = pre_k i^k Jw_k F_k, F_k = Q_k (k even) or i Q_k (k odd)
+        auto amode = [&](int k) {
+            float2 Q = real_unpack(R.sa, P, k, twN(k));
+            if (k & 1) Q = make_float2(-Q.y, Q.x);
+            return cmul(d.syn_pre[k], mul_ipow(cscale(Q, d.Jw[jo + k]), k));
+        };
         if (d.fold_P) {
             const int Pf = d.fold_P;
-            for (int s = threadIdx.x; s < Pf; s += blockDim.x) {
+            for (int sidx = threadIdx.x; sidx < Pf; sidx += blockDim.x) {
                 float2 acc = make_float2(0.f, 0.f);
-                for (int k = s; k <= Kn; k += Pf)
-                    acc = cadd(acc, cmul(d.syn_pre[k], mul_ipow(cscale(sa[k], d.Jw[jo + k]), k)));
-                sb[s] = acc;
+                for (int k = sidx; k <= Kn; k += Pf) acc = cadd(acc, amode(k));
+                R.sy[sidx] = acc;
             }
             __syncthreads();
-            fft_lds<kMaxB>(sb, Pf, 1, fsyn, tws, true);
-            for (int q = threadIdx.x; q < D; q += blockDim.x) ot[q * RT + r] = sb[q].x;
+            if (d.syn_half) {
+                // Re(IFFT_P(y)) as a half-length inverse FFT of the Hermitian part
+                const int H2 = Pf / 2;
+                for (int sidx = threadIdx.x; sidx < H2; sidx += blockDim.x) {
+                    const int s1 = sidx, s2 = sidx + H2;
+                    const float2 y1 = R.sy[s1], y1c = cconj(R.sy[s1 == 0 ? 0 : Pf - s1]);
+                    const float2 y2 = R.sy[s2], y2c = cconj(R.sy[Pf - s2]);
+                    const float2 h1 = cscale(cadd(y1, y1c), 0.5f), h2 = cscale(cadd(y2, y2c), 0.5f);
+                    const float2 E = cadd(h1, h2);
+                    const float2 O = cmulc(csub(h1, h2), twA(sidx));   // times e^{+2 pi i s / P}
+                    R.sc[sidx] = make_float2(E.x - O.y, E.y + O.x);    // E + i O
+                }
+                __syncthreads();
+                fft_lds<RB>(R.sc, H2, 1, d.ffts[d.fft_synh], twB, true);
+                for (int q = threadIdx.x; q < D; q += blockDim.x) {
+                    const float2 z = R.sc[q >> 1];
+                    ot[q * RT + r] = (q & 1) ? z.y : z.x;
+                }
+            } else {
+                fft_lds<RB>(R.sy, Pf, 1, d.ffts[d.fft_syn], twA, true);
+                for (int q = threadIdx.x; q < D; q += blockDim.x) ot[q * RT + r] = R.sy[q].x;
+            }
         } else {
-            for (int q = threadIdx.x; q < S; q += blockDim.x)
-                sb[q] = q <= Kn ? cmul(d.syn_pre[q], mul_ipow(cscale(sa[q], d.Jw[jo + q]), q)) : make_float2(0.f, 0.f);
+            for (int q = threadIdx.x; q < S; q += blockDim.x) R.sy[q] = q <= Kn ? amode(q) : make_float2(0.f, 0.f);
             __syncthreads();
-            fft_lds<kMaxB>(sb, S, 1, fsyn, tws, false);
-            for (int q = threadIdx.x; q < S; q += blockDim.x) sb[q] = cmul(sb[q], d.czt_vhat[q]);
+            fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, false);
+            for (int q = threadIdx.x; q < S; q += blockDim.x) R.sy[q] = cmul(R.sy[q], d.czt_vhat[q]);
             __syncthreads();
-            fft_lds<kMaxB>(sb, S, 1, fsyn, tws, true);
+            fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, true);
             for (int q = threadIdx.x; q < D; q += blockDim.x) {
-                const float2 v = sb[q], w = d.czt_post[q];
+                const float2 v = R.sy[q], w = d.czt_post[q];
                 ot[q * RT + r] = w.x * v.x - w.y * v.y;
             }
         }
@@ -310,6 +376,7 @@ __global__ __launch_bounds__(1024) void k_ring_fwd(PlanDev d, WsLayout L, InstPt
     }
 }
 
+template <int RB>
 __global__ __launch_bounds__(1024) void k_ring_adj(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
 {
     extern __shared__ float2 sm[];
@@ -319,17 +386,14 @@ __global__ __launch_bounds__(1024) void k_ring_adj(PlanDev d, WsLayout L, InstPt
     const int b = item / ntile, tile = item - b * ntile;
     char* wb = wsp.ws + (size_t)b * wsp.stride;
     const float* hT = (const float*)(wb + L.hdet);
-    float2* H = (float2*)(wb + L.polar);
+    float2* Hb = (float2*)(wb + L.polar);
     const int D = d.D, S = d.syn_len;
-    float2* sa = sm;
-    float2* sb = sm + d.npsi_max;
-    float* it = (float*)(sb + S);             // [D][RT]
-    float2* twr_s = (float2*)(it + ((D * RT + 1) & ~1));
-    float2* tws_s = twr_s + tw_lds_slots(d.npsi_max);
+    const RingLds R = ring_lds(sm, d, RT);
+    float* it = R.tile;
     const int n0 = tile * RT;
     const int nr = min(RT, d.nlam - n0);
-    const FftDev& fsyn = d.ffts[d.fft_syn];
-    const TwLds tws = tw_lds_build(tws_s, fsyn, d.tw);
+    const TwLds twA = tw_lds_build(R.twAs, d.ffts[d.fft_syn], d.tw);
+    const TwLds twB = d.syn_half ? tw_lds_build(R.twBs, d.ffts[d.fft_synh], d.tw) : twA;
     for (int e = threadIdx.x; e < D * nr; e += blockDim.x) {
         const int q = e / nr, r = e - q * nr;
         it[q * RT + r] = hT[(size_t)q * d.nlam + n0 + r];
@@ -337,45 +401,76 @@ __global__ __launch_bounds__(1024) void k_ring_adj(PlanDev d, WsLayout L, InstPt
     __syncthreads();
     for (int r = 0; r < nr; ++r) {
         const int n = n0 + r;
-        const int off = d.ring_off[n], P = d.ring_off[n + 1] - off, np = 2 * P;
+        const int off = d.ring_off[n], P = d.ring_off[n + 1] - off;
         const int Kn = d.ring_K[n], jo = d.ring_joff[n];
-        const TwLds twr = tw_lds_build(twr_s, d.ffts[d.ring_fft[n]], d.tw);
-        if (d.fold_P) {
-            const int Pf = d.fold_P;
-            for (int s = threadIdx.x; s < Pf; s += blockDim.x)
-                sb[s] = make_float2(s < D ? it[s * RT + r] : 0.f, 0.f);
-            __syncthreads();
-            fft_lds<kMaxB>(sb, Pf, 1, fsyn, tws, false);
-            for (int k = threadIdx.x; k < np; k += blockDim.x) {
-                float2 o = make_float2(0.f, 0.f);
-                if (k <= Kn) {
-                    int s = k;
-                    while (s >= Pf) s -= Pf;
-                    // conj(pre0_k i^k) Jw_k * y~_{k mod P}
-                    o = cscale(mul_ipow(cmulc(sb[s], d.syn_pre[k]), (4 - (k & 3)) & 3), d.Jw[jo + k]);
-                }
-                sa[k] = o;
+        const TwLds twP = tw_lds_build(R.twPs, d.ffts[d.ring_fft[n]], d.tw);
+        const TwLds twN = tw_lds_build(R.twNs, d.ffts[d.ring_twn[n]], d.tw);
+        // y~ = FFT of the real detector values, zero-padded to the synthesis length
+        if (d.fold_P && d.syn_half) {
+            const int H2 = d.fold_P / 2;
+            for (int t = threadIdx.x; t < H2; t += blockDim.x) {
+                const int q0 = 2 * t, q1 = 2 * t + 1;
+                R.sc[t] = make_float2(q0 < D ? it[q0 * RT + r] : 0.f, q1 < D ? it[q1 * RT + r] : 0.f);
             }
+            __syncthreads();
+            fft_lds<RB>(R.sc, H2, 1, d.ffts[d.fft_synh], twB, false);
+        } else if (d.fold_P) {
+            for (int sidx = threadIdx.x; sidx < S; sidx += blockDim.x)
+                R.sy[sidx] = make_float2(sidx < D ? it[sidx * RT + r] : 0.f, 0.f);
+            __syncthreads();
+            fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, false);
         } else {
             for (int q = threadIdx.x; q < S; q += blockDim.x)
-                sb[q] = q < D ? cmulc(make_float2(it[q * RT + r], 0.f), d.czt_post[q]) : make_float2(0.f, 0.f);
+                R.sy[q] = q < D ? cmulc(make_float2(it[q * RT + r], 0.f), d.czt_post[q]) : make_float2(0.f, 0.f);
             __syncthreads();
-            fft_lds<kMaxB>(sb, S, 1, fsyn, tws, false);
-            for (int q = threadIdx.x; q < S; q += blockDim.x) sb[q] = cmulc(sb[q], d.czt_vhat[q]);
+            fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, false);
+            for (int q = threadIdx.x; q < S; q += blockDim.x) R.sy[q] = cmulc(R.sy[q], d.czt_vhat[q]);
             __syncthreads();
-            fft_lds<kMaxB>(sb, S, 1, fsyn, tws, true);
-            for (int k = threadIdx.x; k < np; k += blockDim.x) {
-                float2 o = make_float2(0.f, 0.f);
-                if (k <= Kn) o = cscale(mul_ipow(cmulc(sb[k], d.syn_pre[k]), (4 - (k & 3)) & 3), d.Jw[jo + k]);
-                sa[k] = o;
-            }
+            fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, true);
+        }
+        // y~ at synthesis index sidx (0 <= sidx < S)
+        auto ytil = [&](int sidx) {
+            if (!(d.fold_P && d.syn_half)) return R.sy[sidx];
+            const int Pf = d.fold_P, H2 = Pf / 2;
+            if (sidx == H2) return make_float2(R.sc[0].x - R.sc[0].y, 0.f);
+            const bool hi = sidx > H2;
+            const int s0 = hi ? Pf - sidx : sidx;
+            const float2 v = real_unpack(R.sc, H2, s0, twA(s0));
+            return hi ? cconj(v) : v;
+        };
+        // Q~_k = F~_k (k even) or -i F~_k (k odd), F~_k = conj(pre_k i^k) Jw_k y~_{k mod P}
+        for (int k = threadIdx.x; k <= Kn; k += blockDim.x) {
+            int sidx = k;
+            if (d.fold_P) while (sidx >= d.fold_P) sidx -= d.fold_P;
+            const float2 F = cscale(mul_ipow(cmulc(ytil(sidx), d.syn_pre[k]), (4 - (k & 3)) & 3), d.Jw[jo + k]);
+            R.sa[k] = (k & 1) ? make_float2(F.y, -F.x) : F;
         }
         __syncthreads();
-        fft_lds<kMaxB>(sa, np, 1, d.ffts[d.ring_fft[n]], twr, true);
+        // Re(IFFT_{2P}(Q~)) as a half-length inverse FFT: build E + i O in place of the
+        // upper part of sa (the Hermitian part of Q~ vanishes above K < P).
+        // Q~_h[s] = Q~[s]/2 (0 < s <= K), Re Q~[0] (s = 0); Q~_h[s + P] = conj Q~[P - s]/2 (P - s <= K).
+        for (int sidx = threadIdx.x; sidx < P; sidx += blockDim.x) {
+            float2 a = make_float2(0.f, 0.f), c = a;
+            if (sidx == 0) a = make_float2(R.sa[0].x, 0.f);
+            else {
+                if (sidx <= Kn) a = cscale(R.sa[sidx], 0.5f);
+                if (P - sidx <= Kn) c = cscale(cconj(R.sa[P - sidx]), 0.5f);
+            }
+            const float2 E = cadd(a, c);
+            const float2 O = cmulc(csub(a, c), twN(sidx));
+            R.sy[sidx] = make_float2(E.x - O.y, E.y + O.x);
+        }
+        __syncthreads();
+        fft_lds<RB>(R.sy, P, 1, d.ffts[d.ring_fft[n]], twP, true);
+        // q~(m): m = 2t -> Re z_t, m = 2t + 1 -> Im z_t;  F~_h(l) = (q~(l) + q~(l+P)) + i (q~(l) - q~(l+P))
         for (int l = threadIdx.x; l < P; l += blockDim.x) {
-            const float2 a = sa[l], c = sa[l + P];
-            const float2 hh = make_float2(a.x + c.x, a.y - c.y);  // F~(l) + conj F~(l + P)
-            H[d.perm[off + l]] = cmulc(hh, d.pt_phase[off + l]);
+            const float2 z1 = R.sy[l >> 1];
+            const float a = (l & 1) ? z1.y : z1.x;
+            const int m = l + P;
+            const float2 z2 = R.sy[m >> 1];
+            const float c = (m & 1) ? z2.y : z2.x;
+            const float2 Fh = make_float2(a + c, a - c);
+            Hb[d.perm[off + l]] = cmulc(Fh, d.pt_phase[off + l]);
         }
         __syncthreads();
     }

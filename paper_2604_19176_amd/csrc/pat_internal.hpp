@@ -50,7 +50,8 @@ struct PlanDev {
     const float2* pt_phase; // e^{-i pi (s_x + s_y)/Ng}  (half-pixel shift of cell-centred pixels)
     const int* ring_off;    // [nlam + 1]
     const int* ring_K;      // [nlam]   K_n: modes kept on ring n
-    const int* ring_fft;    // [nlam]   FFT descriptor of Npsi(n)
+    const int* ring_fft;    // [nlam]   FFT descriptor of Npsi(n)/2 (the ring's real transform)
+    const int* ring_twn;    // [nlam]   descriptor whose twiddles are those of length Npsi(n)
     const int* ring_joff;   // [nlam]   offset of ring n in Jw
     const float* Jw;        // ragged: J_k(lam_n R) W_n / Npsi(n), k = 0..K_n
     // polar points, band order (sorted by (r0, bx)) for the deterministic spread
@@ -61,6 +62,8 @@ struct PlanDev {
     // synthesis over detector angles theta_d = theta_0 + d dtheta
     int fold_P;             // P if dtheta = 2 pi / P (P = 2^a3^b >= D): fold k mod P, one FFT; else 0
     int syn_len;            // P (fold) or the chirp-z FFT length L >= K + D (Bluestein)
+    int syn_half;           // 1: fold with even P, synthesis as a real-output FFT of length P/2
+    int fft_synh;           // descriptor of length P/2 (syn_half only)
     const float2* syn_pre;  // [Kp]  c_k e^{i k theta_0} (fold) or c_k e^{i k theta_0} w^{k^2} (Bluestein); c_0 = 1, c_k = 2
     const float2* czt_post; // [D]   w^{d^2}, w = e^{i dtheta/2} (Bluestein only)
     const float2* czt_vhat; // [L]   FFT_L of the chirp filter w^{-m^2}, divided by L (Bluestein only)
@@ -117,6 +120,7 @@ struct pat_plan {
     int n_col_tiles;        // column-pass tiles (mass partials)
     int n_pair_tiles;       // cosine-transform tiles (data-sum partials)
     int thr_col, thr_row, thr_ring, thr_dct;  // workgroup sizes of the FFT kernels
+    int ring_mb;            // butterflies per thread per stage in the ring kernels (4, 8 or 16)
     size_t lds_ring;        // dynamic LDS of the ring kernels
     // optional per-kernel timing (pat_profile_enable): events around each launch
     int prof;

@@ -257,14 +257,14 @@ static int fft_threads(int nseq, const FftDev& fd)
 
 // Launch shapes: LDS per workgroup <= 64 KB and every FFT stage fits
 // 1024 threads x 4 butterflies.
-int choose_launch(pat_plan* p, const std::vector<FftDev>& fd, int max_ring_bf)
+int choose_launch(pat_plan* p, const std::vector<FftDev>& fd, int max_ring_bf,
+                  const std::vector<const FftDev*>& ring_descs)
 {
     const PlanDev& d = p->dev;
     LaunchCfg& c = p->cfg;
     const size_t kLds = 64 * 1024;
     const FftDev& fg = fd[d.fft_grid];
     const FftDev& fm = fd[d.fft_dct];
-    const FftDev& fs = fd[d.fft_syn];
     auto pick = [&](int maxn, size_t bytes_each, const FftDev& f, size_t fixed) {
         const int tps = (fft_min_tps(f, 4) + 31) / 32 * 32;
         int v = maxn;
@@ -275,22 +275,36 @@ int choose_launch(pat_plan* p, const std::vector<FftDev>& fd, int max_ring_bf)
     c.col_np = pick(8, sizeof(float2) * d.Ng, fg, twb(d.Ng));
     c.row_rpb = pick(8, sizeof(float2) * d.Ng, fg, twb(d.Ng));
     c.dct_dp = pick(4, sizeof(float2) * 2 * d.M, fm, twb(2 * d.M));
-    // ring kernels: angular FFT buffer + synthesis buffer + [D][RT] detector tile + twiddles
-    const size_t base = sizeof(float2) * ((size_t)d.npsi_max + d.syn_len) + twb(d.npsi_max) + twb(d.syn_len);
+    // ring kernels: half-ring FFT buffer, synthesis buffers, [D][RT] detector tile, four twiddle tables
     c.ring_rt = 1;
-    p->lds_ring = base + (((size_t)d.D * c.ring_rt + 1) & ~(size_t)1) * 4;
+    {
+        const size_t Pmax = d.npsi_max / 2, S = d.syn_len;
+        const size_t B2 = std::max(S, Pmax), B3 = d.syn_half ? S / 2 : 0;
+        p->lds_ring = sizeof(float2) * (Pmax + B2 + B3) + (((size_t)d.D * c.ring_rt + 1) & ~(size_t)1) * 4 +
+                      twb((int)Pmax) + twb(d.npsi_max) + twb((int)S) + twb((int)S);
+    }
     c.gat_cb = 64;
     c.gat_th = 16;
     c.spr_cb = 64;
     c.spr_th = 32;
     c.spr_cap = 128;
     if (!c.col_np || !c.row_rpb || !c.dct_dp || p->lds_ring > kLds) return PAT_ERR_UNSUPPORTED;
-    const int ring_tps = std::max(max_ring_bf, fft_min_tps(fs, 4));
     p->thr_col = fft_threads(c.col_np, fg);
     p->thr_row = fft_threads(c.row_rpb, fg);
     p->thr_dct = fft_threads(c.dct_dp, fm);
-    p->thr_ring = std::max(256, ((ring_tps + 63) / 64) * 64);
-    if (p->thr_ring > 1024) return PAT_ERR_UNSUPPORTED;
+    // ring kernels: as few threads per ring as the FFT stages allow (one wave when
+    // possible), so that many rings are resident per CU to hide their latency
+    (void)max_ring_bf;
+    p->thr_ring = 0;
+    for (int mb : {4}) {
+        for (int thr : {64, 128, 256, 512, 1024}) {
+            bool ok = true;
+            for (const FftDev* f : ring_descs) ok = ok && fft_min_tps(*f, mb) <= thr;
+            if (ok) { p->thr_ring = thr; p->ring_mb = mb; break; }
+        }
+        if (p->thr_ring) break;
+    }
+    if (!p->thr_ring) return PAT_ERR_UNSUPPORTED;
     return PAT_OK;
 }
 
@@ -355,6 +369,8 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     d.fold_P = dv.P;
     d.syn_len = dv.P ? dv.P : dv.L;
     d.fft_syn = ffts.get(d.syn_len);
+    d.syn_half = (dv.P && dv.P % 2 == 0) ? 1 : 0;
+    d.fft_synh = d.syn_half ? ffts.get(dv.P / 2) : d.fft_syn;
 
     // --- image-side tables -------------------------------------------------
     std::vector<double> ph = es_hat(N, Ng);
@@ -377,7 +393,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     }
 
     // --- rings: per-ring mode cut-off and angular grid ----------------------
-    std::vector<int> ringK(nlam), ringN(nlam), ringOff(nlam + 1), ringFft(nlam), ringJoff(nlam);
+    std::vector<int> ringK(nlam), ringN(nlam), ringOff(nlam + 1), ringFft(nlam), ringTwn(nlam), ringJoff(nlam);
     std::vector<double> rho(nlam);
     int npts = 0, joff = 0, npsi_max = 0;
     for (int n = 1; n <= nlam; ++n) {
@@ -389,7 +405,8 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
         ringN[n - 1] = np;
         ringOff[n - 1] = npts;
         ringJoff[n - 1] = joff;
-        ringFft[n - 1] = ffts.get(np);
+        ringFft[n - 1] = ffts.get(np / 2);
+        ringTwn[n - 1] = ffts.get(np);
         rho[n - 1] = lam * h * Ng / (2.0 * PI);
         npts += np / 2;
         joff += kn + 1;
@@ -498,8 +515,14 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
 
     {
         int max_ring_bf = 0;
-        for (int n = 0; n < nlam; ++n) max_ring_bf = std::max(max_ring_bf, fft_min_tps(ffts.descs[ringFft[n]], 4));
-        int rc = choose_launch(p, ffts.descs, max_ring_bf);
+        std::vector<const FftDev*> rdesc;
+        for (int n = 0; n < nlam; ++n) {
+            max_ring_bf = std::max(max_ring_bf, fft_min_tps(ffts.descs[ringFft[n]], 4));
+            if (std::find(rdesc.begin(), rdesc.end(), &ffts.descs[ringFft[n]]) == rdesc.end())
+                rdesc.push_back(&ffts.descs[ringFft[n]]);
+        }
+        rdesc.push_back(&ffts.descs[d.syn_half ? d.fft_synh : d.fft_syn]);
+        int rc = choose_launch(p, ffts.descs, max_ring_bf, rdesc);
         if (rc != PAT_OK) return rc;
     }
 
@@ -507,6 +530,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     size_t o_deap = tb.add(deap), o_mask = tb.add(mask);
     size_t o_geo = tb.add(geo), o_phase = tb.add(phase);
     size_t o_roff = tb.add(ringOff), o_rk = tb.add(ringK), o_rfft = tb.add(ringFft), o_rj = tb.add(ringJoff);
+    size_t o_rtwn = tb.add(ringTwn);
     size_t o_jw = tb.add(Jw);
     size_t o_perm = tb.add(perm), o_bgeo = tb.add(bgeo), o_bph = tb.add(bphase), o_bptr = tb.add(bptr);
     size_t o_pre = tb.add(pre), o_post = tb.add(post), o_vhat = tb.add(vhat);
@@ -520,6 +544,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     d.ring_off = (const int*)off(o_roff);
     d.ring_K = (const int*)off(o_rk);
     d.ring_fft = (const int*)off(o_rfft);
+    d.ring_twn = (const int*)off(o_rtwn);
     d.ring_joff = (const int*)off(o_rj);
     d.Jw = (const float*)off(o_jw);
     d.perm = (const int*)off(o_perm);
@@ -561,7 +586,7 @@ extern "C" int pat_plan_create(const pat_plan_desc* desc, pat_plan** out)
     PlanDev& d = p->dev;
     auto rel = [&](auto& ptr) { ptr = (std::remove_reference_t<decltype(ptr)>)(base + (uintptr_t)ptr); };
     rel(d.deap); rel(d.mask_rows); rel(d.pt_geo); rel(d.pt_phase); rel(d.ring_off); rel(d.ring_K);
-    rel(d.ring_fft); rel(d.ring_joff); rel(d.Jw); rel(d.perm); rel(d.bpt_geo); rel(d.bpt_phase);
+    rel(d.ring_fft); rel(d.ring_twn); rel(d.ring_joff); rel(d.Jw); rel(d.perm); rel(d.bpt_geo); rel(d.bpt_phase);
     rel(d.band_ptr); rel(d.syn_pre); rel(d.czt_post); rel(d.czt_vhat); rel(d.ffts); rel(d.tw);
     p->max_batch = desc->max_batch;
     p->n_psi_uniform = dv.n_psi;
