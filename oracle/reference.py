@@ -54,11 +54,14 @@ def discrete_gaussian_data(geom, sz, blobs, mass=None):
     return (S * W) @ C + sz["kappa"] * mass
 
 
-def discrete_impulse_adjoint(geom, sz, d, j):
-    """A* applied to the unit datum at detector d, time index j (0-based), (N, N)."""
+def discrete_impulse_adjoint(geom, sz, d, j, flat_idx=None):
+    """A* applied to the unit datum at detector d, time index j (0-based): the
+    (N, N) image, or its values at the pixels with flat index i*N + j."""
     from pat_inputs import pixel_centres
     lam, W = _lam_W(sz)
     X, Y = pixel_centres(geom.n)
+    if flat_idx is not None:
+        X, Y = X.ravel()[flat_idx], Y.ravel()[flat_idx]
     xd, yd = detector_xy(geom)
     t = geom.times()[j]
     rho = np.hypot(X - xd[d], Y - yd[d])

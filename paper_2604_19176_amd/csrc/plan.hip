@@ -262,14 +262,17 @@ int choose_launch(pat_plan* p, const std::vector<FftDev>& fd, int max_ring_bf,
 {
     const PlanDev& d = p->dev;
     LaunchCfg& c = p->cfg;
-    const size_t kLds = 64 * 1024;
+    const size_t kLds = 64 * 1024, kLdsMax = 160 * 1024;
     const FftDev& fg = fd[d.fft_grid];
     const FftDev& fm = fd[d.fft_dct];
+    // prefer <= 64 KB of LDS per workgroup (several workgroups per CU); a single
+    // sequence that does not fit may use up to the 160 KB a gfx950 workgroup can hold
     auto pick = [&](int maxn, size_t bytes_each, const FftDev& f, size_t fixed) {
         const int tps = (fft_min_tps(f, 4) + 31) / 32 * 32;
         int v = maxn;
         while (v > 1 && (v * bytes_each + fixed > kLds || v * tps > 1024)) --v;
-        return (v * bytes_each + fixed <= kLds && v * tps <= 1024) ? v : 0;
+        if (v * bytes_each + fixed <= kLds && v * tps <= 1024) return v;
+        return (bytes_each + fixed <= kLdsMax && tps <= 1024) ? 1 : 0;
     };
     auto twb = [](int n) { return sizeof(float2) * (size_t)tw_lds_slots(n); };
     c.col_np = pick(8, sizeof(float2) * d.Ng, fg, twb(d.Ng));
@@ -288,7 +291,7 @@ int choose_launch(pat_plan* p, const std::vector<FftDev>& fd, int max_ring_bf,
     c.spr_cb = 64;
     c.spr_th = 32;
     c.spr_cap = 128;
-    if (!c.col_np || !c.row_rpb || !c.dct_dp || p->lds_ring > kLds) return PAT_ERR_UNSUPPORTED;
+    if (!c.col_np || !c.row_rpb || !c.dct_dp || p->lds_ring > kLdsMax) return PAT_ERR_UNSUPPORTED;
     p->thr_col = fft_threads(c.col_np, fg);
     p->thr_row = fft_threads(c.row_rpb, fg);
     p->thr_dct = fft_threads(c.dct_dp, fm);

@@ -1,0 +1,140 @@
+"""GPU parity at the full workload sizes (512^2 and 1024^2).
+
+At 512^2 the oracle still finishes (tens of seconds), so A and A* are compared
+element by element.  At 1024^2 (the large workload: 1024 detectors on a 270
+degree arc, 2048 samples, batch 8) the oracle's direct sums are too slow; the
+outputs are compared instead, at every detector/time sample or pixel, with
+closed forms that hold at any size: the discrete Gaussian form for A (blobs
+well inside the support) and the discrete impulse form for A*; the GPU pair
+also satisfies the adjoint identity and batch-equals-single there.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import reference as ref
+from pat_inputs import Blob, CONFIGS, Geometry, PhantomSpec, config_geometry, make_phantom, render_phantom
+from pat_inputs.geometry import mixed_batch_geometries
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def test_512_full_circle_against_oracle(torch_dev):
+    """The largest instance of the mixed batch: 512^2, 512 detectors on the
+    full circle, 1024 samples."""
+    torch = torch_dev
+    import oracle
+    import paper_2604_19176_amd as pat
+    geom = Geometry(n=512, n_det=512, n_t=1024, dt=2.0 / 1024, arc_span=2 * math.pi)
+    f = make_phantom(geom.n, 5, 1, 0, 4002)
+    d = np.random.default_rng(4002).standard_normal((geom.n_det, geom.n_t))
+    plan = pat.PatPlan(geom)
+    g = plan.forward(torch.tensor(f, dtype=torch.float32, device="cuda")).cpu().double().numpy()
+    a = plan.adjoint(torch.tensor(d, dtype=torch.float32, device="cuda")).cpu().double().numpy()
+    plan.close()
+    ef, ea = _rel(g, oracle.forward(geom, f)), _rel(a, oracle.adjoint(geom, d))
+    print("512^2: forward %.3e adjoint %.3e" % (ef, ea))
+    assert ef <= 1e-5 and ea <= 1e-5
+
+
+def _large_blobs():
+    return [Blob(0.12, -0.2, 0.05, 1.0), Blob(-0.25, 0.1, 0.04, 0.8), Blob(0.05, 0.28, 0.06, 0.6)]
+
+
+def test_1024_forward_gaussian_closed_form(torch_dev):
+    torch = torch_dev
+    import oracle
+    import paper_2604_19176_amd as pat
+    geom = config_geometry(5)
+    blobs = _large_blobs()
+    f = render_phantom(PhantomSpec(blobs=blobs, cutoff_r=10.0), geom.n)
+    plan = pat.PatPlan(geom)
+    g = plan.forward(torch.tensor(f, dtype=torch.float32, device="cuda")).cpu().double().numpy()
+    plan.close()
+    C = ref.discrete_gaussian_data(geom, oracle.sizes(geom), blobs)
+    err = _rel(g, C)
+    print("1024^2 forward vs discrete Gaussian form: %.3e" % err)
+    assert err <= 1e-5
+
+
+def test_1024_adjoint_impulse_closed_form(torch_dev):
+    torch = torch_dev
+    import oracle
+    import paper_2604_19176_amd as pat
+    geom = config_geometry(5)
+    sz = oracle.sizes(geom)
+    plan = pat.PatPlan(geom)
+    rng = np.random.default_rng(5001)
+    X = -1 + (np.arange(geom.n) + 0.5) * geom.h
+    inside = ((X[None, :] ** 2 + X[:, None] ** 2) < geom.support_r ** 2).ravel()
+    idx = rng.choice(np.flatnonzero(inside), 4000, replace=False)
+    for (dd, jj) in [(0, 700), (511, 1500), (1023, 2047)]:
+        data = np.zeros((geom.n_det, geom.n_t))
+        data[dd, jj] = 1.0
+        a = plan.adjoint(torch.tensor(data, dtype=torch.float32, device="cuda")).cpu().double().numpy().ravel()
+        C = ref.discrete_impulse_adjoint(geom, sz, dd, jj, flat_idx=idx)
+        err = _rel(a[idx], C)
+        print("1024^2 adjoint impulse (%d, %d) on %d pixels: %.3e" % (dd, jj, idx.size, err))
+        assert err <= 1e-5
+        assert np.all(a[~inside] == 0.0)
+    plan.close()
+
+
+def test_1024_batch8_dot_and_batch_equals_single(torch_dev):
+    torch = torch_dev
+    import paper_2604_19176_amd as pat
+    geom = config_geometry(5)
+    B = CONFIGS[5]["batch"]
+    fs = np.stack([make_phantom(geom.n, 20, 3, 4, 5000 + b) for b in range(B)])
+    ds = np.random.default_rng(5000).standard_normal((B, geom.n_det, geom.n_t))
+    plan = pat.PatPlan(geom, max_batch=B)
+    ft = torch.tensor(fs, dtype=torch.float32, device="cuda")
+    dt = torch.tensor(ds, dtype=torch.float32, device="cuda")
+    g = plan.forward(ft).clone()
+    a = plan.adjoint(dt).clone()
+    for b in range(B):
+        lhs = float((g[b].double() * dt[b].double()).sum())
+        rhs = float((ft[b].double() * a[b].double()).sum())
+        err = abs(lhs - rhs) / (float(g[b].double().norm()) * float(dt[b].double().norm()))
+        assert err <= 1e-5
+    for b in (0, B - 1):
+        assert torch.equal(g[b], plan.forward(ft[b].contiguous()))
+        assert torch.equal(a[b], plan.adjoint(dt[b].contiguous()))
+    plan.close()
+
+
+def test_mixed_batch_geometries_plan_and_run(torch_dev):
+    """Every geometry of the heterogeneous 64-instance workload builds a plan and
+    passes the adjoint identity on the GPU."""
+    torch = torch_dev
+    import paper_2604_19176_amd as pat
+    seen = set()
+    for geom, seed in mixed_batch_geometries(64):
+        key = (geom.n, geom.n_det, round(geom.arc_span, 6))
+        if key in seen:
+            continue
+        seen.add(key)
+        plan = pat.PatPlan(geom)
+        f = torch.tensor(make_phantom(geom.n, 5, 1, 0, seed), dtype=torch.float32, device="cuda")
+        d = torch.tensor(np.random.default_rng(seed).standard_normal((geom.n_det, geom.n_t)), dtype=torch.float32,
+                         device="cuda")
+        g = plan.forward(f).double()
+        a = plan.adjoint(d).double()
+        err = abs(float((g * d.double()).sum()) - float((f.double() * a).sum())) / (
+            float(g.norm()) * float(d.double().norm()))
+        assert err <= 1e-5, (key, err)
+        plan.close()
+    assert len(seen) == 36
