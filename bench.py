@@ -1,6 +1,6 @@
 """Benchmark: A + A* operator pairs per second at 256^2 FP32, batched vs single.
 
-Workload (default): the limited-view geometry -- 256 x 256 image on [-1,1]^2
+Default workload: the limited-view geometry -- 256 x 256 image on [-1,1]^2
 (zero outside r < 0.9), 256 detectors on a 180 degree arc of the unit circle,
 512 time samples on (0, 2], c = 1 -- with a batch of 64 seeded phantoms
 (20 Gaussian blobs, 3 discs, 4 thin line segments each) and noisy data
@@ -10,11 +10,18 @@ second.  The single-instance rate (batch 1, same geometry) is reported beside
 it.  Before timing, instance 0 is checked against the FP64 oracle (relative
 L2 <= 1e-5); that oracle run, timed on the host cores, is the CPU baseline.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B]
+Other workloads (one JSON line each; not the default):
+  --workload tv3     TV projected-gradient iterations/s at 256^2, 128 detectors on 120 deg
+  --workload large   1024^2, 1024 detectors on 270 deg, 2048 samples, batch 8:
+                     TV iterations/s and staged HBM GB/s
+  --workload paper   the paper's timed shape (760^2, 256 detectors on 270 deg, 2030 samples)
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B] [--workload ...]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -27,8 +34,24 @@ if ROOT not in sys.path:
 
 METRIC = "A+A* operator pairs/sec at 256² FP32 (rel L2 ≤1e-5 vs FP64); batched vs single"
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3           # published FP32 vector peak (packed FP32)
+FP32_NONPACKED_TFLOPS = 78.6       # ceiling of code built without packed FP32
 FWD_NAMES = ["colpass_fwd", "rowpass_fwd", "gather", "ring_fwd", "dct_fwd"]
 ADJ_NAMES = ["dct_adj", "ring_adj", "spread", "rowpass_adj", "colpass_adj"]
+KERNEL_SYMBOL = {"colpass_fwd": "k_colpass_fwd", "rowpass_fwd": "k_rowpass_fwd", "gather": "k_gather",
+                 "ring_fwd": "k_ring_fwd", "dct_fwd": "k_dct_det", "dct_adj": "k_dct_det",
+                 "ring_adj": "k_ring_adj", "spread": "k_spread", "rowpass_adj": "k_rowpass_adj",
+                 "colpass_adj": "k_colpass_adj"}
+# interpolation or spread of one polar point: 16 kernel evaluations (~6 flops),
+# 64 weight products and 64 complex x real multiply-adds (4 flops)
+FLOPS_PER_POINT = 16 * 6 + 64 + 64 * 4
+CALIB_ELEMS = 64 * 1024 * 1024     # float32 elements of the calibration copy (256 MiB each way)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2604_19176_amd", "csrc", "kernels.hip")
+
+
+def kernels_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
 def algorithmic_bytes(info, geom):
@@ -54,45 +77,119 @@ def algorithmic_bytes(info, geom):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--batch", type=int, default=64)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: the operator pair shards by instance with no "
-              "communication, so --gpus %d is not run (see DESIGN.md)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
+def algorithmic_flops(info, geom, name):
+    """Nominal FP32 flops per instance of the compute-bound kernels."""
+    P, NL, D = info.n_points, info.n_lam, geom.n_det
+    if name in ("gather", "spread"):
+        return FLOPS_PER_POINT * P
+    if name in ("ring_fwd", "ring_adj"):
+        ring = P / max(NL, 1)                  # average half-ring length
+        syn = max(info.len_czt, 2)
+        return 5.0 * P * math.log2(max(ring, 2)) + 5.0 * NL * syn * math.log2(syn) / 2
+    return None
 
+
+def roofline(kms, info, geom, B):
+    """Roofline entry for the kernel with the largest per-launch time."""
+    dom = max(kms, key=kms.get)
+    t = kms[dom] * 1e-3
+    traffic = None
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("kernels_hash") == kernels_hash() and tr.get("kernel") == KERNEL_SYMBOL[dom] \
+                and tr.get("batch") == B:
+            traffic = int(tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        traffic = None
+    fl = algorithmic_flops(info, geom, dom)
+    if fl is not None:
+        flops = fl * B
+        ach = flops / t / 1e12
+        return {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4),
+                "frac_of_nonpacked_78.6": round(ach / FP32_NONPACKED_TFLOPS, 4),
+                "flops_per_launch": int(flops), "avg_launch_ms": round(kms[dom], 4), "traffic": traffic,
+                "algorithmic_bytes_per_launch": algorithmic_bytes(info, geom)[dom] * B}
+    byt = algorithmic_bytes(info, geom)[dom] * B
+    ach = byt / t / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_launch": byt, "avg_launch_ms": round(kms[dom], 4),
+            "traffic": traffic}
+
+
+def kernel_times(pat, plan, f, g, gout, fout, nprof=10):
+    """Average per-launch milliseconds of each kernel, from the library's HIP
+    events recorded on the stream the kernels run on."""
+    pat.pat_profile_enable(plan.handle, True)
+    acc_f = [0.0] * len(FWD_NAMES)
+    acc_a = [0.0] * len(ADJ_NAMES)
+    for _ in range(nprof):
+        plan.forward(f, out=gout)
+        acc_f = [a + b for a, b in zip(acc_f, pat.pat_profile_read(plan.handle, 0))]
+        plan.adjoint(g, out=fout)
+        acc_a = [a + b for a, b in zip(acc_a, pat.pat_profile_read(plan.handle, 1))]
+    pat.pat_profile_enable(plan.handle, False)
+    return {n: v / nprof for n, v in zip(FWD_NAMES + ADJ_NAMES, acc_f + acc_a)}
+
+
+def time_pairs(torch, plan, f, g, gout, fout, steps, warmup):
+    stream = torch.cuda.current_stream(plan.device)
+    for _ in range(warmup):
+        plan.forward(f, out=gout)
+        plan.adjoint(g, out=fout)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        plan.forward(f, out=gout)
+        plan.adjoint(g, out=fout)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, time.perf_counter() - t0
+
+
+def copy_calibration(torch, dev):
+    """One float32 multiply-by-one over CALIB_ELEMS elements: a copy of known
+    size whose byte counters calibrate the PMC traffic figures."""
+    x = torch.ones(CALIB_ELEMS, dtype=torch.float32, device=dev)
+    y = torch.mul(x, 1.0)
+    torch.cuda.synchronize()
+    del x, y
+
+
+def make_inputs(np, torch, plan, geom, cfg, B, dev, seed_stride):
+    from pat_inputs import add_noise, make_phantom
+    nb, nd, nl = cfg["phantom"]
+    seeds = [cfg["seed"] + seed_stride * b for b in range(B)]
+    fs = np.stack([make_phantom(geom.n, nb, nd, nl, s) for s in seeds])
+    f = torch.tensor(fs, dtype=torch.float32, device=dev)
+    g_clean = plan.forward(f)
+    torch.cuda.synchronize()
+    gm = np.stack([add_noise(g_clean[b].cpu().double().numpy(), cfg["noise"], s) for b, s in enumerate(seeds)])
+    return fs, f, gm, torch.tensor(gm, dtype=torch.float32, device=dev)
+
+
+def bench_default(args):
     import numpy as np
     import torch
 
     import paper_2604_19176_amd as pat
-    from pat_inputs import CONFIGS, add_noise, config_geometry, make_phantom
+    from pat_inputs import CONFIGS, config_geometry
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     cfg = CONFIGS[2]
     geom = config_geometry(2)
     B = args.batch
-    nb, nd, nl = cfg["phantom"]
     print("bench: building inputs (batch %d)" % B, file=sys.stderr, flush=True)
-    fs = np.stack([make_phantom(geom.n, nb, nd, nl, cfg["seed"] + 1000 * b) for b in range(B)])
     plan = pat.PatPlan(geom, max_batch=B)
     plan1 = pat.PatPlan(geom, max_batch=1)
-    f = torch.tensor(fs, dtype=torch.float32, device=dev)
-    g_clean = plan.forward(f)
-    torch.cuda.synchronize()
-    gm = np.stack([add_noise(g_clean[b].cpu().double().numpy(), cfg["noise"], cfg["seed"] + 1000 * b)
-                   for b in range(B)])
-    g_meas = torch.tensor(gm, dtype=torch.float32, device=dev)
+    fs, f, gm, g_meas = make_inputs(np, torch, plan, geom, cfg, B, dev, 1000)
     g_out = torch.empty_like(g_meas)
     f_out = torch.empty_like(f)
+    copy_calibration(torch, dev)
 
-    # ---- parity of instance 0 against the FP64 oracle (also the CPU baseline) ----
     parity = None
     cpu = None
     if not args.no_cpu_baseline:
@@ -115,65 +212,19 @@ def main():
             "adj_rel_l2": float(np.linalg.norm(a0 - ref_f) / np.linalg.norm(ref_f)),
         }
         assert parity["fwd_rel_l2"] <= 1e-5 and parity["adj_rel_l2"] <= 1e-5, parity
-        cpu = {"value": reps / t_cpu, "unit": "pairs/s", "cores": nthreads, "kind": "oracle",
+        cpu = {"value": round(reps / t_cpu, 4), "unit": "pairs/s", "cores": nthreads, "kind": "oracle",
                "sample": "%d x (one A + one A*) on instance 0 of the 256^2 workload, FP64 direct sums" % reps}
 
-    stream = torch.cuda.current_stream(dev)
-
-    def step(p, fin, gin, gout, fout):
-        p.forward(fin, out=gout)
-        p.adjoint(gin, out=fout)
-
-    # ---- batched ----
     print("bench: timing batched", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        step(plan, f, g_meas, g_out, f_out)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step(plan, f, g_meas, g_out, f_out)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = e0.elapsed_time(e1) / args.steps
+    ms_step, wall = time_pairs(torch, plan, f, g_meas, g_out, f_out, args.steps, args.warmup)
     value = B * 1000.0 / ms_step
-
-    # ---- single instance ----
     print("bench: timing single", file=sys.stderr, flush=True)
     f1, g1 = f[0:1].contiguous(), g_meas[0:1].contiguous()
     go1, fo1 = torch.empty_like(g1), torch.empty_like(f1)
-    for _ in range(args.warmup):
-        step(plan1, f1, g1, go1, fo1)
-    torch.cuda.synchronize()
-    s_steps = max(args.steps, 20)
-    e0.record(stream)
-    for _ in range(s_steps):
-        step(plan1, f1, g1, go1, fo1)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_single = e0.elapsed_time(e1) / s_steps
-
-    # ---- per-kernel durations (HIP events around each launch, same launches) ----
-    pat.pat_profile_enable(plan.handle, True)
-    nprof = 10
-    acc_f = [0.0] * len(FWD_NAMES)
-    acc_a = [0.0] * len(ADJ_NAMES)
-    for _ in range(nprof):
-        plan.forward(f, out=g_out)
-        ms = pat.pat_profile_read(plan.handle, 0)
-        acc_f = [a + b for a, b in zip(acc_f, ms)]
-        plan.adjoint(g_meas, out=f_out)
-        ms = pat.pat_profile_read(plan.handle, 1)
-        acc_a = [a + b for a, b in zip(acc_a, ms)]
-    pat.pat_profile_enable(plan.handle, False)
-    kms = {n: v / nprof for n, v in zip(FWD_NAMES + ADJ_NAMES, acc_f + acc_a)}
+    ms_single, _ = time_pairs(torch, plan1, f1, g1, go1, fo1, max(args.steps, 20), args.warmup)
+    kms = kernel_times(pat, plan, f, g_meas, g_out, f_out)
     abytes = algorithmic_bytes(plan.info, geom)
-    dom = max(kms, key=kms.get)
-    achieved = abytes[dom] * B / (kms[dom] * 1e-3) / 1e9
     gbs = {n: abytes[n] * B / (kms[n] * 1e-3) / 1e9 for n in kms}
-
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -195,15 +246,117 @@ def main():
         "batched_over_single": round(value * ms_single / 1000.0, 2),
         "wall_s_timed": round(wall, 3),
         "parity": parity,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "roofline": roofline(kms, plan.info, geom, B),
         "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
         "kernels_gbs": {k: round(v, 1) for k, v in gbs.items()},
+        "kernels_hash": kernels_hash(),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     plan.close()
     plan1.close()
+
+
+def bench_tv(args, cfg_id, steps_default, seed_stride):
+    import numpy as np
+    import torch
+
+    import paper_2604_19176_amd as pat
+    from paper_2604_19176_amd.recon import TVReconstructor
+    from pat_inputs import CONFIGS, config_geometry
+
+    dev = torch.device("cuda", 0)
+    cfg = CONFIGS[cfg_id]
+    geom = config_geometry(cfg_id)
+    B = cfg["batch"]
+    steps = args.tv_steps or steps_default
+    lam = cfg.get("tv_lambda", 1e-3)
+    print("bench: building inputs (%dx%d, batch %d)" % (geom.n, geom.n, B), file=sys.stderr, flush=True)
+    plan = pat.PatPlan(geom, max_batch=B)
+    fs, f, gm, g_meas = make_inputs(np, torch, plan, geom, cfg, B, dev, seed_stride)
+    g_out, f_out = torch.empty_like(g_meas), torch.empty_like(f)
+    ms_pair, _ = time_pairs(torch, plan, f, g_meas, g_out, f_out, 5, 2)
+    gin = g_meas if B > 1 else g_meas[0]
+    print("bench: TV loop, %d iterations" % steps, file=sys.stderr, flush=True)
+    rec = TVReconstructor(plan, gin, lam=lam)
+    rec.capture()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    rec.run(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ab = algorithmic_bytes(plan.info, geom)
+    n2, dt_ = geom.n * geom.n, geom.n_det * geom.n_t
+    loop_bytes = 8 * n2 + 16 * n2 + 12 * dt_     # TV gradient, projected update, residual
+    it_bytes = B * (sum(ab.values()) + loop_bytes)
+    out = {
+        "metric": "TV projected-gradient iterations/s (A, residual, A*, TV gradient, update per iteration)",
+        "value": round(steps * 1000.0 / ms, 2),
+        "unit": "iterations/s",
+        "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": round(ms / steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "TV loop, %dx%d, %d detectors on %.0f deg, %d samples, batch %d, lambda %.0e, "
+                               "one HIP graph per iteration"
+                               % (geom.n, geom.n, geom.n_det, math.degrees(geom.arc_span), geom.n_t, B, lam),
+                   "batch": B},
+        "staged_hbm_gbs": round(it_bytes * steps / (ms * 1e-3) / 1e9, 1),
+        "pairs_per_s": round(B * 1000.0 / ms_pair, 2),
+        "tau": rec.tau,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+def bench_paper(args):
+    import numpy as np
+    import torch
+
+    import paper_2604_19176_amd as pat
+    from pat_inputs import paper_shape_geometry
+
+    dev = torch.device("cuda", 0)
+    geom = paper_shape_geometry()
+    plan = pat.PatPlan(geom, max_batch=1)
+    cfg = dict(phantom=(20, 3, 4), noise=0.01, seed=760)
+    fs, f, gm, g_meas = make_inputs(np, torch, plan, geom, cfg, 1, dev, 1)
+    g_out, f_out = torch.empty_like(g_meas), torch.empty_like(f)
+    ms, _ = time_pairs(torch, plan, f, g_meas, g_out, f_out, args.steps, args.warmup)
+    out = {"metric": "A+A* pairs/s at the paper's timed shape",
+           "value": round(1000.0 / ms, 1), "unit": "pairs/s", "ms_per_step": round(ms, 4), "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "760x760, 256 detectors on 270 deg, 2030 samples, batch 1"}}
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--workload", default="default", choices=["default", "tv3", "large", "paper"])
+    ap.add_argument("--tv-steps", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the operator pair shards by instance with no "
+              "communication, so --gpus %d is not run" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "default":
+        bench_default(args)
+    elif args.workload == "tv3":
+        bench_tv(args, 3, 500, 1000)
+    elif args.workload == "large":
+        bench_tv(args, 5, 200, 1)
+    else:
+        bench_paper(args)
 
 
 if __name__ == "__main__":

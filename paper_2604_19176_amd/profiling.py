@@ -1,0 +1,133 @@
+"""Summaries of rocprofv3 CSV output for the library's kernels.
+
+`python -m paper_2604_19176_amd.profiling stats <dir>/run_kernel_trace.csv`
+prints, per kernel, the number of dispatches and the average duration of the
+dispatches with the largest grid (the batched launches of a run that also
+makes small-batch calls), next to rocprofv3's own all-dispatch average.
+
+`python -m paper_2604_19176_amd.profiling traffic <fetch.csv> <write.csv>
+--kernel NAME --calib-bytes BYTES` turns two `--pmc FETCH_SIZE` /
+`--pmc WRITE_SIZE` counter-collection files into HBM bytes per launch of one
+kernel.  Each counter (KiB per dispatch) is scaled by known/counted bytes of
+the calibration copy in the same run: the float32 multiply-by-one kernel with
+the largest counter value (it reads and writes BYTES each).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+
+def _short(name):
+    base = name.split("(")[0]
+    if base.startswith("void "):
+        base = base[5:]
+    return base[5:] if base.startswith("pat::") else base
+
+
+def _rows(path):
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _grid(row):
+    if "Grid_Size" in row:
+        return int(row["Grid_Size"])
+    return int(row["Grid_Size_X"]) * int(row["Grid_Size_Y"]) * int(row["Grid_Size_Z"])
+
+
+def kernel_durations(trace_csv):
+    """{kernel: {"grid": largest grid, "n": dispatches at it, "avg_us": mean duration}}."""
+    by = defaultdict(list)
+    for r in _rows(trace_csv):
+        by[_short(r["Kernel_Name"])].append((_grid(r), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    out = {}
+    for k, v in by.items():
+        gmax = max(g for g, _ in v)
+        d = [t for g, t in v if g == gmax]
+        out[k] = {"grid": gmax, "n": len(d), "avg_us": sum(d) / len(d) / 1e3, "all_n": len(v)}
+    return out
+
+
+def stats_table(trace_csv, stats_csv=None):
+    kd = kernel_durations(trace_csv)
+    allavg = {}
+    if stats_csv and os.path.exists(stats_csv):
+        for r in _rows(stats_csv):
+            allavg[_short(r["Name"])] = float(r["AverageNs"]) / 1e3
+    lines = ["| kernel | dispatches (all / largest grid) | largest grid | avg us (largest grid) | avg us (all) |",
+             "|---|---|---|---|---|"]
+    for k, v in sorted(kd.items(), key=lambda kv: -kv[1]["avg_us"] * kv[1]["n"]):
+        a = allavg.get(k)
+        lines.append("| %s | %d / %d | %d | %.1f | %s |" % (k, v["all_n"], v["n"], v["grid"], v["avg_us"],
+                                                           "%.1f" % a if a is not None else "-"))
+    return "\n".join(lines)
+
+
+def _counter(path, kernel):
+    vals, calib = [], []
+    for r in _rows(path):
+        name = r["Kernel_Name"]
+        v = float(r["Counter_Value"])
+        if _short(name) == kernel:
+            vals.append((_grid(r), v))
+        elif "MulFunctor" in name:
+            calib.append(v)
+    if not vals:
+        raise SystemExit("kernel %s not found in %s" % (kernel, path))
+    gmax = max(g for g, _ in vals)
+    kv = [v for g, v in vals if g == gmax]
+    return sum(kv) / len(kv), (max(calib) if calib else None), len(kv)
+
+
+def traffic(fetch_csv, write_csv, kernel, calib_bytes):
+    f_kib, f_cal, nf = _counter(fetch_csv, kernel)
+    w_kib, w_cal, nw = _counter(write_csv, kernel)
+    sf = calib_bytes / (f_cal * 1024.0) if f_cal else 1.0
+    sw = calib_bytes / (w_cal * 1024.0) if w_cal else 1.0
+    return {
+        "kernel": kernel,
+        "fetch_kib_per_launch_raw": f_kib, "write_kib_per_launch_raw": w_kib,
+        "fetch_scale": sf, "write_scale": sw,
+        "fetch_bytes_per_launch": f_kib * 1024.0 * sf, "write_bytes_per_launch": w_kib * 1024.0 * sw,
+        "dispatches": [nf, nw],
+        "calib_bytes": calib_bytes,
+        "calib_fetch_kib": f_cal, "calib_write_kib": w_cal,
+    }
+
+
+def source_hash(path):
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("trace")
+    s.add_argument("--stats-csv")
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch")
+    t.add_argument("write")
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--calib-bytes", type=float, required=True)
+    t.add_argument("--batch", type=int, required=True)
+    t.add_argument("--source", required=True)
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        print(stats_table(a.trace, a.stats_csv))
+    else:
+        d = traffic(a.fetch, a.write, a.kernel, a.calib_bytes)
+        d["batch"] = a.batch
+        d["kernels_hash"] = source_hash(a.source)
+        json.dump(d, sys.stdout, indent=1)
+        print()
+
+
+if __name__ == "__main__":
+    main()
