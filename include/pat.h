@@ -148,6 +148,83 @@ int  pat_residual(float* g, const float* g_meas, float* sq, long count_per, int 
 int  pat_profile_enable(pat_plan* plan, int enable);
 int  pat_profile_read(const pat_plan* plan, int which, float* ms, int max_kernels, int* count);
 
+/* Launch shapes of a plan's kernels (tile sizes; none changes the result
+ * beyond the summation order of the scalar endpoint/data sums).
+ * pat_plan_create picks defaults for max_batch; pat_autotune_plan measures. */
+typedef struct {
+    int col_np;   /* column pairs per column-pass workgroup, 1..64                           */
+    int row_rpb;  /* spectrum rows per row-pass workgroup, 1..64                             */
+    int ring_rt;  /* radial frequencies (rings) per ring-kernel workgroup, 1..64             */
+    int dct_dp;   /* detector pairs per cosine-transform workgroup, 1..64                    */
+    int gat_cb;   /* polar-interpolation workgroup width: 64, 128, 192 or 256 columns        */
+    int gat_th;   /* interpolation bands (footprint base rows) per workgroup, 1..4096        */
+    int spr_cb;   /* spread workgroup width: 64, 128, 192 or 256 columns                     */
+    int spr_th;   /* spread output rows per workgroup, 1..4096                               */
+} pat_launch;
+
+/* pat_plan_get_launch copies the plan's launch shapes.  pat_plan_set_launch
+ * replaces them after checking them on the host: PAT_ERR_ARG for a field out
+ * of range, PAT_ERR_UNSUPPORTED if a tile needs more than the 160 KB of LDS
+ * or the 1024 threads a workgroup can have; on error the plan is unchanged.
+ * Calls already enqueued keep the shapes they were launched with.  The
+ * workspace size does not depend on the launch shapes. */
+int  pat_plan_get_launch(const pat_plan* plan, pat_launch* out);
+int  pat_plan_set_launch(pat_plan* plan, const pat_launch* cfg);
+
+/* Heterogeneous batch: `count` instances, each with its own plan (grid size,
+ * detector count and arc, time samples may all differ; a plan may appear
+ * several times).  pat_batch_forward / pat_batch_adjoint evaluate every
+ * instance with one launch per stage of the operator (five per call) instead
+ * of five per instance; the calls allocate nothing and do not synchronise, so
+ * a caller can record them into a HIP graph.  Instance i uses the FFT-stage
+ * tile shapes of plans[i] as they were at pat_batch_create; the interpolation
+ * and spread workgroups are common to the batch (pat_batch_set_launch).
+ * The plans must outlive the batch and be on the current device.
+ * pat_batch_create: PAT_ERR_ARG (NULL, count < 1 or > 65536, a NULL plan,
+ * plans on different devices), PAT_ERR_ALLOC / PAT_ERR_HIP (instance table
+ * upload).  The batch owns one device allocation (the instance table). */
+typedef struct pat_batch pat_batch;
+int  pat_batch_create(pat_plan* const* plans, int count, pat_batch** out);
+void pat_batch_destroy(pat_batch* batch);
+
+/* Workspace bytes of one batch call (the sum of the instances' workspaces,
+ * each 256-byte aligned); 0 for NULL. */
+size_t pat_batch_workspace_size(const pat_batch* batch);
+
+/* g_i = A_i f_i for every instance i.  f_ptrs and g_ptrs are DEVICE arrays of
+ * `count` device pointers (f_ptrs[i]: [N_i][N_i] FP32 read, g_ptrs[i]:
+ * [D_i][T_i] FP32 written), as in batched BLAS interfaces; the pointed-to
+ * buffers must be valid, distinct for outputs, and sized for instance i (the
+ * device arrays are not inspected on the host).  ws: at least
+ * pat_batch_workspace_size bytes, 256-byte aligned.
+ * Errors: PAT_ERR_ARG (NULL), PAT_ERR_WORKSPACE, PAT_ERR_HIP. */
+int  pat_batch_forward(const pat_batch* batch, const float* const* f_ptrs, float* const* g_ptrs,
+                       void* ws, size_t ws_bytes, void* stream);
+/* f_i = A_i* g_i for every instance i; same conventions (g_ptrs read, f_ptrs written). */
+int  pat_batch_adjoint(const pat_batch* batch, const float* const* g_ptrs, float* const* f_ptrs,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* The batch-wide interpolation and spread shapes (gat_cb, gat_th, spr_cb,
+ * spr_th of pat_launch; the other fields are ignored on set and returned as 0
+ * on get).  pat_batch_set_launch rewrites the device instance table and
+ * therefore waits for the device to be idle first.  Errors: PAT_ERR_ARG
+ * (NULL, field out of range), PAT_ERR_HIP. */
+int  pat_batch_get_launch(const pat_batch* batch, pat_launch* out);
+int  pat_batch_set_launch(pat_batch* batch, const pat_launch* cfg);
+
+/* Autotuner.  pat_autotune_plan times candidate launch shapes of `plan` at
+ * `batch` instances (1 <= batch <= max_batch) on the null stream, choosing each stage's shape by its own measured kernel
+ * time, applies the fastest, and records it in the JSON file cache_path
+ * under a key made of the geometry, the batch and the device name; when that
+ * key is already in the file the stored shapes are applied without timing.
+ * pat_autotune_batch does the same for a batch's interpolation and spread
+ * shapes.  cache_path may be NULL (no cache).  Both allocate temporary device
+ * buffers and synchronise: tuning calls, not for loops or graph capture.
+ * Errors: PAT_ERR_ARG, PAT_ERR_ALLOC, PAT_ERR_HIP, and PAT_ERR_ARG when the
+ * cache file exists but cannot be parsed. */
+int  pat_autotune_plan(pat_plan* plan, int batch, const char* cache_path);
+int  pat_autotune_batch(pat_batch* batch, const char* cache_path);
+
 /* Host-only helpers (no GPU needed).
  * pat_plan_derive: the sizes pat_plan_create would derive for `desc`, without
  * building tables (fields M, dlam, n_lam, K, n_psi, kappa, n_grid, len_czt are

@@ -21,10 +21,13 @@ from . import _lib
 from ._lib import (PatError, pat_plan_desc, pat_status_string, pat_plan_create, pat_plan_query,  # noqa: F401
                    pat_plan_destroy, pat_workspace_size, pat_forward, pat_adjoint, pat_tv_grad,
                    pat_pgd_update, pat_residual, pat_plan_derive, pat_bessel_jn_table,
-                   pat_profile_enable, pat_profile_read)
+                   pat_profile_enable, pat_profile_read, pat_launch, pat_plan_get_launch, pat_plan_set_launch,
+                   pat_batch_create, pat_batch_destroy, pat_batch_workspace_size, pat_batch_forward,
+                   pat_batch_adjoint, pat_batch_get_launch, pat_batch_set_launch, pat_autotune_plan,
+                   pat_autotune_batch)
 
-__all__ = ["PatPlan", "pat_operator", "PatOperatorFn", "tv_grad", "pgd_update", "residual", "PatError",
-           "desc_from_geometry", "library_path"]
+__all__ = ["PatPlan", "PatBatch", "pat_operator", "PatOperatorFn", "tv_grad", "pgd_update", "residual",
+           "PatError", "desc_from_geometry", "library_path"]
 
 
 def library_path() -> str:
@@ -124,11 +127,122 @@ class PatPlan:
                     _stream(self.device))
         return out
 
+    # -- launch shapes ---------------------------------------------------------------
+    @property
+    def launch(self) -> dict:
+        """The kernels' tile shapes (pat_launch fields)."""
+        return pat_plan_get_launch(self.handle).asdict()
+
+    def set_launch(self, **fields):
+        """Change some tile shapes; the library checks them (PatError if they do not fit)."""
+        c = pat_plan_get_launch(self.handle)
+        for k, v in fields.items():
+            if not hasattr(c, k):
+                raise KeyError(k)
+            setattr(c, k, int(v))
+        pat_plan_set_launch(self.handle, c)
+
+    def autotune(self, batch: int | None = None, cache_path: str | None = None) -> dict:
+        """Time candidate tile shapes at `batch` instances (default max_batch) and keep
+        the fastest per stage; cached in the JSON file `cache_path` when given."""
+        with torch.cuda.device(self.device):
+            torch.cuda.synchronize(self.device)
+            pat_autotune_plan(self.handle, self.max_batch if batch is None else int(batch), cache_path)
+        return self.launch
+
     def close(self):
         if getattr(self, "handle", None):
             pat_plan_destroy(self.handle)
             self.handle = None
         self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PatBatch:
+    """A heterogeneous batch: instance i is evaluated with plans[i] (grid size,
+    detector count, arc and time samples may differ).  forward/adjoint launch
+    each stage of the operator once for all instances; the calls allocate
+    nothing on the device once the pointer tables of a given set of tensors
+    exist, so they can be recorded into a CUDA/HIP graph."""
+
+    def __init__(self, plans):
+        if not plans:
+            raise ValueError("PatBatch needs at least one plan")
+        self.plans = list(plans)
+        self.device = self.plans[0].device
+        for p in self.plans:
+            if p.device != self.device:
+                raise ValueError("all plans of a batch must live on one GPU")
+        with torch.cuda.device(self.device):
+            self.handle = pat_batch_create([p.handle for p in self.plans])
+        self.count = len(self.plans)
+        self._ws = torch.empty(max(pat_batch_workspace_size(self.handle), 256), dtype=torch.uint8,
+                               device=self.device)
+        self._ptr_tables = {}
+
+    def _ptr_table(self, tensors, shapes, name):
+        if len(tensors) != self.count:
+            raise ValueError("%s: expected %d tensors, got %d" % (name, self.count, len(tensors)))
+        for i, (t, shp) in enumerate(zip(tensors, shapes)):
+            _check_tensor(t, "%s[%d]" % (name, i), shp, self.device)
+            if t.dim() != 2:
+                raise ValueError("%s[%d] must have shape %s" % (name, i, tuple(shp)))
+        key = tuple(t.data_ptr() for t in tensors)
+        tab = self._ptr_tables.get(key)
+        if tab is None:
+            tab = torch.tensor(key, dtype=torch.int64, device=self.device)
+            self._ptr_tables[key] = tab
+        return tab
+
+    def forward(self, fs, outs=None):
+        """[g_i] = [A_i f_i]; fs: list of (N_i, N_i) float32 GPU tensors."""
+        if outs is None:
+            outs = [torch.empty(p.data_shape, dtype=torch.float32, device=self.device) for p in self.plans]
+        fp = self._ptr_table(fs, [p.image_shape for p in self.plans], "fs")
+        gp = self._ptr_table(outs, [p.data_shape for p in self.plans], "outs")
+        pat_batch_forward(self.handle, fp.data_ptr(), gp.data_ptr(), self._ws.data_ptr(), self._ws.numel(),
+                          _stream(self.device))
+        return outs
+
+    def adjoint(self, gs, outs=None):
+        """[f_i] = [A_i* g_i]; gs: list of (D_i, T_i) float32 GPU tensors."""
+        if outs is None:
+            outs = [torch.empty(p.image_shape, dtype=torch.float32, device=self.device) for p in self.plans]
+        gp = self._ptr_table(gs, [p.data_shape for p in self.plans], "gs")
+        fp = self._ptr_table(outs, [p.image_shape for p in self.plans], "outs")
+        pat_batch_adjoint(self.handle, gp.data_ptr(), fp.data_ptr(), self._ws.data_ptr(), self._ws.numel(),
+                          _stream(self.device))
+        return outs
+
+    @property
+    def launch(self) -> dict:
+        c = pat_batch_get_launch(self.handle).asdict()
+        return {k: c[k] for k in ("gat_cb", "gat_th", "spr_cb", "spr_th")}
+
+    def set_launch(self, **fields):
+        c = pat_batch_get_launch(self.handle)
+        for k, v in fields.items():
+            if k not in ("gat_cb", "gat_th", "spr_cb", "spr_th"):
+                raise KeyError(k)
+            setattr(c, k, int(v))
+        pat_batch_set_launch(self.handle, c)
+
+    def autotune(self, cache_path: str | None = None) -> dict:
+        with torch.cuda.device(self.device):
+            torch.cuda.synchronize(self.device)
+            pat_autotune_batch(self.handle, cache_path)
+        return self.launch
+
+    def close(self):
+        if getattr(self, "handle", None):
+            pat_batch_destroy(self.handle)
+            self.handle = None
+        self._ptr_tables = {}
 
     def __del__(self):
         try:

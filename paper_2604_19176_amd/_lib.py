@@ -44,6 +44,14 @@ class pat_plan_info(ctypes.Structure):
                 ("workspace_per_instance", ctypes.c_size_t), ("table_bytes", ctypes.c_size_t)]
 
 
+class pat_launch(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int) for n in ("col_np", "row_rpb", "ring_rt", "dct_dp", "gat_cb", "gat_th",
+                                             "spr_cb", "spr_th")]
+
+    def asdict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -73,6 +81,17 @@ def load():
         "pat_plan_derive": (ci, [P(pat_plan_desc), P(pat_plan_info)]),
         "pat_bessel_jn_table": (ci, [ci, ctypes.c_double, P(ctypes.c_double)]),
         "pat_status_string": (ctypes.c_char_p, [ci]),
+        "pat_plan_get_launch": (ci, [vp, P(pat_launch)]),
+        "pat_plan_set_launch": (ci, [vp, P(pat_launch)]),
+        "pat_batch_create": (ci, [P(vp), ci, P(vp)]),
+        "pat_batch_destroy": (None, [vp]),
+        "pat_batch_workspace_size": (sz, [vp]),
+        "pat_batch_forward": (ci, [vp, vp, vp, vp, sz, vp]),
+        "pat_batch_adjoint": (ci, [vp, vp, vp, vp, sz, vp]),
+        "pat_batch_get_launch": (ci, [vp, P(pat_launch)]),
+        "pat_batch_set_launch": (ci, [vp, P(pat_launch)]),
+        "pat_autotune_plan": (ci, [vp, ci, ctypes.c_char_p]),
+        "pat_autotune_batch": (ci, [vp, ctypes.c_char_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -162,3 +181,56 @@ def pat_pgd_update(f_ptr, adj_ptr, tvg_ptr, count, tau, lam, stream) -> None:
 
 def pat_residual(g_ptr, gm_ptr, sq_ptr, count_per, batch, stream) -> None:
     _check(load().pat_residual(g_ptr, gm_ptr, sq_ptr, int(count_per), int(batch), stream), "pat_residual")
+
+
+def pat_plan_get_launch(plan) -> pat_launch:
+    c = pat_launch()
+    _check(load().pat_plan_get_launch(plan, ctypes.byref(c)), "pat_plan_get_launch")
+    return c
+
+
+def pat_plan_set_launch(plan, cfg: pat_launch) -> None:
+    _check(load().pat_plan_set_launch(plan, ctypes.byref(cfg)), "pat_plan_set_launch")
+
+
+def pat_batch_create(plans) -> int:
+    arr = (ctypes.c_void_p * len(plans))(*plans)
+    h = ctypes.c_void_p()
+    _check(load().pat_batch_create(arr, len(plans), ctypes.byref(h)), "pat_batch_create")
+    return h.value
+
+
+def pat_batch_destroy(batch) -> None:
+    load().pat_batch_destroy(batch)
+
+
+def pat_batch_workspace_size(batch) -> int:
+    return int(load().pat_batch_workspace_size(batch))
+
+
+def pat_batch_forward(batch, f_ptrs, g_ptrs, ws_ptr, ws_bytes, stream) -> None:
+    _check(load().pat_batch_forward(batch, f_ptrs, g_ptrs, ws_ptr, int(ws_bytes), stream), "pat_batch_forward")
+
+
+def pat_batch_adjoint(batch, g_ptrs, f_ptrs, ws_ptr, ws_bytes, stream) -> None:
+    _check(load().pat_batch_adjoint(batch, g_ptrs, f_ptrs, ws_ptr, int(ws_bytes), stream), "pat_batch_adjoint")
+
+
+def pat_batch_get_launch(batch) -> pat_launch:
+    c = pat_launch()
+    _check(load().pat_batch_get_launch(batch, ctypes.byref(c)), "pat_batch_get_launch")
+    return c
+
+
+def pat_batch_set_launch(batch, cfg: pat_launch) -> None:
+    _check(load().pat_batch_set_launch(batch, ctypes.byref(cfg)), "pat_batch_set_launch")
+
+
+def pat_autotune_plan(plan, batch: int, cache_path) -> None:
+    cp = None if cache_path is None else os.fsencode(cache_path)
+    _check(load().pat_autotune_plan(plan, int(batch), cp), "pat_autotune_plan")
+
+
+def pat_autotune_batch(batch, cache_path) -> None:
+    cp = None if cache_path is None else os.fsencode(cache_path)
+    _check(load().pat_autotune_batch(batch, cp), "pat_autotune_batch")

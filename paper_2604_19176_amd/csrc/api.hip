@@ -6,6 +6,9 @@
 #include "kernels.hip"
 
 #include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
 
 
 
@@ -14,6 +17,12 @@ using namespace pat;
 static size_t twb(int n) { return sizeof(float2) * (size_t)tw_lds_slots(n); }
 
 static unsigned xcd_grid(int items) { return (unsigned)(((items + kXcds - 1) / kXcds) * kXcds); }
+
+// Dynamic LDS of the interpolation ([8][cb + 7] float2 window) and of the
+// spread (2 cb staged points x 19 words).
+static size_t gather_lds(int cb) { return sizeof(float2) * 8 * (cb + 7); }
+static size_t spread_lds(int cb) { return sizeof(float) * 19 * 2 * cb; }
+static size_t fft_tile_lds(int nseq, int n) { return sizeof(float2) * (size_t)nseq * n + twb(n); }
 
 static int check_launch()
 {
@@ -47,21 +56,18 @@ extern "C" int pat_forward(const pat_plan* p, const float* f, float* g, int batc
     const LaunchCfg& c = p->cfg;
     const InstPtrs wsp{(char*)ws, p->ws.bytes};
     prof_mark(p, 0, 0, st);
-    hipLaunchKernelGGL(k_colpass_fwd, dim3(p->n_col_tiles, batch), dim3(p->thr_col), sizeof(float2) * c.col_np * d.Ng + twb(d.Ng),
-                       st, d, p->ws, f, wsp, c.col_np);
+    hipLaunchKernelGGL(k_colpass_fwd, dim3(p->n_col_tiles, batch), dim3(p->thr_col), fft_tile_lds(c.col_np, d.Ng), st,
+                       d, p->ws, f, wsp, c.col_np);
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, 1, st);
     hipLaunchKernelGGL(k_rowpass_fwd, dim3((d.Hy + c.row_rpb - 1) / c.row_rpb, batch), dim3(p->thr_row),
-                       sizeof(float2) * c.row_rpb * d.Ng + twb(d.Ng), st, d, p->ws, wsp, c.row_rpb);
+                       fft_tile_lds(c.row_rpb, d.Ng), st, d, p->ws, wsp, c.row_rpb);
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, 2, st);
     {
-        int cb = c.gat_cb, th = c.gat_th;
-        const long wide = (long)((d.Ng + 255) / 256) * ((d.NB + 31) / 32) * batch;
-        if (wide >= 512) { cb = 256; th = 32; }
+        const int cb = c.gat_cb, th = c.gat_th;
         const int items = ((d.Ng + cb - 1) / cb) * ((d.NB + th - 1) / th) * batch;
-        hipLaunchKernelGGL(k_gather, dim3(xcd_grid(items)), dim3(cb), sizeof(float2) * 8 * (cb + 7), st, d, p->ws, wsp,
-                           th, batch);
+        hipLaunchKernelGGL(k_gather, dim3(xcd_grid(items)), dim3(cb), gather_lds(cb), st, d, p->ws, wsp, th, batch);
     }
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, 3, st);
@@ -72,8 +78,8 @@ extern "C" int pat_forward(const pat_plan* p, const float* f, float* g, int batc
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, 4, st);
     hipLaunchKernelGGL(k_dct_det, dim3(xcd_grid(p->n_pair_tiles * batch)), dim3(p->thr_dct),
-                       sizeof(float2) * c.dct_dp * 2 * d.M + twb(2 * d.M), st, d, p->ws, wsp, g, (const float*)nullptr, c.dct_dp, 0,
-                       p->n_col_tiles, batch);
+                       fft_tile_lds(c.dct_dp, 2 * d.M), st, d, p->ws, wsp, g, (const float*)nullptr, c.dct_dp, 0, d.N,
+                       batch);
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, 5, st);
     return PAT_OK;
@@ -90,8 +96,7 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
     const InstPtrs wsp{(char*)ws, p->ws.bytes};
     prof_mark(p, 1, 0, st);
     hipLaunchKernelGGL(k_dct_det, dim3(xcd_grid(p->n_pair_tiles * batch)), dim3(p->thr_dct),
-                       sizeof(float2) * c.dct_dp * 2 * d.M + twb(2 * d.M), st, d, p->ws, wsp, (float*)nullptr, g, c.dct_dp, 1, 0,
-                       batch);
+                       fft_tile_lds(c.dct_dp, 2 * d.M), st, d, p->ws, wsp, (float*)nullptr, g, c.dct_dp, 1, 0, batch);
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 1, st);
     {
@@ -101,22 +106,19 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 2, st);
     {
-        // wide tiles amortise the per-band weight evaluation; narrow ones keep small batches parallel
-        int cb = c.spr_cb, th = c.spr_th;
-        const long wide = (long)((d.Ng + 255) / 256) * ((d.Hy + 15) / 16) * batch;
-        if (wide >= 1024) { cb = 256; th = 16; }
+        const int cb = c.spr_cb, th = c.spr_th;
         const int items = ((d.Ng + cb - 1) / cb) * ((d.Hy + th - 1) / th) * batch;
-        hipLaunchKernelGGL(k_spread, dim3(xcd_grid(items)), dim3(cb), sizeof(float) * 19 * 2 * cb, st, d, p->ws, wsp,
-                           th, 2 * cb, batch);
+        hipLaunchKernelGGL(k_spread, dim3(xcd_grid(items)), dim3(cb), spread_lds(cb), st, d, p->ws, wsp, th, 2 * cb,
+                           batch);
     }
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 3, st);
     hipLaunchKernelGGL(k_rowpass_adj, dim3((d.Hy + c.row_rpb - 1) / c.row_rpb, batch), dim3(p->thr_row),
-                       sizeof(float2) * c.row_rpb * d.Ng + twb(d.Ng), st, d, p->ws, wsp, c.row_rpb);
+                       fft_tile_lds(c.row_rpb, d.Ng), st, d, p->ws, wsp, c.row_rpb);
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 4, st);
-    hipLaunchKernelGGL(k_colpass_adj, dim3(p->n_col_tiles, batch), dim3(p->thr_col), sizeof(float2) * c.col_np * d.Ng + twb(d.Ng),
-                       st, d, p->ws, wsp, f, c.col_np, p->n_pair_tiles);
+    hipLaunchKernelGGL(k_colpass_adj, dim3(p->n_col_tiles, batch), dim3(p->thr_col), fft_tile_lds(c.col_np, d.Ng), st,
+                       d, p->ws, wsp, f, c.col_np, d.D);
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 5, st);
     return PAT_OK;
@@ -199,4 +201,249 @@ extern "C" const char* pat_status_string(int s)
         case PAT_ERR_ALLOC: return "device allocation failed";
         default: return "unknown status";
     }
+}
+
+// ---------------------------------------------------------------------------
+// launch shapes
+// ---------------------------------------------------------------------------
+namespace pat {
+int apply_launch(pat_plan* p, const LaunchCfg& c);
+}
+
+static void launch_to_public(const LaunchCfg& c, pat_launch* o)
+{
+    o->col_np = c.col_np;
+    o->row_rpb = c.row_rpb;
+    o->ring_rt = c.ring_rt;
+    o->dct_dp = c.dct_dp;
+    o->gat_cb = c.gat_cb;
+    o->gat_th = c.gat_th;
+    o->spr_cb = c.spr_cb;
+    o->spr_th = c.spr_th;
+}
+
+extern "C" int pat_plan_get_launch(const pat_plan* p, pat_launch* out)
+{
+    if (!p || !out) return PAT_ERR_ARG;
+    launch_to_public(p->cfg, out);
+    return PAT_OK;
+}
+
+extern "C" int pat_plan_set_launch(pat_plan* p, const pat_launch* in)
+{
+    if (!p || !in) return PAT_ERR_ARG;
+    LaunchCfg c = p->cfg;
+    c.col_np = in->col_np;
+    c.row_rpb = in->row_rpb;
+    c.ring_rt = in->ring_rt;
+    c.dct_dp = in->dct_dp;
+    c.gat_cb = in->gat_cb;
+    c.gat_th = in->gat_th;
+    c.spr_cb = in->spr_cb;
+    c.spr_th = in->spr_th;
+    return apply_launch(p, c);  // leaves the plan unchanged on error
+}
+
+// ---------------------------------------------------------------------------
+// heterogeneous batches: one launch per stage over every instance
+// ---------------------------------------------------------------------------
+
+static bool batch_shape_ok(const pat_launch& c)
+{
+    auto cb_ok = [](int cb) { return cb >= 64 && cb <= 256 && cb % 64 == 0; };
+    return cb_ok(c.gat_cb) && cb_ok(c.spr_cb) && c.gat_th >= 1 && c.gat_th <= 4096 && c.spr_th >= 1 &&
+           c.spr_th <= 4096;
+}
+
+// Per-stage work-item prefix sums for the current batch-wide shapes, and the
+// per-stage launch maxima.
+static void batch_layout(pat_batch* b)
+{
+    const int n = b->count;
+    b->base.assign((size_t)kNumStages * (n + 1), 0);
+    b->thr_col = b->thr_row = b->thr_ring = b->thr_dct = 0;
+    b->lds_col = b->lds_row = b->lds_ring = b->lds_dct = 0;
+    for (int i = 0; i < n; ++i) {
+        BatchInst& I = b->inst[i];
+        const pat_plan* p = b->plans[i];
+        const PlanDev& d = I.d;
+        I.gat_th = b->gat_th;
+        I.spr_th = b->spr_th;
+        int items[kNumStages];
+        items[kStCol] = I.n_col_tiles;
+        items[kStRow] = (d.Hy + I.row_rpb - 1) / I.row_rpb;
+        items[kStGather] = ((d.Ng + b->gat_cb - 1) / b->gat_cb) * ((d.NB + b->gat_th - 1) / b->gat_th);
+        items[kStRing] = (d.nlam + I.ring_rt - 1) / I.ring_rt;
+        items[kStDct] = I.n_pair_tiles;
+        items[kStSpread] = ((d.Ng + b->spr_cb - 1) / b->spr_cb) * ((d.Hy + b->spr_th - 1) / b->spr_th);
+        for (int s = 0; s < kNumStages; ++s)
+            b->base[(size_t)s * (n + 1) + i + 1] = b->base[(size_t)s * (n + 1) + i] + items[s];
+        b->thr_col = std::max<unsigned>(b->thr_col, p->thr_col);
+        b->thr_row = std::max<unsigned>(b->thr_row, p->thr_row);
+        b->thr_ring = std::max<unsigned>(b->thr_ring, p->thr_ring);
+        b->thr_dct = std::max<unsigned>(b->thr_dct, p->thr_dct);
+        b->lds_col = std::max(b->lds_col, fft_tile_lds(I.col_np, d.Ng));
+        b->lds_row = std::max(b->lds_row, fft_tile_lds(I.row_rpb, d.Ng));
+        b->lds_ring = std::max(b->lds_ring, p->lds_ring);
+        b->lds_dct = std::max(b->lds_dct, fft_tile_lds(I.dct_dp, 2 * d.M));
+    }
+}
+
+static int batch_upload(pat_batch* b)
+{
+    const size_t ti = sizeof(BatchInst) * (size_t)b->count;
+    if (hipMemcpy(b->table, b->inst.data(), ti, hipMemcpyHostToDevice) != hipSuccess) return PAT_ERR_HIP;
+    if (hipMemcpy((char*)b->table + b->base_off, b->base.data(), sizeof(int) * b->base.size(),
+                  hipMemcpyHostToDevice) != hipSuccess)
+        return PAT_ERR_HIP;
+    return PAT_OK;
+}
+
+extern "C" void pat_batch_destroy(pat_batch* b)
+{
+    if (!b) return;
+    if (b->table) {
+        int cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess) cur = b->device;
+        (void)hipSetDevice(b->device);
+        (void)hipFree(b->table);
+        (void)hipSetDevice(cur);
+    }
+    delete b;
+}
+
+extern "C" int pat_batch_create(pat_plan* const* plans, int count, pat_batch** out)
+{
+    if (!plans || !out || count < 1 || count > 65536) return PAT_ERR_ARG;
+    for (int i = 0; i < count; ++i)
+        if (!plans[i] || plans[i]->device != plans[0]->device) return PAT_ERR_ARG;
+    pat_batch* b = new (std::nothrow) pat_batch;
+    if (!b) return PAT_ERR_ALLOC;
+    b->count = count;
+    b->device = plans[0]->device;
+    b->plans.assign(plans, plans + count);
+    b->inst.resize(count);
+    size_t off = 0;
+    for (int i = 0; i < count; ++i) {
+        const pat_plan* p = plans[i];
+        BatchInst& I = b->inst[i];
+        std::memset(&I, 0, sizeof(I));
+        I.d = p->dev;
+        I.L = p->ws;
+        I.ws_off = off;
+        off += (p->ws.bytes + 255) & ~(size_t)255;
+        I.col_np = p->cfg.col_np;
+        I.row_rpb = p->cfg.row_rpb;
+        I.ring_rt = p->cfg.ring_rt;
+        I.dct_dp = p->cfg.dct_dp;
+        I.n_col_tiles = p->n_col_tiles;
+        I.n_pair_tiles = p->n_pair_tiles;
+    }
+    b->ws_bytes = off;
+    // wide interpolation and spread tiles unless the batch is small
+    long cells = 0;
+    for (int i = 0; i < count; ++i) cells += (long)b->inst[i].d.Ng * b->inst[i].d.Hy;
+    if (cells >= 8L * 512 * 265) { b->gat_cb = 256; b->gat_th = 32; b->spr_cb = 256; b->spr_th = 16; }
+    batch_layout(b);
+    b->base_off = (sizeof(BatchInst) * (size_t)count + 255) & ~(size_t)255;
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess || cur != b->device) { delete b; return PAT_ERR_ARG; }
+    if (hipMalloc(&b->table, b->base_off + sizeof(int) * b->base.size()) != hipSuccess) {
+        b->table = nullptr;
+        delete b;
+        return PAT_ERR_ALLOC;
+    }
+    const int rc = batch_upload(b);
+    if (rc != PAT_OK) { pat_batch_destroy(b); return rc; }
+    *out = b;
+    return PAT_OK;
+}
+
+extern "C" size_t pat_batch_workspace_size(const pat_batch* b) { return b ? b->ws_bytes : 0; }
+
+extern "C" int pat_batch_get_launch(const pat_batch* b, pat_launch* out)
+{
+    if (!b || !out) return PAT_ERR_ARG;
+    std::memset(out, 0, sizeof(*out));
+    out->gat_cb = b->gat_cb;
+    out->gat_th = b->gat_th;
+    out->spr_cb = b->spr_cb;
+    out->spr_th = b->spr_th;
+    return PAT_OK;
+}
+
+extern "C" int pat_batch_set_launch(pat_batch* b, const pat_launch* c)
+{
+    if (!b || !c || !batch_shape_ok(*c)) return PAT_ERR_ARG;
+    if (hipDeviceSynchronize() != hipSuccess) return PAT_ERR_HIP;
+    b->gat_cb = c->gat_cb;
+    b->gat_th = c->gat_th;
+    b->spr_cb = c->spr_cb;
+    b->spr_th = c->spr_th;
+    batch_layout(b);
+    return batch_upload(b);
+}
+
+static int batch_validate(const pat_batch* b, const void* a, const void* c, const void* ws, size_t ws_bytes)
+{
+    if (!b || !a || !c) return PAT_ERR_ARG;
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < b->ws_bytes) return PAT_ERR_WORKSPACE;
+    return PAT_OK;
+}
+
+static inline BatchDev batch_dev(const pat_batch* b)
+{
+    return BatchDev{(const BatchInst*)b->table, (const int*)((const char*)b->table + b->base_off), b->count};
+}
+
+static inline int batch_items(const pat_batch* b, int st) { return b->base[(size_t)st * (b->count + 1) + b->count]; }
+
+extern "C" int pat_batch_forward(const pat_batch* b, const float* const* f_ptrs, float* const* g_ptrs, void* ws,
+                                 size_t ws_bytes, void* stream)
+{
+    int rc = batch_validate(b, f_ptrs, g_ptrs, ws, ws_bytes);
+    if (rc != PAT_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const BatchDev bt = batch_dev(b);
+    char* w = (char*)ws;
+    hipLaunchKernelGGL(k_colpass_fwd_b, dim3(xcd_grid(batch_items(b, kStCol))), dim3(b->thr_col), b->lds_col, st, bt,
+                       f_ptrs, w);
+    if ((rc = check_launch())) return rc;
+    hipLaunchKernelGGL(k_rowpass_fwd_b, dim3(xcd_grid(batch_items(b, kStRow))), dim3(b->thr_row), b->lds_row, st, bt,
+                       w);
+    if ((rc = check_launch())) return rc;
+    hipLaunchKernelGGL(k_gather_b, dim3(xcd_grid(batch_items(b, kStGather))), dim3(b->gat_cb), gather_lds(b->gat_cb),
+                       st, bt, w);
+    if ((rc = check_launch())) return rc;
+    hipLaunchKernelGGL(k_ring_fwd_b<4>, dim3(xcd_grid(batch_items(b, kStRing))), dim3(b->thr_ring), b->lds_ring, st,
+                       bt, w);
+    if ((rc = check_launch())) return rc;
+    hipLaunchKernelGGL(k_dct_det_b, dim3(xcd_grid(batch_items(b, kStDct))), dim3(b->thr_dct), b->lds_dct, st, bt, w,
+                       g_ptrs, (const float* const*)nullptr, 0);
+    return check_launch();
+}
+
+extern "C" int pat_batch_adjoint(const pat_batch* b, const float* const* g_ptrs, float* const* f_ptrs, void* ws,
+                                 size_t ws_bytes, void* stream)
+{
+    int rc = batch_validate(b, g_ptrs, f_ptrs, ws, ws_bytes);
+    if (rc != PAT_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const BatchDev bt = batch_dev(b);
+    char* w = (char*)ws;
+    hipLaunchKernelGGL(k_dct_det_b, dim3(xcd_grid(batch_items(b, kStDct))), dim3(b->thr_dct), b->lds_dct, st, bt, w,
+                       (float* const*)nullptr, g_ptrs, 1);
+    if ((rc = check_launch())) return rc;
+    hipLaunchKernelGGL(k_ring_adj_b<4>, dim3(xcd_grid(batch_items(b, kStRing))), dim3(b->thr_ring), b->lds_ring, st,
+                       bt, w);
+    if ((rc = check_launch())) return rc;
+    hipLaunchKernelGGL(k_spread_b, dim3(xcd_grid(batch_items(b, kStSpread))), dim3(b->spr_cb), spread_lds(b->spr_cb),
+                       st, bt, w);
+    if ((rc = check_launch())) return rc;
+    hipLaunchKernelGGL(k_rowpass_adj_b, dim3(xcd_grid(batch_items(b, kStRow))), dim3(b->thr_row), b->lds_row, st, bt,
+                       w);
+    if ((rc = check_launch())) return rc;
+    hipLaunchKernelGGL(k_colpass_adj_b, dim3(xcd_grid(batch_items(b, kStCol))), dim3(b->thr_col), b->lds_col, st, bt,
+                       w, f_ptrs);
+    return check_launch();
 }

@@ -66,6 +66,18 @@ __device__ float block_sum(float v, float* scratch)
     return r;
 }
 
+// Sum of v[0..n) in an order fixed by n alone (64 strided partial sums, then a
+// fixed shuffle tree): the same bits for every workgroup size.  Must be
+// reached by all threads of the first wave; the total is returned to lane 0.
+__device__ __forceinline__ float wave0_fixed_sum(const float* __restrict__ v, int n)
+{
+    float s = 0.f;
+    for (int t = threadIdx.x; t < n; t += 64) s += v[t];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    return s;
+}
+
 struct InstPtrs {
     char* ws;         // workspace base of instance 0
     size_t stride;    // bytes per instance
@@ -74,40 +86,46 @@ struct InstPtrs {
 // ---------------------------------------------------------------------------
 // forward: column pass (FFT along y of real columns, packed in pairs)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_colpass_fwd(PlanDev d, WsLayout L, const float* __restrict__ f,
-                                                     InstPtrs wsp, int NP)
+__device__ __forceinline__ void colpass_fwd_tile(const PlanDev& d, const WsLayout& L, const float* __restrict__ fb,
+                                                 char* wb, int tile, int NP, float2* sm, float* red_s)
 {
-    extern __shared__ float2 sm[];
-    __shared__ float red_s[1024];
-    const int b = blockIdx.y;
     const int N = d.N, Ng = d.Ng, CT = 2 * NP;
-    const float* fb = f + (size_t)b * N * N;
-    char* wb = wsp.ws + (size_t)b * wsp.stride;
     float2* X1 = (float2*)(wb + L.x1);
     float* red = (float*)(wb + L.red);
-    const int j0 = blockIdx.x * CT;
+    const int j0 = tile * CT;
     const TwLds tw = tw_lds_build(sm + NP * Ng, d.ffts[d.fft_grid], d.tw);
     for (int e = threadIdx.x; e < NP * Ng; e += blockDim.x) sm[e] = make_float2(0.f, 0.f);
     __syncthreads();
-    float msum = 0.f;
     for (int e = threadIdx.x; e < N * CT; e += blockDim.x) {
         const int i = e / CT, jj = e - i * CT, j = j0 + jj;
         float v = 0.f;
         if (j < N) {
             const int2 mr = d.mask_rows[i];
-            if (j >= mr.x && j < mr.y) {
-                const float fv = fb[(size_t)i * N + j];
-                msum += fv;
-                v = fv * d.deap[i] * d.deap[j];
-            }
+            if (j >= mr.x && j < mr.y) v = fb[(size_t)i * N + j] * d.deap[i] * d.deap[j];
         }
         int pos = i - N / 2;
         if (pos < 0) pos += Ng;
         float* slot = (float*)&sm[(jj >> 1) * Ng + pos];
         slot[jj & 1] = v;
     }
-    const float tot = block_sum(msum, red_s);
-    if (threadIdx.x == 0) red[blockIdx.x] = tot * d.h2;
+    // endpoint term: h^2 times the masked sum of each column, rows in 8 classes
+    // mod 8 summed in order (independent of the workgroup size and the tiling)
+    for (int t = threadIdx.x; t < 8 * CT; t += blockDim.x) {
+        const int jj = t % CT, c = t / CT, j = j0 + jj;
+        float sc = 0.f;
+        if (j < N)
+            for (int i = c; i < N; i += 8) {
+                const int2 mr = d.mask_rows[i];
+                if (j >= mr.x && j < mr.y) sc += fb[(size_t)i * N + j];
+            }
+        red_s[t] = sc;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < CT && j0 + (int)threadIdx.x < N) {
+        float sc = 0.f;
+        for (int c = 0; c < 8; ++c) sc += red_s[c * CT + threadIdx.x];
+        red[j0 + threadIdx.x] = sc * d.h2;
+    }
     __syncthreads();
     fft_lds<kMaxB>(sm, Ng, NP, d.ffts[d.fft_grid], tw, false);
     for (int e = threadIdx.x; e < d.Hy * CT; e += blockDim.x) {
@@ -130,15 +148,13 @@ __global__ __launch_bounds__(1024) void k_colpass_fwd(PlanDev d, WsLayout L, con
 // ---------------------------------------------------------------------------
 // forward: row pass (FFT along x)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_rowpass_fwd(PlanDev d, WsLayout L, InstPtrs wsp, int RPB)
+__device__ __forceinline__ void rowpass_fwd_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile, int RPB,
+                                                 float2* sm)
 {
-    extern __shared__ float2 sm[];
-    const int b = blockIdx.y;
     const int N = d.N, Ng = d.Ng;
-    char* wb = wsp.ws + (size_t)b * wsp.stride;
     const float2* X1 = (const float2*)(wb + L.x1);
     float2* G = (float2*)(wb + L.grid);
-    const int r0 = blockIdx.x * RPB;
+    const int r0 = tile * RPB;
     const int nr = min(RPB, d.Hy - r0);
     const TwLds tw = tw_lds_build(sm + RPB * Ng, d.ffts[d.fft_grid], d.tw);
     for (int e = threadIdx.x; e < nr * Ng; e += blockDim.x) sm[e] = make_float2(0.f, 0.f);
@@ -176,20 +192,16 @@ __global__ __launch_bounds__(1024) void k_rowpass_fwd(PlanDev d, WsLayout L, Ins
 // and each thread interpolates one point from LDS.  Output Fb[slot] (band
 // order) times the half-pixel phase.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gather(PlanDev d, WsLayout L, InstPtrs wsp, int TH, int batch)
+__device__ __forceinline__ void gather_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile, int TH,
+                                            float2* win /* [8][CB + 7] */)
 {
-    extern __shared__ float2 win[];  // [8][W]
     const int Ng = d.Ng, NB = d.NB, Hy = d.Hy;
     const int CB = blockDim.x, W = CB + 7;
-    const int ncb = (Ng + CB - 1) / CB, nrb = (NB + TH - 1) / TH;
-    const int item = xcd_item(blockIdx.x, ncb * nrb * batch);
-    if (item < 0) return;
-    const int b = item / (ncb * nrb);
-    const int rbk = (item - b * ncb * nrb) / ncb, cbk = item - b * ncb * nrb - rbk * ncb;
+    const int ncb = (Ng + CB - 1) / CB;
+    const int rbk = tile / ncb, cbk = tile - rbk * ncb;
     const int C0 = cbk * CB, R0 = rbk * TH;
     const int rend = min(R0 + TH, NB);
     const int cend = min(C0 + CB, Ng);
-    char* wb = wsp.ws + (size_t)b * wsp.stride;
     const float2* __restrict__ G = (const float2*)(wb + L.grid);
     float2* Fb = (float2*)(wb + L.polar);
     // rows R0 .. R0 + 6 of the window
@@ -282,14 +294,9 @@ __device__ __forceinline__ RingLds ring_lds(float2* sm, const PlanDev& d, int RT
 }
 
 template <int RB>
-__global__ __launch_bounds__(1024) void k_ring_fwd(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
+__device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile, int RT,
+                                              float2* sm)
 {
-    extern __shared__ float2 sm[];
-    const int ntile = (d.nlam + RT - 1) / RT;
-    const int item = xcd_item(blockIdx.x, ntile * batch);
-    if (item < 0) return;
-    const int b = item / ntile, tile = item - b * ntile;
-    char* wb = wsp.ws + (size_t)b * wsp.stride;
     const float2* __restrict__ Fp = (const float2*)(wb + L.polar);
     float* hT = (float*)(wb + L.hdet);
     const int D = d.D, S = d.syn_len;
@@ -377,14 +384,9 @@ __global__ __launch_bounds__(1024) void k_ring_fwd(PlanDev d, WsLayout L, InstPt
 }
 
 template <int RB>
-__global__ __launch_bounds__(1024) void k_ring_adj(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
+__device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile, int RT,
+                                              float2* sm)
 {
-    extern __shared__ float2 sm[];
-    const int ntile = (d.nlam + RT - 1) / RT;
-    const int item = xcd_item(blockIdx.x, ntile * batch);
-    if (item < 0) return;
-    const int b = item / ntile, tile = item - b * ntile;
-    char* wb = wsp.ws + (size_t)b * wsp.stride;
     const float* hT = (const float*)(wb + L.hdet);
     float2* Hb = (float2*)(wb + L.polar);
     const int D = d.D, S = d.syn_len;
@@ -484,51 +486,55 @@ __global__ __launch_bounds__(1024) void k_ring_adj(PlanDev d, WsLayout L, InstPt
 //   forward: hT [D][nlam] -> g [D][T] (+ kappa * mass)
 //   adjoint: g [D][T] -> hT [D][nlam] (+ per-workgroup partial sums of g)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_dct_det(PlanDev d, WsLayout L, InstPtrs wsp, float* __restrict__ gout,
-                                                  const float* __restrict__ gin, int DP, int adj, int n_mass, int batch)
+// gout / gin point at this instance's [D][T] data.
+__device__ __forceinline__ void dct_tile(const PlanDev& d, const WsLayout& L, char* wb, float* __restrict__ gout,
+                                         const float* __restrict__ gin, int tile, int DP, int adj, int n_mass,
+                                         float2* sm, float* red_s, float* mass_s)
 {
-    extern __shared__ float2 sm[];
-    __shared__ float red_s[1024];
-    __shared__ float mass_s;
-    const int ntile = ((d.D + 1) / 2 + DP - 1) / DP;
-    const int item = xcd_item(blockIdx.x, ntile * batch);
-    if (item < 0) return;
-    const int b = item / ntile, tile = item - b * ntile;
     const int twoM = 2 * d.M, D = d.D, T = d.T, NL = d.nlam;
-    char* wb = wsp.ws + (size_t)b * wsp.stride;
     float* hT = (float*)(wb + L.hdet);
     float* red = (float*)(wb + L.red);
     const int p0 = tile * DP;                        // first detector pair
     const int np = min(DP, (D + 1) / 2 - p0);
     const int nin = adj ? T : NL;
     const int nout = adj ? NL : T;
-    const float* src = adj ? gin + (size_t)b * D * T : hT;
+    const float* src = adj ? gin : hT;
     const int sld = adj ? T : NL;
-    if (!adj && threadIdx.x == 0) {
-        float m = 0.f;
-        for (int t = 0; t < n_mass; ++t) m += red[t];
-        mass_s = m;
+    if (!adj && threadIdx.x < 64) {
+        const float m = wave0_fixed_sum(red, n_mass);
+        if (threadIdx.x == 0) *mass_s = m;
     }
     const TwLds tw = tw_lds_build(sm + DP * twoM, d.ffts[d.fft_dct], d.tw);
     for (int e = threadIdx.x; e < np * twoM; e += blockDim.x) sm[e] = make_float2(0.f, 0.f);
     __syncthreads();
-    float ls = 0.f;
     for (int e = threadIdx.x; e < np * nin; e += blockDim.x) {
         const int p = e / nin, q = e - p * nin;
         const int d0 = 2 * (p0 + p);
         const float re = src[(size_t)d0 * sld + q];
         const float im = (d0 + 1 < D) ? src[(size_t)(d0 + 1) * sld + q] : 0.f;
-        ls += re + im;
         sm[p * twoM + q + 1] = make_float2(re, im);
     }
     if (adj) {
-        const float tot = block_sum(ls, red_s);
-        if (threadIdx.x == 0) red[tile] = tot;
+        // data sum of each detector of the tile: samples in 8 classes mod 8, summed in order
+        const int nd = 2 * np;
+        for (int t = threadIdx.x; t < 8 * nd; t += blockDim.x) {
+            const int dd = t % nd, c = t / nd, dg = 2 * p0 + dd;
+            float sc = 0.f;
+            if (dg < D)
+                for (int q = c; q < T; q += 8) sc += gin[(size_t)dg * T + q];
+            red_s[t] = sc;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < nd && 2 * p0 + (int)threadIdx.x < D) {
+            float sc = 0.f;
+            for (int c = 0; c < 8; ++c) sc += red_s[c * nd + threadIdx.x];
+            red[2 * p0 + threadIdx.x] = sc;
+        }
     }
     __syncthreads();
     fft_lds<kMaxB>(sm, twoM, np, d.ffts[d.fft_dct], tw, false);
-    const float add = adj ? 0.f : d.kappa * mass_s;
-    float* dst = adj ? hT : gout + (size_t)b * D * T;
+    const float add = adj ? 0.f : d.kappa * *mass_s;
+    float* dst = adj ? hT : gout;
     const int dld = adj ? NL : T;
     for (int e = threadIdx.x; e < np * nout; e += blockDim.x) {
         const int p = e / nout, q = e - p * nout;
@@ -613,17 +619,13 @@ __device__ __forceinline__ void spread_visit(const float* wxs, const float* wys,
 }
 
 // CAP must be 2 * blockDim.x (two staged points per thread per chunk).
-__global__ __launch_bounds__(256) void k_spread(PlanDev d, WsLayout L, InstPtrs wsp, int TH, int CAP, int batch)
+__device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile, int TH, int CAP,
+                                            float* sf /* [CAP][19] */)
 {
-    extern __shared__ float sf[];
     const int Ng = d.Ng, NB = d.NB, Hy = d.Hy;
     const int CB = blockDim.x;
-    const int ncb = (Ng + CB - 1) / CB, nrb = (Hy + TH - 1) / TH;
-    const int item = xcd_item(blockIdx.x, ncb * nrb * batch);
-    if (item < 0) return;
-    const int b = item / (ncb * nrb);
-    const int rb_ = (item - b * ncb * nrb) / ncb, cb_ = item - b * ncb * nrb - rb_ * ncb;
-    char* wb = wsp.ws + (size_t)b * wsp.stride;
+    const int ncb = (Ng + CB - 1) / CB;
+    const int rb_ = tile / ncb, cb_ = tile - rb_ * ncb;
     const float2* __restrict__ H = (const float2*)(wb + L.polar);
     float2* Gt = (float2*)(wb + L.grid);
     float* wxs = sf;                       // [CAP][8]
@@ -691,15 +693,13 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev d, WsLayout L, InstPtrs 
 // ---------------------------------------------------------------------------
 // adjoint: row pass (inverse FFT along x, crop to the N image columns)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_rowpass_adj(PlanDev d, WsLayout L, InstPtrs wsp, int RPB)
+__device__ __forceinline__ void rowpass_adj_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile, int RPB,
+                                                 float2* sm)
 {
-    extern __shared__ float2 sm[];
-    const int b = blockIdx.y;
     const int N = d.N, Ng = d.Ng;
-    char* wb = wsp.ws + (size_t)b * wsp.stride;
     const float2* Gt = (const float2*)(wb + L.grid);
     float2* X1 = (float2*)(wb + L.x1);
-    const int r0 = blockIdx.x * RPB;
+    const int r0 = tile * RPB;
     const int nr = min(RPB, d.Hy - r0);
     const TwLds tw = tw_lds_build(sm + RPB * Ng, d.ffts[d.fft_grid], d.tw);
     for (int e = threadIdx.x; e < nr * Ng; e += blockDim.x) sm[e] = Gt[(size_t)r0 * Ng + e];
@@ -717,23 +717,17 @@ __global__ __launch_bounds__(1024) void k_rowpass_adj(PlanDev d, WsLayout L, Ins
 // adjoint: column pass (Hermitian symmetrisation, inverse FFT along y, real
 // parts of two columns packed as one complex transform, crop, deapodise, mask)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_colpass_adj(PlanDev d, WsLayout L, InstPtrs wsp, float* __restrict__ f,
-                                                     int NP, int n_sum)
+__device__ __forceinline__ void colpass_adj_tile(const PlanDev& d, const WsLayout& L, char* wb, float* __restrict__ fb,
+                                                 int tile, int NP, int n_sum, float2* sm, float* gsum_s)
 {
-    extern __shared__ float2 sm[];
-    __shared__ float gsum_s;
-    const int b = blockIdx.y;
     const int N = d.N, Ng = d.Ng, CT = 2 * NP;
-    char* wb = wsp.ws + (size_t)b * wsp.stride;
     const float2* X1 = (const float2*)(wb + L.x1);
     const float* red = (const float*)(wb + L.red);
-    float* fb = f + (size_t)b * N * N;
-    if (threadIdx.x == 0) {
-        float s = 0.f;
-        for (int t = 0; t < n_sum; ++t) s += red[t];
-        gsum_s = s;
+    if (threadIdx.x < 64) {
+        const float s = wave0_fixed_sum(red, n_sum);
+        if (threadIdx.x == 0) *gsum_s = s;
     }
-    const int j0 = blockIdx.x * CT;
+    const int j0 = tile * CT;
     const int top = Ng / 2 + 4;
     const TwLds tw = tw_lds_build(sm + NP * Ng, d.ffts[d.fft_grid], d.tw);
     for (int e = threadIdx.x; e < NP * Ng; e += blockDim.x) {
@@ -759,7 +753,7 @@ __global__ __launch_bounds__(1024) void k_colpass_adj(PlanDev d, WsLayout L, Ins
     }
     __syncthreads();
     fft_lds<kMaxB>(sm, Ng, NP, d.ffts[d.fft_grid], tw, true);
-    const float kt = d.kappa * d.h2 * gsum_s;
+    const float kt = d.kappa * d.h2 * *gsum_s;
     for (int e = threadIdx.x; e < N * CT; e += blockDim.x) {
         const int i = e / CT, jj = e - i * CT, j = j0 + jj;
         if (j >= N) continue;
@@ -770,6 +764,222 @@ __global__ __launch_bounds__(1024) void k_colpass_adj(PlanDev d, WsLayout L, Ins
         const int2 mr = d.mask_rows[i];
         fb[(size_t)i * N + j] = (j >= mr.x && j < mr.y) ? d.deap[i] * d.deap[j] * c + kt : 0.f;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Launch wrappers.  Single-plan kernels: `batch` instances of one plan with
+// instance workspaces `wsp.stride` bytes apart.  Batch kernels (suffix _b):
+// one launch covers every instance of a heterogeneous batch; the workgroup's
+// work item is located in the per-stage prefix table and the instance's plan
+// is read from the device table.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int batch_find(const int* __restrict__ base, int count, int item)
+{
+    int lo = 0, hi = count;  // base[lo] <= item < base[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (base[mid] <= item) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Locates the workgroup's instance and local tile for stage `st`; false for padding workgroups.
+__device__ __forceinline__ bool batch_item(const BatchDev& bt, int st, int& inst, int& tile)
+{
+    const int* base = bt.base + st * (bt.count + 1);
+    const int item = xcd_item(blockIdx.x, base[bt.count]);
+    if (item < 0) return false;
+    inst = batch_find(base, bt.count, item);
+    tile = item - base[inst];
+    return true;
+}
+
+__global__ __launch_bounds__(1024) void k_colpass_fwd(PlanDev d, WsLayout L, const float* __restrict__ f,
+                                                     InstPtrs wsp, int NP)
+{
+    extern __shared__ float2 sm[];
+    __shared__ float red_s[1024];
+    const int b = blockIdx.y;
+    colpass_fwd_tile(d, L, f + (size_t)b * d.N * d.N, wsp.ws + (size_t)b * wsp.stride, blockIdx.x, NP, sm, red_s);
+}
+
+__global__ __launch_bounds__(1024) void k_colpass_fwd_b(BatchDev bt, const float* const* __restrict__ fin, char* ws)
+{
+    extern __shared__ float2 sm[];
+    __shared__ float red_s[1024];
+    int i, tile;
+    if (!batch_item(bt, kStCol, i, tile)) return;
+    const BatchInst& I = bt.inst[i];
+    const PlanDev d = I.d;
+    colpass_fwd_tile(d, I.L, fin[i], ws + I.ws_off, tile, I.col_np, sm, red_s);
+}
+
+__global__ __launch_bounds__(1024) void k_rowpass_fwd(PlanDev d, WsLayout L, InstPtrs wsp, int RPB)
+{
+    extern __shared__ float2 sm[];
+    rowpass_fwd_tile(d, L, wsp.ws + (size_t)blockIdx.y * wsp.stride, blockIdx.x, RPB, sm);
+}
+
+__global__ __launch_bounds__(1024) void k_rowpass_fwd_b(BatchDev bt, char* ws)
+{
+    extern __shared__ float2 sm[];
+    int i, tile;
+    if (!batch_item(bt, kStRow, i, tile)) return;
+    const BatchInst& I = bt.inst[i];
+    const PlanDev d = I.d;
+    rowpass_fwd_tile(d, I.L, ws + I.ws_off, tile, I.row_rpb, sm);
+}
+
+__global__ __launch_bounds__(256) void k_gather(PlanDev d, WsLayout L, InstPtrs wsp, int TH, int batch)
+{
+    extern __shared__ float2 win[];
+    const int per = ((d.Ng + (int)blockDim.x - 1) / (int)blockDim.x) * ((d.NB + TH - 1) / TH);
+    const int item = xcd_item(blockIdx.x, per * batch);
+    if (item < 0) return;
+    const int b = item / per;
+    gather_tile(d, L, wsp.ws + (size_t)b * wsp.stride, item - b * per, TH, win);
+}
+
+__global__ __launch_bounds__(256) void k_gather_b(BatchDev bt, char* ws)
+{
+    extern __shared__ float2 win[];
+    int i, tile;
+    if (!batch_item(bt, kStGather, i, tile)) return;
+    const BatchInst& I = bt.inst[i];
+    const PlanDev d = I.d;
+    gather_tile(d, I.L, ws + I.ws_off, tile, I.gat_th, win);
+}
+
+template <int RB>
+__global__ __launch_bounds__(1024) void k_ring_fwd(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
+{
+    extern __shared__ float2 sm[];
+    const int ntile = (d.nlam + RT - 1) / RT;
+    const int item = xcd_item(blockIdx.x, ntile * batch);
+    if (item < 0) return;
+    const int b = item / ntile;
+    ring_fwd_tile<RB>(d, L, wsp.ws + (size_t)b * wsp.stride, item - b * ntile, RT, sm);
+}
+
+template <int RB>
+__global__ __launch_bounds__(1024) void k_ring_fwd_b(BatchDev bt, char* ws)
+{
+    extern __shared__ float2 sm[];
+    int i, tile;
+    if (!batch_item(bt, kStRing, i, tile)) return;
+    const BatchInst& I = bt.inst[i];
+    const PlanDev d = I.d;
+    ring_fwd_tile<RB>(d, I.L, ws + I.ws_off, tile, I.ring_rt, sm);
+}
+
+template <int RB>
+__global__ __launch_bounds__(1024) void k_ring_adj(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
+{
+    extern __shared__ float2 sm[];
+    const int ntile = (d.nlam + RT - 1) / RT;
+    const int item = xcd_item(blockIdx.x, ntile * batch);
+    if (item < 0) return;
+    const int b = item / ntile;
+    ring_adj_tile<RB>(d, L, wsp.ws + (size_t)b * wsp.stride, item - b * ntile, RT, sm);
+}
+
+template <int RB>
+__global__ __launch_bounds__(1024) void k_ring_adj_b(BatchDev bt, char* ws)
+{
+    extern __shared__ float2 sm[];
+    int i, tile;
+    if (!batch_item(bt, kStRing, i, tile)) return;
+    const BatchInst& I = bt.inst[i];
+    const PlanDev d = I.d;
+    ring_adj_tile<RB>(d, I.L, ws + I.ws_off, tile, I.ring_rt, sm);
+}
+
+__global__ __launch_bounds__(1024) void k_dct_det(PlanDev d, WsLayout L, InstPtrs wsp, float* __restrict__ gout,
+                                                  const float* __restrict__ gin, int DP, int adj, int n_mass, int batch)
+{
+    extern __shared__ float2 sm[];
+    __shared__ float red_s[1024];
+    __shared__ float mass_s;
+    const int ntile = ((d.D + 1) / 2 + DP - 1) / DP;
+    const int item = xcd_item(blockIdx.x, ntile * batch);
+    if (item < 0) return;
+    const int b = item / ntile;
+    const size_t go = (size_t)b * d.D * d.T;
+    dct_tile(d, L, wsp.ws + (size_t)b * wsp.stride, adj ? nullptr : gout + go, adj ? gin + go : nullptr,
+             item - b * ntile, DP, adj, n_mass, sm, red_s, &mass_s);
+}
+
+// adj = 0: out[i] receives the data of instance i; adj = 1: in[i] is read.
+__global__ __launch_bounds__(1024) void k_dct_det_b(BatchDev bt, char* ws, float* const* __restrict__ out,
+                                                    const float* const* __restrict__ in, int adj)
+{
+    extern __shared__ float2 sm[];
+    __shared__ float red_s[1024];
+    __shared__ float mass_s;
+    int i, tile;
+    if (!batch_item(bt, kStDct, i, tile)) return;
+    const BatchInst& I = bt.inst[i];
+    const PlanDev d = I.d;
+    dct_tile(d, I.L, ws + I.ws_off, adj ? nullptr : out[i], adj ? in[i] : nullptr, tile, I.dct_dp, adj, d.N, sm,
+             red_s, &mass_s);
+}
+
+__global__ __launch_bounds__(256) void k_spread(PlanDev d, WsLayout L, InstPtrs wsp, int TH, int CAP, int batch)
+{
+    extern __shared__ float sf[];
+    const int per = ((d.Ng + (int)blockDim.x - 1) / (int)blockDim.x) * ((d.Hy + TH - 1) / TH);
+    const int item = xcd_item(blockIdx.x, per * batch);
+    if (item < 0) return;
+    const int b = item / per;
+    spread_tile(d, L, wsp.ws + (size_t)b * wsp.stride, item - b * per, TH, CAP, sf);
+}
+
+__global__ __launch_bounds__(256) void k_spread_b(BatchDev bt, char* ws)
+{
+    extern __shared__ float sf[];
+    int i, tile;
+    if (!batch_item(bt, kStSpread, i, tile)) return;
+    const BatchInst& I = bt.inst[i];
+    const PlanDev d = I.d;
+    spread_tile(d, I.L, ws + I.ws_off, tile, I.spr_th, 2 * (int)blockDim.x, sf);
+}
+
+__global__ __launch_bounds__(1024) void k_rowpass_adj(PlanDev d, WsLayout L, InstPtrs wsp, int RPB)
+{
+    extern __shared__ float2 sm[];
+    rowpass_adj_tile(d, L, wsp.ws + (size_t)blockIdx.y * wsp.stride, blockIdx.x, RPB, sm);
+}
+
+__global__ __launch_bounds__(1024) void k_rowpass_adj_b(BatchDev bt, char* ws)
+{
+    extern __shared__ float2 sm[];
+    int i, tile;
+    if (!batch_item(bt, kStRow, i, tile)) return;
+    const BatchInst& I = bt.inst[i];
+    const PlanDev d = I.d;
+    rowpass_adj_tile(d, I.L, ws + I.ws_off, tile, I.row_rpb, sm);
+}
+
+__global__ __launch_bounds__(1024) void k_colpass_adj(PlanDev d, WsLayout L, InstPtrs wsp, float* __restrict__ f,
+                                                     int NP, int n_sum)
+{
+    extern __shared__ float2 sm[];
+    __shared__ float gsum_s;
+    const int b = blockIdx.y;
+    colpass_adj_tile(d, L, wsp.ws + (size_t)b * wsp.stride, f + (size_t)b * d.N * d.N, blockIdx.x, NP, n_sum, sm,
+                     &gsum_s);
+}
+
+__global__ __launch_bounds__(1024) void k_colpass_adj_b(BatchDev bt, char* ws, float* const* __restrict__ fout)
+{
+    extern __shared__ float2 sm[];
+    __shared__ float gsum_s;
+    int i, tile;
+    if (!batch_item(bt, kStCol, i, tile)) return;
+    const BatchInst& I = bt.inst[i];
+    const PlanDev d = I.d;
+    colpass_adj_tile(d, I.L, ws + I.ws_off, fout[i], tile, I.col_np, d.D, sm, &gsum_s);
 }
 
 // ---------------------------------------------------------------------------

@@ -8,6 +8,10 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
+#include "../../include/pat.h"
+
 namespace pat {
 
 // ES ("exponential of semicircle") interpolation kernel of the polar
@@ -101,12 +105,43 @@ struct WsLayout {
     size_t bytes;    // total per instance
 };
 
+// Work-item classes of the stage kernels; a heterogeneous batch launches each
+// class once over all of its instances.
+enum BatchStage {
+    kStCol = 0,   // column passes: ceil(N / (2 col_np)) tiles
+    kStRow,       // row passes: ceil(Hy / row_rpb) tiles
+    kStGather,    // interpolation: ceil(Ng / gat_cb) x ceil(NB / gat_th) tiles
+    kStRing,      // ring kernels: ceil(nlam / ring_rt) tiles
+    kStDct,       // cosine transforms: ceil(ceil(D / 2) / dct_dp) tiles
+    kStSpread,    // spread: ceil(Ng / spr_cb) x ceil(Hy / spr_th) tiles
+    kNumStages
+};
+
+// One instance of a heterogeneous batch (device table entry).  Tile shapes
+// that fix a workgroup's size (gat_cb, spr_cb) are common to the batch; the
+// others are per instance.
+struct BatchInst {
+    PlanDev d;
+    WsLayout L;
+    size_t ws_off;    // byte offset of the instance's workspace in the batch workspace
+    int col_np, row_rpb, ring_rt, dct_dp, gat_th, spr_th;
+    int n_col_tiles, n_pair_tiles;
+};
+
+struct BatchDev {
+    const BatchInst* inst;  // [count]
+    const int* base;        // [kNumStages][count + 1]: first work item of each instance, per stage
+    int count;
+};
+
 }  // namespace pat
 
 struct pat_plan {
+    pat_plan_desc desc;     // as given at creation
     pat::PlanDev dev;
     pat::LaunchCfg cfg;
     pat::WsLayout ws;
+    pat::FftDev h_fft_grid, h_fft_dct;  // host copies of two FFT descriptors (launch checks)
     int device;
     int max_batch;
     int n_psi_uniform;
@@ -120,10 +155,26 @@ struct pat_plan {
     int n_col_tiles;        // column-pass tiles (mass partials)
     int n_pair_tiles;       // cosine-transform tiles (data-sum partials)
     int thr_col, thr_row, thr_ring, thr_dct;  // workgroup sizes of the FFT kernels
-    int ring_mb;            // butterflies per thread per stage in the ring kernels (4, 8 or 16)
+    int ring_mb;            // butterflies per thread per stage in the ring kernels
     size_t lds_ring;        // dynamic LDS of the ring kernels
     // optional per-kernel timing (pat_profile_enable): events around each launch
     int prof;
     hipEvent_t ev[2][8];
     int ev_count[2];
+};
+
+// A heterogeneous batch (pat_batch_create).
+struct pat_batch {
+    int count = 0;
+    int device = 0;
+    std::vector<pat_plan*> plans;
+    std::vector<pat::BatchInst> inst;  // host copy of the device table
+    std::vector<int> base;             // [kNumStages][count + 1]
+    void* table = nullptr;             // device: BatchInst[count], then base
+    size_t base_off = 0;
+    size_t ws_bytes = 0;
+    int gat_cb = 64, gat_th = 16, spr_cb = 64, spr_th = 32;
+    // per-stage workgroup size and dynamic LDS (maxima over the instances)
+    unsigned thr_col = 0, thr_row = 0, thr_ring = 0, thr_dct = 0;
+    size_t lds_col = 0, lds_row = 0, lds_ring = 0, lds_dct = 0;
 };

@@ -255,18 +255,63 @@ static int fft_threads(int nseq, const FftDev& fd)
     return nseq * tps;
 }
 
-// Launch shapes: LDS per workgroup <= 64 KB and every FFT stage fits
-// 1024 threads x 4 butterflies.
-int choose_launch(pat_plan* p, const std::vector<FftDev>& fd, int max_ring_bf,
+static size_t twb_bytes(int n) { return sizeof(float2) * (size_t)tw_lds_slots(n); }
+
+// Dynamic LDS of the ring kernels: half-ring FFT buffer, synthesis buffers,
+// [D][RT] detector tile and four twiddle tables.
+static size_t ring_lds_bytes(const PlanDev& d, int RT)
+{
+    const size_t Pmax = d.npsi_max / 2, S = d.syn_len;
+    const size_t B2 = std::max(S, Pmax), B3 = d.syn_half ? S / 2 : 0;
+    return sizeof(float2) * (Pmax + B2 + B3) + (((size_t)d.D * RT + 1) & ~(size_t)1) * 4 + twb_bytes((int)Pmax) +
+           twb_bytes(d.npsi_max) + twb_bytes((int)S) + twb_bytes((int)S);
+}
+
+constexpr size_t kLdsMax = 160 * 1024;  // LDS a gfx950 workgroup can hold
+
+// Checks a launch configuration against the LDS, thread and width limits of
+// the kernels and, if it fits, makes it the plan's (workgroup sizes, ring
+// LDS, tile counts).  The workspace layout does not depend on it.
+int apply_launch(pat_plan* p, const LaunchCfg& c)
+{
+    const PlanDev& d = p->dev;
+    auto fft_ok = [&](int v, size_t each, const FftDev& f, size_t fixed) {
+        return v >= 1 && v <= 64 && v * each + fixed <= kLdsMax && fft_threads(v, f) <= 1024;
+    };
+    auto cb_ok = [](int cb) { return cb >= 64 && cb <= 256 && cb % 64 == 0; };
+    if (c.ring_rt < 1 || c.ring_rt > 64 || c.gat_th < 1 || c.gat_th > 4096 || c.spr_th < 1 || c.spr_th > 4096 ||
+        !cb_ok(c.gat_cb) || !cb_ok(c.spr_cb))
+        return PAT_ERR_ARG;
+    if (!fft_ok(c.col_np, sizeof(float2) * d.Ng, p->h_fft_grid, twb_bytes(d.Ng)) ||
+        !fft_ok(c.row_rpb, sizeof(float2) * d.Ng, p->h_fft_grid, twb_bytes(d.Ng)) ||
+        !fft_ok(c.dct_dp, sizeof(float2) * 2 * d.M, p->h_fft_dct, twb_bytes(2 * d.M)))
+        return PAT_ERR_UNSUPPORTED;
+    const size_t lr = ring_lds_bytes(d, c.ring_rt);
+    if (lr > kLdsMax) return PAT_ERR_UNSUPPORTED;
+    p->cfg = c;
+    p->cfg.spr_cap = 2 * c.spr_cb;
+    p->lds_ring = lr;
+    p->thr_col = fft_threads(c.col_np, p->h_fft_grid);
+    p->thr_row = fft_threads(c.row_rpb, p->h_fft_grid);
+    p->thr_dct = fft_threads(c.dct_dp, p->h_fft_dct);
+    p->n_col_tiles = (d.N + 2 * c.col_np - 1) / (2 * c.col_np);
+    p->n_pair_tiles = ((d.D + 1) / 2 + c.dct_dp - 1) / c.dct_dp;
+    return PAT_OK;
+}
+
+// Default launch shapes: FFT tiles of <= 64 KB of LDS where possible (several
+// workgroups per CU; a single sequence may use up to 160 KB), interpolation
+// and spread tiles sized for `max_batch` instances.
+int choose_launch(pat_plan* p, const std::vector<FftDev>& fd, int max_batch,
                   const std::vector<const FftDev*>& ring_descs)
 {
     const PlanDev& d = p->dev;
-    LaunchCfg& c = p->cfg;
-    const size_t kLds = 64 * 1024, kLdsMax = 160 * 1024;
-    const FftDev& fg = fd[d.fft_grid];
-    const FftDev& fm = fd[d.fft_dct];
-    // prefer <= 64 KB of LDS per workgroup (several workgroups per CU); a single
-    // sequence that does not fit may use up to the 160 KB a gfx950 workgroup can hold
+    LaunchCfg c{};
+    const size_t kLds = 64 * 1024;
+    p->h_fft_grid = fd[d.fft_grid];
+    p->h_fft_dct = fd[d.fft_dct];
+    const FftDev& fg = p->h_fft_grid;
+    const FftDev& fm = p->h_fft_dct;
     auto pick = [&](int maxn, size_t bytes_each, const FftDev& f, size_t fixed) {
         const int tps = (fft_min_tps(f, 4) + 31) / 32 * 32;
         int v = maxn;
@@ -274,41 +319,28 @@ int choose_launch(pat_plan* p, const std::vector<FftDev>& fd, int max_ring_bf,
         if (v * bytes_each + fixed <= kLds && v * tps <= 1024) return v;
         return (bytes_each + fixed <= kLdsMax && tps <= 1024) ? 1 : 0;
     };
-    auto twb = [](int n) { return sizeof(float2) * (size_t)tw_lds_slots(n); };
-    c.col_np = pick(8, sizeof(float2) * d.Ng, fg, twb(d.Ng));
-    c.row_rpb = pick(8, sizeof(float2) * d.Ng, fg, twb(d.Ng));
-    c.dct_dp = pick(4, sizeof(float2) * 2 * d.M, fm, twb(2 * d.M));
-    // ring kernels: half-ring FFT buffer, synthesis buffers, [D][RT] detector tile, four twiddle tables
+    c.col_np = pick(8, sizeof(float2) * d.Ng, fg, twb_bytes(d.Ng));
+    c.row_rpb = pick(8, sizeof(float2) * d.Ng, fg, twb_bytes(d.Ng));
+    c.dct_dp = pick(4, sizeof(float2) * 2 * d.M, fm, twb_bytes(2 * d.M));
     c.ring_rt = 1;
-    {
-        const size_t Pmax = d.npsi_max / 2, S = d.syn_len;
-        const size_t B2 = std::max(S, Pmax), B3 = d.syn_half ? S / 2 : 0;
-        p->lds_ring = sizeof(float2) * (Pmax + B2 + B3) + (((size_t)d.D * c.ring_rt + 1) & ~(size_t)1) * 4 +
-                      twb((int)Pmax) + twb(d.npsi_max) + twb((int)S) + twb((int)S);
-    }
-    c.gat_cb = 64;
-    c.gat_th = 16;
-    c.spr_cb = 64;
-    c.spr_th = 32;
-    c.spr_cap = 128;
-    if (!c.col_np || !c.row_rpb || !c.dct_dp || p->lds_ring > kLdsMax) return PAT_ERR_UNSUPPORTED;
-    p->thr_col = fft_threads(c.col_np, fg);
-    p->thr_row = fft_threads(c.row_rpb, fg);
-    p->thr_dct = fft_threads(c.dct_dp, fm);
+    // wide tiles amortise the per-band work; narrow ones keep small batches parallel
+    const long gwide = (long)((d.Ng + 255) / 256) * ((d.NB + 31) / 32) * max_batch;
+    c.gat_cb = gwide >= 512 ? 256 : 64;
+    c.gat_th = gwide >= 512 ? 32 : 16;
+    const long swide = (long)((d.Ng + 255) / 256) * ((d.Hy + 15) / 16) * max_batch;
+    c.spr_cb = swide >= 1024 ? 256 : 64;
+    c.spr_th = swide >= 1024 ? 16 : 32;
+    if (!c.col_np || !c.row_rpb || !c.dct_dp) return PAT_ERR_UNSUPPORTED;
     // ring kernels: as few threads per ring as the FFT stages allow (one wave when
     // possible), so that many rings are resident per CU to hide their latency
-    (void)max_ring_bf;
     p->thr_ring = 0;
-    for (int mb : {4}) {
-        for (int thr : {64, 128, 256, 512, 1024}) {
-            bool ok = true;
-            for (const FftDev* f : ring_descs) ok = ok && fft_min_tps(*f, mb) <= thr;
-            if (ok) { p->thr_ring = thr; p->ring_mb = mb; break; }
-        }
-        if (p->thr_ring) break;
+    for (int thr : {64, 128, 256, 512, 1024}) {
+        bool ok = true;
+        for (const FftDev* f : ring_descs) ok = ok && fft_min_tps(*f, 4) <= thr;
+        if (ok) { p->thr_ring = thr; p->ring_mb = 4; break; }
     }
     if (!p->thr_ring) return PAT_ERR_UNSUPPORTED;
-    return PAT_OK;
+    return apply_launch(p, c);
 }
 
 void layout_workspace(pat_plan* p)
@@ -320,9 +352,8 @@ void layout_workspace(pat_plan* p)
     w.grid = o;   o += align256(sizeof(float2) * (size_t)d.Hy * d.Ng);
     w.hdet = o;   o += align256(sizeof(float) * (size_t)d.D * d.nlam);
     w.polar = o;  o += align256(sizeof(float2) * (size_t)d.npts);
-    p->n_col_tiles = (d.N + 2 * p->cfg.col_np - 1) / (2 * p->cfg.col_np);
-    p->n_pair_tiles = ((d.D + 1) / 2 + p->cfg.dct_dp - 1) / p->cfg.dct_dp;
-    w.n_red = std::max(p->n_col_tiles, p->n_pair_tiles);
+    // endpoint-term partial sums: one per image column (forward) or detector (adjoint)
+    w.n_red = std::max(d.N, d.D);
     w.red = o;    o += align256(sizeof(float) * (size_t)w.n_red);
     w.bytes = o;
 }
@@ -517,15 +548,13 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     }
 
     {
-        int max_ring_bf = 0;
         std::vector<const FftDev*> rdesc;
         for (int n = 0; n < nlam; ++n) {
-            max_ring_bf = std::max(max_ring_bf, fft_min_tps(ffts.descs[ringFft[n]], 4));
             if (std::find(rdesc.begin(), rdesc.end(), &ffts.descs[ringFft[n]]) == rdesc.end())
                 rdesc.push_back(&ffts.descs[ringFft[n]]);
         }
         rdesc.push_back(&ffts.descs[d.syn_half ? d.fft_synh : d.fft_syn]);
-        int rc = choose_launch(p, ffts.descs, max_ring_bf, rdesc);
+        int rc = choose_launch(p, ffts.descs, desc->max_batch, rdesc);
         if (rc != PAT_OK) return rc;
     }
 
@@ -591,6 +620,7 @@ extern "C" int pat_plan_create(const pat_plan_desc* desc, pat_plan** out)
     rel(d.deap); rel(d.mask_rows); rel(d.pt_geo); rel(d.pt_phase); rel(d.ring_off); rel(d.ring_K);
     rel(d.ring_fft); rel(d.ring_twn); rel(d.ring_joff); rel(d.Jw); rel(d.perm); rel(d.bpt_geo); rel(d.bpt_phase);
     rel(d.band_ptr); rel(d.syn_pre); rel(d.czt_post); rel(d.czt_vhat); rel(d.ffts); rel(d.tw);
+    p->desc = *desc;
     p->max_batch = desc->max_batch;
     p->n_psi_uniform = dv.n_psi;
     p->M = dv.M;

@@ -120,3 +120,27 @@ def test_calls_reject_null_arguments_before_launch(patlib):
     assert lib.pat_workspace_size(None, 1) == 0
     assert lib.pat_plan_query(None, None) == -1
     lib.pat_plan_destroy(None)  # no-op
+
+
+def test_batch_and_tuner_entry_points_reject_null_arguments(patlib):
+    """The launch-shape, batch and autotuner entry points check their
+    arguments on the host before any HIP call."""
+    lib = patlib.load()
+    one = ctypes.c_void_p(1)
+    cfg = patlib.pat_launch()
+    assert lib.pat_plan_get_launch(None, ctypes.byref(cfg)) == -1
+    assert lib.pat_plan_set_launch(None, ctypes.byref(cfg)) == -1
+    out = ctypes.c_void_p()
+    assert lib.pat_batch_create(None, 1, ctypes.byref(out)) == -1
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert lib.pat_batch_create(arr, 2, ctypes.byref(out)) == -1     # NULL plans
+    assert lib.pat_batch_create(arr, 0, ctypes.byref(out)) == -1     # empty batch
+    assert out.value is None
+    assert lib.pat_batch_workspace_size(None) == 0
+    assert lib.pat_batch_forward(None, one, one, one, 1 << 20, None) == -1
+    assert lib.pat_batch_adjoint(None, one, one, one, 1 << 20, None) == -1
+    assert lib.pat_batch_get_launch(None, ctypes.byref(cfg)) == -1
+    assert lib.pat_batch_set_launch(None, ctypes.byref(cfg)) == -1
+    assert lib.pat_autotune_plan(None, 1, None) == -1
+    assert lib.pat_autotune_batch(None, None) == -1
+    lib.pat_batch_destroy(None)  # no-op
