@@ -11,6 +11,8 @@ it.  Before timing, instance 0 is checked against the FP64 oracle (relative
 L2 <= 1e-5); that oracle run, timed on the host cores, is the CPU baseline.
 
 Other workloads (one JSON line each; not the default):
+  --workload mixed   64 heterogeneous instances (N 128..512, D 64..512, arcs 90..360 deg)
+                     batched vs per-instance launches, eager and graph-captured
   --workload tv3     TV projected-gradient iterations/s at 256^2, 128 detectors on 120 deg
   --workload large   1024^2, 1024 detectors on 270 deg, 2048 samples, batch 8:
                      TV iterations/s and staged HBM GB/s
@@ -150,6 +152,44 @@ def time_pairs(torch, plan, f, g, gout, fout, steps, warmup):
     return e0.elapsed_time(e1) / steps, time.perf_counter() - t0
 
 
+def time_graph(torch, dev, fn, steps, warmup=2):
+    """Milliseconds per replay of fn() captured into one CUDA/HIP graph."""
+    s = torch.cuda.Stream(device=dev)
+    s.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(s):
+        fn()
+    torch.cuda.current_stream(dev).wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        fn()
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        graph.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    del graph
+    return e0.elapsed_time(e1) / steps
+
+
+def time_eager(torch, dev, fn, steps, warmup=2):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
 def copy_calibration(torch, dev):
     """One float32 multiply-by-one over CALIB_ELEMS elements: a copy of known
     size whose byte counters calibrate the PMC traffic figures."""
@@ -189,6 +229,11 @@ def bench_default(args):
     g_out = torch.empty_like(g_meas)
     f_out = torch.empty_like(f)
     copy_calibration(torch, dev)
+    launch = {"batched": plan.launch, "single": plan1.launch}
+    if args.tune:
+        print("bench: autotuning the launch shapes", file=sys.stderr, flush=True)
+        launch = {"batched": plan.autotune(batch=B, cache_path=args.tune_cache),
+                  "single": plan1.autotune(batch=1, cache_path=args.tune_cache)}
 
     parity = None
     cpu = None
@@ -222,7 +267,13 @@ def bench_default(args):
     f1, g1 = f[0:1].contiguous(), g_meas[0:1].contiguous()
     go1, fo1 = torch.empty_like(g1), torch.empty_like(f1)
     ms_single, _ = time_pairs(torch, plan1, f1, g1, go1, fo1, max(args.steps, 20), args.warmup)
+
+    def pair1():
+        plan1.forward(f1, out=go1)
+        plan1.adjoint(g1, out=fo1)
+    ms_single_graph = time_graph(torch, dev, pair1, max(args.steps, 20))
     kms = kernel_times(pat, plan, f, g_meas, g_out, f_out)
+    kms1 = kernel_times(pat, plan1, f1, g1, go1, fo1)
     abytes = algorithmic_bytes(plan.info, geom)
     gbs = {n: abytes[n] * B / (kms[n] * 1e-3) / 1e9 for n in kms}
     out = {
@@ -242,14 +293,17 @@ def bench_default(args):
                                "batch %d; step = A then A* over the batch" % B,
                    "n": geom.n, "n_det": geom.n_det, "n_t": geom.n_t, "arc_deg": 180, "batch": B},
         "single": {"value": round(1000.0 / ms_single, 1), "unit": "pairs/s", "ms_per_pair": round(ms_single, 4),
-                   "batch": 1},
+                   "batch": 1, "graph_value": round(1000.0 / ms_single_graph, 1),
+                   "graph_ms_per_pair": round(ms_single_graph, 4)},
         "batched_over_single": round(value * ms_single / 1000.0, 2),
         "wall_s_timed": round(wall, 3),
         "parity": parity,
         "roofline": roofline(kms, plan.info, geom, B),
         "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
         "kernels_gbs": {k: round(v, 1) for k, v in gbs.items()},
+        "kernels_ms_single": {k: round(v, 4) for k, v in kms1.items()},
         "kernels_hash": kernels_hash(),
+        "launch": launch, "tuned": bool(args.tune),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -310,6 +364,88 @@ def bench_tv(args, cfg_id, steps_default, seed_stride):
     plan.close()
 
 
+def bench_mixed(args):
+    """64 heterogeneous instances (grids 128^2 / 256^2 / 512^2, 64..512
+    detectors, 90 / 180 / 360 degree arcs, T = 2N): one PatBatch call per
+    direction against a loop of per-instance plan calls, eager and as graphs."""
+    import numpy as np
+    import torch
+
+    import paper_2604_19176_amd as pat
+    from pat_inputs import make_phantom
+    from pat_inputs.geometry import mixed_batch_geometries
+
+    dev = torch.device("cuda", 0)
+    inst = mixed_batch_geometries(64)
+    plans, by_geo = [], {}
+    for geom, _ in inst:
+        key = (geom.n, geom.n_det, geom.n_t, round(geom.arc_span, 9))
+        if key not in by_geo:
+            by_geo[key] = pat.PatPlan(geom)
+        plans.append(by_geo[key])
+    print("bench: mixed batch of %d instances, %d plans" % (len(inst), len(by_geo)), file=sys.stderr, flush=True)
+    fs = [torch.tensor(make_phantom(g.n, 5, 1, 0, s), dtype=torch.float32, device=dev) for g, s in inst]
+    gs = [p.forward(f) for p, f in zip(plans, fs)]
+    gout = [torch.empty_like(g) for g in gs]
+    aout = [torch.empty_like(f) for f in fs]
+    batch = pat.PatBatch(plans)
+    tuned = batch.autotune(None) if args.tune else batch.launch
+    # parity: batch equals per-instance bitwise; N = 128 instances against the oracle
+    bo = batch.forward(fs)
+    ba = batch.adjoint(gs)
+    for i, p in enumerate(plans):
+        assert torch.equal(bo[i], p.forward(fs[i])) and torch.equal(ba[i], p.adjoint(gs[i])), i
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        errs = []
+        for i in [i for i, (g, _) in enumerate(inst) if g.n == 128][:2]:
+            g = inst[i][0]
+            rf = oracle.forward(g, fs[i].cpu().double().numpy())
+            ra = oracle.adjoint(g, gs[i].cpu().double().numpy())
+            errs.append((float(np.linalg.norm(bo[i].cpu().double().numpy() - rf) / np.linalg.norm(rf)),
+                         float(np.linalg.norm(ba[i].cpu().double().numpy() - ra) / np.linalg.norm(ra))))
+        assert all(e <= 1e-5 for pair in errs for e in pair), errs
+        parity = {"instances_checked": len(errs), "max_rel_l2": max(max(e) for e in errs)}
+
+    def batched():
+        batch.forward(fs, gout)
+        batch.adjoint(gs, aout)
+
+    def per_instance():
+        for i, p in enumerate(plans):
+            p.forward(fs[i], out=gout[i])
+            p.adjoint(gs[i], out=aout[i])
+
+    print("bench: timing", file=sys.stderr, flush=True)
+    steps = max(5, args.steps // 2)
+    t_b_graph = time_graph(torch, dev, batched, steps)
+    t_b_eager = time_eager(torch, dev, batched, steps)
+    t_p_graph = time_graph(torch, dev, per_instance, steps)
+    t_p_eager = time_eager(torch, dev, per_instance, steps)
+    n = len(inst)
+    out = {
+        "metric": "A+A* operator pairs/sec, heterogeneous batch of 64 (FP32, rel L2 <= 1e-5 vs FP64)",
+        "value": round(n * 1000.0 / t_b_graph, 1), "unit": "pairs/s", "n_gpus": 1, "steps": steps, "warmup": 2,
+        "ms_per_step": round(t_b_graph, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "64 instances: N in {128,256,512}, D in {64,128,256,512}, arcs {90,180,360} deg, "
+                               "T = 2N; one batched A and A* per step, captured as one graph",
+                   "instances": n, "plans": len(by_geo)},
+        "batched_graph_pairs_s": round(n * 1000.0 / t_b_graph, 1),
+        "batched_eager_pairs_s": round(n * 1000.0 / t_b_eager, 1),
+        "per_instance_graph_pairs_s": round(n * 1000.0 / t_p_graph, 1),
+        "per_instance_eager_pairs_s": round(n * 1000.0 / t_p_eager, 1),
+        "batched_over_per_instance_graph": round(t_p_graph / t_b_graph, 2),
+        "batched_over_per_instance_eager": round(t_p_eager / t_b_eager, 2),
+        "launch": tuned, "tuned": bool(args.tune), "parity": parity,
+    }
+    print(json.dumps(out), flush=True)
+    batch.close()
+    for p in by_geo.values():
+        p.close()
+
+
 def bench_paper(args):
     import numpy as np
     import torch
@@ -339,7 +475,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=64)
-    ap.add_argument("--workload", default="default", choices=["default", "tv3", "large", "paper"])
+    ap.add_argument("--workload", default="default", choices=["default", "mixed", "tv3", "large", "paper"])
+    ap.add_argument("--tune", action="store_true", help="autotune the launch shapes before timing")
+    ap.add_argument("--tune-cache", default=None, help="JSON cache file of the autotuner")
     ap.add_argument("--tv-steps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -351,10 +489,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "default":
         bench_default(args)
+    elif args.workload == "mixed":
+        bench_mixed(args)
     elif args.workload == "tv3":
         bench_tv(args, 3, 500, 1000)
     elif args.workload == "large":
-        bench_tv(args, 5, 200, 1)
+        bench_tv(args, 5, 2000, 1)
     else:
         bench_paper(args)
 

@@ -152,12 +152,13 @@ int  pat_profile_read(const pat_plan* plan, int which, float* ms, int max_kernel
  * beyond the summation order of the scalar endpoint/data sums).
  * pat_plan_create picks defaults for max_batch; pat_autotune_plan measures. */
 typedef struct {
-    int col_np;   /* column pairs per column-pass workgroup, 1..64                           */
-    int row_rpb;  /* spectrum rows per row-pass workgroup, 1..64                             */
+    int col_np;   /* column pairs per column-pass workgroup, 1..16                           */
+    int row_rpb;  /* spectrum rows per row-pass workgroup, 1..16                             */
     int ring_rt;  /* radial frequencies (rings) per ring-kernel workgroup, 1..64             */
-    int dct_dp;   /* detector pairs per cosine-transform workgroup, 1..64                    */
-    int gat_cb;   /* polar-interpolation workgroup width: 64, 128, 192 or 256 columns        */
-    int gat_th;   /* interpolation bands (footprint base rows) per workgroup, 1..4096        */
+    int dct_dp;   /* detector pairs per cosine-transform workgroup, 1..16                    */
+    int gat_cb;   /* polar-interpolation tile width in grid columns: multiple of 8, 8..512  */
+    int gat_th;   /* interpolation bands (footprint base rows) per tile: 1, 2, 4, .., 64;
+                     the tile window (gat_th + 7) x (gat_cb + 7) x 8 bytes is at most 64 KB  */
     int spr_cb;   /* spread workgroup width: 64, 128, 192 or 256 columns                     */
     int spr_th;   /* spread output rows per workgroup, 1..4096                               */
 } pat_launch;

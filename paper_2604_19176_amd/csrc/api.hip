@@ -20,8 +20,11 @@ static unsigned xcd_grid(int items) { return (unsigned)(((items + kXcds - 1) / k
 
 // Dynamic LDS of the interpolation ([8][cb + 7] float2 window) and of the
 // spread (2 cb staged points x 19 words).
-static size_t gather_lds(int cb) { return sizeof(float2) * 8 * (cb + 7); }
-static size_t spread_lds(int cb) { return sizeof(float) * 19 * 2 * cb; }
+static size_t spread_lds(int cb, int ib) { return sizeof(float) * spread_lds_words(2 * cb, ib); }
+
+// Instances per spread workgroup for a batch of one plan: the ES weights and
+// indexing of a tile are shared by up to four instances.
+static int spread_ib(int batch) { return batch >= 4 ? 4 : (batch >= 2 ? 2 : 1); }
 static size_t fft_tile_lds(int nseq, int n) { return sizeof(float2) * (size_t)nseq * n + twb(n); }
 
 static int check_launch()
@@ -67,7 +70,8 @@ extern "C" int pat_forward(const pat_plan* p, const float* f, float* g, int batc
     {
         const int cb = c.gat_cb, th = c.gat_th;
         const int items = ((d.Ng + cb - 1) / cb) * ((d.NB + th - 1) / th) * batch;
-        hipLaunchKernelGGL(k_gather, dim3(xcd_grid(items)), dim3(cb), gather_lds(cb), st, d, p->ws, wsp, th, batch);
+        hipLaunchKernelGGL(k_gather, dim3(xcd_grid(items)), dim3(kGatherThreads), gather_lds_bytes(cb, th), st, d,
+                           p->ws, wsp, cb, th, batch);
     }
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, 3, st);
@@ -106,10 +110,15 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 2, st);
     {
-        const int cb = c.spr_cb, th = c.spr_th;
-        const int items = ((d.Ng + cb - 1) / cb) * ((d.Hy + th - 1) / th) * batch;
-        hipLaunchKernelGGL(k_spread, dim3(xcd_grid(items)), dim3(cb), spread_lds(cb), st, d, p->ws, wsp, th, 2 * cb,
-                           batch);
+        const int cb = c.spr_cb, th = c.spr_th, ib = spread_ib(batch);
+        const int items = ((d.Ng + cb - 1) / cb) * ((d.Hy + th - 1) / th) * ((batch + ib - 1) / ib);
+        const dim3 grid(xcd_grid(items)), blk(cb);
+        if (ib == 4)
+            hipLaunchKernelGGL(k_spread<4>, grid, blk, spread_lds(cb, 4), st, d, p->ws, wsp, th, 2 * cb, batch);
+        else if (ib == 2)
+            hipLaunchKernelGGL(k_spread<2>, grid, blk, spread_lds(cb, 2), st, d, p->ws, wsp, th, 2 * cb, batch);
+        else
+            hipLaunchKernelGGL(k_spread<1>, grid, blk, spread_lds(cb, 1), st, d, p->ws, wsp, th, 2 * cb, batch);
     }
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 3, st);
@@ -250,9 +259,7 @@ extern "C" int pat_plan_set_launch(pat_plan* p, const pat_launch* in)
 
 static bool batch_shape_ok(const pat_launch& c)
 {
-    auto cb_ok = [](int cb) { return cb >= 64 && cb <= 256 && cb % 64 == 0; };
-    return cb_ok(c.gat_cb) && cb_ok(c.spr_cb) && c.gat_th >= 1 && c.gat_th <= 4096 && c.spr_th >= 1 &&
-           c.spr_th <= 4096;
+    return gather_shape_ok(c.gat_cb, c.gat_th) && spread_shape_ok(c.spr_cb, c.spr_th);
 }
 
 // Per-stage work-item prefix sums for the current batch-wide shapes, and the
@@ -343,7 +350,9 @@ extern "C" int pat_batch_create(pat_plan* const* plans, int count, pat_batch** o
     // wide interpolation and spread tiles unless the batch is small
     long cells = 0;
     for (int i = 0; i < count; ++i) cells += (long)b->inst[i].d.Ng * b->inst[i].d.Hy;
-    if (cells >= 8L * 512 * 265) { b->gat_cb = 256; b->gat_th = 32; b->spr_cb = 256; b->spr_th = 16; }
+    b->gat_cb = 64;
+    b->gat_th = 8;
+    if (cells >= 8L * 512 * 265) { b->gat_cb = 128; b->gat_th = 16; b->spr_cb = 256; b->spr_th = 16; }
     batch_layout(b);
     b->base_off = (sizeof(BatchInst) * (size_t)count + 255) & ~(size_t)255;
     int cur = 0;
@@ -412,8 +421,8 @@ extern "C" int pat_batch_forward(const pat_batch* b, const float* const* f_ptrs,
     hipLaunchKernelGGL(k_rowpass_fwd_b, dim3(xcd_grid(batch_items(b, kStRow))), dim3(b->thr_row), b->lds_row, st, bt,
                        w);
     if ((rc = check_launch())) return rc;
-    hipLaunchKernelGGL(k_gather_b, dim3(xcd_grid(batch_items(b, kStGather))), dim3(b->gat_cb), gather_lds(b->gat_cb),
-                       st, bt, w);
+    hipLaunchKernelGGL(k_gather_b, dim3(xcd_grid(batch_items(b, kStGather))), dim3(kGatherThreads),
+                       gather_lds_bytes(b->gat_cb, b->gat_th), st, bt, w, b->gat_cb);
     if ((rc = check_launch())) return rc;
     hipLaunchKernelGGL(k_ring_fwd_b<4>, dim3(xcd_grid(batch_items(b, kStRing))), dim3(b->thr_ring), b->lds_ring, st,
                        bt, w);
@@ -437,7 +446,7 @@ extern "C" int pat_batch_adjoint(const pat_batch* b, const float* const* g_ptrs,
     hipLaunchKernelGGL(k_ring_adj_b<4>, dim3(xcd_grid(batch_items(b, kStRing))), dim3(b->thr_ring), b->lds_ring, st,
                        bt, w);
     if ((rc = check_launch())) return rc;
-    hipLaunchKernelGGL(k_spread_b, dim3(xcd_grid(batch_items(b, kStSpread))), dim3(b->spr_cb), spread_lds(b->spr_cb),
+    hipLaunchKernelGGL(k_spread_b, dim3(xcd_grid(batch_items(b, kStSpread))), dim3(b->spr_cb), spread_lds(b->spr_cb, 1),
                        st, bt, w);
     if ((rc = check_launch())) return rc;
     hipLaunchKernelGGL(k_rowpass_adj_b, dim3(xcd_grid(batch_items(b, kStRow))), dim3(b->thr_row), b->lds_row, st, bt,

@@ -90,10 +90,16 @@ __device__ __forceinline__ void butterfly(float2 (&v)[R], bool inv)
 
 // Twiddles w_n^e = e^{-2 pi i e / n} from a two-level table in LDS:
 // w^e = lo[e & 63] * hi[e >> 6] (lo: 64 entries, hi: ceil(n/64) entries).
+// With sh = 1 the table of length 2n serves length n (w_n^e = w_2n^{2e}).
 struct TwLds {
     const float2* lo;
     const float2* hi;
-    __device__ __forceinline__ float2 operator()(int e) const { return cmul(lo[e & 63], hi[e >> 6]); }
+    int sh;
+    __device__ __forceinline__ float2 operator()(int e) const
+    {
+        e <<= sh;
+        return cmul(lo[e & 63], hi[e >> 6]);
+    }
 };
 
 // Number of float2 slots tw_lds_build needs for length n.
@@ -110,7 +116,7 @@ __device__ __forceinline__ TwLds tw_lds_build(float2* dst, const FftDev& d, cons
         while (idx >= d.n) idx -= d.n;
         dst[e] = tw[idx];
     }
-    return TwLds{dst, dst + 64};
+    return TwLds{dst, dst + 64, 0};
 }
 
 // One Stockham stage of radix R on the sequence `xs` (length n), done by the

@@ -36,17 +36,22 @@ __device__ __forceinline__ int xcd_item(int w, int U)
     return x * Q + min(x, Rm) + q;
 }
 
-__device__ __forceinline__ float es_weight(float t)
-{
-    const float z = t * (2.0f / kEsWidth);
-    const float q = 1.0f - z * z;
-    return q >= 0.0f ? __expf((float)kEsBeta * (__fsqrt_rn(q) - 1.0f)) : 0.0f;
-}
-
+// The 8 taps of the ES kernel phi(t) = exp(beta (sqrt(1 - (2t/w)^2) - 1)) at
+// t = frac + 3 - d (d = 0..7, frac in [0, 1)): z = t / 4 lies in [-1, 1], so
+// 1 - z^2 only needs a clamp against rounding below 0; the hardware square
+// root and base-2 exponential (about 1 ulp each) are used directly, since the
+// argument of the exponential lies in [-beta log2(e), 0].  The same routine
+// serves the interpolation and the spread, which keeps them exact transposes.
 __device__ __forceinline__ void es_weights8(float frac, float (&w)[8])
 {
+    constexpr float kb = (float)(kEsBeta * 1.4426950408889634);  // beta log2(e)
+    const float z0 = frac * 0.25f;
 #pragma unroll
-    for (int d = 0; d < 8; ++d) w[d] = es_weight(frac + 3.0f - (float)d);
+    for (int d = 0; d < 8; ++d) {
+        const float z = z0 + 0.25f * (float)(3 - d);
+        const float q = fmaxf(fmaf(-z, z, 1.0f), 0.0f);
+        w[d] = __builtin_amdgcn_exp2f(fmaf(kb, __builtin_amdgcn_sqrtf(q), -kb));
+    }
 }
 
 __device__ __forceinline__ int fbits(float v) { return __float_as_int(v); }
@@ -65,6 +70,11 @@ __device__ float block_sum(float v, float* scratch)
     __syncthreads();
     return r;
 }
+
+// Row / sample classes of the endpoint-term sums; red_s[1024] holds
+// kSumClasses x (columns or detectors of a tile), so tiles have at most 32 of
+// either (col_np, dct_dp <= 16).
+constexpr int kSumClasses = 32;
 
 // Sum of v[0..n) in an order fixed by n alone (64 strided partial sums, then a
 // fixed shuffle tree): the same bits for every workgroup size.  Must be
@@ -108,13 +118,14 @@ __device__ __forceinline__ void colpass_fwd_tile(const PlanDev& d, const WsLayou
         float* slot = (float*)&sm[(jj >> 1) * Ng + pos];
         slot[jj & 1] = v;
     }
-    // endpoint term: h^2 times the masked sum of each column, rows in 8 classes
-    // mod 8 summed in order (independent of the workgroup size and the tiling)
-    for (int t = threadIdx.x; t < 8 * CT; t += blockDim.x) {
+    // endpoint term: h^2 times the masked sum of each column; rows in kSumClasses
+    // classes, each summed in order, then the classes in order (independent of
+    // the workgroup size and of the tiling)
+    for (int t = threadIdx.x; t < kSumClasses * CT; t += blockDim.x) {
         const int jj = t % CT, c = t / CT, j = j0 + jj;
         float sc = 0.f;
         if (j < N)
-            for (int i = c; i < N; i += 8) {
+            for (int i = c; i < N; i += kSumClasses) {
                 const int2 mr = d.mask_rows[i];
                 if (j >= mr.x && j < mr.y) sc += fb[(size_t)i * N + j];
             }
@@ -123,7 +134,7 @@ __device__ __forceinline__ void colpass_fwd_tile(const PlanDev& d, const WsLayou
     __syncthreads();
     if ((int)threadIdx.x < CT && j0 + (int)threadIdx.x < N) {
         float sc = 0.f;
-        for (int c = 0; c < 8; ++c) sc += red_s[c * CT + threadIdx.x];
+        for (int c = 0; c < kSumClasses; ++c) sc += red_s[c * CT + threadIdx.x];
         red[j0 + threadIdx.x] = sc * d.h2;
     }
     __syncthreads();
@@ -181,70 +192,70 @@ __device__ __forceinline__ void rowpass_fwd_tile(const PlanDev& d, const WsLayou
 //            dtheta = 2 pi / P, else Bluestein with two FFTs of length L),
 //            -> hT[d][n]  (real; the cosine transform over n follows)
 //   adjoint: the exact transpose, ending with the Hermitian fold and the
-//            conjugate half-pixel phase -> H (band order) for the spread.
+//            conjugate half-pixel phase -> H, stored in band order for the
+//            spread (scattered writes here, contiguous reads there).
 // ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // forward: ES interpolation of the half spectrum at the half-plane polar
-// points, in band order (points sorted by footprint base row r0, then by
-// base column bx).  A workgroup owns the points with r0 in [R0, R0 + TH) and
-// bx in [C0, C0 + CB); it keeps the 8 spectrum rows r0 .. r0 + 7 of columns
-// C0 .. C0 + CB + 6 in an LDS ring buffer (one coalesced row load per band)
-// and each thread interpolates one point from LDS.  Output Fb[slot] (band
-// order) times the half-pixel phase.
+// points.  Points are visited in band order (sorted by footprint base row r0,
+// then base column bx); a tile is TH bands x CB columns: the points with r0
+// in [R0, R0 + TH) and bx in [C0, C0 + CB).  The tile's whole window of the
+// spectrum (rows R0 .. R0 + TH + 6, columns C0 .. C0 + CB + 6, wrapping
+// around the periodic grid) is loaded into LDS once; then each band is
+// handled by kGatherThreads / TH threads, one point per thread at a time.
+// Output: the polar value times the half-pixel phase, stored in ring order.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void gather_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile, int TH,
-                                            float2* win /* [8][CB + 7] */)
+__device__ __forceinline__ void gather_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile, int CB, int TH,
+                                            float2* win)
 {
     const int Ng = d.Ng, NB = d.NB, Hy = d.Hy;
-    const int CB = blockDim.x, W = CB + 7;
+    const int W = CB + 7, R = TH + 7;
     const int ncb = (Ng + CB - 1) / CB;
     const int rbk = tile / ncb, cbk = tile - rbk * ncb;
     const int C0 = cbk * CB, R0 = rbk * TH;
-    const int rend = min(R0 + TH, NB);
     const int cend = min(C0 + CB, Ng);
+    const int nbands = min(TH, NB - R0);
     const float2* __restrict__ G = (const float2*)(wb + L.grid);
-    float2* Fb = (float2*)(wb + L.polar);
-    // rows R0 .. R0 + 6 of the window
-    for (int e = threadIdx.x; e < 7 * W; e += CB) {
+    float2* Fp = (float2*)(wb + L.polar);
+    int* seg_lo = (int*)(win + R * W);
+    int* seg_hi = seg_lo + TH;
+    for (int e = threadIdx.x; e < R * W; e += blockDim.x) {
         const int rr = e / W, cc = e - rr * W;
         const int r = R0 + rr;
-        const int c = (C0 + cc) % Ng;  // the window may wrap around the periodic grid
-        win[(r & 7) * W + cc] = r < Hy ? G[(size_t)r * Ng + c] : make_float2(0.f, 0.f);
+        const int c = (C0 + cc) % Ng;
+        win[e] = r < Hy ? G[(size_t)r * Ng + c] : make_float2(0.f, 0.f);
     }
-    for (int rb = R0; rb < rend; ++rb) {
-        {
-            const int r = rb + 7;  // <= NB - 1 + 7 = Hy - 1
-            for (int cc = threadIdx.x; cc < W; cc += CB) {
-                const int c = (C0 + cc) % Ng;
-                win[(r & 7) * W + cc] = G[(size_t)r * Ng + c];
-            }
-        }
-        __syncthreads();
-        const int* bp = d.band_ptr + (size_t)rb * (Ng + 1);
-        const int lo = bp[C0], hi = bp[cend];
-        for (int s = lo + threadIdx.x; s < hi; s += CB) {
-            const float4 gq = d.bpt_geo[s];
-            const int c0 = fbits(gq.x) - C0;
-            float wx[8], wy[8];
-            es_weights8(gq.z, wx);
-            es_weights8(gq.w, wy);
-            float2 acc = make_float2(0.f, 0.f);
+    if ((int)threadIdx.x < nbands) {
+        const int* bp = d.band_ptr + (size_t)(R0 + threadIdx.x) * (Ng + 1);
+        seg_lo[threadIdx.x] = bp[C0];
+        seg_hi[threadIdx.x] = bp[cend];
+    }
+    __syncthreads();
+    const int Q = kGatherThreads / TH;  // threads per band
+    const int b = threadIdx.x / Q, u = threadIdx.x - b * Q;
+    if (b >= nbands) return;            // no barrier follows
+    const int hi = seg_hi[b];
+    for (int s = seg_lo[b] + u; s < hi; s += Q) {
+        const float4 gq = d.bpt_geo[s];
+        const int c0 = fbits(gq.x) - C0;
+        float wx[8], wy[8];
+        es_weights8(gq.z, wx);
+        es_weights8(gq.w, wy);
+        float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
-            for (int dy = 0; dy < 8; ++dy) {
-                const float2* row = win + ((rb + dy) & 7) * W + c0;
-                float2 ra = make_float2(0.f, 0.f);
+        for (int dy = 0; dy < 8; ++dy) {
+            const float2* row = win + (b + dy) * W + c0;
+            float2 ra = make_float2(0.f, 0.f);
 #pragma unroll
-                for (int dx = 0; dx < 8; ++dx) {
-                    const float2 gv = row[dx];
-                    ra.x += wx[dx] * gv.x;
-                    ra.y += wx[dx] * gv.y;
-                }
-                acc.x += wy[dy] * ra.x;
-                acc.y += wy[dy] * ra.y;
+            for (int dx = 0; dx < 8; ++dx) {
+                const float2 gv = row[dx];
+                ra.x = fmaf(wx[dx], gv.x, ra.x);
+                ra.y = fmaf(wx[dx], gv.y, ra.y);
             }
-            Fb[s] = cmul(acc, d.bpt_phase[s]);
+            acc.x = fmaf(wy[dy], ra.x, acc.x);
+            acc.y = fmaf(wy[dy], ra.y, acc.y);
         }
-        __syncthreads();
+        Fp[d.ring_of[s]] = cmul(acc, d.bpt_phase[s]);
     }
 }
 
@@ -269,10 +280,13 @@ __device__ __forceinline__ float2 real_unpack(const float2* Z, int H, int k, flo
     return make_float2(0.5f * (sm.x + t.y), 0.5f * (sm.y - t.x));
 }
 
-// Layout of the ring kernels' dynamic LDS (float2 slots unless noted).
+// Layout of the ring kernels' dynamic LDS (float2 slots, ring_lds_slots):
+// sa (ring FFT; the half-length synthesis buffer sc shares it), sy
+// (synthesis), the [D][RT] float tile, and the twiddles of length Npsi(n)
+// (twN, which also serve length Npsi(n)/2), S (twA) and S/2 (twB).
 struct RingLds {
-    float2 *sa, *sy, *sc, *twPs, *twNs, *twAs, *twBs;
-    float* tile;  // [D][RT] floats
+    float2 *sa, *sc, *sy, *twN, *twA, *twB;
+    float* tile;
 };
 
 __device__ __forceinline__ RingLds ring_lds(float2* sm, const PlanDev& d, int RT)
@@ -280,16 +294,15 @@ __device__ __forceinline__ RingLds ring_lds(float2* sm, const PlanDev& d, int RT
     RingLds r;
     const int Pmax = d.npsi_max / 2;
     const int S = d.syn_len;
-    const int B2 = S > Pmax ? S : Pmax;
-    const int B3 = d.syn_half ? S / 2 : 0;
+    const int B1 = max(Pmax, d.syn_half ? S / 2 : 0);
+    const int B2 = max(S, Pmax);
     r.sa = sm;
-    r.sy = r.sa + Pmax;
-    r.sc = r.sy + B2;
-    r.tile = (float*)(r.sc + B3);
-    r.twPs = (float2*)(r.tile + ((d.D * RT + 1) & ~1));
-    r.twNs = r.twPs + tw_lds_slots(Pmax);
-    r.twAs = r.twNs + tw_lds_slots(d.npsi_max);
-    r.twBs = r.twAs + tw_lds_slots(S);
+    r.sc = sm;
+    r.sy = sm + B1;
+    r.tile = (float*)(r.sy + B2);
+    r.twN = (float2*)(r.tile + ((d.D * RT + 1) & ~1));
+    r.twA = r.twN + ring_tw_slots(d.npsi_max);
+    r.twB = r.twA + ring_tw_slots(S);
     return r;
 }
 
@@ -300,51 +313,65 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
     const float2* __restrict__ Fp = (const float2*)(wb + L.polar);
     float* hT = (float*)(wb + L.hdet);
     const int D = d.D, S = d.syn_len;
+    const int tid = threadIdx.x, bd = blockDim.x;
     const RingLds R = ring_lds(sm, d, RT);
     float* ot = R.tile;
     const int n0 = tile * RT;
     const int nr = min(RT, d.nlam - n0);
     // synthesis tables: fold with even P -> FFT of P/2 (twB) + twiddles of P (twA); else FFT of S (twA)
-    const TwLds twA = tw_lds_build(R.twAs, d.ffts[d.fft_syn], d.tw);
-    const TwLds twB = d.syn_half ? tw_lds_build(R.twBs, d.ffts[d.fft_synh], d.tw) : twA;
+    const TwLds twA = tw_lds_build(R.twA, d.ffts[d.fft_syn], d.tw);
+    const TwLds twB = d.syn_half ? tw_lds_build(R.twB, d.ffts[d.fft_synh], d.tw) : twA;
     for (int r = 0; r < nr; ++r) {
         const int n = n0 + r;
         const int off = d.ring_off[n], P = d.ring_off[n + 1] - off;
-        const TwLds twP = tw_lds_build(R.twPs, d.ffts[d.ring_fft[n]], d.tw);   // FFT of length P
-        const TwLds twN = tw_lds_build(R.twNs, d.ffts[d.ring_twn[n]], d.tw);   // w_{2P}^k
+        const int Kn = d.ring_K[n];
+        const float2* __restrict__ cf = d.coef + d.ring_joff[n];
+        // this thread's modes k = tid + j bd: coefficients fetched before the FFT
+        float2 cpre[kRingModesPerThread];
+#pragma unroll
+        for (int j = 0; j < kRingModesPerThread; ++j) {
+            const int k = tid + j * bd;
+            cpre[j] = k <= Kn ? cf[k] : make_float2(0.f, 0.f);
+        }
+        const TwLds twN = tw_lds_build(R.twN, d.ffts[d.ring_twn[n]], d.tw);  // w_{2P}^k
+        const TwLds twP{twN.lo, twN.hi, 1};                                   // w_P^k = w_{2P}^{2k}
         // q(m) = Re F + Im F (m < P), Re F - Im F (m >= P) is real; pack z(t) = q(2t) + i q(2t+1)
-        for (int t = threadIdx.x; t < P; t += blockDim.x) {
+        for (int t = tid; t < P; t += bd) {
             float qv[2];
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const int m = 2 * t + u;
                 const bool lo = m < P;
-                const float2 F = Fp[d.perm[off + (lo ? m : m - P)]];
+                const float2 F = Fp[off + (lo ? m : m - P)];
                 qv[u] = lo ? F.x + F.y : F.x - F.y;
             }
             R.sa[t] = make_float2(qv[0], qv[1]);
         }
         __syncthreads();
         fft_lds<RB>(R.sa, P, 1, d.ffts[d.ring_fft[n]], twP, false);
-        const int Kn = d.ring_K[n], jo = d.ring_joff[n];
-        // a_k = pre_k i^k Jw_k F_k, F_k = Q_k (k even) or i Q_k (k odd)
-        auto amode = [&](int k) {
-            float2 Q = real_unpack(R.sa, P, k, twN(k));
-            if (k & 1) Q = make_float2(-Q.y, Q.x);
-            return cmul(d.syn_pre[k], mul_ipow(cscale(Q, d.Jw[jo + k]), k));
-        };
-        if (d.fold_P) {
-            const int Pf = d.fold_P;
-            for (int sidx = threadIdx.x; sidx < Pf; sidx += blockDim.x) {
-                float2 acc = make_float2(0.f, 0.f);
-                for (int k = sidx; k <= Kn; k += Pf) acc = cadd(acc, amode(k));
-                R.sy[sidx] = acc;
+        // y = the a_k = coef_k Q_k (Q: the real length-2P transform of q) folded
+        // mod Pf (fold) or zero-padded to S (chirp-z), summed in order of k: pass
+        // 0 writes k < Pf, each further pass adds the next Pf modes
+        const int Pf = d.fold_P ? d.fold_P : S;
+        for (int q = tid; q < Pf; q += bd)
+            if (q > Kn) R.sy[q] = make_float2(0.f, 0.f);
+        for (int base = 0; base <= Kn; base += Pf) {
+            if (base) __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kRingModesPerThread; ++j) {
+                const int k = tid + j * bd;
+                if (k <= Kn && k >= base && k < base + Pf) {
+                    const float2 a = cmul(cpre[j], real_unpack(R.sa, P, k, twN(k)));
+                    R.sy[k - base] = base ? cadd(R.sy[k - base], a) : a;
+                }
             }
-            __syncthreads();
+        }
+        __syncthreads();
+        if (d.fold_P) {
             if (d.syn_half) {
                 // Re(IFFT_P(y)) as a half-length inverse FFT of the Hermitian part
                 const int H2 = Pf / 2;
-                for (int sidx = threadIdx.x; sidx < H2; sidx += blockDim.x) {
+                for (int sidx = tid; sidx < H2; sidx += bd) {
                     const int s1 = sidx, s2 = sidx + H2;
                     const float2 y1 = R.sy[s1], y1c = cconj(R.sy[s1 == 0 ? 0 : Pf - s1]);
                     const float2 y2 = R.sy[s2], y2c = cconj(R.sy[Pf - s2]);
@@ -355,29 +382,27 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
                 }
                 __syncthreads();
                 fft_lds<RB>(R.sc, H2, 1, d.ffts[d.fft_synh], twB, true);
-                for (int q = threadIdx.x; q < D; q += blockDim.x) {
+                for (int q = tid; q < D; q += bd) {
                     const float2 z = R.sc[q >> 1];
                     ot[q * RT + r] = (q & 1) ? z.y : z.x;
                 }
             } else {
                 fft_lds<RB>(R.sy, Pf, 1, d.ffts[d.fft_syn], twA, true);
-                for (int q = threadIdx.x; q < D; q += blockDim.x) ot[q * RT + r] = R.sy[q].x;
+                for (int q = tid; q < D; q += bd) ot[q * RT + r] = R.sy[q].x;
             }
         } else {
-            for (int q = threadIdx.x; q < S; q += blockDim.x) R.sy[q] = q <= Kn ? amode(q) : make_float2(0.f, 0.f);
-            __syncthreads();
             fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, false);
-            for (int q = threadIdx.x; q < S; q += blockDim.x) R.sy[q] = cmul(R.sy[q], d.czt_vhat[q]);
+            for (int q = tid; q < S; q += bd) R.sy[q] = cmul(R.sy[q], d.czt_vhat[q]);
             __syncthreads();
             fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, true);
-            for (int q = threadIdx.x; q < D; q += blockDim.x) {
+            for (int q = tid; q < D; q += bd) {
                 const float2 v = R.sy[q], w = d.czt_post[q];
                 ot[q * RT + r] = w.x * v.x - w.y * v.y;
             }
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < D * nr; e += blockDim.x) {
+    for (int e = tid; e < D * nr; e += bd) {
         const int q = e / nr, r = e - q * nr;
         hT[(size_t)q * d.nlam + n0 + r] = ot[q * RT + r];
     }
@@ -390,13 +415,18 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
     const float* hT = (const float*)(wb + L.hdet);
     float2* Hb = (float2*)(wb + L.polar);
     const int D = d.D, S = d.syn_len;
+    const int tid = threadIdx.x, bd = blockDim.x;
     const RingLds R = ring_lds(sm, d, RT);
     float* it = R.tile;
     const int n0 = tile * RT;
     const int nr = min(RT, d.nlam - n0);
-    const TwLds twA = tw_lds_build(R.twAs, d.ffts[d.fft_syn], d.tw);
-    const TwLds twB = d.syn_half ? tw_lds_build(R.twBs, d.ffts[d.fft_synh], d.tw) : twA;
-    for (int e = threadIdx.x; e < D * nr; e += blockDim.x) {
+    const bool half = d.fold_P && d.syn_half;
+    // the mode values Q~ go to qb, the Hermitian-part input of the ring's inverse FFT to eb
+    float2* const qb = half ? R.sy : R.sa;
+    float2* const eb = half ? R.sa : R.sy;
+    const TwLds twA = tw_lds_build(R.twA, d.ffts[d.fft_syn], d.tw);
+    const TwLds twB = d.syn_half ? tw_lds_build(R.twB, d.ffts[d.fft_synh], d.tw) : twA;
+    for (int e = tid; e < D * nr; e += bd) {
         const int q = e / nr, r = e - q * nr;
         it[q * RT + r] = hT[(size_t)q * d.nlam + n0 + r];
     }
@@ -404,35 +434,42 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
     for (int r = 0; r < nr; ++r) {
         const int n = n0 + r;
         const int off = d.ring_off[n], P = d.ring_off[n + 1] - off;
-        const int Kn = d.ring_K[n], jo = d.ring_joff[n];
-        const TwLds twP = tw_lds_build(R.twPs, d.ffts[d.ring_fft[n]], d.tw);
-        const TwLds twN = tw_lds_build(R.twNs, d.ffts[d.ring_twn[n]], d.tw);
+        const int Kn = d.ring_K[n];
+        const float2* __restrict__ cf = d.coef + d.ring_joff[n];
+        float2 cpre[kRingModesPerThread];
+#pragma unroll
+        for (int j = 0; j < kRingModesPerThread; ++j) {
+            const int k = tid + j * bd;
+            cpre[j] = k <= Kn ? cf[k] : make_float2(0.f, 0.f);
+        }
+        const TwLds twN = tw_lds_build(R.twN, d.ffts[d.ring_twn[n]], d.tw);
+        const TwLds twP{twN.lo, twN.hi, 1};
         // y~ = FFT of the real detector values, zero-padded to the synthesis length
-        if (d.fold_P && d.syn_half) {
+        if (half) {
             const int H2 = d.fold_P / 2;
-            for (int t = threadIdx.x; t < H2; t += blockDim.x) {
+            for (int t = tid; t < H2; t += bd) {
                 const int q0 = 2 * t, q1 = 2 * t + 1;
                 R.sc[t] = make_float2(q0 < D ? it[q0 * RT + r] : 0.f, q1 < D ? it[q1 * RT + r] : 0.f);
             }
             __syncthreads();
             fft_lds<RB>(R.sc, H2, 1, d.ffts[d.fft_synh], twB, false);
         } else if (d.fold_P) {
-            for (int sidx = threadIdx.x; sidx < S; sidx += blockDim.x)
+            for (int sidx = tid; sidx < S; sidx += bd)
                 R.sy[sidx] = make_float2(sidx < D ? it[sidx * RT + r] : 0.f, 0.f);
             __syncthreads();
             fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, false);
         } else {
-            for (int q = threadIdx.x; q < S; q += blockDim.x)
+            for (int q = tid; q < S; q += bd)
                 R.sy[q] = q < D ? cmulc(make_float2(it[q * RT + r], 0.f), d.czt_post[q]) : make_float2(0.f, 0.f);
             __syncthreads();
             fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, false);
-            for (int q = threadIdx.x; q < S; q += blockDim.x) R.sy[q] = cmulc(R.sy[q], d.czt_vhat[q]);
+            for (int q = tid; q < S; q += bd) R.sy[q] = cmulc(R.sy[q], d.czt_vhat[q]);
             __syncthreads();
             fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, true);
         }
         // y~ at synthesis index sidx (0 <= sidx < S)
         auto ytil = [&](int sidx) {
-            if (!(d.fold_P && d.syn_half)) return R.sy[sidx];
+            if (!half) return R.sy[sidx];
             const int Pf = d.fold_P, H2 = Pf / 2;
             if (sidx == H2) return make_float2(R.sc[0].x - R.sc[0].y, 0.f);
             const bool hi = sidx > H2;
@@ -440,39 +477,42 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
             const float2 v = real_unpack(R.sc, H2, s0, twA(s0));
             return hi ? cconj(v) : v;
         };
-        // Q~_k = F~_k (k even) or -i F~_k (k odd), F~_k = conj(pre_k i^k) Jw_k y~_{k mod P}
-        for (int k = threadIdx.x; k <= Kn; k += blockDim.x) {
-            int sidx = k;
-            if (d.fold_P) while (sidx >= d.fold_P) sidx -= d.fold_P;
-            const float2 F = cscale(mul_ipow(cmulc(ytil(sidx), d.syn_pre[k]), (4 - (k & 3)) & 3), d.Jw[jo + k]);
-            R.sa[k] = (k & 1) ? make_float2(F.y, -F.x) : F;
+        // Q~_k = conj(coef_k) y~_{k mod Pf}
+#pragma unroll
+        for (int j = 0; j < kRingModesPerThread; ++j) {
+            const int k = tid + j * bd;
+            if (k <= Kn) {
+                int sidx = k;
+                if (d.fold_P) while (sidx >= d.fold_P) sidx -= d.fold_P;
+                qb[k] = cmulc(ytil(sidx), cpre[j]);
+            }
         }
         __syncthreads();
-        // Re(IFFT_{2P}(Q~)) as a half-length inverse FFT: build E + i O in place of the
-        // upper part of sa (the Hermitian part of Q~ vanishes above K < P).
+        // Re(IFFT_{2P}(Q~)) as a half-length inverse FFT: E + i O from the
+        // Hermitian part of Q~ (which vanishes above K_n < P).
         // Q~_h[s] = Q~[s]/2 (0 < s <= K), Re Q~[0] (s = 0); Q~_h[s + P] = conj Q~[P - s]/2 (P - s <= K).
-        for (int sidx = threadIdx.x; sidx < P; sidx += blockDim.x) {
+        for (int sidx = tid; sidx < P; sidx += bd) {
             float2 a = make_float2(0.f, 0.f), c = a;
-            if (sidx == 0) a = make_float2(R.sa[0].x, 0.f);
+            if (sidx == 0) a = make_float2(qb[0].x, 0.f);
             else {
-                if (sidx <= Kn) a = cscale(R.sa[sidx], 0.5f);
-                if (P - sidx <= Kn) c = cscale(cconj(R.sa[P - sidx]), 0.5f);
+                if (sidx <= Kn) a = cscale(qb[sidx], 0.5f);
+                if (P - sidx <= Kn) c = cscale(cconj(qb[P - sidx]), 0.5f);
             }
             const float2 E = cadd(a, c);
             const float2 O = cmulc(csub(a, c), twN(sidx));
-            R.sy[sidx] = make_float2(E.x - O.y, E.y + O.x);
+            eb[sidx] = make_float2(E.x - O.y, E.y + O.x);
         }
         __syncthreads();
-        fft_lds<RB>(R.sy, P, 1, d.ffts[d.ring_fft[n]], twP, true);
+        fft_lds<RB>(eb, P, 1, d.ffts[d.ring_fft[n]], twP, true);
         // q~(m): m = 2t -> Re z_t, m = 2t + 1 -> Im z_t;  F~_h(l) = (q~(l) + q~(l+P)) + i (q~(l) - q~(l+P))
-        for (int l = threadIdx.x; l < P; l += blockDim.x) {
-            const float2 z1 = R.sy[l >> 1];
+        for (int l = tid; l < P; l += bd) {
+            const float2 z1 = eb[l >> 1];
             const float a = (l & 1) ? z1.y : z1.x;
             const int m = l + P;
-            const float2 z2 = R.sy[m >> 1];
+            const float2 z2 = eb[m >> 1];
             const float c = (m & 1) ? z2.y : z2.x;
             const float2 Fh = make_float2(a + c, a - c);
-            Hb[d.perm[off + l]] = cmulc(Fh, d.pt_phase[off + l]);
+            Hb[d.band_of[off + l]] = cmulc(Fh, d.pt_phase[off + l]);
         }
         __syncthreads();
     }
@@ -515,19 +555,20 @@ __device__ __forceinline__ void dct_tile(const PlanDev& d, const WsLayout& L, ch
         sm[p * twoM + q + 1] = make_float2(re, im);
     }
     if (adj) {
-        // data sum of each detector of the tile: samples in 8 classes mod 8, summed in order
+        // data sum of each detector of the tile: samples in kSumClasses classes,
+        // each summed in order, then the classes in order
         const int nd = 2 * np;
-        for (int t = threadIdx.x; t < 8 * nd; t += blockDim.x) {
-            const int dd = t % nd, c = t / nd, dg = 2 * p0 + dd;
+        for (int t = threadIdx.x; t < kSumClasses * nd; t += blockDim.x) {
+            const int c = t % kSumClasses, dd = t / kSumClasses, dg = 2 * p0 + dd;
             float sc = 0.f;
             if (dg < D)
-                for (int q = c; q < T; q += 8) sc += gin[(size_t)dg * T + q];
+                for (int q = c; q < T; q += kSumClasses) sc += gin[(size_t)dg * T + q];
             red_s[t] = sc;
         }
         __syncthreads();
         if ((int)threadIdx.x < nd && 2 * p0 + (int)threadIdx.x < D) {
             float sc = 0.f;
-            for (int c = 0; c < 8; ++c) sc += red_s[c * nd + threadIdx.x];
+            for (int c = 0; c < kSumClasses; ++c) sc += red_s[threadIdx.x * kSumClasses + c];
             red[2 * p0 + threadIdx.x] = sc;
         }
     }
@@ -583,110 +624,163 @@ __device__ __forceinline__ int band_slot(const BandMeta& m, int idx)
     return idx < m.nA ? m.aLo + idx : m.bLo + (idx - m.nA);
 }
 
-__device__ __forceinline__ void spread_stage(float* wxs, float* wys, float2* hs, int* bxs, int e, float4 gq, float2 h)
+// LDS of the spread (spread_lds_words): column-major so that lanes reading
+// neighbouring points hit distinct banks.
+template <int IB>
+struct SpreadLds {
+    float* wx;
+    float* wy;
+    int* bx;
+    float2* h;
+};
+
+template <int IB>
+__device__ __forceinline__ void spread_stage(const SpreadLds<IB>& S, int CAP, int e, float4 gq, int bx_rel,
+                                             const float2 (&h)[IB])
 {
     float w[8];
     es_weights8(gq.z, w);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) wxs[e * 8 + k] = w[k];
+    for (int k = 0; k < 8; ++k) S.wx[k * CAP + e] = w[k];
     es_weights8(gq.w, w);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) wys[e * 8 + k] = w[k];
-    hs[e] = h;
-    bxs[e] = fbits(gq.x);
+    for (int k = 0; k < 8; ++k) S.wy[k * CAP + e] = w[k];
+    S.bx[e] = bx_rel;
+#pragma unroll
+    for (int b = 0; b < IB; ++b) S.h[b * CAP + e] = h[b];
 }
 
-__device__ __forceinline__ void spread_visit(const float* wxs, const float* wys, const float2* hs, const int* bxs,
-                                             int s0, int s1, int c0, int mx, int Ng, float2 (&acc)[8])
+template <int IB>
+__device__ __forceinline__ void spread_visit(const SpreadLds<IB>& S, int CAP, int s0, int s1, int c0, int lane7,
+                                             float2 (&acc)[IB][8])
 {
     for (int s = s0; s < s1; ++s) {
         const int e = s - c0;
-        int dx = mx - bxs[e];
-        if (dx < 0) dx += Ng;
-        const float w = wxs[e * 8 + dx];
-        const float2 t = cscale(hs[e], w);
-        const float4 wa = *(const float4*)&wys[e * 8];
-        const float4 wb4 = *(const float4*)&wys[e * 8 + 4];
-        acc[0].x += wa.x * t.x; acc[0].y += wa.x * t.y;
-        acc[1].x += wa.y * t.x; acc[1].y += wa.y * t.y;
-        acc[2].x += wa.z * t.x; acc[2].y += wa.z * t.y;
-        acc[3].x += wa.w * t.x; acc[3].y += wa.w * t.y;
-        acc[4].x += wb4.x * t.x; acc[4].y += wb4.x * t.y;
-        acc[5].x += wb4.y * t.x; acc[5].y += wb4.y * t.y;
-        acc[6].x += wb4.z * t.x; acc[6].y += wb4.z * t.y;
-        acc[7].x += wb4.w * t.x; acc[7].y += wb4.w * t.y;
+        const int dx = lane7 - S.bx[e];
+        const float w = S.wx[dx * CAP + e];
+        float wy[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) wy[k] = S.wy[k * CAP + e];
+#pragma unroll
+        for (int b = 0; b < IB; ++b) {
+            const float2 t = cscale(S.h[b * CAP + e], w);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                acc[b][k].x = fmaf(wy[k], t.x, acc[b][k].x);
+                acc[b][k].y = fmaf(wy[k], t.y, acc[b][k].y);
+            }
+        }
     }
 }
 
-// CAP must be 2 * blockDim.x (two staged points per thread per chunk).
-__device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile, int TH, int CAP,
-                                            float* sf /* [CAP][19] */)
+// One tile of the spread for IB instances of one plan (wbs[b], b < nb, are the
+// instance workspaces; instances b >= nb are padding and neither read nor
+// written).  CAP = 2 * blockDim.x: two staged points per thread per chunk.
+template <int IB>
+__device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L, char* const (&wbs)[IB], int nb,
+                                            int tile, int TH, int CAP, float* sf)
 {
     const int Ng = d.Ng, NB = d.NB, Hy = d.Hy;
     const int CB = blockDim.x;
     const int ncb = (Ng + CB - 1) / CB;
     const int rb_ = tile / ncb, cb_ = tile - rb_ * ncb;
-    const float2* __restrict__ H = (const float2*)(wb + L.polar);
-    float2* Gt = (float2*)(wb + L.grid);
-    float* wxs = sf;                       // [CAP][8]
-    float* wys = sf + CAP * 8;             // [CAP][8]
-    float2* hs = (float2*)(sf + CAP * 16); // [CAP]
-    int* bxs = (int*)(sf + CAP * 18);      // [CAP]
+    const float2* __restrict__ H[IB];
+    float2* Gt[IB];
+#pragma unroll
+    for (int b = 0; b < IB; ++b) {
+        H[b] = (const float2*)(wbs[b] + L.polar);
+        Gt[b] = (float2*)(wbs[b] + L.grid);
+    }
+    SpreadLds<IB> S;
+    S.wx = sf;
+    S.wy = sf + 8 * CAP;
+    S.bx = (int*)(sf + 16 * CAP);
+    S.h = (float2*)(sf + 17 * CAP);  // CAP is even: 8-byte aligned
     const int C0 = cb_ * CB, R0 = rb_ * TH;
     const int mx = C0 + threadIdx.x;
+    const int lane7 = threadIdx.x + 7;
     const bool active = mx < Ng;
     const int rend = min(R0 + TH, Hy);
-    float2 acc[8];
+    float2 acc[IB][8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) acc[k] = make_float2(0.f, 0.f);
+    for (int b = 0; b < IB; ++b)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[b][k] = make_float2(0.f, 0.f);
     const int band_lo = max(0, R0 - 7), band_hi = min(NB - 1, rend - 1);
     const int e0 = threadIdx.x, e1 = threadIdx.x + CB;
-    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    // tile-relative footprint column of a staged point: the wrapped segment
+    // (columns Ng-7 .. Ng-1 seen from a tile at column 0) is shifted by -Ng
+    auto rel = [&](const BandMeta& m, int idx, float4 gq) {
+        return fbits(gq.x) - (idx < m.nA ? Ng : 0) - C0 + 7;
+    };
+    auto fetch = [&](const BandMeta& m, int idx, float4& gq, float2 (&h)[IB]) {
+        const int sl = band_slot(m, idx);
+        gq = d.bpt_geo[sl];
+#pragma unroll
+        for (int b = 0; b < IB; ++b) h[b] = b < nb ? H[b][sl] : make_float2(0.f, 0.f);
+    };
     BandMeta nm;
-    float4 ng0 = zero4, ng1 = zero4;
-    float2 nh0 = make_float2(0.f, 0.f), nh1 = nh0;
+    float4 ng0 = make_float4(0.f, 0.f, 0.f, 0.f), ng1 = ng0;
+    float2 nh0[IB], nh1[IB];
+#pragma unroll
+    for (int b = 0; b < IB; ++b) nh0[b] = nh1[b] = make_float2(0.f, 0.f);
     if (band_lo <= band_hi) {
         nm = band_meta(d, band_lo, C0, mx, active);
-        if (e0 < nm.ntot) { const int sl = band_slot(nm, e0); ng0 = d.bpt_geo[sl]; nh0 = H[sl]; }
-        if (e1 < nm.ntot) { const int sl = band_slot(nm, e1); ng1 = d.bpt_geo[sl]; nh1 = H[sl]; }
+        if (e0 < nm.ntot) fetch(nm, e0, ng0, nh0);
+        if (e1 < nm.ntot) fetch(nm, e1, ng1, nh1);
     }
     for (int rb = band_lo; rb <= band_hi; ++rb) {
         const BandMeta m = nm;
         const float4 g0 = ng0, g1 = ng1;
-        const float2 h0 = nh0, h1 = nh1;
+        float2 h0[IB], h1[IB];
+#pragma unroll
+        for (int b = 0; b < IB; ++b) { h0[b] = nh0[b]; h1[b] = nh1[b]; }
         if (rb < band_hi) {  // prefetch the next band
             nm = band_meta(d, rb + 1, C0, mx, active);
-            if (e0 < nm.ntot) { const int sl = band_slot(nm, e0); ng0 = d.bpt_geo[sl]; nh0 = H[sl]; }
-            if (e1 < nm.ntot) { const int sl = band_slot(nm, e1); ng1 = d.bpt_geo[sl]; nh1 = H[sl]; }
+            if (e0 < nm.ntot) fetch(nm, e0, ng0, nh0);
+            if (e1 < nm.ntot) fetch(nm, e1, ng1, nh1);
         }
         // chunk 0 from registers
-        if (e0 < m.ntot) spread_stage(wxs, wys, hs, bxs, e0, g0, h0);
-        if (e1 < m.ntot) spread_stage(wxs, wys, hs, bxs, e1, g1, h1);
+        if (e0 < m.ntot) spread_stage<IB>(S, CAP, e0, g0, rel(m, e0, g0), h0);
+        if (e1 < m.ntot) spread_stage<IB>(S, CAP, e1, g1, rel(m, e1, g1), h1);
         __syncthreads();
-        spread_visit(wxs, wys, hs, bxs, m.lo, min(m.hi, CAP), 0, mx, Ng, acc);
+        spread_visit<IB>(S, CAP, m.lo, min(m.hi, CAP), 0, lane7, acc);
         __syncthreads();
         // further chunks (dense bands only)
         for (int c0 = CAP; c0 < m.ntot; c0 += CAP) {
             const int cn = min(CAP, m.ntot - c0);
             for (int e = threadIdx.x; e < cn; e += CB) {
-                const int sl = band_slot(m, c0 + e);
-                spread_stage(wxs, wys, hs, bxs, e, d.bpt_geo[sl], H[sl]);
+                float4 gq;
+                float2 hh[IB];
+                fetch(m, c0 + e, gq, hh);
+                spread_stage<IB>(S, CAP, e, gq, rel(m, c0 + e, gq), hh);
             }
             __syncthreads();
-            spread_visit(wxs, wys, hs, bxs, max(m.lo, c0), min(m.hi, c0 + cn), c0, mx, Ng, acc);
+            spread_visit<IB>(S, CAP, max(m.lo, c0), min(m.hi, c0 + cn), c0, lane7, acc);
             __syncthreads();
         }
         // row rb is complete
-        if (active && rb >= R0 && rb < rend) Gt[(size_t)rb * Ng + mx] = acc[0];
+        if (active && rb >= R0 && rb < rend) {
 #pragma unroll
-        for (int k = 0; k < 7; ++k) acc[k] = acc[k + 1];
-        acc[7] = make_float2(0.f, 0.f);
+            for (int b = 0; b < IB; ++b)
+                if (b < nb) Gt[b][(size_t)rb * Ng + mx] = acc[b][0];
+        }
+#pragma unroll
+        for (int b = 0; b < IB; ++b) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) acc[b][k] = acc[b][k + 1];
+            acc[b][7] = make_float2(0.f, 0.f);
+        }
     }
     // rows after the last band receive no further contributions
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
         const int r = band_hi + 1 + k;
-        if (active && r >= R0 && r < rend) Gt[(size_t)r * Ng + mx] = acc[k];
+        if (active && r >= R0 && r < rend) {
+#pragma unroll
+            for (int b = 0; b < IB; ++b)
+                if (b < nb) Gt[b][(size_t)r * Ng + mx] = acc[b][k];
+        }
     }
 }
 
@@ -831,28 +925,34 @@ __global__ __launch_bounds__(1024) void k_rowpass_fwd_b(BatchDev bt, char* ws)
     rowpass_fwd_tile(d, I.L, ws + I.ws_off, tile, I.row_rpb, sm);
 }
 
-__global__ __launch_bounds__(256) void k_gather(PlanDev d, WsLayout L, InstPtrs wsp, int TH, int batch)
+__global__ __launch_bounds__(kGatherThreads) void k_gather(PlanDev d, WsLayout L, InstPtrs wsp, int CB, int TH,
+                                                           int batch)
 {
     extern __shared__ float2 win[];
-    const int per = ((d.Ng + (int)blockDim.x - 1) / (int)blockDim.x) * ((d.NB + TH - 1) / TH);
+    const int per = ((d.Ng + CB - 1) / CB) * ((d.NB + TH - 1) / TH);
     const int item = xcd_item(blockIdx.x, per * batch);
     if (item < 0) return;
     const int b = item / per;
-    gather_tile(d, L, wsp.ws + (size_t)b * wsp.stride, item - b * per, TH, win);
+    gather_tile(d, L, wsp.ws + (size_t)b * wsp.stride, item - b * per, CB, TH, win);
 }
 
-__global__ __launch_bounds__(256) void k_gather_b(BatchDev bt, char* ws)
+// CB is the batch-wide tile width (the instance table carries TH).
+__global__ __launch_bounds__(kGatherThreads) void k_gather_b(BatchDev bt, char* ws, int CB)
 {
     extern __shared__ float2 win[];
     int i, tile;
     if (!batch_item(bt, kStGather, i, tile)) return;
     const BatchInst& I = bt.inst[i];
     const PlanDev d = I.d;
-    gather_tile(d, I.L, ws + I.ws_off, tile, I.gat_th, win);
+    gather_tile(d, I.L, ws + I.ws_off, tile, CB, I.gat_th, win);
 }
 
+// Ring kernels: at most kRingMaxThreads threads (one wave for most rings).  The
+// adjoint is held to 128 VGPRs (four waves per SIMD) where it does not spill;
+// the forward needs more registers for its coefficient prefetch and runs best
+// unconstrained (three waves per SIMD, no spills).
 template <int RB>
-__global__ __launch_bounds__(1024) void k_ring_fwd(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
+__global__ __launch_bounds__(kRingMaxThreads) void k_ring_fwd(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
 {
     extern __shared__ float2 sm[];
     const int ntile = (d.nlam + RT - 1) / RT;
@@ -863,7 +963,7 @@ __global__ __launch_bounds__(1024) void k_ring_fwd(PlanDev d, WsLayout L, InstPt
 }
 
 template <int RB>
-__global__ __launch_bounds__(1024) void k_ring_fwd_b(BatchDev bt, char* ws)
+__global__ __launch_bounds__(kRingMaxThreads) void k_ring_fwd_b(BatchDev bt, char* ws)
 {
     extern __shared__ float2 sm[];
     int i, tile;
@@ -874,7 +974,7 @@ __global__ __launch_bounds__(1024) void k_ring_fwd_b(BatchDev bt, char* ws)
 }
 
 template <int RB>
-__global__ __launch_bounds__(1024) void k_ring_adj(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
+__global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_ring_adj(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
 {
     extern __shared__ float2 sm[];
     const int ntile = (d.nlam + RT - 1) / RT;
@@ -885,7 +985,7 @@ __global__ __launch_bounds__(1024) void k_ring_adj(PlanDev d, WsLayout L, InstPt
 }
 
 template <int RB>
-__global__ __launch_bounds__(1024) void k_ring_adj_b(BatchDev bt, char* ws)
+__global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_ring_adj_b(BatchDev bt, char* ws)
 {
     extern __shared__ float2 sm[];
     int i, tile;
@@ -925,14 +1025,21 @@ __global__ __launch_bounds__(1024) void k_dct_det_b(BatchDev bt, char* ws, float
              red_s, &mass_s);
 }
 
+// IB instances per workgroup: instances g*IB .. g*IB + IB - 1 of the batch.
+template <int IB>
 __global__ __launch_bounds__(256) void k_spread(PlanDev d, WsLayout L, InstPtrs wsp, int TH, int CAP, int batch)
 {
     extern __shared__ float sf[];
     const int per = ((d.Ng + (int)blockDim.x - 1) / (int)blockDim.x) * ((d.Hy + TH - 1) / TH);
-    const int item = xcd_item(blockIdx.x, per * batch);
+    const int ngroups = (batch + IB - 1) / IB;
+    const int item = xcd_item(blockIdx.x, per * ngroups);
     if (item < 0) return;
-    const int b = item / per;
-    spread_tile(d, L, wsp.ws + (size_t)b * wsp.stride, item - b * per, TH, CAP, sf);
+    const int g = item / per;
+    const int b0 = g * IB, nb = min(IB, batch - b0);
+    char* wbs[IB];
+#pragma unroll
+    for (int b = 0; b < IB; ++b) wbs[b] = wsp.ws + (size_t)(b0 + (b < nb ? b : 0)) * wsp.stride;
+    spread_tile<IB>(d, L, wbs, nb, item - g * per, TH, CAP, sf);
 }
 
 __global__ __launch_bounds__(256) void k_spread_b(BatchDev bt, char* ws)
@@ -942,7 +1049,8 @@ __global__ __launch_bounds__(256) void k_spread_b(BatchDev bt, char* ws)
     if (!batch_item(bt, kStSpread, i, tile)) return;
     const BatchInst& I = bt.inst[i];
     const PlanDev d = I.d;
-    spread_tile(d, I.L, ws + I.ws_off, tile, I.spr_th, 2 * (int)blockDim.x, sf);
+    char* const wbs[1] = {ws + I.ws_off};
+    spread_tile<1>(d, I.L, wbs, 1, tile, I.spr_th, 2 * (int)blockDim.x, sf);
 }
 
 __global__ __launch_bounds__(1024) void k_rowpass_adj(PlanDev d, WsLayout L, InstPtrs wsp, int RPB)

@@ -57,9 +57,10 @@ struct PlanDev {
     const int* ring_fft;    // [nlam]   FFT descriptor of Npsi(n)/2 (the ring's real transform)
     const int* ring_twn;    // [nlam]   descriptor whose twiddles are those of length Npsi(n)
     const int* ring_joff;   // [nlam]   offset of ring n in Jw
-    const float* Jw;        // ragged: J_k(lam_n R) W_n / Npsi(n), k = 0..K_n
+    const float2* coef;     // ragged [ring_joff[n] + k], k = 0..K_n: pre_k i^k J_k(lam_n R) W_n / Npsi(n) (i for odd k)
     // polar points, band order (sorted by (r0, bx)) for the deterministic spread
-    const int* perm;        // [npts]   ring-order index -> band-order slot
+    const int* ring_of;     // [npts]   band-order slot -> ring-order index
+    const int* band_of;     // [npts]   ring-order index -> band-order slot
     const float4* bpt_geo;  // [npts]   same fields as pt_geo, band order
     const float2* bpt_phase;// [npts]   pt_phase in band order
     const int* band_ptr;    // [NB][Ng + 1] CSR: first band-order slot with (r0, bx' >= bx)
@@ -68,7 +69,8 @@ struct PlanDev {
     int syn_len;            // P (fold) or the chirp-z FFT length L >= K + D (Bluestein)
     int syn_half;           // 1: fold with even P, synthesis as a real-output FFT of length P/2
     int fft_synh;           // descriptor of length P/2 (syn_half only)
-    const float2* syn_pre;  // [Kp]  c_k e^{i k theta_0} (fold) or c_k e^{i k theta_0} w^{k^2} (Bluestein); c_0 = 1, c_k = 2
+    // (the synthesis factor pre_k = c_k e^{i k theta_0} (fold) or c_k e^{i k theta_0} w^{k^2} (Bluestein),
+    //  c_0 = 1, c_k = 2, is part of coef)
     const float2* czt_post; // [D]   w^{d^2}, w = e^{i dtheta/2} (Bluestein only)
     const float2* czt_vhat; // [L]   FFT_L of the chirp filter w^{-m^2}, divided by L (Bluestein only)
     int npsi_max;           // largest per-ring angular grid
@@ -87,19 +89,54 @@ struct LaunchCfg {
     int row_rpb;     // rows per row-pass workgroup
     int ring_rt;     // rings per ring-kernel workgroup
     int dct_dp;      // detector pairs per cosine-transform workgroup
-    int gat_cb;      // interpolation: columns per workgroup (multiple of 64)
-    int gat_th;      // interpolation: bands per workgroup
+    int gat_cb;      // interpolation: columns per tile (multiple of 8, 8..512)
+    int gat_th;      // interpolation: bands per tile (power of two, 1..64)
     int spr_cb;      // spread: columns per workgroup (multiple of 64)
     int spr_th;      // spread: rows per workgroup
     int spr_cap;     // spread: points staged in LDS per chunk
 };
+
+// Interpolation tiles: kGatherThreads threads; window of (TH + 7) x (CB + 7)
+// spectrum values plus two ints per band.
+constexpr int kGatherThreads = 256;
+__host__ __device__ constexpr size_t gather_lds_bytes(int CB, int TH)
+{
+    return sizeof(float2) * (size_t)(TH + 7) * (CB + 7) + sizeof(int) * 2 * (size_t)TH;
+}
+// Spread tiles for CAP staged points and IB instances:
+//   wx [8][CAP], wy [8][CAP] (ES weights), bx [CAP] (footprint column relative
+//   to the tile: lane + 7 - bx is the tap), h [IB][CAP] (complex).
+__host__ __device__ constexpr size_t spread_lds_words(int CAP, int IB) { return (size_t)CAP * (17 + 2 * IB); }
+
+// Ring kernels: modes k = thread + j * threads (j < kRingModesPerThread) of a
+// ring are handled by one thread (coefficients prefetched into registers), so
+// a ring workgroup has at least (K + 1) / kRingModesPerThread threads.
+constexpr int kRingModesPerThread = 8;
+constexpr int kRingMaxThreads = 256;
+// Their LDS in float2 slots: ring buffer (aliased by the half-length
+// synthesis buffer), synthesis buffer, [D][RT] float tile, three twiddle tables.
+__host__ __device__ constexpr int ring_tw_slots(int n) { return 64 + (n + 63) / 64; }
+__host__ __device__ constexpr size_t ring_lds_slots(int npsi_max, int S, int syn_half, int tile_floats)
+{
+    return (size_t)((npsi_max / 2 > (syn_half ? S / 2 : 0)) ? npsi_max / 2 : S / 2) +
+           (size_t)(S > npsi_max / 2 ? S : npsi_max / 2) + (size_t)((tile_floats + 1) / 2) +
+           (size_t)ring_tw_slots(npsi_max) + 2 * (size_t)ring_tw_slots(S);
+}
+
+// Tile-shape limits of the interpolation and the spread.
+inline bool gather_shape_ok(int cb, int th)
+{
+    return cb >= 8 && cb <= 512 && cb % 8 == 0 && th >= 1 && th <= 64 && (th & (th - 1)) == 0 &&
+           gather_lds_bytes(cb, th) <= 64 * 1024;
+}
+inline bool spread_shape_ok(int cb, int th) { return cb >= 64 && cb <= 256 && cb % 64 == 0 && th >= 1 && th <= 4096; }
 
 // Per-instance workspace layout (byte offsets; all 256-byte aligned).
 struct WsLayout {
     size_t x1;       // [Hy][N]   float2   column-pass output / row-pass-adjoint output
     size_t grid;     // [Hy][Ng]  float2   spectrum / spread target
     size_t hdet;     // [D][nlam] float    ring output (synthesised at the detectors) / cosine-adjoint output
-    size_t polar;    // [npts]    float2   spread input (band order)
+    size_t polar;    // [npts]    float2   polar values: ring order (interpolation output), band order (spread input)
     size_t red;      // small FP32 partial sums (mass / data sum)
     int n_red;       // number of partial sums
     size_t bytes;    // total per instance
@@ -173,7 +210,7 @@ struct pat_batch {
     void* table = nullptr;             // device: BatchInst[count], then base
     size_t base_off = 0;
     size_t ws_bytes = 0;
-    int gat_cb = 64, gat_th = 16, spr_cb = 64, spr_th = 32;
+    int gat_cb = 64, gat_th = 8, spr_cb = 64, spr_th = 32;
     // per-stage workgroup size and dynamic LDS (maxima over the instances)
     unsigned thr_col = 0, thr_row = 0, thr_ring = 0, thr_dct = 0;
     size_t lds_col = 0, lds_row = 0, lds_ring = 0, lds_dct = 0;

@@ -261,10 +261,7 @@ static size_t twb_bytes(int n) { return sizeof(float2) * (size_t)tw_lds_slots(n)
 // [D][RT] detector tile and four twiddle tables.
 static size_t ring_lds_bytes(const PlanDev& d, int RT)
 {
-    const size_t Pmax = d.npsi_max / 2, S = d.syn_len;
-    const size_t B2 = std::max(S, Pmax), B3 = d.syn_half ? S / 2 : 0;
-    return sizeof(float2) * (Pmax + B2 + B3) + (((size_t)d.D * RT + 1) & ~(size_t)1) * 4 + twb_bytes((int)Pmax) +
-           twb_bytes(d.npsi_max) + twb_bytes((int)S) + twb_bytes((int)S);
+    return sizeof(float2) * ring_lds_slots(d.npsi_max, d.syn_len, d.syn_half, d.D * RT);
 }
 
 constexpr size_t kLdsMax = 160 * 1024;  // LDS a gfx950 workgroup can hold
@@ -275,12 +272,12 @@ constexpr size_t kLdsMax = 160 * 1024;  // LDS a gfx950 workgroup can hold
 int apply_launch(pat_plan* p, const LaunchCfg& c)
 {
     const PlanDev& d = p->dev;
+    // column and detector tiles of at most 32 columns / detectors (the endpoint-term sums)
     auto fft_ok = [&](int v, size_t each, const FftDev& f, size_t fixed) {
-        return v >= 1 && v <= 64 && v * each + fixed <= kLdsMax && fft_threads(v, f) <= 1024;
+        return v >= 1 && v <= 16 && v * each + fixed <= kLdsMax && fft_threads(v, f) <= 1024;
     };
-    auto cb_ok = [](int cb) { return cb >= 64 && cb <= 256 && cb % 64 == 0; };
-    if (c.ring_rt < 1 || c.ring_rt > 64 || c.gat_th < 1 || c.gat_th > 4096 || c.spr_th < 1 || c.spr_th > 4096 ||
-        !cb_ok(c.gat_cb) || !cb_ok(c.spr_cb))
+    if (c.col_np < 1 || c.col_np > 16 || c.row_rpb < 1 || c.row_rpb > 16 || c.dct_dp < 1 || c.dct_dp > 16 ||
+        c.ring_rt < 1 || c.ring_rt > 64 || !gather_shape_ok(c.gat_cb, c.gat_th) || !spread_shape_ok(c.spr_cb, c.spr_th))
         return PAT_ERR_ARG;
     if (!fft_ok(c.col_np, sizeof(float2) * d.Ng, p->h_fft_grid, twb_bytes(d.Ng)) ||
         !fft_ok(c.row_rpb, sizeof(float2) * d.Ng, p->h_fft_grid, twb_bytes(d.Ng)) ||
@@ -325,17 +322,25 @@ int choose_launch(pat_plan* p, const std::vector<FftDev>& fd, int max_batch,
     c.ring_rt = 1;
     // wide tiles amortise the per-band work; narrow ones keep small batches parallel
     const long gwide = (long)((d.Ng + 255) / 256) * ((d.NB + 31) / 32) * max_batch;
-    c.gat_cb = gwide >= 512 ? 256 : 64;
-    c.gat_th = gwide >= 512 ? 32 : 16;
-    const long swide = (long)((d.Ng + 255) / 256) * ((d.Hy + 15) / 16) * max_batch;
-    c.spr_cb = swide >= 1024 ? 256 : 64;
-    c.spr_th = swide >= 1024 ? 16 : 32;
+    c.gat_cb = gwide >= 512 ? 128 : 64;
+    c.gat_th = gwide >= 512 ? 16 : 8;
+    // spread: wide tiles for large batches; rows per tile as many as keep about
+    // 512 workgroups (a tile sweeps th + 7 bands for th output rows)
+    const int ib = max_batch >= 4 ? 4 : (max_batch >= 2 ? 2 : 1);
+    const long groups = (max_batch + ib - 1) / ib;
+    c.spr_cb = (d.Ng >= 512 && groups >= 8) ? 256 : 64;
+    c.spr_th = 1;
+    for (int th = 32; th >= 1; th /= 2)
+        if ((long)((d.Ng + c.spr_cb - 1) / c.spr_cb) * ((d.Hy + th - 1) / th) * groups >= 512) {
+            c.spr_th = th;
+            break;
+        }
     if (!c.col_np || !c.row_rpb || !c.dct_dp) return PAT_ERR_UNSUPPORTED;
     // ring kernels: as few threads per ring as the FFT stages allow (one wave when
     // possible), so that many rings are resident per CU to hide their latency
     p->thr_ring = 0;
-    for (int thr : {64, 128, 256, 512, 1024}) {
-        bool ok = true;
+    for (int thr = 64; thr <= kRingMaxThreads; thr *= 2) {
+        bool ok = thr * kRingModesPerThread >= d.K + 1;  // every mode's coefficient prefetched
         for (const FftDev* f : ring_descs) ok = ok && fft_min_tps(*f, 4) <= thr;
         if (ok) { p->thr_ring = thr; p->ring_mb = 4; break; }
     }
@@ -452,8 +457,8 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     d.npts = npts;
     p->n_psi_max = npsi_max;
 
-    // radial weights J_k(lam_n R) W_n / Npsi(n)
-    std::vector<float> Jw(joff);
+    // radial weights J_k(lam_n R) W_n / Npsi(n) (FP64; combined with the synthesis factors below)
+    std::vector<double> Jw(joff);
     {
         std::vector<double> jt(K + 1);
         for (int n = 1; n <= nlam; ++n) {
@@ -461,7 +466,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
             double W = lam * dv.dlam / (2.0 * PI);
             bessel_jn_table(ringK[n - 1], lam * R, jt.data());
             for (int k = 0; k <= ringK[n - 1]; ++k)
-                Jw[ringJoff[n - 1] + k] = (float)(jt[k] * W / ringN[n - 1]);
+                Jw[ringJoff[n - 1] + k] = jt[k] * W / ringN[n - 1];
         }
     }
 
@@ -499,10 +504,16 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         return r0s[a] != r0s[b] ? r0s[a] < r0s[b] : bxs[a] < bxs[b];
     });
-    std::vector<int> perm(npts);
+    std::vector<int> ring_of(npts);  // band-order slot -> ring-order index
+    std::vector<int> band_of(npts);  // ring-order index -> band-order slot
     std::vector<float4> bgeo(npts);
     std::vector<float2> bphase(npts);
-    for (int s = 0; s < npts; ++s) { perm[order[s]] = s; bgeo[s] = geo[order[s]]; bphase[s] = phase[order[s]]; }
+    for (int s = 0; s < npts; ++s) {
+        ring_of[s] = order[s];
+        band_of[order[s]] = s;
+        bgeo[s] = geo[order[s]];
+        bphase[s] = phase[order[s]];
+    }
     const int NB = d.NB;
     std::vector<int> bptr((size_t)NB * (Ng + 1));
     {
@@ -526,13 +537,26 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
         double a = std::fmod(0.5 * dth * (double)m * (double)m, 2.0 * PI);
         return cd(std::cos(a), std::sin(a));
     };
-    std::vector<float2> pre(K + 1), post, vhat;
+    std::vector<cd> pre(K + 1);
+    std::vector<float2> post, vhat;
     for (int k = 0; k <= K; ++k) {
         double a = std::fmod(k * th0, 2.0 * PI);
         cd v = (k == 0 ? 1.0 : 2.0) * cd(std::cos(a), std::sin(a));
         if (!dv.P) v *= wpow(k);
-        pre[k] = make_float2((float)v.real(), (float)v.imag());
+        pre[k] = v;
     }
+    // Per ring n and mode k <= K_n, one coefficient
+    //   coef = pre_k i^k J_k(lam_n R) W_n / Npsi(n) * (i for odd k),
+    // the last factor because the ring's angular coefficient is i Q_k for odd k
+    // when the real transform Q of the conjugate-antipodal ring is used; the
+    // product i^k (i for odd k) is the real sign (-1)^ceil(k/2).
+    std::vector<float2> coef(joff);
+    for (int n = 0; n < nlam; ++n)
+        for (int k = 0; k <= ringK[n]; ++k) {
+            const double sg = (((k + 1) / 2) & 1) ? -1.0 : 1.0;
+            const cd v = pre[k] * (sg * Jw[ringJoff[n] + k]);
+            coef[ringJoff[n] + k] = make_float2((float)v.real(), (float)v.imag());
+        }
     if (!dv.P) {
         const int L = dv.L;
         post.resize(D);
@@ -563,9 +587,9 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     size_t o_geo = tb.add(geo), o_phase = tb.add(phase);
     size_t o_roff = tb.add(ringOff), o_rk = tb.add(ringK), o_rfft = tb.add(ringFft), o_rj = tb.add(ringJoff);
     size_t o_rtwn = tb.add(ringTwn);
-    size_t o_jw = tb.add(Jw);
-    size_t o_perm = tb.add(perm), o_bgeo = tb.add(bgeo), o_bph = tb.add(bphase), o_bptr = tb.add(bptr);
-    size_t o_pre = tb.add(pre), o_post = tb.add(post), o_vhat = tb.add(vhat);
+    size_t o_coef = tb.add(coef);
+    size_t o_ringof = tb.add(ring_of), o_bandof = tb.add(band_of), o_bgeo = tb.add(bgeo), o_bph = tb.add(bphase), o_bptr = tb.add(bptr);
+    size_t o_post = tb.add(post), o_vhat = tb.add(vhat);
     size_t o_ffts = tb.add(ffts.descs), o_tw = tb.add(ffts.tw);
     // store offsets in the pointer fields; relocated after the upload
     auto off = [](size_t o) { return (const void*)(uintptr_t)o; };
@@ -578,12 +602,12 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     d.ring_fft = (const int*)off(o_rfft);
     d.ring_twn = (const int*)off(o_rtwn);
     d.ring_joff = (const int*)off(o_rj);
-    d.Jw = (const float*)off(o_jw);
-    d.perm = (const int*)off(o_perm);
+    d.coef = (const float2*)off(o_coef);
+    d.ring_of = (const int*)off(o_ringof);
+    d.band_of = (const int*)off(o_bandof);
     d.bpt_geo = (const float4*)off(o_bgeo);
     d.bpt_phase = (const float2*)off(o_bph);
     d.band_ptr = (const int*)off(o_bptr);
-    d.syn_pre = (const float2*)off(o_pre);
     d.czt_post = (const float2*)off(o_post);
     d.czt_vhat = (const float2*)off(o_vhat);
     d.ffts = (const FftDev*)off(o_ffts);
@@ -618,8 +642,8 @@ extern "C" int pat_plan_create(const pat_plan_desc* desc, pat_plan** out)
     PlanDev& d = p->dev;
     auto rel = [&](auto& ptr) { ptr = (std::remove_reference_t<decltype(ptr)>)(base + (uintptr_t)ptr); };
     rel(d.deap); rel(d.mask_rows); rel(d.pt_geo); rel(d.pt_phase); rel(d.ring_off); rel(d.ring_K);
-    rel(d.ring_fft); rel(d.ring_twn); rel(d.ring_joff); rel(d.Jw); rel(d.perm); rel(d.bpt_geo); rel(d.bpt_phase);
-    rel(d.band_ptr); rel(d.syn_pre); rel(d.czt_post); rel(d.czt_vhat); rel(d.ffts); rel(d.tw);
+    rel(d.ring_fft); rel(d.ring_twn); rel(d.ring_joff); rel(d.coef); rel(d.ring_of); rel(d.band_of); rel(d.bpt_geo); rel(d.bpt_phase);
+    rel(d.band_ptr); rel(d.czt_post); rel(d.czt_vhat); rel(d.ffts); rel(d.tw);
     p->desc = *desc;
     p->max_batch = desc->max_batch;
     p->n_psi_uniform = dv.n_psi;

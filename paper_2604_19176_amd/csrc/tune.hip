@@ -23,8 +23,8 @@ const int kColNp[] = {1, 2, 4, 8, 16};
 const int kRowRpb[] = {1, 2, 4, 8, 16};
 const int kRingRt[] = {1, 2, 4};
 const int kDctDp[] = {1, 2, 4, 8};
-const int kGather[][2] = {{64, 8}, {64, 16}, {64, 32}, {128, 16}, {128, 32}, {256, 16}, {256, 32}, {256, 64}};
-const int kSpread[][2] = {{64, 16}, {64, 32}, {128, 16}, {128, 32}, {192, 16}, {256, 8}, {256, 16}, {256, 32}};
+const int kGather[][2] = {{32, 8}, {64, 4}, {64, 8}, {64, 16}, {128, 8}, {128, 16}, {64, 32}, {256, 16}};
+const int kSpread[][2] = {{64, 1}, {64, 2}, {64, 4}, {64, 8}, {128, 8}, {256, 4}, {256, 8}, {256, 16}};
 
 enum { kSCol, kSRow, kSRing, kSDct, kSGather, kSSpread, kNS };
 

@@ -48,8 +48,8 @@ def _inputs(torch, geom, seed, batch=None):
 SHAPES = [
     dict(col_np=1, row_rpb=1, ring_rt=1, dct_dp=1, gat_cb=64, gat_th=8, spr_cb=64, spr_th=16),
     dict(col_np=2, row_rpb=16, ring_rt=2, dct_dp=8, gat_cb=128, gat_th=32, spr_cb=192, spr_th=16),
-    dict(col_np=16, row_rpb=4, ring_rt=4, dct_dp=2, gat_cb=256, gat_th=64, spr_cb=256, spr_th=8),
-    dict(col_np=4, row_rpb=2, ring_rt=3, dct_dp=3, gat_cb=192, gat_th=5, spr_cb=128, spr_th=37),
+    dict(col_np=16, row_rpb=4, ring_rt=4, dct_dp=2, gat_cb=256, gat_th=16, spr_cb=256, spr_th=8),
+    dict(col_np=4, row_rpb=2, ring_rt=3, dct_dp=3, gat_cb=24, gat_th=1, spr_cb=128, spr_th=37),
 ]
 
 
@@ -87,13 +87,20 @@ def test_launch_shapes_against_oracle_and_rejections(torch_dev):
     assert _rel(g, oracle.forward(geom, f.cpu().double().numpy())) <= 1e-5
     assert _rel(a, oracle.adjoint(geom, d.cpu().double().numpy())) <= 1e-5
     before = plan.launch
-    for bad, status in [(dict(gat_cb=100), -1), (dict(spr_cb=320), -1), (dict(gat_th=0), -1),
-                        (dict(ring_rt=0), -1), (dict(col_np=64), -2), (dict(dct_dp=64), -2)]:
+    for bad in [dict(gat_cb=100), dict(gat_th=12), dict(gat_cb=512, gat_th=64), dict(spr_cb=320), dict(gat_th=0),
+                dict(ring_rt=0), dict(col_np=17), dict(dct_dp=0), dict(row_rpb=17)]:
         with pytest.raises(pat.PatError) as ei:
             plan.set_launch(**bad)
-        assert ei.value.status == status
+        assert ei.value.status == -1
         assert plan.launch == before
     plan.close()
+    plan2 = pat.PatPlan(config_geometry(2))   # cosine transform of length 2M = 2048
+    before = plan2.launch
+    with pytest.raises(pat.PatError) as ei:
+        plan2.set_launch(dct_dp=16)               # 16 x 2048 complex values: more LDS than a workgroup has
+    assert ei.value.status == -2
+    assert plan2.launch == before
+    plan2.close()
 
 
 def _mixed(count):
@@ -130,7 +137,7 @@ def test_batch_equals_per_instance_bitwise(torch_dev):
         assert torch.equal(gb[i], p.forward(fs[i])), i
         assert torch.equal(ab[i], p.adjoint(ds[i])), i
     # other batch-wide interpolation / spread shapes: still bitwise the same
-    for shp in [dict(gat_cb=64, gat_th=8, spr_cb=64, spr_th=16), dict(gat_cb=192, gat_th=40, spr_cb=128, spr_th=7)]:
+    for shp in [dict(gat_cb=64, gat_th=8, spr_cb=64, spr_th=16), dict(gat_cb=192, gat_th=32, spr_cb=128, spr_th=7)]:
         batch.set_launch(**shp)
         assert batch.launch == shp
         g2 = batch.forward(fs)
