@@ -476,7 +476,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--workload", default="default", choices=["default", "mixed", "tv3", "large", "paper"])
-    ap.add_argument("--tune", action="store_true", help="autotune the launch shapes before timing")
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="time the default launch shapes instead of autotuning them first")
     ap.add_argument("--tune-cache", default=None, help="JSON cache file of the autotuner")
     ap.add_argument("--tv-steps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -190,7 +190,7 @@ __device__ __forceinline__ void rowpass_fwd_tile(const PlanDev& d, const WsLayou
 //            synthesis over detectors h(d) = Re sum_k a_k e^{i k d dtheta}
 //            (one inverse FFT of length P after folding k mod P when
 //            dtheta = 2 pi / P, else Bluestein with two FFTs of length L),
-//            -> hT[d][n]  (real; the cosine transform over n follows)
+//            -> hT[n][d]  (real; the cosine transform over n follows)
 //   adjoint: the exact transpose, ending with the Hermitian fold and the
 //            conjugate half-pixel phase -> H, stored in band order for the
 //            spread (scattered writes here, contiguous reads there).
@@ -282,14 +282,13 @@ __device__ __forceinline__ float2 real_unpack(const float2* Z, int H, int k, flo
 
 // Layout of the ring kernels' dynamic LDS (float2 slots, ring_lds_slots):
 // sa (ring FFT; the half-length synthesis buffer sc shares it), sy
-// (synthesis), the [D][RT] float tile, and the twiddles of length Npsi(n)
-// (twN, which also serve length Npsi(n)/2), S (twA) and S/2 (twB).
+// (synthesis), and the twiddles of length Npsi(n) (twN, which also serve
+// length Npsi(n)/2), S (twA) and S/2 (twB).
 struct RingLds {
     float2 *sa, *sc, *sy, *twN, *twA, *twB;
-    float* tile;
 };
 
-__device__ __forceinline__ RingLds ring_lds(float2* sm, const PlanDev& d, int RT)
+__device__ __forceinline__ RingLds ring_lds(float2* sm, const PlanDev& d)
 {
     RingLds r;
     const int Pmax = d.npsi_max / 2;
@@ -299,8 +298,7 @@ __device__ __forceinline__ RingLds ring_lds(float2* sm, const PlanDev& d, int RT
     r.sa = sm;
     r.sc = sm;
     r.sy = sm + B1;
-    r.tile = (float*)(r.sy + B2);
-    r.twN = (float2*)(r.tile + ((d.D * RT + 1) & ~1));
+    r.twN = r.sy + B2;
     r.twA = r.twN + ring_tw_slots(d.npsi_max);
     r.twB = r.twA + ring_tw_slots(S);
     return r;
@@ -311,11 +309,10 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
                                               float2* sm)
 {
     const float2* __restrict__ Fp = (const float2*)(wb + L.polar);
-    float* hT = (float*)(wb + L.hdet);
+    float* hT = (float*)(wb + L.hdet);  // [nlam][D]
     const int D = d.D, S = d.syn_len;
     const int tid = threadIdx.x, bd = blockDim.x;
-    const RingLds R = ring_lds(sm, d, RT);
-    float* ot = R.tile;
+    const RingLds R = ring_lds(sm, d);
     const int n0 = tile * RT;
     const int nr = min(RT, d.nlam - n0);
     // synthesis tables: fold with even P -> FFT of P/2 (twB) + twiddles of P (twA); else FFT of S (twA)
@@ -326,6 +323,7 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
         const int off = d.ring_off[n], P = d.ring_off[n + 1] - off;
         const int Kn = d.ring_K[n];
         const float2* __restrict__ cf = d.coef + d.ring_joff[n];
+        float* hn = hT + (size_t)n * D;
         // this thread's modes k = tid + j bd: coefficients fetched before the FFT
         float2 cpre[kRingModesPerThread];
 #pragma unroll
@@ -384,11 +382,11 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
                 fft_lds<RB>(R.sc, H2, 1, d.ffts[d.fft_synh], twB, true);
                 for (int q = tid; q < D; q += bd) {
                     const float2 z = R.sc[q >> 1];
-                    ot[q * RT + r] = (q & 1) ? z.y : z.x;
+                    hn[q] = (q & 1) ? z.y : z.x;
                 }
             } else {
                 fft_lds<RB>(R.sy, Pf, 1, d.ffts[d.fft_syn], twA, true);
-                for (int q = tid; q < D; q += bd) ot[q * RT + r] = R.sy[q].x;
+                for (int q = tid; q < D; q += bd) hn[q] = R.sy[q].x;
             }
         } else {
             fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, false);
@@ -397,14 +395,10 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
             fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, true);
             for (int q = tid; q < D; q += bd) {
                 const float2 v = R.sy[q], w = d.czt_post[q];
-                ot[q * RT + r] = w.x * v.x - w.y * v.y;
+                hn[q] = w.x * v.x - w.y * v.y;
             }
         }
         __syncthreads();
-    }
-    for (int e = tid; e < D * nr; e += bd) {
-        const int q = e / nr, r = e - q * nr;
-        hT[(size_t)q * d.nlam + n0 + r] = ot[q * RT + r];
     }
 }
 
@@ -412,12 +406,11 @@ template <int RB>
 __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile, int RT,
                                               float2* sm)
 {
-    const float* hT = (const float*)(wb + L.hdet);
+    const float* hT = (const float*)(wb + L.hdet);  // [nlam][D]
     float2* Hb = (float2*)(wb + L.polar);
     const int D = d.D, S = d.syn_len;
     const int tid = threadIdx.x, bd = blockDim.x;
-    const RingLds R = ring_lds(sm, d, RT);
-    float* it = R.tile;
+    const RingLds R = ring_lds(sm, d);
     const int n0 = tile * RT;
     const int nr = min(RT, d.nlam - n0);
     const bool half = d.fold_P && d.syn_half;
@@ -426,16 +419,12 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
     float2* const eb = half ? R.sa : R.sy;
     const TwLds twA = tw_lds_build(R.twA, d.ffts[d.fft_syn], d.tw);
     const TwLds twB = d.syn_half ? tw_lds_build(R.twB, d.ffts[d.fft_synh], d.tw) : twA;
-    for (int e = tid; e < D * nr; e += bd) {
-        const int q = e / nr, r = e - q * nr;
-        it[q * RT + r] = hT[(size_t)q * d.nlam + n0 + r];
-    }
-    __syncthreads();
     for (int r = 0; r < nr; ++r) {
         const int n = n0 + r;
         const int off = d.ring_off[n], P = d.ring_off[n + 1] - off;
         const int Kn = d.ring_K[n];
         const float2* __restrict__ cf = d.coef + d.ring_joff[n];
+        const float* hn = hT + (size_t)n * D;
         float2 cpre[kRingModesPerThread];
 #pragma unroll
         for (int j = 0; j < kRingModesPerThread; ++j) {
@@ -449,18 +438,18 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
             const int H2 = d.fold_P / 2;
             for (int t = tid; t < H2; t += bd) {
                 const int q0 = 2 * t, q1 = 2 * t + 1;
-                R.sc[t] = make_float2(q0 < D ? it[q0 * RT + r] : 0.f, q1 < D ? it[q1 * RT + r] : 0.f);
+                R.sc[t] = make_float2(q0 < D ? hn[q0] : 0.f, q1 < D ? hn[q1] : 0.f);
             }
             __syncthreads();
             fft_lds<RB>(R.sc, H2, 1, d.ffts[d.fft_synh], twB, false);
         } else if (d.fold_P) {
             for (int sidx = tid; sidx < S; sidx += bd)
-                R.sy[sidx] = make_float2(sidx < D ? it[sidx * RT + r] : 0.f, 0.f);
+                R.sy[sidx] = make_float2(sidx < D ? hn[sidx] : 0.f, 0.f);
             __syncthreads();
             fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, false);
         } else {
             for (int q = tid; q < S; q += bd)
-                R.sy[q] = q < D ? cmulc(make_float2(it[q * RT + r], 0.f), d.czt_post[q]) : make_float2(0.f, 0.f);
+                R.sy[q] = q < D ? cmulc(make_float2(hn[q], 0.f), d.czt_post[q]) : make_float2(0.f, 0.f);
             __syncthreads();
             fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, false);
             for (int q = tid; q < S; q += bd) R.sy[q] = cmulc(R.sy[q], d.czt_vhat[q]);
@@ -523,8 +512,8 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
 // as the real and imaginary parts of one complex sequence (the transform is
 // real):  out(q) = sum_p in(p) cos(pi p q / M) = (X[q] + X[2M - q]) / 2 with
 // X = FFT_2M of the zero-padded input (p, q >= 1).
-//   forward: hT [D][nlam] -> g [D][T] (+ kappa * mass)
-//   adjoint: g [D][T] -> hT [D][nlam] (+ per-workgroup partial sums of g)
+//   forward: hT [nlam][D] -> g [D][T] (+ kappa * mass)
+//   adjoint: g [D][T] -> hT [nlam][D] (+ per-detector sums of g)
 // ---------------------------------------------------------------------------
 // gout / gin point at this instance's [D][T] data.
 __device__ __forceinline__ void dct_tile(const PlanDev& d, const WsLayout& L, char* wb, float* __restrict__ gout,
@@ -538,8 +527,6 @@ __device__ __forceinline__ void dct_tile(const PlanDev& d, const WsLayout& L, ch
     const int np = min(DP, (D + 1) / 2 - p0);
     const int nin = adj ? T : NL;
     const int nout = adj ? NL : T;
-    const float* src = adj ? gin : hT;
-    const int sld = adj ? T : NL;
     if (!adj && threadIdx.x < 64) {
         const float m = wave0_fixed_sum(red, n_mass);
         if (threadIdx.x == 0) *mass_s = m;
@@ -547,12 +534,23 @@ __device__ __forceinline__ void dct_tile(const PlanDev& d, const WsLayout& L, ch
     const TwLds tw = tw_lds_build(sm + DP * twoM, d.ffts[d.fft_dct], d.tw);
     for (int e = threadIdx.x; e < np * twoM; e += blockDim.x) sm[e] = make_float2(0.f, 0.f);
     __syncthreads();
-    for (int e = threadIdx.x; e < np * nin; e += blockDim.x) {
-        const int p = e / nin, q = e - p * nin;
-        const int d0 = 2 * (p0 + p);
-        const float re = src[(size_t)d0 * sld + q];
-        const float im = (d0 + 1 < D) ? src[(size_t)(d0 + 1) * sld + q] : 0.f;
-        sm[p * twoM + q + 1] = make_float2(re, im);
+    if (adj) {  // g [D][T]: contiguous along t
+        for (int e = threadIdx.x; e < np * nin; e += blockDim.x) {
+            const int p = e / nin, q = e - p * nin;
+            const int d0 = 2 * (p0 + p);
+            const float re = gin[(size_t)d0 * T + q];
+            const float im = (d0 + 1 < D) ? gin[(size_t)(d0 + 1) * T + q] : 0.f;
+            sm[p * twoM + q + 1] = make_float2(re, im);
+        }
+    } else {    // hT [nlam][D]: the tile's detectors are contiguous within a row
+        for (int e = threadIdx.x; e < np * nin; e += blockDim.x) {
+            const int q = e / np, p = e - q * np;
+            const int d0 = 2 * (p0 + p);
+            const float* row = hT + (size_t)q * D;
+            const float re = row[d0];
+            const float im = (d0 + 1 < D) ? row[d0 + 1] : 0.f;
+            sm[p * twoM + q + 1] = make_float2(re, im);
+        }
     }
     if (adj) {
         // data sum of each detector of the tile: samples in kSumClasses classes,
@@ -575,14 +573,23 @@ __device__ __forceinline__ void dct_tile(const PlanDev& d, const WsLayout& L, ch
     __syncthreads();
     fft_lds<kMaxB>(sm, twoM, np, d.ffts[d.fft_dct], tw, false);
     const float add = adj ? 0.f : d.kappa * *mass_s;
-    float* dst = adj ? hT : gout;
-    const int dld = adj ? NL : T;
-    for (int e = threadIdx.x; e < np * nout; e += blockDim.x) {
-        const int p = e / nout, q = e - p * nout;
-        const int d0 = 2 * (p0 + p);
-        const float2 a = sm[p * twoM + q + 1], c = sm[p * twoM + twoM - q - 1];
-        dst[(size_t)d0 * dld + q] = 0.5f * (a.x + c.x) + add;
-        if (d0 + 1 < D) dst[(size_t)(d0 + 1) * dld + q] = 0.5f * (a.y + c.y) + add;
+    if (adj) {  // -> hT [nlam][D]
+        for (int e = threadIdx.x; e < np * nout; e += blockDim.x) {
+            const int q = e / np, p = e - q * np;
+            const int d0 = 2 * (p0 + p);
+            const float2 a = sm[p * twoM + q + 1], c = sm[p * twoM + twoM - q - 1];
+            float* row = hT + (size_t)q * D;
+            row[d0] = 0.5f * (a.x + c.x);
+            if (d0 + 1 < D) row[d0 + 1] = 0.5f * (a.y + c.y);
+        }
+    } else {    // -> g [D][T]
+        for (int e = threadIdx.x; e < np * nout; e += blockDim.x) {
+            const int p = e / nout, q = e - p * nout;
+            const int d0 = 2 * (p0 + p);
+            const float2 a = sm[p * twoM + q + 1], c = sm[p * twoM + twoM - q - 1];
+            gout[(size_t)d0 * T + q] = 0.5f * (a.x + c.x) + add;
+            if (d0 + 1 < D) gout[(size_t)(d0 + 1) * T + q] = 0.5f * (a.y + c.y) + add;
+        }
     }
 }
 

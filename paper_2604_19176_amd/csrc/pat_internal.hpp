@@ -114,13 +114,13 @@ __host__ __device__ constexpr size_t spread_lds_words(int CAP, int IB) { return 
 constexpr int kRingModesPerThread = 8;
 constexpr int kRingMaxThreads = 256;
 // Their LDS in float2 slots: ring buffer (aliased by the half-length
-// synthesis buffer), synthesis buffer, [D][RT] float tile, three twiddle tables.
+// synthesis buffer), synthesis buffer, three twiddle tables.
 __host__ __device__ constexpr int ring_tw_slots(int n) { return 64 + (n + 63) / 64; }
-__host__ __device__ constexpr size_t ring_lds_slots(int npsi_max, int S, int syn_half, int tile_floats)
+__host__ __device__ constexpr size_t ring_lds_slots(int npsi_max, int S, int syn_half)
 {
     return (size_t)((npsi_max / 2 > (syn_half ? S / 2 : 0)) ? npsi_max / 2 : S / 2) +
-           (size_t)(S > npsi_max / 2 ? S : npsi_max / 2) + (size_t)((tile_floats + 1) / 2) +
-           (size_t)ring_tw_slots(npsi_max) + 2 * (size_t)ring_tw_slots(S);
+           (size_t)(S > npsi_max / 2 ? S : npsi_max / 2) + (size_t)ring_tw_slots(npsi_max) +
+           2 * (size_t)ring_tw_slots(S);
 }
 
 // Tile-shape limits of the interpolation and the spread.
@@ -135,7 +135,7 @@ inline bool spread_shape_ok(int cb, int th) { return cb >= 64 && cb <= 256 && cb
 struct WsLayout {
     size_t x1;       // [Hy][N]   float2   column-pass output / row-pass-adjoint output
     size_t grid;     // [Hy][Ng]  float2   spectrum / spread target
-    size_t hdet;     // [D][nlam] float    ring output (synthesised at the detectors) / cosine-adjoint output
+    size_t hdet;     // [nlam][D] float    ring output (synthesised at the detectors) / cosine-adjoint output
     size_t polar;    // [npts]    float2   polar values: ring order (interpolation output), band order (spread input)
     size_t red;      // small FP32 partial sums (mass / data sum)
     int n_red;       // number of partial sums

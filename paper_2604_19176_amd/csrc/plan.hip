@@ -261,7 +261,8 @@ static size_t twb_bytes(int n) { return sizeof(float2) * (size_t)tw_lds_slots(n)
 // [D][RT] detector tile and four twiddle tables.
 static size_t ring_lds_bytes(const PlanDev& d, int RT)
 {
-    return sizeof(float2) * ring_lds_slots(d.npsi_max, d.syn_len, d.syn_half, d.D * RT);
+    (void)RT;  // rings of a workgroup are processed one after another in the same LDS
+    return sizeof(float2) * ring_lds_slots(d.npsi_max, d.syn_len, d.syn_half);
 }
 
 constexpr size_t kLdsMax = 160 * 1024;  // LDS a gfx950 workgroup can hold
