@@ -161,6 +161,9 @@ typedef struct {
                      the tile window (gat_th + 7) x (gat_cb + 7) x 8 bytes is at most 64 KB  */
     int spr_cb;   /* spread workgroup width: 64, 128, 192 or 256 columns                     */
     int spr_th;   /* spread output rows per workgroup, 1..4096                               */
+    int gat_ib;   /* instances of a batch sharing one interpolation tile: 1, 2 or 4 (the
+                     ES weights and indexing are shared; windows: gat_ib x the size above) */
+    int spr_ib;   /* instances of a batch sharing one spread tile: 1, 2 or 4              */
 } pat_launch;
 
 /* pat_plan_get_launch copies the plan's launch shapes.  pat_plan_set_launch
@@ -206,7 +209,8 @@ int  pat_batch_adjoint(const pat_batch* batch, const float* const* g_ptrs, float
                        void* ws, size_t ws_bytes, void* stream);
 
 /* The batch-wide interpolation and spread shapes (gat_cb, gat_th, spr_cb,
- * spr_th of pat_launch; the other fields are ignored on set and returned as 0
+ * spr_th of pat_launch; the instances of a heterogeneous batch never share a
+ * tile; the other fields are ignored on set and returned as 0
  * on get).  pat_batch_set_launch rewrites the device instance table and
  * therefore waits for the device to be idle first.  Errors: PAT_ERR_ARG
  * (NULL, field out of range), PAT_ERR_HIP. */

@@ -46,7 +46,7 @@ class pat_plan_info(ctypes.Structure):
 
 class pat_launch(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int) for n in ("col_np", "row_rpb", "ring_rt", "dct_dp", "gat_cb", "gat_th",
-                                             "spr_cb", "spr_th")]
+                                             "spr_cb", "spr_th", "gat_ib", "spr_ib")]
 
     def asdict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

@@ -21,10 +21,6 @@ static unsigned xcd_grid(int items) { return (unsigned)(((items + kXcds - 1) / k
 // Dynamic LDS of the interpolation ([8][cb + 7] float2 window) and of the
 // spread (2 cb staged points x 19 words).
 static size_t spread_lds(int cb, int ib) { return sizeof(float) * spread_lds_words(2 * cb, ib); }
-
-// Instances per spread workgroup for a batch of one plan: the ES weights and
-// indexing of a tile are shared by up to four instances.
-static int spread_ib(int batch) { return batch >= 4 ? 4 : (batch >= 2 ? 2 : 1); }
 static size_t fft_tile_lds(int nseq, int n) { return sizeof(float2) * (size_t)nseq * n + twb(n); }
 
 static int check_launch()
@@ -68,10 +64,13 @@ extern "C" int pat_forward(const pat_plan* p, const float* f, float* g, int batc
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, 2, st);
     {
-        const int cb = c.gat_cb, th = c.gat_th;
-        const int items = ((d.Ng + cb - 1) / cb) * ((d.NB + th - 1) / th) * batch;
-        hipLaunchKernelGGL(k_gather, dim3(xcd_grid(items)), dim3(kGatherThreads), gather_lds_bytes(cb, th), st, d,
-                           p->ws, wsp, cb, th, batch);
+        const int cb = c.gat_cb, th = c.gat_th, ib = tile_ib(c.gat_ib, batch);
+        const int items = ((d.Ng + cb - 1) / cb) * ((d.NB + th - 1) / th) * ((batch + ib - 1) / ib);
+        const dim3 grid(xcd_grid(items)), blk(kGatherThreads);
+        const size_t lds = gather_lds_bytes(cb, th, ib);
+        if (ib == 4) hipLaunchKernelGGL(k_gather<4>, grid, blk, lds, st, d, p->ws, wsp, cb, th, batch);
+        else if (ib == 2) hipLaunchKernelGGL(k_gather<2>, grid, blk, lds, st, d, p->ws, wsp, cb, th, batch);
+        else hipLaunchKernelGGL(k_gather<1>, grid, blk, lds, st, d, p->ws, wsp, cb, th, batch);
     }
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, 3, st);
@@ -110,7 +109,7 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 2, st);
     {
-        const int cb = c.spr_cb, th = c.spr_th, ib = spread_ib(batch);
+        const int cb = c.spr_cb, th = c.spr_th, ib = tile_ib(c.spr_ib, batch);
         const int items = ((d.Ng + cb - 1) / cb) * ((d.Hy + th - 1) / th) * ((batch + ib - 1) / ib);
         const dim3 grid(xcd_grid(items)), blk(cb);
         if (ib == 4)
@@ -229,6 +228,8 @@ static void launch_to_public(const LaunchCfg& c, pat_launch* o)
     o->gat_th = c.gat_th;
     o->spr_cb = c.spr_cb;
     o->spr_th = c.spr_th;
+    o->gat_ib = c.gat_ib;
+    o->spr_ib = c.spr_ib;
 }
 
 extern "C" int pat_plan_get_launch(const pat_plan* p, pat_launch* out)
@@ -250,6 +251,8 @@ extern "C" int pat_plan_set_launch(pat_plan* p, const pat_launch* in)
     c.gat_th = in->gat_th;
     c.spr_cb = in->spr_cb;
     c.spr_th = in->spr_th;
+    c.gat_ib = in->gat_ib;
+    c.spr_ib = in->spr_ib;
     return apply_launch(p, c);  // leaves the plan unchanged on error
 }
 
@@ -259,7 +262,7 @@ extern "C" int pat_plan_set_launch(pat_plan* p, const pat_launch* in)
 
 static bool batch_shape_ok(const pat_launch& c)
 {
-    return gather_shape_ok(c.gat_cb, c.gat_th) && spread_shape_ok(c.spr_cb, c.spr_th);
+    return gather_shape_ok(c.gat_cb, c.gat_th, 1) && spread_shape_ok(c.spr_cb, c.spr_th, 1);
 }
 
 // Per-stage work-item prefix sums for the current batch-wide shapes, and the
@@ -422,7 +425,7 @@ extern "C" int pat_batch_forward(const pat_batch* b, const float* const* f_ptrs,
                        w);
     if ((rc = check_launch())) return rc;
     hipLaunchKernelGGL(k_gather_b, dim3(xcd_grid(batch_items(b, kStGather))), dim3(kGatherThreads),
-                       gather_lds_bytes(b->gat_cb, b->gat_th), st, bt, w, b->gat_cb);
+                       gather_lds_bytes(b->gat_cb, b->gat_th, 1), st, bt, w, b->gat_cb);
     if ((rc = check_launch())) return rc;
     hipLaunchKernelGGL(k_ring_fwd_b<4>, dim3(xcd_grid(batch_items(b, kStRing))), dim3(b->thr_ring), b->lds_ring, st,
                        bt, w);

@@ -205,25 +205,32 @@ __device__ __forceinline__ void rowpass_fwd_tile(const PlanDev& d, const WsLayou
 // handled by kGatherThreads / TH threads, one point per thread at a time.
 // Output: the polar value times the half-pixel phase, stored in ring order.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void gather_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile, int CB, int TH,
-                                            float2* win)
+// IB instances of one plan share a tile (wbs[b], b < nb; b >= nb is padding):
+// one window per instance, the ES weights and indexing of each point once.
+template <int IB>
+__device__ __forceinline__ void gather_tile(const PlanDev& d, const WsLayout& L, char* const (&wbs)[IB], int nb,
+                                            int tile, int CB, int TH, float2* win)
 {
     const int Ng = d.Ng, NB = d.NB, Hy = d.Hy;
-    const int W = CB + 7, R = TH + 7;
+    const int W = CB + 7, R = TH + 7, RW = R * W;
     const int ncb = (Ng + CB - 1) / CB;
     const int rbk = tile / ncb, cbk = tile - rbk * ncb;
     const int C0 = cbk * CB, R0 = rbk * TH;
     const int cend = min(C0 + CB, Ng);
     const int nbands = min(TH, NB - R0);
-    const float2* __restrict__ G = (const float2*)(wb + L.grid);
-    float2* Fp = (float2*)(wb + L.polar);
-    int* seg_lo = (int*)(win + R * W);
+    int* seg_lo = (int*)(win + IB * RW);
     int* seg_hi = seg_lo + TH;
-    for (int e = threadIdx.x; e < R * W; e += blockDim.x) {
-        const int rr = e / W, cc = e - rr * W;
-        const int r = R0 + rr;
-        const int c = (C0 + cc) % Ng;
-        win[e] = r < Hy ? G[(size_t)r * Ng + c] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int b = 0; b < IB; ++b) {
+        if (b >= nb) break;
+        const float2* __restrict__ G = (const float2*)(wbs[b] + L.grid);
+        float2* wn = win + b * RW;
+        for (int e = threadIdx.x; e < RW; e += blockDim.x) {
+            const int rr = e / W, cc = e - rr * W;
+            const int r = R0 + rr;
+            const int c = (C0 + cc) % Ng;
+            wn[e] = r < Hy ? G[(size_t)r * Ng + c] : make_float2(0.f, 0.f);
+        }
     }
     if ((int)threadIdx.x < nbands) {
         const int* bp = d.band_ptr + (size_t)(R0 + threadIdx.x) * (Ng + 1);
@@ -232,30 +239,36 @@ __device__ __forceinline__ void gather_tile(const PlanDev& d, const WsLayout& L,
     }
     __syncthreads();
     const int Q = kGatherThreads / TH;  // threads per band
-    const int b = threadIdx.x / Q, u = threadIdx.x - b * Q;
-    if (b >= nbands) return;            // no barrier follows
-    const int hi = seg_hi[b];
-    for (int s = seg_lo[b] + u; s < hi; s += Q) {
+    const int bnd = threadIdx.x / Q, u = threadIdx.x - bnd * Q;
+    if (bnd >= nbands) return;          // no barrier follows
+    const int hi = seg_hi[bnd];
+    for (int s = seg_lo[bnd] + u; s < hi; s += Q) {
         const float4 gq = d.bpt_geo[s];
         const int c0 = fbits(gq.x) - C0;
         float wx[8], wy[8];
         es_weights8(gq.z, wx);
         es_weights8(gq.w, wy);
-        float2 acc = make_float2(0.f, 0.f);
+        const float2 ph = d.bpt_phase[s];
+        const int ri = d.ring_of[s];
 #pragma unroll
-        for (int dy = 0; dy < 8; ++dy) {
-            const float2* row = win + (b + dy) * W + c0;
-            float2 ra = make_float2(0.f, 0.f);
+        for (int b = 0; b < IB; ++b) {
+            if (b >= nb) break;
+            float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
-            for (int dx = 0; dx < 8; ++dx) {
-                const float2 gv = row[dx];
-                ra.x = fmaf(wx[dx], gv.x, ra.x);
-                ra.y = fmaf(wx[dx], gv.y, ra.y);
+            for (int dy = 0; dy < 8; ++dy) {
+                const float2* row = win + b * RW + (bnd + dy) * W + c0;
+                float2 ra = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int dx = 0; dx < 8; ++dx) {
+                    const float2 gv = row[dx];
+                    ra.x = fmaf(wx[dx], gv.x, ra.x);
+                    ra.y = fmaf(wx[dx], gv.y, ra.y);
+                }
+                acc.x = fmaf(wy[dy], ra.x, acc.x);
+                acc.y = fmaf(wy[dy], ra.y, acc.y);
             }
-            acc.x = fmaf(wy[dy], ra.x, acc.x);
-            acc.y = fmaf(wy[dy], ra.y, acc.y);
+            ((float2*)(wbs[b] + L.polar))[ri] = cmul(acc, ph);
         }
-        Fp[d.ring_of[s]] = cmul(acc, d.bpt_phase[s]);
     }
 }
 
@@ -932,15 +945,21 @@ __global__ __launch_bounds__(1024) void k_rowpass_fwd_b(BatchDev bt, char* ws)
     rowpass_fwd_tile(d, I.L, ws + I.ws_off, tile, I.row_rpb, sm);
 }
 
+template <int IB>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(PlanDev d, WsLayout L, InstPtrs wsp, int CB, int TH,
                                                            int batch)
 {
     extern __shared__ float2 win[];
     const int per = ((d.Ng + CB - 1) / CB) * ((d.NB + TH - 1) / TH);
-    const int item = xcd_item(blockIdx.x, per * batch);
+    const int ngroups = (batch + IB - 1) / IB;
+    const int item = xcd_item(blockIdx.x, per * ngroups);
     if (item < 0) return;
-    const int b = item / per;
-    gather_tile(d, L, wsp.ws + (size_t)b * wsp.stride, item - b * per, CB, TH, win);
+    const int g = item / per;
+    const int b0 = g * IB, nb = min(IB, batch - b0);
+    char* wbs[IB];
+#pragma unroll
+    for (int b = 0; b < IB; ++b) wbs[b] = wsp.ws + (size_t)(b0 + (b < nb ? b : 0)) * wsp.stride;
+    gather_tile<IB>(d, L, wbs, nb, item - g * per, CB, TH, win);
 }
 
 // CB is the batch-wide tile width (the instance table carries TH).
@@ -951,7 +970,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_b(BatchDev bt, char* 
     if (!batch_item(bt, kStGather, i, tile)) return;
     const BatchInst& I = bt.inst[i];
     const PlanDev d = I.d;
-    gather_tile(d, I.L, ws + I.ws_off, tile, CB, I.gat_th, win);
+    char* const wbs[1] = {ws + I.ws_off};
+    gather_tile<1>(d, I.L, wbs, 1, tile, CB, I.gat_th, win);
 }
 
 // Ring kernels: at most kRingMaxThreads threads (one wave for most rings).  The

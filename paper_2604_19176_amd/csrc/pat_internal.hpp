@@ -93,15 +93,17 @@ struct LaunchCfg {
     int gat_th;      // interpolation: bands per tile (power of two, 1..64)
     int spr_cb;      // spread: columns per workgroup (multiple of 64)
     int spr_th;      // spread: rows per workgroup
+    int gat_ib;      // interpolation: instances per tile (1, 2 or 4)
+    int spr_ib;      // spread: instances per tile (1, 2 or 4)
     int spr_cap;     // spread: points staged in LDS per chunk
 };
 
 // Interpolation tiles: kGatherThreads threads; window of (TH + 7) x (CB + 7)
 // spectrum values plus two ints per band.
 constexpr int kGatherThreads = 256;
-__host__ __device__ constexpr size_t gather_lds_bytes(int CB, int TH)
+__host__ __device__ constexpr size_t gather_lds_bytes(int CB, int TH, int IB)
 {
-    return sizeof(float2) * (size_t)(TH + 7) * (CB + 7) + sizeof(int) * 2 * (size_t)TH;
+    return sizeof(float2) * (size_t)IB * (TH + 7) * (CB + 7) + sizeof(int) * 2 * (size_t)TH;
 }
 // Spread tiles for CAP staged points and IB instances:
 //   wx [8][CAP], wy [8][CAP] (ES weights), bx [CAP] (footprint column relative
@@ -124,12 +126,23 @@ __host__ __device__ constexpr size_t ring_lds_slots(int npsi_max, int S, int syn
 }
 
 // Tile-shape limits of the interpolation and the spread.
-inline bool gather_shape_ok(int cb, int th)
+inline bool ib_ok(int ib) { return ib == 1 || ib == 2 || ib == 4; }
+inline bool gather_shape_ok(int cb, int th, int ib)
 {
-    return cb >= 8 && cb <= 512 && cb % 8 == 0 && th >= 1 && th <= 64 && (th & (th - 1)) == 0 &&
-           gather_lds_bytes(cb, th) <= 64 * 1024;
+    return cb >= 8 && cb <= 512 && cb % 8 == 0 && th >= 1 && th <= 64 && (th & (th - 1)) == 0 && ib_ok(ib) &&
+           gather_lds_bytes(cb, th, ib) <= 64 * 1024;
 }
-inline bool spread_shape_ok(int cb, int th) { return cb >= 64 && cb <= 256 && cb % 64 == 0 && th >= 1 && th <= 4096; }
+inline bool spread_shape_ok(int cb, int th, int ib)
+{
+    return cb >= 64 && cb <= 256 && cb % 64 == 0 && th >= 1 && th <= 4096 && ib_ok(ib);
+}
+// Instances per tile for a call on `batch` instances of one plan: the largest
+// of 4, 2, 1 that is at most the configured count and the batch.
+inline int tile_ib(int cfg_ib, int batch)
+{
+    const int m = cfg_ib < batch ? cfg_ib : batch;
+    return m >= 4 ? 4 : (m >= 2 ? 2 : 1);
+}
 
 // Per-instance workspace layout (byte offsets; all 256-byte aligned).
 struct WsLayout {

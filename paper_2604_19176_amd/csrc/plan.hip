@@ -278,7 +278,8 @@ int apply_launch(pat_plan* p, const LaunchCfg& c)
         return v >= 1 && v <= 16 && v * each + fixed <= kLdsMax && fft_threads(v, f) <= 1024;
     };
     if (c.col_np < 1 || c.col_np > 16 || c.row_rpb < 1 || c.row_rpb > 16 || c.dct_dp < 1 || c.dct_dp > 16 ||
-        c.ring_rt < 1 || c.ring_rt > 64 || !gather_shape_ok(c.gat_cb, c.gat_th) || !spread_shape_ok(c.spr_cb, c.spr_th))
+        c.ring_rt < 1 || c.ring_rt > 64 || !gather_shape_ok(c.gat_cb, c.gat_th, c.gat_ib) ||
+        !spread_shape_ok(c.spr_cb, c.spr_th, c.spr_ib))
         return PAT_ERR_ARG;
     if (!fft_ok(c.col_np, sizeof(float2) * d.Ng, p->h_fft_grid, twb_bytes(d.Ng)) ||
         !fft_ok(c.row_rpb, sizeof(float2) * d.Ng, p->h_fft_grid, twb_bytes(d.Ng)) ||
@@ -323,11 +324,13 @@ int choose_launch(pat_plan* p, const std::vector<FftDev>& fd, int max_batch,
     c.ring_rt = 1;
     // wide tiles amortise the per-band work; narrow ones keep small batches parallel
     const long gwide = (long)((d.Ng + 255) / 256) * ((d.NB + 31) / 32) * max_batch;
-    c.gat_cb = gwide >= 512 ? 128 : 64;
+    c.gat_cb = 64;
     c.gat_th = gwide >= 512 ? 16 : 8;
     // spread: wide tiles for large batches; rows per tile as many as keep about
     // 512 workgroups (a tile sweeps th + 7 bands for th output rows)
-    const int ib = max_batch >= 4 ? 4 : (max_batch >= 2 ? 2 : 1);
+    const int ib = tile_ib(4, max_batch);
+    c.gat_ib = ib;
+    c.spr_ib = ib;
     const long groups = (max_batch + ib - 1) / ib;
     c.spr_cb = (d.Ng >= 512 && groups >= 8) ? 256 : 64;
     c.spr_th = 1;

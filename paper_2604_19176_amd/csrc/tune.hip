@@ -16,15 +16,18 @@
 
 namespace {
 
-constexpr int kRounds = 8;
+constexpr int kRounds = 10;
 constexpr int kReps = 3;  // timed repetitions per round (after one warm-up); the minimum is kept
 
 const int kColNp[] = {1, 2, 4, 8, 16};
 const int kRowRpb[] = {1, 2, 4, 8, 16};
 const int kRingRt[] = {1, 2, 4};
 const int kDctDp[] = {1, 2, 4, 8};
-const int kGather[][2] = {{32, 8}, {64, 4}, {64, 8}, {64, 16}, {128, 8}, {128, 16}, {64, 32}, {256, 16}};
-const int kSpread[][2] = {{64, 1}, {64, 2}, {64, 4}, {64, 8}, {128, 8}, {256, 4}, {256, 8}, {256, 16}};
+// (columns, rows or bands, instances per tile); a candidate whose LDS does not fit is skipped
+const int kGather[][3] = {{64, 8, 4}, {64, 16, 4}, {32, 8, 4}, {64, 4, 4}, {64, 16, 2}, {128, 16, 1},
+                          {64, 8, 1}, {128, 8, 2}, {64, 4, 1}, {32, 16, 4}};
+const int kSpread[][3] = {{256, 16, 4}, {256, 8, 4}, {128, 8, 4}, {256, 16, 2}, {256, 8, 2}, {64, 4, 1},
+                          {64, 2, 1}, {256, 4, 1}, {64, 8, 4}, {128, 16, 2}};
 
 enum { kSCol, kSRow, kSRing, kSDct, kSGather, kSSpread, kNS };
 
@@ -36,8 +39,14 @@ bool set_candidate(pat_launch& c, int s, int r)
         case kSRow: if (r >= 5) return false; c.row_rpb = kRowRpb[r]; return true;
         case kSRing: if (r >= 3) return false; c.ring_rt = kRingRt[r]; return true;
         case kSDct: if (r >= 4) return false; c.dct_dp = kDctDp[r]; return true;
-        case kSGather: if (r >= 8) return false; c.gat_cb = kGather[r][0]; c.gat_th = kGather[r][1]; return true;
-        default: if (r >= 8) return false; c.spr_cb = kSpread[r][0]; c.spr_th = kSpread[r][1]; return true;
+        case kSGather:
+            if (r >= 10) return false;
+            c.gat_cb = kGather[r][0]; c.gat_th = kGather[r][1]; c.gat_ib = kGather[r][2];
+            return true;
+        default:
+            if (r >= 10) return false;
+            c.spr_cb = kSpread[r][0]; c.spr_th = kSpread[r][1]; c.spr_ib = kSpread[r][2];
+            return true;
     }
 }
 
@@ -48,8 +57,8 @@ void copy_stage(pat_launch& dst, const pat_launch& src, int s)
         case kSRow: dst.row_rpb = src.row_rpb; break;
         case kSRing: dst.ring_rt = src.ring_rt; break;
         case kSDct: dst.dct_dp = src.dct_dp; break;
-        case kSGather: dst.gat_cb = src.gat_cb; dst.gat_th = src.gat_th; break;
-        default: dst.spr_cb = src.spr_cb; dst.spr_th = src.spr_th; break;
+        case kSGather: dst.gat_cb = src.gat_cb; dst.gat_th = src.gat_th; dst.gat_ib = src.gat_ib; break;
+        default: dst.spr_cb = src.spr_cb; dst.spr_th = src.spr_th; dst.spr_ib = src.spr_ib; break;
     }
 }
 
@@ -100,11 +109,14 @@ std::string batch_key(const pat_batch* b)
 }
 
 // ---- cache file: {"key": {"col_np": 1, ...}, ...} --------------------------
-const char* kFields[8] = {"col_np", "row_rpb", "ring_rt", "dct_dp", "gat_cb", "gat_th", "spr_cb", "spr_th"};
+constexpr int kNumFields = 10;
+const char* kFields[kNumFields] = {"col_np", "row_rpb", "ring_rt", "dct_dp", "gat_cb",
+                                   "gat_th", "spr_cb",  "spr_th",  "gat_ib", "spr_ib"};
 
 int* field_ptr(pat_launch& c, int i)
 {
-    int* f[8] = {&c.col_np, &c.row_rpb, &c.ring_rt, &c.dct_dp, &c.gat_cb, &c.gat_th, &c.spr_cb, &c.spr_th};
+    int* f[kNumFields] = {&c.col_np, &c.row_rpb, &c.ring_rt, &c.dct_dp, &c.gat_cb,
+                          &c.gat_th, &c.spr_cb,  &c.spr_th,  &c.gat_ib, &c.spr_ib};
     return f[i];
 }
 
@@ -133,7 +145,7 @@ bool cache_lookup(const std::string& text, const std::string& key, pat_launch& c
     const size_t end = text.find('}', at + pat.size());
     if (end == std::string::npos) return false;
     const std::string body = text.substr(at + pat.size(), end - at - pat.size());
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < kNumFields; ++i) {
         const std::string f = "\"" + std::string(kFields[i]) + "\": ";
         const size_t q = body.find(f);
         if (q == std::string::npos) return false;
@@ -149,7 +161,7 @@ bool cache_store(const char* path, const std::string& key, const pat_launch& c0)
     if (cache_read(path, text) < 0) return false;
     char entry[768];
     int o = std::snprintf(entry, sizeof entry, "\"%s\": {", key.c_str());
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < kNumFields; ++i)
         o += std::snprintf(entry + o, sizeof entry - o, "%s\"%s\": %d", i ? ", " : "", kFields[i], *field_ptr(c, i));
     std::snprintf(entry + o, sizeof entry - o, "}");
     const std::string pat = "\"" + key + "\": {";
