@@ -99,7 +99,7 @@ def roofline(kms, info, geom, B):
     try:
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
-        if tr.get("kernels_hash") == kernels_hash() and tr.get("kernel") == KERNEL_SYMBOL[dom] \
+        if tr.get("kernels_hash") == kernels_hash() and tr.get("kernel", "").split("<")[0] == KERNEL_SYMBOL[dom] \
                 and tr.get("batch") == B:
             traffic = int(tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"])
     except (OSError, ValueError, KeyError):

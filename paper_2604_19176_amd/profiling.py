@@ -1,9 +1,9 @@
 """Summaries of rocprofv3 CSV output for the library's kernels.
 
 `python -m paper_2604_19176_amd.profiling stats <dir>/run_kernel_trace.csv`
-prints, per kernel, the number of dispatches and the average duration of the
-dispatches with the largest grid (the batched launches of a run that also
-makes small-batch calls), next to rocprofv3's own all-dispatch average.
+prints, per kernel and launch grid (a run mixes batched and single-instance
+calls), the number of dispatches and their average duration, next to
+rocprofv3's own average over all of a kernel's dispatches.
 
 `python -m paper_2604_19176_amd.profiling traffic <fetch.csv> <write.csv>
 --kernel NAME --calib-bytes BYTES` turns two `--pmc FETCH_SIZE` /
@@ -42,34 +42,34 @@ def _grid(row):
 
 
 def kernel_durations(trace_csv):
-    """{kernel: {"grid": largest grid, "n": dispatches at it, "avg_us": mean duration}}."""
+    """{(kernel, grid): {"n": dispatches, "avg_us": mean duration}} -- one entry
+    per launch shape, since a run mixes batched, single-instance and tuning calls."""
     by = defaultdict(list)
     for r in _rows(trace_csv):
-        by[_short(r["Kernel_Name"])].append((_grid(r), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
-    out = {}
-    for k, v in by.items():
-        gmax = max(g for g, _ in v)
-        d = [t for g, t in v if g == gmax]
-        out[k] = {"grid": gmax, "n": len(d), "avg_us": sum(d) / len(d) / 1e3, "all_n": len(v)}
-    return out
+        by[(_short(r["Kernel_Name"]), _grid(r))].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return {k: {"n": len(v), "avg_us": sum(v) / len(v) / 1e3} for k, v in by.items()}
 
 
-def stats_table(trace_csv, stats_csv=None):
+def stats_table(trace_csv, stats_csv=None, min_dispatches=5):
     kd = kernel_durations(trace_csv)
     allavg = {}
     if stats_csv and os.path.exists(stats_csv):
         for r in _rows(stats_csv):
             allavg[_short(r["Name"])] = float(r["AverageNs"]) / 1e3
-    lines = ["| kernel | dispatches (all / largest grid) | largest grid | avg us (largest grid) | avg us (all) |",
+    lines = ["| kernel | grid (work-items) | dispatches | avg us | rocprofv3 avg over all grids (us) |",
              "|---|---|---|---|---|"]
-    for k, v in sorted(kd.items(), key=lambda kv: -kv[1]["avg_us"] * kv[1]["n"]):
-        a = allavg.get(k)
-        lines.append("| %s | %d / %d | %d | %.1f | %s |" % (k, v["all_n"], v["n"], v["grid"], v["avg_us"],
-                                                           "%.1f" % a if a is not None else "-"))
+    rows = [(k, v) for k, v in kd.items() if v["n"] >= min_dispatches]
+    for (name, grid), v in sorted(rows, key=lambda kv: -kv[1]["avg_us"] * kv[1]["n"]):
+        a = allavg.get(name)
+        lines.append("| %s | %d | %d | %.1f | %s |" % (name, grid, v["n"], v["avg_us"],
+                                                    "%.1f" % a if a is not None else "-"))
     return "\n".join(lines)
 
 
 def _counter(path, kernel):
+    """Mean counter value over the dispatches of `kernel` at its most frequent
+    grid among the grids of at least half the largest one (the timed batched
+    launches, not the single-instance or untuned calls)."""
     vals, calib = [], []
     for r in _rows(path):
         name = r["Kernel_Name"]
@@ -81,7 +81,12 @@ def _counter(path, kernel):
     if not vals:
         raise SystemExit("kernel %s not found in %s" % (kernel, path))
     gmax = max(g for g, _ in vals)
-    kv = [v for g, v in vals if g == gmax]
+    count = defaultdict(int)
+    for g, _ in vals:
+        if 2 * g >= gmax:
+            count[g] += 1
+    gsel = max(count, key=lambda g: (count[g], g))
+    kv = [v for g, v in vals if g == gsel]
     return sum(kv) / len(kv), (max(calib) if calib else None), len(kv)
 
 
