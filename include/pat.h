@@ -156,7 +156,7 @@ typedef struct {
     int row_rpb;  /* spectrum rows per row-pass workgroup, 1..16                             */
     int ring_rt;  /* radial frequencies (rings) per ring-kernel workgroup, 1..64             */
     int dct_dp;   /* detector pairs per cosine-transform workgroup, 1..16                    */
-    int gat_cb;   /* polar-interpolation tile width in grid columns: multiple of 8, 8..512  */
+    int gat_cb;   /* polar-interpolation tile width in grid columns: 32, 64, 128 or 256      */
     int gat_th;   /* interpolation bands (footprint base rows) per tile: 1, 2, 4, .., 64;
                      the tile window (gat_th + 7) x (gat_cb + 7) x 8 bytes is at most 64 KB  */
     int spr_cb;   /* spread workgroup width: 64, 128, 192 or 256 columns                     */

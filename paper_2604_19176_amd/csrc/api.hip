@@ -21,6 +21,33 @@ static unsigned xcd_grid(int items) { return (unsigned)(((items + kXcds - 1) / k
 // Dynamic LDS of the interpolation ([8][cb + 7] float2 window) and of the
 // spread (2 cb staged points x 19 words).
 static size_t spread_lds(int cb, int ib) { return sizeof(float) * spread_lds_words(2 * cb, ib); }
+
+// Launches of the interpolation and spread instantiations (tile width and
+// instances per tile are template parameters of the kernels).
+template <int IB>
+static void gather_launch_ib(int cb, dim3 grid, size_t lds, hipStream_t st, const PlanDev& d, const WsLayout& L,
+                             InstPtrs wsp, int th, int batch)
+{
+    const dim3 blk(kGatherThreads);
+    switch (cb) {
+        case 32: hipLaunchKernelGGL((k_gather<IB, 32>), grid, blk, lds, st, d, L, wsp, th, batch); break;
+        case 64: hipLaunchKernelGGL((k_gather<IB, 64>), grid, blk, lds, st, d, L, wsp, th, batch); break;
+        case 128: hipLaunchKernelGGL((k_gather<IB, 128>), grid, blk, lds, st, d, L, wsp, th, batch); break;
+        default: hipLaunchKernelGGL((k_gather<IB, 256>), grid, blk, lds, st, d, L, wsp, th, batch); break;
+    }
+}
+
+template <int IB>
+static void spread_launch_ib(int cb, dim3 grid, size_t lds, hipStream_t st, const PlanDev& d, const WsLayout& L,
+                             InstPtrs wsp, int th, int batch)
+{
+    switch (cb) {
+        case 64: hipLaunchKernelGGL((k_spread<IB, 64>), grid, dim3(64), lds, st, d, L, wsp, th, batch); break;
+        case 128: hipLaunchKernelGGL((k_spread<IB, 128>), grid, dim3(128), lds, st, d, L, wsp, th, batch); break;
+        case 192: hipLaunchKernelGGL((k_spread<IB, 192>), grid, dim3(192), lds, st, d, L, wsp, th, batch); break;
+        default: hipLaunchKernelGGL((k_spread<IB, 256>), grid, dim3(256), lds, st, d, L, wsp, th, batch); break;
+    }
+}
 static size_t fft_tile_lds(int nseq, int n) { return sizeof(float2) * (size_t)nseq * n + twb(n); }
 
 static int check_launch()
@@ -66,11 +93,11 @@ extern "C" int pat_forward(const pat_plan* p, const float* f, float* g, int batc
     {
         const int cb = c.gat_cb, th = c.gat_th, ib = tile_ib(c.gat_ib, batch);
         const int items = ((d.Ng + cb - 1) / cb) * ((d.NB + th - 1) / th) * ((batch + ib - 1) / ib);
-        const dim3 grid(xcd_grid(items)), blk(kGatherThreads);
+        const dim3 grid(xcd_grid(items));
         const size_t lds = gather_lds_bytes(cb, th, ib);
-        if (ib == 4) hipLaunchKernelGGL(k_gather<4>, grid, blk, lds, st, d, p->ws, wsp, cb, th, batch);
-        else if (ib == 2) hipLaunchKernelGGL(k_gather<2>, grid, blk, lds, st, d, p->ws, wsp, cb, th, batch);
-        else hipLaunchKernelGGL(k_gather<1>, grid, blk, lds, st, d, p->ws, wsp, cb, th, batch);
+        if (ib == 4) gather_launch_ib<4>(cb, grid, lds, st, d, p->ws, wsp, th, batch);
+        else if (ib == 2) gather_launch_ib<2>(cb, grid, lds, st, d, p->ws, wsp, th, batch);
+        else gather_launch_ib<1>(cb, grid, lds, st, d, p->ws, wsp, th, batch);
     }
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, 3, st);
@@ -111,13 +138,11 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
     {
         const int cb = c.spr_cb, th = c.spr_th, ib = tile_ib(c.spr_ib, batch);
         const int items = ((d.Ng + cb - 1) / cb) * ((d.Hy + th - 1) / th) * ((batch + ib - 1) / ib);
-        const dim3 grid(xcd_grid(items)), blk(cb);
-        if (ib == 4)
-            hipLaunchKernelGGL(k_spread<4>, grid, blk, spread_lds(cb, 4), st, d, p->ws, wsp, th, 2 * cb, batch);
-        else if (ib == 2)
-            hipLaunchKernelGGL(k_spread<2>, grid, blk, spread_lds(cb, 2), st, d, p->ws, wsp, th, 2 * cb, batch);
-        else
-            hipLaunchKernelGGL(k_spread<1>, grid, blk, spread_lds(cb, 1), st, d, p->ws, wsp, th, 2 * cb, batch);
+        const dim3 grid(xcd_grid(items));
+        const size_t lds = spread_lds(cb, ib);
+        if (ib == 4) spread_launch_ib<4>(cb, grid, lds, st, d, p->ws, wsp, th, batch);
+        else if (ib == 2) spread_launch_ib<2>(cb, grid, lds, st, d, p->ws, wsp, th, batch);
+        else spread_launch_ib<1>(cb, grid, lds, st, d, p->ws, wsp, th, batch);
     }
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 3, st);
@@ -424,8 +449,16 @@ extern "C" int pat_batch_forward(const pat_batch* b, const float* const* f_ptrs,
     hipLaunchKernelGGL(k_rowpass_fwd_b, dim3(xcd_grid(batch_items(b, kStRow))), dim3(b->thr_row), b->lds_row, st, bt,
                        w);
     if ((rc = check_launch())) return rc;
-    hipLaunchKernelGGL(k_gather_b, dim3(xcd_grid(batch_items(b, kStGather))), dim3(kGatherThreads),
-                       gather_lds_bytes(b->gat_cb, b->gat_th, 1), st, bt, w, b->gat_cb);
+    {
+        const dim3 grid(xcd_grid(batch_items(b, kStGather))), blk(kGatherThreads);
+        const size_t lds = gather_lds_bytes(b->gat_cb, b->gat_th, 1);
+        switch (b->gat_cb) {
+            case 32: hipLaunchKernelGGL(k_gather_b<32>, grid, blk, lds, st, bt, w); break;
+            case 64: hipLaunchKernelGGL(k_gather_b<64>, grid, blk, lds, st, bt, w); break;
+            case 128: hipLaunchKernelGGL(k_gather_b<128>, grid, blk, lds, st, bt, w); break;
+            default: hipLaunchKernelGGL(k_gather_b<256>, grid, blk, lds, st, bt, w); break;
+        }
+    }
     if ((rc = check_launch())) return rc;
     hipLaunchKernelGGL(k_ring_fwd_b<4>, dim3(xcd_grid(batch_items(b, kStRing))), dim3(b->thr_ring), b->lds_ring, st,
                        bt, w);
@@ -449,8 +482,16 @@ extern "C" int pat_batch_adjoint(const pat_batch* b, const float* const* g_ptrs,
     hipLaunchKernelGGL(k_ring_adj_b<4>, dim3(xcd_grid(batch_items(b, kStRing))), dim3(b->thr_ring), b->lds_ring, st,
                        bt, w);
     if ((rc = check_launch())) return rc;
-    hipLaunchKernelGGL(k_spread_b, dim3(xcd_grid(batch_items(b, kStSpread))), dim3(b->spr_cb), spread_lds(b->spr_cb, 1),
-                       st, bt, w);
+    {
+        const dim3 grid(xcd_grid(batch_items(b, kStSpread)));
+        const size_t lds = spread_lds(b->spr_cb, 1);
+        switch (b->spr_cb) {
+            case 64: hipLaunchKernelGGL(k_spread_b<64>, grid, dim3(64), lds, st, bt, w); break;
+            case 128: hipLaunchKernelGGL(k_spread_b<128>, grid, dim3(128), lds, st, bt, w); break;
+            case 192: hipLaunchKernelGGL(k_spread_b<192>, grid, dim3(192), lds, st, bt, w); break;
+            default: hipLaunchKernelGGL(k_spread_b<256>, grid, dim3(256), lds, st, bt, w); break;
+        }
+    }
     if ((rc = check_launch())) return rc;
     hipLaunchKernelGGL(k_rowpass_adj_b, dim3(xcd_grid(batch_items(b, kStRow))), dim3(b->thr_row), b->lds_row, st, bt,
                        w);

@@ -207,12 +207,13 @@ __device__ __forceinline__ void rowpass_fwd_tile(const PlanDev& d, const WsLayou
 // ---------------------------------------------------------------------------
 // IB instances of one plan share a tile (wbs[b], b < nb; b >= nb is padding):
 // one window per instance, the ES weights and indexing of each point once.
-template <int IB>
+template <int IB, int CB>
 __device__ __forceinline__ void gather_tile(const PlanDev& d, const WsLayout& L, char* const (&wbs)[IB], int nb,
-                                            int tile, int CB, int TH, float2* win)
+                                            int tile, int TH, float2* win)
 {
+    constexpr int W = CB + 7;  // compile-time row stride: the 64 taps are immediate offsets
     const int Ng = d.Ng, NB = d.NB, Hy = d.Hy;
-    const int W = CB + 7, R = TH + 7, RW = R * W;
+    const int R = TH + 7, RW = R * W;
     const int ncb = (Ng + CB - 1) / CB;
     const int rbk = tile / ncb, cbk = tile - rbk * ncb;
     const int C0 = cbk * CB, R0 = rbk * TH;
@@ -618,23 +619,52 @@ struct BandMeta {
     int aLo, nA, bLo, ntot, lo, hi;
 };
 
-__device__ __forceinline__ BandMeta band_meta(const PlanDev& d, int rb, int C0, int mx, bool active)
+// A band's row of the band CSR as the spread tile at columns [C0, C0 + CB)
+// needs it: v[k] = band_ptr[rb][col] for col = C0 - 7 + k (k = 0 .. CB + 8),
+// wrapped to col + Ng below 0 and clamped to Ng above, and v[CB + 9] =
+// band_ptr[rb][Ng].  Each thread fetches entries tid and tid + CB.
+__device__ __forceinline__ void band_row_fetch(const PlanDev& d, int rb, int C0, int CB, int (&v)[2])
 {
     const int Ng = d.Ng;
     const int* bp = d.band_ptr + (size_t)rb * (Ng + 1);
-    const int lo_col = C0 - 7, hi_col = min(C0 + (int)blockDim.x, Ng);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int k = threadIdx.x + i * CB;
+        v[i] = 0;
+        if (k < CB + 10) {
+            const int col = C0 - 7 + k;
+            v[i] = k == CB + 9 ? bp[Ng] : bp[col < 0 ? col + Ng : min(col, Ng)];
+        }
+    }
+}
+
+__device__ __forceinline__ void band_row_store(int* row, int CB, const int (&v)[2])
+{
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int k = threadIdx.x + i * CB;
+        if (k < CB + 10) row[k] = v[i];
+    }
+}
+
+// Staged-index ranges of a band from its CSR row in LDS: the wrapped segment
+// (columns Ng-7 .. Ng-1, only for the tile at column 0) comes first, then the
+// columns C0-7 .. C0+CB-1; lane's visit range is its footprint columns mx-7 .. mx.
+__device__ __forceinline__ BandMeta band_meta(const int* row, int Ng, int C0, int CB, bool active)
+{
+    const int lo_col = C0 - 7;
+    const int khi = min(C0 + CB, Ng) - lo_col;
     BandMeta m;
-    m.aLo = lo_col < 0 ? bp[Ng + lo_col] : 0;
-    const int aHi = lo_col < 0 ? bp[Ng] : 0;
-    m.bLo = bp[max(lo_col, 0)];
-    const int bHi = bp[hi_col];
+    m.aLo = lo_col < 0 ? row[0] : 0;
+    const int aHi = lo_col < 0 ? row[CB + 9] : 0;
+    m.bLo = row[lo_col < 0 ? -lo_col : 0];
     m.nA = aHi - m.aLo;
-    m.ntot = m.nA + (bHi - m.bLo);
+    m.ntot = m.nA + (row[khi] - m.bLo);
     m.lo = m.hi = 0;
     if (active) {
-        const int c = mx - 7;
-        m.lo = c < 0 ? (bp[Ng + c] - m.aLo) : (m.nA + bp[c] - m.bLo);
-        m.hi = m.nA + bp[mx + 1] - m.bLo;
+        const int t = threadIdx.x;
+        m.lo = (lo_col + t < 0) ? (row[t] - m.aLo) : (m.nA + row[t] - m.bLo);
+        m.hi = m.nA + row[t + 8] - m.bLo;
     }
     return m;
 }
@@ -654,8 +684,8 @@ struct SpreadLds {
     float2* h;
 };
 
-template <int IB>
-__device__ __forceinline__ void spread_stage(const SpreadLds<IB>& S, int CAP, int e, float4 gq, int bx_rel,
+template <int IB, int CAP>
+__device__ __forceinline__ void spread_stage(const SpreadLds<IB>& S, int e, float4 gq, int bx_rel,
                                              const float2 (&h)[IB])
 {
     float w[8];
@@ -670,8 +700,8 @@ __device__ __forceinline__ void spread_stage(const SpreadLds<IB>& S, int CAP, in
     for (int b = 0; b < IB; ++b) S.h[b * CAP + e] = h[b];
 }
 
-template <int IB>
-__device__ __forceinline__ void spread_visit(const SpreadLds<IB>& S, int CAP, int s0, int s1, int c0, int lane7,
+template <int IB, int CAP>
+__device__ __forceinline__ void spread_visit(const SpreadLds<IB>& S, int s0, int s1, int c0, int lane7,
                                              float2 (&acc)[IB][8])
 {
     for (int s = s0; s < s1; ++s) {
@@ -695,13 +725,15 @@ __device__ __forceinline__ void spread_visit(const SpreadLds<IB>& S, int CAP, in
 
 // One tile of the spread for IB instances of one plan (wbs[b], b < nb, are the
 // instance workspaces; instances b >= nb are padding and neither read nor
-// written).  CAP = 2 * blockDim.x: two staged points per thread per chunk.
-template <int IB>
+// written).  The workgroup has CB threads, one per column; CAP = 2 CB points
+// are staged per chunk.  CB is a compile-time constant so that every LDS
+// access of the inner loops is an immediate offset from one base address.
+template <int IB, int CB>
 __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L, char* const (&wbs)[IB], int nb,
-                                            int tile, int TH, int CAP, float* sf)
+                                            int tile, int TH, float* sf)
 {
+    constexpr int CAP = 2 * CB;
     const int Ng = d.Ng, NB = d.NB, Hy = d.Hy;
-    const int CB = blockDim.x;
     const int ncb = (Ng + CB - 1) / CB;
     const int rb_ = tile / ncb, cb_ = tile - rb_ * ncb;
     const float2* __restrict__ H[IB];
@@ -716,6 +748,7 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
     S.wy = sf + 8 * CAP;
     S.bx = (int*)(sf + 16 * CAP);
     S.h = (float2*)(sf + 17 * CAP);  // CAP is even: 8-byte aligned
+    int* rows = (int*)(sf + (size_t)CAP * (17 + 2 * IB));  // [3][CB + 10]
     const int C0 = cb_ * CB, R0 = rb_ * TH;
     const int mx = C0 + threadIdx.x;
     const int lane7 = threadIdx.x + 7;
@@ -739,32 +772,52 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
 #pragma unroll
         for (int b = 0; b < IB; ++b) h[b] = b < nb ? H[b][sl] : make_float2(0.f, 0.f);
     };
+    // band_lo <= band_hi always: R0 <= Hy - 1 = NB + 7 - 1 gives R0 - 7 <= NB - 1
+    // Pipeline over bands (three LDS slots of CSR rows, slot of band r = (r - band_lo) % 3):
+    // in the step of band rb, the CSR row of band rb+2 (fetched in the previous
+    // step) is stored, the row of band rb+3 and the points of band rb+1 are
+    // fetched, and band rb (points fetched in the previous step) is staged and
+    // visited.  Every global load is first waited for one step after it is issued.
+    auto slot = [&](int r) { return rows + ((r - band_lo) % 3) * (CB + 10); };
     BandMeta nm;
     float4 ng0 = make_float4(0.f, 0.f, 0.f, 0.f), ng1 = ng0;
     float2 nh0[IB], nh1[IB];
 #pragma unroll
     for (int b = 0; b < IB; ++b) nh0[b] = nh1[b] = make_float2(0.f, 0.f);
-    if (band_lo <= band_hi) {
-        nm = band_meta(d, band_lo, C0, mx, active);
-        if (e0 < nm.ntot) fetch(nm, e0, ng0, nh0);
-        if (e1 < nm.ntot) fetch(nm, e1, ng1, nh1);
+    int rv[2] = {0, 0};  // CSR row in flight (band rb + 2 at the top of the step of band rb)
+    {
+        int v[2];
+        band_row_fetch(d, band_lo, C0, CB, v);
+        band_row_store(slot(band_lo), CB, v);
+        if (band_lo + 1 <= band_hi) {
+            band_row_fetch(d, band_lo + 1, C0, CB, v);
+            band_row_store(slot(band_lo + 1), CB, v);
+        }
+        if (band_lo + 2 <= band_hi) band_row_fetch(d, band_lo + 2, C0, CB, rv);
     }
+    __syncthreads();
+    nm = band_meta(slot(band_lo), Ng, C0, CB, active);
+    if (e0 < nm.ntot) fetch(nm, e0, ng0, nh0);
+    if (e1 < nm.ntot) fetch(nm, e1, ng1, nh1);
     for (int rb = band_lo; rb <= band_hi; ++rb) {
+        // slot of band rb+2 last held band rb-1, whose row was read two steps ago
+        if (rb + 2 <= band_hi) band_row_store(slot(rb + 2), CB, rv);
         const BandMeta m = nm;
         const float4 g0 = ng0, g1 = ng1;
         float2 h0[IB], h1[IB];
 #pragma unroll
         for (int b = 0; b < IB; ++b) { h0[b] = nh0[b]; h1[b] = nh1[b]; }
-        if (rb < band_hi) {  // prefetch the next band
-            nm = band_meta(d, rb + 1, C0, mx, active);
+        // chunk 0 from registers
+        if (e0 < m.ntot) spread_stage<IB, CAP>(S, e0, g0, rel(m, e0, g0), h0);
+        if (e1 < m.ntot) spread_stage<IB, CAP>(S, e1, g1, rel(m, e1, g1), h1);
+        __syncthreads();
+        if (rb < band_hi) {  // band rb+1: its CSR row was stored one step ago
+            nm = band_meta(slot(rb + 1), Ng, C0, CB, active);
             if (e0 < nm.ntot) fetch(nm, e0, ng0, nh0);
             if (e1 < nm.ntot) fetch(nm, e1, ng1, nh1);
         }
-        // chunk 0 from registers
-        if (e0 < m.ntot) spread_stage<IB>(S, CAP, e0, g0, rel(m, e0, g0), h0);
-        if (e1 < m.ntot) spread_stage<IB>(S, CAP, e1, g1, rel(m, e1, g1), h1);
-        __syncthreads();
-        spread_visit<IB>(S, CAP, m.lo, min(m.hi, CAP), 0, lane7, acc);
+        if (rb + 3 <= band_hi) band_row_fetch(d, rb + 3, C0, CB, rv);
+        spread_visit<IB, CAP>(S, m.lo, min(m.hi, CAP), 0, lane7, acc);
         __syncthreads();
         // further chunks (dense bands only)
         for (int c0 = CAP; c0 < m.ntot; c0 += CAP) {
@@ -773,10 +826,10 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
                 float4 gq;
                 float2 hh[IB];
                 fetch(m, c0 + e, gq, hh);
-                spread_stage<IB>(S, CAP, e, gq, rel(m, c0 + e, gq), hh);
+                spread_stage<IB, CAP>(S, e, gq, rel(m, c0 + e, gq), hh);
             }
             __syncthreads();
-            spread_visit<IB>(S, CAP, max(m.lo, c0), min(m.hi, c0 + cn), c0, lane7, acc);
+            spread_visit<IB, CAP>(S, max(m.lo, c0), min(m.hi, c0 + cn), c0, lane7, acc);
             __syncthreads();
         }
         // row rb is complete
@@ -945,9 +998,8 @@ __global__ __launch_bounds__(1024) void k_rowpass_fwd_b(BatchDev bt, char* ws)
     rowpass_fwd_tile(d, I.L, ws + I.ws_off, tile, I.row_rpb, sm);
 }
 
-template <int IB>
-__global__ __launch_bounds__(kGatherThreads) void k_gather(PlanDev d, WsLayout L, InstPtrs wsp, int CB, int TH,
-                                                           int batch)
+template <int IB, int CB>
+__global__ __launch_bounds__(kGatherThreads) void k_gather(PlanDev d, WsLayout L, InstPtrs wsp, int TH, int batch)
 {
     extern __shared__ float2 win[];
     const int per = ((d.Ng + CB - 1) / CB) * ((d.NB + TH - 1) / TH);
@@ -959,11 +1011,12 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(PlanDev d, WsLayout L
     char* wbs[IB];
 #pragma unroll
     for (int b = 0; b < IB; ++b) wbs[b] = wsp.ws + (size_t)(b0 + (b < nb ? b : 0)) * wsp.stride;
-    gather_tile<IB>(d, L, wbs, nb, item - g * per, CB, TH, win);
+    gather_tile<IB, CB>(d, L, wbs, nb, item - g * per, TH, win);
 }
 
 // CB is the batch-wide tile width (the instance table carries TH).
-__global__ __launch_bounds__(kGatherThreads) void k_gather_b(BatchDev bt, char* ws, int CB)
+template <int CB>
+__global__ __launch_bounds__(kGatherThreads) void k_gather_b(BatchDev bt, char* ws)
 {
     extern __shared__ float2 win[];
     int i, tile;
@@ -971,7 +1024,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_b(BatchDev bt, char* 
     const BatchInst& I = bt.inst[i];
     const PlanDev d = I.d;
     char* const wbs[1] = {ws + I.ws_off};
-    gather_tile<1>(d, I.L, wbs, 1, tile, CB, I.gat_th, win);
+    gather_tile<1, CB>(d, I.L, wbs, 1, tile, I.gat_th, win);
 }
 
 // Ring kernels: at most kRingMaxThreads threads (one wave for most rings).  The
@@ -1052,12 +1105,12 @@ __global__ __launch_bounds__(1024) void k_dct_det_b(BatchDev bt, char* ws, float
              red_s, &mass_s);
 }
 
-// IB instances per workgroup: instances g*IB .. g*IB + IB - 1 of the batch.
-template <int IB>
-__global__ __launch_bounds__(256) void k_spread(PlanDev d, WsLayout L, InstPtrs wsp, int TH, int CAP, int batch)
+// IB instances per workgroup: instances g*IB .. g*IB + IB - 1 of the batch; CB threads.
+template <int IB, int CB>
+__global__ __launch_bounds__(CB) void k_spread(PlanDev d, WsLayout L, InstPtrs wsp, int TH, int batch)
 {
     extern __shared__ float sf[];
-    const int per = ((d.Ng + (int)blockDim.x - 1) / (int)blockDim.x) * ((d.Hy + TH - 1) / TH);
+    const int per = ((d.Ng + CB - 1) / CB) * ((d.Hy + TH - 1) / TH);
     const int ngroups = (batch + IB - 1) / IB;
     const int item = xcd_item(blockIdx.x, per * ngroups);
     if (item < 0) return;
@@ -1066,10 +1119,11 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev d, WsLayout L, InstPtrs 
     char* wbs[IB];
 #pragma unroll
     for (int b = 0; b < IB; ++b) wbs[b] = wsp.ws + (size_t)(b0 + (b < nb ? b : 0)) * wsp.stride;
-    spread_tile<IB>(d, L, wbs, nb, item - g * per, TH, CAP, sf);
+    spread_tile<IB, CB>(d, L, wbs, nb, item - g * per, TH, sf);
 }
 
-__global__ __launch_bounds__(256) void k_spread_b(BatchDev bt, char* ws)
+template <int CB>
+__global__ __launch_bounds__(CB) void k_spread_b(BatchDev bt, char* ws)
 {
     extern __shared__ float sf[];
     int i, tile;
@@ -1077,7 +1131,7 @@ __global__ __launch_bounds__(256) void k_spread_b(BatchDev bt, char* ws)
     const BatchInst& I = bt.inst[i];
     const PlanDev d = I.d;
     char* const wbs[1] = {ws + I.ws_off};
-    spread_tile<1>(d, I.L, wbs, 1, tile, I.spr_th, 2 * (int)blockDim.x, sf);
+    spread_tile<1, CB>(d, I.L, wbs, 1, tile, I.spr_th, sf);
 }
 
 __global__ __launch_bounds__(1024) void k_rowpass_adj(PlanDev d, WsLayout L, InstPtrs wsp, int RPB)

@@ -89,7 +89,7 @@ struct LaunchCfg {
     int row_rpb;     // rows per row-pass workgroup
     int ring_rt;     // rings per ring-kernel workgroup
     int dct_dp;      // detector pairs per cosine-transform workgroup
-    int gat_cb;      // interpolation: columns per tile (multiple of 8, 8..512)
+    int gat_cb;      // interpolation: columns per tile (32, 64, 128 or 256)
     int gat_th;      // interpolation: bands per tile (power of two, 1..64)
     int spr_cb;      // spread: columns per workgroup (multiple of 64)
     int spr_th;      // spread: rows per workgroup
@@ -105,10 +105,14 @@ __host__ __device__ constexpr size_t gather_lds_bytes(int CB, int TH, int IB)
 {
     return sizeof(float2) * (size_t)IB * (TH + 7) * (CB + 7) + sizeof(int) * 2 * (size_t)TH;
 }
-// Spread tiles for CAP staged points and IB instances:
+// Spread tiles for CAP = 2 CB staged points and IB instances:
 //   wx [8][CAP], wy [8][CAP] (ES weights), bx [CAP] (footprint column relative
-//   to the tile: lane + 7 - bx is the tap), h [IB][CAP] (complex).
-__host__ __device__ constexpr size_t spread_lds_words(int CAP, int IB) { return (size_t)CAP * (17 + 2 * IB); }
+//   to the tile: lane + 7 - bx is the tap), h [IB][CAP] (complex), and three
+//   slots of CB + 10 ints holding bands' rows of the band CSR (pipeline).
+__host__ __device__ constexpr size_t spread_lds_words(int CAP, int IB)
+{
+    return (size_t)CAP * (17 + 2 * IB) + 3 * (size_t)(CAP / 2 + 10);
+}
 
 // Ring kernels: modes k = thread + j * threads (j < kRingModesPerThread) of a
 // ring are handled by one thread (coefficients prefetched into registers), so
@@ -129,8 +133,8 @@ __host__ __device__ constexpr size_t ring_lds_slots(int npsi_max, int S, int syn
 inline bool ib_ok(int ib) { return ib == 1 || ib == 2 || ib == 4; }
 inline bool gather_shape_ok(int cb, int th, int ib)
 {
-    return cb >= 8 && cb <= 512 && cb % 8 == 0 && th >= 1 && th <= 64 && (th & (th - 1)) == 0 && ib_ok(ib) &&
-           gather_lds_bytes(cb, th, ib) <= 64 * 1024;
+    return (cb == 32 || cb == 64 || cb == 128 || cb == 256) && th >= 1 && th <= 64 && (th & (th - 1)) == 0 &&
+           ib_ok(ib) && gather_lds_bytes(cb, th, ib) <= 64 * 1024;
 }
 inline bool spread_shape_ok(int cb, int th, int ib)
 {
