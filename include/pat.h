@@ -135,6 +135,29 @@ int  pat_pgd_update(float* f, const float* adj, const float* tvgrad, long count,
 int  pat_residual(float* g, const float* g_meas, float* sq, long count_per, int batch,
                   void* stream);
 
+/* Primal-dual TV reconstruction (the classical baseline of Sec. 2.1:
+ * min_{f >= 0} 0.5 ||A f - g||^2 + alpha TV(f), solved with the primal-dual
+ * hybrid gradient method the paper cites, stopped on the relative change of
+ * Sec. 2.4.2).  With K = (A, grad), one iteration is
+ *   A fbar -> ax (pat_forward);  pat_pd_dual_data;  pat_pd_dual_tv;
+ *   A* y1 -> aty (pat_adjoint);  pat_pd_primal;  [pat_pd_change]
+ * with step sizes sigma tau (||A||^2 + 8) < 1.  TV is the isotropic total
+ * variation with forward differences and a zero difference across the last
+ * row / column (Neumann boundary).  All buffers are device FP32, [batch]-major.
+ * pat_pd_dual_data: y1 <- (y1 + sigma (ax - g)) / (1 + sigma), count elements.
+ * pat_pd_dual_tv:   y2 <- projection of y2 + sigma grad(xbar) onto
+ *                   {|y2_ij| <= alpha}; y2 [batch][n][n][2] (x, y components).
+ * pat_pd_primal:    f' = max(f - tau (aty + grad* y2), 0); xbar <- 2 f' - f;
+ *                   f <- f' (f, xbar, aty [batch][n][n]; in place).
+ * pat_pd_change:    out[2b] = ||xbar_b - f_b||^2 = ||f'_b - f_b(old)||^2 and
+ *                   out[2b+1] = ||f_b||^2 right after pat_pd_primal (fixed-order sums).
+ * Errors: PAT_ERR_ARG (NULL, n < 2, batch < 1, sigma or tau <= 0, alpha < 0), PAT_ERR_HIP. */
+int  pat_pd_dual_data(float* y1, const float* ax, const float* g, long count, float sigma, void* stream);
+int  pat_pd_dual_tv(float* y2, const float* xbar, int n, int batch, float sigma, float alpha, void* stream);
+int  pat_pd_primal(float* f, float* xbar, const float* aty, const float* y2, int n, int batch, float tau,
+                   void* stream);
+int  pat_pd_change(const float* f, const float* xbar, float* out, int n, int batch, void* stream);
+
 /* Per-kernel timing.  pat_profile_enable(plan, 1) creates HIP events; from
  * then on every pat_forward / pat_adjoint call on `plan` records an event
  * before and after each of its kernels on the call's stream (a few

@@ -92,6 +92,10 @@ def load():
         "pat_batch_set_launch": (ci, [vp, P(pat_launch)]),
         "pat_autotune_plan": (ci, [vp, ci, ctypes.c_char_p]),
         "pat_autotune_batch": (ci, [vp, ctypes.c_char_p]),
+        "pat_pd_dual_data": (ci, [vp, vp, vp, cl, cf, vp]),
+        "pat_pd_dual_tv": (ci, [vp, vp, ci, ci, cf, cf, vp]),
+        "pat_pd_primal": (ci, [vp, vp, vp, vp, ci, ci, cf, vp]),
+        "pat_pd_change": (ci, [vp, vp, vp, ci, ci, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -234,3 +238,21 @@ def pat_autotune_plan(plan, batch: int, cache_path) -> None:
 def pat_autotune_batch(batch, cache_path) -> None:
     cp = None if cache_path is None else os.fsencode(cache_path)
     _check(load().pat_autotune_batch(batch, cp), "pat_autotune_batch")
+
+
+def pat_pd_dual_data(y1_ptr, ax_ptr, g_ptr, count, sigma, stream) -> None:
+    _check(load().pat_pd_dual_data(y1_ptr, ax_ptr, g_ptr, int(count), float(sigma), stream), "pat_pd_dual_data")
+
+
+def pat_pd_dual_tv(y2_ptr, xbar_ptr, n, batch, sigma, alpha, stream) -> None:
+    _check(load().pat_pd_dual_tv(y2_ptr, xbar_ptr, int(n), int(batch), float(sigma), float(alpha), stream),
+           "pat_pd_dual_tv")
+
+
+def pat_pd_primal(f_ptr, xbar_ptr, aty_ptr, y2_ptr, n, batch, tau, stream) -> None:
+    _check(load().pat_pd_primal(f_ptr, xbar_ptr, aty_ptr, y2_ptr, int(n), int(batch), float(tau), stream),
+           "pat_pd_primal")
+
+
+def pat_pd_change(f_ptr, xbar_ptr, out_ptr, n, batch, stream) -> None:
+    _check(load().pat_pd_change(f_ptr, xbar_ptr, out_ptr, int(n), int(batch), stream), "pat_pd_change")

@@ -192,6 +192,40 @@ extern "C" int pat_residual(float* g, const float* g_meas, float* sq, long count
     return check_launch();
 }
 
+extern "C" int pat_pd_dual_data(float* y1, const float* ax, const float* g, long count, float sigma, void* stream)
+{
+    if (!y1 || !ax || !g || count < 1 || !(sigma > 0.f)) return PAT_ERR_ARG;
+    const long blocks = std::min<long>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_pd_dual_data, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, y1, ax, g, count,
+                       sigma, 1.f / (1.f + sigma));
+    return check_launch();
+}
+
+extern "C" int pat_pd_dual_tv(float* y2, const float* xbar, int n, int batch, float sigma, float alpha, void* stream)
+{
+    if (!y2 || !xbar || n < 2 || batch < 1 || !(sigma > 0.f) || !(alpha >= 0.f)) return PAT_ERR_ARG;
+    const dim3 grid((n + 15) / 16, (n + 15) / 16, batch);
+    hipLaunchKernelGGL(k_pd_dual_tv, grid, dim3(256), 0, (hipStream_t)stream, (float2*)y2, xbar, n, sigma, alpha);
+    return check_launch();
+}
+
+extern "C" int pat_pd_primal(float* f, float* xbar, const float* aty, const float* y2, int n, int batch, float tau,
+                             void* stream)
+{
+    if (!f || !xbar || !aty || !y2 || n < 2 || batch < 1 || !(tau > 0.f)) return PAT_ERR_ARG;
+    const dim3 grid((n + 15) / 16, (n + 15) / 16, batch);
+    hipLaunchKernelGGL(k_pd_primal, grid, dim3(256), 0, (hipStream_t)stream, f, xbar, aty, (const float2*)y2, n,
+                       tau);
+    return check_launch();
+}
+
+extern "C" int pat_pd_change(const float* f, const float* xbar, float* out, int n, int batch, void* stream)
+{
+    if (!f || !xbar || !out || n < 1 || batch < 1) return PAT_ERR_ARG;
+    hipLaunchKernelGGL(k_pd_change, dim3(batch), dim3(1024), 0, (hipStream_t)stream, f, xbar, out, (long)n * n);
+    return check_launch();
+}
+
 extern "C" int pat_profile_enable(pat_plan* p, int enable)
 {
     if (!p) return PAT_ERR_ARG;

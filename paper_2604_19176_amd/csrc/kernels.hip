@@ -1251,4 +1251,86 @@ __global__ __launch_bounds__(1024) void k_half_sq(const float* __restrict__ g, f
     if (threadIdx.x == 0) sq[b] = 0.5f * tot;
 }
 
+// ---------------------------------------------------------------------------
+// primal-dual TV iteration (the paper's TV baseline): dual steps for the data
+// term and the isotropic TV term, primal step with the f >= 0 projection and
+// the extrapolation fbar = 2 f' - f, and the relative-change norms
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pd_dual_data(float* __restrict__ y1, const float* __restrict__ ax,
+                                                      const float* __restrict__ g, long count, float sigma,
+                                                      float inv1s)
+{
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count; e += (long)gridDim.x * blockDim.x)
+        y1[e] = (y1[e] + sigma * (ax[e] - g[e])) * inv1s;
+}
+
+// y2 [batch][n][n] float2 (x and y components), xbar [batch][n][n]
+__global__ __launch_bounds__(256) void k_pd_dual_tv(float2* __restrict__ y2, const float* __restrict__ xbar, int n,
+                                                    float sigma, float alpha)
+{
+    const int b = blockIdx.z;
+    const int j = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int i = blockIdx.y * 16 + (threadIdx.x >> 4);
+    if (i >= n || j >= n) return;
+    const float* xb = xbar + (size_t)b * n * n;
+    const size_t e = (size_t)b * n * n + (size_t)i * n + j;
+    const float c = xb[(size_t)i * n + j];
+    const float dx = (j + 1 < n) ? xb[(size_t)i * n + j + 1] - c : 0.f;
+    const float dy = (i + 1 < n) ? xb[(size_t)(i + 1) * n + j] - c : 0.f;
+    float2 v = y2[e];
+    v.x += sigma * dx;
+    v.y += sigma * dy;
+    const float m = sqrtf(v.x * v.x + v.y * v.y);
+    const float sc = m > alpha ? alpha / m : 1.f;  // projection onto |v| <= alpha
+    y2[e] = make_float2(v.x * sc, v.y * sc);
+}
+
+// f' = max(f - tau (aty + grad* y2), 0); xbar = 2 f' - f; f = f'
+__global__ __launch_bounds__(256) void k_pd_primal(float* __restrict__ f, float* __restrict__ xbar,
+                                                   const float* __restrict__ aty, const float2* __restrict__ y2,
+                                                   int n, float tau)
+{
+    const int b = blockIdx.z;
+    const int j = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int i = blockIdx.y * 16 + (threadIdx.x >> 4);
+    if (i >= n || j >= n) return;
+    const size_t base = (size_t)b * n * n;
+    const size_t e = base + (size_t)i * n + j;
+    // (grad* y2)_ij: the x component enters at (i, j) with -1 (j < n-1) and at (i, j+1) with +1,
+    // the y component at (i, j) with -1 (i < n-1) and at (i+1, j) with +1
+    const float2 p = y2[e];
+    float gs = 0.f;
+    if (j + 1 < n) gs -= p.x;
+    if (j > 0) gs += y2[e - 1].x;
+    if (i + 1 < n) gs -= p.y;
+    if (i > 0) gs += y2[e - n].y;
+    const float old = f[e];
+    const float fn = fmaxf(old - tau * (aty[e] + gs), 0.f);
+    f[e] = fn;
+    xbar[e] = 2.f * fn - old;
+}
+
+// out[b] = (sum (xbar - f)^2, sum f^2) over instance b (after k_pd_primal,
+// xbar - f = f' - f_old): one workgroup per instance, fixed-order sums
+__global__ __launch_bounds__(1024) void k_pd_change(const float* __restrict__ f, const float* __restrict__ xbar,
+                                                    float* __restrict__ out, long per)
+{
+    __shared__ float red_s[1024];
+    const int b = blockIdx.x;
+    const float* fb = f + (size_t)b * per;
+    const float* xb = xbar + (size_t)b * per;
+    float sd = 0.f, sf = 0.f;
+    for (long e = threadIdx.x; e < per; e += blockDim.x) {
+        const float v = fb[e], dlt = xb[e] - v;
+        sd += dlt * dlt;
+        sf += v * v;
+    }
+    const float td = block_sum(sd, red_s);
+    const float tf = block_sum(sf, red_s);
+    if (threadIdx.x == 0) {
+        out[2 * b] = td;
+        out[2 * b + 1] = tf;
+    }
+}
+
 }  // namespace pat
