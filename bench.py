@@ -17,6 +17,9 @@ Other workloads (one JSON line each; not the default):
   --workload large   1024^2, 1024 detectors on 270 deg, 2048 samples, batch 8:
                      TV iterations/s and staged HBM GB/s
   --workload paper   the paper's timed shape (760^2, 256 detectors on 270 deg, 2030 samples)
+  --workload pdhg3   primal-dual TV (the paper's TV baseline) at 256^2, 128 detectors on 120 deg,
+                     run to relative change <= 1e-4: iterations/s and time to solution
+  --workload pdhg-large  the same at 1024^2, 1024 detectors on 270 deg, batch 8
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B] [--workload ...]
 """
@@ -328,6 +331,8 @@ def bench_tv(args, cfg_id, steps_default, seed_stride):
     print("bench: building inputs (%dx%d, batch %d)" % (geom.n, geom.n, B), file=sys.stderr, flush=True)
     plan = pat.PatPlan(geom, max_batch=B)
     fs, f, gm, g_meas = make_inputs(np, torch, plan, geom, cfg, B, dev, seed_stride)
+    if args.tune:
+        plan.autotune(batch=B, cache_path=args.tune_cache)
     g_out, f_out = torch.empty_like(g_meas), torch.empty_like(f)
     ms_pair, _ = time_pairs(torch, plan, f, g_meas, g_out, f_out, 5, 2)
     gin = g_meas if B > 1 else g_meas[0]
@@ -359,6 +364,8 @@ def bench_tv(args, cfg_id, steps_default, seed_stride):
         "staged_hbm_gbs": round(it_bytes * steps / (ms * 1e-3) / 1e9, 1),
         "pairs_per_s": round(B * 1000.0 / ms_pair, 2),
         "tau": rec.tau,
+        "launch": plan.launch,
+        "kernels_ms": {k: round(v, 4) for k, v in kernel_times(pat, plan, f, g_meas, g_out, f_out, 5).items()},
     }
     print(json.dumps(out), flush=True)
     plan.close()
@@ -446,6 +453,58 @@ def bench_mixed(args):
         p.close()
 
 
+def bench_pdhg(args, cfg_id, seed_stride):
+    """Primal-dual TV reconstruction (the paper's classical baseline) run to the
+    paper's stopping rule: relative change <= 1e-4, checked every 10 iterations."""
+    import numpy as np
+    import torch
+
+    import paper_2604_19176_amd as pat
+    from paper_2604_19176_amd.recon import PDHGReconstructor
+    from pat_inputs import CONFIGS, config_geometry
+
+    dev = torch.device("cuda", 0)
+    cfg = CONFIGS[cfg_id]
+    geom = config_geometry(cfg_id)
+    B = cfg["batch"]
+    plan = pat.PatPlan(geom, max_batch=B)
+    fs, f, gm, g_meas = make_inputs(np, torch, plan, geom, cfg, B, dev, seed_stride)
+    if args.tune:
+        plan.autotune(batch=B, cache_path=args.tune_cache)
+    alpha = 0.05 * float(np.abs(gm).max())
+    gin = g_meas if B > 1 else g_meas[0]
+    rec = PDHGReconstructor(plan, gin, alpha)
+    rec.capture()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    iters = rec.run(args.tv_steps or 5000, tol=1e-4, check_every=10)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    done = iters - 1  # the capture's warm-up iteration ran before the timed region
+    rel = rec.relative_change()
+    err = float(np.linalg.norm((rec.f.cpu().double().numpy() - fs).ravel()) / np.linalg.norm(fs.ravel()))
+    out = {
+        "metric": "primal-dual TV iterations/s (A, A*, dual and primal steps per iteration) to relative change <= 1e-4",
+        "value": round(done * 1000.0 / ms, 2), "unit": "iterations/s", "n_gpus": 1, "steps": done, "warmup": 1,
+        "ms_per_step": round(ms / done, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "primal-dual TV, %dx%d, %d detectors on %.0f deg, %d samples, batch %d, "
+                               "alpha = 0.05 max|g|, eta %.0f %%, stopping at relative change 1e-4 (checked every 10)"
+                               % (geom.n, geom.n, geom.n_det, math.degrees(geom.arc_span), geom.n_t, B,
+                                  100 * cfg["noise"]), "batch": B},
+        "iterations_to_stop": iters, "seconds_to_stop": round(ms / 1000.0, 4), "wall_s": round(wall, 3),
+        "final_relative_change": [round(r, 8) for r in rel],
+        "rel_l2_to_phantom": round(err, 4),
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
 def bench_paper(args):
     import numpy as np
     import torch
@@ -458,6 +517,8 @@ def bench_paper(args):
     plan = pat.PatPlan(geom, max_batch=1)
     cfg = dict(phantom=(20, 3, 4), noise=0.01, seed=760)
     fs, f, gm, g_meas = make_inputs(np, torch, plan, geom, cfg, 1, dev, 1)
+    if args.tune:
+        plan.autotune(batch=1, cache_path=args.tune_cache)
     g_out, f_out = torch.empty_like(g_meas), torch.empty_like(f)
     ms, _ = time_pairs(torch, plan, f, g_meas, g_out, f_out, args.steps, args.warmup)
     out = {"metric": "A+A* pairs/s at the paper's timed shape",
@@ -475,7 +536,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=64)
-    ap.add_argument("--workload", default="default", choices=["default", "mixed", "tv3", "large", "paper"])
+    ap.add_argument("--workload", default="default",
+                    choices=["default", "mixed", "tv3", "large", "paper", "pdhg3", "pdhg-large"])
     ap.add_argument("--no-tune", dest="tune", action="store_false",
                     help="time the default launch shapes instead of autotuning them first")
     ap.add_argument("--tune-cache", default=None, help="JSON cache file of the autotuner")
@@ -492,6 +554,10 @@ def main():
         bench_default(args)
     elif args.workload == "mixed":
         bench_mixed(args)
+    elif args.workload == "pdhg3":
+        bench_pdhg(args, 3, 1000)
+    elif args.workload == "pdhg-large":
+        bench_pdhg(args, 5, 1)
     elif args.workload == "tv3":
         bench_tv(args, 3, 500, 1000)
     elif args.workload == "large":
