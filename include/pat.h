@@ -79,7 +79,10 @@ typedef struct {
     int    n_grid;            /* oversampled spectral grid side used for the polar interpolation      */
     int    n_points;          /* polar points evaluated per image (half plane, per-ring angular grids) */
     int    len_czt;           /* FFT length of the synthesis over detector angles: P when the detector
-                                 pitch is 2 pi / P (P = 2^a 3^b >= D), else the chirp-z length >= K + D */
+                                 pitch is 2 pi s / P (P = 2^a 3^b, integer s), else the chirp-z length
+                                 >= K + D                                                             */
+    int    syn_stride;        /* s in that case (detector d sits at point s d of the P-point grid),
+                                 0 for the chirp-z synthesis                                          */
     int    n_ring_modes;      /* sum over radial frequencies of the angular modes kept (K_n + 1)       */
     size_t workspace_per_instance; /* workspace bytes per batch instance                              */
     size_t table_bytes;       /* device bytes held by the plan's tables                               */

@@ -40,7 +40,7 @@ class pat_plan_info(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int), ("dlam", ctypes.c_double), ("n_lam", ctypes.c_int),
                 ("K", ctypes.c_int), ("n_psi", ctypes.c_int), ("kappa", ctypes.c_double),
                 ("n_grid", ctypes.c_int), ("n_points", ctypes.c_int), ("len_czt", ctypes.c_int),
-                ("n_ring_modes", ctypes.c_int),
+                ("syn_stride", ctypes.c_int), ("n_ring_modes", ctypes.c_int),
                 ("workspace_per_instance", ctypes.c_size_t), ("table_bytes", ctypes.c_size_t)]
 
 

@@ -394,13 +394,15 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
                 }
                 __syncthreads();
                 fft_lds<RB>(R.sc, H2, 1, d.ffts[d.fft_synh], twB, true);
+                // detector q is point s q of the P-point grid
                 for (int q = tid; q < D; q += bd) {
-                    const float2 z = R.sc[q >> 1];
-                    hn[q] = (q & 1) ? z.y : z.x;
+                    const int j = q * d.fold_s;
+                    const float2 z = R.sc[j >> 1];
+                    hn[q] = (j & 1) ? z.y : z.x;
                 }
             } else {
                 fft_lds<RB>(R.sy, Pf, 1, d.ffts[d.fft_syn], twA, true);
-                for (int q = tid; q < D; q += bd) hn[q] = R.sy[q].x;
+                for (int q = tid; q < D; q += bd) hn[q] = R.sy[q * d.fold_s].x;
             }
         } else {
             fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, false);
@@ -414,6 +416,14 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
         }
         __syncthreads();
     }
+}
+
+// Value at point j of the P-point angular grid of the detector values placed
+// at points s q (q < D), zero elsewhere.
+__device__ __forceinline__ float grid_det(const float* hn, int j, int s, int D)
+{
+    const int q = s == 1 ? j : j / s;
+    return (q * s == j && q < D) ? hn[q] : 0.f;
 }
 
 template <int RB>
@@ -450,15 +460,13 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
         // y~ = FFT of the real detector values, zero-padded to the synthesis length
         if (half) {
             const int H2 = d.fold_P / 2;
-            for (int t = tid; t < H2; t += bd) {
-                const int q0 = 2 * t, q1 = 2 * t + 1;
-                R.sc[t] = make_float2(q0 < D ? hn[q0] : 0.f, q1 < D ? hn[q1] : 0.f);
-            }
+            for (int t = tid; t < H2; t += bd)
+                R.sc[t] = make_float2(grid_det(hn, 2 * t, d.fold_s, D), grid_det(hn, 2 * t + 1, d.fold_s, D));
             __syncthreads();
             fft_lds<RB>(R.sc, H2, 1, d.ffts[d.fft_synh], twB, false);
         } else if (d.fold_P) {
             for (int sidx = tid; sidx < S; sidx += bd)
-                R.sy[sidx] = make_float2(sidx < D ? hn[sidx] : 0.f, 0.f);
+                R.sy[sidx] = make_float2(grid_det(hn, sidx, d.fold_s, D), 0.f);
             __syncthreads();
             fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, false);
         } else {

@@ -65,7 +65,8 @@ struct PlanDev {
     const float2* bpt_phase;// [npts]   pt_phase in band order
     const int* band_ptr;    // [NB][Ng + 1] CSR: first band-order slot with (r0, bx' >= bx)
     // synthesis over detector angles theta_d = theta_0 + d dtheta
-    int fold_P;             // P if dtheta = 2 pi / P (P = 2^a3^b >= D): fold k mod P, one FFT; else 0
+    int fold_P;             // P if dtheta = 2 pi s / P (P = 2^a3^b, gcd(s, P) = 1): fold k mod P, one FFT; else 0
+    int fold_s;             // s: detector d is point s d of the P-point angular grid (s (D - 1) < P)
     int syn_len;            // P (fold) or the chirp-z FFT length L >= K + D (Bluestein)
     int syn_half;           // 1: fold with even P, synthesis as a real-output FFT of length P/2
     int fft_synh;           // descriptor of length P/2 (syn_half only)

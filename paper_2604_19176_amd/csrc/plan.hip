@@ -161,7 +161,7 @@ static std::vector<double> es_hat(int N, int Ng)
 }
 
 struct Derived {
-    int M, n_lam, K, n_psi, Ng, L, P;
+    int M, n_lam, K, n_psi, Ng, L, P, S;
     double h, dlam, kappa;
 };
 
@@ -184,11 +184,21 @@ static int derive(const pat_plan_desc* d, Derived* o)
     o->kappa = d->em_correction ? o->dlam * o->dlam / (24.0 * PI) : 0.0;
     o->Ng = (int)smooth23(2.0 * d->n, 2);
     o->L = (int)smooth23((double)o->K + d->n_det, 1);
-    {   // detector pitch dtheta = 2 pi / P with P = 2^a 3^b >= D: synthesis by one FFT of length P
-        double Pd = 2.0 * PI * d->n_det / d->arc_span;
-        long Pi = std::lround(Pd);
-        o->P = (std::fabs(Pd - (double)Pi) < 1e-9 * Pd && Pi >= d->n_det && smooth23((double)Pi, 1) == Pi &&
-                Pi <= 8192) ? (int)Pi : 0;
+    {   // detector pitch dtheta = 2 pi s / P with P = 2^a 3^b (the smallest such P; then gcd(s, P) = 1
+        // and s (D - 1) < P): the detectors are every s-th point of a P-point angular grid and the
+        // synthesis is one FFT of length P.  Taken while that FFT is no dearer than the chirp-z pair.
+        const double turns = d->arc_span / (2.0 * PI * d->n_det);  // dtheta / (2 pi)
+        o->P = 0;
+        o->S = 0;
+        for (long P = smooth23((double)d->n_det, 1); P <= 8192 && P <= 3L * o->L; P = smooth23((double)P + 1, 1)) {
+            const double sd = turns * (double)P;
+            const long s = std::lround(sd);
+            if (s >= 1 && std::fabs(sd - (double)s) < 1e-9 * sd && s * (long)(d->n_det - 1) < P) {
+                o->P = (int)P;
+                o->S = (int)s;
+                break;
+            }
+        }
     }
     // limits of the kernels: every FFT length must fit the LDS plans
     if (d->n < 16 || o->Ng > 8192 || 2L * o->M > 8192 || (!o->P && o->L > 8192) || o->n_psi > 8192)
@@ -384,6 +394,7 @@ extern "C" int pat_plan_derive(const pat_plan_desc* desc, pat_plan_info* out)
     out->kappa = dv.kappa;
     out->n_grid = dv.Ng;
     out->len_czt = dv.P ? dv.P : dv.L;
+    out->syn_stride = dv.P ? dv.S : 0;
     return PAT_OK;
 }
 
@@ -410,6 +421,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     d.fft_grid = ffts.get(Ng);
     d.fft_dct = ffts.get(2L * dv.M);
     d.fold_P = dv.P;
+    d.fold_s = dv.P ? dv.S : 0;
     d.syn_len = dv.P ? dv.P : dv.L;
     d.fft_syn = ffts.get(d.syn_len);
     d.syn_half = (dv.P && dv.P % 2 == 0) ? 1 : 0;
@@ -672,6 +684,7 @@ extern "C" int pat_plan_query(const pat_plan* p, pat_plan_info* out)
     out->n_grid = p->dev.Ng;
     out->n_points = p->dev.npts;
     out->len_czt = p->dev.syn_len;
+    out->syn_stride = p->dev.fold_s;
     out->n_ring_modes = p->n_ring_modes;
     out->workspace_per_instance = p->ws.bytes;
     out->table_bytes = p->table_bytes;

@@ -12,6 +12,7 @@ import pytest
 from scipy import special
 
 from pat_inputs import Geometry, config_geometry
+from pat_inputs.geometry import paper_shape_geometry
 
 
 @pytest.fixture(scope="module")
@@ -39,11 +40,51 @@ def test_derived_sizes_match_oracle(patlib, oracle_mod, cfg):
     assert info.dlam == pytest.approx(ref["dlam"], rel=1e-15)
     assert info.kappa == pytest.approx(ref["kappa"], rel=1e-15)
     assert info.n_grid >= 2 * geom.n and info.n_grid % 2 == 0
-    pitch_turns = geom.n_det * 2 * math.pi / geom.arc_span   # 2 pi / dtheta
-    if abs(pitch_turns - round(pitch_turns)) < 1e-9 * pitch_turns and info.len_czt == round(pitch_turns):
-        assert info.len_czt >= geom.n_det            # one FFT of length P after folding modes mod P
+    _check_synthesis(info, geom)
+
+
+def _is_smooth23(p):
+    while p % 2 == 0:
+        p //= 2
+    while p % 3 == 0:
+        p //= 3
+    return p == 1
+
+
+def _check_synthesis(info, geom):
+    """Synthesis over detector angles: one FFT of length P when dtheta = 2 pi s / P
+    with P = 2^a 3^b (detectors at every s-th grid point), else the chirp-z."""
+    turns = geom.arc_span / (2 * math.pi * geom.n_det)       # dtheta / (2 pi)
+    D = geom.n_det
+    if info.syn_stride:
+        P, s = info.len_czt, info.syn_stride
+        assert _is_smooth23(P) and P <= 8192 and math.gcd(s, P) == 1
+        assert abs(P * turns - s) <= 1e-9 * s
+        assert s * (D - 1) < P                       # detectors are distinct grid points
     else:
-        assert info.len_czt >= info.K + geom.n_det   # Bluestein chirp-z
+        assert info.syn_stride == 0
+        assert info.len_czt >= info.K + D            # Bluestein chirp-z
+        # no 2^a 3^b grid within the size limits carries the detectors
+        for P in range(D, min(8192, 3 * info.len_czt) + 1):
+            if _is_smooth23(P):
+                assert abs(P * turns - round(P * turns)) > 1e-9 * P * turns or round(P * turns) == 0
+
+
+@pytest.mark.parametrize("geom,P,s", [
+    (config_geometry(1), 64, 1), (config_geometry(2), 512, 1), (config_geometry(3), 384, 1),
+    (config_geometry(5), 4096, 3), (paper_shape_geometry(), 1024, 3),
+    (Geometry(n=32, n_det=12, n_t=64, dt=2 / 64, arc_span=2 * math.pi * 24 / 27), 27, 2),
+    (Geometry(n=40, n_det=37, n_t=75, dt=2.2 / 75, arc_span=math.radians(250)), 0, 0)])
+def test_synthesis_grid(patlib, geom, P, s):
+    """Known detector layouts: 270 degrees with D detectors is every third point of
+    a 4D grid; 250 degrees over 37 detectors lies on no 2^a 3^b grid."""
+    import paper_2604_19176_amd as pat
+    info = pat.pat_plan_derive(pat.desc_from_geometry(geom))
+    _check_synthesis(info, geom)
+    if P:
+        assert (info.len_czt, info.syn_stride) == (P, s)
+    else:
+        assert info.syn_stride == 0
 
 
 def test_derived_sizes_random_geometries(patlib, oracle_mod):
@@ -65,6 +106,34 @@ def test_derived_sizes_random_geometries(patlib, oracle_mod):
             assert e.status == pat._lib.PAT_ERR_UNSUPPORTED  # valid but beyond the kernels' limits
             continue
         assert (info.M, info.n_lam, info.K, info.n_psi) == (ref["M"], ref["n_lam"], ref["K"], ref["n_psi"])
+        _check_synthesis(info, geom)
+
+
+def _smooth23_at_least(x):
+    return min(p for p in (2 ** a * 3 ** b for a in range(16) for b in range(10)) if p >= x)
+
+
+def test_synthesis_grid_random_rational_arcs(patlib):
+    """Arcs of D detectors with pitch 2 pi s / P (P = 2^a 3^b, gcd(s, P) = 1) use
+    the P-point grid with stride s whenever P is within the size limits."""
+    import paper_2604_19176_amd as pat
+    rng = np.random.default_rng(12)
+    smooth = [p for p in (2 ** a * 3 ** b for a in range(14) for b in range(9)) if 8 <= p <= 8192]
+    seen = 0
+    for _ in range(120):
+        P = int(rng.choice(smooth))
+        s = int(rng.integers(1, 8))
+        if math.gcd(s, P) != 1 or P // s < 2:
+            continue
+        D = int(rng.integers(1, min(P // s, 600) + 1))
+        geom = Geometry(n=32, n_det=D, n_t=64, dt=2 / 64, arc_span=2 * math.pi * s * D / P)
+        info = pat.pat_plan_derive(pat.desc_from_geometry(geom))
+        _check_synthesis(info, geom)
+        L = _smooth23_at_least(info.K + D)
+        if P <= min(8192, 3 * L):
+            assert (info.len_czt, info.syn_stride) == (P, s), (P, s, D)
+            seen += 1
+    assert seen >= 20
 
 
 @pytest.mark.parametrize("kw,status", [

@@ -27,6 +27,10 @@ GEOMS = {
                      lambda_oversample=3.0),
     "cfg2": config_geometry(2),
     "cfg3": config_geometry(3),
+    # 270 degrees: every third point of a 4D-point angular grid (even grid, stride 3), off-centre
+    "stride3": Geometry(n=48, n_det=64, n_t=96, dt=2 / 96, arc_span=math.radians(270), arc_center=0.7),
+    # 12 detectors spaced 2 pi 2/27: odd grid of 27 points, stride 2
+    "stride2_odd": Geometry(n=32, n_det=12, n_t=64, dt=2 / 64, arc_span=2 * math.pi * 24 / 27),
 }
 
 
