@@ -14,7 +14,6 @@
 
 using namespace pat;
 
-static size_t twb(int n) { return sizeof(float2) * (size_t)tw_lds_slots(n); }
 
 static unsigned xcd_grid(int items) { return (unsigned)(((items + kXcds - 1) / kXcds) * kXcds); }
 
@@ -48,7 +47,8 @@ static void spread_launch_ib(int cb, dim3 grid, size_t lds, hipStream_t st, cons
         default: hipLaunchKernelGGL((k_spread<IB, 256>), grid, dim3(256), lds, st, d, L, wsp, th, batch); break;
     }
 }
-static size_t fft_tile_lds(int nseq, int n) { return sizeof(float2) * (size_t)nseq * n + twb(n); }
+// LDS of an FFT tile: nseq sequences of the length plus its per-pass twiddles
+static size_t fft_tile_lds(int nseq, const FftDev& f) { return sizeof(float2) * ((size_t)nseq * f.n + f.ntb); }
 
 static int check_launch()
 {
@@ -82,12 +82,12 @@ extern "C" int pat_forward(const pat_plan* p, const float* f, float* g, int batc
     const LaunchCfg& c = p->cfg;
     const InstPtrs wsp{(char*)ws, p->ws.bytes};
     prof_mark(p, 0, 0, st);
-    hipLaunchKernelGGL(k_colpass_fwd, dim3(p->n_col_tiles, batch), dim3(p->thr_col), fft_tile_lds(c.col_np, d.Ng), st,
+    hipLaunchKernelGGL(k_colpass_fwd, dim3(p->n_col_tiles, batch), dim3(p->thr_col), fft_tile_lds(c.col_np, p->h_fft_grid), st,
                        d, p->ws, f, wsp, c.col_np);
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, 1, st);
     hipLaunchKernelGGL(k_rowpass_fwd, dim3((d.Hy + c.row_rpb - 1) / c.row_rpb, batch), dim3(p->thr_row),
-                       fft_tile_lds(c.row_rpb, d.Ng), st, d, p->ws, wsp, c.row_rpb);
+                       fft_tile_lds(c.row_rpb, p->h_fft_grid), st, d, p->ws, wsp, c.row_rpb);
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, 2, st);
     {
@@ -103,12 +103,12 @@ extern "C" int pat_forward(const pat_plan* p, const float* f, float* g, int batc
     prof_mark(p, 0, 3, st);
     {
         const dim3 grid(xcd_grid((d.nlam + c.ring_rt - 1) / c.ring_rt * batch)), blk(p->thr_ring);
-        hipLaunchKernelGGL(k_ring_fwd<4>, grid, blk, p->lds_ring, st, d, p->ws, wsp, c.ring_rt, batch);
+        hipLaunchKernelGGL(k_ring_fwd, grid, blk, p->lds_ring, st, d, p->ws, wsp, c.ring_rt, batch);
     }
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, 4, st);
     hipLaunchKernelGGL(k_dct_det, dim3(xcd_grid(p->n_pair_tiles * batch)), dim3(p->thr_dct),
-                       fft_tile_lds(c.dct_dp, 2 * d.M), st, d, p->ws, wsp, g, (const float*)nullptr, c.dct_dp, 0, d.N,
+                       fft_tile_lds(c.dct_dp, p->h_fft_dct), st, d, p->ws, wsp, g, (const float*)nullptr, c.dct_dp, 0, d.N,
                        batch);
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, 5, st);
@@ -126,12 +126,12 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
     const InstPtrs wsp{(char*)ws, p->ws.bytes};
     prof_mark(p, 1, 0, st);
     hipLaunchKernelGGL(k_dct_det, dim3(xcd_grid(p->n_pair_tiles * batch)), dim3(p->thr_dct),
-                       fft_tile_lds(c.dct_dp, 2 * d.M), st, d, p->ws, wsp, (float*)nullptr, g, c.dct_dp, 1, 0, batch);
+                       fft_tile_lds(c.dct_dp, p->h_fft_dct), st, d, p->ws, wsp, (float*)nullptr, g, c.dct_dp, 1, 0, batch);
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 1, st);
     {
         const dim3 grid(xcd_grid((d.nlam + c.ring_rt - 1) / c.ring_rt * batch)), blk(p->thr_ring);
-        hipLaunchKernelGGL(k_ring_adj<4>, grid, blk, p->lds_ring, st, d, p->ws, wsp, c.ring_rt, batch);
+        hipLaunchKernelGGL(k_ring_adj, grid, blk, p->lds_ring, st, d, p->ws, wsp, c.ring_rt, batch);
     }
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 2, st);
@@ -147,10 +147,10 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 3, st);
     hipLaunchKernelGGL(k_rowpass_adj, dim3((d.Hy + c.row_rpb - 1) / c.row_rpb, batch), dim3(p->thr_row),
-                       fft_tile_lds(c.row_rpb, d.Ng), st, d, p->ws, wsp, c.row_rpb);
+                       fft_tile_lds(c.row_rpb, p->h_fft_grid), st, d, p->ws, wsp, c.row_rpb);
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 4, st);
-    hipLaunchKernelGGL(k_colpass_adj, dim3(p->n_col_tiles, batch), dim3(p->thr_col), fft_tile_lds(c.col_np, d.Ng), st,
+    hipLaunchKernelGGL(k_colpass_adj, dim3(p->n_col_tiles, batch), dim3(p->thr_col), fft_tile_lds(c.col_np, p->h_fft_grid), st,
                        d, p->ws, wsp, f, c.col_np, d.D);
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 5, st);
@@ -351,10 +351,10 @@ static void batch_layout(pat_batch* b)
         b->thr_row = std::max<unsigned>(b->thr_row, p->thr_row);
         b->thr_ring = std::max<unsigned>(b->thr_ring, p->thr_ring);
         b->thr_dct = std::max<unsigned>(b->thr_dct, p->thr_dct);
-        b->lds_col = std::max(b->lds_col, fft_tile_lds(I.col_np, d.Ng));
-        b->lds_row = std::max(b->lds_row, fft_tile_lds(I.row_rpb, d.Ng));
+        b->lds_col = std::max(b->lds_col, fft_tile_lds(I.col_np, p->h_fft_grid));
+        b->lds_row = std::max(b->lds_row, fft_tile_lds(I.row_rpb, p->h_fft_grid));
         b->lds_ring = std::max(b->lds_ring, p->lds_ring);
-        b->lds_dct = std::max(b->lds_dct, fft_tile_lds(I.dct_dp, 2 * d.M));
+        b->lds_dct = std::max(b->lds_dct, fft_tile_lds(I.dct_dp, p->h_fft_dct));
     }
 }
 
@@ -494,7 +494,7 @@ extern "C" int pat_batch_forward(const pat_batch* b, const float* const* f_ptrs,
         }
     }
     if ((rc = check_launch())) return rc;
-    hipLaunchKernelGGL(k_ring_fwd_b<4>, dim3(xcd_grid(batch_items(b, kStRing))), dim3(b->thr_ring), b->lds_ring, st,
+    hipLaunchKernelGGL(k_ring_fwd_b, dim3(xcd_grid(batch_items(b, kStRing))), dim3(b->thr_ring), b->lds_ring, st,
                        bt, w);
     if ((rc = check_launch())) return rc;
     hipLaunchKernelGGL(k_dct_det_b, dim3(xcd_grid(batch_items(b, kStDct))), dim3(b->thr_dct), b->lds_dct, st, bt, w,
@@ -513,7 +513,7 @@ extern "C" int pat_batch_adjoint(const pat_batch* b, const float* const* g_ptrs,
     hipLaunchKernelGGL(k_dct_det_b, dim3(xcd_grid(batch_items(b, kStDct))), dim3(b->thr_dct), b->lds_dct, st, bt, w,
                        (float* const*)nullptr, g_ptrs, 1);
     if ((rc = check_launch())) return rc;
-    hipLaunchKernelGGL(k_ring_adj_b<4>, dim3(xcd_grid(batch_items(b, kStRing))), dim3(b->thr_ring), b->lds_ring, st,
+    hipLaunchKernelGGL(k_ring_adj_b, dim3(xcd_grid(batch_items(b, kStRing))), dim3(b->thr_ring), b->lds_ring, st,
                        bt, w);
     if ((rc = check_launch())) return rc;
     {

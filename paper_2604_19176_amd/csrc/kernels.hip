@@ -20,7 +20,6 @@
 
 namespace pat {
 
-constexpr int kMaxB = 4;  // butterflies per thread per FFT stage (workgroups of up to 1024 threads)
 
 // XCD-aware work mapping.  The hardware hands workgroup w to XCD (w mod 8);
 // remap so that XCD x owns the contiguous item range [start(x), start(x+1))
@@ -103,7 +102,7 @@ __device__ __forceinline__ void colpass_fwd_tile(const PlanDev& d, const WsLayou
     float2* X1 = (float2*)(wb + L.x1);
     float* red = (float*)(wb + L.red);
     const int j0 = tile * CT;
-    const TwLds tw = tw_lds_build(sm + NP * Ng, d.ffts[d.fft_grid], d.tw);
+    const float2* tb = fft_twiddles_to_lds(sm + NP * Ng, d.ffts[d.fft_grid], d.tw);
     for (int e = threadIdx.x; e < NP * Ng; e += blockDim.x) sm[e] = make_float2(0.f, 0.f);
     __syncthreads();
     for (int e = threadIdx.x; e < N * CT; e += blockDim.x) {
@@ -138,7 +137,7 @@ __device__ __forceinline__ void colpass_fwd_tile(const PlanDev& d, const WsLayou
         red[j0 + threadIdx.x] = sc * d.h2;
     }
     __syncthreads();
-    fft_lds<kMaxB>(sm, Ng, NP, d.ffts[d.fft_grid], tw, false);
+    fft_lds<false>(sm, Ng, NP, d.ffts[d.fft_grid], tb);
     for (int e = threadIdx.x; e < d.Hy * CT; e += blockDim.x) {
         const int r = e / CT, jj = e - r * CT, j = j0 + jj;
         if (j >= N) continue;
@@ -167,7 +166,7 @@ __device__ __forceinline__ void rowpass_fwd_tile(const PlanDev& d, const WsLayou
     float2* G = (float2*)(wb + L.grid);
     const int r0 = tile * RPB;
     const int nr = min(RPB, d.Hy - r0);
-    const TwLds tw = tw_lds_build(sm + RPB * Ng, d.ffts[d.fft_grid], d.tw);
+    const float2* tb = fft_twiddles_to_lds(sm + RPB * Ng, d.ffts[d.fft_grid], d.tw);
     for (int e = threadIdx.x; e < nr * Ng; e += blockDim.x) sm[e] = make_float2(0.f, 0.f);
     __syncthreads();
     for (int e = threadIdx.x; e < nr * N; e += blockDim.x) {
@@ -177,7 +176,7 @@ __device__ __forceinline__ void rowpass_fwd_tile(const PlanDev& d, const WsLayou
         sm[rr * Ng + pos] = X1[(size_t)(r0 + rr) * N + j];
     }
     __syncthreads();
-    fft_lds<kMaxB>(sm, Ng, nr, d.ffts[d.fft_grid], tw, false);
+    fft_lds<false>(sm, Ng, nr, d.ffts[d.fft_grid], tb);
     for (int e = threadIdx.x; e < nr * Ng; e += blockDim.x) G[(size_t)r0 * Ng + e] = sm[e];
 }
 
@@ -296,10 +295,13 @@ __device__ __forceinline__ float2 real_unpack(const float2* Z, int H, int k, flo
 
 // Layout of the ring kernels' dynamic LDS (float2 slots, ring_lds_slots):
 // sa (ring FFT; the half-length synthesis buffer sc shares it), sy
-// (synthesis), and the twiddles of length Npsi(n) (twN, which also serve
-// length Npsi(n)/2), S (twA) and S/2 (twB).
+// (synthesis), and the two-level twiddles of lengths Npsi(n) (twN) and S
+// (twA) used outside the transforms.  The transforms read their per-pass
+// twiddles from the plan's table in global memory (a few KB shared by all
+// rings of a length, cache resident), which keeps the LDS per ring small
+// enough for three workgroups per CU at the largest sizes.
 struct RingLds {
-    float2 *sa, *sc, *sy, *twN, *twA, *twB;
+    float2 *sa, *sc, *sy, *twN, *twA;
 };
 
 __device__ __forceinline__ RingLds ring_lds(float2* sm, const PlanDev& d)
@@ -314,11 +316,9 @@ __device__ __forceinline__ RingLds ring_lds(float2* sm, const PlanDev& d)
     r.sy = sm + B1;
     r.twN = r.sy + B2;
     r.twA = r.twN + ring_tw_slots(d.npsi_max);
-    r.twB = r.twA + ring_tw_slots(S);
     return r;
 }
 
-template <int RB>
 __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile, int RT,
                                               float2* sm)
 {
@@ -329,15 +329,18 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
     const RingLds R = ring_lds(sm, d);
     const int n0 = tile * RT;
     const int nr = min(RT, d.nlam - n0);
-    // synthesis tables: fold with even P -> FFT of P/2 (twB) + twiddles of P (twA); else FFT of S (twA)
+    // synthesis: fold with even P -> transform of P/2 + twiddles of P (twA); else transform of S
     const TwLds twA = tw_lds_build(R.twA, d.ffts[d.fft_syn], d.tw);
-    const TwLds twB = d.syn_half ? tw_lds_build(R.twB, d.ffts[d.fft_synh], d.tw) : twA;
+    const FftDev& fS = d.ffts[d.fft_synh];
+    const float2* __restrict__ tbS = d.tw + fS.tb;
     for (int r = 0; r < nr; ++r) {
         const int n = n0 + r;
         const int off = d.ring_off[n], P = d.ring_off[n + 1] - off;
         const int Kn = d.ring_K[n];
         const float2* __restrict__ cf = d.coef + d.ring_joff[n];
         float* hn = hT + (size_t)n * D;
+        const FftDev& fR = d.ffts[d.ring_fft[n]];
+        const float2* __restrict__ tbR = d.tw + fR.tb;
         // this thread's modes k = tid + j bd: coefficients fetched before the FFT
         float2 cpre[kRingModesPerThread];
 #pragma unroll
@@ -346,7 +349,6 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
             cpre[j] = k <= Kn ? cf[k] : make_float2(0.f, 0.f);
         }
         const TwLds twN = tw_lds_build(R.twN, d.ffts[d.ring_twn[n]], d.tw);  // w_{2P}^k
-        const TwLds twP{twN.lo, twN.hi, 1};                                   // w_P^k = w_{2P}^{2k}
         // q(m) = Re F + Im F (m < P), Re F - Im F (m >= P) is real; pack z(t) = q(2t) + i q(2t+1)
         for (int t = tid; t < P; t += bd) {
             float qv[2];
@@ -360,7 +362,7 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
             R.sa[t] = make_float2(qv[0], qv[1]);
         }
         __syncthreads();
-        fft_lds<RB>(R.sa, P, 1, d.ffts[d.ring_fft[n]], twP, false);
+        fft_lds<false, kRingFftMaxButterflies>(R.sa, P, 1, fR, tbR);
         // y = the a_k = coef_k Q_k (Q: the real length-2P transform of q) folded
         // mod Pf (fold) or zero-padded to S (chirp-z), summed in order of k: pass
         // 0 writes k < Pf, each further pass adds the next Pf modes
@@ -393,7 +395,7 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
                     R.sc[sidx] = make_float2(E.x - O.y, E.y + O.x);    // E + i O
                 }
                 __syncthreads();
-                fft_lds<RB>(R.sc, H2, 1, d.ffts[d.fft_synh], twB, true);
+                fft_lds<true, kRingFftMaxButterflies>(R.sc, H2, 1, fS, tbS);
                 // detector q is point s q of the P-point grid
                 for (int q = tid; q < D; q += bd) {
                     const int j = q * d.fold_s;
@@ -401,14 +403,14 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
                     hn[q] = (j & 1) ? z.y : z.x;
                 }
             } else {
-                fft_lds<RB>(R.sy, Pf, 1, d.ffts[d.fft_syn], twA, true);
+                fft_lds<true, kRingFftMaxButterflies>(R.sy, Pf, 1, fS, tbS);
                 for (int q = tid; q < D; q += bd) hn[q] = R.sy[q * d.fold_s].x;
             }
         } else {
-            fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, false);
+            fft_lds<false, kRingFftMaxButterflies>(R.sy, S, 1, fS, tbS);
             for (int q = tid; q < S; q += bd) R.sy[q] = cmul(R.sy[q], d.czt_vhat[q]);
             __syncthreads();
-            fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, true);
+            fft_lds<true, kRingFftMaxButterflies>(R.sy, S, 1, fS, tbS);
             for (int q = tid; q < D; q += bd) {
                 const float2 v = R.sy[q], w = d.czt_post[q];
                 hn[q] = w.x * v.x - w.y * v.y;
@@ -426,7 +428,6 @@ __device__ __forceinline__ float grid_det(const float* hn, int j, int s, int D)
     return (q * s == j && q < D) ? hn[q] : 0.f;
 }
 
-template <int RB>
 __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile, int RT,
                                               float2* sm)
 {
@@ -442,13 +443,16 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
     float2* const qb = half ? R.sy : R.sa;
     float2* const eb = half ? R.sa : R.sy;
     const TwLds twA = tw_lds_build(R.twA, d.ffts[d.fft_syn], d.tw);
-    const TwLds twB = d.syn_half ? tw_lds_build(R.twB, d.ffts[d.fft_synh], d.tw) : twA;
+    const FftDev& fS = d.ffts[d.fft_synh];
+    const float2* __restrict__ tbS = d.tw + fS.tb;
     for (int r = 0; r < nr; ++r) {
         const int n = n0 + r;
         const int off = d.ring_off[n], P = d.ring_off[n + 1] - off;
         const int Kn = d.ring_K[n];
         const float2* __restrict__ cf = d.coef + d.ring_joff[n];
         const float* hn = hT + (size_t)n * D;
+        const FftDev& fR = d.ffts[d.ring_fft[n]];
+        const float2* __restrict__ tbR = d.tw + fR.tb;
         float2 cpre[kRingModesPerThread];
 #pragma unroll
         for (int j = 0; j < kRingModesPerThread; ++j) {
@@ -456,27 +460,26 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
             cpre[j] = k <= Kn ? cf[k] : make_float2(0.f, 0.f);
         }
         const TwLds twN = tw_lds_build(R.twN, d.ffts[d.ring_twn[n]], d.tw);
-        const TwLds twP{twN.lo, twN.hi, 1};
         // y~ = FFT of the real detector values, zero-padded to the synthesis length
         if (half) {
             const int H2 = d.fold_P / 2;
             for (int t = tid; t < H2; t += bd)
                 R.sc[t] = make_float2(grid_det(hn, 2 * t, d.fold_s, D), grid_det(hn, 2 * t + 1, d.fold_s, D));
             __syncthreads();
-            fft_lds<RB>(R.sc, H2, 1, d.ffts[d.fft_synh], twB, false);
+            fft_lds<false, kRingFftMaxButterflies>(R.sc, H2, 1, fS, tbS);
         } else if (d.fold_P) {
             for (int sidx = tid; sidx < S; sidx += bd)
                 R.sy[sidx] = make_float2(grid_det(hn, sidx, d.fold_s, D), 0.f);
             __syncthreads();
-            fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, false);
+            fft_lds<false, kRingFftMaxButterflies>(R.sy, S, 1, fS, tbS);
         } else {
             for (int q = tid; q < S; q += bd)
                 R.sy[q] = q < D ? cmulc(make_float2(hn[q], 0.f), d.czt_post[q]) : make_float2(0.f, 0.f);
             __syncthreads();
-            fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, false);
+            fft_lds<false, kRingFftMaxButterflies>(R.sy, S, 1, fS, tbS);
             for (int q = tid; q < S; q += bd) R.sy[q] = cmulc(R.sy[q], d.czt_vhat[q]);
             __syncthreads();
-            fft_lds<RB>(R.sy, S, 1, d.ffts[d.fft_syn], twA, true);
+            fft_lds<true, kRingFftMaxButterflies>(R.sy, S, 1, fS, tbS);
         }
         // y~ at synthesis index sidx (0 <= sidx < S)
         auto ytil = [&](int sidx) {
@@ -514,7 +517,7 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
             eb[sidx] = make_float2(E.x - O.y, E.y + O.x);
         }
         __syncthreads();
-        fft_lds<RB>(eb, P, 1, d.ffts[d.ring_fft[n]], twP, true);
+        fft_lds<true, kRingFftMaxButterflies>(eb, P, 1, fR, tbR);
         // q~(m): m = 2t -> Re z_t, m = 2t + 1 -> Im z_t;  F~_h(l) = (q~(l) + q~(l+P)) + i (q~(l) - q~(l+P))
         for (int l = tid; l < P; l += bd) {
             const float2 z1 = eb[l >> 1];
@@ -553,7 +556,7 @@ __device__ __forceinline__ void dct_tile(const PlanDev& d, const WsLayout& L, ch
         const float m = wave0_fixed_sum(red, n_mass);
         if (threadIdx.x == 0) *mass_s = m;
     }
-    const TwLds tw = tw_lds_build(sm + DP * twoM, d.ffts[d.fft_dct], d.tw);
+    const float2* tb = fft_twiddles_to_lds(sm + DP * twoM, d.ffts[d.fft_dct], d.tw);
     for (int e = threadIdx.x; e < np * twoM; e += blockDim.x) sm[e] = make_float2(0.f, 0.f);
     __syncthreads();
     if (adj) {  // g [D][T]: contiguous along t
@@ -593,7 +596,7 @@ __device__ __forceinline__ void dct_tile(const PlanDev& d, const WsLayout& L, ch
         }
     }
     __syncthreads();
-    fft_lds<kMaxB>(sm, twoM, np, d.ffts[d.fft_dct], tw, false);
+    fft_lds<false>(sm, twoM, np, d.ffts[d.fft_dct], tb);
     const float add = adj ? 0.f : d.kappa * *mass_s;
     if (adj) {  // -> hT [nlam][D]
         for (int e = threadIdx.x; e < np * nout; e += blockDim.x) {
@@ -876,10 +879,10 @@ __device__ __forceinline__ void rowpass_adj_tile(const PlanDev& d, const WsLayou
     float2* X1 = (float2*)(wb + L.x1);
     const int r0 = tile * RPB;
     const int nr = min(RPB, d.Hy - r0);
-    const TwLds tw = tw_lds_build(sm + RPB * Ng, d.ffts[d.fft_grid], d.tw);
+    const float2* tb = fft_twiddles_to_lds(sm + RPB * Ng, d.ffts[d.fft_grid], d.tw);
     for (int e = threadIdx.x; e < nr * Ng; e += blockDim.x) sm[e] = Gt[(size_t)r0 * Ng + e];
     __syncthreads();
-    fft_lds<kMaxB>(sm, Ng, nr, d.ffts[d.fft_grid], tw, true);
+    fft_lds<true>(sm, Ng, nr, d.ffts[d.fft_grid], tb);
     for (int e = threadIdx.x; e < nr * N; e += blockDim.x) {
         const int rr = e / N, j = e - rr * N;
         int pos = j - N / 2;
@@ -904,7 +907,7 @@ __device__ __forceinline__ void colpass_adj_tile(const PlanDev& d, const WsLayou
     }
     const int j0 = tile * CT;
     const int top = Ng / 2 + 4;
-    const TwLds tw = tw_lds_build(sm + NP * Ng, d.ffts[d.fft_grid], d.tw);
+    const float2* tb = fft_twiddles_to_lds(sm + NP * Ng, d.ffts[d.fft_grid], d.tw);
     for (int e = threadIdx.x; e < NP * Ng; e += blockDim.x) {
         const int p = e / Ng, q = e - p * Ng;
         const int ja = j0 + 2 * p, jb = ja + 1;
@@ -927,7 +930,7 @@ __device__ __forceinline__ void colpass_adj_tile(const PlanDev& d, const WsLayou
         sm[e] = make_float2(ha.x - hb.y, ha.y + hb.x);
     }
     __syncthreads();
-    fft_lds<kMaxB>(sm, Ng, NP, d.ffts[d.fft_grid], tw, true);
+    fft_lds<true>(sm, Ng, NP, d.ffts[d.fft_grid], tb);
     const float kt = d.kappa * d.h2 * *gsum_s;
     for (int e = threadIdx.x; e < N * CT; e += blockDim.x) {
         const int i = e / CT, jj = e - i * CT, j = j0 + jj;
@@ -1039,7 +1042,6 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_b(BatchDev bt, char* 
 // adjoint is held to 128 VGPRs (four waves per SIMD) where it does not spill;
 // the forward needs more registers for its coefficient prefetch and runs best
 // unconstrained (three waves per SIMD, no spills).
-template <int RB>
 __global__ __launch_bounds__(kRingMaxThreads) void k_ring_fwd(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
 {
     extern __shared__ float2 sm[];
@@ -1047,10 +1049,9 @@ __global__ __launch_bounds__(kRingMaxThreads) void k_ring_fwd(PlanDev d, WsLayou
     const int item = xcd_item(blockIdx.x, ntile * batch);
     if (item < 0) return;
     const int b = item / ntile;
-    ring_fwd_tile<RB>(d, L, wsp.ws + (size_t)b * wsp.stride, item - b * ntile, RT, sm);
+    ring_fwd_tile(d, L, wsp.ws + (size_t)b * wsp.stride, item - b * ntile, RT, sm);
 }
 
-template <int RB>
 __global__ __launch_bounds__(kRingMaxThreads) void k_ring_fwd_b(BatchDev bt, char* ws)
 {
     extern __shared__ float2 sm[];
@@ -1058,10 +1059,9 @@ __global__ __launch_bounds__(kRingMaxThreads) void k_ring_fwd_b(BatchDev bt, cha
     if (!batch_item(bt, kStRing, i, tile)) return;
     const BatchInst& I = bt.inst[i];
     const PlanDev d = I.d;
-    ring_fwd_tile<RB>(d, I.L, ws + I.ws_off, tile, I.ring_rt, sm);
+    ring_fwd_tile(d, I.L, ws + I.ws_off, tile, I.ring_rt, sm);
 }
 
-template <int RB>
 __global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_ring_adj(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
 {
     extern __shared__ float2 sm[];
@@ -1069,10 +1069,9 @@ __global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu
     const int item = xcd_item(blockIdx.x, ntile * batch);
     if (item < 0) return;
     const int b = item / ntile;
-    ring_adj_tile<RB>(d, L, wsp.ws + (size_t)b * wsp.stride, item - b * ntile, RT, sm);
+    ring_adj_tile(d, L, wsp.ws + (size_t)b * wsp.stride, item - b * ntile, RT, sm);
 }
 
-template <int RB>
 __global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_ring_adj_b(BatchDev bt, char* ws)
 {
     extern __shared__ float2 sm[];
@@ -1080,7 +1079,7 @@ __global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu
     if (!batch_item(bt, kStRing, i, tile)) return;
     const BatchInst& I = bt.inst[i];
     const PlanDev d = I.d;
-    ring_adj_tile<RB>(d, I.L, ws + I.ws_off, tile, I.ring_rt, sm);
+    ring_adj_tile(d, I.L, ws + I.ws_off, tile, I.ring_rt, sm);
 }
 
 __global__ __launch_bounds__(1024) void k_dct_det(PlanDev d, WsLayout L, InstPtrs wsp, float* __restrict__ gout,

@@ -19,16 +19,41 @@ namespace pat {
 constexpr int kEsWidth = 8;
 constexpr double kEsBeta = 2.30 * kEsWidth;
 
-constexpr int kMaxStages = 24;
+constexpr int kMaxStages = 16;
 
-// One complex FFT length n = 2^a 3^b: Stockham stages of radix 4, 2 or 3.
+// One complex FFT length n = 2^a 3^b: Stockham passes of radix 2, 3, 4, 6, 8, 9 or 16.
 struct FftDev {
     int n;
-    int nst;
+    int nst;                       // number of passes
     int tw;                        // offset of this length's twiddles e^{-2 pi i e/n}, e = 0..n-1
-    int pad;
-    unsigned char rad[kMaxStages];
+    int tb;                        // offset of the per-pass base twiddles e^{-2 pi i k/(Ns R)}, k < Ns
+    int ntb;                       // their count: the sum of the passes' Ns
+    int pad[3];
+    unsigned char rad[kMaxStages]; // radix of each pass
 };
+
+// Butterflies one thread holds in a pass of radix R: at most 32 complex values
+// and at most `maxb` butterflies (kFftMaxButterflies for the fixed-length
+// transforms, kRingFftMaxButterflies in the ring kernels, whose other live
+// state leaves fewer registers).
+constexpr int kFftMaxButterflies = 4;
+constexpr int kRingFftMaxButterflies = 2;
+__host__ __device__ constexpr int radix_max_butterflies(int R, int maxb = kFftMaxButterflies)
+{
+    return (R <= 4 ? 4 : (R <= 9 ? 2 : 1)) < maxb ? (R <= 4 ? 4 : (R <= 9 ? 2 : 1)) : maxb;
+}
+
+// Threads per sequence the passes of `d` need (at most `maxb` butterflies per thread).
+__host__ __device__ inline int fft_min_tps(const FftDev& d, int maxb = kFftMaxButterflies)
+{
+    int t = 1;
+    for (int s = 0; s < d.nst; ++s) {
+        const int R = d.rad[s], per = radix_max_butterflies(R, maxb);
+        const int need = (d.n / R + per - 1) / per;
+        t = need > t ? need : t;
+    }
+    return t;
+}
 
 struct PlanDev {
     // sizes
@@ -121,13 +146,14 @@ __host__ __device__ constexpr size_t spread_lds_words(int CAP, int IB)
 constexpr int kRingModesPerThread = 8;
 constexpr int kRingMaxThreads = 256;
 // Their LDS in float2 slots: ring buffer (aliased by the half-length
-// synthesis buffer), synthesis buffer, three twiddle tables.
+// synthesis buffer), synthesis buffer, two-level twiddle tables of lengths
+// Npsi_max and S.
 __host__ __device__ constexpr int ring_tw_slots(int n) { return 64 + (n + 63) / 64; }
 __host__ __device__ constexpr size_t ring_lds_slots(int npsi_max, int S, int syn_half)
 {
     return (size_t)((npsi_max / 2 > (syn_half ? S / 2 : 0)) ? npsi_max / 2 : S / 2) +
            (size_t)(S > npsi_max / 2 ? S : npsi_max / 2) + (size_t)ring_tw_slots(npsi_max) +
-           2 * (size_t)ring_tw_slots(S);
+           (size_t)ring_tw_slots(S);
 }
 
 // Tile-shape limits of the interpolation and the spread.
@@ -210,7 +236,6 @@ struct pat_plan {
     int n_col_tiles;        // column-pass tiles (mass partials)
     int n_pair_tiles;       // cosine-transform tiles (data-sum partials)
     int thr_col, thr_row, thr_ring, thr_dct;  // workgroup sizes of the FFT kernels
-    int ring_mb;            // butterflies per thread per stage in the ring kernels
     size_t lds_ring;        // dynamic LDS of the ring kernels
     // optional per-kernel timing (pat_profile_enable): events around each launch
     int prof;

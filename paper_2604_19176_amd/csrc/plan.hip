@@ -31,8 +31,9 @@ long smooth23(double x, int multiple_of)
     return best;
 }
 
-// Radix plan for n = 2^a 3^b: radix-8 stages, then 4 x 4 / 4 / 2 for the rest of
-// the power of two (a radix-2 stage only when a = 1), then radix-3 stages.
+// Radix plan of the host's FP64 FFT (chirp-z filter spectrum) for n = 2^a 3^b:
+// radix-8 stages, then 4 x 4 / 4 / 2 for the rest of the power of two (a
+// radix-2 stage only when a = 1), then radix-3 stages.
 static int radix_plan(long n, unsigned char* rad)
 {
     int a = 0;
@@ -48,7 +49,7 @@ static int radix_plan(long n, unsigned char* rad)
     return n == 1 ? ns : -1;
 }
 
-// FP64 Stockham FFT on the host (same decomposition as the device FFT), sign -1.
+// FP64 Stockham FFT on the host, sign -1.
 static void host_fft(std::vector<cd>& x)
 {
     const long n = (long)x.size();
@@ -228,23 +229,209 @@ struct TableBuilder {
     size_t add(const std::vector<T>& v) { return add(v.data(), v.size() * sizeof(T)); }
 };
 
+// Pass plans of the device FFT (fft.hpp) for length n at `tps` threads per
+// sequence, each thread holding at most `maxb` butterflies per pass.
+//
+// kFftMeasured holds the fastest plan measured on an MI355X (gfx950) for
+// every length 2^a 3^b the transforms use: all plans (every multiset of
+// radices {2, 3, 4, 6, 8, 9, 16} in both orders) timed in a one-workgroup-per-
+// sequence kernel, for the ring kernels (maxb 2) at 64, 128 and 256 threads
+// and for the fixed-length transforms (maxb 4) at their thread counts.
+// Lengths outside the table use a cost model fitted to the same measurements:
+// per pass, the rounds of butterflies times a per-radix cost, the LDS bank
+// multiplicity of the pass's stores, the division k = j mod Ns when Ns is not
+// a power of two, and a fixed cost per pass; every ordering of every multiset
+// (at most two radix-16 passes) is ranked.
+struct FftMeasured {
+    short n, tps;
+    unsigned char maxb;
+    unsigned char rad[6];
+};
+static const FftMeasured kFftMeasured[] = {
+    {8, 64, 2, {8}}, {9, 64, 2, {9}}, {12, 64, 2, {6, 2}}, {16, 64, 2, {4, 4}}, {18, 64, 2, {6, 3}},
+    {24, 64, 2, {8, 3}}, {27, 64, 2, {9, 3}}, {32, 64, 2, {8, 4}}, {36, 64, 2, {6, 6}}, {48, 64, 2, {8, 6}},
+    {54, 64, 2, {9, 6}}, {64, 64, 2, {8, 8}}, {72, 64, 2, {9, 8}}, {81, 64, 2, {9, 9}},
+    {96, 64, 2, {4, 4, 6}}, {108, 64, 2, {6, 6, 3}}, {128, 64, 2, {8, 4, 4}}, {144, 64, 2, {8, 3, 6}},
+    {162, 64, 2, {9, 6, 3}}, {192, 64, 2, {6, 8, 4}}, {216, 64, 2, {6, 6, 6}}, {243, 64, 2, {9, 9, 3}},
+    {256, 64, 2, {4, 4, 4, 4}}, {288, 64, 2, {6, 6, 8}}, {324, 64, 2, {9, 6, 6}}, {384, 64, 2, {6, 8, 8}},
+    {432, 64, 2, {9, 6, 8}}, {486, 64, 2, {6, 9, 9}}, {512, 64, 2, {8, 8, 8}}, {576, 64, 2, {9, 8, 8}},
+    {648, 64, 2, {9, 9, 8}}, {729, 64, 2, {9, 9, 9}}, {768, 64, 2, {6, 16, 8}}, {1024, 64, 2, {8, 8, 16}},
+    {8, 128, 2, {8}}, {9, 128, 2, {9}}, {12, 128, 2, {4, 3}}, {16, 128, 2, {16}}, {18, 128, 2, {6, 3}},
+    {24, 128, 2, {8, 3}}, {27, 128, 2, {9, 3}}, {32, 128, 2, {8, 4}}, {36, 128, 2, {6, 6}},
+    {48, 128, 2, {8, 6}}, {54, 128, 2, {9, 6}}, {64, 128, 2, {8, 8}}, {72, 128, 2, {8, 9}},
+    {81, 128, 2, {9, 9}}, {96, 128, 2, {16, 6}}, {108, 128, 2, {6, 6, 3}}, {128, 128, 2, {8, 4, 4}},
+    {144, 128, 2, {8, 3, 6}}, {162, 128, 2, {9, 6, 3}}, {192, 128, 2, {8, 8, 3}}, {216, 128, 2, {6, 6, 6}},
+    {243, 128, 2, {9, 9, 3}}, {256, 128, 2, {8, 8, 4}}, {288, 128, 2, {8, 6, 6}}, {324, 128, 2, {9, 6, 6}},
+    {384, 128, 2, {6, 8, 8}}, {432, 128, 2, {9, 6, 8}}, {486, 128, 2, {9, 9, 6}}, {512, 128, 2, {8, 8, 8}},
+    {576, 128, 2, {9, 8, 8}}, {648, 128, 2, {9, 9, 8}}, {729, 128, 2, {9, 9, 9}}, {768, 128, 2, {6, 16, 8}},
+    {864, 128, 2, {9, 6, 16}}, {1024, 128, 2, {8, 8, 16}}, {1152, 128, 2, {9, 16, 8}},
+    {1296, 128, 2, {9, 9, 16}}, {1536, 128, 2, {6, 16, 16}}, {2048, 128, 2, {8, 16, 16}}, {8, 256, 2, {8}},
+    {9, 256, 2, {9}}, {12, 256, 2, {6, 2}}, {16, 256, 2, {16}}, {18, 256, 2, {6, 3}}, {24, 256, 2, {8, 3}},
+    {27, 256, 2, {9, 3}}, {32, 256, 2, {8, 4}}, {36, 256, 2, {6, 6}}, {48, 256, 2, {8, 6}},
+    {54, 256, 2, {9, 6}}, {64, 256, 2, {8, 8}}, {72, 256, 2, {8, 9}}, {81, 256, 2, {9, 9}},
+    {96, 256, 2, {16, 6}}, {108, 256, 2, {6, 6, 3}}, {128, 256, 2, {16, 8}}, {144, 256, 2, {8, 3, 6}},
+    {162, 256, 2, {9, 6, 3}}, {192, 256, 2, {8, 8, 3}}, {216, 256, 2, {9, 6, 4}}, {243, 256, 2, {9, 9, 3}},
+    {256, 256, 2, {8, 8, 4}}, {288, 256, 2, {8, 6, 6}}, {324, 256, 2, {9, 6, 6}}, {384, 256, 2, {8, 8, 6}},
+    {432, 256, 2, {8, 6, 9}}, {486, 256, 2, {9, 9, 6}}, {512, 256, 2, {8, 8, 8}}, {576, 256, 2, {9, 8, 8}},
+    {648, 256, 2, {9, 9, 8}}, {729, 256, 2, {9, 9, 9}}, {768, 256, 2, {6, 16, 8}}, {864, 256, 2, {9, 6, 16}},
+    {972, 256, 2, {9, 6, 6, 3}}, {1024, 256, 2, {4, 4, 8, 8}}, {1152, 256, 2, {9, 16, 8}},
+    {1296, 256, 2, {6, 6, 6, 6}}, {1458, 256, 2, {9, 9, 6, 3}}, {1536, 256, 2, {3, 8, 8, 8}},
+    {1728, 256, 2, {9, 6, 8, 4}}, {1944, 256, 2, {9, 9, 6, 4}}, {2048, 256, 2, {4, 8, 8, 8}},
+    {2304, 256, 2, {9, 16, 16}}, {2592, 256, 2, {9, 6, 6, 8}}, {2916, 256, 2, {9, 9, 6, 6}},
+    {3072, 256, 2, {6, 8, 8, 8}}, {4096, 256, 2, {8, 8, 8, 8}}, {32, 32, 4, {8, 4}}, {36, 32, 4, {6, 6}},
+    {48, 32, 4, {6, 8}}, {54, 32, 4, {9, 6}}, {64, 32, 4, {8, 8}}, {72, 32, 4, {6, 3, 4}},
+    {96, 32, 4, {6, 4, 4}}, {108, 32, 4, {6, 6, 3}}, {128, 32, 4, {4, 4, 8}}, {144, 32, 4, {6, 6, 4}},
+    {162, 32, 4, {9, 6, 3}}, {192, 32, 4, {6, 8, 4}}, {216, 32, 4, {9, 3, 8}}, {256, 32, 4, {4, 8, 8}},
+    {288, 32, 4, {9, 8, 4}}, {324, 32, 4, {9, 6, 6}}, {384, 32, 4, {6, 16, 4}}, {512, 32, 4, {4, 8, 16}},
+    {432, 64, 4, {9, 6, 8}}, {486, 64, 4, {6, 9, 9}}, {576, 64, 4, {9, 16, 4}}, {648, 64, 4, {3, 6, 6, 6}},
+    {768, 64, 4, {6, 16, 8}}, {1024, 64, 4, {4, 16, 16}}, {864, 96, 4, {9, 6, 16}},
+    {972, 96, 4, {9, 6, 6, 3}}, {1152, 96, 4, {9, 16, 8}}, {1296, 96, 4, {9, 9, 16}},
+    {1458, 128, 4, {9, 9, 6, 3}}, {1536, 128, 4, {6, 16, 16}}, {2048, 128, 4, {8, 16, 16}},
+    {1728, 160, 4, {6, 6, 6, 8}}, {2304, 160, 4, {9, 16, 16}}, {1944, 192, 4, {9, 6, 6, 6}},
+    {2592, 192, 4, {9, 9, 8, 4}}, {2916, 192, 4, {9, 9, 9, 4}}, {3072, 256, 4, {6, 8, 8, 8}},
+    {4096, 256, 4, {4, 8, 8, 16}}, {3456, 288, 4, {6, 6, 6, 16}}, {4608, 288, 4, {9, 8, 8, 8}},
+    {3888, 352, 4, {9, 9, 3, 16}}, {5184, 352, 4, {9, 9, 8, 8}}, {4374, 384, 4, {6, 9, 9, 9}},
+    {5832, 384, 4, {9, 9, 9, 8}}, {6144, 512, 4, {6, 16, 8, 8}}, {8192, 512, 4, {4, 8, 16, 16}},
+    {6912, 576, 4, {9, 6, 16, 8}}, {7776, 672, 4, {9, 9, 6, 16}},
+};
+
+static double fft_radix_cost(int R)
+{
+    switch (R) {
+        case 2: return 0.0408;
+        case 3: return 0.0665;
+        case 4: return 0.1071;
+        case 6: return 0.1386;
+        case 8: return 0.1963;
+        case 9: return 0.2150;
+        default: return 0.3514;
+    }
+}
+
+// Model cost of the pass order `rad` (or a negative value if it does not fit
+// tps threads holding at most maxb butterflies each)
+static double fft_plan_cost(long n, int tps, int maxb, const std::vector<int>& rad)
+{
+    double c = 0.0;
+    long Ns = 1;
+    for (int R : rad) {
+        const long rounds = (n / R + tps - 1) / tps;
+        if (rounds > radix_max_butterflies(R, maxb)) return -1.0;
+        int conf = 0;  // max stores per float2 bank slot (32 slots) in a half wave, summed over outputs r
+        for (int r = 0; r < R; ++r) {
+            int cnt[32] = {0}, mx = 0;
+            for (long j = 0; j < std::min<long>(32, n / R); ++j) {
+                const long a = (j / Ns) * Ns * R + j % Ns + r * Ns;
+                mx = std::max(mx, ++cnt[a & 31]);
+            }
+            conf += mx;
+        }
+        c += rounds * (fft_radix_cost(R) + 0.0033 * conf + ((Ns & (Ns - 1)) ? 0.0086 : 0.0)) + 0.0731;
+        Ns *= R;
+    }
+    return c;
+}
+
+// Passes of length n at tps threads per sequence, each holding at most maxb
+// butterflies, into rad; returns their number or -1.
+int fft_passes(long n, int tps, int maxb, unsigned char* rad)
+{
+    for (const FftMeasured& m : kFftMeasured)
+        if (m.n == n && m.tps == tps && m.maxb == maxb) {
+            std::vector<int> p;
+            for (int i = 0; i < 6 && m.rad[i]; ++i) p.push_back(m.rad[i]);
+            if (fft_plan_cost(n, tps, maxb, p) < 0.0) break;  // measured at more butterflies per thread
+            for (size_t i = 0; i < p.size(); ++i) rad[i] = (unsigned char)p[i];
+            return (int)p.size();
+        }
+    int a = 0, b = 0;
+    long m = n;
+    while (m % 2 == 0) { ++a; m /= 2; }
+    while (m % 3 == 0) { ++b; m /= 3; }
+    if (m != 1 || n < 2) return -1;
+    double best = -1.0;
+    std::vector<int> bestp;
+    for (int c6 = 0; c6 <= std::min(a, b); ++c6)
+        for (int c9 = 0; c9 <= (b - c6) / 2; ++c9) {
+            const int c3 = b - c6 - 2 * c9, ap = a - c6;
+            for (int c16 = 0; c16 <= std::min(2, ap / 4); ++c16)
+                for (int c8 = 0; c8 <= (ap - 4 * c16) / 3; ++c8)
+                    for (int c4 = 0; c4 <= (ap - 4 * c16 - 3 * c8) / 2; ++c4) {
+                        const int c2 = ap - 4 * c16 - 3 * c8 - 2 * c4;
+                        std::vector<int> p;
+                        p.insert(p.end(), c2, 2);
+                        p.insert(p.end(), c3, 3);
+                        p.insert(p.end(), c4, 4);
+                        p.insert(p.end(), c6, 6);
+                        p.insert(p.end(), c8, 8);
+                        p.insert(p.end(), c9, 9);
+                        p.insert(p.end(), c16, 16);
+                        if (p.size() > 10) continue;
+                        do {
+                            const double c = fft_plan_cost(n, tps, maxb, p);
+                            if (c >= 0.0 && (best < 0.0 || c < best)) { best = c; bestp = p; }
+                        } while (std::next_permutation(p.begin(), p.end()));
+                    }
+        }
+    if (best < 0.0 || (int)bestp.size() > kMaxStages) return -1;
+    for (size_t i = 0; i < bestp.size(); ++i) rad[i] = (unsigned char)bestp[i];
+    return (int)bestp.size();
+}
+
+// Threads per sequence the fixed-length transforms (grid, cosine) are planned
+// for: the smallest multiple of 32, from n/16 up (one radix-16 or two radix-8
+// butterflies per thread and pass), for which a pass plan fits; 0 if none does.
+static int fixed_fft_tps(long n)
+{
+    unsigned char rad[kMaxStages];
+    for (long t = std::max<long>(32, ((n + 15) / 16 + 31) / 32 * 32); t <= 1024; t += 32)
+        if (fft_passes(n, (int)t, kFftMaxButterflies, rad) >= 0) return (int)t;
+    return 0;
+}
+
 struct FftSet {
     std::vector<FftDev> descs;
+    std::vector<int> key_tps;
     std::vector<float2> tw;
-    int get(long n)
+    // descriptor of length n planned for tps threads per sequence holding at
+    // most maxb butterflies each (tps = 0: only the twiddle table
+    // e^{-2 pi i e/n}, no transform); -1 if no plan fits
+    int get(long n, int tps, int maxb = kFftMaxButterflies)
     {
-        for (size_t i = 0; i < descs.size(); ++i)
-            if (descs[i].n == n) return (int)i;
+        int full = -1;
+        for (size_t i = 0; i < descs.size(); ++i) {
+            if (descs[i].n != n) continue;
+            if (key_tps[i] == tps * 16 + maxb) return (int)i;
+            full = descs[i].tw;
+        }
         FftDev d;
         std::memset(&d, 0, sizeof(d));
         d.n = (int)n;
-        d.nst = radix_plan(n, d.rad);
-        d.tw = (int)tw.size();
-        for (long e = 0; e < n; ++e) {
-            double a = -2.0 * PI * (double)e / (double)n;
-            tw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+        if (tps > 0) {
+            d.nst = fft_passes(n, tps, maxb, d.rad);
+            if (d.nst < 0) return -1;
+        }
+        if (full < 0) {
+            full = (int)tw.size();
+            for (long e = 0; e < n; ++e) {
+                double a = -2.0 * PI * (double)e / (double)n;
+                tw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+            }
+        }
+        d.tw = full;
+        d.tb = (int)tw.size();
+        long Ns = 1;
+        for (int s = 0; s < d.nst; ++s) {
+            const long R = d.rad[s];
+            for (long k = 0; k < Ns; ++k) {
+                double a = -2.0 * PI * (double)k / (double)(Ns * R);
+                tw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+            }
+            d.ntb += (int)Ns;
+            Ns *= R;
         }
         descs.push_back(d);
+        key_tps.push_back(tps * 16 + maxb);
         return (int)descs.size() - 1;
     }
 };
@@ -255,17 +442,18 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 namespace pat {
 
-// Threads for `nseq` sequences of one length: tps per sequence (4 butterflies
-// per thread per stage, rounded to 32); at least 128 threads in total.
+// Threads for `nseq` sequences of one length: tps per sequence (what the
+// passes need, rounded to 32); at least 128 threads in total.
 static int fft_threads(int nseq, const FftDev& fd)
 {
-    int tps = fft_min_tps(fd, 4);
+    int tps = fft_min_tps(fd);
     tps = ((tps + 31) / 32) * 32;
     while (nseq * tps < 128) tps += 32;
     return nseq * tps;
 }
 
-static size_t twb_bytes(int n) { return sizeof(float2) * (size_t)tw_lds_slots(n); }
+// LDS of a length's per-pass twiddles
+static size_t twb_bytes(const FftDev& f) { return sizeof(float2) * (size_t)f.ntb; }
 
 // Dynamic LDS of the ring kernels: half-ring FFT buffer, synthesis buffers,
 // [D][RT] detector tile and four twiddle tables.
@@ -291,9 +479,9 @@ int apply_launch(pat_plan* p, const LaunchCfg& c)
         c.ring_rt < 1 || c.ring_rt > 64 || !gather_shape_ok(c.gat_cb, c.gat_th, c.gat_ib) ||
         !spread_shape_ok(c.spr_cb, c.spr_th, c.spr_ib))
         return PAT_ERR_ARG;
-    if (!fft_ok(c.col_np, sizeof(float2) * d.Ng, p->h_fft_grid, twb_bytes(d.Ng)) ||
-        !fft_ok(c.row_rpb, sizeof(float2) * d.Ng, p->h_fft_grid, twb_bytes(d.Ng)) ||
-        !fft_ok(c.dct_dp, sizeof(float2) * 2 * d.M, p->h_fft_dct, twb_bytes(2 * d.M)))
+    if (!fft_ok(c.col_np, sizeof(float2) * d.Ng, p->h_fft_grid, twb_bytes(p->h_fft_grid)) ||
+        !fft_ok(c.row_rpb, sizeof(float2) * d.Ng, p->h_fft_grid, twb_bytes(p->h_fft_grid)) ||
+        !fft_ok(c.dct_dp, sizeof(float2) * 2 * d.M, p->h_fft_dct, twb_bytes(p->h_fft_dct)))
         return PAT_ERR_UNSUPPORTED;
     const size_t lr = ring_lds_bytes(d, c.ring_rt);
     if (lr > kLdsMax) return PAT_ERR_UNSUPPORTED;
@@ -311,8 +499,7 @@ int apply_launch(pat_plan* p, const LaunchCfg& c)
 // Default launch shapes: FFT tiles of <= 64 KB of LDS where possible (several
 // workgroups per CU; a single sequence may use up to 160 KB), interpolation
 // and spread tiles sized for `max_batch` instances.
-int choose_launch(pat_plan* p, const std::vector<FftDev>& fd, int max_batch,
-                  const std::vector<const FftDev*>& ring_descs)
+int choose_launch(pat_plan* p, const std::vector<FftDev>& fd, int max_batch)
 {
     const PlanDev& d = p->dev;
     LaunchCfg c{};
@@ -322,15 +509,15 @@ int choose_launch(pat_plan* p, const std::vector<FftDev>& fd, int max_batch,
     const FftDev& fg = p->h_fft_grid;
     const FftDev& fm = p->h_fft_dct;
     auto pick = [&](int maxn, size_t bytes_each, const FftDev& f, size_t fixed) {
-        const int tps = (fft_min_tps(f, 4) + 31) / 32 * 32;
+        const int tps = (fft_min_tps(f) + 31) / 32 * 32;
         int v = maxn;
         while (v > 1 && (v * bytes_each + fixed > kLds || v * tps > 1024)) --v;
         if (v * bytes_each + fixed <= kLds && v * tps <= 1024) return v;
         return (bytes_each + fixed <= kLdsMax && tps <= 1024) ? 1 : 0;
     };
-    c.col_np = pick(8, sizeof(float2) * d.Ng, fg, twb_bytes(d.Ng));
-    c.row_rpb = pick(8, sizeof(float2) * d.Ng, fg, twb_bytes(d.Ng));
-    c.dct_dp = pick(4, sizeof(float2) * 2 * d.M, fm, twb_bytes(2 * d.M));
+    c.col_np = pick(8, sizeof(float2) * d.Ng, fg, twb_bytes(fg));
+    c.row_rpb = pick(8, sizeof(float2) * d.Ng, fg, twb_bytes(fg));
+    c.dct_dp = pick(4, sizeof(float2) * 2 * d.M, fm, twb_bytes(fm));
     c.ring_rt = 1;
     // wide tiles amortise the per-band work; narrow ones keep small batches parallel
     const long gwide = (long)((d.Ng + 255) / 256) * ((d.NB + 31) / 32) * max_batch;
@@ -350,15 +537,6 @@ int choose_launch(pat_plan* p, const std::vector<FftDev>& fd, int max_batch,
             break;
         }
     if (!c.col_np || !c.row_rpb || !c.dct_dp) return PAT_ERR_UNSUPPORTED;
-    // ring kernels: as few threads per ring as the FFT stages allow (one wave when
-    // possible), so that many rings are resident per CU to hide their latency
-    p->thr_ring = 0;
-    for (int thr = 64; thr <= kRingMaxThreads; thr *= 2) {
-        bool ok = thr * kRingModesPerThread >= d.K + 1;  // every mode's coefficient prefetched
-        for (const FftDev* f : ring_descs) ok = ok && fft_min_tps(*f, 4) <= thr;
-        if (ok) { p->thr_ring = thr; p->ring_mb = 4; break; }
-    }
-    if (!p->thr_ring) return PAT_ERR_UNSUPPORTED;
     return apply_launch(p, c);
 }
 
@@ -418,14 +596,16 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     d.h2 = (float)(h * h);
 
     FftSet ffts;
-    d.fft_grid = ffts.get(Ng);
-    d.fft_dct = ffts.get(2L * dv.M);
+    const int tps_grid = fixed_fft_tps(Ng), tps_dct = fixed_fft_tps(2L * dv.M);
+    if (!tps_grid || !tps_dct) return PAT_ERR_UNSUPPORTED;
+    d.fft_grid = ffts.get(Ng, tps_grid);
+    d.fft_dct = ffts.get(2L * dv.M, tps_dct);
+    if (d.fft_grid < 0 || d.fft_dct < 0) return PAT_ERR_UNSUPPORTED;
     d.fold_P = dv.P;
     d.fold_s = dv.P ? dv.S : 0;
     d.syn_len = dv.P ? dv.P : dv.L;
-    d.fft_syn = ffts.get(d.syn_len);
     d.syn_half = (dv.P && dv.P % 2 == 0) ? 1 : 0;
-    d.fft_synh = d.syn_half ? ffts.get(dv.P / 2) : d.fft_syn;
+    // (the synthesis transforms are planned below, once the ring kernels' threads are known)
 
     // --- image-side tables -------------------------------------------------
     std::vector<double> ph = es_hat(N, Ng);
@@ -460,14 +640,41 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
         ringN[n - 1] = np;
         ringOff[n - 1] = npts;
         ringJoff[n - 1] = joff;
-        ringFft[n - 1] = ffts.get(np / 2);
-        ringTwn[n - 1] = ffts.get(np);
+        ringTwn[n - 1] = ffts.get(np, 0);
         rho[n - 1] = lam * h * Ng / (2.0 * PI);
         npts += np / 2;
         joff += kn + 1;
         npsi_max = std::max(npsi_max, np);
     }
     ringOff[nlam] = npts;
+    // ring kernels: as few threads per ring as the transforms allow (one wave when
+    // possible, so that many rings are resident per CU to hide their latency),
+    // at least (K + 1) / kRingModesPerThread (every mode's coefficient prefetched);
+    // the ring and synthesis transforms are planned for that many threads
+    {
+        const long syn_fft_n = d.syn_half ? dv.P / 2 : d.syn_len;
+        p->thr_ring = 0;
+        for (int thr = 64; thr <= kRingMaxThreads && !p->thr_ring; thr *= 2) {
+            unsigned char rad[kMaxStages];
+            bool ok = thr * kRingModesPerThread >= K + 1 &&
+                      fft_passes(syn_fft_n, thr, kRingFftMaxButterflies, rad) >= 0;
+            for (int n = 0; n < nlam && ok; ++n)
+                if (n == 0 || ringN[n] != ringN[n - 1])
+                    ok = fft_passes(ringN[n] / 2, thr, kRingFftMaxButterflies, rad) >= 0;
+            if (ok) p->thr_ring = thr;
+        }
+        if (!p->thr_ring) return PAT_ERR_UNSUPPORTED;
+        const int thr = p->thr_ring;
+        for (int n = 0; n < nlam; ++n) {
+            ringFft[n] = ffts.get(ringN[n] / 2, thr, kRingFftMaxButterflies);
+            if (ringFft[n] < 0) return PAT_ERR_UNSUPPORTED;
+        }
+        // fft_syn: length syn_len (its twiddles; the transform itself unless the
+        // synthesis runs as a half-length real transform, fft_synh)
+        d.fft_syn = ffts.get(d.syn_len, d.syn_half ? 0 : thr, kRingFftMaxButterflies);
+        d.fft_synh = d.syn_half ? ffts.get(dv.P / 2, thr, kRingFftMaxButterflies) : d.fft_syn;
+        if (d.fft_syn < 0 || d.fft_synh < 0) return PAT_ERR_UNSUPPORTED;
+    }
     p->n_ring_modes = joff;
     d.npsi_max = npsi_max;
     d.npts = npts;
@@ -588,13 +795,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     }
 
     {
-        std::vector<const FftDev*> rdesc;
-        for (int n = 0; n < nlam; ++n) {
-            if (std::find(rdesc.begin(), rdesc.end(), &ffts.descs[ringFft[n]]) == rdesc.end())
-                rdesc.push_back(&ffts.descs[ringFft[n]]);
-        }
-        rdesc.push_back(&ffts.descs[d.syn_half ? d.fft_synh : d.fft_syn]);
-        int rc = choose_launch(p, ffts.descs, desc->max_batch, rdesc);
+        int rc = choose_launch(p, ffts.descs, desc->max_batch);
         if (rc != PAT_OK) return rc;
     }
 
