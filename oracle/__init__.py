@@ -42,7 +42,7 @@ class _Geom(ctypes.Structure):
                 ("n_det", ctypes.c_int), ("arc_center", ctypes.c_double),
                 ("arc_span", ctypes.c_double), ("n_t", ctypes.c_int), ("dt", ctypes.c_double),
                 ("c", ctypes.c_double), ("lambda_oversample", ctypes.c_double),
-                ("em_correction", ctypes.c_int)]
+                ("em_correction", ctypes.c_int), ("det_theta", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Sizes(ctypes.Structure):
@@ -95,9 +95,17 @@ def restore_library(handle):
 
 
 def _g(geom) -> _Geom:
-    return _Geom(int(geom.n), float(geom.support_r), float(geom.det_r), int(geom.n_det),
-                 float(geom.arc_center), float(geom.arc_span), int(geom.n_t), float(geom.dt),
-                 float(geom.c), float(geom.lambda_oversample), int(geom.em_correction))
+    th = getattr(geom, "det_theta", None)
+    g = _Geom(int(geom.n), float(geom.support_r), float(geom.det_r), int(geom.n_det),
+              float(geom.arc_center), float(geom.arc_span), int(geom.n_t), float(geom.dt),
+              float(geom.c), float(geom.lambda_oversample), int(geom.em_correction), None)
+    if th is not None:
+        arr = np.ascontiguousarray(th, dtype=np.float64)
+        if arr.shape != (int(geom.n_det),):
+            raise ValueError("det_theta needs n_det angles")
+        g.det_theta = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        g._keep = arr  # the array outlives the call through the structure
+    return g
 
 
 def _dp(a):

@@ -100,8 +100,10 @@ static int in_mask(const oracle_geom* g, int i, int j)
     return x * x + y * y < g->support_r * g->support_r;
 }
 
+/* detector angle: explicit, or uniform on the arc (cell-centred elements) */
 static double theta_det(const oracle_geom* g, int d)
 {
+    if (g->det_theta) return g->det_theta[d];
     return g->arc_center - 0.5 * g->arc_span + (d + 0.5) * g->arc_span / g->n_det;
 }
 

@@ -37,6 +37,8 @@ typedef struct {
     double c;                 /* speed of sound                                     */
     double lambda_oversample; /* sigma_t                                            */
     int    em_correction;     /* 1: add the rank-1 endpoint (kappa) term            */
+    const double* det_theta;  /* NULL, or D explicit detector angles [rad] that
+                                 replace the uniform arc (arc_* then unused)       */
 } oracle_geom;
 
 typedef struct {

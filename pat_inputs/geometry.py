@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, asdict, replace
+from typing import Optional, Tuple
 
 
 @dataclass(frozen=True)
@@ -27,6 +28,15 @@ class Geometry:
     det_r: float = 1.0          # R
     lambda_oversample: float = 2.0
     em_correction: int = 1
+    # explicit detector angles theta_d [rad] (D values, any order and spacing);
+    # None: the uniform arc above
+    det_theta: Optional[Tuple[float, ...]] = None
+
+    def __post_init__(self):
+        if self.det_theta is not None:
+            object.__setattr__(self, "det_theta", tuple(float(t) for t in self.det_theta))
+            if len(self.det_theta) != self.n_det:
+                raise ValueError("det_theta needs n_det = %d angles" % self.n_det)
 
     def asdict(self):
         return asdict(self)
@@ -39,6 +49,8 @@ class Geometry:
         return 2.0 / self.n
 
     def det_angles(self):
+        if self.det_theta is not None:
+            return list(self.det_theta)
         a, D = self.arc_span, self.n_det
         return [self.arc_center - a / 2 + (d + 0.5) * a / D for d in range(D)]
 
