@@ -46,7 +46,8 @@ ADJ_NAMES = ["dct_adj", "ring_adj", "spread", "rowpass_adj", "colpass_adj"]
 KERNEL_SYMBOL = {"colpass_fwd": "k_colpass_fwd", "rowpass_fwd": "k_rowpass_fwd", "gather": "k_gather",
                  "ring_fwd": "k_ring_fwd", "dct_fwd": "k_dct_det", "dct_adj": "k_dct_det",
                  "ring_adj": "k_ring_adj", "spread": "k_spread", "rowpass_adj": "k_rowpass_adj",
-                 "colpass_adj": "k_colpass_adj"}
+                 "colpass_adj": "k_colpass_adj", "syn_fwd": "k_syn_dense_fwd", "syn_adj": "k_syn_dense_adj"}
+MFMA_FP32_PEAK_TFLOPS = 157.3   # dense FP32 matrix-core peak of the MI355X
 # interpolation or spread of one polar point: 16 kernel evaluations (~6 flops),
 # 64 weight products and 64 complex x real multiply-adds (4 flops)
 FLOPS_PER_POINT = 16 * 6 + 64 + 64 * 4
@@ -89,8 +90,11 @@ def algorithmic_flops(info, geom, name):
         return FLOPS_PER_POINT * P
     if name in ("ring_fwd", "ring_adj"):
         ring = P / max(NL, 1)                  # average half-ring length
-        syn = max(info.len_czt, 2)
-        return 5.0 * P * math.log2(max(ring, 2)) + 5.0 * NL * syn * math.log2(syn) / 2
+        syn = 0 if info.syn_dense else max(info.len_czt, 2)
+        return 5.0 * P * math.log2(max(ring, 2)) + (5.0 * NL * syn * math.log2(syn) / 2 if syn else 0.0)
+    if name in ("syn_fwd", "syn_adj"):
+        # dense synthesis: 2 (K_n + 1) real coefficients x D detectors per ring, one multiply-add each
+        return 4.0 * info.n_ring_modes * D
     return None
 
 
@@ -108,6 +112,12 @@ def roofline(kms, info, geom, B):
     except (OSError, ValueError, KeyError):
         traffic = None
     fl = algorithmic_flops(info, geom, dom)
+    if fl is not None and dom.startswith("syn_"):
+        flops = fl * B
+        ach = flops / t / 1e12
+        return {"bound": "mfma", "kernel": dom, "achieved": round(ach, 3), "peak": MFMA_FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / MFMA_FP32_PEAK_TFLOPS, 4), "flops_per_launch": int(flops),
+                "avg_launch_ms": round(kms[dom], 4), "traffic": traffic}
     if fl is not None:
         flops = fl * B
         ach = flops / t / 1e12
@@ -126,16 +136,20 @@ def roofline(kms, info, geom, B):
 def kernel_times(pat, plan, f, g, gout, fout, nprof=10):
     """Average per-launch milliseconds of each kernel, from the library's HIP
     events recorded on the stream the kernels run on."""
+    fwd, adj = FWD_NAMES, ADJ_NAMES
+    if plan.info.syn_dense:  # explicit detector angles: the dense synthesis has its own slot
+        fwd = FWD_NAMES[:4] + ["syn_fwd"] + FWD_NAMES[4:]
+        adj = ADJ_NAMES[:1] + ["syn_adj"] + ADJ_NAMES[1:]
     pat.pat_profile_enable(plan.handle, True)
-    acc_f = [0.0] * len(FWD_NAMES)
-    acc_a = [0.0] * len(ADJ_NAMES)
+    acc_f = [0.0] * len(fwd)
+    acc_a = [0.0] * len(adj)
     for _ in range(nprof):
         plan.forward(f, out=gout)
         acc_f = [a + b for a, b in zip(acc_f, pat.pat_profile_read(plan.handle, 0))]
         plan.adjoint(g, out=fout)
         acc_a = [a + b for a, b in zip(acc_a, pat.pat_profile_read(plan.handle, 1))]
     pat.pat_profile_enable(plan.handle, False)
-    return {n: v / nprof for n, v in zip(FWD_NAMES + ADJ_NAMES, acc_f + acc_a)}
+    return {n: v / nprof for n, v in zip(fwd + adj, acc_f + acc_a)}
 
 
 def time_pairs(torch, plan, f, g, gout, fout, steps, warmup):
@@ -530,6 +544,53 @@ def bench_paper(args):
     plan.close()
 
 
+def bench_dense(args):
+    """Explicit detector angles: the 256^2 limited-view workload with its 256
+    detectors each displaced by up to +-0.3 element pitch (seeded), so the
+    angular synthesis runs as the dense product on the matrix cores."""
+    import numpy as np
+    import torch
+
+    import paper_2604_19176_amd as pat
+    from pat_inputs import CONFIGS
+    from pat_inputs.geometry import jittered_array_geometry
+
+    dev = torch.device("cuda", 0)
+    cfg = CONFIGS[2]
+    geom = jittered_array_geometry()
+    B = args.batch
+    plan = pat.PatPlan(geom, max_batch=B)
+    fs, f, gm, g_meas = make_inputs(np, torch, plan, geom, cfg, B, dev, 1000)
+    g_out, f_out = torch.empty_like(g_meas), torch.empty_like(f)
+    launch = plan.launch
+    if args.tune:
+        launch = plan.autotune(batch=B, cache_path=args.tune_cache)
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        ref_g = oracle.forward(geom, fs[0])
+        ref_f = oracle.adjoint(geom, gm[0])
+        g0 = plan.forward(f[0:1].contiguous())[0].cpu().double().numpy()
+        a0 = plan.adjoint(g_meas[0:1].contiguous())[0].cpu().double().numpy()
+        parity = {"fwd_rel_l2": float(np.linalg.norm(g0 - ref_g) / np.linalg.norm(ref_g)),
+                  "adj_rel_l2": float(np.linalg.norm(a0 - ref_f) / np.linalg.norm(ref_f))}
+        assert parity["fwd_rel_l2"] <= 1e-5 and parity["adj_rel_l2"] <= 1e-5, parity
+    ms_step, wall = time_pairs(torch, plan, f, g_meas, g_out, f_out, args.steps, args.warmup)
+    kms = kernel_times(pat, plan, f, g_meas, g_out, f_out)
+    syn = {k: kms[k] for k in ("syn_fwd", "syn_adj")}
+    out = {"metric": "A+A* pairs/s, explicit (jittered) detector angles, dense synthesis on the matrix cores",
+           "value": round(B * 1000.0 / ms_step, 1), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "256x256, 256 detectors on 180 deg jittered by up to +-0.3 pitch, 512 samples, "
+                                  "batch %d" % B, "batch": B},
+           "parity": parity, "roofline": roofline(kms, plan.info, geom, B),
+           "roofline_dense_synthesis": roofline(syn, plan.info, geom, B),
+           "kernels_ms": {k: round(v, 4) for k, v in kms.items()}, "launch": launch, "tuned": bool(args.tune)}
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -537,7 +598,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--workload", default="default",
-                    choices=["default", "mixed", "tv3", "large", "paper", "pdhg3", "pdhg-large"])
+                    choices=["default", "mixed", "tv3", "large", "paper", "pdhg3", "pdhg-large", "dense"])
     ap.add_argument("--no-tune", dest="tune", action="store_false",
                     help="time the default launch shapes instead of autotuning them first")
     ap.add_argument("--tune-cache", default=None, help="JSON cache file of the autotuner")
@@ -552,6 +613,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "default":
         bench_default(args)
+    elif args.workload == "dense":
+        bench_dense(args)
     elif args.workload == "mixed":
         bench_mixed(args)
     elif args.workload == "pdhg3":

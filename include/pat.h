@@ -66,6 +66,12 @@ typedef struct {
     double lambda_oversample; /* sigma_t >= 1 (2.0); radial frequency step dlam = pi/(M c dt)         */
     int    em_correction;     /* 1: add the rank-1 endpoint term kappa*h^2*sum(m f) (default 1)       */
     int    max_batch;         /* capacity of the batch dimension (>= 1); sizes pat_workspace_size     */
+    const double* det_theta;  /* NULL: the uniform arc above.  Else D explicit detector angles [rad],
+                                 any order and spacing (gaps, several arcs, sparse elements), in host
+                                 memory read only during pat_plan_create / pat_plan_derive (the plan
+                                 keeps a copy); arc_center and arc_span are then unused.  The angular
+                                 synthesis Re sum_k e^{ik theta_d} B_k of eq. (2) then runs as a dense
+                                 product on the matrix cores instead of an FFT.                       */
 } pat_plan_desc;
 
 /* What a plan derived (pat_plan_query). */
@@ -83,6 +89,9 @@ typedef struct {
                                  >= K + D                                                             */
     int    syn_stride;        /* s in that case (detector d sits at point s d of the P-point grid),
                                  0 for the chirp-z synthesis                                          */
+    int    syn_dense;         /* 1: explicit detector angles; the synthesis is the product of the
+                                 (K+1)-mode coefficients with a [2(K+1)][D] cos/sin table (len_czt,
+                                 syn_stride 0)                                                        */
     int    n_ring_modes;      /* sum over radial frequencies of the angular modes kept (K_n + 1)       */
     size_t workspace_per_instance; /* workspace bytes per batch instance                              */
     size_t table_bytes;       /* device bytes held by the plan's tables                               */
@@ -169,7 +178,9 @@ int  pat_pd_change(const float* f, const float* xbar, float* out, int n, int bat
  * 1 = adjoint) to finish and writes its kernel durations in milliseconds to
  * ms[0..*count-1], in launch order (forward: column pass, row pass, polar
  * interpolation, ring (angular FFT, weights, detector synthesis), cosine transform;
- * adjoint: cosine transform, ring, spread, row pass, column pass).  Errors: PAT_ERR_ARG (NULL, profiling off,
+ * adjoint: cosine transform, ring, spread, row pass, column pass).  With
+ * explicit detector angles the dense synthesis follows the ring in the forward
+ * and precedes it in the adjoint (six durations per direction).  Errors: PAT_ERR_ARG (NULL, profiling off,
  * max_kernels too small), PAT_ERR_HIP. */
 int  pat_profile_enable(pat_plan* plan, int enable);
 int  pat_profile_read(const pat_plan* plan, int which, float* ms, int max_kernels, int* count);

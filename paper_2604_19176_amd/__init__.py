@@ -15,6 +15,8 @@ from __future__ import annotations
 
 import ctypes
 
+import numpy as np
+
 import torch
 
 from . import _lib
@@ -35,11 +37,21 @@ def library_path() -> str:
 
 
 def desc_from_geometry(geom, max_batch: int = 1) -> pat_plan_desc:
-    """pat_plan_desc from any object with the Geometry fields."""
-    return pat_plan_desc(int(geom.n), float(geom.support_r), float(geom.det_r), int(geom.n_det),
-                         float(geom.arc_center), float(geom.arc_span), int(geom.n_t), float(geom.dt),
-                         float(geom.c), float(geom.lambda_oversample), int(geom.em_correction),
-                         int(max_batch))
+    """pat_plan_desc from any object with the Geometry fields (explicit
+    detector angles `det_theta`, if the object has them, are passed as a host
+    array that the descriptor keeps alive)."""
+    d = pat_plan_desc(int(geom.n), float(geom.support_r), float(geom.det_r), int(geom.n_det),
+                      float(geom.arc_center), float(geom.arc_span), int(geom.n_t), float(geom.dt),
+                      float(geom.c), float(geom.lambda_oversample), int(geom.em_correction),
+                      int(max_batch), None)
+    th = getattr(geom, "det_theta", None)
+    if th is not None:
+        arr = np.ascontiguousarray(th, dtype=np.float64)
+        if arr.shape != (int(geom.n_det),):
+            raise ValueError("det_theta needs n_det angles")
+        d.det_theta = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d._keep = arr
+    return d
 
 
 def _stream(device):

@@ -33,14 +33,14 @@ class pat_plan_desc(ctypes.Structure):
                 ("n_det", ctypes.c_int), ("arc_center", ctypes.c_double), ("arc_span", ctypes.c_double),
                 ("n_t", ctypes.c_int), ("dt", ctypes.c_double), ("c", ctypes.c_double),
                 ("lambda_oversample", ctypes.c_double), ("em_correction", ctypes.c_int),
-                ("max_batch", ctypes.c_int)]
+                ("max_batch", ctypes.c_int), ("det_theta", ctypes.POINTER(ctypes.c_double))]
 
 
 class pat_plan_info(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int), ("dlam", ctypes.c_double), ("n_lam", ctypes.c_int),
                 ("K", ctypes.c_int), ("n_psi", ctypes.c_int), ("kappa", ctypes.c_double),
                 ("n_grid", ctypes.c_int), ("n_points", ctypes.c_int), ("len_czt", ctypes.c_int),
-                ("syn_stride", ctypes.c_int), ("n_ring_modes", ctypes.c_int),
+                ("syn_stride", ctypes.c_int), ("syn_dense", ctypes.c_int), ("n_ring_modes", ctypes.c_int),
                 ("workspace_per_instance", ctypes.c_size_t), ("table_bytes", ctypes.c_size_t)]
 
 

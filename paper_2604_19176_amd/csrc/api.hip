@@ -50,6 +50,16 @@ static void spread_launch_ib(int cb, dim3 grid, size_t lds, hipStream_t st, cons
 // LDS of an FFT tile: nseq sequences of the length plus its per-pass twiddles
 static size_t fft_tile_lds(int nseq, const FftDev& f) { return sizeof(float2) * ((size_t)nseq * f.n + f.ntb); }
 
+// Output tiles of the dense synthesis (explicit detector angles) per instance
+static int syn_fwd_tiles(const PlanDev& d)
+{
+    return ((d.nlam + kSynTile - 1) / kSynTile) * ((d.D + kSynTile - 1) / kSynTile);
+}
+static int syn_adj_tiles(const PlanDev& d)
+{
+    return ((d.nlam + kSynTile - 1) / kSynTile) * ((2 * d.Kp + kSynTile - 1) / kSynTile);
+}
+
 static int check_launch()
 {
     return hipGetLastError() == hipSuccess ? PAT_OK : PAT_ERR_HIP;
@@ -107,11 +117,17 @@ extern "C" int pat_forward(const pat_plan* p, const float* f, float* g, int batc
     }
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, 4, st);
+    const int qd = d.syn_dense ? 5 : 4;  // event index after the synthesis
+    if (d.syn_dense) {  // explicit detector angles: synthesis on the matrix cores
+        hipLaunchKernelGGL(k_syn_dense_fwd, dim3(syn_fwd_tiles(d), batch), dim3(kSynThreads), 0, st, d, p->ws, wsp);
+        if ((rc = check_launch())) return rc;
+        prof_mark(p, 0, qd, st);
+    }
     hipLaunchKernelGGL(k_dct_det, dim3(xcd_grid(p->n_pair_tiles * batch)), dim3(p->thr_dct),
                        fft_tile_lds(c.dct_dp, p->h_fft_dct), st, d, p->ws, wsp, g, (const float*)nullptr, c.dct_dp, 0, d.N,
                        batch);
     if ((rc = check_launch())) return rc;
-    prof_mark(p, 0, 5, st);
+    prof_mark(p, 0, qd + 1, st);
     return PAT_OK;
 }
 
@@ -129,12 +145,18 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
                        fft_tile_lds(c.dct_dp, p->h_fft_dct), st, d, p->ws, wsp, (float*)nullptr, g, c.dct_dp, 1, 0, batch);
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 1, st);
+    const int qa = d.syn_dense ? 1 : 0;  // event offset after the transposed synthesis
+    if (d.syn_dense) {  // explicit detector angles: the transposed synthesis on the matrix cores
+        hipLaunchKernelGGL(k_syn_dense_adj, dim3(syn_adj_tiles(d), batch), dim3(kSynThreads), 0, st, d, p->ws, wsp);
+        if ((rc = check_launch())) return rc;
+        prof_mark(p, 1, 2, st);
+    }
     {
         const dim3 grid(xcd_grid((d.nlam + c.ring_rt - 1) / c.ring_rt * batch)), blk(p->thr_ring);
         hipLaunchKernelGGL(k_ring_adj, grid, blk, p->lds_ring, st, d, p->ws, wsp, c.ring_rt, batch);
     }
     if ((rc = check_launch())) return rc;
-    prof_mark(p, 1, 2, st);
+    prof_mark(p, 1, 2 + qa, st);
     {
         const int cb = c.spr_cb, th = c.spr_th, ib = tile_ib(c.spr_ib, batch);
         const int items = ((d.Ng + cb - 1) / cb) * ((d.Hy + th - 1) / th) * ((batch + ib - 1) / ib);
@@ -145,15 +167,15 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
         else spread_launch_ib<1>(cb, grid, lds, st, d, p->ws, wsp, th, batch);
     }
     if ((rc = check_launch())) return rc;
-    prof_mark(p, 1, 3, st);
+    prof_mark(p, 1, 3 + qa, st);
     hipLaunchKernelGGL(k_rowpass_adj, dim3((d.Hy + c.row_rpb - 1) / c.row_rpb, batch), dim3(p->thr_row),
                        fft_tile_lds(c.row_rpb, p->h_fft_grid), st, d, p->ws, wsp, c.row_rpb);
     if ((rc = check_launch())) return rc;
-    prof_mark(p, 1, 4, st);
+    prof_mark(p, 1, 4 + qa, st);
     hipLaunchKernelGGL(k_colpass_adj, dim3(p->n_col_tiles, batch), dim3(p->thr_col), fft_tile_lds(c.col_np, p->h_fft_grid), st,
                        d, p->ws, wsp, f, c.col_np, d.D);
     if ((rc = check_launch())) return rc;
-    prof_mark(p, 1, 5, st);
+    prof_mark(p, 1, 5 + qa, st);
     return PAT_OK;
 }
 
@@ -233,8 +255,8 @@ extern "C" int pat_profile_enable(pat_plan* p, int enable)
         for (int dir = 0; dir < 2; ++dir)
             for (int q = 0; q < 8; ++q)
                 if (hipEventCreate(&p->ev[dir][q]) != hipSuccess) return PAT_ERR_HIP;
-        p->ev_count[0] = 6;  // 5 forward kernels
-        p->ev_count[1] = 6;  // 5 adjoint kernels
+        // 5 kernels per direction, 6 with the dense synthesis (explicit angles)
+        p->ev_count[0] = p->ev_count[1] = p->dev.syn_dense ? 7 : 6;
         p->prof = 1;
     } else if (!enable && p->prof) {
         for (int dir = 0; dir < 2; ++dir)
@@ -344,6 +366,8 @@ static void batch_layout(pat_batch* b)
         items[kStGather] = ((d.Ng + b->gat_cb - 1) / b->gat_cb) * ((d.NB + b->gat_th - 1) / b->gat_th);
         items[kStRing] = (d.nlam + I.ring_rt - 1) / I.ring_rt;
         items[kStDct] = I.n_pair_tiles;
+        items[kStSynFwd] = d.syn_dense ? syn_fwd_tiles(d) : 0;
+        items[kStSynAdj] = d.syn_dense ? syn_adj_tiles(d) : 0;
         items[kStSpread] = ((d.Ng + b->spr_cb - 1) / b->spr_cb) * ((d.Hy + b->spr_th - 1) / b->spr_th);
         for (int s = 0; s < kNumStages; ++s)
             b->base[(size_t)s * (n + 1) + i + 1] = b->base[(size_t)s * (n + 1) + i] + items[s];
@@ -497,6 +521,11 @@ extern "C" int pat_batch_forward(const pat_batch* b, const float* const* f_ptrs,
     hipLaunchKernelGGL(k_ring_fwd_b, dim3(xcd_grid(batch_items(b, kStRing))), dim3(b->thr_ring), b->lds_ring, st,
                        bt, w);
     if ((rc = check_launch())) return rc;
+    if (batch_items(b, kStSynFwd) > 0) {
+        hipLaunchKernelGGL(k_syn_dense_fwd_b, dim3(xcd_grid(batch_items(b, kStSynFwd))), dim3(kSynThreads), 0, st,
+                           bt, w);
+        if ((rc = check_launch())) return rc;
+    }
     hipLaunchKernelGGL(k_dct_det_b, dim3(xcd_grid(batch_items(b, kStDct))), dim3(b->thr_dct), b->lds_dct, st, bt, w,
                        g_ptrs, (const float* const*)nullptr, 0);
     return check_launch();
@@ -513,6 +542,11 @@ extern "C" int pat_batch_adjoint(const pat_batch* b, const float* const* g_ptrs,
     hipLaunchKernelGGL(k_dct_det_b, dim3(xcd_grid(batch_items(b, kStDct))), dim3(b->thr_dct), b->lds_dct, st, bt, w,
                        (float* const*)nullptr, g_ptrs, 1);
     if ((rc = check_launch())) return rc;
+    if (batch_items(b, kStSynAdj) > 0) {
+        hipLaunchKernelGGL(k_syn_dense_adj_b, dim3(xcd_grid(batch_items(b, kStSynAdj))), dim3(kSynThreads), 0, st,
+                           bt, w);
+        if ((rc = check_launch())) return rc;
+    }
     hipLaunchKernelGGL(k_ring_adj_b, dim3(xcd_grid(batch_items(b, kStRing))), dim3(b->thr_ring), b->lds_ring, st,
                        bt, w);
     if ((rc = check_launch())) return rc;

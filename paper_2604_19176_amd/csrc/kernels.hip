@@ -330,7 +330,7 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
     const int n0 = tile * RT;
     const int nr = min(RT, d.nlam - n0);
     // synthesis: fold with even P -> transform of P/2 + twiddles of P (twA); else transform of S
-    const TwLds twA = tw_lds_build(R.twA, d.ffts[d.fft_syn], d.tw);
+    const TwLds twA = d.syn_dense ? TwLds{R.twA, R.twA, 0} : tw_lds_build(R.twA, d.ffts[d.fft_syn], d.tw);
     const FftDev& fS = d.ffts[d.fft_synh];
     const float2* __restrict__ tbS = d.tw + fS.tb;
     for (int r = 0; r < nr; ++r) {
@@ -363,6 +363,18 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
         }
         __syncthreads();
         fft_lds<false, kRingFftMaxButterflies>(R.sa, P, 1, fR, tbR);
+        if (d.syn_dense) {
+            // explicit detector angles: the mode coefficients a_k go to the workspace;
+            // the dense product with the cos/sin table synthesises the detectors
+            float2* am = (float2*)(wb + L.modes) + (size_t)n * d.Kp;
+#pragma unroll
+            for (int j = 0; j < kRingModesPerThread; ++j) {
+                const int k = tid + j * bd;
+                if (k <= Kn) am[k] = cmul(cpre[j], real_unpack(R.sa, P, k, twN(k)));
+            }
+            __syncthreads();
+            continue;
+        }
         // y = the a_k = coef_k Q_k (Q: the real length-2P transform of q) folded
         // mod Pf (fold) or zero-padded to S (chirp-z), summed in order of k: pass
         // 0 writes k < Pf, each further pass adds the next Pf modes
@@ -442,7 +454,7 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
     // the mode values Q~ go to qb, the Hermitian-part input of the ring's inverse FFT to eb
     float2* const qb = half ? R.sy : R.sa;
     float2* const eb = half ? R.sa : R.sy;
-    const TwLds twA = tw_lds_build(R.twA, d.ffts[d.fft_syn], d.tw);
+    const TwLds twA = d.syn_dense ? TwLds{R.twA, R.twA, 0} : tw_lds_build(R.twA, d.ffts[d.fft_syn], d.tw);
     const FftDev& fS = d.ffts[d.fft_synh];
     const float2* __restrict__ tbS = d.tw + fS.tb;
     for (int r = 0; r < nr; ++r) {
@@ -451,6 +463,8 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
         const int Kn = d.ring_K[n];
         const float2* __restrict__ cf = d.coef + d.ring_joff[n];
         const float* hn = hT + (size_t)n * D;
+        // explicit detector angles: y~_k from the dense product (workspace), no transform
+        const float2* __restrict__ am = (const float2*)(wb + L.modes) + (size_t)n * d.Kp;
         const FftDev& fR = d.ffts[d.ring_fft[n]];
         const float2* __restrict__ tbR = d.tw + fR.tb;
         float2 cpre[kRingModesPerThread];
@@ -461,7 +475,8 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
         }
         const TwLds twN = tw_lds_build(R.twN, d.ffts[d.ring_twn[n]], d.tw);
         // y~ = FFT of the real detector values, zero-padded to the synthesis length
-        if (half) {
+        if (d.syn_dense) {
+        } else if (half) {
             const int H2 = d.fold_P / 2;
             for (int t = tid; t < H2; t += bd)
                 R.sc[t] = make_float2(grid_det(hn, 2 * t, d.fold_s, D), grid_det(hn, 2 * t + 1, d.fold_s, D));
@@ -498,7 +513,7 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
             if (k <= Kn) {
                 int sidx = k;
                 if (d.fold_P) while (sidx >= d.fold_P) sidx -= d.fold_P;
-                qb[k] = cmulc(ytil(sidx), cpre[j]);
+                qb[k] = cmulc(d.syn_dense ? am[k] : ytil(sidx), cpre[j]);
             }
         }
         __syncthreads();
@@ -529,6 +544,106 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
             Hb[d.band_of[off + l]] = cmulc(Fh, d.pt_phase[off + l]);
         }
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Explicit detector angles: the angular synthesis h(n, d) = Re sum_k a_k(n)
+// e^{ik theta_d} (eq. (2)) as a dense product on the matrix cores,
+//   forward  H[n][d] = sum_{j < 2(K_n + 1)} A[n][j] S[j][d],
+//   adjoint  A[n][j] = sum_d H[n][d] S[j][d],
+// with A the mode coefficients (re, im interleaved: [nlam][2(K+1)] floats) and
+// S the FP64-computed table S[2k] = cos(k theta_d), S[2k+1] = -sin(k theta_d).
+// 64 x 64 output tiles, four waves of 32 x 32 each (v_mfma_f32_32x32x2f32:
+// lane i holds A[i % 32][i / 32] and B[i / 32][i % 32]; accumulator r holds
+// D[8 (r / 4) + 4 (i / 32) + r % 4][i % 32]); the contraction runs in chunks of
+// 32 staged in LDS.  Rows are rings: a tile stops at 2 (K_n + 1) of its last
+// ring (K_n grows with n), and A's entries beyond a ring's own cut-off are
+// read as zero, so the product skips the modes a ring does not have.
+// ---------------------------------------------------------------------------
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int kSynTile = 64;     // output tile side
+constexpr int kSynChunk = 32;    // contraction chunk
+constexpr int kSynThreads = 256; // four waves
+
+__device__ __forceinline__ void syn_dense_fwd_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile)
+{
+    __shared__ float As[kSynTile][kSynChunk + 1];   // [ring][mode chunk]
+    __shared__ float Bs[kSynChunk][kSynTile + 32];  // [mode chunk][detector]; stride 96: halves on other banks
+    __shared__ int jn[kSynTile];                    // 2 (K_n + 1) of the tile's rings
+    const int J = 2 * d.Kp, D = d.D, NL = d.nlam;
+    const int tq = (D + kSynTile - 1) / kSynTile;
+    const int n0 = (tile / tq) * kSynTile, q0 = (tile % tq) * kSynTile;
+    const float* __restrict__ A = (const float*)(wb + L.modes);
+    float* __restrict__ H = (float*)(wb + L.hdet);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    if (tid < kSynTile) jn[tid] = n0 + tid < NL ? 2 * (d.ring_K[n0 + tid] + 1) : 0;
+    const int jmax = 2 * (d.ring_K[min(n0 + kSynTile - 1, NL - 1)] + 1);
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    __syncthreads();
+    for (int j0 = 0; j0 < jmax; j0 += kSynChunk) {
+        for (int e = tid; e < kSynTile * kSynChunk; e += kSynThreads) {
+            const int r = e >> 5, c = e & 31, j = j0 + c;
+            As[r][c] = j < jn[r] ? A[(size_t)(n0 + r) * J + j] : 0.f;
+        }
+        for (int e = tid; e < kSynChunk * kSynTile; e += kSynThreads) {
+            const int r = e >> 6, c = e & 63, j = j0 + r, q = q0 + c;
+            Bs[r][c] = (j < J && q < D) ? d.syn_tab[(size_t)j * D + q] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kSynChunk; kk += 2) {
+            const float a = As[wm + (lane & 31)][kk + (lane >> 5)];
+            const float b = Bs[kk + (lane >> 5)][wn + (lane & 31)];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int n = n0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), q = q0 + wn + (lane & 31);
+        if (n < NL && q < D) H[(size_t)n * D + q] = acc[r];
+    }
+}
+
+__device__ __forceinline__ void syn_dense_adj_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile)
+{
+    __shared__ float Hs[kSynTile][kSynChunk + 1];   // [ring][detector chunk]
+    __shared__ float St[kSynTile][kSynChunk + 1];   // [table row j][detector chunk]
+    const int J = 2 * d.Kp, D = d.D, NL = d.nlam;
+    const int tj = (J + kSynTile - 1) / kSynTile;
+    const int n0 = (tile / tj) * kSynTile, j0 = (tile % tj) * kSynTile;
+    // rows j >= 2 (K_n + 1) of every ring of the tile are never read: skip the tile
+    if (j0 >= 2 * (d.ring_K[min(n0 + kSynTile - 1, NL - 1)] + 1)) return;
+    const float* __restrict__ H = (const float*)(wb + L.hdet);
+    float* __restrict__ A = (float*)(wb + L.modes);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    for (int q0 = 0; q0 < D; q0 += kSynChunk) {
+        for (int e = tid; e < kSynTile * kSynChunk; e += kSynThreads) {
+            const int r = e >> 5, c = e & 31, q = q0 + c;
+            Hs[r][c] = (n0 + r < NL && q < D) ? H[(size_t)(n0 + r) * D + q] : 0.f;
+            St[r][c] = (j0 + r < J && q < D) ? d.syn_tab[(size_t)(j0 + r) * D + q] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kSynChunk; kk += 2) {
+            const float a = Hs[wm + (lane & 31)][kk + (lane >> 5)];
+            const float b = St[wn + (lane & 31)][kk + (lane >> 5)];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int n = n0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), j = j0 + wn + (lane & 31);
+        if (n < NL && j < J) A[(size_t)n * J + j] = acc[r];
     }
 }
 
@@ -1080,6 +1195,36 @@ __global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu
     const BatchInst& I = bt.inst[i];
     const PlanDev d = I.d;
     ring_adj_tile(d, I.L, ws + I.ws_off, tile, I.ring_rt, sm);
+}
+
+// Dense synthesis (explicit detector angles): grid (tiles, batch) for one plan;
+// the _b forms take their instance and tile from the batch tables.
+__global__ __launch_bounds__(kSynThreads) void k_syn_dense_fwd(PlanDev d, WsLayout L, InstPtrs wsp)
+{
+    syn_dense_fwd_tile(d, L, wsp.ws + (size_t)blockIdx.y * wsp.stride, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kSynThreads) void k_syn_dense_adj(PlanDev d, WsLayout L, InstPtrs wsp)
+{
+    syn_dense_adj_tile(d, L, wsp.ws + (size_t)blockIdx.y * wsp.stride, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kSynThreads) void k_syn_dense_fwd_b(BatchDev bt, char* ws)
+{
+    int i, tile;
+    if (!batch_item(bt, kStSynFwd, i, tile)) return;
+    const BatchInst& I = bt.inst[i];
+    const PlanDev d = I.d;
+    syn_dense_fwd_tile(d, I.L, ws + I.ws_off, tile);
+}
+
+__global__ __launch_bounds__(kSynThreads) void k_syn_dense_adj_b(BatchDev bt, char* ws)
+{
+    int i, tile;
+    if (!batch_item(bt, kStSynAdj, i, tile)) return;
+    const BatchInst& I = bt.inst[i];
+    const PlanDev d = I.d;
+    syn_dense_adj_tile(d, I.L, ws + I.ws_off, tile);
 }
 
 __global__ __launch_bounds__(1024) void k_dct_det(PlanDev d, WsLayout L, InstPtrs wsp, float* __restrict__ gout,

@@ -99,6 +99,8 @@ struct PlanDev {
     //  c_0 = 1, c_k = 2, is part of coef)
     const float2* czt_post; // [D]   w^{d^2}, w = e^{i dtheta/2} (Bluestein only)
     const float2* czt_vhat; // [L]   FFT_L of the chirp filter w^{-m^2}, divided by L (Bluestein only)
+    int syn_dense;          // 1: explicit detector angles, synthesis by the dense product with syn_tab
+    const float* syn_tab;   // [2(K+1)][D] cos(k theta_d), -sin(k theta_d) (syn_dense only)
     int npsi_max;           // largest per-ring angular grid
     // FFTs
     const FftDev* ffts;
@@ -181,6 +183,7 @@ struct WsLayout {
     size_t grid;     // [Hy][Ng]  float2   spectrum / spread target
     size_t hdet;     // [nlam][D] float    ring output (synthesised at the detectors) / cosine-adjoint output
     size_t polar;    // [npts]    float2   polar values: ring order (interpolation output), band order (spread input)
+    size_t modes;    // [nlam][K+1] float2 mode coefficients (explicit detector angles only)
     size_t red;      // small FP32 partial sums (mass / data sum)
     int n_red;       // number of partial sums
     size_t bytes;    // total per instance
@@ -195,6 +198,8 @@ enum BatchStage {
     kStRing,      // ring kernels: ceil(nlam / ring_rt) tiles
     kStDct,       // cosine transforms: ceil(ceil(D / 2) / dct_dp) tiles
     kStSpread,    // spread: ceil(Ng / spr_cb) x ceil(Hy / spr_th) tiles
+    kStSynFwd,    // dense synthesis (explicit angles): ceil(nlam / 64) x ceil(D / 64) tiles, else 0
+    kStSynAdj,    // its transpose: ceil(nlam / 64) x ceil(2 (K + 1) / 64) tiles, else 0
     kNumStages
 };
 
@@ -237,6 +242,7 @@ struct pat_plan {
     int n_pair_tiles;       // cosine-transform tiles (data-sum partials)
     int thr_col, thr_row, thr_ring, thr_dct;  // workgroup sizes of the FFT kernels
     size_t lds_ring;        // dynamic LDS of the ring kernels
+    double* det_theta;      // copy of the explicit detector angles (NULL for a uniform arc)
     // optional per-kernel timing (pat_profile_enable): events around each launch
     int prof;
     hipEvent_t ev[2][8];

@@ -7,6 +7,7 @@
 #include "../../include/pat.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -163,6 +164,7 @@ static std::vector<double> es_hat(int N, int Ng)
 
 struct Derived {
     int M, n_lam, K, n_psi, Ng, L, P, S;
+    int dense;  // explicit detector angles: synthesis as a dense product
     double h, dlam, kappa;
 };
 
@@ -185,12 +187,16 @@ static int derive(const pat_plan_desc* d, Derived* o)
     o->kappa = d->em_correction ? o->dlam * o->dlam / (24.0 * PI) : 0.0;
     o->Ng = (int)smooth23(2.0 * d->n, 2);
     o->L = (int)smooth23((double)o->K + d->n_det, 1);
-    {   // detector pitch dtheta = 2 pi s / P with P = 2^a 3^b (the smallest such P; then gcd(s, P) = 1
+    o->P = 0;
+    o->S = 0;
+    o->dense = d->det_theta ? 1 : 0;
+    if (o->dense)
+        for (int q = 0; q < d->n_det; ++q)
+            if (!std::isfinite(d->det_theta[q])) return PAT_ERR_ARG;
+    if (!o->dense) {   // detector pitch dtheta = 2 pi s / P with P = 2^a 3^b (the smallest such P; then gcd(s, P) = 1
         // and s (D - 1) < P): the detectors are every s-th point of a P-point angular grid and the
         // synthesis is one FFT of length P.  Taken while that FFT is no dearer than the chirp-z pair.
         const double turns = d->arc_span / (2.0 * PI * d->n_det);  // dtheta / (2 pi)
-        o->P = 0;
-        o->S = 0;
         for (long P = smooth23((double)d->n_det, 1); P <= 8192 && P <= 3L * o->L; P = smooth23((double)P + 1, 1)) {
             const double sd = turns * (double)P;
             const long s = std::lround(sd);
@@ -202,7 +208,7 @@ static int derive(const pat_plan_desc* d, Derived* o)
         }
     }
     // limits of the kernels: every FFT length must fit the LDS plans
-    if (d->n < 16 || o->Ng > 8192 || 2L * o->M > 8192 || (!o->P && o->L > 8192) || o->n_psi > 8192)
+    if (d->n < 16 || o->Ng > 8192 || 2L * o->M > 8192 || (!o->P && !o->dense && o->L > 8192) || o->n_psi > 8192)
         return PAT_ERR_UNSUPPORTED;
     if (o->n_lam >= 2 * o->M) return PAT_ERR_UNSUPPORTED;  // cosine grid index n < 2M
     return PAT_OK;
@@ -549,6 +555,8 @@ void layout_workspace(pat_plan* p)
     w.grid = o;   o += align256(sizeof(float2) * (size_t)d.Hy * d.Ng);
     w.hdet = o;   o += align256(sizeof(float) * (size_t)d.D * d.nlam);
     w.polar = o;  o += align256(sizeof(float2) * (size_t)d.npts);
+    // explicit angles: mode coefficients a_k(n) (forward) / their adjoints, [nlam][K+1]
+    w.modes = o;  o += d.syn_dense ? align256(sizeof(float2) * (size_t)d.nlam * d.Kp) : 0;
     // endpoint-term partial sums: one per image column (forward) or detector (adjoint)
     w.n_red = std::max(d.N, d.D);
     w.red = o;    o += align256(sizeof(float) * (size_t)w.n_red);
@@ -571,8 +579,9 @@ extern "C" int pat_plan_derive(const pat_plan_desc* desc, pat_plan_info* out)
     out->n_psi = dv.n_psi;
     out->kappa = dv.kappa;
     out->n_grid = dv.Ng;
-    out->len_czt = dv.P ? dv.P : dv.L;
+    out->len_czt = dv.dense ? 0 : (dv.P ? dv.P : dv.L);
     out->syn_stride = dv.P ? dv.S : 0;
+    out->syn_dense = dv.dense;
     return PAT_OK;
 }
 
@@ -591,7 +600,8 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     const int N = desc->n, Ng = dv.Ng, nlam = dv.n_lam, K = dv.K, D = desc->n_det, T = desc->n_t;
     const double h = dv.h, R = desc->det_r;
     d.N = N; d.Ng = Ng; d.Hy = Ng / 2 + 9; d.nlam = nlam; d.K = K; d.Kp = K + 1; d.M = dv.M;
-    d.T = T; d.D = D; d.L = dv.P ? 0 : dv.L; d.NB = Ng / 2 + 2;
+    d.T = T; d.D = D; d.L = (dv.P || dv.dense) ? 0 : dv.L; d.NB = Ng / 2 + 2;
+    d.syn_dense = dv.dense;
     d.kappa = (float)dv.kappa;
     d.h2 = (float)(h * h);
 
@@ -603,7 +613,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     if (d.fft_grid < 0 || d.fft_dct < 0) return PAT_ERR_UNSUPPORTED;
     d.fold_P = dv.P;
     d.fold_s = dv.P ? dv.S : 0;
-    d.syn_len = dv.P ? dv.P : dv.L;
+    d.syn_len = dv.dense ? 0 : (dv.P ? dv.P : dv.L);
     d.syn_half = (dv.P && dv.P % 2 == 0) ? 1 : 0;
     // (the synthesis transforms are planned below, once the ring kernels' threads are known)
 
@@ -657,7 +667,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
         for (int thr = 64; thr <= kRingMaxThreads && !p->thr_ring; thr *= 2) {
             unsigned char rad[kMaxStages];
             bool ok = thr * kRingModesPerThread >= K + 1 &&
-                      fft_passes(syn_fft_n, thr, kRingFftMaxButterflies, rad) >= 0;
+                      (dv.dense || fft_passes(syn_fft_n, thr, kRingFftMaxButterflies, rad) >= 0);
             for (int n = 0; n < nlam && ok; ++n)
                 if (n == 0 || ringN[n] != ringN[n - 1])
                     ok = fft_passes(ringN[n] / 2, thr, kRingFftMaxButterflies, rad) >= 0;
@@ -671,8 +681,12 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
         }
         // fft_syn: length syn_len (its twiddles; the transform itself unless the
         // synthesis runs as a half-length real transform, fft_synh)
-        d.fft_syn = ffts.get(d.syn_len, d.syn_half ? 0 : thr, kRingFftMaxButterflies);
-        d.fft_synh = d.syn_half ? ffts.get(dv.P / 2, thr, kRingFftMaxButterflies) : d.fft_syn;
+        if (dv.dense) {  // no synthesis transform (the ring kernels do not read these)
+            d.fft_syn = d.fft_synh = d.fft_grid;
+        } else {
+            d.fft_syn = ffts.get(d.syn_len, d.syn_half ? 0 : thr, kRingFftMaxButterflies);
+            d.fft_synh = d.syn_half ? ffts.get(dv.P / 2, thr, kRingFftMaxButterflies) : d.fft_syn;
+        }
         if (d.fft_syn < 0 || d.fft_synh < 0) return PAT_ERR_UNSUPPORTED;
     }
     p->n_ring_modes = joff;
@@ -754,8 +768,10 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     }
 
     // --- synthesis over detector angles --------------------------------------
+    // uniform arc: theta_d = theta_0 + d dtheta; explicit angles: the phases are
+    // in the dense table below (theta_0 = 0 in the coefficients)
     const double dth = desc->arc_span / D;
-    const double th0 = desc->arc_center - 0.5 * desc->arc_span + 0.5 * dth;
+    const double th0 = dv.dense ? 0.0 : desc->arc_center - 0.5 * desc->arc_span + 0.5 * dth;
     auto wpow = [&](long m) {  // w^{m^2}, w = e^{i dth/2}; phase reduced mod 2 pi in FP64
         double a = std::fmod(0.5 * dth * (double)m * (double)m, 2.0 * PI);
         return cd(std::cos(a), std::sin(a));
@@ -765,7 +781,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     for (int k = 0; k <= K; ++k) {
         double a = std::fmod(k * th0, 2.0 * PI);
         cd v = (k == 0 ? 1.0 : 2.0) * cd(std::cos(a), std::sin(a));
-        if (!dv.P) v *= wpow(k);
+        if (!dv.P && !dv.dense) v *= wpow(k);
         pre[k] = v;
     }
     // Per ring n and mode k <= K_n, one coefficient
@@ -793,6 +809,19 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
         host_fft(v);
         for (int q = 0; q < L; ++q) vhat[q] = make_float2((float)(v[q].real() / L), (float)(v[q].imag() / L));
     }
+    // explicit angles: rows 2k and 2k + 1 of the dense synthesis table hold
+    // cos(k theta_d) and -sin(k theta_d), so that Re(a_k e^{ik theta_d}) =
+    // Re a_k row_2k[d] + Im a_k row_2k+1[d] (angles reduced mod 2 pi in FP64)
+    std::vector<float> syn_tab;
+    if (dv.dense) {
+        syn_tab.resize((size_t)2 * (K + 1) * D);
+        for (int k = 0; k <= K; ++k)
+            for (int q = 0; q < D; ++q) {
+                const double a = std::fmod((double)k * desc->det_theta[q], 2.0 * PI);
+                syn_tab[(size_t)(2 * k) * D + q] = (float)std::cos(a);
+                syn_tab[(size_t)(2 * k + 1) * D + q] = (float)-std::sin(a);
+            }
+    }
 
     {
         int rc = choose_launch(p, ffts.descs, desc->max_batch);
@@ -806,7 +835,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     size_t o_rtwn = tb.add(ringTwn);
     size_t o_coef = tb.add(coef);
     size_t o_ringof = tb.add(ring_of), o_bandof = tb.add(band_of), o_bgeo = tb.add(bgeo), o_bph = tb.add(bphase), o_bptr = tb.add(bptr);
-    size_t o_post = tb.add(post), o_vhat = tb.add(vhat);
+    size_t o_post = tb.add(post), o_vhat = tb.add(vhat), o_syn = tb.add(syn_tab);
     size_t o_ffts = tb.add(ffts.descs), o_tw = tb.add(ffts.tw);
     // store offsets in the pointer fields; relocated after the upload
     auto off = [](size_t o) { return (const void*)(uintptr_t)o; };
@@ -827,6 +856,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     d.band_ptr = (const int*)off(o_bptr);
     d.czt_post = (const float2*)off(o_post);
     d.czt_vhat = (const float2*)off(o_vhat);
+    d.syn_tab = (const float*)off(o_syn);
     d.ffts = (const FftDev*)off(o_ffts);
     d.tw = (const float2*)off(o_tw);
     return PAT_OK;
@@ -860,8 +890,18 @@ extern "C" int pat_plan_create(const pat_plan_desc* desc, pat_plan** out)
     auto rel = [&](auto& ptr) { ptr = (std::remove_reference_t<decltype(ptr)>)(base + (uintptr_t)ptr); };
     rel(d.deap); rel(d.mask_rows); rel(d.pt_geo); rel(d.pt_phase); rel(d.ring_off); rel(d.ring_K);
     rel(d.ring_fft); rel(d.ring_twn); rel(d.ring_joff); rel(d.coef); rel(d.ring_of); rel(d.band_of); rel(d.bpt_geo); rel(d.bpt_phase);
-    rel(d.band_ptr); rel(d.czt_post); rel(d.czt_vhat); rel(d.ffts); rel(d.tw);
+    rel(d.band_ptr); rel(d.czt_post); rel(d.czt_vhat); rel(d.syn_tab); rel(d.ffts); rel(d.tw);
     p->desc = *desc;
+    if (desc->det_theta) {  // the plan keeps its own copy of the angles
+        p->det_theta = (double*)std::malloc(sizeof(double) * (size_t)desc->n_det);
+        if (!p->det_theta) {
+            (void)hipFree(mem);
+            delete p;
+            return PAT_ERR_ALLOC;
+        }
+        std::memcpy(p->det_theta, desc->det_theta, sizeof(double) * (size_t)desc->n_det);
+        p->desc.det_theta = p->det_theta;
+    }
     p->max_batch = desc->max_batch;
     p->n_psi_uniform = dv.n_psi;
     p->M = dv.M;
@@ -886,6 +926,7 @@ extern "C" int pat_plan_query(const pat_plan* p, pat_plan_info* out)
     out->n_points = p->dev.npts;
     out->len_czt = p->dev.syn_len;
     out->syn_stride = p->dev.fold_s;
+    out->syn_dense = p->dev.syn_dense;
     out->n_ring_modes = p->n_ring_modes;
     out->workspace_per_instance = p->ws.bytes;
     out->table_bytes = p->table_bytes;
@@ -905,6 +946,7 @@ extern "C" void pat_plan_destroy(pat_plan* p)
         (void)hipFree(p->table_mem);
         (void)hipSetDevice(cur);
     }
+    std::free(p->det_theta);
     delete p;
 }
 

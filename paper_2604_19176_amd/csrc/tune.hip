@@ -73,15 +73,26 @@ std::string device_name()
     return s;
 }
 
+// FNV-1a of a plan's explicit detector angles (0 for a uniform arc)
+static uint64_t angles_hash(const pat_plan_desc& d)
+{
+    if (!d.det_theta) return 0;
+    uint64_t h = 1469598103934665603ull;
+    const unsigned char* c = (const unsigned char*)d.det_theta;
+    for (size_t i = 0; i < sizeof(double) * (size_t)d.n_det; ++i) h = (h ^ c[i]) * 1099511628211ull;
+    return h;
+}
+
 std::string plan_key(const pat_plan* p, int batch)
 {
     const pat_plan_desc& d = p->desc;
     char buf[512];
     std::snprintf(buf, sizeof buf,
                   "plan n=%d D=%d T=%d arc=%.12g ctr=%.12g dt=%.12g c=%.12g R=%.12g rho=%.12g sig=%.12g em=%d "
-                  "batch=%d dev=%s",
+                  "angles=%016llx batch=%d dev=%s",
                   d.n, d.n_det, d.n_t, d.arc_span, d.arc_center, d.dt, d.c, d.det_r, d.support_r,
-                  d.lambda_oversample, d.em_correction, batch, device_name().c_str());
+                  d.lambda_oversample, d.em_correction, (unsigned long long)angles_hash(d), batch,
+                  device_name().c_str());
     return buf;
 }
 
@@ -95,6 +106,8 @@ std::string batch_key(const pat_batch* b)
     };
     for (const pat_plan* p : b->plans) {
         const pat_plan_desc& d = p->desc;
+        const uint64_t ah = angles_hash(d);
+        mix(&ah, sizeof ah);
         mix(&d.n, sizeof d.n); mix(&d.n_det, sizeof d.n_det); mix(&d.n_t, sizeof d.n_t);
         mix(&d.arc_span, sizeof d.arc_span); mix(&d.arc_center, sizeof d.arc_center); mix(&d.dt, sizeof d.dt);
         mix(&d.c, sizeof d.c); mix(&d.det_r, sizeof d.det_r); mix(&d.support_r, sizeof d.support_r);
@@ -243,15 +256,21 @@ extern "C" int pat_autotune_plan(pat_plan* p, int batch, const char* cache_path)
             used[s] = true;
         }
         if ((rc = pat_plan_set_launch(p, &c)) != PAT_OK) break;
-        float fw[5], ad[5], fmin[5], amin[5];
+        float fw[6], ad[6], fmin[5], amin[5];
         for (int k = 0; k < 5; ++k) fmin[k] = amin[k] = 3.0e38f;
         for (int rep = 0; rep <= kReps && rc == PAT_OK; ++rep) {
-            int cnt = 0;
+            int cf = 0, ca = 0;
             if ((rc = pat_forward(p, f, g, batch, ws, wsb, nullptr)) != PAT_OK) break;
-            if ((rc = pat_profile_read(p, 0, fw, 5, &cnt)) != PAT_OK) break;
+            if ((rc = pat_profile_read(p, 0, fw, 6, &cf)) != PAT_OK) break;
             if ((rc = pat_adjoint(p, g, f, batch, ws, wsb, nullptr)) != PAT_OK) break;
-            if ((rc = pat_profile_read(p, 1, ad, 5, &cnt)) != PAT_OK) break;
+            if ((rc = pat_profile_read(p, 1, ad, 6, &ca)) != PAT_OK) break;
             if (rep == 0) continue;
+            if (cf == 6) {  // dense synthesis: counted with the ring stage (its shape is fixed)
+                fw[3] += fw[4];
+                fw[4] = fw[5];
+                ad[1] += ad[2];
+                for (int k = 2; k < 5; ++k) ad[k] = ad[k + 1];
+            }
             for (int k = 0; k < 5; ++k) {
                 fmin[k] = std::min(fmin[k], fw[k]);
                 amin[k] = std::min(amin[k], ad[k]);

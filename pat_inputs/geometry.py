@@ -105,3 +105,15 @@ def paper_shape_geometry() -> Geometry:
     """The shape of the paper's timed workload (Sec. 4.3 / 2.4.2): a 760^2
     grid, 256 detectors on 270 degrees, 2030 time samples."""
     return _geom(760, 256, 2030, 270.0)
+
+
+def jittered_array_geometry(n: int = 256, n_det: int = 256, n_t: int = 512, arc_deg: float = 180.0,
+                            jitter: float = 0.3, seed: int = 2) -> Geometry:
+    """The limited-view workload's array with each element displaced along the
+    circle by a uniform draw in [-jitter, jitter] element pitches (seeded):
+    a non-uniform array whose angles only the dense synthesis handles."""
+    import numpy as np
+    g = _geom(n, n_det, n_t, arc_deg)
+    pitch = g.arc_span / n_det
+    th = np.asarray(g.det_angles()) + pitch * np.random.default_rng(seed).uniform(-jitter, jitter, n_det)
+    return g.with_(det_theta=tuple(th))

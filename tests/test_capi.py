@@ -213,3 +213,21 @@ def test_batch_and_tuner_entry_points_reject_null_arguments(patlib):
     assert lib.pat_autotune_plan(None, 1, None) == -1
     assert lib.pat_autotune_batch(None, None) == -1
     lib.pat_batch_destroy(None)  # no-op
+
+
+def test_explicit_angles_select_the_dense_synthesis(patlib):
+    """Explicit detector angles (host array in the descriptor) give syn_dense = 1
+    with the same radial/angular sizes as the uniform arc; a non-finite angle is
+    rejected before any allocation."""
+    import paper_2604_19176_amd as pat
+    g = Geometry(n=48, n_det=20, n_t=96, dt=2 / 96, arc_span=math.radians(90))
+    ge = g.with_(det_theta=tuple(np.random.default_rng(1).uniform(-3, 3, 20)))
+    iu = pat.pat_plan_derive(pat.desc_from_geometry(g))
+    ie = pat.pat_plan_derive(pat.desc_from_geometry(ge))
+    assert (iu.syn_dense, ie.syn_dense) == (0, 1)
+    assert (ie.len_czt, ie.syn_stride) == (0, 0)
+    assert (ie.M, ie.n_lam, ie.K, ie.n_psi) == (iu.M, iu.n_lam, iu.K, iu.n_psi)
+    bad = g.with_(det_theta=tuple([0.0] * 19 + [float("nan")]))
+    with pytest.raises(pat.PatError) as e:
+        pat.pat_plan_derive(pat.desc_from_geometry(bad))
+    assert e.value.status == patlib.PAT_ERR_ARG
