@@ -119,7 +119,9 @@ extern "C" int pat_forward(const pat_plan* p, const float* f, float* g, int batc
     prof_mark(p, 0, 4, st);
     const int qd = d.syn_dense ? 5 : 4;  // event index after the synthesis
     if (d.syn_dense) {  // explicit detector angles: synthesis on the matrix cores
-        hipLaunchKernelGGL(k_syn_dense_fwd, dim3(syn_fwd_tiles(d), batch), dim3(kSynThreads), 0, st, d, p->ws, wsp);
+        const int nt = syn_fwd_tiles(d);
+        hipLaunchKernelGGL(k_syn_dense_fwd, dim3(xcd_grid(nt * batch)), dim3(kSynThreads), 0, st, d, p->ws, wsp, nt,
+                           batch);
         if ((rc = check_launch())) return rc;
         prof_mark(p, 0, qd, st);
     }
@@ -147,7 +149,9 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
     prof_mark(p, 1, 1, st);
     const int qa = d.syn_dense ? 1 : 0;  // event offset after the transposed synthesis
     if (d.syn_dense) {  // explicit detector angles: the transposed synthesis on the matrix cores
-        hipLaunchKernelGGL(k_syn_dense_adj, dim3(syn_adj_tiles(d), batch), dim3(kSynThreads), 0, st, d, p->ws, wsp);
+        const int nt = syn_adj_tiles(d);
+        hipLaunchKernelGGL(k_syn_dense_adj, dim3(xcd_grid(nt * batch)), dim3(kSynThreads), 0, st, d, p->ws, wsp, nt,
+                           batch);
         if ((rc = check_launch())) return rc;
         prof_mark(p, 1, 2, st);
     }

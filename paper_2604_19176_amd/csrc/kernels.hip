@@ -565,79 +565,162 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kSynTile = 64;     // output tile side
 constexpr int kSynChunk = 32;    // contraction chunk
 constexpr int kSynThreads = 256; // four waves
+constexpr int kSynLd = kSynChunk + 4;                    // LDS row stride (floats) of the operand fragments
+constexpr int kSynPer = kSynTile * kSynChunk / kSynThreads;  // fragment elements fetched per thread
+constexpr int kSynRows = kSynThreads / kSynChunk;        // rows one fetch step covers
 
+// Operand fragments of a chunk in LDS, [64 tile rows / columns][kSynLd]: the
+// element of contraction index k (0 .. kSynChunk-1) sits in slot
+// (k & 1) * kSynChunk/2 + k / 2, so that the values lane group h = lane / 32
+// feeds to the MFMAs of a chunk (k = 2 i + h) are contiguous: 128-bit LDS reads.
+__device__ __forceinline__ int syn_slot(int k) { return (k & 1) * (kSynChunk / 2) + (k >> 1); }
+
+__device__ __forceinline__ void syn_mfma_chunk(const float (*Ap)[kSynLd], const float (*Bp)[kSynLd], int wm, int wn,
+                                               int lane, f32x16& acc)
+{
+    constexpr int NV = kSynChunk / 8;  // float4 per operand and lane
+    const int h = lane >> 5, rr = lane & 31;
+    const float4* ar = (const float4*)&Ap[wm + rr][h * (kSynChunk / 2)];
+    const float4* br = (const float4*)&Bp[wn + rr][h * (kSynChunk / 2)];
+    float4 a4[NV], b4[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        a4[i] = ar[i];
+        b4[i] = br[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[i].x, b4[i].x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[i].y, b4[i].y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[i].z, b4[i].z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[i].w, b4[i].w, acc, 0, 0, 0);
+    }
+}
+
+// Forward: each chunk, thread t holds kSynPer values of the mode block
+// (ring r = t / kSynChunk + kSynRows i, index c = t % kSynChunk) and kSynPer of
+// the table block (k = t / 64 + 4 i, detector c = t % 64); the next chunk is fetched into
+// registers while the matrix cores work on the current one.  Loads go to
+// clamped in-bounds addresses without branches and masked entries are zeroed
+// afterwards, so all 16 loads of a chunk are in flight together.
 __device__ __forceinline__ void syn_dense_fwd_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile)
 {
-    __shared__ float As[kSynTile][kSynChunk + 1];   // [ring][mode chunk]
-    __shared__ float Bs[kSynChunk][kSynTile + 32];  // [mode chunk][detector]; stride 96: halves on other banks
-    __shared__ int jn[kSynTile];                    // 2 (K_n + 1) of the tile's rings
+    __shared__ __align__(16) float Ap[kSynTile][kSynLd];  // [ring][slot]
+    __shared__ __align__(16) float Bp[kSynTile][kSynLd];  // [detector][slot]
     const int J = 2 * d.Kp, D = d.D, NL = d.nlam;
     const int tq = (D + kSynTile - 1) / kSynTile;
     const int n0 = (tile / tq) * kSynTile, q0 = (tile % tq) * kSynTile;
     const float* __restrict__ A = (const float*)(wb + L.modes);
+    const float* __restrict__ S = d.syn_tab;
     float* __restrict__ H = (float*)(wb + L.hdet);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
-    if (tid < kSynTile) jn[tid] = n0 + tid < NL ? 2 * (d.ring_K[n0 + tid] + 1) : 0;
     const int jmax = 2 * (d.ring_K[min(n0 + kSynTile - 1, NL - 1)] + 1);
+    const int nch = (jmax + kSynChunk - 1) / kSynChunk;
+    // this thread's rings: row offsets and mode limits 2 (K_n + 1) (0 past nlam)
+    int aoff[kSynPer], jlim[kSynPer];
+#pragma unroll
+    for (int i = 0; i < kSynPer; ++i) {
+        const int n = n0 + tid / kSynChunk + kSynRows * i;
+        const int nc = min(n, NL - 1);
+        aoff[i] = nc * J;
+        jlim[i] = n < NL ? 2 * (d.ring_K[nc] + 1) : 0;
+    }
+    const int ca = tid % kSynChunk, cb = tid & 63;
+    const int q = q0 + cb, qc = min(q, D - 1);
+    float ra[kSynPer], rb[kSynPer];
+    auto fetch = [&](int j0) {
+        const int j = j0 + ca, jc = min(j, J - 1);
+#pragma unroll
+        for (int i = 0; i < kSynPer; ++i) {
+            ra[i] = A[aoff[i] + jc];
+            const int jb = j0 + (tid >> 6) + 4 * i;
+            rb[i] = S[(size_t)min(jb, J - 1) * D + qc];
+        }
+#pragma unroll
+        for (int i = 0; i < kSynPer; ++i) {
+            if (j >= jlim[i]) ra[i] = 0.f;
+            if (j0 + (tid >> 6) + 4 * i >= J || q >= D) rb[i] = 0.f;
+        }
+    };
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-    __syncthreads();
-    for (int j0 = 0; j0 < jmax; j0 += kSynChunk) {
-        for (int e = tid; e < kSynTile * kSynChunk; e += kSynThreads) {
-            const int r = e >> 5, c = e & 31, j = j0 + c;
-            As[r][c] = j < jn[r] ? A[(size_t)(n0 + r) * J + j] : 0.f;
-        }
-        for (int e = tid; e < kSynChunk * kSynTile; e += kSynThreads) {
-            const int r = e >> 6, c = e & 63, j = j0 + r, q = q0 + c;
-            Bs[r][c] = (j < J && q < D) ? d.syn_tab[(size_t)j * D + q] : 0.f;
+    if (nch > 0) fetch(0);
+    for (int ch = 0; ch < nch; ++ch) {
+#pragma unroll
+        for (int i = 0; i < kSynPer; ++i) {
+            Ap[tid / kSynChunk + kSynRows * i][syn_slot(ca)] = ra[i];
+            Bp[cb][syn_slot((tid >> 6) + 4 * i)] = rb[i];
         }
         __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < kSynChunk; kk += 2) {
-            const float a = As[wm + (lane & 31)][kk + (lane >> 5)];
-            const float b = Bs[kk + (lane >> 5)][wn + (lane & 31)];
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
-        }
+        if (ch + 1 < nch) fetch((ch + 1) * kSynChunk);
+        syn_mfma_chunk(Ap, Bp, wm, wn, lane, acc);
         __syncthreads();
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        const int n = n0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), q = q0 + wn + (lane & 31);
-        if (n < NL && q < D) H[(size_t)n * D + q] = acc[r];
+        const int n = n0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), qq = q0 + wn + (lane & 31);
+        if (n < NL && qq < D) H[(size_t)n * D + qq] = acc[r];
     }
 }
 
+// Adjoint: both operands are read along the detector index (row
+// r = t / kSynChunk + kSynRows i, detector c = t % kSynChunk), with the same
+// branch-free clamped loads.
 __device__ __forceinline__ void syn_dense_adj_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile)
 {
-    __shared__ float Hs[kSynTile][kSynChunk + 1];   // [ring][detector chunk]
-    __shared__ float St[kSynTile][kSynChunk + 1];   // [table row j][detector chunk]
+    __shared__ __align__(16) float Ap[kSynTile][kSynLd];  // [ring][slot]
+    __shared__ __align__(16) float Bp[kSynTile][kSynLd];  // [table row j][slot]
     const int J = 2 * d.Kp, D = d.D, NL = d.nlam;
     const int tj = (J + kSynTile - 1) / kSynTile;
     const int n0 = (tile / tj) * kSynTile, j0 = (tile % tj) * kSynTile;
     // rows j >= 2 (K_n + 1) of every ring of the tile are never read: skip the tile
     if (j0 >= 2 * (d.ring_K[min(n0 + kSynTile - 1, NL - 1)] + 1)) return;
     const float* __restrict__ H = (const float*)(wb + L.hdet);
+    const float* __restrict__ S = d.syn_tab;
     float* __restrict__ A = (float*)(wb + L.modes);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    const int nch = (D + kSynChunk - 1) / kSynChunk;
+    const int ca = tid % kSynChunk, r0 = tid / kSynChunk;
+    int hoff[kSynPer], soff[kSynPer];
+    unsigned okh = 0, oks = 0;  // row i inside nlam / inside the table
+#pragma unroll
+    for (int i = 0; i < kSynPer; ++i) {
+        const int n = n0 + r0 + kSynRows * i, j = j0 + r0 + kSynRows * i;
+        hoff[i] = min(n, NL - 1) * D;
+        soff[i] = min(j, J - 1) * D;
+        okh |= (n < NL ? 1u : 0u) << i;
+        oks |= (j < J ? 1u : 0u) << i;
+    }
+    float ra[kSynPer], rb[kSynPer];
+    auto fetch = [&](int c0) {
+        const int qv = c0 + ca, qc = min(qv, D - 1);
+#pragma unroll
+        for (int i = 0; i < kSynPer; ++i) {
+            ra[i] = H[hoff[i] + qc];
+            rb[i] = S[soff[i] + qc];
+        }
+#pragma unroll
+        for (int i = 0; i < kSynPer; ++i) {
+            if (qv >= D || !((okh >> i) & 1u)) ra[i] = 0.f;
+            if (qv >= D || !((oks >> i) & 1u)) rb[i] = 0.f;
+        }
+    };
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-    for (int q0 = 0; q0 < D; q0 += kSynChunk) {
-        for (int e = tid; e < kSynTile * kSynChunk; e += kSynThreads) {
-            const int r = e >> 5, c = e & 31, q = q0 + c;
-            Hs[r][c] = (n0 + r < NL && q < D) ? H[(size_t)(n0 + r) * D + q] : 0.f;
-            St[r][c] = (j0 + r < J && q < D) ? d.syn_tab[(size_t)(j0 + r) * D + q] : 0.f;
+    fetch(0);
+    for (int ch = 0; ch < nch; ++ch) {
+#pragma unroll
+        for (int i = 0; i < kSynPer; ++i) {
+            Ap[r0 + kSynRows * i][syn_slot(ca)] = ra[i];
+            Bp[r0 + kSynRows * i][syn_slot(ca)] = rb[i];
         }
         __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < kSynChunk; kk += 2) {
-            const float a = Hs[wm + (lane & 31)][kk + (lane >> 5)];
-            const float b = St[wn + (lane & 31)][kk + (lane >> 5)];
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
-        }
+        if (ch + 1 < nch) fetch((ch + 1) * kSynChunk);
+        syn_mfma_chunk(Ap, Bp, wm, wn, lane, acc);
         __syncthreads();
     }
 #pragma unroll
@@ -1197,16 +1280,26 @@ __global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu
     ring_adj_tile(d, I.L, ws + I.ws_off, tile, I.ring_rt, sm);
 }
 
-// Dense synthesis (explicit detector angles): grid (tiles, batch) for one plan;
-// the _b forms take their instance and tile from the batch tables.
-__global__ __launch_bounds__(kSynThreads) void k_syn_dense_fwd(PlanDev d, WsLayout L, InstPtrs wsp)
+// Dense synthesis (explicit detector angles): `ntile` tiles per instance,
+// instance-major and XCD-contiguous, so one instance's mode coefficients stay
+// in one XCD's L2 while all its tiles read them; the _b forms take their
+// instance and tile from the batch tables.
+__global__ __launch_bounds__(kSynThreads) void k_syn_dense_fwd(PlanDev d, WsLayout L, InstPtrs wsp, int ntile,
+                                                               int batch)
 {
-    syn_dense_fwd_tile(d, L, wsp.ws + (size_t)blockIdx.y * wsp.stride, blockIdx.x);
+    const int item = xcd_item(blockIdx.x, ntile * batch);
+    if (item < 0) return;
+    const int b = item / ntile;
+    syn_dense_fwd_tile(d, L, wsp.ws + (size_t)b * wsp.stride, item - b * ntile);
 }
 
-__global__ __launch_bounds__(kSynThreads) void k_syn_dense_adj(PlanDev d, WsLayout L, InstPtrs wsp)
+__global__ __launch_bounds__(kSynThreads) void k_syn_dense_adj(PlanDev d, WsLayout L, InstPtrs wsp, int ntile,
+                                                               int batch)
 {
-    syn_dense_adj_tile(d, L, wsp.ws + (size_t)blockIdx.y * wsp.stride, blockIdx.x);
+    const int item = xcd_item(blockIdx.x, ntile * batch);
+    if (item < 0) return;
+    const int b = item / ntile;
+    syn_dense_adj_tile(d, L, wsp.ws + (size_t)b * wsp.stride, item - b * ntile);
 }
 
 __global__ __launch_bounds__(kSynThreads) void k_syn_dense_fwd_b(BatchDev bt, char* ws)
