@@ -591,6 +591,48 @@ def bench_dense(args):
     plan.close()
 
 
+def bench_cgls(args):
+    """CGLS, the iterative stand-in for the fast inverse (the deep image
+    prior's input): workload (2), batch B, `--tv-steps` (default 20) steps,
+    two steps per HIP-graph replay."""
+    import numpy as np
+    import torch
+
+    import paper_2604_19176_amd as pat
+    from paper_2604_19176_amd.recon import CGLSReconstructor
+    from pat_inputs import CONFIGS, config_geometry
+
+    dev = torch.device("cuda", 0)
+    cfg, geom, B = CONFIGS[2], config_geometry(2), args.batch
+    plan = pat.PatPlan(geom, max_batch=B)
+    _, f, _, g_meas = make_inputs(np, torch, plan, geom, cfg, B, dev, 1000)
+    launch = plan.autotune(batch=B, cache_path=args.tune_cache) if args.tune else plan.launch
+    steps = args.tv_steps or 20
+    steps += steps % 2
+    rec = CGLSReconstructor(plan, g_meas)
+    r0 = rec.residual_norm()
+    rec.capture()                          # two eager steps + record two
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps // 2):
+        rec.graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    rn = rec.residual_norm()
+    rel = float(np.max(np.asarray(rn) / np.asarray(r0)))
+    out = {"metric": "CGLS steps/s (A p, A* r, two norms, two updates per step; batch of %d)" % B,
+           "value": round(steps * 1000.0 / ms, 2), "unit": "steps/s", "n_gpus": 1, "steps": steps, "warmup": 2,
+           "ms_per_step": round(ms / steps, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "CGLS, limited-view 256x256, 256 detectors on 180 deg, 512 samples, batch %d, "
+                                  "two steps per HIP graph" % B, "batch": B},
+           "relative_residual_after": round(rel, 5), "launch": launch, "tuned": bool(args.tune)}
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -598,7 +640,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--workload", default="default",
-                    choices=["default", "mixed", "tv3", "large", "paper", "pdhg3", "pdhg-large", "dense"])
+                    choices=["default", "mixed", "tv3", "large", "paper", "pdhg3", "pdhg-large", "dense", "cgls"])
     ap.add_argument("--no-tune", dest="tune", action="store_false",
                     help="time the default launch shapes instead of autotuning them first")
     ap.add_argument("--tune-cache", default=None, help="JSON cache file of the autotuner")
@@ -613,6 +655,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "default":
         bench_default(args)
+    elif args.workload == "cgls":
+        bench_cgls(args)
     elif args.workload == "dense":
         bench_dense(args)
     elif args.workload == "mixed":

@@ -170,6 +170,28 @@ int  pat_pd_primal(float* f, float* xbar, const float* aty, const float* y2, int
                    void* stream);
 int  pat_pd_change(const float* f, const float* xbar, float* out, int n, int batch, void* stream);
 
+/* CGLS: conjugate gradients on the normal equations A* A f = A* g, the
+ * iterative stand-in for the fast inverse that produces the network input of
+ * the deep image prior (Sec. 2.3; the paper takes a closed-form inversion
+ * from the cited literature).  From f_0: r = g - A f_0, s = A* r, p = s,
+ * gamma = <s, s>; one step, with every scalar on the device (graph-capturable):
+ *   q = A p (pat_forward);            pat_cg_norm2(q -> qq)
+ *   pat_cg_step_fr:  alpha = gamma / qq;  f += alpha p;  r -= alpha q
+ *   s = A* r (pat_adjoint);           pat_cg_norm2(s -> gamma_new)
+ *   pat_cg_step_p:   p = s + (gamma_new / gamma) p
+ * after which gamma_new is the next step's gamma (callers alternate two
+ * buffers).  Per instance b < batch, with [batch]-major device FP32 arrays:
+ * pat_cg_norm2:   out[b] = sum of x_b^2 over its `count` elements (fixed order).
+ * pat_cg_step_fr: f_b, p_b have nf elements, r_b, q_b nr; gamma, qq [batch];
+ *                 alpha = 0 where qq_b = 0.
+ * pat_cg_step_p:  p_b, s_b have n elements; beta = 0 where gamma_b = 0.
+ * Errors: PAT_ERR_ARG (NULL, counts or batch < 1), PAT_ERR_HIP. */
+int  pat_cg_norm2(const float* x, float* out, long count, int batch, void* stream);
+int  pat_cg_step_fr(float* f, const float* p, long nf, float* r, const float* q, long nr, const float* gamma,
+                    const float* qq, int batch, void* stream);
+int  pat_cg_step_p(float* p, const float* s, long n, const float* gamma_new, const float* gamma, int batch,
+                   void* stream);
+
 /* Per-kernel timing.  pat_profile_enable(plan, 1) creates HIP events; from
  * then on every pat_forward / pat_adjoint call on `plan` records an event
  * before and after each of its kernels on the call's stream (a few

@@ -26,7 +26,8 @@ from ._lib import (PatError, pat_plan_desc, pat_status_string, pat_plan_create, 
                    pat_profile_enable, pat_profile_read, pat_launch, pat_plan_get_launch, pat_plan_set_launch,
                    pat_batch_create, pat_batch_destroy, pat_batch_workspace_size, pat_batch_forward,
                    pat_batch_adjoint, pat_batch_get_launch, pat_batch_set_launch, pat_autotune_plan,
-                   pat_autotune_batch, pat_pd_dual_data, pat_pd_dual_tv, pat_pd_primal, pat_pd_change)
+                   pat_autotune_batch, pat_pd_dual_data, pat_pd_dual_tv, pat_pd_primal, pat_pd_change,
+                   pat_cg_norm2, pat_cg_step_fr, pat_cg_step_p)
 
 __all__ = ["PatPlan", "PatBatch", "pat_operator", "PatOperatorFn", "tv_grad", "pgd_update", "residual",
            "PatError", "desc_from_geometry", "library_path"]

@@ -96,6 +96,9 @@ def load():
         "pat_pd_dual_tv": (ci, [vp, vp, ci, ci, cf, cf, vp]),
         "pat_pd_primal": (ci, [vp, vp, vp, vp, ci, ci, cf, vp]),
         "pat_pd_change": (ci, [vp, vp, vp, ci, ci, vp]),
+        "pat_cg_norm2": (ci, [vp, vp, cl, ci, vp]),
+        "pat_cg_step_fr": (ci, [vp, vp, cl, vp, vp, cl, vp, vp, ci, vp]),
+        "pat_cg_step_p": (ci, [vp, vp, cl, vp, vp, ci, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -256,3 +259,16 @@ def pat_pd_primal(f_ptr, xbar_ptr, aty_ptr, y2_ptr, n, batch, tau, stream) -> No
 
 def pat_pd_change(f_ptr, xbar_ptr, out_ptr, n, batch, stream) -> None:
     _check(load().pat_pd_change(f_ptr, xbar_ptr, out_ptr, int(n), int(batch), stream), "pat_pd_change")
+
+
+def pat_cg_norm2(x_ptr, out_ptr, count, batch, stream) -> None:
+    _check(load().pat_cg_norm2(x_ptr, out_ptr, int(count), int(batch), stream), "pat_cg_norm2")
+
+
+def pat_cg_step_fr(f_ptr, p_ptr, nf, r_ptr, q_ptr, nr, gamma_ptr, qq_ptr, batch, stream) -> None:
+    _check(load().pat_cg_step_fr(f_ptr, p_ptr, int(nf), r_ptr, q_ptr, int(nr), gamma_ptr, qq_ptr, int(batch),
+                                 stream), "pat_cg_step_fr")
+
+
+def pat_cg_step_p(p_ptr, s_ptr, n, gnew_ptr, gamma_ptr, batch, stream) -> None:
+    _check(load().pat_cg_step_p(p_ptr, s_ptr, int(n), gnew_ptr, gamma_ptr, int(batch), stream), "pat_cg_step_p")

@@ -252,6 +252,38 @@ extern "C" int pat_pd_change(const float* f, const float* xbar, float* out, int 
     return check_launch();
 }
 
+static dim3 elementwise_grid(long n, int batch)
+{
+    long blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    return dim3((unsigned)(blocks < 1 ? 1 : blocks), (unsigned)batch);
+}
+
+extern "C" int pat_cg_norm2(const float* x, float* out, long count, int batch, void* stream)
+{
+    if (!x || !out || count < 1 || batch < 1) return PAT_ERR_ARG;
+    hipLaunchKernelGGL(k_cg_norm2, dim3(batch), dim3(1024), 0, (hipStream_t)stream, x, out, count);
+    return check_launch();
+}
+
+extern "C" int pat_cg_step_fr(float* f, const float* p, long nf, float* r, const float* q, long nr,
+                              const float* gamma, const float* qq, int batch, void* stream)
+{
+    if (!f || !p || !r || !q || !gamma || !qq || nf < 1 || nr < 1 || batch < 1) return PAT_ERR_ARG;
+    hipLaunchKernelGGL(k_cg_step_fr, elementwise_grid(nf > nr ? nf : nr, batch), dim3(256), 0, (hipStream_t)stream,
+                       f, p, nf, r, q, nr, gamma, qq);
+    return check_launch();
+}
+
+extern "C" int pat_cg_step_p(float* p, const float* s, long n, const float* gamma_new, const float* gamma, int batch,
+                             void* stream)
+{
+    if (!p || !s || !gamma_new || !gamma || n < 1 || batch < 1) return PAT_ERR_ARG;
+    hipLaunchKernelGGL(k_cg_step_p, elementwise_grid(n, batch), dim3(256), 0, (hipStream_t)stream, p, s, n,
+                       gamma_new, gamma);
+    return check_launch();
+}
+
 extern "C" int pat_profile_enable(pat_plan* p, int enable)
 {
     if (!p) return PAT_ERR_ARG;

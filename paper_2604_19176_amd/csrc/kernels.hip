@@ -1578,4 +1578,44 @@ __global__ __launch_bounds__(1024) void k_pd_change(const float* __restrict__ f,
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// CGLS pieces (one workgroup per instance for the norms: fixed-order sums)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_cg_norm2(const float* __restrict__ x, float* __restrict__ out, long per)
+{
+    __shared__ float red_s[1024];
+    const int b = blockIdx.x;
+    const float* xb = x + (size_t)b * per;
+    float acc = 0.f;
+    for (long e = threadIdx.x; e < per; e += blockDim.x) acc += xb[e] * xb[e];
+    const float t = block_sum(acc, red_s);
+    if (threadIdx.x == 0) out[b] = t;
+}
+
+__global__ void k_cg_step_fr(float* __restrict__ f, const float* __restrict__ p, long nf, float* __restrict__ r,
+                             const float* __restrict__ q, long nr, const float* __restrict__ gamma,
+                             const float* __restrict__ qq)
+{
+    const int b = blockIdx.y;
+    const float den = qq[b];
+    const float alpha = den > 0.f ? gamma[b] / den : 0.f;
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nf; e += stride)
+        f[(size_t)b * nf + e] += alpha * p[(size_t)b * nf + e];
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nr; e += stride)
+        r[(size_t)b * nr + e] -= alpha * q[(size_t)b * nr + e];
+}
+
+__global__ void k_cg_step_p(float* __restrict__ p, const float* __restrict__ s, long n,
+                            const float* __restrict__ gamma_new, const float* __restrict__ gamma)
+{
+    const int b = blockIdx.y;
+    const float den = gamma[b];
+    const float beta = den > 0.f ? gamma_new[b] / den : 0.f;
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
+        p[(size_t)b * n + e] = s[(size_t)b * n + e] + beta * p[(size_t)b * n + e];
+}
+
 }  // namespace pat

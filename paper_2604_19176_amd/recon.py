@@ -204,3 +204,96 @@ class PDHGReconstructor:
             if tol is not None and max(self.relative_change()) <= tol:
                 break
         return self.iterations
+
+
+class CGLSReconstructor:
+    """CGLS (conjugate gradients on A* A f = A* g): the iterative stand-in for
+    the fast inverse that gives the deep image prior its input (Sec. 2.3).
+    Every scalar stays on the device; two consecutive steps (which alternate
+    the two gamma buffers) can be captured as one HIP graph."""
+
+    def __init__(self, plan: PatPlan, g_meas: torch.Tensor, f0: torch.Tensor | None = None):
+        from . import _stream, pat_cg_norm2
+        self.plan = plan
+        self.g_meas = g_meas.contiguous()
+        self.batch = 1 if g_meas.dim() == 2 else int(g_meas.shape[0])
+        shape = g_meas.shape[:-2] + plan.image_shape
+        dev = plan.device
+        self.f = (torch.zeros(shape, device=dev, dtype=torch.float32) if f0 is None
+                  else f0.clone().contiguous())
+        self.nf = plan.geom.n * plan.geom.n
+        self.nr = plan.geom.n_det * plan.geom.n_t
+        self.r = torch.empty_like(self.g_meas)
+        self.q = torch.empty_like(self.g_meas)
+        self.s = torch.empty_like(self.f)
+        self.gam = torch.zeros(2, self.batch, device=dev, dtype=torch.float32)
+        self.qq = torch.zeros(self.batch, device=dev, dtype=torch.float32)
+        self.rr = torch.zeros(self.batch, device=dev, dtype=torch.float32)
+        # r = g - A f0, s = A* r, p = s, gamma = <s, s>
+        self.r.copy_(self.g_meas)
+        if f0 is not None:  # r -= 1 * A f0 with the CGLS update kernel (f += 1 * 0 leaves f alone)
+            from . import pat_cg_step_fr
+            plan.forward(self.f, out=self.q)
+            one = torch.ones(self.batch, device=dev, dtype=torch.float32)
+            zero = torch.zeros_like(self.f)
+            pat_cg_step_fr(self.f.data_ptr(), zero.data_ptr(), self.nf, self.r.data_ptr(), self.q.data_ptr(),
+                           self.nr, one.data_ptr(), one.data_ptr(), self.batch, _stream(dev))
+        plan.adjoint(self.r, out=self.s)
+        self.p = self.s.clone()
+        pat_cg_norm2(self.s.data_ptr(), self.gam[0].data_ptr(), self.nf, self.batch, _stream(dev))
+        self.cur = 0
+        self.graph = None
+        self.iterations = 0
+
+    def _step(self, cur):
+        from . import _stream, pat_cg_norm2, pat_cg_step_fr, pat_cg_step_p
+        st = _stream(self.f.device)
+        B = self.batch
+        g_cur, g_new = self.gam[cur], self.gam[1 - cur]
+        self.plan.forward(self.p, out=self.q)
+        pat_cg_norm2(self.q.data_ptr(), self.qq.data_ptr(), self.nr, B, st)
+        pat_cg_step_fr(self.f.data_ptr(), self.p.data_ptr(), self.nf, self.r.data_ptr(), self.q.data_ptr(), self.nr,
+                       g_cur.data_ptr(), self.qq.data_ptr(), B, st)
+        self.plan.adjoint(self.r, out=self.s)
+        pat_cg_norm2(self.s.data_ptr(), g_new.data_ptr(), self.nf, B, st)
+        pat_cg_step_p(self.p.data_ptr(), self.s.data_ptr(), self.nf, g_new.data_ptr(), g_cur.data_ptr(), B, st)
+
+    def step(self):
+        self._step(self.cur)
+        self.cur = 1 - self.cur
+        self.iterations += 1
+
+    def capture(self):
+        """Record two steps as a HIP graph (runs two steps eagerly first)."""
+        s = torch.cuda.Stream(device=self.plan.device)
+        s.wait_stream(torch.cuda.current_stream(self.plan.device))
+        with torch.cuda.stream(s):
+            self.step()
+            self.step()
+        torch.cuda.current_stream(self.plan.device).wait_stream(s)
+        cur = self.cur
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._step(cur)
+            self._step(1 - cur)
+        return self.graph
+
+    def residual_norm(self):
+        """||g - A f|| per instance (from the recursively updated residual)."""
+        from . import _stream, pat_cg_norm2
+        pat_cg_norm2(self.r.data_ptr(), self.rr.data_ptr(), self.nr, self.batch, _stream(self.f.device))
+        return self.rr.double().sqrt().cpu().tolist()
+
+    def run(self, iters: int, use_graph: bool = True):
+        """`iters` more steps (an even count with the graph: it holds two)."""
+        if use_graph:
+            if self.graph is None:
+                self.capture()  # two eager steps
+                iters -= 2
+            while iters >= 2:
+                self.graph.replay()
+                self.iterations += 2
+                iters -= 2
+        for _ in range(iters):
+            self.step()
+        return self.iterations
