@@ -633,6 +633,56 @@ def bench_cgls(args):
     plan.close()
 
 
+def bench_dip(args):
+    """Deep image prior (eq. (5)) at the paper's timed shape: U-Net forward and
+    backward (float32, stock layers), A and A* in this library's kernels, the
+    TV kernel, an Adam step; the input z from 10 CGLS steps."""
+    import numpy as np
+    import torch
+
+    import paper_2604_19176_amd as pat
+    from paper_2604_19176_amd.dip import DIPReconstructor
+    from paper_2604_19176_amd.recon import CGLSReconstructor
+    from pat_inputs import paper_shape_geometry
+
+    dev = torch.device("cuda", 0)
+    geom = paper_shape_geometry()
+    plan = pat.PatPlan(geom, max_batch=1)
+    cfg = dict(phantom=(20, 3, 4), noise=0.01, seed=760)
+    _, f, _, g_meas = make_inputs(np, torch, plan, geom, cfg, 1, dev, 1)
+    g1 = g_meas[0].contiguous()
+    launch = plan.autotune(batch=1, cache_path=args.tune_cache) if args.tune else plan.launch
+    cg = CGLSReconstructor(plan, g1)
+    for _ in range(10):
+        cg.step()
+    steps = args.steps
+    rec = DIPReconstructor(plan, g1, cg.f, lam=0.1, iters=steps + args.warmup)
+    for _ in range(args.warmup):
+        rec.step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        rec.step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    gout, fout = torch.empty_like(g1), torch.empty_like(f[0])
+    kms = kernel_times(pat, plan, f[0].contiguous(), g1, gout, fout, 5)
+    op_ms = sum(kms.values())
+    out = {"metric": "DIP iterations/s at the paper's timed shape (U-Net fwd+bwd, A, A*, TV, Adam)",
+           "value": round(1000.0 / ms, 2), "unit": "iterations/s", "n_gpus": 1, "steps": steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "DIP, 760x760, 256 detectors on 270 deg, 2030 samples, batch 1, U-Net 32-256 "
+                                  "channels", "batch": 1},
+           "operator_pair_ms": round(op_ms, 4), "operator_share": round(op_ms / ms, 4),
+           "paper_context": "142.9 ms per DIP iteration on an RTX A5000 (Sec. 4.3; other hardware)",
+           "final_objective": float(rec.last_loss), "launch": launch, "tuned": bool(args.tune)}
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -640,7 +690,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--workload", default="default",
-                    choices=["default", "mixed", "tv3", "large", "paper", "pdhg3", "pdhg-large", "dense", "cgls"])
+                    choices=["default", "mixed", "tv3", "large", "paper", "pdhg3", "pdhg-large", "dense", "cgls",
+                             "dip"])
     ap.add_argument("--no-tune", dest="tune", action="store_false",
                     help="time the default launch shapes instead of autotuning them first")
     ap.add_argument("--tune-cache", default=None, help="JSON cache file of the autotuner")
@@ -655,6 +706,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "default":
         bench_default(args)
+    elif args.workload == "dip":
+        bench_dip(args)
     elif args.workload == "cgls":
         bench_cgls(args)
     elif args.workload == "dense":
