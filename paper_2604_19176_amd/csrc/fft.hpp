@@ -302,18 +302,51 @@ struct TwLds {
 // Number of float2 slots tw_lds_build needs for length n.
 __host__ __device__ inline int tw_lds_slots(int n) { return 64 + (n + 63) / 64; }
 
-// Fill the two-level table of length d.n at `dst` from the plan's table of
-// w_n^e (e < n).  Caller synchronises before use.
+// Entry e of the two-level table of length d.n, read from the plan's table of
+// w_n^e (e < n).
+__device__ __forceinline__ float2 tw_lds_entry(const FftDev& d, const float2* __restrict__ twall, int e)
+{
+    const unsigned idx = e < 64 ? e : 64 * (e - 64);
+    return twall[d.tw + (int)(idx % (unsigned)d.n)];
+}
+
+// The first two entries per thread of a two-level table (e = threadIdx.x and
+// threadIdx.x + blockDim.x), loaded into registers so that the loads can be
+// in flight together with others (indices past the table are clamped, not
+// branched around); tw_lds_store writes them and the rest.
+struct TwFetch {
+    float2 v[2];
+};
+
+__device__ __forceinline__ TwFetch tw_lds_fetch(const FftDev& d, const float2* __restrict__ twall)
+{
+    const int cnt = tw_lds_slots(d.n);
+    TwFetch f;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        f.v[i] = tw_lds_entry(d, twall, min((int)(threadIdx.x + i * blockDim.x), cnt - 1));
+    }
+    return f;
+}
+
+// Fill the two-level table of length d.n at `dst` (the fetched entries plus
+// any beyond two per thread).  Caller synchronises before use.
+__device__ __forceinline__ TwLds tw_lds_store(float2* dst, const FftDev& d, const float2* __restrict__ twall,
+                                              const TwFetch& f)
+{
+    const int cnt = tw_lds_slots(d.n);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int e = threadIdx.x + i * blockDim.x;
+        if (e < cnt) dst[e] = f.v[i];
+    }
+    for (int e = threadIdx.x + 2 * blockDim.x; e < cnt; e += blockDim.x) dst[e] = tw_lds_entry(d, twall, e);
+    return TwLds{dst, dst + 64, 0};
+}
+
 __device__ __forceinline__ TwLds tw_lds_build(float2* dst, const FftDev& d, const float2* __restrict__ twall)
 {
-    const float2* tw = twall + d.tw;
-    const int nhi = (d.n + 63) / 64;
-    for (int e = threadIdx.x; e < 64 + nhi; e += blockDim.x) {
-        int idx = e < 64 ? e : 64 * (e - 64);
-        while (idx >= d.n) idx -= d.n;
-        dst[e] = tw[idx];
-    }
-    return TwLds{dst, dst + 64, 0};
+    return tw_lds_store(dst, d, twall, tw_lds_fetch(d, twall));
 }
 
 }  // namespace pat

@@ -293,13 +293,40 @@ __device__ __forceinline__ float2 real_unpack(const float2* Z, int H, int k, flo
     return make_float2(0.5f * (sm.x + t.y), 0.5f * (sm.y - t.x));
 }
 
+// st(t, ld(t)) for t < count by the workgroup (t = t0 + threadIdx.x + j blockDim.x,
+// U values of t per thread and chunk).  A chunk issues all of a thread's loads
+// before its first store, and no load sits under a divergent branch (indices
+// past the end are clamped to count - 1 and their values dropped), so a chunk
+// waits for one memory latency instead of one per element.
+template <int U, class Ld, class St>
+__device__ __forceinline__ void fill_batched(int count, Ld ld, St st)
+{
+    const int tid = threadIdx.x, bd = blockDim.x;
+    for (int t0 = 0; t0 < count; t0 += U * bd) {
+        decltype(ld(0)) v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) v[j] = ld(min(t0 + tid + j * bd, count - 1));
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int t = t0 + tid + j * bd;
+            if (t < count) st(t, v[j]);
+        }
+    }
+}
+
+struct IdxVal {
+    int i;
+    float2 v;
+};
+
 // Layout of the ring kernels' dynamic LDS (float2 slots, ring_lds_slots):
 // sa (ring FFT; the half-length synthesis buffer sc shares it), sy
 // (synthesis), and the two-level twiddles of lengths Npsi(n) (twN) and S
 // (twA) used outside the transforms.  The transforms read their per-pass
-// twiddles from the plan's table in global memory (a few KB shared by all
-// rings of a length, cache resident), which keeps the LDS per ring small
-// enough for three workgroups per CU at the largest sizes.
+// twiddles, and the mode loops the ring's coefficients, from global memory
+// (tables shared by all instances of a plan, cache resident): small LDS per
+// ring keeps many rings resident per CU, and nothing is held in registers
+// across a transform.
 struct RingLds {
     float2 *sa, *sc, *sy, *twN, *twA;
 };
@@ -341,37 +368,35 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
         float* hn = hT + (size_t)n * D;
         const FftDev& fR = d.ffts[d.ring_fft[n]];
         const float2* __restrict__ tbR = d.tw + fR.tb;
-        // this thread's modes k = tid + j bd: coefficients fetched before the FFT
-        float2 cpre[kRingModesPerThread];
+        const FftDev& fN = d.ffts[d.ring_twn[n]];
+        // the ring's inputs, all loads in flight together: twiddles w_{2P}^k (twN)
+        // and the polar values, packed as follows:
+        // q(m) = Re F + Im F (m < P), Re F - Im F (m >= P) is real; z(t) = q(2t) + i q(2t+1)
+        const TwFetch twf = tw_lds_fetch(fN, d.tw);
+        fill_batched<kRingFillUnroll>(
+            P,
+            [&](int t) {
+                float qv[2];
 #pragma unroll
-        for (int j = 0; j < kRingModesPerThread; ++j) {
-            const int k = tid + j * bd;
-            cpre[j] = k <= Kn ? cf[k] : make_float2(0.f, 0.f);
-        }
-        const TwLds twN = tw_lds_build(R.twN, d.ffts[d.ring_twn[n]], d.tw);  // w_{2P}^k
-        // q(m) = Re F + Im F (m < P), Re F - Im F (m >= P) is real; pack z(t) = q(2t) + i q(2t+1)
-        for (int t = tid; t < P; t += bd) {
-            float qv[2];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int m = 2 * t + u;
-                const bool lo = m < P;
-                const float2 F = Fp[off + (lo ? m : m - P)];
-                qv[u] = lo ? F.x + F.y : F.x - F.y;
-            }
-            R.sa[t] = make_float2(qv[0], qv[1]);
-        }
+                for (int u = 0; u < 2; ++u) {
+                    const int m = 2 * t + u;
+                    const bool lo = m < P;
+                    const float2 F = Fp[off + (lo ? m : m - P)];
+                    qv[u] = lo ? F.x + F.y : F.x - F.y;
+                }
+                return make_float2(qv[0], qv[1]);
+            },
+            [&](int t, float2 v) { R.sa[t] = v; });
+        const TwLds twN = tw_lds_store(R.twN, fN, d.tw, twf);
         __syncthreads();
         fft_lds<false, kRingFftMaxButterflies>(R.sa, P, 1, fR, tbR);
         if (d.syn_dense) {
             // explicit detector angles: the mode coefficients a_k go to the workspace;
             // the dense product with the cos/sin table synthesises the detectors
             float2* am = (float2*)(wb + L.modes) + (size_t)n * d.Kp;
-#pragma unroll
-            for (int j = 0; j < kRingModesPerThread; ++j) {
-                const int k = tid + j * bd;
-                if (k <= Kn) am[k] = cmul(cpre[j], real_unpack(R.sa, P, k, twN(k)));
-            }
+            fill_batched<kRingFillUnroll>(
+                Kn + 1, [&](int k) { return cmul(cf[k], real_unpack(R.sa, P, k, twN(k))); },
+                [&](int k, float2 v) { am[k] = v; });
             __syncthreads();
             continue;
         }
@@ -383,14 +408,14 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
             if (q > Kn) R.sy[q] = make_float2(0.f, 0.f);
         for (int base = 0; base <= Kn; base += Pf) {
             if (base) __syncthreads();
-#pragma unroll
-            for (int j = 0; j < kRingModesPerThread; ++j) {
-                const int k = tid + j * bd;
-                if (k <= Kn && k >= base && k < base + Pf) {
-                    const float2 a = cmul(cpre[j], real_unpack(R.sa, P, k, twN(k)));
-                    R.sy[k - base] = base ? cadd(R.sy[k - base], a) : a;
-                }
-            }
+            fill_batched<kRingFillUnroll>(
+                min(Kn + 1 - base, Pf),
+                [&](int t) {
+                    const int k = base + t;
+                    const float2 a = cmul(cf[k], real_unpack(R.sa, P, k, twN(k)));
+                    return base ? cadd(R.sy[t], a) : a;
+                },
+                [&](int t, float2 v) { R.sy[t] = v; });
         }
         __syncthreads();
         if (d.fold_P) {
@@ -437,7 +462,8 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
 __device__ __forceinline__ float grid_det(const float* hn, int j, int s, int D)
 {
     const int q = s == 1 ? j : j / s;
-    return (q * s == j && q < D) ? hn[q] : 0.f;
+    const float v = hn[min(q, D - 1)];  // unconditional load (batched by the caller), value selected
+    return (q * s == j && q < D) ? v : 0.f;
 }
 
 __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile, int RT,
@@ -467,35 +493,50 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
         const float2* __restrict__ am = (const float2*)(wb + L.modes) + (size_t)n * d.Kp;
         const FftDev& fR = d.ffts[d.ring_fft[n]];
         const float2* __restrict__ tbR = d.tw + fR.tb;
-        float2 cpre[kRingModesPerThread];
-#pragma unroll
-        for (int j = 0; j < kRingModesPerThread; ++j) {
-            const int k = tid + j * bd;
-            cpre[j] = k <= Kn ? cf[k] : make_float2(0.f, 0.f);
-        }
-        const TwLds twN = tw_lds_build(R.twN, d.ffts[d.ring_twn[n]], d.tw);
-        // y~ = FFT of the real detector values, zero-padded to the synthesis length
+        const FftDev& fN = d.ffts[d.ring_twn[n]];
+        const TwFetch twf = tw_lds_fetch(fN, d.tw);
+        // the ring's inputs, all loads in flight together: twiddles (twN) and the
+        // detector values zero-padded to the synthesis length; then y~ = their
+        // FFT.  Explicit angles: Q~ directly.
         if (d.syn_dense) {
+            fill_batched<kRingFillUnroll>(
+                Kn + 1, [&](int k) { return cmulc(am[k], cf[k]); }, [&](int k, float2 v) { qb[k] = v; });
+            tw_lds_store(R.twN, fN, d.tw, twf);
         } else if (half) {
             const int H2 = d.fold_P / 2;
-            for (int t = tid; t < H2; t += bd)
-                R.sc[t] = make_float2(grid_det(hn, 2 * t, d.fold_s, D), grid_det(hn, 2 * t + 1, d.fold_s, D));
+            fill_batched<kRingFillUnroll>(
+                H2,
+                [&](int t) {
+                    return make_float2(grid_det(hn, 2 * t, d.fold_s, D), grid_det(hn, 2 * t + 1, d.fold_s, D));
+                },
+                [&](int t, float2 v) { R.sc[t] = v; });
+            tw_lds_store(R.twN, fN, d.tw, twf);
             __syncthreads();
             fft_lds<false, kRingFftMaxButterflies>(R.sc, H2, 1, fS, tbS);
         } else if (d.fold_P) {
-            for (int sidx = tid; sidx < S; sidx += bd)
-                R.sy[sidx] = make_float2(grid_det(hn, sidx, d.fold_s, D), 0.f);
+            fill_batched<kRingFillUnroll>(
+                S, [&](int t) { return make_float2(grid_det(hn, t, d.fold_s, D), 0.f); },
+                [&](int t, float2 v) { R.sy[t] = v; });
+            tw_lds_store(R.twN, fN, d.tw, twf);
             __syncthreads();
             fft_lds<false, kRingFftMaxButterflies>(R.sy, S, 1, fS, tbS);
         } else {
-            for (int q = tid; q < S; q += bd)
-                R.sy[q] = q < D ? cmulc(make_float2(hn[q], 0.f), d.czt_post[q]) : make_float2(0.f, 0.f);
+            fill_batched<kRingFillUnroll>(
+                S,
+                [&](int q) {
+                    const int qc = min(q, D - 1);
+                    const float2 v = cmulc(make_float2(hn[qc], 0.f), d.czt_post[qc]);
+                    return q < D ? v : make_float2(0.f, 0.f);
+                },
+                [&](int q, float2 v) { R.sy[q] = v; });
+            tw_lds_store(R.twN, fN, d.tw, twf);
             __syncthreads();
             fft_lds<false, kRingFftMaxButterflies>(R.sy, S, 1, fS, tbS);
             for (int q = tid; q < S; q += bd) R.sy[q] = cmulc(R.sy[q], d.czt_vhat[q]);
             __syncthreads();
             fft_lds<true, kRingFftMaxButterflies>(R.sy, S, 1, fS, tbS);
         }
+        const TwLds twN{R.twN, R.twN + 64, 0};
         // y~ at synthesis index sidx (0 <= sidx < S)
         auto ytil = [&](int sidx) {
             if (!half) return R.sy[sidx];
@@ -507,14 +548,14 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
             return hi ? cconj(v) : v;
         };
         // Q~_k = conj(coef_k) y~_{k mod Pf}
-#pragma unroll
-        for (int j = 0; j < kRingModesPerThread; ++j) {
-            const int k = tid + j * bd;
-            if (k <= Kn) {
-                int sidx = k;
-                if (d.fold_P) while (sidx >= d.fold_P) sidx -= d.fold_P;
-                qb[k] = cmulc(d.syn_dense ? am[k] : ytil(sidx), cpre[j]);
-            }
+        if (!d.syn_dense) {
+            fill_batched<kRingFillUnroll>(
+                Kn + 1,
+                [&](int k) {
+                    const int sidx = d.fold_P ? k % d.fold_P : k;
+                    return cmulc(ytil(sidx), cf[k]);
+                },
+                [&](int k, float2 v) { qb[k] = v; });
         }
         __syncthreads();
         // Re(IFFT_{2P}(Q~)) as a half-length inverse FFT: E + i O from the
@@ -534,15 +575,18 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
         __syncthreads();
         fft_lds<true, kRingFftMaxButterflies>(eb, P, 1, fR, tbR);
         // q~(m): m = 2t -> Re z_t, m = 2t + 1 -> Im z_t;  F~_h(l) = (q~(l) + q~(l+P)) + i (q~(l) - q~(l+P))
-        for (int l = tid; l < P; l += bd) {
-            const float2 z1 = eb[l >> 1];
-            const float a = (l & 1) ? z1.y : z1.x;
-            const int m = l + P;
-            const float2 z2 = eb[m >> 1];
-            const float c = (m & 1) ? z2.y : z2.x;
-            const float2 Fh = make_float2(a + c, a - c);
-            Hb[d.band_of[off + l]] = cmulc(Fh, d.pt_phase[off + l]);
-        }
+        fill_batched<kRingFillUnroll>(
+            P,
+            [&](int l) {
+                const float2 z1 = eb[l >> 1];
+                const float a = (l & 1) ? z1.y : z1.x;
+                const int m = l + P;
+                const float2 z2 = eb[m >> 1];
+                const float c = (m & 1) ? z2.y : z2.x;
+                const float2 Fh = make_float2(a + c, a - c);
+                return IdxVal{d.band_of[off + l], cmulc(Fh, d.pt_phase[off + l])};
+            },
+            [&](int, IdxVal iv) { Hb[iv.i] = iv.v; });
         __syncthreads();
     }
 }
@@ -1236,11 +1280,11 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_b(BatchDev bt, char* 
     gather_tile<1, CB>(d, I.L, wbs, 1, tile, I.gat_th, win);
 }
 
-// Ring kernels: at most kRingMaxThreads threads (one wave for most rings).  The
-// adjoint is held to 128 VGPRs (four waves per SIMD) where it does not spill;
-// the forward needs more registers for its coefficient prefetch and runs best
-// unconstrained (three waves per SIMD, no spills).
-__global__ __launch_bounds__(kRingMaxThreads) void k_ring_fwd(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
+// Ring kernels: at most kRingMaxThreads threads (one wave for most rings).  Both
+// are held to 128 VGPRs (four waves per SIMD), where the per-instance kernels
+// do not spill: they are latency bound, so resident waves count more than the
+// extra registers an unconstrained schedule would take.
+__global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_ring_fwd(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
 {
     extern __shared__ float2 sm[];
     const int ntile = (d.nlam + RT - 1) / RT;
@@ -1250,7 +1294,7 @@ __global__ __launch_bounds__(kRingMaxThreads) void k_ring_fwd(PlanDev d, WsLayou
     ring_fwd_tile(d, L, wsp.ws + (size_t)b * wsp.stride, item - b * ntile, RT, sm);
 }
 
-__global__ __launch_bounds__(kRingMaxThreads) void k_ring_fwd_b(BatchDev bt, char* ws)
+__global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_ring_fwd_b(BatchDev bt, char* ws)
 {
     extern __shared__ float2 sm[];
     int i, tile;

@@ -142,10 +142,11 @@ __host__ __device__ constexpr size_t spread_lds_words(int CAP, int IB)
     return (size_t)CAP * (17 + 2 * IB) + 3 * (size_t)(CAP / 2 + 10);
 }
 
-// Ring kernels: modes k = thread + j * threads (j < kRingModesPerThread) of a
-// ring are handled by one thread (coefficients prefetched into registers), so
-// a ring workgroup has at least (K + 1) / kRingModesPerThread threads.
+// Ring kernels: a ring workgroup has at least (K + 1) / kRingModesPerThread
+// threads; its fills of ring inputs issue kRingFillUnroll loads per thread
+// and input at a time (more would cost the transforms registers).
 constexpr int kRingModesPerThread = 8;
+constexpr int kRingFillUnroll = 4;
 constexpr int kRingMaxThreads = 256;
 // Their LDS in float2 slots: ring buffer (aliased by the half-length
 // synthesis buffer), synthesis buffer, two-level twiddle tables of lengths
