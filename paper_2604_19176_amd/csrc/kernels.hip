@@ -92,6 +92,32 @@ struct InstPtrs {
     size_t stride;    // bytes per instance
 };
 
+// st(t, ld(t)) for t < count by the workgroup (t = t0 + threadIdx.x + j blockDim.x,
+// U values of t per thread and chunk).  A chunk issues all of a thread's loads
+// before its first store, and no load sits under a divergent branch (indices
+// past the end are clamped to count - 1 and their values dropped), so a chunk
+// waits for one memory latency instead of one per element.
+template <int U, class Ld, class St>
+__device__ __forceinline__ void fill_batched(int count, Ld ld, St st)
+{
+    const int tid = threadIdx.x, bd = blockDim.x;
+    for (int t0 = 0; t0 < count; t0 += U * bd) {
+        decltype(ld(0)) v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) v[j] = ld(min(t0 + tid + j * bd, count - 1));
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int t = t0 + tid + j * bd;
+            if (t < count) st(t, v[j]);
+        }
+    }
+}
+
+struct IdxVal {
+    int i;
+    float2 v;
+};
+
 // ---------------------------------------------------------------------------
 // forward: column pass (FFT along y of real columns, packed in pairs)
 // ---------------------------------------------------------------------------
@@ -225,12 +251,19 @@ __device__ __forceinline__ void gather_tile(const PlanDev& d, const WsLayout& L,
         if (b >= nb) break;
         const float2* __restrict__ G = (const float2*)(wbs[b] + L.grid);
         float2* wn = win + b * RW;
-        for (int e = threadIdx.x; e < RW; e += blockDim.x) {
-            const int rr = e / W, cc = e - rr * W;
-            const int r = R0 + rr;
-            const int c = (C0 + cc) % Ng;
-            wn[e] = r < Hy ? G[(size_t)r * Ng + c] : make_float2(0.f, 0.f);
-        }
+        // window rows R0 .. R0 + TH + 6 (zero past the stored rows), columns
+        // C0 .. C0 + CB + 6 wrapped mod Ng (C0 + CB + 6 < 2 Ng)
+        fill_batched<4>(
+            RW,
+            [&](int e) {
+                const int rr = e / W, cc = e - rr * W;
+                const int r = R0 + rr;
+                int c = C0 + cc;
+                c = c >= Ng ? c - Ng : c;
+                const float2 v = G[(size_t)min(r, Hy - 1) * Ng + c];
+                return r < Hy ? v : make_float2(0.f, 0.f);
+            },
+            [&](int e, float2 v) { wn[e] = v; });
     }
     if ((int)threadIdx.x < nbands) {
         const int* bp = d.band_ptr + (size_t)(R0 + threadIdx.x) * (Ng + 1);
@@ -242,14 +275,26 @@ __device__ __forceinline__ void gather_tile(const PlanDev& d, const WsLayout& L,
     const int bnd = threadIdx.x / Q, u = threadIdx.x - bnd * Q;
     if (bnd >= nbands) return;          // no barrier follows
     const int hi = seg_hi[bnd];
-    for (int s = seg_lo[bnd] + u; s < hi; s += Q) {
-        const float4 gq = d.bpt_geo[s];
+    // the next point's geometry is loaded while the current one is interpolated
+    // (index clamped to the segment's last point, or to point 0 for an empty
+    // segment at the start: always a valid point)
+    const int slast = max(hi - 1, 0);
+    int s = seg_lo[bnd] + u;
+    float4 ngq = d.bpt_geo[min(s, slast)];
+    float2 nph = d.bpt_phase[min(s, slast)];
+    int nri = d.ring_of[min(s, slast)];
+    for (; s < hi; s += Q) {
+        const float4 gq = ngq;
+        const float2 ph = nph;
+        const int ri = nri;
+        const int sn = min(s + Q, slast);
+        ngq = d.bpt_geo[sn];
+        nph = d.bpt_phase[sn];
+        nri = d.ring_of[sn];
         const int c0 = fbits(gq.x) - C0;
         float wx[8], wy[8];
         es_weights8(gq.z, wx);
         es_weights8(gq.w, wy);
-        const float2 ph = d.bpt_phase[s];
-        const int ri = d.ring_of[s];
 #pragma unroll
         for (int b = 0; b < IB; ++b) {
             if (b >= nb) break;
@@ -292,32 +337,6 @@ __device__ __forceinline__ float2 real_unpack(const float2* Z, int H, int k, flo
     const float2 t = cmul(wk, df);
     return make_float2(0.5f * (sm.x + t.y), 0.5f * (sm.y - t.x));
 }
-
-// st(t, ld(t)) for t < count by the workgroup (t = t0 + threadIdx.x + j blockDim.x,
-// U values of t per thread and chunk).  A chunk issues all of a thread's loads
-// before its first store, and no load sits under a divergent branch (indices
-// past the end are clamped to count - 1 and their values dropped), so a chunk
-// waits for one memory latency instead of one per element.
-template <int U, class Ld, class St>
-__device__ __forceinline__ void fill_batched(int count, Ld ld, St st)
-{
-    const int tid = threadIdx.x, bd = blockDim.x;
-    for (int t0 = 0; t0 < count; t0 += U * bd) {
-        decltype(ld(0)) v[U];
-#pragma unroll
-        for (int j = 0; j < U; ++j) v[j] = ld(min(t0 + tid + j * bd, count - 1));
-#pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const int t = t0 + tid + j * bd;
-            if (t < count) st(t, v[j]);
-        }
-    }
-}
-
-struct IdxVal {
-    int i;
-    float2 v;
-};
 
 // Layout of the ring kernels' dynamic LDS (float2 slots, ring_lds_slots):
 // sa (ring FFT; the half-length synthesis buffer sc shares it), sy
@@ -422,26 +441,33 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
             if (d.syn_half) {
                 // Re(IFFT_P(y)) as a half-length inverse FFT of the Hermitian part
                 const int H2 = Pf / 2;
-                for (int sidx = tid; sidx < H2; sidx += bd) {
-                    const int s1 = sidx, s2 = sidx + H2;
-                    const float2 y1 = R.sy[s1], y1c = cconj(R.sy[s1 == 0 ? 0 : Pf - s1]);
-                    const float2 y2 = R.sy[s2], y2c = cconj(R.sy[Pf - s2]);
-                    const float2 h1 = cscale(cadd(y1, y1c), 0.5f), h2 = cscale(cadd(y2, y2c), 0.5f);
-                    const float2 E = cadd(h1, h2);
-                    const float2 O = cmulc(csub(h1, h2), twA(sidx));   // times e^{+2 pi i s / P}
-                    R.sc[sidx] = make_float2(E.x - O.y, E.y + O.x);    // E + i O
-                }
+                fill_batched<kRingFillUnroll>(
+                    H2,
+                    [&](int sidx) {
+                        const int s1 = sidx, s2 = sidx + H2;
+                        const float2 y1 = R.sy[s1], y1c = cconj(R.sy[s1 == 0 ? 0 : Pf - s1]);
+                        const float2 y2 = R.sy[s2], y2c = cconj(R.sy[Pf - s2]);
+                        const float2 h1 = cscale(cadd(y1, y1c), 0.5f), h2 = cscale(cadd(y2, y2c), 0.5f);
+                        const float2 E = cadd(h1, h2);
+                        const float2 O = cmulc(csub(h1, h2), twA(sidx));  // times e^{+2 pi i s / P}
+                        return make_float2(E.x - O.y, E.y + O.x);         // E + i O
+                    },
+                    [&](int sidx, float2 v) { R.sc[sidx] = v; });
                 __syncthreads();
                 fft_lds<true, kRingFftMaxButterflies>(R.sc, H2, 1, fS, tbS);
                 // detector q is point s q of the P-point grid
-                for (int q = tid; q < D; q += bd) {
-                    const int j = q * d.fold_s;
-                    const float2 z = R.sc[j >> 1];
-                    hn[q] = (j & 1) ? z.y : z.x;
-                }
+                fill_batched<kRingFillUnroll>(
+                    D,
+                    [&](int q) {
+                        const int j = q * d.fold_s;
+                        const float2 z = R.sc[j >> 1];
+                        return (j & 1) ? z.y : z.x;
+                    },
+                    [&](int q, float v) { hn[q] = v; });
             } else {
                 fft_lds<true, kRingFftMaxButterflies>(R.sy, Pf, 1, fS, tbS);
-                for (int q = tid; q < D; q += bd) hn[q] = R.sy[q * d.fold_s].x;
+                fill_batched<kRingFillUnroll>(
+                    D, [&](int q) { return R.sy[q * d.fold_s].x; }, [&](int q, float v) { hn[q] = v; });
             }
         } else {
             fft_lds<false, kRingFftMaxButterflies>(R.sy, S, 1, fS, tbS);
@@ -459,11 +485,12 @@ __device__ __forceinline__ void ring_fwd_tile(const PlanDev& d, const WsLayout& 
 
 // Value at point j of the P-point angular grid of the detector values placed
 // at points s q (q < D), zero elsewhere.
-__device__ __forceinline__ float grid_det(const float* hn, int j, int s, int D)
+__device__ __forceinline__ float grid_det(const float* hn, int j, int s, float rcp_s, int D)
 {
-    const int q = s == 1 ? j : j / s;
+    int q = j, rem = 0;
+    if (s != 1) fdivmod(j, s, rcp_s, q, rem);
     const float v = hn[min(q, D - 1)];  // unconditional load (batched by the caller), value selected
-    return (q * s == j && q < D) ? v : 0.f;
+    return (rem == 0 && q < D) ? v : 0.f;
 }
 
 __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile, int RT,
@@ -477,6 +504,7 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
     const int n0 = tile * RT;
     const int nr = min(RT, d.nlam - n0);
     const bool half = d.fold_P && d.syn_half;
+    const float rcp_s = 1.0f / (float)max(d.fold_s, 1);
     // the mode values Q~ go to qb, the Hermitian-part input of the ring's inverse FFT to eb
     float2* const qb = half ? R.sy : R.sa;
     float2* const eb = half ? R.sa : R.sy;
@@ -507,7 +535,7 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
             fill_batched<kRingFillUnroll>(
                 H2,
                 [&](int t) {
-                    return make_float2(grid_det(hn, 2 * t, d.fold_s, D), grid_det(hn, 2 * t + 1, d.fold_s, D));
+                    return make_float2(grid_det(hn, 2 * t, d.fold_s, rcp_s, D), grid_det(hn, 2 * t + 1, d.fold_s, rcp_s, D));
                 },
                 [&](int t, float2 v) { R.sc[t] = v; });
             tw_lds_store(R.twN, fN, d.tw, twf);
@@ -515,7 +543,7 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
             fft_lds<false, kRingFftMaxButterflies>(R.sc, H2, 1, fS, tbS);
         } else if (d.fold_P) {
             fill_batched<kRingFillUnroll>(
-                S, [&](int t) { return make_float2(grid_det(hn, t, d.fold_s, D), 0.f); },
+                S, [&](int t) { return make_float2(grid_det(hn, t, d.fold_s, rcp_s, D), 0.f); },
                 [&](int t, float2 v) { R.sy[t] = v; });
             tw_lds_store(R.twN, fN, d.tw, twf);
             __syncthreads();
@@ -561,17 +589,19 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
         // Re(IFFT_{2P}(Q~)) as a half-length inverse FFT: E + i O from the
         // Hermitian part of Q~ (which vanishes above K_n < P).
         // Q~_h[s] = Q~[s]/2 (0 < s <= K), Re Q~[0] (s = 0); Q~_h[s + P] = conj Q~[P - s]/2 (P - s <= K).
-        for (int sidx = tid; sidx < P; sidx += bd) {
-            float2 a = make_float2(0.f, 0.f), c = a;
-            if (sidx == 0) a = make_float2(qb[0].x, 0.f);
-            else {
-                if (sidx <= Kn) a = cscale(qb[sidx], 0.5f);
-                if (P - sidx <= Kn) c = cscale(cconj(qb[P - sidx]), 0.5f);
-            }
-            const float2 E = cadd(a, c);
-            const float2 O = cmulc(csub(a, c), twN(sidx));
-            eb[sidx] = make_float2(E.x - O.y, E.y + O.x);
-        }
+        fill_batched<kRingFillUnroll>(
+            P,
+            [&](int sidx) {
+                // reads clamped into qb[0 .. Kn], values outside the mode range dropped
+                const float2 q1 = qb[min(sidx, Kn)], q2 = qb[min(P - sidx, Kn)];
+                const float2 zero = make_float2(0.f, 0.f);
+                const float2 a = sidx == 0 ? make_float2(q1.x, 0.f) : (sidx <= Kn ? cscale(q1, 0.5f) : zero);
+                const float2 c = (sidx != 0 && P - sidx <= Kn) ? cscale(cconj(q2), 0.5f) : zero;
+                const float2 E = cadd(a, c);
+                const float2 O = cmulc(csub(a, c), twN(sidx));
+                return make_float2(E.x - O.y, E.y + O.x);
+            },
+            [&](int sidx, float2 v) { eb[sidx] = v; });
         __syncthreads();
         fft_lds<true, kRingFftMaxButterflies>(eb, P, 1, fR, tbR);
         // q~(m): m = 2t -> Re z_t, m = 2t + 1 -> Im z_t;  F~_h(l) = (q~(l) + q~(l+P)) + i (q~(l) - q~(l+P))
@@ -801,33 +831,51 @@ __device__ __forceinline__ void dct_tile(const PlanDev& d, const WsLayout& L, ch
     const float2* tb = fft_twiddles_to_lds(sm + DP * twoM, d.ffts[d.fft_dct], d.tw);
     for (int e = threadIdx.x; e < np * twoM; e += blockDim.x) sm[e] = make_float2(0.f, 0.f);
     __syncthreads();
+    // input pairs (detector d0 real, d0 + 1 imaginary) at sm[p][q + 1]; the loads
+    // of a thread are batched (fill_batched), the partner of the last odd detector is 0
     if (adj) {  // g [D][T]: contiguous along t
-        for (int e = threadIdx.x; e < np * nin; e += blockDim.x) {
-            const int p = e / nin, q = e - p * nin;
-            const int d0 = 2 * (p0 + p);
-            const float re = gin[(size_t)d0 * T + q];
-            const float im = (d0 + 1 < D) ? gin[(size_t)(d0 + 1) * T + q] : 0.f;
-            sm[p * twoM + q + 1] = make_float2(re, im);
-        }
+        const float rcp = 1.0f / (float)nin;
+        fill_batched<4>(
+            np * nin,
+            [&](int e) {
+                int p, q;
+                fdivmod(e, nin, rcp, p, q);
+                const int d0 = 2 * (p0 + p);
+                const float re = gin[(size_t)d0 * T + q];
+                const float im = gin[(size_t)min(d0 + 1, D - 1) * T + q];
+                return IdxVal{p * twoM + q + 1, make_float2(re, d0 + 1 < D ? im : 0.f)};
+            },
+            [&](int, IdxVal iv) { sm[iv.i] = iv.v; });
     } else {    // hT [nlam][D]: the tile's detectors are contiguous within a row
-        for (int e = threadIdx.x; e < np * nin; e += blockDim.x) {
-            const int q = e / np, p = e - q * np;
-            const int d0 = 2 * (p0 + p);
-            const float* row = hT + (size_t)q * D;
-            const float re = row[d0];
-            const float im = (d0 + 1 < D) ? row[d0 + 1] : 0.f;
-            sm[p * twoM + q + 1] = make_float2(re, im);
-        }
+        const float rcp = 1.0f / (float)np;
+        fill_batched<4>(
+            np * nin,
+            [&](int e) {
+                int q, p;
+                fdivmod(e, np, rcp, q, p);
+                const int d0 = 2 * (p0 + p);
+                const float* row = hT + (size_t)q * D;
+                const float re = row[d0];
+                const float im = row[min(d0 + 1, D - 1)];
+                return IdxVal{p * twoM + q + 1, make_float2(re, d0 + 1 < D ? im : 0.f)};
+            },
+            [&](int, IdxVal iv) { sm[iv.i] = iv.v; });
     }
     if (adj) {
-        // data sum of each detector of the tile: samples in kSumClasses classes,
-        // each summed in order, then the classes in order
+        // data sum of each detector of the tile (from the copy in LDS): samples in
+        // kSumClasses classes, each summed in order, then the classes in order
+        __syncthreads();
         const int nd = 2 * np;
         for (int t = threadIdx.x; t < kSumClasses * nd; t += blockDim.x) {
             const int c = t % kSumClasses, dd = t / kSumClasses, dg = 2 * p0 + dd;
+            const float2* col = sm + (dd >> 1) * twoM + 1;
             float sc = 0.f;
-            if (dg < D)
-                for (int q = c; q < T; q += kSumClasses) sc += gin[(size_t)dg * T + q];
+            if (dg < D) {
+                if (dd & 1)
+                    for (int q = c; q < T; q += kSumClasses) sc += col[q].y;
+                else
+                    for (int q = c; q < T; q += kSumClasses) sc += col[q].x;
+            }
             red_s[t] = sc;
         }
         __syncthreads();
@@ -840,23 +888,43 @@ __device__ __forceinline__ void dct_tile(const PlanDev& d, const WsLayout& L, ch
     __syncthreads();
     fft_lds<false>(sm, twoM, np, d.ffts[d.fft_dct], tb);
     const float add = adj ? 0.f : d.kappa * *mass_s;
+    // outputs X[q + 1] + X[2M - q - 1] (halved) of each pair; the LDS reads of a
+    // thread are batched ahead of its stores
     if (adj) {  // -> hT [nlam][D]
-        for (int e = threadIdx.x; e < np * nout; e += blockDim.x) {
-            const int q = e / np, p = e - q * np;
-            const int d0 = 2 * (p0 + p);
-            const float2 a = sm[p * twoM + q + 1], c = sm[p * twoM + twoM - q - 1];
-            float* row = hT + (size_t)q * D;
-            row[d0] = 0.5f * (a.x + c.x);
-            if (d0 + 1 < D) row[d0 + 1] = 0.5f * (a.y + c.y);
-        }
+        const float rcp = 1.0f / (float)np;
+        fill_batched<4>(
+            np * nout,
+            [&](int e) {
+                int q, p;
+                fdivmod(e, np, rcp, q, p);
+                const float2 a = sm[p * twoM + q + 1], c = sm[p * twoM + twoM - q - 1];
+                return make_float2(0.5f * (a.x + c.x), 0.5f * (a.y + c.y));
+            },
+            [&](int e, float2 v) {
+                int q, p;
+                fdivmod(e, np, rcp, q, p);
+                const int d0 = 2 * (p0 + p);
+                float* row = hT + (size_t)q * D;
+                row[d0] = v.x;
+                if (d0 + 1 < D) row[d0 + 1] = v.y;
+            });
     } else {    // -> g [D][T]
-        for (int e = threadIdx.x; e < np * nout; e += blockDim.x) {
-            const int p = e / nout, q = e - p * nout;
-            const int d0 = 2 * (p0 + p);
-            const float2 a = sm[p * twoM + q + 1], c = sm[p * twoM + twoM - q - 1];
-            gout[(size_t)d0 * T + q] = 0.5f * (a.x + c.x) + add;
-            if (d0 + 1 < D) gout[(size_t)(d0 + 1) * T + q] = 0.5f * (a.y + c.y) + add;
-        }
+        const float rcp = 1.0f / (float)nout;
+        fill_batched<4>(
+            np * nout,
+            [&](int e) {
+                int p, q;
+                fdivmod(e, nout, rcp, p, q);
+                const float2 a = sm[p * twoM + q + 1], c = sm[p * twoM + twoM - q - 1];
+                return make_float2(0.5f * (a.x + c.x) + add, 0.5f * (a.y + c.y) + add);
+            },
+            [&](int e, float2 v) {
+                int p, q;
+                fdivmod(e, nout, rcp, p, q);
+                const int d0 = 2 * (p0 + p);
+                gout[(size_t)d0 * T + q] = v.x;
+                if (d0 + 1 < D) gout[(size_t)(d0 + 1) * T + q] = v.y;
+            });
     }
 }
 
