@@ -218,7 +218,10 @@ __device__ __forceinline__ void rowpass_fwd_tile(const PlanDev& d, const WsLayou
 //            -> hT[n][d]  (real; the cosine transform over n follows)
 //   adjoint: the exact transpose, ending with the Hermitian fold and the
 //            conjugate half-pixel phase -> H, stored in band order for the
-//            spread (scattered writes here, contiguous reads there).
+//            spread (scattered writes here, contiguous reads there: reading
+//            H through each band-order point's ring index instead makes every
+//            wave-load of the spread touch tens of cache lines per instance,
+//            which costs the spread more than the scatter costs here).
 // ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // forward: ES interpolation of the half spectrum at the half-plane polar
@@ -228,7 +231,8 @@ __device__ __forceinline__ void rowpass_fwd_tile(const PlanDev& d, const WsLayou
 // spectrum (rows R0 .. R0 + TH + 6, columns C0 .. C0 + CB + 6, wrapping
 // around the periodic grid) is loaded into LDS once; then each band is
 // handled by kGatherThreads / TH threads, one point per thread at a time.
-// Output: the polar value times the half-pixel phase, stored in ring order.
+// Output: the polar value times the half-pixel phase, stored in ring order
+// (the ring-order index is the y field of the point's band-order geometry).
 // ---------------------------------------------------------------------------
 // IB instances of one plan share a tile (wbs[b], b < nb; b >= nb is padding):
 // one window per instance, the ES weights and indexing of each point once.
@@ -282,15 +286,13 @@ __device__ __forceinline__ void gather_tile(const PlanDev& d, const WsLayout& L,
     int s = seg_lo[bnd] + u;
     float4 ngq = d.bpt_geo[min(s, slast)];
     float2 nph = d.bpt_phase[min(s, slast)];
-    int nri = d.ring_of[min(s, slast)];
     for (; s < hi; s += Q) {
         const float4 gq = ngq;
         const float2 ph = nph;
-        const int ri = nri;
+        const int ri = fbits(gq.y);  // ring-order index of the point
         const int sn = min(s + Q, slast);
         ngq = d.bpt_geo[sn];
         nph = d.bpt_phase[sn];
-        nri = d.ring_of[sn];
         const int c0 = fbits(gq.x) - C0;
         float wx[8], wy[8];
         es_weights8(gq.z, wx);

@@ -75,7 +75,6 @@ struct PlanDev {
     const float* deap;      // [N]: h / phihat(k - N/2), k = 0..N-1 (one factor per axis)
     const int2* mask_rows;  // [N]: row i keeps columns jlo <= j < jhi
     // polar points, ring order (ring n = 1..nlam occupies [ring_off[n-1], ring_off[n]))
-    const float4* pt_geo;   // (bx mod Ng as int bits, r0 = by + 4 as int bits, fx, fy)
     const float2* pt_phase; // e^{-i pi (s_x + s_y)/Ng}  (half-pixel shift of cell-centred pixels)
     const int* ring_off;    // [nlam + 1]
     const int* ring_K;      // [nlam]   K_n: modes kept on ring n
@@ -83,10 +82,10 @@ struct PlanDev {
     const int* ring_twn;    // [nlam]   descriptor whose twiddles are those of length Npsi(n)
     const int* ring_joff;   // [nlam]   offset of ring n in Jw
     const float2* coef;     // ragged [ring_joff[n] + k], k = 0..K_n: pre_k i^k J_k(lam_n R) W_n / Npsi(n) (i for odd k)
-    // polar points, band order (sorted by (r0, bx)) for the deterministic spread
-    const int* ring_of;     // [npts]   band-order slot -> ring-order index
+    // polar points, band order (sorted by footprint base row r0 = by + 4, then bx)
+    // for the interpolation and the deterministic spread
     const int* band_of;     // [npts]   ring-order index -> band-order slot
-    const float4* bpt_geo;  // [npts]   same fields as pt_geo, band order
+    const float4* bpt_geo;  // [npts]   (bx mod Ng as int bits, ring-order index as int bits, fx, fy)
     const float2* bpt_phase;// [npts]   pt_phase in band order
     const int* band_ptr;    // [NB][Ng + 1] CSR: first band-order slot with (r0, bx' >= bx)
     // synthesis over detector angles theta_d = theta_0 + d dtheta

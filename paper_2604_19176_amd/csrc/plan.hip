@@ -723,9 +723,9 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
             int bxm = (int)(((bx % Ng) + Ng) % Ng);
             int q = ringOff[n] + l;
             float4 gq;
-            int ibx = bxm, ir0 = r0;
+            int ibx = bxm, iq = q;
             std::memcpy(&gq.x, &ibx, 4);
-            std::memcpy(&gq.y, &ir0, 4);
+            std::memcpy(&gq.y, &iq, 4);
             gq.z = (float)(sx - flx);
             gq.w = (float)(sy - fly);
             geo[q] = gq;
@@ -741,12 +741,10 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         return r0s[a] != r0s[b] ? r0s[a] < r0s[b] : bxs[a] < bxs[b];
     });
-    std::vector<int> ring_of(npts);  // band-order slot -> ring-order index
     std::vector<int> band_of(npts);  // ring-order index -> band-order slot
-    std::vector<float4> bgeo(npts);
+    std::vector<float4> bgeo(npts);  // geometry in band order (y: the point's ring-order index)
     std::vector<float2> bphase(npts);
     for (int s = 0; s < npts; ++s) {
-        ring_of[s] = order[s];
         band_of[order[s]] = s;
         bgeo[s] = geo[order[s]];
         bphase[s] = phase[order[s]];
@@ -830,18 +828,17 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
 
     // --- pack ---------------------------------------------------------------
     size_t o_deap = tb.add(deap), o_mask = tb.add(mask);
-    size_t o_geo = tb.add(geo), o_phase = tb.add(phase);
+    size_t o_phase = tb.add(phase);
     size_t o_roff = tb.add(ringOff), o_rk = tb.add(ringK), o_rfft = tb.add(ringFft), o_rj = tb.add(ringJoff);
     size_t o_rtwn = tb.add(ringTwn);
     size_t o_coef = tb.add(coef);
-    size_t o_ringof = tb.add(ring_of), o_bandof = tb.add(band_of), o_bgeo = tb.add(bgeo), o_bph = tb.add(bphase), o_bptr = tb.add(bptr);
+    size_t o_bandof = tb.add(band_of), o_bgeo = tb.add(bgeo), o_bph = tb.add(bphase), o_bptr = tb.add(bptr);
     size_t o_post = tb.add(post), o_vhat = tb.add(vhat), o_syn = tb.add(syn_tab);
     size_t o_ffts = tb.add(ffts.descs), o_tw = tb.add(ffts.tw);
     // store offsets in the pointer fields; relocated after the upload
     auto off = [](size_t o) { return (const void*)(uintptr_t)o; };
     d.deap = (const float*)off(o_deap);
     d.mask_rows = (const int2*)off(o_mask);
-    d.pt_geo = (const float4*)off(o_geo);
     d.pt_phase = (const float2*)off(o_phase);
     d.ring_off = (const int*)off(o_roff);
     d.ring_K = (const int*)off(o_rk);
@@ -849,7 +846,6 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     d.ring_twn = (const int*)off(o_rtwn);
     d.ring_joff = (const int*)off(o_rj);
     d.coef = (const float2*)off(o_coef);
-    d.ring_of = (const int*)off(o_ringof);
     d.band_of = (const int*)off(o_bandof);
     d.bpt_geo = (const float4*)off(o_bgeo);
     d.bpt_phase = (const float2*)off(o_bph);
@@ -888,8 +884,8 @@ extern "C" int pat_plan_create(const pat_plan_desc* desc, pat_plan** out)
     char* base = (char*)mem;
     PlanDev& d = p->dev;
     auto rel = [&](auto& ptr) { ptr = (std::remove_reference_t<decltype(ptr)>)(base + (uintptr_t)ptr); };
-    rel(d.deap); rel(d.mask_rows); rel(d.pt_geo); rel(d.pt_phase); rel(d.ring_off); rel(d.ring_K);
-    rel(d.ring_fft); rel(d.ring_twn); rel(d.ring_joff); rel(d.coef); rel(d.ring_of); rel(d.band_of); rel(d.bpt_geo); rel(d.bpt_phase);
+    rel(d.deap); rel(d.mask_rows); rel(d.pt_phase); rel(d.ring_off); rel(d.ring_K);
+    rel(d.ring_fft); rel(d.ring_twn); rel(d.ring_joff); rel(d.coef); rel(d.band_of); rel(d.bpt_geo); rel(d.bpt_phase);
     rel(d.band_ptr); rel(d.czt_post); rel(d.czt_vhat); rel(d.syn_tab); rel(d.ffts); rel(d.tw);
     p->desc = *desc;
     if (desc->det_theta) {  // the plan keeps its own copy of the angles
