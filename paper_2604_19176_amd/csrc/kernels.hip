@@ -118,6 +118,11 @@ struct IdxVal {
     float2 v;
 };
 
+struct IdxF {
+    int i;
+    float v;
+};
+
 // ---------------------------------------------------------------------------
 // forward: column pass (FFT along y of real columns, packed in pairs)
 // ---------------------------------------------------------------------------
@@ -131,29 +136,42 @@ __device__ __forceinline__ void colpass_fwd_tile(const PlanDev& d, const WsLayou
     const float2* tb = fft_twiddles_to_lds(sm + NP * Ng, d.ffts[d.fft_grid], d.tw);
     for (int e = threadIdx.x; e < NP * Ng; e += blockDim.x) sm[e] = make_float2(0.f, 0.f);
     __syncthreads();
-    for (int e = threadIdx.x; e < N * CT; e += blockDim.x) {
-        const int i = e / CT, jj = e - i * CT, j = j0 + jj;
-        float v = 0.f;
-        if (j < N) {
+    // the tile's columns, masked and deapodised, at rows centred in the padded
+    // column (batched, branch-free loads; columns past N read as zero)
+    const float rcpCT = 1.0f / (float)CT;
+    fill_batched<4>(
+        N * CT,
+        [&](int e) {
+            int i, jj;
+            fdivmod(e, CT, rcpCT, i, jj);
+            const int j = j0 + jj, jc = min(j, N - 1);
             const int2 mr = d.mask_rows[i];
-            if (j >= mr.x && j < mr.y) v = fb[(size_t)i * N + j] * d.deap[i] * d.deap[j];
-        }
-        int pos = i - N / 2;
-        if (pos < 0) pos += Ng;
-        float* slot = (float*)&sm[(jj >> 1) * Ng + pos];
-        slot[jj & 1] = v;
-    }
+            const float fv = fb[(size_t)i * N + jc], di = d.deap[i], dj = d.deap[jc];
+            const float v = (j < N && j >= mr.x && j < mr.y) ? fv * di * dj : 0.f;
+            int pos = i - N / 2;
+            if (pos < 0) pos += Ng;
+            return IdxF{2 * ((jj >> 1) * Ng + pos) + (jj & 1), v};
+        },
+        [&](int, IdxF iv) { ((float*)sm)[iv.i] = iv.v; });
     // endpoint term: h^2 times the masked sum of each column; rows in kSumClasses
     // classes, each summed in order, then the classes in order (independent of
-    // the workgroup size and of the tiling)
+    // the workgroup size and of the tiling).  Loads four rows ahead of the sum.
     for (int t = threadIdx.x; t < kSumClasses * CT; t += blockDim.x) {
-        const int jj = t % CT, c = t / CT, j = j0 + jj;
+        const int jj = t % CT, c = t / CT, j = j0 + jj, jc = min(j, N - 1);
         float sc = 0.f;
-        if (j < N)
-            for (int i = c; i < N; i += kSumClasses) {
-                const int2 mr = d.mask_rows[i];
-                if (j >= mr.x && j < mr.y) sc += fb[(size_t)i * N + j];
+        for (int i0 = c; i0 < N; i0 += 4 * kSumClasses) {
+            float v[4];
+            bool in[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + u * kSumClasses, ic = min(i, N - 1);
+                const int2 mr = d.mask_rows[ic];
+                v[u] = fb[(size_t)ic * N + jc];
+                in[u] = i < N && j < N && j >= mr.x && j < mr.y;
             }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) sc = in[u] ? sc + v[u] : sc;
+        }
         red_s[t] = sc;
     }
     __syncthreads();
@@ -164,21 +182,24 @@ __device__ __forceinline__ void colpass_fwd_tile(const PlanDev& d, const WsLayou
     }
     __syncthreads();
     fft_lds<false>(sm, Ng, NP, d.ffts[d.fft_grid], tb);
-    for (int e = threadIdx.x; e < d.Hy * CT; e += blockDim.x) {
-        const int r = e / CT, jj = e - r * CT, j = j0 + jj;
-        if (j >= N) continue;
-        const int m = r - 4;
-        const int ip = m < 0 ? m + Ng : m;
-        const int in = m > 0 ? Ng - m : -m;
-        const float2 zp = sm[(jj >> 1) * Ng + ip], zn = sm[(jj >> 1) * Ng + in];
-        float2 o;
-        if ((jj & 1) == 0) {  // (Z(m) + conj Z(-m)) / 2
-            o = make_float2(0.5f * (zp.x + zn.x), 0.5f * (zp.y - zn.y));
-        } else {              // (Z(m) - conj Z(-m)) / (2i)
-            o = make_float2(0.5f * (zp.y + zn.y), -0.5f * (zp.x - zn.x));
-        }
-        X1[(size_t)r * N + j] = o;
-    }
+    fill_batched<4>(
+        d.Hy * CT,
+        [&](int e) {
+            int r, jj;
+            fdivmod(e, CT, rcpCT, r, jj);
+            const int j = j0 + jj;
+            const int m = r - 4;
+            const int ip = m < 0 ? m + Ng : m;
+            const int in = m > 0 ? Ng - m : -m;
+            const float2 zp = sm[(jj >> 1) * Ng + ip], zn = sm[(jj >> 1) * Ng + in];
+            // even column: (Z(m) + conj Z(-m)) / 2; odd: (Z(m) - conj Z(-m)) / (2i)
+            const float2 o = (jj & 1) == 0 ? make_float2(0.5f * (zp.x + zn.x), 0.5f * (zp.y - zn.y))
+                                           : make_float2(0.5f * (zp.y + zn.y), -0.5f * (zp.x - zn.x));
+            return IdxVal{j < N ? r * N + j : -1, o};
+        },
+        [&](int, IdxVal iv) {
+            if (iv.i >= 0) X1[iv.i] = iv.v;
+        });
 }
 
 // ---------------------------------------------------------------------------
@@ -195,15 +216,21 @@ __device__ __forceinline__ void rowpass_fwd_tile(const PlanDev& d, const WsLayou
     const float2* tb = fft_twiddles_to_lds(sm + RPB * Ng, d.ffts[d.fft_grid], d.tw);
     for (int e = threadIdx.x; e < nr * Ng; e += blockDim.x) sm[e] = make_float2(0.f, 0.f);
     __syncthreads();
-    for (int e = threadIdx.x; e < nr * N; e += blockDim.x) {
-        const int rr = e / N, j = e - rr * N;
-        int pos = j - N / 2;
-        if (pos < 0) pos += Ng;
-        sm[rr * Ng + pos] = X1[(size_t)(r0 + rr) * N + j];
-    }
+    const float rcpN = 1.0f / (float)N;
+    fill_batched<4>(
+        nr * N,
+        [&](int e) {
+            int rr, j;
+            fdivmod(e, N, rcpN, rr, j);
+            int pos = j - N / 2;
+            if (pos < 0) pos += Ng;
+            return IdxVal{rr * Ng + pos, X1[(size_t)(r0 + rr) * N + j]};
+        },
+        [&](int, IdxVal iv) { sm[iv.i] = iv.v; });
     __syncthreads();
     fft_lds<false>(sm, Ng, nr, d.ffts[d.fft_grid], tb);
-    for (int e = threadIdx.x; e < nr * Ng; e += blockDim.x) G[(size_t)r0 * Ng + e] = sm[e];
+    fill_batched<4>(
+        nr * Ng, [&](int e) { return sm[e]; }, [&](int e, float2 v) { G[(size_t)r0 * Ng + e] = v; });
 }
 
 // ---------------------------------------------------------------------------
@@ -1192,15 +1219,21 @@ __device__ __forceinline__ void rowpass_adj_tile(const PlanDev& d, const WsLayou
     const int r0 = tile * RPB;
     const int nr = min(RPB, d.Hy - r0);
     const float2* tb = fft_twiddles_to_lds(sm + RPB * Ng, d.ffts[d.fft_grid], d.tw);
-    for (int e = threadIdx.x; e < nr * Ng; e += blockDim.x) sm[e] = Gt[(size_t)r0 * Ng + e];
+    fill_batched<4>(
+        nr * Ng, [&](int e) { return Gt[(size_t)r0 * Ng + e]; }, [&](int e, float2 v) { sm[e] = v; });
     __syncthreads();
     fft_lds<true>(sm, Ng, nr, d.ffts[d.fft_grid], tb);
-    for (int e = threadIdx.x; e < nr * N; e += blockDim.x) {
-        const int rr = e / N, j = e - rr * N;
-        int pos = j - N / 2;
-        if (pos < 0) pos += Ng;
-        X1[(size_t)(r0 + rr) * N + j] = sm[rr * Ng + pos];
-    }
+    const float rcpN = 1.0f / (float)N;
+    fill_batched<4>(
+        nr * N,
+        [&](int e) {
+            int rr, j;
+            fdivmod(e, N, rcpN, rr, j);
+            int pos = j - N / 2;
+            if (pos < 0) pos += Ng;
+            return sm[rr * Ng + pos];
+        },
+        [&](int e, float2 v) { X1[(size_t)r0 * N + e] = v; });
 }
 
 // ---------------------------------------------------------------------------
@@ -1220,40 +1253,53 @@ __device__ __forceinline__ void colpass_adj_tile(const PlanDev& d, const WsLayou
     const int j0 = tile * CT;
     const int top = Ng / 2 + 4;
     const float2* tb = fft_twiddles_to_lds(sm + NP * Ng, d.ffts[d.fft_grid], d.tw);
-    for (int e = threadIdx.x; e < NP * Ng; e += blockDim.x) {
-        const int p = e / Ng, q = e - p * Ng;
-        const int ja = j0 + 2 * p, jb = ja + 1;
-        // stored row of residue q and of -q (or -1 if not stored)
-        const int rq = q <= top ? q + 4 : (q >= Ng - 4 ? q - Ng + 4 : -1);
-        const int qn = q == 0 ? 0 : Ng - q;
-        const int rn = qn <= top ? qn + 4 : (qn >= Ng - 4 ? qn - Ng + 4 : -1);
-        float2 ua = make_float2(0.f, 0.f), una = ua, ub = ua, unb = ua;
-        if (ja < N) {
-            if (rq >= 0) ua = X1[(size_t)rq * N + ja];
-            if (rn >= 0) una = X1[(size_t)rn * N + ja];
-        }
-        if (jb < N) {
-            if (rq >= 0) ub = X1[(size_t)rq * N + jb];
-            if (rn >= 0) unb = X1[(size_t)rn * N + jb];
-        }
-        // z = (ua + conj una)/2 + i (ub + conj unb)/2
-        const float2 ha = make_float2(0.5f * (ua.x + una.x), 0.5f * (ua.y - una.y));
-        const float2 hb = make_float2(0.5f * (ub.x + unb.x), 0.5f * (ub.y - unb.y));
-        sm[e] = make_float2(ha.x - hb.y, ha.y + hb.x);
-    }
+    // column pair p at residue q: batched loads with rows and columns clamped
+    // into the stored range, values outside it selected as zero
+    const float rcpNg = 1.0f / (float)Ng;
+    fill_batched<4>(
+        NP * Ng,
+        [&](int e) {
+            int p, q;
+            fdivmod(e, Ng, rcpNg, p, q);
+            const int ja = j0 + 2 * p, jb = ja + 1;
+            // stored row of residue q and of -q (or -1 if not stored)
+            const int rq = q <= top ? q + 4 : (q >= Ng - 4 ? q - Ng + 4 : -1);
+            const int qn = q == 0 ? 0 : Ng - q;
+            const int rn = qn <= top ? qn + 4 : (qn >= Ng - 4 ? qn - Ng + 4 : -1);
+            const int rqc = max(rq, 0), rnc = max(rn, 0), jac = min(ja, N - 1), jbc = min(jb, N - 1);
+            const float2 z0 = make_float2(0.f, 0.f);
+            const float2 la = X1[(size_t)rqc * N + jac], lna = X1[(size_t)rnc * N + jac];
+            const float2 lb = X1[(size_t)rqc * N + jbc], lnb = X1[(size_t)rnc * N + jbc];
+            const float2 ua = (ja < N && rq >= 0) ? la : z0, una = (ja < N && rn >= 0) ? lna : z0;
+            const float2 ub = (jb < N && rq >= 0) ? lb : z0, unb = (jb < N && rn >= 0) ? lnb : z0;
+            // z = (ua + conj una)/2 + i (ub + conj unb)/2
+            const float2 ha = make_float2(0.5f * (ua.x + una.x), 0.5f * (ua.y - una.y));
+            const float2 hb = make_float2(0.5f * (ub.x + unb.x), 0.5f * (ub.y - unb.y));
+            return make_float2(ha.x - hb.y, ha.y + hb.x);
+        },
+        [&](int e, float2 v) { sm[e] = v; });
     __syncthreads();
     fft_lds<true>(sm, Ng, NP, d.ffts[d.fft_grid], tb);
     const float kt = d.kappa * d.h2 * *gsum_s;
-    for (int e = threadIdx.x; e < N * CT; e += blockDim.x) {
-        const int i = e / CT, jj = e - i * CT, j = j0 + jj;
-        if (j >= N) continue;
-        int pos = i - N / 2;
-        if (pos < 0) pos += Ng;
-        const float2 z = sm[(jj >> 1) * Ng + pos];
-        const float c = (jj & 1) ? z.y : z.x;
-        const int2 mr = d.mask_rows[i];
-        fb[(size_t)i * N + j] = (j >= mr.x && j < mr.y) ? d.deap[i] * d.deap[j] * c + kt : 0.f;
-    }
+    const float rcpCT = 1.0f / (float)CT;
+    fill_batched<4>(
+        N * CT,
+        [&](int e) {
+            int i, jj;
+            fdivmod(e, CT, rcpCT, i, jj);
+            const int j = j0 + jj, jc = min(j, N - 1);
+            int pos = i - N / 2;
+            if (pos < 0) pos += Ng;
+            const float2 z = sm[(jj >> 1) * Ng + pos];
+            const float c = (jj & 1) ? z.y : z.x;
+            const int2 mr = d.mask_rows[i];
+            const float di = d.deap[i], dj = d.deap[jc];
+            const float v = (j >= mr.x && j < mr.y) ? di * dj * c + kt : 0.f;
+            return IdxF{j < N ? i * N + j : -1, v};
+        },
+        [&](int, IdxF iv) {
+            if (iv.i >= 0) fb[iv.i] = iv.v;
+        });
 }
 
 // ---------------------------------------------------------------------------
