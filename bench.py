@@ -26,7 +26,6 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B] [--worklo
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -57,7 +56,9 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2604_19176_amd", "csrc", "kernels.hip")
 
 
 def kernels_hash():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the device sources (kernels.hip and the headers it includes)."""
+    from paper_2604_19176_amd.profiling import source_hash
+    return source_hash(KERNEL_SRC)
 
 
 def algorithmic_bytes(info, geom):

@@ -3,18 +3,22 @@
 // Forward A (steps of the discrete operator; layouts per instance, row-major):
 //   colpass_fwd : f [N][N] -> mask, deapodise, zero-pad to Ng, FFT along y of
 //                 column pairs packed as complex -> X1 [Hy][N] (rows m_y = -4..Ng/2+4)
-//                 + per-tile partial sums of h^2 m f (endpoint term)
+//                 + per-column sums of h^2 m f (endpoint term)
 //   rowpass_fwd : X1 -> FFT along x -> G [Hy][Ng]  (oversampled half spectrum)
-//   ring_fwd    : per radial frequency n: ES interpolation of G at the ring's
-//                 half-plane points, completion by conjugate symmetry, angular
-//                 FFT, weight i^k J_k(lam_n R) W_n / Npsi(n) -> b [nlam][Kp]
-//   dct         : per mode k: B_k(j) = sum_n b_k(n) cos(pi n j / M) via one
-//                 complex FFT of length 2M -> Bt [T][Kp]
-//   czt_fwd     : per time sample: Bluestein chirp-z over detector angles,
-//                 g = Re(...) + kappa * mass -> g [D][T]
-// Adjoint A* runs the exact transposes in reverse (czt_adj, dct, ring_adj,
-// spread, rowpass_adj, colpass_adj).  No floating-point atomics anywhere:
-// every sum has a fixed order, so results are bitwise repeatable.
+//   gather      : ES interpolation of G at the half-plane polar points, times
+//                 the half-pixel phase -> F [npts] in ring order
+//   ring_fwd    : per radial frequency n: angular FFT of the ring (completed by
+//                 conjugate symmetry), weights c_k i^k J_k(lam_n R) W_n / Npsi(n),
+//                 synthesis over the detector angles (one FFT after folding
+//                 k mod P, or Bluestein) -> hT [nlam][D]
+//   syn_dense   : explicit detector angles only: the synthesis as a matrix-core
+//                 product of the ring's mode coefficients with a cos/sin table
+//   dct         : per detector: g(d, j) = sum_n hT[n][d] cos(pi n j / M) via one
+//                 complex FFT of length 2M for two detectors, + kappa * mass -> g [D][T]
+// Adjoint A* runs the exact transposes in reverse (dct, ring_adj or
+// syn_dense adjoint + ring_adj, spread, rowpass_adj, colpass_adj).  No
+// floating-point atomics anywhere: every sum has a fixed order, so results are
+// bitwise repeatable.
 #include "fft.hpp"
 #include "pat_internal.hpp"
 

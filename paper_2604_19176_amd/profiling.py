@@ -19,6 +19,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import sys
 from collections import defaultdict
 
@@ -106,8 +107,23 @@ def traffic(fetch_csv, write_csv, kernel, calib_bytes):
     }
 
 
+# the device sources every kernel is compiled from
+KERNEL_FILES = ("kernels.hip", "fft.hpp", "pat_internal.hpp")
+
+
 def source_hash(path):
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    """Hash of the device sources' code (comments and whitespace removed, so
+    that a comment edit keeps measured figures valid): `path` is the source
+    directory or a file in it."""
+    d = path if os.path.isdir(path) else os.path.dirname(os.path.abspath(path))
+    h = hashlib.sha256()
+    for f in KERNEL_FILES:
+        with open(os.path.join(d, f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
+    return h.hexdigest()[:16]
 
 
 def main(argv=None):
