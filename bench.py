@@ -536,11 +536,14 @@ def bench_paper(args):
         plan.autotune(batch=1, cache_path=args.tune_cache)
     g_out, f_out = torch.empty_like(g_meas), torch.empty_like(f)
     ms, _ = time_pairs(torch, plan, f, g_meas, g_out, f_out, args.steps, args.warmup)
+    kms = kernel_times(pat, plan, f, g_meas, g_out, f_out, 5)
     out = {"metric": "A+A* pairs/s at the paper's timed shape",
            "value": round(1000.0 / ms, 1), "unit": "pairs/s", "ms_per_step": round(ms, 4), "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "760x760, 256 detectors on 270 deg, 2030 samples, batch 1"}}
+           "config": {"workload": "760x760, 256 detectors on 270 deg, 2030 samples, batch 1"},
+           "kernels_ms": {k: round(v, 4) for k, v in kms.items()}, "launch": plan.launch,
+           "tuned": bool(args.tune)}
     print(json.dumps(out), flush=True)
     plan.close()
 
