@@ -687,6 +687,60 @@ def bench_dip(args):
     plan.close()
 
 
+def bench_sim(args):
+    """The wave-propagation data simulator at the simulation study's shape:
+    512^2 fine grid, 256 detectors on 270 deg, 512 samples on (0, 2]."""
+    import numpy as np
+    import torch
+
+    import paper_2604_19176_amd as pat
+    from pat_inputs import Geometry, make_phantom
+
+    dev = torch.device("cuda", 0)
+    geom = Geometry(n=512, n_det=256, n_t=512, dt=2.0 / 512, arc_span=math.radians(270.0))
+    f_np = make_phantom(geom.n, 20, 3, 4, 512)
+    f = torch.tensor(f_np, dtype=torch.float32, device=dev)
+    sim = pat.PatSim(geom)
+    g = torch.empty((geom.n_det, geom.n_t), dtype=torch.float32, device=dev)
+    steps = max(1, min(args.steps, 20))
+    for _ in range(max(1, args.warmup)):
+        sim.run(f, out=g)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        sim.run(f, out=g)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    M = sim.box_side
+    pairs = (geom.n_t + 1) // 2
+    parity, cpu = None, None
+    if not args.no_cpu_baseline:
+        from oracle import simulate as ref
+        cols = [0, 255, 511]
+        t0 = time.perf_counter()
+        g_ref = ref.simulate(geom, f_np, times=[(j + 1) * geom.dt for j in cols])
+        t_cpu = time.perf_counter() - t0
+        gg = g.cpu().double().numpy()[:, cols]
+        parity = {"sampled_times": cols,
+                  "rel_l2": float(np.linalg.norm(gg - g_ref) / np.linalg.norm(g_ref))}
+        cpu = {"seconds_per_time_sample": round(t_cpu / len(cols), 4), "kind": "oracle (numpy FP64 FFTs)",
+               "sample": "3 time samples of the same simulation"}
+    out = {"metric": "wave-propagation simulations/s (FFT k-space propagator on the fine grid, Keys sampling)",
+           "value": round(1000.0 / ms, 2), "unit": "simulations/s", "ms_per_step": round(ms, 4), "n_gpus": 1,
+           "steps": steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "simulator: 512x512 fine grid (box %d), 256 detectors on 270 deg, "
+                                  "512 samples on (0,2]" % M, "box": M},
+           # per simulation: the box spectrum is read once per pair of samples by the column pass
+           "bytes_spectrum_reads_per_simulation": int(8 * M * M * pairs),
+           "parity": parity, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+    sim.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -695,7 +749,7 @@ def main():
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--workload", default="default",
                     choices=["default", "mixed", "tv3", "large", "paper", "pdhg3", "pdhg-large", "dense", "cgls",
-                             "dip"])
+                             "dip", "sim"])
     ap.add_argument("--no-tune", dest="tune", action="store_false",
                     help="time the default launch shapes instead of autotuning them first")
     ap.add_argument("--tune-cache", default=None, help="JSON cache file of the autotuner")
@@ -726,6 +780,8 @@ def main():
         bench_tv(args, 3, 500, 1000)
     elif args.workload == "large":
         bench_tv(args, 5, 2000, 1)
+    elif args.workload == "sim":
+        bench_sim(args)
     else:
         bench_paper(args)
 

@@ -300,6 +300,41 @@ int  pat_autotune_batch(pat_batch* batch, const char* cache_path);
 int  pat_plan_derive(const pat_plan_desc* desc, pat_plan_info* out);
 int  pat_bessel_jn_table(int kmax, double x, double* out);
 
+/* ---- FFT wave-propagation data simulator ---------------------------------
+ * The simulation study (Sec. 3, simulations) computes its data on a finer
+ * Cartesian grid with an FFT-based wave propagation method in the manner of
+ * k-Wave, so that the data do not come from the reconstruction's own
+ * discretisation.  Reading for a constant speed of sound c:
+ *   - the fine image (desc->n pixels a side, cell centres on [-1,1]^2, h = 2/n,
+ *     pixels with centre radius >= support_r dropped) is zero-padded to a
+ *     periodic box of M x M cells of the same size, centred, with M the
+ *     smallest even 2^a 3^b (M - n even) whose half-width L = M h / 2 meets
+ *     2 L - det_r - support_r > c t_T (no wave wraps around to a detector by
+ *     the last sample t_T = n_t dt) and L > det_r + 3 h;
+ *   - p(t) = IFFT2[ FFT2(f) cos(c |k| t) ] (k: the box's wave vectors), the
+ *     exact solution of the periodic wave equation with p_t(0) = 0;
+ *   - g(d, j) = p(x_d, j dt), j = 1..n_t, at the detectors (uniform arc or
+ *     det_theta, radius det_r) by separable Keys cubic convolution (a = -1/2)
+ *     on the box's cell centres.
+ * pat_sim_create uses desc's fields n, support_r, det_r, n_det, arc_center,
+ * arc_span, det_theta, n_t, dt and c (the operator-only fields are ignored);
+ * it builds the tables (FP64 on the host, device memory owned by the
+ * simulator) and may allocate; errors PAT_ERR_ARG (null pointers, n < 8,
+ * n_det < 1, n_t < 1, dt <= 0, c <= 0, det_r <= 0, support_r <= 0),
+ * PAT_ERR_UNSUPPORTED (box side above 4096 or no FFT plan), PAT_ERR_ALLOC,
+ * PAT_ERR_HIP.
+ * pat_sim_query: the box side M and the workspace bytes pat_sim_run needs.
+ * pat_sim_run: f_dev [n][n] f32 (rows y, columns x) -> g_dev [n_det][n_t]
+ * f32, device pointers owned by the caller, with a caller-owned device
+ * workspace of at least the queried size; asynchronous on `stream`
+ * (hipStream_t, NULL = the null stream), allocates nothing.  Errors
+ * PAT_ERR_ARG (null pointers), PAT_ERR_WORKSPACE, PAT_ERR_HIP. */
+typedef struct pat_sim pat_sim;
+int  pat_sim_create(const pat_plan_desc* desc, pat_sim** out);
+int  pat_sim_query(const pat_sim* sim, int* box_side, size_t* workspace_bytes);
+int  pat_sim_run(const pat_sim* sim, const float* f_dev, float* g_dev, void* ws_dev, size_t ws_bytes, void* stream);
+void pat_sim_destroy(pat_sim* sim);
+
 /* Human-readable text of a status code (static storage). */
 const char* pat_status_string(int status);
 

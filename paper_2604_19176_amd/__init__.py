@@ -27,9 +27,10 @@ from ._lib import (PatError, pat_plan_desc, pat_status_string, pat_plan_create, 
                    pat_batch_create, pat_batch_destroy, pat_batch_workspace_size, pat_batch_forward,
                    pat_batch_adjoint, pat_batch_get_launch, pat_batch_set_launch, pat_autotune_plan,
                    pat_autotune_batch, pat_pd_dual_data, pat_pd_dual_tv, pat_pd_primal, pat_pd_change,
-                   pat_cg_norm2, pat_cg_step_fr, pat_cg_step_p)
+                   pat_cg_norm2, pat_cg_step_fr, pat_cg_step_p, pat_sim_create, pat_sim_query, pat_sim_run,
+                   pat_sim_destroy)
 
-__all__ = ["PatPlan", "PatBatch", "pat_operator", "PatOperatorFn", "tv_grad", "pgd_update", "residual",
+__all__ = ["PatPlan", "PatBatch", "PatSim", "pat_operator", "PatOperatorFn", "tv_grad", "pgd_update", "residual",
            "PatError", "desc_from_geometry", "library_path"]
 
 
@@ -256,6 +257,51 @@ class PatBatch:
             pat_batch_destroy(self.handle)
             self.handle = None
         self._ptr_tables = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PatSim:
+    """The FFT wave-propagation data simulator for a geometry whose `n` is the
+    fine grid side (the simulation study's finer Cartesian grid): run(f) maps
+    an (n, n) float32 image on the GPU to (n_det, n_t) data."""
+
+    def __init__(self, geom, device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("PatSim needs a GPU: torch.cuda.is_available() is False")
+        _lib.load()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        self.geom = geom
+        with torch.cuda.device(self.device):
+            self.handle = pat_sim_create(desc_from_geometry(geom, 1))
+        self.box_side, self.workspace_bytes = pat_sim_query(self.handle)
+        self._ws = None
+
+    def run(self, f, out=None):
+        _check_tensor(f, "f", (self.geom.n, self.geom.n), self.device)
+        if f.dim() != 2:
+            raise ValueError("f must be one (n, n) image")
+        shape = (self.geom.n_det, self.geom.n_t)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=self.device)
+        else:
+            _check_tensor(out, "out", shape, self.device)
+        if self._ws is None:
+            self._ws = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            pat_sim_run(self.handle, f.data_ptr(), out.data_ptr(), self._ws.data_ptr(), self._ws.numel(),
+                        _stream(self.device))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            pat_sim_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

@@ -99,6 +99,10 @@ def load():
         "pat_cg_norm2": (ci, [vp, vp, cl, ci, vp]),
         "pat_cg_step_fr": (ci, [vp, vp, cl, vp, vp, cl, vp, vp, ci, vp]),
         "pat_cg_step_p": (ci, [vp, vp, cl, vp, vp, ci, vp]),
+        "pat_sim_create": (ci, [P(pat_plan_desc), P(vp)]),
+        "pat_sim_query": (ci, [vp, P(ci), P(sz)]),
+        "pat_sim_run": (ci, [vp, vp, vp, vp, sz, vp]),
+        "pat_sim_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -272,3 +276,23 @@ def pat_cg_step_fr(f_ptr, p_ptr, nf, r_ptr, q_ptr, nr, gamma_ptr, qq_ptr, batch,
 
 def pat_cg_step_p(p_ptr, s_ptr, n, gnew_ptr, gamma_ptr, batch, stream) -> None:
     _check(load().pat_cg_step_p(p_ptr, s_ptr, int(n), gnew_ptr, gamma_ptr, int(batch), stream), "pat_cg_step_p")
+
+
+def pat_sim_create(desc: pat_plan_desc) -> int:
+    h = ctypes.c_void_p()
+    _check(load().pat_sim_create(ctypes.byref(desc), ctypes.byref(h)), "pat_sim_create")
+    return h.value
+
+
+def pat_sim_query(sim: int):
+    m, ws = ctypes.c_int(), ctypes.c_size_t()
+    _check(load().pat_sim_query(sim, ctypes.byref(m), ctypes.byref(ws)), "pat_sim_query")
+    return m.value, ws.value
+
+
+def pat_sim_run(sim, f_ptr, g_ptr, ws_ptr, ws_bytes, stream) -> None:
+    _check(load().pat_sim_run(sim, f_ptr, g_ptr, ws_ptr, int(ws_bytes), stream), "pat_sim_run")
+
+
+def pat_sim_destroy(sim: int) -> None:
+    load().pat_sim_destroy(sim)

@@ -44,6 +44,14 @@ __host__ __device__ constexpr int radix_max_butterflies(int R, int maxb = kFftMa
 }
 
 // Threads per sequence the passes of `d` need (at most `maxb` butterflies per thread).
+// Host helpers of the plan builder for other modules (plan.hip):
+// fixed_fft_for plans a fixed-length transform of length n (twiddles appended
+// to tw; returns the threads per sequence, 0 if none fits);
+// fft_workgroup_threads gives the threads of a workgroup transforming `nseq`
+// sequences of that length.
+int fixed_fft_for(long n, FftDev* out, std::vector<float2>& tw);
+int fft_workgroup_threads(int nseq, const FftDev& fd);
+
 __host__ __device__ inline int fft_min_tps(const FftDev& d, int maxb = kFftMaxButterflies)
 {
     int t = 1;

@@ -461,6 +461,27 @@ static int fft_threads(int nseq, const FftDev& fd)
 // LDS of a length's per-pass twiddles
 static size_t twb_bytes(const FftDev& f) { return sizeof(float2) * (size_t)f.ntb; }
 
+// A fixed-length transform of length n for another module: its descriptor,
+// planned like the grid and cosine transforms, with its twiddles appended to
+// `tw` (the descriptor's offsets index `tw`).  Returns the threads per
+// sequence, 0 if no plan fits.
+int fixed_fft_for(long n, FftDev* out, std::vector<float2>& tw)
+{
+    const int tps = fixed_fft_tps(n);
+    if (!tps) return 0;
+    FftSet s;
+    const int i = s.get(n, tps);
+    if (i < 0) return 0;
+    FftDev d = s.descs[i];
+    d.tw += (int)tw.size();
+    d.tb += (int)tw.size();
+    tw.insert(tw.end(), s.tw.begin(), s.tw.end());
+    *out = d;
+    return tps;
+}
+
+int fft_workgroup_threads(int nseq, const FftDev& fd) { return fft_threads(nseq, fd); }
+
 // Dynamic LDS of the ring kernels: half-ring FFT buffer, synthesis buffers,
 // [D][RT] detector tile and four twiddle tables.
 static size_t ring_lds_bytes(const PlanDev& d, int RT)
