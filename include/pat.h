@@ -321,7 +321,7 @@ int  pat_bessel_jn_table(int kmax, double x, double* out);
  * it builds the tables (FP64 on the host, device memory owned by the
  * simulator) and may allocate; errors PAT_ERR_ARG (null pointers, n < 8,
  * n_det < 1, n_t < 1, dt <= 0, c <= 0, det_r <= 0, support_r <= 0),
- * PAT_ERR_UNSUPPORTED (box side above 4096 or no FFT plan), PAT_ERR_ALLOC,
+ * PAT_ERR_UNSUPPORTED (box side above 8192 or no FFT plan), PAT_ERR_ALLOC,
  * PAT_ERR_HIP.
  * pat_sim_query: the box side M and the workspace bytes pat_sim_run needs.
  * pat_sim_run: f_dev [n][n] f32 (rows y, columns x) -> g_dev [n_det][n_t]

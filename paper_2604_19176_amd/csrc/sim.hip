@@ -189,7 +189,7 @@ struct pat_sim {
 
 namespace {
 
-constexpr int kSimMaxBox = 4096;
+constexpr int kSimMaxBox = 8192;
 constexpr int kSimChunk = 16;
 constexpr size_t kSimLdsMax = 160 * 1024;
 

@@ -106,8 +106,8 @@ def test_simulator_rejects_bad_arguments(torch_dev):
         with pytest.raises(pat.PatError) as ei:
             pat.PatSim(bad)
         assert ei.value.status == -1
-    with pytest.raises(pat.PatError) as ei:      # box above 4096 cells
-        pat.PatSim(good.with_(n=1024, n_t=4000, dt=0.002))
+    with pytest.raises(pat.PatError) as ei:      # box above 8192 cells
+        pat.PatSim(good.with_(n=2048, n_t=8000, dt=0.002))
     assert ei.value.status == -2
     sim = pat.PatSim(good)
     with pytest.raises(ValueError):
