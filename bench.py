@@ -371,7 +371,7 @@ def bench_tv(args, cfg_id, steps_default, seed_stride):
     gin = g_meas if B > 1 else g_meas[0]
     print("bench: TV loop, %d iterations" % steps, file=sys.stderr, flush=True)
     rec = TVReconstructor(plan, gin, lam=lam)
-    rec.capture()
+    rec.capture(10)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream(dev)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -391,7 +391,7 @@ def bench_tv(args, cfg_id, steps_default, seed_stride):
         "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": round(ms / steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "TV loop, %dx%d, %d detectors on %.0f deg, %d samples, batch %d, lambda %.0e, "
-                               "one HIP graph per iteration"
+                               "HIP graphs of 10 iterations"
                                % (geom.n, geom.n, geom.n_det, math.degrees(geom.arc_span), geom.n_t, B, lam),
                    "batch": B},
         "staged_hbm_gbs": round(it_bytes * steps / (ms * 1e-3) / 1e9, 1),

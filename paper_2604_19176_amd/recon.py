@@ -4,8 +4,8 @@ Projected gradient descent on 0.5 ||A f - g||^2 + lam TV_eps(f) with f >= 0:
     r   = A f - g                       (pat_forward + pat_residual)
     G   = A* r + lam grad TV_eps(f)     (pat_adjoint + pat_tv_grad)
     f  <- max(f - tau G, 0)             (pat_pgd_update)
-Every step runs in the library's kernels; one iteration can be captured once
-as a HIP graph and replayed.  The step is tau = 1 / (||A||^2 + 8 lam / eps),
+Every step runs in the library's kernels; a run of iterations can be
+captured once as a HIP graph and replayed.  The step is tau = 1 / (||A||^2 + 8 lam / eps),
 a Lipschitz bound of the objective's gradient, with ||A||^2 from power
 iteration on A* A.
 """
@@ -47,6 +47,7 @@ class TVReconstructor:
         self.r = torch.empty_like(self.g_meas)
         self.adj = torch.empty_like(self.f)
         self.graph = None
+        self.graph_iters = 0
 
     def step(self):
         p = self.plan
@@ -56,8 +57,10 @@ class TVReconstructor:
         tg = tv_grad(self.f, self.eps)
         pgd_update(self.f, self.adj, tg, self.tau, self.lam)
 
-    def capture(self):
-        """Record one iteration as a HIP graph (torch.cuda.CUDAGraph)."""
+    def capture(self, iters: int = 1):
+        """Record `iters` iterations as one HIP graph (torch.cuda.CUDAGraph);
+        one iteration runs eagerly first (warm-up).  Several iterations per
+        graph remove the gap between consecutive graph launches."""
         self.tg = torch.empty_like(self.f)
         s = torch.cuda.Stream(device=self.plan.device)
         s.wait_stream(torch.cuda.current_stream(self.plan.device))
@@ -66,7 +69,9 @@ class TVReconstructor:
         torch.cuda.current_stream(self.plan.device).wait_stream(s)
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            self._step_static()
+            for _ in range(iters):
+                self._step_static()
+        self.graph_iters = iters
         return self.graph
 
     def _step_static(self):
@@ -81,11 +86,14 @@ class TVReconstructor:
         pgd_update(self.f, self.adj, self.tg, self.tau, self.lam)
 
     def run(self, steps: int, use_graph: bool = True):
+        """`steps` iterations: whole graph replays, then the remainder eagerly."""
         if use_graph:
             if self.graph is None:
                 self.capture()
-            for _ in range(steps):
+            for _ in range(steps // self.graph_iters):
                 self.graph.replay()
+            for _ in range(steps % self.graph_iters):
+                self._step_static()
         else:
             for _ in range(steps):
                 self.step()
@@ -128,8 +136,9 @@ class PDHGReconstructor:
     by the primal-dual hybrid gradient method with K = (A, grad), theta = 1 and
     sigma = tau = 0.99 / sqrt(||A||^2 + 8).  Stops when the relative change
     ||f_k - f_{k-1}|| / ||f_k|| of every instance is at most `tol` (1e-4, Sec. 2.4.2).
-    One iteration runs five launches of the operator pair plus four small
-    kernels; it can be captured as a HIP graph."""
+    One iteration runs the launches of the operator pair plus three small
+    kernels, and the change reduction where the stopping rule reads it; a
+    run of iterations can be captured as one HIP graph."""
 
     def __init__(self, plan: PatPlan, g_meas: torch.Tensor, alpha: float, sigma: float | None = None,
                  tau: float | None = None, f0: torch.Tensor | None = None):
@@ -154,9 +163,12 @@ class PDHGReconstructor:
             tau = s if tau is None else tau
         self.sigma, self.tau = float(sigma), float(tau)
         self.graph = None
+        self.graph_iters = 0
         self.iterations = 0
 
-    def step(self):
+    def step(self, change: bool = True):
+        """One iteration; `change` also reduces ||f_k - f_{k-1}||^2 and ||f_k||^2
+        into self.change (the stopping rule's input)."""
         from . import _stream, pat_pd_change, pat_pd_dual_data, pat_pd_dual_tv, pat_pd_primal
         p, n, B = self.plan, self.plan.geom.n, self.batch
         st = _stream(self.f.device)
@@ -167,10 +179,13 @@ class PDHGReconstructor:
         p.adjoint(self.y1, out=self.aty)
         pat_pd_primal(self.f.data_ptr(), self.fbar.data_ptr(), self.aty.data_ptr(), self.y2.data_ptr(), n, B,
                       self.tau, st)
-        pat_pd_change(self.f.data_ptr(), self.fbar.data_ptr(), self.change.data_ptr(), n, B, st)
+        if change:
+            pat_pd_change(self.f.data_ptr(), self.fbar.data_ptr(), self.change.data_ptr(), n, B, st)
 
-    def capture(self):
-        """Record one iteration as a HIP graph (runs one iteration to warm up)."""
+    def capture(self, iters: int = 10):
+        """Record `iters` iterations as one HIP graph, the change reduction in
+        the last only (runs one iteration eagerly first to warm up).  With
+        `iters` equal to run()'s check interval, every check is one replay."""
         s = torch.cuda.Stream(device=self.plan.device)
         s.wait_stream(torch.cuda.current_stream(self.plan.device))
         with torch.cuda.stream(s):
@@ -179,26 +194,30 @@ class PDHGReconstructor:
         self.iterations += 1
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            self.step()
+            for i in range(iters):
+                self.step(change=i == iters - 1)
+        self.graph_iters = iters
         return self.graph
 
     def relative_change(self):
-        c = self.change.double().cpu()
+        c = self.change.cpu().double()  # copy, then widen on the host: no device kernel
         return (c[:, 0].sqrt() / c[:, 1].sqrt().clamp_min(1e-300)).tolist()
 
     def run(self, max_iters: int, tol: float | None = 1e-4, check_every: int = 10, use_graph: bool = True):
         """Iterate until every instance's relative change is <= tol (checked
         every `check_every` iterations) or max_iters; returns the iteration count."""
         if use_graph and self.graph is None:
-            self.capture()
+            self.capture(check_every)
         done = 0
         while done < max_iters:
             k = min(check_every, max_iters - done)
-            for _ in range(k):
-                if use_graph:
+            rest = k
+            if use_graph:
+                for _ in range(k // self.graph_iters):
                     self.graph.replay()
-                else:
-                    self.step()
+                rest = k % self.graph_iters
+            for i in range(rest):
+                self.step(change=i == rest - 1)
             done += k
             self.iterations += k
             if tol is not None and max(self.relative_change()) <= tol:

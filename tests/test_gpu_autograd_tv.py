@@ -125,6 +125,15 @@ def test_tv_loop_graph_matches_eager_and_cpu(torch_dev):
         _ = (eager.f * 2.0).sum()  # unrelated eager work between replays
         torch.cuda.synchronize()
         assert torch.equal(graph.f, eager.f)
+    # several iterations per graph: run(7) is two replays of three and one eager step
+    multi = TVReconstructor(plan, gmt, lam, eps, tau=eager.tau)
+    multi.capture(3)
+    multi.run(7)
+    level = TVReconstructor(plan, gmt, lam, eps, tau=eager.tau)
+    for _ in range(8):
+        level.step()
+    torch.cuda.synchronize()
+    assert torch.equal(multi.f, level.f)
     # FP64 CPU loop, same tau, same number of steps (5)
     fc = np.zeros((geom.n, geom.n))
     for _ in range(5):

@@ -119,21 +119,31 @@ def test_pdhg_batch_and_graph(torch_dev):
     both = PDHGReconstructor(plan, gb, alpha, sigma=s, tau=t)
     singles = [PDHGReconstructor(plan, gb[b].contiguous(), alpha, sigma=s, tau=t) for b in range(2)]
     graphed = PDHGReconstructor(plan, gb, alpha, sigma=s, tau=t)
-    graphed.capture()          # runs one iteration eagerly, records the next
+    graphed.capture(3)         # runs one iteration eagerly, records the next three
     for r in [both] + singles:
         r.step()
     torch.cuda.synchronize()
     assert torch.equal(graphed.f, both.f)
     for k in range(4):
         graphed.graph.replay()
-        both.step()
-        for r in singles:
-            r.step()
+        for _ in range(3):
+            both.step()
+            for r in singles:
+                r.step()
         _ = float(both.f.sum())  # unrelated eager work between replays
         torch.cuda.synchronize()
         assert torch.equal(graphed.f, both.f), k
+        # the graph reduces the change in its last iteration only
+        assert torch.equal(graphed.change, both.change), k
         for b in range(2):
             assert torch.equal(both.f[b], singles[b].f), (k, b)
+    # run() with a check interval that is not a multiple of the graph's length
+    its = graphed.run(7, tol=None, check_every=5)
+    for _ in range(7):
+        both.step()
+    torch.cuda.synchronize()
+    assert its == 1 + 7        # the warm-up and run(); direct replays are not counted
+    assert torch.equal(graphed.f, both.f) and torch.equal(graphed.change, both.change)
     plan.close()
 
 
