@@ -219,7 +219,10 @@ typedef struct {
     int gat_th;   /* interpolation bands (footprint base rows) per tile: 1, 2, 4, .., 64;
                      the tile window (gat_th + 7) x (gat_cb + 7) x 8 bytes is at most 64 KB  */
     int spr_cb;   /* spread workgroup width: 64, 128, 192 or 256 columns                     */
-    int spr_th;   /* spread output rows per workgroup, 1..4096                               */
+    int spr_th;   /* spread rows (bands) per workgroup: always 8.  Each workgroup sweeps its
+                     own 8 bands; a band's footprint reaches 7 rows further, and those
+                     partial rows are completed in the adjoint row pass, so every grid
+                     row is summed in one fixed order for every launch shape             */
     int gat_ib;   /* instances of a batch sharing one interpolation tile: 1, 2 or 4 (the
                      ES weights and indexing are shared; windows: gat_ib x the size above) */
     int spr_ib;   /* instances of a batch sharing one spread tile: 1, 2 or 4              */
@@ -280,7 +283,8 @@ int  pat_batch_set_launch(pat_batch* batch, const pat_launch* cfg);
  * `batch` instances (1 <= batch <= max_batch) on the null stream, choosing each stage's shape by its own measured kernel
  * time, applies the fastest, and records it in the JSON file cache_path
  * under a key made of the geometry, the batch and the device name; when that
- * key is already in the file the stored shapes are applied without timing.
+ * key is already in the file the stored shapes are applied without timing
+ * (an entry the shape checks now reject is tuned again and replaced).
  * pat_autotune_batch does the same for a batch's interpolation and spread
  * shapes.  cache_path may be NULL (no cache).  Both allocate temporary device
  * buffers and synchronise: tuning calls, not for loops or graph capture.

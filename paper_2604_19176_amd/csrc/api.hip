@@ -38,13 +38,13 @@ static void gather_launch_ib(int cb, dim3 grid, size_t lds, hipStream_t st, cons
 
 template <int IB>
 static void spread_launch_ib(int cb, dim3 grid, size_t lds, hipStream_t st, const PlanDev& d, const WsLayout& L,
-                             InstPtrs wsp, int th, int batch)
+                             InstPtrs wsp, int batch)
 {
     switch (cb) {
-        case 64: hipLaunchKernelGGL((k_spread<IB, 64>), grid, dim3(64), lds, st, d, L, wsp, th, batch); break;
-        case 128: hipLaunchKernelGGL((k_spread<IB, 128>), grid, dim3(128), lds, st, d, L, wsp, th, batch); break;
-        case 192: hipLaunchKernelGGL((k_spread<IB, 192>), grid, dim3(192), lds, st, d, L, wsp, th, batch); break;
-        default: hipLaunchKernelGGL((k_spread<IB, 256>), grid, dim3(256), lds, st, d, L, wsp, th, batch); break;
+        case 64: hipLaunchKernelGGL((k_spread<IB, 64>), grid, dim3(64), lds, st, d, L, wsp, batch); break;
+        case 128: hipLaunchKernelGGL((k_spread<IB, 128>), grid, dim3(128), lds, st, d, L, wsp, batch); break;
+        case 192: hipLaunchKernelGGL((k_spread<IB, 192>), grid, dim3(192), lds, st, d, L, wsp, batch); break;
+        default: hipLaunchKernelGGL((k_spread<IB, 256>), grid, dim3(256), lds, st, d, L, wsp, batch); break;
     }
 }
 // LDS of an FFT tile: nseq sequences of the length plus its per-pass twiddles
@@ -162,13 +162,13 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 2 + qa, st);
     {
-        const int cb = c.spr_cb, th = c.spr_th, ib = tile_ib(c.spr_ib, batch);
-        const int items = ((d.Ng + cb - 1) / cb) * ((d.Hy + th - 1) / th) * ((batch + ib - 1) / ib);
+        const int cb = c.spr_cb, ib = tile_ib(c.spr_ib, batch);
+        const int items = ((d.Ng + cb - 1) / cb) * spread_row_tiles(d.NB) * ((batch + ib - 1) / ib);
         const dim3 grid(xcd_grid(items));
         const size_t lds = spread_lds(cb, ib);
-        if (ib == 4) spread_launch_ib<4>(cb, grid, lds, st, d, p->ws, wsp, th, batch);
-        else if (ib == 2) spread_launch_ib<2>(cb, grid, lds, st, d, p->ws, wsp, th, batch);
-        else spread_launch_ib<1>(cb, grid, lds, st, d, p->ws, wsp, th, batch);
+        if (ib == 4) spread_launch_ib<4>(cb, grid, lds, st, d, p->ws, wsp, batch);
+        else if (ib == 2) spread_launch_ib<2>(cb, grid, lds, st, d, p->ws, wsp, batch);
+        else spread_launch_ib<1>(cb, grid, lds, st, d, p->ws, wsp, batch);
     }
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 3 + qa, st);
@@ -395,7 +395,6 @@ static void batch_layout(pat_batch* b)
         const pat_plan* p = b->plans[i];
         const PlanDev& d = I.d;
         I.gat_th = b->gat_th;
-        I.spr_th = b->spr_th;
         int items[kNumStages];
         items[kStCol] = I.n_col_tiles;
         items[kStRow] = (d.Hy + I.row_rpb - 1) / I.row_rpb;
@@ -404,7 +403,7 @@ static void batch_layout(pat_batch* b)
         items[kStDct] = I.n_pair_tiles;
         items[kStSynFwd] = d.syn_dense ? syn_fwd_tiles(d) : 0;
         items[kStSynAdj] = d.syn_dense ? syn_adj_tiles(d) : 0;
-        items[kStSpread] = ((d.Ng + b->spr_cb - 1) / b->spr_cb) * ((d.Hy + b->spr_th - 1) / b->spr_th);
+        items[kStSpread] = ((d.Ng + b->spr_cb - 1) / b->spr_cb) * spread_row_tiles(d.NB);
         for (int s = 0; s < kNumStages; ++s)
             b->base[(size_t)s * (n + 1) + i + 1] = b->base[(size_t)s * (n + 1) + i] + items[s];
         b->thr_col = std::max<unsigned>(b->thr_col, p->thr_col);
@@ -474,7 +473,7 @@ extern "C" int pat_batch_create(pat_plan* const* plans, int count, pat_batch** o
     for (int i = 0; i < count; ++i) cells += (long)b->inst[i].d.Ng * b->inst[i].d.Hy;
     b->gat_cb = 64;
     b->gat_th = 8;
-    if (cells >= 8L * 512 * 265) { b->gat_cb = 128; b->gat_th = 16; b->spr_cb = 256; b->spr_th = 16; }
+    if (cells >= 8L * 512 * 265) { b->gat_cb = 128; b->gat_th = 16; b->spr_cb = 256; }
     batch_layout(b);
     b->base_off = (sizeof(BatchInst) * (size_t)count + 255) & ~(size_t)255;
     int cur = 0;

@@ -1080,14 +1080,17 @@ __device__ __forceinline__ void spread_visit(const SpreadLds<IB>& S, int s0, int
 // One tile of the spread for IB instances of one plan (wbs[b], b < nb, are the
 // instance workspaces; instances b >= nb are padding and neither read nor
 // written).  The workgroup has CB threads, one per column; CAP = 2 CB points
-// are staged per chunk.  CB is a compile-time constant so that every LDS
+// are staged per chunk.  Row tile rt sweeps bands [8 rt, 8 rt + 8) only and
+// writes their grid rows; the 7 rows after its last band are partial sums,
+// left in the tail region unless the tile is the last one (the adjoint row
+// pass adds them to the next tile's first rows).  CB is a compile-time constant so that every LDS
 // access of the inner loops is an immediate offset from one base address.
 template <int IB, int CB>
 __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L, char* const (&wbs)[IB], int nb,
-                                            int tile, int TH, float* sf)
+                                            int tile, float* sf)
 {
     constexpr int CAP = 2 * CB;
-    const int Ng = d.Ng, NB = d.NB, Hy = d.Hy;
+    const int Ng = d.Ng, NB = d.NB;
     const int ncb = (Ng + CB - 1) / CB;
     const int rb_ = tile / ncb, cb_ = tile - rb_ * ncb;
     const float2* __restrict__ H[IB];
@@ -1103,17 +1106,16 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
     S.bx = (int*)(sf + 16 * CAP);
     S.h = (float2*)(sf + 17 * CAP);  // CAP is even: 8-byte aligned
     int* rows = (int*)(sf + (size_t)CAP * (17 + 2 * IB));  // [3][CB + 10]
-    const int C0 = cb_ * CB, R0 = rb_ * TH;
+    const int C0 = cb_ * CB, R0 = rb_ * kSpreadTh;
     const int mx = C0 + threadIdx.x;
     const int lane7 = threadIdx.x + 7;
     const bool active = mx < Ng;
-    const int rend = min(R0 + TH, Hy);
     float2 acc[IB][8];
 #pragma unroll
     for (int b = 0; b < IB; ++b)
 #pragma unroll
         for (int k = 0; k < 8; ++k) acc[b][k] = make_float2(0.f, 0.f);
-    const int band_lo = max(0, R0 - 7), band_hi = min(NB - 1, rend - 1);
+    const int band_lo = R0, band_hi = min(NB - 1, R0 + kSpreadTh - 1);
     const int e0 = threadIdx.x, e1 = threadIdx.x + CB;
     // tile-relative footprint column of a staged point: the wrapped segment
     // (columns Ng-7 .. Ng-1 seen from a tile at column 0) is shifted by -Ng
@@ -1126,7 +1128,7 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
 #pragma unroll
         for (int b = 0; b < IB; ++b) h[b] = b < nb ? H[b][sl] : make_float2(0.f, 0.f);
     };
-    // band_lo <= band_hi always: R0 <= Hy - 1 = NB + 7 - 1 gives R0 - 7 <= NB - 1
+    // band_lo <= band_hi always: there are ceil(NB / kSpreadTh) row tiles
     // Pipeline over bands (three LDS slots of CSR rows, slot of band r = (r - band_lo) % 3):
     // in the step of band rb, the CSR row of band rb+2 (fetched in the previous
     // step) is stored, the row of band rb+3 and the points of band rb+1 are
@@ -1186,8 +1188,8 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
             spread_visit<IB, CAP>(S, max(m.lo, c0), min(m.hi, c0 + cn), c0, lane7, acc);
             __syncthreads();
         }
-        // row rb is complete
-        if (active && rb >= R0 && rb < rend) {
+        // row rb has all of this tile's contributions
+        if (active) {
 #pragma unroll
             for (int b = 0; b < IB; ++b)
                 if (b < nb) Gt[b][(size_t)rb * Ng + mx] = acc[b][0];
@@ -1199,14 +1201,18 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
             acc[b][7] = make_float2(0.f, 0.f);
         }
     }
-    // rows after the last band receive no further contributions
+    // the 7 rows after the tile's last band: complete after the plan's last band
+    // (rows NB .. Hy - 1), else partial sums for the tail region
+    const bool last = band_hi == NB - 1;
+    if (active) {
 #pragma unroll
-    for (int k = 0; k < 7; ++k) {
-        const int r = band_hi + 1 + k;
-        if (active && r >= R0 && r < rend) {
+        for (int k = 0; k < 7; ++k) {
 #pragma unroll
-            for (int b = 0; b < IB; ++b)
-                if (b < nb) Gt[b][(size_t)r * Ng + mx] = acc[b][k];
+            for (int b = 0; b < IB; ++b) {
+                if (b >= nb) continue;
+                if (last) Gt[b][(size_t)(band_hi + 1 + k) * Ng + mx] = acc[b][k];
+                else ((float2*)(wbs[b] + L.tail))[((size_t)rb_ * 7 + k) * Ng + mx] = acc[b][k];
+            }
         }
     }
 }
@@ -1214,6 +1220,8 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
 // ---------------------------------------------------------------------------
 // adjoint: row pass (inverse FFT along x, crop to the N image columns)
 // ---------------------------------------------------------------------------
+// Grid row r = 8 q + k with q >= 1, k < 7 and 8 q < NB (a spread row tile q
+// exists) receives the tail left by spread row tile q - 1.
 __device__ __forceinline__ void rowpass_adj_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile, int RPB,
                                                  float2* sm)
 {
@@ -1223,8 +1231,24 @@ __device__ __forceinline__ void rowpass_adj_tile(const PlanDev& d, const WsLayou
     const int r0 = tile * RPB;
     const int nr = min(RPB, d.Hy - r0);
     const float2* tb = fft_twiddles_to_lds(sm + RPB * Ng, d.ffts[d.fft_grid], d.tw);
+    static_assert(kSpreadTh == 8, "the tail lookup below divides by shifting");
+    const float2* Tl = (const float2*)(wb + L.tail);
+    const float rcpNg = 1.0f / (float)Ng;
     fill_batched<4>(
-        nr * Ng, [&](int e) { return Gt[(size_t)r0 * Ng + e]; }, [&](int e, float2 v) { sm[e] = v; });
+        nr * Ng,
+        [&](int e) {
+            int rr, c;
+            fdivmod(e, Ng, rcpNg, rr, c);
+            const int r = r0 + rr, q = r >> 3, k = r & 7;
+            float2 v = Gt[(size_t)r0 * Ng + e];
+            if (q >= 1 && k < 7 && 8 * q < d.NB) {
+                const float2 t = Tl[((size_t)(q - 1) * 7 + k) * Ng + c];
+                v.x += t.x;
+                v.y += t.y;
+            }
+            return v;
+        },
+        [&](int e, float2 v) { sm[e] = v; });
     __syncthreads();
     fft_lds<true>(sm, Ng, nr, d.ffts[d.fft_grid], tb);
     const float rcpN = 1.0f / (float)N;
@@ -1516,10 +1540,10 @@ __global__ __launch_bounds__(1024) void k_dct_det_b(BatchDev bt, char* ws, float
 
 // IB instances per workgroup: instances g*IB .. g*IB + IB - 1 of the batch; CB threads.
 template <int IB, int CB>
-__global__ __launch_bounds__(CB) void k_spread(PlanDev d, WsLayout L, InstPtrs wsp, int TH, int batch)
+__global__ __launch_bounds__(CB) void k_spread(PlanDev d, WsLayout L, InstPtrs wsp, int batch)
 {
     extern __shared__ float sf[];
-    const int per = ((d.Ng + CB - 1) / CB) * ((d.Hy + TH - 1) / TH);
+    const int per = ((d.Ng + CB - 1) / CB) * spread_row_tiles(d.NB);
     const int ngroups = (batch + IB - 1) / IB;
     const int item = xcd_item(blockIdx.x, per * ngroups);
     if (item < 0) return;
@@ -1528,7 +1552,7 @@ __global__ __launch_bounds__(CB) void k_spread(PlanDev d, WsLayout L, InstPtrs w
     char* wbs[IB];
 #pragma unroll
     for (int b = 0; b < IB; ++b) wbs[b] = wsp.ws + (size_t)(b0 + (b < nb ? b : 0)) * wsp.stride;
-    spread_tile<IB, CB>(d, L, wbs, nb, item - g * per, TH, sf);
+    spread_tile<IB, CB>(d, L, wbs, nb, item - g * per, sf);
 }
 
 template <int CB>
@@ -1540,7 +1564,7 @@ __global__ __launch_bounds__(CB) void k_spread_b(BatchDev bt, char* ws)
     const BatchInst& I = bt.inst[i];
     const PlanDev d = I.d;
     char* const wbs[1] = {ws + I.ws_off};
-    spread_tile<1, CB>(d, I.L, wbs, 1, tile, I.spr_th, sf);
+    spread_tile<1, CB>(d, I.L, wbs, 1, tile, sf);
 }
 
 __global__ __launch_bounds__(1024) void k_rowpass_adj(PlanDev d, WsLayout L, InstPtrs wsp, int RPB)

@@ -127,7 +127,7 @@ struct LaunchCfg {
     int gat_cb;      // interpolation: columns per tile (32, 64, 128 or 256)
     int gat_th;      // interpolation: bands per tile (power of two, 1..64)
     int spr_cb;      // spread: columns per workgroup (multiple of 64)
-    int spr_th;      // spread: rows per workgroup
+    int spr_th;      // spread: rows per workgroup (always kSpreadTh)
     int gat_ib;      // interpolation: instances per tile (1, 2 or 4)
     int spr_ib;      // spread: instances per tile (1, 2 or 4)
     int spr_cap;     // spread: points staged in LDS per chunk
@@ -173,9 +173,19 @@ inline bool gather_shape_ok(int cb, int th, int ib)
     return (cb == 32 || cb == 64 || cb == 128 || cb == 256) && th >= 1 && th <= 64 && (th & (th - 1)) == 0 &&
            ib_ok(ib) && gather_lds_bytes(cb, th, ib) <= 64 * 1024;
 }
+// Spread row tiles: kSpreadTh consecutive bands each (ceil(NB / kSpreadTh)
+// tiles), every band swept by one tile only.  A band's footprint reaches the 7
+// rows after it, so a tile's contributions to the 7 rows after its last band
+// are partial sums: unless the tile is the last one, it leaves them in the
+// workspace's tail region and the adjoint row pass adds them to the next
+// tile's first 7 rows.  Every grid row is thus the sum of its bands from the
+// same 8-row block, then plus the sum of its bands from the block before: one
+// fixed order for every launch shape and batch.
+constexpr int kSpreadTh = 8;
+__host__ __device__ inline int spread_row_tiles(int NB) { return (NB + kSpreadTh - 1) / kSpreadTh; }
 inline bool spread_shape_ok(int cb, int th, int ib)
 {
-    return cb >= 64 && cb <= 256 && cb % 64 == 0 && th >= 1 && th <= 4096 && ib_ok(ib);
+    return cb >= 64 && cb <= 256 && cb % 64 == 0 && th == kSpreadTh && ib_ok(ib);
 }
 // Instances per tile for a call on `batch` instances of one plan: the largest
 // of 4, 2, 1 that is at most the configured count and the batch.
@@ -192,6 +202,7 @@ struct WsLayout {
     size_t hdet;     // [nlam][D] float    ring output (synthesised at the detectors) / cosine-adjoint output
     size_t polar;    // [npts]    float2   polar values: ring order (interpolation output), band order (spread input)
     size_t modes;    // [nlam][K+1] float2 mode coefficients (explicit detector angles only)
+    size_t tail;     // [ceil(NB/8)][7][Ng] float2  spread: partial sums after each row tile's last band
     size_t red;      // small FP32 partial sums (mass / data sum)
     int n_red;       // number of partial sums
     size_t bytes;    // total per instance
@@ -205,7 +216,7 @@ enum BatchStage {
     kStGather,    // interpolation: ceil(Ng / gat_cb) x ceil(NB / gat_th) tiles
     kStRing,      // ring kernels: ceil(nlam / ring_rt) tiles
     kStDct,       // cosine transforms: ceil(ceil(D / 2) / dct_dp) tiles
-    kStSpread,    // spread: ceil(Ng / spr_cb) x ceil(Hy / spr_th) tiles
+    kStSpread,    // spread: ceil(Ng / spr_cb) x ceil(NB / kSpreadTh) tiles
     kStSynFwd,    // dense synthesis (explicit angles): ceil(nlam / 64) x ceil(D / 64) tiles, else 0
     kStSynAdj,    // its transpose: ceil(nlam / 64) x ceil(2 (K + 1) / 64) tiles, else 0
     kNumStages
@@ -218,7 +229,7 @@ struct BatchInst {
     PlanDev d;
     WsLayout L;
     size_t ws_off;    // byte offset of the instance's workspace in the batch workspace
-    int col_np, row_rpb, ring_rt, dct_dp, gat_th, spr_th;
+    int col_np, row_rpb, ring_rt, dct_dp, gat_th;
     int n_col_tiles, n_pair_tiles;
 };
 
@@ -267,7 +278,7 @@ struct pat_batch {
     void* table = nullptr;             // device: BatchInst[count], then base
     size_t base_off = 0;
     size_t ws_bytes = 0;
-    int gat_cb = 64, gat_th = 8, spr_cb = 64, spr_th = 32;
+    int gat_cb = 64, gat_th = 8, spr_cb = 64, spr_th = pat::kSpreadTh;
     // per-stage workgroup size and dynamic LDS (maxima over the instances)
     unsigned thr_col = 0, thr_row = 0, thr_ring = 0, thr_dct = 0;
     size_t lds_col = 0, lds_row = 0, lds_ring = 0, lds_dct = 0;

@@ -550,19 +550,14 @@ int choose_launch(pat_plan* p, const std::vector<FftDev>& fd, int max_batch)
     const long gwide = (long)((d.Ng + 255) / 256) * ((d.NB + 31) / 32) * max_batch;
     c.gat_cb = 64;
     c.gat_th = gwide >= 512 ? 16 : 8;
-    // spread: wide tiles for large batches; rows per tile as many as keep about
-    // 512 workgroups (a tile sweeps th + 7 bands for th output rows)
+    // spread: wide tiles for large batches, 128 columns for small ones (measured
+    // at 256^2: batch 1 fastest with 128..256 columns, 64 slower)
     const int ib = tile_ib(4, max_batch);
     c.gat_ib = ib;
     c.spr_ib = ib;
     const long groups = (max_batch + ib - 1) / ib;
-    c.spr_cb = (d.Ng >= 512 && groups >= 8) ? 256 : 64;
-    c.spr_th = 1;
-    for (int th = 32; th >= 1; th /= 2)
-        if ((long)((d.Ng + c.spr_cb - 1) / c.spr_cb) * ((d.Hy + th - 1) / th) * groups >= 512) {
-            c.spr_th = th;
-            break;
-        }
+    c.spr_cb = (d.Ng >= 512 && groups >= 8) ? 256 : (d.Ng >= 256 ? 128 : 64);
+    c.spr_th = kSpreadTh;
     if (!c.col_np || !c.row_rpb || !c.dct_dp) return PAT_ERR_UNSUPPORTED;
     return apply_launch(p, c);
 }
@@ -578,6 +573,8 @@ void layout_workspace(pat_plan* p)
     w.polar = o;  o += align256(sizeof(float2) * (size_t)d.npts);
     // explicit angles: mode coefficients a_k(n) (forward) / their adjoints, [nlam][K+1]
     w.modes = o;  o += d.syn_dense ? align256(sizeof(float2) * (size_t)d.nlam * d.Kp) : 0;
+    // spread: 7 partial rows per row tile
+    w.tail = o;   o += align256(sizeof(float2) * 7 * (size_t)d.Ng * spread_row_tiles(d.NB));
     // endpoint-term partial sums: one per image column (forward) or detector (adjoint)
     w.n_red = std::max(d.N, d.D);
     w.red = o;    o += align256(sizeof(float) * (size_t)w.n_red);

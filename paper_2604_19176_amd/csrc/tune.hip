@@ -26,8 +26,8 @@ const int kDctDp[] = {1, 2, 4, 8};
 // (columns, rows or bands, instances per tile); a candidate whose LDS does not fit is skipped
 const int kGather[][3] = {{64, 8, 4}, {64, 16, 4}, {32, 8, 4}, {64, 4, 4}, {64, 16, 2}, {128, 16, 1},
                           {64, 8, 1}, {128, 8, 2}, {64, 4, 1}, {32, 16, 4}};
-const int kSpread[][3] = {{256, 16, 4}, {256, 8, 4}, {128, 8, 4}, {256, 16, 2}, {256, 8, 2}, {64, 4, 1},
-                          {64, 2, 1}, {256, 4, 1}, {64, 8, 4}, {128, 16, 2}};
+const int kSpread[][3] = {{256, 8, 4}, {192, 8, 4}, {128, 8, 4}, {256, 8, 2}, {128, 8, 2}, {192, 8, 1},
+                          {128, 8, 1}, {256, 8, 1}, {64, 8, 4}, {64, 8, 1}};
 
 enum { kSCol, kSRow, kSRing, kSDct, kSGather, kSSpread, kNS };
 
@@ -227,7 +227,8 @@ extern "C" int pat_autotune_plan(pat_plan* p, int batch, const char* cache_path)
         const int rc = cache_read(cache_path, text);
         if (rc < 0) return PAT_ERR_ARG;
         pat_launch c = def;
-        if (rc > 0 && cache_lookup(text, key, c)) return pat_plan_set_launch(p, &c);
+        // an entry the library no longer accepts (older shape rules) is re-tuned and replaced
+        if (rc > 0 && cache_lookup(text, key, c) && pat_plan_set_launch(p, &c) == PAT_OK) return PAT_OK;
     }
     const pat_plan_desc& dsc = p->desc;
     DevBufs bufs;
@@ -307,7 +308,7 @@ extern "C" int pat_autotune_batch(pat_batch* b, const char* cache_path)
         const int rc = cache_read(cache_path, text);
         if (rc < 0) return PAT_ERR_ARG;
         pat_launch c = def;
-        if (rc > 0 && cache_lookup(text, key, c)) return pat_batch_set_launch(b, &c);
+        if (rc > 0 && cache_lookup(text, key, c) && pat_batch_set_launch(b, &c) == PAT_OK) return PAT_OK;
     }
     DevBufs bufs;
     size_t nf = 0, ng = 0;

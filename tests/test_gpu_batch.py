@@ -46,12 +46,12 @@ def _inputs(torch, geom, seed, batch=None):
 
 
 SHAPES = [
-    dict(col_np=1, row_rpb=1, ring_rt=1, dct_dp=1, gat_cb=64, gat_th=8, spr_cb=64, spr_th=16, gat_ib=1, spr_ib=1),
-    dict(col_np=2, row_rpb=16, ring_rt=2, dct_dp=8, gat_cb=128, gat_th=32, spr_cb=192, spr_th=16, gat_ib=1,
+    dict(col_np=1, row_rpb=1, ring_rt=1, dct_dp=1, gat_cb=64, gat_th=8, spr_cb=64, spr_th=8, gat_ib=1, spr_ib=1),
+    dict(col_np=2, row_rpb=16, ring_rt=2, dct_dp=8, gat_cb=128, gat_th=32, spr_cb=192, spr_th=8, gat_ib=1,
          spr_ib=2),
     dict(col_np=16, row_rpb=4, ring_rt=4, dct_dp=2, gat_cb=64, gat_th=16, spr_cb=256, spr_th=8, gat_ib=4,
          spr_ib=4),
-    dict(col_np=4, row_rpb=2, ring_rt=3, dct_dp=3, gat_cb=32, gat_th=1, spr_cb=128, spr_th=37, gat_ib=2, spr_ib=4),
+    dict(col_np=4, row_rpb=2, ring_rt=3, dct_dp=3, gat_cb=32, gat_th=1, spr_cb=128, spr_th=8, gat_ib=2, spr_ib=4),
 ]
 
 
@@ -91,7 +91,7 @@ def test_launch_shapes_against_oracle_and_rejections(torch_dev):
     before = plan.launch
     for bad in [dict(gat_cb=100), dict(gat_cb=24), dict(gat_th=12), dict(gat_cb=256, gat_th=64), dict(spr_cb=320), dict(gat_th=0),
                 dict(ring_rt=0), dict(col_np=17), dict(dct_dp=0), dict(row_rpb=17), dict(gat_ib=3),
-                dict(spr_ib=0), dict(gat_cb=128, gat_th=16, gat_ib=4)]:
+                dict(spr_ib=0), dict(gat_cb=128, gat_th=16, gat_ib=4), dict(spr_th=16), dict(spr_th=4)]:
         with pytest.raises(pat.PatError) as ei:
             plan.set_launch(**bad)
         assert ei.value.status == -1
@@ -140,7 +140,7 @@ def test_batch_equals_per_instance_bitwise(torch_dev):
         assert torch.equal(gb[i], p.forward(fs[i])), i
         assert torch.equal(ab[i], p.adjoint(ds[i])), i
     # other batch-wide interpolation / spread shapes: still bitwise the same
-    for shp in [dict(gat_cb=64, gat_th=8, spr_cb=64, spr_th=16), dict(gat_cb=128, gat_th=32, spr_cb=128, spr_th=7)]:
+    for shp in [dict(gat_cb=64, gat_th=8, spr_cb=64, spr_th=8), dict(gat_cb=128, gat_th=32, spr_cb=192, spr_th=8)]:
         batch.set_launch(**shp)
         assert batch.launch == shp
         g2 = batch.forward(fs)

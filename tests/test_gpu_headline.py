@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-5
 B = 64
 # the batch-64 shapes of the tuned bench run at this workload
-TUNED = dict(col_np=8, row_rpb=4, ring_rt=1, dct_dp=2, gat_cb=64, gat_th=16, spr_cb=256, spr_th=16, gat_ib=2,
+TUNED = dict(col_np=8, row_rpb=4, ring_rt=1, dct_dp=2, gat_cb=64, gat_th=16, spr_cb=256, spr_th=8, gat_ib=2,
              spr_ib=4)
 SAMPLED = (0, 31, 63)
 
