@@ -99,39 +99,55 @@ def algorithmic_flops(info, geom, name):
     return None
 
 
-def roofline(kms, info, geom, B):
-    """Roofline entry for the kernel with the largest per-launch time."""
-    dom = max(kms, key=kms.get)
-    t = kms[dom] * 1e-3
-    traffic = None
+def measured_traffic(dom, B):
+    """HBM bytes per launch of kernel `dom` from the committed counter summary,
+    or None when it was taken at another batch or from other device sources."""
     try:
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
-        if tr.get("kernels_hash") == kernels_hash() and tr.get("kernel", "").split("<")[0] == KERNEL_SYMBOL[dom] \
-                and tr.get("batch") == B:
-            traffic = int(tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"])
-    except (OSError, ValueError, KeyError):
-        traffic = None
+        if tr.get("kernels_hash") != kernels_hash() or tr.get("batch") != B:
+            return None
+        for name, d in tr.get("kernels", {}).items():
+            if name.split("<")[0] == KERNEL_SYMBOL[dom]:
+                return int(d["fetch_bytes_per_launch"] + d["write_bytes_per_launch"])
+    except (OSError, ValueError, KeyError, AttributeError):
+        pass
+    return None
+
+
+def roofline(kms, info, geom, B):
+    """Roofline entry for the kernel with the largest per-launch time.  A
+    kernel with nominal flops is ALU-bound when its flops per algorithmic byte
+    exceed the ridge point of the FP32 rate this build can issue (packed FP32
+    is off, so 78.6 TFLOP/s) over HBM's 8 TB/s; otherwise it is HBM-bound."""
+    dom = max(kms, key=kms.get)
+    t = kms[dom] * 1e-3
+    traffic = measured_traffic(dom, B)
     fl = algorithmic_flops(info, geom, dom)
+    byt = algorithmic_bytes(info, geom)[dom] * B
+    ridge = FP32_NONPACKED_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
     if fl is not None and dom.startswith("syn_"):
         flops = fl * B
         ach = flops / t / 1e12
         return {"bound": "mfma", "kernel": dom, "achieved": round(ach, 3), "peak": MFMA_FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / MFMA_FP32_PEAK_TFLOPS, 4), "flops_per_launch": int(flops),
                 "avg_launch_ms": round(kms[dom], 4), "traffic": traffic}
-    if fl is not None:
+    if fl is not None and fl * B / byt > ridge:
         flops = fl * B
         ach = flops / t / 1e12
         return {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4),
                 "frac_of_nonpacked_78.6": round(ach / FP32_NONPACKED_TFLOPS, 4),
                 "flops_per_launch": int(flops), "avg_launch_ms": round(kms[dom], 4), "traffic": traffic,
-                "algorithmic_bytes_per_launch": algorithmic_bytes(info, geom)[dom] * B}
-    byt = algorithmic_bytes(info, geom)[dom] * B
+                "algorithmic_bytes_per_launch": byt}
     ach = byt / t / 1e9
-    return {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_launch": byt, "avg_launch_ms": round(kms[dom], 4),
-            "traffic": traffic}
+    out = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_launch": byt, "avg_launch_ms": round(kms[dom], 4),
+           "traffic": traffic}
+    if fl is not None:  # below the ridge point: the nominal flops for reference
+        out["flops_per_launch"] = int(fl * B)
+        out["flops_per_byte"] = round(fl * B / byt, 2)
+    return out
 
 
 def kernel_times(pat, plan, f, g, gout, fout, nprof=10):

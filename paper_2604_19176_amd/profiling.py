@@ -6,9 +6,9 @@ calls), the number of dispatches and their average duration, next to
 rocprofv3's own average over all of a kernel's dispatches.
 
 `python -m paper_2604_19176_amd.profiling traffic <fetch.csv> <write.csv>
---kernel NAME --calib-bytes BYTES` turns two `--pmc FETCH_SIZE` /
-`--pmc WRITE_SIZE` counter-collection files into HBM bytes per launch of one
-kernel.  Each counter (KiB per dispatch) is scaled by known/counted bytes of
+--kernel NAME [NAME ...] --calib-bytes BYTES` turns two `--pmc FETCH_SIZE` /
+`--pmc WRITE_SIZE` counter-collection files into HBM bytes per launch of
+each named kernel (one JSON object, entries under "kernels").  Each counter (KiB per dispatch) is scaled by known/counted bytes of
 the calibration copy in the same run: the float32 multiply-by-one kernel with
 the largest counter value (it reads and writes BYTES each).
 """
@@ -135,7 +135,7 @@ def main(argv=None):
     t = sub.add_parser("traffic")
     t.add_argument("fetch")
     t.add_argument("write")
-    t.add_argument("--kernel", required=True)
+    t.add_argument("--kernel", required=True, nargs="+")
     t.add_argument("--calib-bytes", type=float, required=True)
     t.add_argument("--batch", type=int, required=True)
     t.add_argument("--source", required=True)
@@ -143,9 +143,8 @@ def main(argv=None):
     if a.cmd == "stats":
         print(stats_table(a.trace, a.stats_csv))
     else:
-        d = traffic(a.fetch, a.write, a.kernel, a.calib_bytes)
-        d["batch"] = a.batch
-        d["kernels_hash"] = source_hash(a.source)
+        d = {"batch": a.batch, "kernels_hash": source_hash(a.source), "calib_bytes": a.calib_bytes,
+             "kernels": {k: traffic(a.fetch, a.write, k, a.calib_bytes) for k in a.kernel}}
         json.dump(d, sys.stdout, indent=1)
         print()
 
