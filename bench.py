@@ -124,7 +124,6 @@ def roofline(kms, info, geom, B):
     t = kms[dom] * 1e-3
     traffic = measured_traffic(dom, B)
     fl = algorithmic_flops(info, geom, dom)
-    byt = algorithmic_bytes(info, geom)[dom] * B
     ridge = FP32_NONPACKED_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
     if fl is not None and dom.startswith("syn_"):
         flops = fl * B
@@ -132,6 +131,7 @@ def roofline(kms, info, geom, B):
         return {"bound": "mfma", "kernel": dom, "achieved": round(ach, 3), "peak": MFMA_FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / MFMA_FP32_PEAK_TFLOPS, 4), "flops_per_launch": int(flops),
                 "avg_launch_ms": round(kms[dom], 4), "traffic": traffic}
+    byt = algorithmic_bytes(info, geom)[dom] * B
     if fl is not None and fl * B / byt > ridge:
         flops = fl * B
         ach = flops / t / 1e12
