@@ -207,7 +207,9 @@ __device__ __forceinline__ void fft_pass(float2* xs, bool active, int u, int tps
 {
     constexpr int MB = radix_max_butterflies(R, MAXB);
     const int nb = n / R;
-    const float rcp = 1.0f / (float)Ns;
+    // the hardware reciprocal (within 1 ulp): fdivmod's correction step makes
+    // the quotient exact, so no IEEE division is needed here
+    const float rcp = __builtin_amdgcn_rcpf((float)Ns);
     float2 v[MB][R];
     int dst[MB];
 #pragma unroll
@@ -306,8 +308,13 @@ __host__ __device__ inline int tw_lds_slots(int n) { return 64 + (n + 63) / 64; 
 // w_n^e (e < n).
 __device__ __forceinline__ float2 tw_lds_entry(const FftDev& d, const float2* __restrict__ twall, int e)
 {
-    const unsigned idx = e < 64 ? e : 64 * (e - 64);
-    return twall[d.tw + (int)(idx % (unsigned)d.n)];
+    // for e < tw_lds_slots(n) the hi entries 64 (e - 64) are below n and the lo
+    // entries e < 64 wrap only when n < 64: reduce by subtraction (n is the
+    // same for the whole workgroup; at most 63 / n rounds)
+    const int n = max(d.n, 1);
+    int idx = e < 64 ? e : 64 * (e - 64);
+    while (idx >= n) idx -= n;
+    return twall[d.tw + idx];
 }
 
 // The first two entries per thread of a two-level table (e = threadIdx.x and

@@ -538,6 +538,7 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
     const int nr = min(RT, d.nlam - n0);
     const bool half = d.fold_P && d.syn_half;
     const float rcp_s = 1.0f / (float)max(d.fold_s, 1);
+    const float rcp_P = __builtin_amdgcn_rcpf((float)max(d.fold_P, 1));  // fdivmod makes k mod P exact
     // the mode values Q~ go to qb, the Hermitian-part input of the ring's inverse FFT to eb
     float2* const qb = half ? R.sy : R.sa;
     float2* const eb = half ? R.sa : R.sy;
@@ -613,7 +614,8 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
             fill_batched<kRingFillUnroll>(
                 Kn + 1,
                 [&](int k) {
-                    const int sidx = d.fold_P ? k % d.fold_P : k;
+                    int sidx = k, fq;
+                    if (d.fold_P) fdivmod(k, d.fold_P, rcp_P, fq, sidx);
                     return cmulc(ytil(sidx), cf[k]);
                 },
                 [&](int k, float2 v) { qb[k] = v; });
