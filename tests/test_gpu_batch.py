@@ -231,8 +231,18 @@ def test_autotune_plan_writes_and_reuses_cache(torch_dev, tmp_path):
     assert plan2.autotune(batch=4, cache_path=cache) == chosen       # from the cache
     plan2.autotune(batch=1, cache_path=cache)                         # a second key
     assert len(json.load(open(cache))) == 2
+    # an entry the shape checks now reject (another spread tile height) is tuned again and replaced
+    stale = json.load(open(cache))
+    stale[key] = dict(stale[key], spr_th=16)
+    with open(cache, "w") as fh:
+        json.dump(stale, fh)
+    plan3 = pat.PatPlan(geom, max_batch=4)
+    again = plan3.autotune(batch=4, cache_path=cache)
+    assert again["spr_th"] == 8 and json.load(open(cache))[key] == again
+    assert torch.equal(plan3.forward(f), g0) and torch.equal(plan3.adjoint(d), a0)
     plan.close()
     plan2.close()
+    plan3.close()
 
 
 def test_autotune_batch(torch_dev, tmp_path):
