@@ -20,8 +20,15 @@ Other workloads (one JSON line each; not the default):
   --workload pdhg3   primal-dual TV (the paper's TV baseline) at 256^2, 128 detectors on 120 deg,
                      run to relative change <= 1e-4: iterations/s and time to solution
   --workload pdhg-large  the same at 1024^2, 1024 detectors on 270 deg, batch 8
+      (with --sim-data, both primal-dual workloads reconstruct from data the FFT
+      wave-propagation simulator computed on a grid twice as fine)
+  --workload cgls    CGLS steps/s on the default workload (two steps per HIP graph)
+  --workload dip     deep-image-prior iterations/s at the paper's timed shape
+  --workload dense   the default workload with jittered explicit detector angles
+                     (dense angular synthesis on the matrix cores)
+  --workload sim     FFT wave-propagation data simulations/s on the 512^2 fine grid
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B] [--workload ...]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B] [--workload ...] [--sim-data]
 """
 from __future__ import annotations
 
