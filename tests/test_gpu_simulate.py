@@ -79,6 +79,24 @@ def test_simulator_full_size_sampled_times(torch_dev):
     sim.close()
 
 
+def test_simulator_box_above_4096(torch_dev):
+    torch = torch_dev
+    import paper_2604_19176_amd as pat
+    from oracle import simulate as ref
+    # 64 samples up to t = 32: the wrap-free box for a 256^2 grid is 4374 cells wide
+    geom = Geometry(n=256, n_det=64, n_t=64, dt=0.5, arc_span=math.radians(270))
+    f = make_phantom(geom.n, 8, 2, 2, 77)
+    sim = pat.PatSim(geom)
+    assert sim.box_side == 4374 == ref.box_side(geom.n, geom.det_r, geom.support_r, geom.c, geom.n_t * geom.dt)
+    g = sim.run(torch.tensor(f, dtype=torch.float32, device="cuda")).cpu().double().numpy()
+    cols = [0, 1, 2, 3]
+    g_ref = ref.simulate(geom, f, times=[(j + 1) * geom.dt for j in cols])
+    err = _rel(g[:, cols], g_ref)
+    print("256^2, box 4374: rel L2 %.2e at %d sampled times" % (err, len(cols)))
+    assert err <= TOL
+    sim.close()
+
+
 def test_simulator_and_operator_model_the_same_waves(torch_dev):
     torch = torch_dev
     import paper_2604_19176_amd as pat
