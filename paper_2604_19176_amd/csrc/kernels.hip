@@ -1085,8 +1085,9 @@ __device__ __forceinline__ void spread_visit(const SpreadLds<IB>& S, int s0, int
 // are staged per chunk.  Row tile rt sweeps bands [8 rt, 8 rt + 8) only and
 // writes their grid rows; the 7 rows after its last band are partial sums,
 // left in the tail region unless the tile is the last one (the adjoint row
-// pass adds them to the next tile's first rows).  CB is a compile-time constant so that every LDS
-// access of the inner loops is an immediate offset from one base address.
+// pass adds them to the next tile's first rows).  CB is a compile-time
+// constant so that every LDS access of the inner loops is an immediate offset
+// from one base address.
 template <int IB, int CB>
 __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L, char* const (&wbs)[IB], int nb,
                                             int tile, float* sf)
