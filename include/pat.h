@@ -150,7 +150,7 @@ int  pat_residual(float* g, const float* g_meas, float* sq, long count_per, int 
 /* Primal-dual TV reconstruction (the classical baseline of Sec. 2.1:
  * min_{f >= 0} 0.5 ||A f - g||^2 + alpha TV(f), solved with the primal-dual
  * hybrid gradient method the paper cites, stopped on the relative change of
- * Sec. 2.4.2).  With K = (A, grad), one iteration is
+ * Sec. 2.3).  With K = (A, grad), one iteration is
  *   A fbar -> ax (pat_forward);  pat_pd_dual_data;  pat_pd_dual_tv;
  *   A* y1 -> aty (pat_adjoint);  pat_pd_primal;  [pat_pd_change]
  * with step sizes sigma tau (||A||^2 + 8) < 1.  TV is the isotropic total
@@ -172,7 +172,7 @@ int  pat_pd_change(const float* f, const float* xbar, float* out, int n, int bat
 
 /* CGLS: conjugate gradients on the normal equations A* A f = A* g, the
  * iterative stand-in for the fast inverse that produces the network input of
- * the deep image prior (Sec. 2.3; the paper takes a closed-form inversion
+ * the deep image prior (Sec. 2.2; the paper takes a closed-form inversion
  * from the cited literature).  From f_0: r = g - A f_0, s = A* r, p = s,
  * gamma = <s, s>; one step, with every scalar on the device (graph-capturable):
  *   q = A p (pat_forward);            pat_cg_norm2(q -> qq)
@@ -305,7 +305,7 @@ int  pat_plan_derive(const pat_plan_desc* desc, pat_plan_info* out);
 int  pat_bessel_jn_table(int kmax, double x, double* out);
 
 /* ---- FFT wave-propagation data simulator ---------------------------------
- * The simulation study (Sec. 3, simulations) computes its data on a finer
+ * The simulation study (Sec. 2.4.1, simulations) computes its data on a finer
  * Cartesian grid with an FFT-based wave propagation method in the manner of
  * k-Wave, so that the data do not come from the reconstruction's own
  * discretisation.  Reading for a constant speed of sound c:

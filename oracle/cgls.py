@@ -1,7 +1,7 @@
 """FP64 reference of CGLS, the iterative stand-in for the fast inverse -- TEST
 INFRASTRUCTURE ONLY.
 
-The network input of the paper's deep image prior (Sec. 2.3) is an approximate
+The network input of the paper's deep image prior (Sec. 2.2) is an approximate
 inverse of the data, obtained there with a fast inversion formula from the
 cited literature that the paper does not state.  The stand-in here is a few
 steps of conjugate gradients on the normal equations A* A f = A* g (CGLS, the

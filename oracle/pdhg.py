@@ -6,7 +6,7 @@ The paper's classical baseline (Sec. 2.1) is the minimiser of
 
 computed with the primal-dual hybrid gradient method of Chambolle and Pock
 (the paper's reference [chambolle2011first]) and stopped when the relative
-change ||f_k - f_{k-1}|| / ||f_k|| reaches 1e-4 (Sec. 2.4.2).  TV is the
+change ||f_k - f_{k-1}|| / ||f_k|| reaches 1e-4 (Sec. 2.3).  TV is the
 isotropic total variation with forward differences and a zero difference
 across the last row / column (Neumann boundary), unsmoothed here.
 

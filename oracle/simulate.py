@@ -1,7 +1,7 @@
 """FP64 reference of the FFT wave-propagation data simulator -- TEST
 INFRASTRUCTURE ONLY.
 
-The paper's simulation study (Sec. 3, "Simulations") generates its data on a
+The paper's simulation study (Sec. 2.4.1, "Simulations") generates its data on a
 finer Cartesian grid (512 x 512) with an FFT-based wave propagation method in
 the manner of k-Wave, so that the data do not come from the reconstruction's
 own discretisation (no inverse crime).  The paper gives no formulas; the

@@ -78,6 +78,26 @@ def _check_tensor(t, name, shape_tail, device):
     return 1 if t.dim() == len(shape_tail) else int(t.shape[0])
 
 
+def _check_out(t, name, shape, device):
+    """A caller-supplied output must have exactly the shape the call writes
+    (batch included): the kernels write that many floats."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    _check_tensor(t, name, shape[-2:], device)
+
+
+def _check_like(t, name, ref, ref_name):
+    """`t` must match `ref` in shape (checked first) and be a contiguous float32
+    tensor on ref's GPU: the elementwise kernels read ref.numel() floats of it."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if tuple(t.shape) != tuple(ref.shape):
+        raise ValueError("%s has shape %s but %s has %s" % (name, tuple(t.shape), ref_name, tuple(ref.shape)))
+    _check_tensor(t, name, tuple(ref.shape[-2:]), ref.device)
+
+
 class PatPlan:
     """A plan for one geometry: device tables plus a workspace for up to
     `max_batch` images, on the current CUDA/HIP device."""
@@ -122,7 +142,7 @@ class PatPlan:
         if out is None:
             out = torch.empty(shape, dtype=torch.float32, device=self.device)
         else:
-            _check_tensor(out, "out", self.data_shape, self.device)
+            _check_out(out, "out", shape, self.device)
         ws = self.workspace(B)
         pat_forward(self.handle, f.data_ptr(), out.data_ptr(), B, ws.data_ptr(), ws.numel(),
                     _stream(self.device))
@@ -135,7 +155,7 @@ class PatPlan:
         if out is None:
             out = torch.empty(shape, dtype=torch.float32, device=self.device)
         else:
-            _check_tensor(out, "out", self.image_shape, self.device)
+            _check_out(out, "out", shape, self.device)
         ws = self.workspace(B)
         pat_adjoint(self.handle, g.data_ptr(), out.data_ptr(), B, ws.data_ptr(), ws.numel(),
                     _stream(self.device))
@@ -344,14 +364,26 @@ def tv_grad(f, eps: float = 1e-3, with_value: bool = False):
 
 
 def pgd_update(f, adj, tvg, tau: float, lam: float):
-    """In place: f <- max(f - tau (adj + lam tvg), 0)."""
+    """In place: f <- max(f - tau (adj + lam tvg), 0).  f, adj and tvg (if
+    given) are contiguous float32 GPU tensors of one shape, (N, N) or (B, N, N)."""
+    if not isinstance(f, torch.Tensor) or f.dim() not in (2, 3):
+        raise ValueError("f must be an (N, N) or (B, N, N) tensor")
+    _check_like(adj, "adj", f, "f")
+    if tvg is not None:
+        _check_like(tvg, "tvg", f, "f")
+    _check_tensor(f, "f", tuple(f.shape[-2:]), None)
     pat_pgd_update(f.data_ptr(), adj.data_ptr(), tvg.data_ptr() if tvg is not None else None, f.numel(),
                    tau, lam, _stream(f.device))
     return f
 
 
 def residual(g, g_meas, with_value: bool = False):
-    """In place: g <- g - g_meas; optionally 0.5 ||r||^2 per instance."""
+    """In place: g <- g - g_meas; optionally 0.5 ||r||^2 per instance.  g and
+    g_meas are contiguous float32 GPU tensors of one shape, (D, T) or (B, D, T)."""
+    if not isinstance(g, torch.Tensor) or g.dim() not in (2, 3):
+        raise ValueError("g must be a (D, T) or (B, D, T) tensor")
+    _check_like(g_meas, "g_meas", g, "g")
+    _check_tensor(g, "g", tuple(g.shape[-2:]), None)
     B = g.shape[0] if g.dim() == 3 else 1
     per = g.numel() // B
     sq = torch.empty(B, dtype=torch.float32, device=g.device) if with_value else None

@@ -406,10 +406,12 @@ static void batch_layout(pat_batch* b)
         items[kStSpread] = ((d.Ng + b->spr_cb - 1) / b->spr_cb) * spread_row_tiles(d.NB);
         for (int s = 0; s < kNumStages; ++s)
             b->base[(size_t)s * (n + 1) + i + 1] = b->base[(size_t)s * (n + 1) + i] + items[s];
-        b->thr_col = std::max<unsigned>(b->thr_col, p->thr_col);
-        b->thr_row = std::max<unsigned>(b->thr_row, p->thr_row);
+        // workgroup sizes from the tile shapes copied into the instance (a later
+        // set_launch or autotune of the plan does not change this batch)
+        b->thr_col = std::max<unsigned>(b->thr_col, fft_workgroup_threads(I.col_np, p->h_fft_grid));
+        b->thr_row = std::max<unsigned>(b->thr_row, fft_workgroup_threads(I.row_rpb, p->h_fft_grid));
         b->thr_ring = std::max<unsigned>(b->thr_ring, p->thr_ring);
-        b->thr_dct = std::max<unsigned>(b->thr_dct, p->thr_dct);
+        b->thr_dct = std::max<unsigned>(b->thr_dct, fft_workgroup_threads(I.dct_dp, p->h_fft_dct));
         b->lds_col = std::max(b->lds_col, fft_tile_lds(I.col_np, p->h_fft_grid));
         b->lds_row = std::max(b->lds_row, fft_tile_lds(I.row_rpb, p->h_fft_grid));
         b->lds_ring = std::max(b->lds_ring, p->lds_ring);

@@ -1,6 +1,6 @@
 // sim.hip -- FFT wave-propagation data simulator (gfx950 kernels and host plan).
 //
-// The simulation study (Sec. 3) computes its data on a finer Cartesian grid
+// The simulation study (Sec. 2.4.1) computes its data on a finer Cartesian grid
 // with an FFT-based wave propagation method.  For a constant speed of sound the
 // field is p(t) = IFFT2[F cos(c|k|t)], F = FFT2 of the zero-padded fine image on
 // a periodic box wide enough that no wave wraps around to a detector by the

@@ -1,8 +1,8 @@
-"""Deep image prior (DIP) reconstruction, eq. (5) and Sec. 2.3.
+"""Deep image prior (DIP) reconstruction, eq. (5) and Sec. 2.2.
 
     f^ = phi_theta*(z),  theta* = argmin_theta ||A phi_theta(z) - g||^2 + lambda TV(phi_theta(z))
 
-* phi is the U-Net of Sec. 2.3: an encoder of four stages with 32, 64, 128
+* phi is the U-Net of Sec. 2.2.1: an encoder of four stages with 32, 64, 128
   and 256 feature channels (two 3x3 convolutions with batch normalisation and
   ReLU per stage, 2x2 max pooling between stages), a decoder of three stages
   (2x2 transposed convolution, concatenation with the encoder features of the
@@ -13,7 +13,7 @@
   backward of A is A*); the TV term is the smoothed isotropic TV of the TV
   kernel (value and gradient in one launch).
 * Adam with learning rate 5e-4, cosine annealing over the planned number of
-  iterations (Sec. 2.3).
+  iterations (Sec. 2.2.1).
 * The network input z is an approximate inverse of the data.  The paper uses
   a closed-form fast inverse from the cited literature, which it does not
   state; here z comes from a few CGLS steps (recon.CGLSReconstructor).
@@ -35,7 +35,7 @@ def _double_conv(cin: int, cout: int) -> nn.Sequential:
 
 
 class UNet(nn.Module):
-    """The encoder-decoder of Sec. 2.3 (channels 32-64-128-256, three skips)."""
+    """The encoder-decoder of Sec. 2.2.1 (channels 32-64-128-256, three skips)."""
 
     def __init__(self, channels=(32, 64, 128, 256), in_ch: int = 1):
         super().__init__()

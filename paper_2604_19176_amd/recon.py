@@ -135,7 +135,7 @@ class PDHGReconstructor:
     min_{f >= 0} 0.5 ||A f - g||^2 + alpha TV(f) with isotropic, unsmoothed TV,
     by the primal-dual hybrid gradient method with K = (A, grad), theta = 1 and
     sigma = tau = 0.99 / sqrt(||A||^2 + 8).  Stops when the relative change
-    ||f_k - f_{k-1}|| / ||f_k|| of every instance is at most `tol` (1e-4, Sec. 2.4.2).
+    ||f_k - f_{k-1}|| / ||f_k|| of every instance is at most `tol` (1e-4, Sec. 2.3).
     One iteration runs the launches of the operator pair plus three small
     kernels, and the change reduction where the stopping rule reads it; a
     run of iterations can be captured as one HIP graph."""
@@ -227,7 +227,7 @@ class PDHGReconstructor:
 
 class CGLSReconstructor:
     """CGLS (conjugate gradients on A* A f = A* g): the iterative stand-in for
-    the fast inverse that gives the deep image prior its input (Sec. 2.3).
+    the fast inverse that gives the deep image prior its input (Sec. 2.2).
     Every scalar stays on the device; two consecutive steps (which alternate
     the two gamma buffers) can be captured as one HIP graph."""
 

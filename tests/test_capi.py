@@ -231,3 +231,29 @@ def test_explicit_angles_select_the_dense_synthesis(patlib):
     with pytest.raises(pat.PatError) as e:
         pat.pat_plan_derive(pat.desc_from_geometry(bad))
     assert e.value.status == patlib.PAT_ERR_ARG
+
+
+def test_python_layer_rejects_mismatched_tensors():
+    """The binding checks shapes before it hands raw pointers to the library:
+    an output of the wrong batch, or elementwise operands of different shapes,
+    raise ValueError on the host (the C-ABI cannot see buffer sizes)."""
+    import torch
+    import paper_2604_19176_amd as pat
+    with pytest.raises(ValueError):
+        pat._check_out(torch.zeros(3, 32, 64), "out", (2, 32, 64), None)   # batch 3 for a batch-2 call
+    with pytest.raises(ValueError):
+        pat._check_out(torch.zeros(32, 64), "out", (2, 32, 64), None)      # unbatched out, batched call
+    f = torch.zeros(2, 16, 16)
+    with pytest.raises(ValueError):
+        pat.pgd_update(f, torch.zeros(16, 16), None, 0.1, 0.0)
+    with pytest.raises(ValueError):
+        pat.pgd_update(f, torch.zeros(2, 16, 16), torch.zeros(1, 16, 16), 0.1, 0.0)
+    with pytest.raises(ValueError):
+        pat.residual(torch.zeros(2, 8, 10), torch.zeros(2, 8, 11))
+    with pytest.raises(ValueError):
+        pat.residual(torch.zeros(8, 10), torch.zeros(1, 8, 10))
+    # matching shapes still need GPU tensors
+    with pytest.raises(ValueError):
+        pat.pgd_update(f, torch.zeros(2, 16, 16), None, 0.1, 0.0)
+    with pytest.raises((TypeError, ValueError)):
+        pat.pgd_update(f, torch.zeros(2, 16, 16, dtype=torch.float64), None, 0.1, 0.0)

@@ -152,6 +152,32 @@ def test_batch_equals_per_instance_bitwise(torch_dev):
         p.close()
 
 
+def test_batch_keeps_its_shapes_after_plan_changes(torch_dev):
+    """A batch runs each instance with the FFT-stage shapes its plan had at
+    batch creation; changing the plan's shapes afterwards (set_launch or
+    autotune) must leave the batch's workgroup sizes consistent with the
+    shapes it copied, so its results stay bitwise the per-instance ones."""
+    torch = torch_dev
+    import paper_2604_19176_amd as pat
+    geoms = [config_geometry(2), config_geometry(1)]
+    wide = dict(col_np=16, row_rpb=16, dct_dp=4)
+    plans = [pat.PatPlan(g) for g in geoms]
+    for p in plans:
+        p.set_launch(**wide)
+    batch = pat.PatBatch(plans)
+    for p in plans:
+        p.set_launch(col_np=1, row_rpb=1, dct_dp=1)
+    fs, ds = zip(*[_inputs(torch, g, 300 + i) for i, g in enumerate(geoms)])
+    gb = [x.clone() for x in batch.forward(list(fs))]
+    ab = [x.clone() for x in batch.adjoint(list(ds))]
+    for i, p in enumerate(plans):
+        assert torch.equal(gb[i], p.forward(fs[i])), i
+        assert torch.equal(ab[i], p.adjoint(ds[i])), i
+    batch.close()
+    for p in plans:
+        p.close()
+
+
 def test_batch_against_oracle(torch_dev):
     torch = torch_dev
     import oracle

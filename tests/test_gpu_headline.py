@@ -2,9 +2,9 @@
 times: 256x256, 256 detectors on a 180 degree arc, 512 samples, batch 64.
 
 - Every one of the 64 instances is computed with the plan's default batch-64
-  shapes and with the shapes the autotuner picks for this workload on the
-  MI355X (the tile spread shared by four instances, the interpolation by two);
-  launch shapes change no result, so both batches are bitwise equal.
+  shapes and with the shapes the autotuner picks on this device for this
+  workload at batch 64 (what bench.py times); launch shapes change no
+  result, so both batches are bitwise equal.
 - The first, a middle and the last instance are compared element by element
   with the FP64 oracle (relative L2 <= 1e-5, the operator's FP32 tolerance).
 - Each instance equals its single-instance call bitwise.
@@ -18,9 +18,6 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
 B = 64
-# the batch-64 shapes of the tuned bench run at this workload
-TUNED = dict(col_np=8, row_rpb=4, ring_rt=1, dct_dp=2, gat_cb=64, gat_th=16, spr_cb=256, spr_th=8, gat_ib=2,
-             spr_ib=4)
 SAMPLED = (0, 31, 63)
 
 
@@ -48,8 +45,9 @@ def test_headline_batch_in_bench_launch_shapes(torch_dev):
     ft = torch.tensor(fs, dtype=torch.float32, device="cuda")
     dt = torch.tensor(ds, dtype=torch.float32, device="cuda")
     g0, a0 = plan.forward(ft).clone(), plan.adjoint(dt).clone()
-    plan.set_launch(**TUNED)
-    assert plan.launch == TUNED
+    tuned = plan.autotune(batch=B)
+    print("tuned launch shapes:", tuned)
+    assert plan.launch == tuned
     g1, a1 = plan.forward(ft).clone(), plan.adjoint(dt).clone()
     assert torch.equal(g1, g0) and torch.equal(a1, a0)
     for b in SAMPLED:
