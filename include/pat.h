@@ -126,6 +126,23 @@ int  pat_forward(const pat_plan* plan, const float* f, float* g, int batch,
 int  pat_adjoint(const pat_plan* plan, const float* g, float* f, int batch,
                  void* ws, size_t ws_bytes, void* stream);
 
+/* g = A f without a caller workspace, for callers that cannot allocate device
+ * memory (code recorded into a HIP graph, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same operator, kernels, launch shapes and results as
+ * pat_forward (bitwise); the workspace is instead a device array of
+ * PAT_NOALLOC_SCRATCH_BYTES (128 MiB) inside the library, one per GPU, held
+ * from the first call on that GPU until the process ends.  f, g, batch,
+ * stream: as for pat_forward; the current HIP device must be the plan's.
+ * The call allocates and frees nothing (the first call on a device looks up
+ * the array's device address once).  All calls on one GPU share the array:
+ * calls that overlap on one GPU (other streams, other threads) race, so a
+ * caller serialises them.  Errors: PAT_ERR_ARG (null pointer, batch out of
+ * range, current device is not the plan's), PAT_ERR_WORKSPACE
+ * (pat_workspace_size(plan, batch) exceeds PAT_NOALLOC_SCRATCH_BYTES),
+ * PAT_ERR_HIP. */
+#define PAT_NOALLOC_SCRATCH_BYTES (128u * 1024u * 1024u)
+int  pat_forward_noalloc(const pat_plan* plan, const float* f, float* g, int batch, void* stream);
+
 /* Smoothed isotropic total variation of eq. (4)/(5) (Sec. 2.1, 2.2):
  *   TV_eps(f) = sum_{i,j} sqrt((f_{i,j+1}-f_{i,j})^2 + (f_{i+1,j}-f_{i,j})^2 + eps^2)
  * with forward differences and zero difference across the last row/column

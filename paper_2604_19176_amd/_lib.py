@@ -20,6 +20,8 @@ PAT_ERR_UNSUPPORTED = -2
 PAT_ERR_WORKSPACE = -3
 PAT_ERR_HIP = -4
 PAT_ERR_ALLOC = -5
+# device bytes of the workspace array pat_forward_noalloc uses (include/pat.h)
+PAT_NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024
 
 
 class PatError(RuntimeError):
@@ -73,6 +75,7 @@ def load():
         "pat_workspace_size": (sz, [vp, ci]),
         "pat_forward": (ci, [vp, vp, vp, ci, vp, sz, vp]),
         "pat_adjoint": (ci, [vp, vp, vp, ci, vp, sz, vp]),
+        "pat_forward_noalloc": (ci, [vp, vp, vp, ci, vp]),
         "pat_tv_grad": (ci, [vp, vp, vp, ci, ci, cf, vp]),
         "pat_pgd_update": (ci, [vp, vp, vp, cl, cf, cf, vp]),
         "pat_residual": (ci, [vp, vp, vp, cl, ci, vp]),
@@ -164,6 +167,10 @@ def pat_workspace_size(plan: int, batch: int) -> int:
 
 def pat_forward(plan, f_ptr, g_ptr, batch, ws_ptr, ws_bytes, stream) -> None:
     _check(load().pat_forward(plan, f_ptr, g_ptr, int(batch), ws_ptr, int(ws_bytes), stream), "pat_forward")
+
+
+def pat_forward_noalloc(plan, f_ptr, g_ptr, batch, stream) -> None:
+    _check(load().pat_forward_noalloc(plan, f_ptr, g_ptr, int(batch), stream), "pat_forward_noalloc")
 
 
 def pat_adjoint(plan, g_ptr, f_ptr, batch, ws_ptr, ws_bytes, stream) -> None:

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -181,6 +182,47 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 5 + qa, st);
     return PAT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// pat_forward_noalloc: pat_forward with the library's own workspace, a
+// file-scope device array (one per GPU, held until the process ends).  On the
+// host the array's name only stands for the symbol; its device address is
+// looked up once per device (hipGetSymbolAddress) and kept in
+// g_scratch_ptr.  Calls on one device share the array: calls that overlap
+// on a device race.  The forward kernels write every workspace word they
+// read, so nothing needs clearing between calls.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[PAT_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+static int scratch_for_device(int dev, void** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return PAT_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;  // the caller's current device is `dev`
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PAT_ERR_HIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PAT_OK;
+}
+
+extern "C" int pat_forward_noalloc(const pat_plan* p, const float* f, float* g, int batch, void* stream)
+{
+    if (!p || !f || !g || batch < 1 || batch > p->max_batch) return PAT_ERR_ARG;
+    if (pat_workspace_size(p, batch) > (size_t)PAT_NOALLOC_SCRATCH_BYTES) return PAT_ERR_WORKSPACE;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return PAT_ERR_HIP;
+    if (dev != p->device) return PAT_ERR_ARG;
+    void* ws = nullptr;
+    const int rc = scratch_for_device(dev, &ws);
+    if (rc != PAT_OK) return rc;
+    return pat_forward(p, f, g, batch, ws, (size_t)PAT_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 extern "C" int pat_tv_grad(const float* f, float* grad, float* tv, int n, int batch, float eps, void* stream)
