@@ -68,27 +68,45 @@ def kernels_hash():
     return source_hash(KERNEL_SRC)
 
 
-def algorithmic_bytes(info, geom):
-    """Compulsory HBM bytes per instance of each kernel: every input element
-    read once, every output element written once (tables not counted)."""
+def algorithmic_bytes(info, geom, B):
+    """Compulsory HBM bytes of one launch of each kernel over B instances of
+    one plan: every instance's own inputs read once and outputs written once
+    (B times), plus each plan table the kernel reads counted once per launch
+    (the instances share it).  Workspace the staging alone adds (the spread's
+    partial rows, tile halos) is not counted."""
     N, D, T = geom.n, geom.n_det, geom.n_t
     Ng = info.n_grid
     Hy = Ng // 2 + 9
+    NB = Ng // 2 + 2
     P = info.n_points
     NL = info.n_lam
+    KM = info.n_ring_modes                 # sum over rings of the modes kept
     c8 = 8
-    return {
-        "colpass_fwd": 4 * N * N + c8 * Hy * N,
+    inst = {
+        "colpass_fwd": 4 * N * N + c8 * Hy * N + 4 * N,     # f; column spectra; per-column mass sums
         "rowpass_fwd": c8 * Hy * N + c8 * Hy * Ng,
-        "gather": c8 * Hy * Ng + 24 * P + c8 * P,
-        "ring_fwd": c8 * P + 4 * D * NL,
-        "dct_fwd": 4 * D * NL + 4 * D * T,
-        "dct_adj": 4 * D * T + 4 * D * NL,
-        "ring_adj": 4 * D * NL + 12 * P + c8 * P,
-        "spread": c8 * P + 16 * P + c8 * Hy * Ng,
+        "gather": c8 * Hy * Ng + c8 * P,                    # spectrum; polar values
+        "ring_fwd": c8 * P + 4 * D * NL,                    # polar values; ring output at the detectors
+        "dct_fwd": 4 * D * NL + 4 * D * T + 4 * N,
+        "dct_adj": 4 * D * T + 4 * D * NL + 4 * D,
+        "ring_adj": 4 * D * NL + c8 * P,
+        "spread": c8 * P + c8 * Hy * Ng,
         "rowpass_adj": c8 * Hy * Ng + c8 * Hy * N,
-        "colpass_adj": c8 * Hy * N + 4 * N * N,
+        "colpass_adj": c8 * Hy * N + 4 * N * N + 4 * D,
     }
+    image_tab = 4 * N + 8 * N                               # deapodisation, mask row ranges
+    band_tab = 4 * NB * (Ng + 1)                            # band CSR
+    ring_tab = c8 * KM + 16 * NL                            # mode coefficients; ring offsets, K_n, descriptors
+    table = {
+        "colpass_fwd": image_tab, "rowpass_fwd": 0,
+        "gather": 16 * P + c8 * P + band_tab,               # band-order geometry and half-pixel phase
+        "ring_fwd": ring_tab,
+        "dct_fwd": 0, "dct_adj": 0,
+        "ring_adj": ring_tab + 4 * P + c8 * P,              # band-order slot and phase per point
+        "spread": 16 * P + band_tab,
+        "rowpass_adj": 0, "colpass_adj": image_tab,
+    }
+    return {k: B * inst[k] + table[k] for k in inst}
 
 
 def algorithmic_flops(info, geom, name):
@@ -122,7 +140,7 @@ def measured_traffic(dom, B):
     return None
 
 
-def roofline(kms, info, geom, B):
+def roofline(kms, info, geom, B, copy_gbs=None):
     """Roofline entry for the kernel with the largest per-launch time.  A
     kernel with nominal flops is ALU-bound when its flops per algorithmic byte
     exceed the ridge point of the FP32 rate this build can issue (packed FP32
@@ -138,7 +156,7 @@ def roofline(kms, info, geom, B):
         return {"bound": "mfma", "kernel": dom, "achieved": round(ach, 3), "peak": MFMA_FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / MFMA_FP32_PEAK_TFLOPS, 4), "flops_per_launch": int(flops),
                 "avg_launch_ms": round(kms[dom], 4), "traffic": traffic}
-    byt = algorithmic_bytes(info, geom)[dom] * B
+    byt = algorithmic_bytes(info, geom, B)[dom]
     if fl is not None and fl * B / byt > ridge:
         flops = fl * B
         ach = flops / t / 1e12
@@ -151,6 +169,8 @@ def roofline(kms, info, geom, B):
     out = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_launch": byt, "avg_launch_ms": round(kms[dom], 4),
            "traffic": traffic}
+    if copy_gbs:
+        out["frac_of_measured_copy"] = round(ach / copy_gbs, 4)
     if fl is not None:  # below the ridge point: the nominal flops for reference
         out["flops_per_launch"] = int(fl * B)
         out["flops_per_byte"] = round(fl * B / byt, 2)
@@ -232,12 +252,57 @@ def time_eager(torch, dev, fn, steps, warmup=2):
 
 
 def copy_calibration(torch, dev):
-    """One float32 multiply-by-one over CALIB_ELEMS elements: a copy of known
-    size whose byte counters calibrate the PMC traffic figures."""
+    """The library's streaming copy over CALIB_ELEMS float32 (256 MiB read,
+    256 MiB written) and its 8-byte scatter over the same bytes: copies of
+    known size whose byte counters calibrate the PMC traffic figures."""
+    import paper_2604_19176_amd as pat
     x = torch.ones(CALIB_ELEMS, dtype=torch.float32, device=dev)
-    y = torch.mul(x, 1.0)
+    y = torch.empty_like(x)
+    st = pat._stream(dev)
+    pat.pat_stream_copy(x.data_ptr(), y.data_ptr(), 4 * CALIB_ELEMS, None, st)
+    perm = torch.randperm(CALIB_ELEMS // 2, device=dev, dtype=torch.int64).to(torch.int32)
+    pat.pat_stream_copy(x.data_ptr(), y.data_ptr(), 4 * CALIB_ELEMS, perm.data_ptr(), st)
     torch.cuda.synchronize()
+    del x, y, perm
+
+
+def measure_copy(torch, dev, nbytes=1 << 30, reps=20):
+    """GB/s (read + write bytes / time) of the library's streaming copy over
+    `nbytes` (1 GiB each way), best of `reps` launches timed with HIP events
+    on the launch stream."""
+    import paper_2604_19176_amd as pat
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    st = pat._stream(dev)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(3):
+        pat.pat_stream_copy(x.data_ptr(), y.data_ptr(), nbytes, None, st)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        pat.pat_stream_copy(x.data_ptr(), y.data_ptr(), nbytes, None, st)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    ok = bool(torch.equal(x[:1 << 20], y[:1 << 20])) and bool(torch.equal(x[-(1 << 20):], y[-(1 << 20):]))
     del x, y
+    return {"gbs": round(2.0 * nbytes / (best * 1e-3) / 1e9, 1), "bytes_each_way": nbytes, "best_ms": round(best, 4),
+            "kernel": "k_stream_copy", "copied_correctly": ok}
+
+
+def step_roofline(kms, info, geom, B, ms_step, copy_gbs=None):
+    """The whole A + A* step: the sum of every kernel's algorithmic bytes per
+    launch (algorithmic_bytes) over the measured step time."""
+    ab = algorithmic_bytes(info, geom, B)
+    byt = sum(ab[k] for k in kms if k in ab)
+    ach = byt / (ms_step * 1e-3) / 1e9
+    out = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_step": int(byt), "ms_per_step": round(ms_step, 4)}
+    if copy_gbs:
+        out["frac_of_measured_copy"] = round(ach / copy_gbs, 4)
+    return out
 
 
 def make_inputs(np, torch, plan, geom, cfg, B, dev, seed_stride):
@@ -270,6 +335,95 @@ def make_sim_inputs(np, torch, geom, cfg, B, dev, seed_stride):
     return fs, torch.tensor(fs, dtype=torch.float32, device=dev), gm, torch.tensor(gm, dtype=torch.float32, device=dev)
 
 
+GOLDEN_LARGE = os.path.join(ROOT, "tests", "golden", "large_1024.npz")
+
+
+def parity_against_oracle(np, geom, fs, gm, g_out, f_out, idx):
+    """Relative L2 of the timed batch outputs (A f and A* g_meas, instances
+    `idx`) against the FP64 oracle, and the oracle's wall time for them."""
+    import oracle
+    errs, t_cpu = [], 0.0
+    for b in idx:
+        t0 = time.perf_counter()
+        ref_g = oracle.forward(geom, fs[b])
+        ref_f = oracle.adjoint(geom, gm[b])
+        t_cpu += time.perf_counter() - t0
+        gb = g_out[b].cpu().double().numpy()
+        ab = f_out[b].cpu().double().numpy()
+        errs.append({"instance": int(b),
+                     "fwd_rel_l2": float(np.linalg.norm(gb - ref_g) / np.linalg.norm(ref_g)),
+                     "adj_rel_l2": float(np.linalg.norm(ab - ref_f) / np.linalg.norm(ref_f))})
+    return errs, t_cpu, oracle.get_threads()
+
+
+def large_leg(args, np, torch, pat, dev):
+    """The 1024^2 workload (1024 detectors on a 270 deg arc, 2048 samples,
+    batch 8, 1 % noise): the projected-gradient TV loop (A, residual, A*, TV
+    gradient, update per iteration, HIP graphs of 10 iterations) over
+    `--large-steps` iterations, its per-kernel times and roofline, and
+    instance 0 of the timed launch shapes against the stored FP64 oracle values
+    (every 16th detector's trace of A f, A* d at 4000 pixels)."""
+    from paper_2604_19176_amd.recon import TVReconstructor
+    from pat_inputs import CONFIGS, config_geometry
+    cfg = CONFIGS[5]
+    geom = config_geometry(5)
+    B = cfg["batch"]
+    print("bench: large workload (1024^2, batch %d)" % B, file=sys.stderr, flush=True)
+    plan = pat.PatPlan(geom, max_batch=B)
+    fs, f, gm, g_meas = make_inputs(np, torch, plan, geom, cfg, B, dev, 1)
+    launch = plan.autotune(batch=B, cache_path=args.tune_cache) if args.tune else plan.launch
+    g_out, f_out = torch.empty_like(g_meas), torch.empty_like(f)
+    parity = None
+    if os.path.exists(GOLDEN_LARGE):
+        gold = np.load(GOLDEN_LARGE)
+        plan.forward(f, out=g_out)
+        d0 = np.random.default_rng(5100).standard_normal((geom.n_det, geom.n_t))
+        dd = g_meas.clone()
+        dd[0] = torch.tensor(d0, dtype=torch.float32, device=dev)
+        plan.adjoint(dd, out=f_out)
+        gr = g_out[0].cpu().double().numpy()[gold["det"]]
+        ap = f_out[0].cpu().double().numpy().ravel()[gold["pix"]]
+        parity = {"fwd_rel_l2_sampled_traces": float(np.linalg.norm(gr - gold["g_rows"]) /
+                                                     np.linalg.norm(gold["g_rows"])),
+                  "adj_rel_l2_sampled_pixels": float(np.linalg.norm(ap - gold["a_pix"]) /
+                                                     np.linalg.norm(gold["a_pix"])),
+                  "reference": "stored FP64 oracle values, tests/golden/large_1024.npz"}
+        assert parity["fwd_rel_l2_sampled_traces"] <= 1e-5 and parity["adj_rel_l2_sampled_pixels"] <= 1e-5, parity
+    ms_pair, _ = time_pairs(torch, plan, f, g_meas, g_out, f_out, 10, 2)
+    kms = kernel_times(pat, plan, f, g_meas, g_out, f_out, 5)
+    steps = args.large_steps
+    rec = TVReconstructor(plan, g_meas, lam=cfg.get("tv_lambda", 1e-3))
+    rec.capture(10)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    rec.run(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ab = algorithmic_bytes(plan.info, geom, B)
+    n2, dt_ = geom.n * geom.n, geom.n_det * geom.n_t
+    loop_bytes = B * (8 * n2 + 16 * n2 + 12 * dt_)     # TV gradient, projected update, residual
+    it_bytes = sum(ab.values()) + loop_bytes
+    out = {
+        "workload": "TV projected-gradient loop, 1024x1024, 1024 detectors on 270 deg, 2048 samples on (0,2], "
+                    "batch %d, 1 %% noise, lambda 1e-3, HIP graphs of 10 iterations" % B,
+        "iterations_per_s": round(steps * 1000.0 / ms, 2), "iterations": steps,
+        "ms_per_iteration": round(ms / steps, 4),
+        "pairs_per_s": round(B * 1000.0 / ms_pair, 2), "ms_per_pair_batch": round(ms_pair, 4),
+        "roofline": roofline(kms, plan.info, geom, B),
+        "roofline_iteration": {"bound": "hbm", "bytes_per_iteration": int(it_bytes),
+                               "achieved": round(it_bytes * steps / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s",
+                               "frac": round(it_bytes * steps / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
+        "parity": parity, "launch": launch,
+    }
+    plan.close()
+    return out
+
+
 def bench_default(args):
     import numpy as np
     import torch
@@ -288,40 +442,29 @@ def bench_default(args):
     g_out = torch.empty_like(g_meas)
     f_out = torch.empty_like(f)
     copy_calibration(torch, dev)
+    copy = measure_copy(torch, dev)
     launch = {"batched": plan.launch, "single": plan1.launch}
     if args.tune:
         print("bench: autotuning the launch shapes", file=sys.stderr, flush=True)
         launch = {"batched": plan.autotune(batch=B, cache_path=args.tune_cache),
                   "single": plan1.autotune(batch=1, cache_path=args.tune_cache)}
 
-    parity = None
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        print("bench: oracle parity + CPU baseline", file=sys.stderr, flush=True)
-        nthreads = oracle.get_threads()
-        reps, t_cpu = 0, 0.0
-        while True:
-            t0 = time.perf_counter()
-            ref_g = oracle.forward(geom, fs[0])
-            ref_f = oracle.adjoint(geom, gm[0])
-            t_cpu += time.perf_counter() - t0
-            reps += 1
-            if t_cpu >= 10.0 or reps >= 3:
-                break
-        g0 = plan.forward(f[0:1].contiguous())[0].cpu().double().numpy()
-        a0 = plan.adjoint(g_meas[0:1].contiguous())[0].cpu().double().numpy()
-        parity = {
-            "fwd_rel_l2": float(np.linalg.norm(g0 - ref_g) / np.linalg.norm(ref_g)),
-            "adj_rel_l2": float(np.linalg.norm(a0 - ref_f) / np.linalg.norm(ref_f)),
-        }
-        assert parity["fwd_rel_l2"] <= 1e-5 and parity["adj_rel_l2"] <= 1e-5, parity
-        cpu = {"value": round(reps / t_cpu, 4), "unit": "pairs/s", "cores": nthreads, "kind": "oracle",
-               "sample": "%d x (one A + one A*) on instance 0 of the 256^2 workload, FP64 direct sums" % reps}
-
     print("bench: timing batched", file=sys.stderr, flush=True)
     ms_step, wall = time_pairs(torch, plan, f, g_meas, g_out, f_out, args.steps, args.warmup)
     value = B * 1000.0 / ms_step
+    parity = None
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the outputs of the timed launches: g_out = A f and f_out = A* g_meas over the batch
+        print("bench: oracle parity of the timed outputs + CPU baseline", file=sys.stderr, flush=True)
+        idx = (0, B - 1)
+        errs, t_cpu, nthreads = parity_against_oracle(np, geom, fs, gm, g_out, f_out, idx)
+        parity = {"instances": errs, "fwd_rel_l2": max(e["fwd_rel_l2"] for e in errs),
+                  "adj_rel_l2": max(e["adj_rel_l2"] for e in errs)}
+        assert parity["fwd_rel_l2"] <= 1e-5 and parity["adj_rel_l2"] <= 1e-5, parity
+        cpu = {"value": round(len(idx) / t_cpu, 4), "unit": "pairs/s", "cores": nthreads, "kind": "oracle",
+               "sample": "%d x (one A + one A*): instances %s of the 256^2 batch, FP64 direct sums"
+                         % (len(idx), ", ".join(str(b) for b in idx))}
     print("bench: timing single", file=sys.stderr, flush=True)
     f1, g1 = f[0:1].contiguous(), g_meas[0:1].contiguous()
     go1, fo1 = torch.empty_like(g1), torch.empty_like(f1)
@@ -333,8 +476,8 @@ def bench_default(args):
     ms_single_graph = time_graph(torch, dev, pair1, max(args.steps, 20))
     kms = kernel_times(pat, plan, f, g_meas, g_out, f_out)
     kms1 = kernel_times(pat, plan1, f1, g1, go1, fo1)
-    abytes = algorithmic_bytes(plan.info, geom)
-    gbs = {n: abytes[n] * B / (kms[n] * 1e-3) / 1e9 for n in kms}
+    abytes = algorithmic_bytes(plan.info, geom, B)
+    gbs = {n: abytes[n] / (kms[n] * 1e-3) / 1e9 for n in kms}
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -357,7 +500,9 @@ def bench_default(args):
         "batched_over_single": round(value * ms_single / 1000.0, 2),
         "wall_s_timed": round(wall, 3),
         "parity": parity,
-        "roofline": roofline(kms, plan.info, geom, B),
+        "roofline": roofline(kms, plan.info, geom, B, copy["gbs"]),
+        "roofline_step": step_roofline(kms, plan.info, geom, B, ms_step, copy["gbs"]),
+        "copy_gbs": copy,
         "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
         "kernels_gbs": {k: round(v, 1) for k, v in gbs.items()},
         "kernels_ms_single": {k: round(v, 4) for k, v in kms1.items()},
@@ -365,9 +510,11 @@ def bench_default(args):
         "launch": launch, "tuned": bool(args.tune),
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
     plan.close()
     plan1.close()
+    if not args.no_large:
+        out["large"] = large_leg(args, np, torch, pat, dev)
+    print(json.dumps(out), flush=True)
 
 
 def bench_tv(args, cfg_id, steps_default, seed_stride):
@@ -403,10 +550,10 @@ def bench_tv(args, cfg_id, steps_default, seed_stride):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    ab = algorithmic_bytes(plan.info, geom)
+    ab = algorithmic_bytes(plan.info, geom, B)
     n2, dt_ = geom.n * geom.n, geom.n_det * geom.n_t
     loop_bytes = 8 * n2 + 16 * n2 + 12 * dt_     # TV gradient, projected update, residual
-    it_bytes = B * (sum(ab.values()) + loop_bytes)
+    it_bytes = sum(ab.values()) + B * loop_bytes
     out = {
         "metric": "TV projected-gradient iterations/s (A, residual, A*, TV gradient, update per iteration)",
         "value": round(steps * 1000.0 / ms, 2),
@@ -811,6 +958,10 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="JSON cache file of the autotuner")
     ap.add_argument("--tv-steps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="default workload: skip the 1024^2 TV leg (the 'large' key of the line)")
+    ap.add_argument("--large-steps", type=int, default=2000,
+                    help="TV iterations of the 1024^2 leg of the default workload")
     ap.add_argument("--sim-data", action="store_true",
                     help="pdhg workloads: measurements from the data simulator on a twice finer grid")
     args = ap.parse_args()

@@ -224,6 +224,17 @@ int  pat_cg_step_p(float* p, const float* s, long n, const float* gamma_new, con
 int  pat_profile_enable(pat_plan* plan, int enable);
 int  pat_profile_read(const pat_plan* plan, int which, float* ms, int max_kernels, int* count);
 
+/* Device copy of `bytes` bytes, the measured-bandwidth yardstick that the
+ * roofline fractions of the operator kernels are quoted against (besides the
+ * published 8 TB/s), and a copy of known size that calibrates the HBM byte
+ * counters.  perm == NULL: dst = src, 16-byte elements (bytes, src and dst
+ * multiples of 16).  perm != NULL: the 8-byte scatter dst[perm[e]] = src[e]
+ * for e < bytes/8 (src, dst 8-byte aligned), perm a DEVICE array of bytes/8
+ * indices in [0, bytes/8) (not inspected on the host; the caller guarantees
+ * the range).  Asynchronous on `stream`.  Errors: PAT_ERR_ARG (NULL,
+ * zero bytes, misaligned size or pointer), PAT_ERR_HIP. */
+int  pat_stream_copy(const void* src, void* dst, size_t bytes, const int* perm, void* stream);
+
 /* Launch shapes of a plan's kernels (tile sizes; none changes the result
  * beyond the summation order of the scalar endpoint/data sums).
  * pat_plan_create picks defaults for max_batch; pat_autotune_plan measures. */

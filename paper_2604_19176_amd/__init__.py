@@ -23,6 +23,7 @@ from . import _lib
 from ._lib import (PatError, PAT_ERR_WORKSPACE, PAT_NOALLOC_SCRATCH_BYTES,  # noqa: F401
                    pat_plan_desc, pat_status_string, pat_plan_create, pat_plan_query,
                    pat_plan_destroy, pat_workspace_size, pat_forward, pat_forward_noalloc, pat_adjoint,
+                   pat_stream_copy,
                    pat_tv_grad, pat_pgd_update, pat_residual, pat_plan_derive, pat_bessel_jn_table,
                    pat_profile_enable, pat_profile_read, pat_launch, pat_plan_get_launch, pat_plan_set_launch,
                    pat_batch_create, pat_batch_destroy, pat_batch_workspace_size, pat_batch_forward,

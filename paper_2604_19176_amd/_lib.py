@@ -80,6 +80,7 @@ def load():
         "pat_pgd_update": (ci, [vp, vp, vp, cl, cf, cf, vp]),
         "pat_residual": (ci, [vp, vp, vp, cl, ci, vp]),
         "pat_profile_enable": (ci, [vp, ci]),
+        "pat_stream_copy": (ci, [vp, vp, sz, vp, vp]),
         "pat_profile_read": (ci, [vp, ci, P(ctypes.c_float), ci, P(ci)]),
         "pat_plan_derive": (ci, [P(pat_plan_desc), P(pat_plan_info)]),
         "pat_bessel_jn_table": (ci, [ci, ctypes.c_double, P(ctypes.c_double)]),
@@ -171,6 +172,10 @@ def pat_forward(plan, f_ptr, g_ptr, batch, ws_ptr, ws_bytes, stream) -> None:
 
 def pat_forward_noalloc(plan, f_ptr, g_ptr, batch, stream) -> None:
     _check(load().pat_forward_noalloc(plan, f_ptr, g_ptr, int(batch), stream), "pat_forward_noalloc")
+
+
+def pat_stream_copy(src_ptr, dst_ptr, nbytes, perm_ptr, stream) -> None:
+    _check(load().pat_stream_copy(src_ptr, dst_ptr, int(nbytes), perm_ptr, stream), "pat_stream_copy")
 
 
 def pat_adjoint(plan, g_ptr, f_ptr, batch, ws_ptr, ws_bytes, stream) -> None:

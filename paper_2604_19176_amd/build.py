@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpat.so")
 SOURCES = ["plan.hip", "api.hip", "tune.hip", "sim.hip"]
-HEADERS = ["pat_internal.hpp", "fft.hpp", "kernels.hip"]
+HEADERS = ["pat_internal.hpp", "fft.hpp", "cfft.hpp", "kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

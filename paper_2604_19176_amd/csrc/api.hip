@@ -113,8 +113,10 @@ extern "C" int pat_forward(const pat_plan* p, const float* f, float* g, int batc
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, 3, st);
     {
-        const dim3 grid(xcd_grid((d.nlam + c.ring_rt - 1) / c.ring_rt * batch)), blk(p->thr_ring);
-        hipLaunchKernelGGL(k_ring_fwd, grid, blk, p->lds_ring, st, d, p->ws, wsp, c.ring_rt, batch);
+        const int rt = d.ring_spec ? 1 : c.ring_rt;  // compile-time ring kernels: one ring per workgroup
+        const dim3 grid(xcd_grid((d.nlam + rt - 1) / rt * batch)), blk(p->thr_ring);
+        if (d.ring_spec) hipLaunchKernelGGL(k_ring_fwd_spec, grid, blk, p->lds_ring, st, d, p->ws, wsp, batch);
+        else hipLaunchKernelGGL(k_ring_fwd, grid, blk, p->lds_ring, st, d, p->ws, wsp, c.ring_rt, batch);
     }
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, 4, st);
@@ -157,8 +159,10 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
         prof_mark(p, 1, 2, st);
     }
     {
-        const dim3 grid(xcd_grid((d.nlam + c.ring_rt - 1) / c.ring_rt * batch)), blk(p->thr_ring);
-        hipLaunchKernelGGL(k_ring_adj, grid, blk, p->lds_ring, st, d, p->ws, wsp, c.ring_rt, batch);
+        const int rt = d.ring_spec ? 1 : c.ring_rt;
+        const dim3 grid(xcd_grid((d.nlam + rt - 1) / rt * batch)), blk(p->thr_ring);
+        if (d.ring_spec) hipLaunchKernelGGL(k_ring_adj_spec, grid, blk, p->lds_ring, st, d, p->ws, wsp, batch);
+        else hipLaunchKernelGGL(k_ring_adj, grid, blk, p->lds_ring, st, d, p->ws, wsp, c.ring_rt, batch);
     }
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 2 + qa, st);
@@ -326,6 +330,27 @@ extern "C" int pat_cg_step_p(float* p, const float* s, long n, const float* gamm
     return check_launch();
 }
 
+extern "C" int pat_stream_copy(const void* src, void* dst, size_t bytes, const int* perm, void* stream)
+{
+    if (!src || !dst || bytes == 0) return PAT_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    if (!perm) {
+        if ((bytes & 15) || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15)) return PAT_ERR_ARG;
+        const long n4 = (long)(bytes / 16);
+        const long blocks = std::min<long>((n4 + 1023) / 1024, 256L * 32);
+        hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, st, (const float4*)src,
+                           (float4*)dst, n4);
+    } else {
+        if ((bytes & 7) || ((uintptr_t)src & 7) || ((uintptr_t)dst & 7) || bytes / 8 > 0x7fffffffUL)
+            return PAT_ERR_ARG;
+        const long n = (long)(bytes / 8);
+        const long blocks = std::min<long>((n + 255) / 256, 256L * 64);
+        hipLaunchKernelGGL(k_scatter_copy, dim3((unsigned)blocks), dim3(256), 0, st, (const float2*)src,
+                           (float2*)dst, perm, n);
+    }
+    return check_launch();
+}
+
 extern "C" int pat_profile_enable(pat_plan* p, int enable)
 {
     if (!p) return PAT_ERR_ARG;
@@ -441,7 +466,7 @@ static void batch_layout(pat_batch* b)
         items[kStCol] = I.n_col_tiles;
         items[kStRow] = (d.Hy + I.row_rpb - 1) / I.row_rpb;
         items[kStGather] = ((d.Ng + b->gat_cb - 1) / b->gat_cb) * ((d.NB + b->gat_th - 1) / b->gat_th);
-        items[kStRing] = (d.nlam + I.ring_rt - 1) / I.ring_rt;
+        items[kStRing] = d.ring_spec ? d.nlam : (d.nlam + I.ring_rt - 1) / I.ring_rt;
         items[kStDct] = I.n_pair_tiles;
         items[kStSynFwd] = d.syn_dense ? syn_fwd_tiles(d) : 0;
         items[kStSynAdj] = d.syn_dense ? syn_adj_tiles(d) : 0;

@@ -1,0 +1,216 @@
+// cfft.hpp -- complex FFTs of compile-time length, run by one wavefront.
+//
+// Stockham autosort passes as in fft.hpp (the pass of radix R after
+// sub-transforms of size Ns reads x[j + r n/R], multiplies input r by
+// w^{r k} with w = e^{-2 pi i / (Ns R)}, k = j mod Ns, does an R-point DFT and
+// writes x[(j - k) R + k + r Ns]), but with the length, the radix sequence and
+// every pass's Ns fixed at compile time: the loads and stores of a pass are
+// immediate offsets from one lane address, j mod Ns is a shift or a constant
+// multiply, and each butterfly reads its R - 1 twiddles w^{r k} from a table
+// (FP64-computed, stored FP32) instead of forming powers.  The 64 lanes of
+// wave 0 of the workgroup do the work; other waves of the workgroup only pass
+// the barriers, so the result is the same for any workgroup size.
+//
+// The radix sequence depends on the length alone (make_cplan): the plan
+// builder lays out the twiddle tables with the same function.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft.hpp"
+
+namespace pat {
+
+constexpr int kCfftLanes = 64;
+constexpr int kCfftMax = 1024;   // longest compile-time length
+constexpr int kCfftMaxPasses = 12;
+
+struct CPlan {
+    int np;                       // passes (0: no plan)
+    int rad[kCfftMaxPasses];      // radix of each pass, in execution order
+    int ns[kCfftMaxPasses];       // sub-transform size before each pass
+    int twoff[kCfftMaxPasses + 1];  // table offset of each pass; twoff[np] = table entries
+};
+
+// Estimated VALU instructions of one radix-R butterfly (fft.hpp's DFTs)
+__host__ __device__ constexpr int cbf_valu(int R)
+{
+    return R == 2 ? 4 : R == 3 ? 12 : R == 4 ? 16 : R == 6 ? 44 : R == 8 ? 60 : R == 9 ? 88 : 158;
+}
+
+// Cost of a pass of radix R over length n at 64 lanes: rounds of butterflies
+// (arithmetic, twiddle products, address work, LDS issue) plus a fixed cost
+// per pass (two barriers and an LDS round trip).
+__host__ __device__ constexpr int cpass_cost(int n, int R, bool twiddled)
+{
+    const int rounds = (n / R + kCfftLanes - 1) / kCfftLanes;
+    return rounds * (cbf_valu(R) + (twiddled ? 4 * (R - 1) : 0) + 8 + R) + 40;
+}
+
+// Radix sequence of length n = 2^a 3^b (2 <= n <= kCfftMax): the multiset of
+// radices {16, 9, 8, 6, 4, 3, 2} of least modelled cost (dynamic programming
+// over the remaining powers of 2 and 3), at most 32 complex values per lane
+// and pass, ordered largest first (the first pass multiplies by no twiddle).
+__host__ __device__ constexpr CPlan make_cplan(int n)
+{
+    CPlan p{};
+    p.np = 0;
+    if (n < 2 || n > kCfftMax) return p;
+    const int RS[7] = {16, 9, 8, 6, 4, 3, 2};
+    const int A[7] = {4, 0, 3, 1, 2, 0, 1};
+    const int B[7] = {0, 2, 0, 1, 0, 1, 0};
+    int x = 0, y = 0, m = n;
+    while (m % 2 == 0) { m /= 2; ++x; }
+    while (m % 3 == 0) { m /= 3; ++y; }
+    if (m != 1) return p;
+    int best[11][8] = {};
+    int choice[11][8] = {};
+    for (int i = 0; i <= x; ++i)
+        for (int j = 0; j <= y; ++j) {
+            choice[i][j] = -1;
+            if (i == 0 && j == 0) { best[i][j] = 0; continue; }
+            best[i][j] = 1 << 30;
+            for (int c = 0; c < 7; ++c) {
+                if (A[c] > i || B[c] > j) continue;
+                const int R = RS[c];
+                if (((n / R + kCfftLanes - 1) / kCfftLanes) * R > 32) continue;
+                if (best[i - A[c]][j - B[c]] >= (1 << 30)) continue;
+                const int v = best[i - A[c]][j - B[c]] + cpass_cost(n, R, true);
+                if (v < best[i][j]) { best[i][j] = v; choice[i][j] = c; }
+            }
+        }
+    int i = x, j = y;
+    while (i > 0 || j > 0) {
+        const int c = choice[i][j];
+        if (c < 0 || p.np >= kCfftMaxPasses) { p.np = 0; return p; }
+        p.rad[p.np++] = RS[c];
+        i -= A[c];
+        j -= B[c];
+    }
+    for (int a = 0; a < p.np; ++a)
+        for (int b = a + 1; b < p.np; ++b)
+            if (p.rad[b] > p.rad[a]) { const int t = p.rad[a]; p.rad[a] = p.rad[b]; p.rad[b] = t; }
+    int ns = 1, off = 0;
+    for (int s = 0; s < p.np; ++s) {
+        p.ns[s] = ns;
+        p.twoff[s] = off;
+        if (ns > 1) off += ns * (p.rad[s] - 1);
+        ns *= p.rad[s];
+    }
+    p.twoff[p.np] = off;
+    return p;
+}
+
+// Lengths with a compile-time transform (the switch in cfft_run).
+#define PAT_CFFT_LENGTHS(X)                                                                                   \
+    X(2) X(3) X(4) X(6) X(8) X(9) X(12) X(16) X(18) X(24) X(27) X(32) X(36) X(48) X(54) X(64) X(72) X(81) \
+    X(96) X(108) X(128) X(144) X(162) X(192) X(216) X(243) X(256) X(288) X(324) X(384) X(432) X(486) X(512) \
+    X(576) X(648) X(729) X(768) X(864) X(972) X(1024)
+
+__host__ __device__ constexpr bool cfft_len_ok(int n)
+{
+#define PAT_CFFT_CASE_OK(L) if (n == L) return true;
+    PAT_CFFT_LENGTHS(PAT_CFFT_CASE_OK)
+#undef PAT_CFFT_CASE_OK
+    return false;
+}
+
+// Table entries of length n's transform: for each pass s with Ns > 1, Ns rows
+// of R - 1 twiddles e^{-2 pi i k r / (Ns R)}, r = 1..R-1 (row k at
+// twoff[s] + k (R - 1)).
+__host__ __device__ constexpr int cfft_table_size(int n) { return make_cplan(n).twoff[make_cplan(n).np]; }
+
+template <int N>
+struct CPlanOf {
+    static constexpr CPlan p = make_cplan(N);
+};
+
+// One pass; `active` lanes (wave 0) compute, every thread passes the barriers.
+template <int N, int R, int NS, int TWOFF, bool INV>
+__device__ __forceinline__ void cpass(float2* __restrict__ x, const float2* __restrict__ tw, bool active, int lane)
+{
+    constexpr int NB = N / R;
+    constexpr int RND = (NB + kCfftLanes - 1) / kCfftLanes;
+    float2 v[RND][R];
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < RND; ++i) {
+            const int j0 = lane + i * kCfftLanes;
+            // the last round's idle lanes work on the last butterfly (results dropped)
+            const int j = (NB % kCfftLanes == 0 || i + 1 < RND) ? j0 : min(j0, NB - 1);
+            if constexpr (NS > 1) {
+                const int k = j % NS;
+                const float2* tp = tw + TWOFF + k * (R - 1);
+                float2 w[R - 1];
+#pragma unroll
+                for (int r = 1; r < R; ++r) w[r - 1] = tp[r - 1];
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[i][r] = x[j + r * NB];
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[i][r] = INV ? cmulc(v[i][r], w[r - 1]) : cmul(v[i][r], w[r - 1]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[i][r] = x[j + r * NB];
+            }
+            butterfly<R, INV>(v[i]);
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < RND; ++i) {
+            const int j = lane + i * kCfftLanes;
+            if (NB % kCfftLanes == 0 || i + 1 < RND || j < NB) {
+                const int k = j % NS;
+                const int dst = (j - k) * R + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) x[dst + r * NS] = v[i][r];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int N, bool INV, int S>
+__device__ __forceinline__ void cfft_passes(float2* x, const float2* __restrict__ tw, bool active, int lane)
+{
+    constexpr CPlan P = CPlanOf<N>::p;
+    if constexpr (S < P.np) {
+        cpass<N, P.rad[S], P.ns[S], P.twoff[S], INV>(x, tw, active, lane);
+        cfft_passes<N, INV, S + 1>(x, tw, active, lane);
+    }
+}
+
+// In-place transform of x[0..N) in LDS (forward: e^{-2 pi i jk/N}, inverse:
+// e^{+2 pi i jk/N}, unnormalised); `tw` = the length's table.  Every thread of
+// the workgroup calls it (barriers); lanes 0..63 of wave 0 compute.
+template <int N, bool INV>
+__device__ __forceinline__ void cfft(float2* x, const float2* __restrict__ tw)
+{
+    static_assert(CPlanOf<N>::p.np > 0, "no compile-time plan for this length");
+    const int lane = threadIdx.x;
+    cfft_passes<N, INV, 0>(x, tw, lane < kCfftLanes, lane);
+}
+
+// Out-of-line instance (one per length and direction), for run-time dispatch.
+template <int N, bool INV>
+__device__ __forceinline__ void cfft_call(float2* x, const float2* __restrict__ tw)
+{
+    cfft<N, INV>(x, tw);
+}
+
+// Run-time length: dispatch to the compile-time transform (n must satisfy
+// cfft_len_ok; the plan builder only selects such lengths).
+template <bool INV>
+__device__ __forceinline__ void cfft_run(float2* x, int n, const float2* __restrict__ tw)
+{
+    switch (n) {
+#define PAT_CFFT_CASE_RUN(L) \
+    case L: cfft_call<L, INV>(x, tw); break;
+        PAT_CFFT_LENGTHS(PAT_CFFT_CASE_RUN)
+#undef PAT_CFFT_CASE_RUN
+        default: break;
+    }
+}
+
+}  // namespace pat

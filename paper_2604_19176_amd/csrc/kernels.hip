@@ -19,6 +19,7 @@
 // syn_dense adjoint + ring_adj, spread, rowpass_adj, colpass_adj).  No
 // floating-point atomics anywhere: every sum has a fixed order, so results are
 // bitwise repeatable.
+#include "cfft.hpp"
 #include "fft.hpp"
 #include "pat_internal.hpp"
 
@@ -653,6 +654,289 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
             },
             [&](int, IdxVal iv) { Hb[iv.i] = iv.v; });
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Ring kernels with compile-time transforms (plans with ring_spec: a uniform
+// arc whose pitch is 2 pi s / P with P even, modes folded mod P, every length
+// with a cfft.hpp plan).  The same operator as ring_fwd_tile /
+// ring_adj_tile; lanes 0..63 of wave 0 do all the work in one LDS buffer of
+// max(Npsi_max, P) / 2 complex values:
+//   forward: head<Pn> (packed ring -> ring transform -> modes times their
+//            coefficients, folded, straight into the half-length synthesis
+//            input), synthesis transform (length P/2), tail (detectors);
+//   adjoint: head (detectors -> synthesis transform), tail<Pn> (mode
+//            coefficients straight into the half-length input of the ring's
+//            inverse transform, transform, band-order stores).
+// Each mode is evaluated once: the synthesis input at s and P/2 - s (forward),
+// or the ring input at u and Pn - u (adjoint), need the same modes, so one
+// lane computes both.  Twiddles come from the plan's FP64-computed tables.
+// ---------------------------------------------------------------------------
+struct RingSpecArgs {
+    int off, Kn;
+    const float2* __restrict__ cf;   // ring coefficients coef_k, k <= K_n
+    const float2* __restrict__ ctwR; // ring transform table
+    const float2* __restrict__ uw;   // w_{2 Pn}^k, k = 0..Pn
+};
+
+__device__ __forceinline__ RingSpecArgs ring_spec_args(const PlanDev& d, int n)
+{
+    RingSpecArgs a;
+    a.off = d.ring_off[n];
+    a.Kn = d.ring_K[n];
+    a.cf = d.coef + d.ring_joff[n];
+    a.ctwR = d.ctw + d.ring_ctw[n];
+    a.uw = d.ctw + d.ring_uw[n];
+    return a;
+}
+
+// E + i O of the real-output half-length synthesis at index s (0 <= s <= P/2)
+// from y_s, y_{P-s}, y_{s+P/2}, y_{P/2-s} (y_q = a_q, q <= K_n; 0 above)
+__device__ __forceinline__ float2 syn_prologue(float2 y1, float2 y1m, float2 y2, float2 y2m, float2 w)
+{
+    const float2 h1 = cscale(cadd(y1, cconj(y1m)), 0.5f), h2 = cscale(cadd(y2, cconj(y2m)), 0.5f);
+    const float2 E = cadd(h1, h2);
+    const float2 O = cmulc(csub(h1, h2), w);  // times e^{+2 pi i s / P}
+    return make_float2(E.x - O.y, E.y + O.x);
+}
+
+template <int Pn>
+__device__ __forceinline__ void ring_fwd_spec_head(const PlanDev& d, const float2* __restrict__ Fp,
+                                                   const RingSpecArgs& a, float2* buf, float2* syn)
+{
+    const int lane = threadIdx.x;
+    const bool act = lane < kCfftLanes;
+    // the ring's half-plane values packed as the real sequence q(m) = Re F + Im F
+    // (m < Pn), Re F - Im F (m >= Pn), z(t) = q(2t) + i q(2t + 1)
+    if (act) {
+        constexpr int RND = (Pn + kCfftLanes - 1) / kCfftLanes;
+        float2 v[RND];
+#pragma unroll
+        for (int i = 0; i < RND; ++i) {
+            const int t = min(lane + i * kCfftLanes, Pn - 1);
+            const int m0 = 2 * t, m1 = 2 * t + 1;
+            const float2 F0 = Fp[a.off + (m0 < Pn ? m0 : m0 - Pn)];
+            const float2 F1 = Fp[a.off + (m1 < Pn ? m1 : m1 - Pn)];
+            v[i] = make_float2(m0 < Pn ? F0.x + F0.y : F0.x - F0.y, m1 < Pn ? F1.x + F1.y : F1.x - F1.y);
+        }
+#pragma unroll
+        for (int i = 0; i < RND; ++i) {
+            const int t = lane + i * kCfftLanes;
+            if (Pn % kCfftLanes == 0 || t < Pn) buf[t] = v[i];
+        }
+    }
+    __syncthreads();
+    cfft<Pn, false>(buf, a.ctwR);
+    // a_k = coef_k Q_k, Q_k = (Z_k + conj Z_{Pn-k})/2 - (i/2) w_{2Pn}^k (Z_k - conj Z_{Pn-k})
+    auto amode = [&](int k) {
+        const int kc = min(k, a.Kn);  // loads clamped into the ring's modes; k > K_n gives 0
+        const float2 zk = buf[kc];
+        const float2 zc = cconj(buf[kc == 0 ? 0 : Pn - kc]);
+        const float2 sm = cadd(zk, zc), df = csub(zk, zc);
+        const float2 t = cmul(a.uw[kc], df);
+        const float2 Q = make_float2(0.5f * (sm.x + t.y), 0.5f * (sm.y - t.x));
+        const float2 v = cmul(a.cf[kc], Q);
+        return k <= a.Kn ? v : make_float2(0.f, 0.f);
+    };
+    const int Pf = d.fold_P, SH = Pf >> 1;
+    // y_q = sum of a_k over k = q mod Pf, k <= K_n (in increasing k)
+    auto mode = [&](int q) {
+        float2 y = amode(q);
+        for (int k = q + Pf; k <= a.Kn; k += Pf) y = cadd(y, amode(k));
+        return y;
+    };
+    const float2* __restrict__ sw = d.ctw + d.syn_sw;
+    const int items = (SH + 1) >> 1;
+    if (act) {
+        for (int s = lane; s < items; s += kCfftLanes) {
+            if (s == 0) {
+                const float2 y0 = mode(0), yh = mode(SH), yq = mode(SH >> 1), y3 = mode(SH + (SH >> 1));
+                syn[0] = syn_prologue(y0, y0, yh, yh, sw[0]);
+                if ((SH & 1) == 0) syn[SH >> 1] = syn_prologue(yq, y3, y3, yq, sw[SH >> 1]);
+            } else {
+                const float2 ya = mode(s), yb = mode(Pf - s), yc = mode(s + SH), yd = mode(SH - s);
+                syn[s] = syn_prologue(ya, yb, yc, yd, sw[s]);
+                syn[SH - s] = syn_prologue(yd, yc, yb, ya, sw[SH - s]);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void ring_fwd_spec_tail(const PlanDev& d, const float2* buf, float* hn)
+{
+    const int lane = threadIdx.x;
+    if (lane < kCfftLanes) {
+        // detector q is point s q of the P-point grid: Re part at even, Im at odd points
+        for (int q0 = 0; q0 < d.D; q0 += 4 * kCfftLanes) {
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = min(q0 + lane + u * kCfftLanes, d.D - 1);
+                const int j = q * d.fold_s;
+                const float2 z = buf[j >> 1];
+                v[u] = (j & 1) ? z.y : z.x;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + lane + u * kCfftLanes;
+                if (q < d.D) hn[q] = v[u];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void ring_fwd_spec_tile(const PlanDev& d, const WsLayout& L, char* wb, int n, float2* buf)
+{
+    // one ring per workgroup: a loop over rings would keep every length's
+    // synthesis twiddles live across it
+    const float2* __restrict__ Fp = (const float2*)(wb + L.polar);
+    float* hT = (float*)(wb + L.hdet);  // [nlam][D]
+    float2* syn = buf + d.npsi_max / 2;  // the synthesis input after the ring buffer
+    const RingSpecArgs a = ring_spec_args(d, n);
+    const int Pn = d.ring_off[n + 1] - a.off;
+    switch (Pn) {
+#define PAT_RING_FWD_HEAD(LEN) \
+    case LEN: ring_fwd_spec_head<LEN>(d, Fp, a, buf, syn); break;
+        PAT_CFFT_LENGTHS(PAT_RING_FWD_HEAD)
+#undef PAT_RING_FWD_HEAD
+        default: break;
+    }
+    cfft_run<true>(syn, d.fold_P >> 1, d.ctw + d.syn_ctw);
+    ring_fwd_spec_tail(d, syn, hT + (size_t)n * d.D);
+}
+
+__device__ __forceinline__ void ring_adj_spec_head(const PlanDev& d, const float* __restrict__ hn, float2* buf)
+{
+    const int lane = threadIdx.x;
+    const int SH = d.fold_P >> 1, fs = d.fold_s, D = d.D;
+    // the detector values at points s q of the P-point grid (zero between), packed
+    // as z(t) = h(2t) + i h(2t + 1)
+    if (lane < kCfftLanes) {
+        const float rcp_s = __builtin_amdgcn_rcpf((float)fs);
+        for (int t0 = 0; t0 < SH; t0 += 2 * kCfftLanes) {
+            float2 v[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int t = min(t0 + lane + u * kCfftLanes, SH - 1);
+                float h[2];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int j = 2 * t + e;
+                    int q = j, rem = 0;
+                    if (fs != 1) fdivmod(j, fs, rcp_s, q, rem);
+                    const float x = hn[min(q, D - 1)];
+                    h[e] = (rem == 0 && q < D) ? x : 0.f;
+                }
+                v[u] = make_float2(h[0], h[1]);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int t = t0 + lane + u * kCfftLanes;
+                if (t < SH) buf[t] = v[u];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int Pn>
+__device__ __forceinline__ void ring_adj_spec_tail(const PlanDev& d, const RingSpecArgs& a, const float2* syn,
+                                                   float2* buf, float2* Hb)
+{
+    const int lane = threadIdx.x;
+    const bool act = lane < kCfftLanes;
+    const int Pf = d.fold_P, SH = Pf >> 1;
+    const float2* __restrict__ sw = d.ctw + d.syn_sw;
+    // y~ at synthesis index k (< P) from the half-length transform Z = buf, then
+    // Q~_k = conj(coef_k) y~_k for k <= K_n (0 above)
+    auto qmode = [&](int k) {
+        const int kc = min(k, a.Kn);
+        int kf = kc;  // synthesis index k mod Pf
+        while (kf >= Pf) kf -= Pf;
+        const bool hi = kf > SH;
+        const int s0 = hi ? Pf - kf : kf;
+        const float2 zk = syn[min(s0, SH - 1)];
+        const float2 zc = cconj(syn[s0 == 0 ? 0 : SH - s0]);
+        const float2 sm = cadd(zk, zc), df = csub(zk, zc);
+        const float2 t = cmul(sw[s0], df);
+        float2 y = make_float2(0.5f * (sm.x + t.y), 0.5f * (sm.y - t.x));
+        if (kf == SH) y = make_float2(zc.x + zc.y, 0.f);  // s0 = SH: zc = conj Z_0, y = Re Z_0 - Im Z_0
+        if (hi) y = cconj(y);
+        const float2 v = cmulc(y, a.cf[kc]);
+        return k <= a.Kn ? v : make_float2(0.f, 0.f);
+    };
+    // input of the ring's half-length inverse transform at u: E + i O from the
+    // Hermitian part of Q~ (q1 = Q~_u, q2 = Q~_{Pn-u})
+    auto herm = [&](int u, float2 q1, float2 q2) {
+        const float2 zero = make_float2(0.f, 0.f);
+        const float2 av = u == 0 ? make_float2(q1.x, 0.f) : cscale(q1, 0.5f);
+        const float2 cv = u == 0 ? zero : cscale(cconj(q2), 0.5f);
+        const float2 E = cadd(av, cv);
+        const float2 O = cmulc(csub(av, cv), a.uw[u]);
+        return make_float2(E.x - O.y, E.y + O.x);
+    };
+    constexpr int items = (Pn + 1) / 2;
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < (items + kCfftLanes - 1) / kCfftLanes; ++i) {
+            const int u = lane + i * kCfftLanes;
+            if (items % kCfftLanes != 0 && u >= items) break;
+            if (u == 0) {
+                const float2 q0 = qmode(0);
+                buf[0] = herm(0, q0, q0);
+                if constexpr ((Pn & 1) == 0) {
+                    const float2 qh = qmode(Pn / 2);
+                    buf[Pn / 2] = herm(Pn / 2, qh, qh);
+                }
+            } else {
+                const float2 qa = qmode(u), qb = qmode(Pn - u);
+                buf[u] = herm(u, qa, qb);
+                buf[Pn - u] = herm(Pn - u, qb, qa);
+            }
+        }
+    }
+    __syncthreads();
+    cfft<Pn, true>(buf, a.ctwR);
+    // q~(m): m = 2t -> Re z_t, m = 2t + 1 -> Im z_t;  F~_h(l) = (q~(l) + q~(l+Pn)) + i (q~(l) - q~(l+Pn)),
+    // times the conjugate half-pixel phase, stored in band order
+    if (act) {
+        constexpr int RO = (Pn + kCfftLanes - 1) / kCfftLanes;
+#pragma unroll
+        for (int i = 0; i < RO; ++i) {
+            const int l0 = lane + i * kCfftLanes;
+            const int l = min(l0, Pn - 1);
+            const float2 z1 = buf[l >> 1];
+            const float av = (l & 1) ? z1.y : z1.x;
+            const int m = l + Pn;
+            const float2 z2 = buf[m >> 1];
+            const float cv = (m & 1) ? z2.y : z2.x;
+            const float2 Fh = make_float2(av + cv, av - cv);
+            const int slot = d.band_of[a.off + l];
+            const float2 v = cmulc(Fh, d.pt_phase[a.off + l]);
+            if (Pn % kCfftLanes == 0 || l0 < Pn) Hb[slot] = v;
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void ring_adj_spec_tile(const PlanDev& d, const WsLayout& L, char* wb, int n, float2* buf)
+{
+    const float* hT = (const float*)(wb + L.hdet);  // [nlam][D]
+    float2* Hb = (float2*)(wb + L.polar);
+    float2* syn = buf + d.npsi_max / 2;  // the synthesis transform after the ring buffer
+    ring_adj_spec_head(d, hT + (size_t)n * d.D, syn);
+    cfft_run<false>(syn, d.fold_P >> 1, d.ctw + d.syn_ctw);
+    const RingSpecArgs a = ring_spec_args(d, n);
+    const int Pn = d.ring_off[n + 1] - a.off;
+    switch (Pn) {
+#define PAT_RING_ADJ_TAIL(LEN) \
+    case LEN: ring_adj_spec_tail<LEN>(d, a, syn, buf, Hb); break;
+        PAT_CFFT_LENGTHS(PAT_RING_ADJ_TAIL)
+#undef PAT_RING_ADJ_TAIL
+        default: break;
     }
 }
 
@@ -1472,7 +1756,26 @@ __global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu
     if (!batch_item(bt, kStRing, i, tile)) return;
     const BatchInst& I = bt.inst[i];
     const PlanDev d = I.d;
-    ring_fwd_tile(d, I.L, ws + I.ws_off, tile, I.ring_rt, sm);
+    if (d.ring_spec) ring_fwd_spec_tile(d, I.L, ws + I.ws_off, tile, sm);
+    else ring_fwd_tile(d, I.L, ws + I.ws_off, tile, I.ring_rt, sm);
+}
+
+// Ring kernels of plans with compile-time transforms: one wave and one ring
+// per workgroup (ring_rt does not apply), largest rings first.
+__global__ __launch_bounds__(kCfftLanes) void k_ring_fwd_spec(PlanDev d, WsLayout L, InstPtrs wsp, int batch)
+{
+    extern __shared__ float2 sm[];
+    int b, n;
+    if (!ring_item<false>(blockIdx.x, d.nlam, batch, b, n)) return;
+    ring_fwd_spec_tile(d, L, wsp.ws + (size_t)b * wsp.stride, n, sm);
+}
+
+__global__ __launch_bounds__(kCfftLanes) void k_ring_adj_spec(PlanDev d, WsLayout L, InstPtrs wsp, int batch)
+{
+    extern __shared__ float2 sm[];
+    int b, n;
+    if (!ring_item<true>(blockIdx.x, d.nlam, batch, b, n)) return;
+    ring_adj_spec_tile(d, L, wsp.ws + (size_t)b * wsp.stride, n, sm);
 }
 
 __global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_ring_adj(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
@@ -1490,7 +1793,8 @@ __global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu
     if (!batch_item(bt, kStRing, i, tile)) return;
     const BatchInst& I = bt.inst[i];
     const PlanDev d = I.d;
-    ring_adj_tile(d, I.L, ws + I.ws_off, tile, I.ring_rt, sm);
+    if (d.ring_spec) ring_adj_spec_tile(d, I.L, ws + I.ws_off, tile, sm);
+    else ring_adj_tile(d, I.L, ws + I.ws_off, tile, I.ring_rt, sm);
 }
 
 // Dense synthesis (explicit detector angles): `ntile` tiles per instance,
@@ -1829,6 +2133,41 @@ __global__ void k_cg_step_p(float* __restrict__ p, const float* __restrict__ s, 
     const long stride = (long)gridDim.x * blockDim.x;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
         p[(size_t)b * n + e] = s[(size_t)b * n + e] + beta * p[(size_t)b * n + e];
+}
+
+
+// ---------------------------------------------------------------------------
+// Streaming copies: the bandwidth yardstick the roofline figures are quoted
+// against, and the known-size traffic that calibrates the byte counters.
+// k_stream_copy: dst = src over n4 16-byte elements, four loads in flight per
+// thread before its stores.  k_scatter_copy: dst[perm[i]] = src[i] over
+// 8-byte elements (the scattered-store pattern of the ring adjoint's
+// band-order output).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_stream_copy(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                     long n4)
+{
+    const long stride = (long)gridDim.x * 1024;
+    for (long base = (long)blockIdx.x * 1024 + threadIdx.x; base < n4; base += stride) {
+        float4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const long e = base + u * 256;
+            v[u] = src[e < n4 ? e : n4 - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const long e = base + u * 256;
+            if (e < n4) dst[e] = v[u];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scatter_copy(const float2* __restrict__ src, float2* __restrict__ dst,
+                                                      const int* __restrict__ perm, long n)
+{
+    const long stride = (long)gridDim.x * 256;
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += stride) dst[perm[e]] = src[e];
 }
 
 }  // namespace pat

@@ -115,7 +115,16 @@ struct PlanDev {
     int fft_grid;  // length Ng
     int fft_dct;   // length 2M
     int fft_syn;   // length syn_len
+    // ring kernels with compile-time transforms (cfft.hpp): every ring length
+    // Npsi(n)/2 and the half-length synthesis P/2 have one (folded synthesis
+    // of even length P, no explicit angles)
+    int ring_spec;
+    int syn_ctw;            // offset in ctw of the synthesis transform's table (length P/2)
+    int syn_sw;             // offset in ctw of w_P^s = e^{-2 pi i s/P}, s = 0..P/2
     int pad0;
+    const int* ring_ctw;    // [nlam] offset in ctw of ring n's transform table (length Npsi(n)/2)
+    const int* ring_uw;     // [nlam] offset in ctw of w_{Npsi(n)}^k, k = 0..Npsi(n)/2
+    const float2* ctw;      // the tables (FP64-computed, FP32)
 };
 
 // Launch shapes chosen at plan creation (the autotuner may overwrite them).
@@ -159,6 +168,12 @@ constexpr int kRingMaxThreads = 256;
 // synthesis buffer), synthesis buffer, two-level twiddle tables of lengths
 // Npsi_max and S.
 __host__ __device__ constexpr int ring_tw_slots(int n) { return 64 + (n + 63) / 64; }
+// With compile-time transforms: the ring buffer (Npsi_max/2 values), then the
+// synthesis transform's P/2.
+__host__ __device__ constexpr size_t ring_spec_lds_slots(int npsi_max, int S)
+{
+    return (size_t)(npsi_max / 2) + (size_t)(S / 2);
+}
 __host__ __device__ constexpr size_t ring_lds_slots(int npsi_max, int S, int syn_half)
 {
     return (size_t)((npsi_max / 2 > (syn_half ? S / 2 : 0)) ? npsi_max / 2 : S / 2) +

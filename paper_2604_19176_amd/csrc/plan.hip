@@ -3,6 +3,7 @@
 // Everything here runs once per plan on the host in FP64; kernels only read
 // the resulting FP32/int tables.
 #include "fft.hpp"
+#include "cfft.hpp"
 #include "pat_internal.hpp"
 #include "../../include/pat.h"
 
@@ -12,6 +13,7 @@
 #include <complex>
 #include <cstring>
 #include <numeric>
+#include <map>
 #include <vector>
 
 namespace pat {
@@ -487,6 +489,7 @@ int fft_workgroup_threads(int nseq, const FftDev& fd) { return fft_threads(nseq,
 static size_t ring_lds_bytes(const PlanDev& d, int RT)
 {
     (void)RT;  // rings of a workgroup are processed one after another in the same LDS
+    if (d.ring_spec) return sizeof(float2) * ring_spec_lds_slots(d.npsi_max, d.syn_len);
     return sizeof(float2) * ring_lds_slots(d.npsi_max, d.syn_len, d.syn_half);
 }
 
@@ -712,6 +715,61 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     d.npts = npts;
     p->n_psi_max = npsi_max;
 
+    // ring kernels with compile-time transforms (cfft.hpp) where every length
+    // has one (uniform arc with a folded synthesis of even length P): tables of the transforms (per distinct length), of the
+    // real-transform unpacking twiddles w_{Npsi}^k (per distinct ring length)
+    // and of the synthesis prologue/epilogue twiddles w_P^s
+    std::vector<float2> ctw;
+    std::vector<int> ringCtw(nlam, 0), ringUw(nlam, 0);
+    d.ring_spec = 0;
+    {
+        const int SH = dv.P / 2;
+        bool ok = !dv.dense && dv.P > 0 && d.syn_half && cfft_len_ok(SH);
+        for (int n = 0; n < nlam && ok; ++n) ok = cfft_len_ok(ringN[n] / 2);
+        if (ok) {
+            std::map<int, int> tab_of, uw_of;
+            auto add_cfft = [&](int L) {
+                auto it = tab_of.find(L);
+                if (it != tab_of.end()) return it->second;
+                const CPlan cp = make_cplan(L);
+                const int o = (int)ctw.size();
+                ctw.resize(ctw.size() + std::max(cp.twoff[cp.np], 1));
+                for (int st = 0; st < cp.np; ++st) {
+                    const int R = cp.rad[st], NS = cp.ns[st];
+                    if (NS == 1) continue;
+                    for (int k = 0; k < NS; ++k)
+                        for (int r = 1; r < R; ++r) {
+                            const double a = -2.0 * PI * (double)(k * r) / (double)(NS * R);
+                            ctw[o + cp.twoff[st] + k * (R - 1) + r - 1] =
+                                make_float2((float)std::cos(a), (float)std::sin(a));
+                        }
+                }
+                tab_of[L] = o;
+                return o;
+            };
+            auto add_pow = [&](int n, int count) {  // e^{-2 pi i e / n}, e = 0..count-1
+                const int o = (int)ctw.size();
+                for (int e = 0; e < count; ++e) {
+                    const double a = -2.0 * PI * (double)e / (double)n;
+                    ctw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+                }
+                return o;
+            };
+            d.syn_ctw = add_cfft(SH);
+            d.syn_sw = add_pow(dv.P, SH + 1);
+            for (int n = 0; n < nlam; ++n) {
+                const int Pn = ringN[n] / 2;
+                ringCtw[n] = add_cfft(Pn);
+                auto it = uw_of.find(Pn);
+                if (it == uw_of.end()) it = uw_of.emplace(Pn, add_pow(2 * Pn, Pn + 1)).first;
+                ringUw[n] = it->second;
+            }
+            d.ring_spec = 1;
+            p->thr_ring = kCfftLanes;
+        }
+    }
+    if (ctw.empty()) ctw.push_back(make_float2(0.f, 0.f));
+
     // radial weights J_k(lam_n R) W_n / Npsi(n) (FP64; combined with the synthesis factors below)
     std::vector<double> Jw(joff);
     {
@@ -853,6 +911,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     size_t o_bandof = tb.add(band_of), o_bgeo = tb.add(bgeo), o_bph = tb.add(bphase), o_bptr = tb.add(bptr);
     size_t o_post = tb.add(post), o_vhat = tb.add(vhat), o_syn = tb.add(syn_tab);
     size_t o_ffts = tb.add(ffts.descs), o_tw = tb.add(ffts.tw);
+    size_t o_rctw = tb.add(ringCtw), o_ruw = tb.add(ringUw), o_ctw = tb.add(ctw);
     // store offsets in the pointer fields; relocated after the upload
     auto off = [](size_t o) { return (const void*)(uintptr_t)o; };
     d.deap = (const float*)off(o_deap);
@@ -873,6 +932,9 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     d.syn_tab = (const float*)off(o_syn);
     d.ffts = (const FftDev*)off(o_ffts);
     d.tw = (const float2*)off(o_tw);
+    d.ring_ctw = (const int*)off(o_rctw);
+    d.ring_uw = (const int*)off(o_ruw);
+    d.ctw = (const float2*)off(o_ctw);
     return PAT_OK;
 }
 
@@ -905,6 +967,7 @@ extern "C" int pat_plan_create(const pat_plan_desc* desc, pat_plan** out)
     rel(d.deap); rel(d.mask_rows); rel(d.pt_phase); rel(d.ring_off); rel(d.ring_K);
     rel(d.ring_fft); rel(d.ring_twn); rel(d.ring_joff); rel(d.coef); rel(d.band_of); rel(d.bpt_geo); rel(d.bpt_phase);
     rel(d.band_ptr); rel(d.czt_post); rel(d.czt_vhat); rel(d.syn_tab); rel(d.ffts); rel(d.tw);
+    rel(d.ring_ctw); rel(d.ring_uw); rel(d.ctw);
     p->desc = *desc;
     if (desc->det_theta) {  // the plan keeps its own copy of the angles
         p->det_theta = (double*)std::malloc(sizeof(double) * (size_t)desc->n_det);

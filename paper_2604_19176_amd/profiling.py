@@ -8,9 +8,12 @@ rocprofv3's own average over all of a kernel's dispatches.
 `python -m paper_2604_19176_amd.profiling traffic <fetch.csv> <write.csv>
 --kernel NAME [NAME ...] --calib-bytes BYTES` turns two `--pmc FETCH_SIZE` /
 `--pmc WRITE_SIZE` counter-collection files into HBM bytes per launch of
-each named kernel (one JSON object, entries under "kernels").  Each counter (KiB per dispatch) is scaled by known/counted bytes of
-the calibration copy in the same run: the float32 multiply-by-one kernel with
-the largest counter value (it reads and writes BYTES each).
+each named kernel (one JSON object, entries under "kernels").  Each counter
+(KiB per dispatch) is scaled by known/counted bytes of the calibration copy in
+the same run: the library's streaming copy k_stream_copy with the largest
+counter value (it reads and writes BYTES each).  The same factors for the
+library's 8-byte scatter copy k_scatter_copy over BYTES (the scattered-store
+pattern of the ring adjoint) are reported beside them.
 """
 from __future__ import annotations
 
@@ -77,7 +80,7 @@ def _counter(path, kernel):
         v = float(r["Counter_Value"])
         if _short(name) == kernel:
             vals.append((_grid(r), v))
-        elif "MulFunctor" in name:
+        elif _short(name) == "k_stream_copy":
             calib.append(v)
     if not vals:
         raise SystemExit("kernel %s not found in %s" % (kernel, path))
@@ -89,6 +92,16 @@ def _counter(path, kernel):
     gsel = max(count, key=lambda g: (count[g], g))
     kv = [v for g, v in vals if g == gsel]
     return sum(kv) / len(kv), (max(calib) if calib else None), len(kv)
+
+
+def scatter_factors(fetch_csv, write_csv, calib_bytes):
+    """Known/counted bytes of the 8-byte scatter copy (largest dispatch) for
+    each counter, or None when the run has none."""
+    out = []
+    for path in (fetch_csv, write_csv):
+        v = [float(r["Counter_Value"]) for r in _rows(path) if _short(r["Kernel_Name"]) == "k_scatter_copy"]
+        out.append(calib_bytes / (max(v) * 1024.0) if v and max(v) > 0 else None)
+    return {"fetch_scale": out[0], "write_scale": out[1]}
 
 
 def traffic(fetch_csv, write_csv, kernel, calib_bytes):
@@ -108,7 +121,7 @@ def traffic(fetch_csv, write_csv, kernel, calib_bytes):
 
 
 # the device sources every kernel is compiled from
-KERNEL_FILES = ("kernels.hip", "fft.hpp", "pat_internal.hpp")
+KERNEL_FILES = ("kernels.hip", "fft.hpp", "cfft.hpp", "pat_internal.hpp")
 
 
 def source_hash(path):
@@ -144,6 +157,7 @@ def main(argv=None):
         print(stats_table(a.trace, a.stats_csv))
     else:
         d = {"batch": a.batch, "kernels_hash": source_hash(a.source), "calib_bytes": a.calib_bytes,
+             "scatter_copy_factors": scatter_factors(a.fetch, a.write, a.calib_bytes),
              "kernels": {k: traffic(a.fetch, a.write, k, a.calib_bytes) for k in a.kernel}}
         json.dump(d, sys.stdout, indent=1)
         print()

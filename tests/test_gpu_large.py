@@ -6,7 +6,10 @@ degree arc, 2048 samples, batch 8) the oracle's direct sums are too slow; the
 outputs are compared instead, at every detector/time sample or pixel, with
 closed forms that hold at any size: the discrete Gaussian form for A (blobs
 well inside the support) and the discrete impulse form for A*; the GPU pair
-also satisfies the adjoint identity and batch-equals-single there.
+also satisfies the adjoint identity and batch-equals-single there.  The
+workload's own broadband instance (blobs, discs and lines) is checked against
+FP64 oracle values computed once on the CPU and stored in tests/golden
+(large_1024.npz: every 16th detector's trace of A f and A* d at 4000 pixels).
 """
 import math
 
@@ -138,3 +141,42 @@ def test_mixed_batch_geometries_plan_and_run(torch_dev):
         assert err <= 1e-5, (key, err)
         plan.close()
     assert len(seen) == 36
+
+
+def _golden_module():
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_large_1024.py")
+    spec = importlib.util.spec_from_file_location("make_large_1024", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod, os.path.join(os.path.dirname(path), "large_1024.npz")
+
+
+def test_1024_broadband_batch8_against_stored_oracle(torch_dev):
+    """The large workload's own broadband instance (seed 5000: 20 blobs, 3 discs,
+    4 two-pixel lines; Sec. 2.4.1's limited-view setting at 1024^2 with the
+    270 degree arc of Sec. 2.4.2) as instance 0 of a batch of 8, in the launch
+    shapes the autotuner picks at batch 8: A at every 16th detector's full trace
+    and A* of a seeded datum at 4000 pixels, against FP64 oracle values stored
+    by tests/golden/make_large_1024.py (relative L2 <= 1e-5)."""
+    torch = torch_dev
+    import paper_2604_19176_amd as pat
+    mod, path = _golden_module()
+    gold = np.load(path)
+    geom = config_geometry(5)
+    B = CONFIGS[5]["batch"]
+    f0, d0, pix = mod.large_inputs(geom)
+    assert np.array_equal(pix, gold["pix"])
+    fs = np.stack([f0] + [make_phantom(geom.n, 20, 3, 4, 5000 + b) for b in range(1, B)])
+    ds = np.concatenate([d0[None], np.random.default_rng(5101).standard_normal((B - 1, geom.n_det, geom.n_t))])
+    plan = pat.PatPlan(geom, max_batch=B)
+    print("tuned:", plan.autotune(batch=B))
+    g = plan.forward(torch.tensor(fs, dtype=torch.float32, device="cuda"))
+    a = plan.adjoint(torch.tensor(ds, dtype=torch.float32, device="cuda"))
+    g0 = g[0].cpu().double().numpy()[gold["det"]]
+    a0 = a[0].cpu().double().numpy().ravel()[gold["pix"]]
+    plan.close()
+    ef, ea = _rel(g0, gold["g_rows"]), _rel(a0, gold["a_pix"])
+    print("1024^2 broadband: forward (64 traces) %.3e, adjoint (4000 pixels) %.3e" % (ef, ea))
+    assert ef <= 1e-5 and ea <= 1e-5
