@@ -49,15 +49,18 @@ FP32_PEAK_TFLOPS = 157.3           # published FP32 vector peak (packed FP32)
 FP32_NONPACKED_TFLOPS = 78.6       # ceiling of code built without packed FP32
 FWD_NAMES = ["colpass_fwd", "rowpass_fwd", "gather", "ring_fwd", "dct_fwd"]
 ADJ_NAMES = ["dct_adj", "ring_adj", "spread", "rowpass_adj", "colpass_adj"]
-KERNEL_SYMBOL = {"colpass_fwd": "k_colpass_fwd", "rowpass_fwd": "k_rowpass_fwd", "gather": "k_gather",
-                 "ring_fwd": "k_ring_fwd", "dct_fwd": "k_dct_det", "dct_adj": "k_dct_det",
-                 "ring_adj": "k_ring_adj", "spread": "k_spread", "rowpass_adj": "k_rowpass_adj",
-                 "colpass_adj": "k_colpass_adj", "syn_fwd": "k_syn_dense_fwd", "syn_adj": "k_syn_dense_adj"}
+# kernel symbols (without template arguments) of each timed stage; the
+# compile-time-length variants where a plan has them
+KERNEL_SYMBOL = {"colpass_fwd": ("k_colpass_fwd",), "rowpass_fwd": ("k_rowpass_fwd",), "gather": ("k_gather",),
+                 "ring_fwd": ("k_ring_fwd", "k_ring_fwd_spec"), "dct_fwd": ("k_dct_det", "k_dct_spec"),
+                 "dct_adj": ("k_dct_det", "k_dct_spec"), "ring_adj": ("k_ring_adj", "k_ring_adj_spec"),
+                 "spread": ("k_spread",), "rowpass_adj": ("k_rowpass_adj",), "colpass_adj": ("k_colpass_adj",),
+                 "syn_fwd": ("k_syn_dense_fwd",), "syn_adj": ("k_syn_dense_adj",)}
 MFMA_FP32_PEAK_TFLOPS = 157.3   # dense FP32 matrix-core peak of the MI355X
 # interpolation or spread of one polar point: 16 kernel evaluations (~6 flops),
 # 64 weight products and 64 complex x real multiply-adds (4 flops)
 FLOPS_PER_POINT = 16 * 6 + 64 + 64 * 4
-CALIB_ELEMS = 64 * 1024 * 1024     # float32 elements of the calibration copy (256 MiB each way)
+CALIB_ELEMS = 256 * 1024 * 1024    # float32 elements of the calibration copies (1 GiB each way)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2604_19176_amd", "csrc", "kernels.hip")
 
@@ -133,7 +136,7 @@ def measured_traffic(dom, B):
         if tr.get("kernels_hash") != kernels_hash() or tr.get("batch") != B:
             return None
         for name, d in tr.get("kernels", {}).items():
-            if name.split("<")[0] == KERNEL_SYMBOL[dom]:
+            if name.split("<")[0] in KERNEL_SYMBOL[dom]:
                 return int(d["fetch_bytes_per_launch"] + d["write_bytes_per_launch"])
     except (OSError, ValueError, KeyError, AttributeError):
         pass
@@ -252,9 +255,10 @@ def time_eager(torch, dev, fn, steps, warmup=2):
 
 
 def copy_calibration(torch, dev):
-    """The library's streaming copy over CALIB_ELEMS float32 (256 MiB read,
-    256 MiB written) and its 8-byte scatter over the same bytes: copies of
-    known size whose byte counters calibrate the PMC traffic figures."""
+    """The library's streaming copy over CALIB_ELEMS float32 (1 GiB read,
+    1 GiB written, the size measure_copy times) and its 8-byte scatter over
+    the same bytes: copies of known size whose byte counters calibrate the PMC
+    traffic figures."""
     import paper_2604_19176_amd as pat
     x = torch.ones(CALIB_ELEMS, dtype=torch.float32, device=dev)
     y = torch.empty_like(x)

@@ -61,6 +61,33 @@ static int syn_adj_tiles(const PlanDev& d)
     return ((d.nlam + kSynTile - 1) / kSynTile) * ((2 * d.Kp + kSynTile - 1) / kSynTile);
 }
 
+// LDS of a cosine-transform tile (compile-time length: no twiddles in LDS)
+static size_t dct_tile_lds(const pat_plan* p, int dp)
+{
+    if (p->dev.dct_spec) return sizeof(float2) * (size_t)dp * 2 * p->dev.M;
+    return fft_tile_lds(dp, p->h_fft_dct);
+}
+
+static void dct_launch(const pat_plan* p, hipStream_t st, const InstPtrs& wsp, float* gout, const float* gin, int adj,
+                       int n_mass, int batch)
+{
+    const PlanDev& d = p->dev;
+    const int dp = p->cfg.dct_dp;
+    const dim3 grid(xcd_grid(p->n_pair_tiles * batch)), blk(p->thr_dct);
+    const size_t lds = dct_tile_lds(p, dp);
+    if (!d.dct_spec) {
+        hipLaunchKernelGGL(k_dct_det, grid, blk, lds, st, d, p->ws, wsp, gout, gin, dp, adj, n_mass, batch);
+        return;
+    }
+    switch (2 * d.M) {
+#define PAT_DCT_LAUNCH(N2) \
+    case N2: hipLaunchKernelGGL(k_dct_spec<N2>, grid, blk, lds, st, d, p->ws, wsp, gout, gin, dp, adj, n_mass, batch); break;
+        PAT_DCT_LENGTHS(PAT_DCT_LAUNCH)
+#undef PAT_DCT_LAUNCH
+        default: break;
+    }
+}
+
 static int check_launch()
 {
     return hipGetLastError() == hipSuccess ? PAT_OK : PAT_ERR_HIP;
@@ -128,9 +155,7 @@ extern "C" int pat_forward(const pat_plan* p, const float* f, float* g, int batc
         if ((rc = check_launch())) return rc;
         prof_mark(p, 0, qd, st);
     }
-    hipLaunchKernelGGL(k_dct_det, dim3(xcd_grid(p->n_pair_tiles * batch)), dim3(p->thr_dct),
-                       fft_tile_lds(c.dct_dp, p->h_fft_dct), st, d, p->ws, wsp, g, (const float*)nullptr, c.dct_dp, 0, d.N,
-                       batch);
+    dct_launch(p, st, wsp, g, nullptr, 0, d.N, batch);
     if ((rc = check_launch())) return rc;
     prof_mark(p, 0, qd + 1, st);
     return PAT_OK;
@@ -146,8 +171,7 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
     const LaunchCfg& c = p->cfg;
     const InstPtrs wsp{(char*)ws, p->ws.bytes};
     prof_mark(p, 1, 0, st);
-    hipLaunchKernelGGL(k_dct_det, dim3(xcd_grid(p->n_pair_tiles * batch)), dim3(p->thr_dct),
-                       fft_tile_lds(c.dct_dp, p->h_fft_dct), st, d, p->ws, wsp, (float*)nullptr, g, c.dct_dp, 1, 0, batch);
+    dct_launch(p, st, wsp, nullptr, g, 1, 0, batch);
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 1, st);
     const int qa = d.syn_dense ? 1 : 0;  // event offset after the transposed synthesis
@@ -475,14 +499,15 @@ static void batch_layout(pat_batch* b)
             b->base[(size_t)s * (n + 1) + i + 1] = b->base[(size_t)s * (n + 1) + i] + items[s];
         // workgroup sizes from the tile shapes copied into the instance (a later
         // set_launch or autotune of the plan does not change this batch)
-        b->thr_col = std::max<unsigned>(b->thr_col, fft_workgroup_threads(I.col_np, p->h_fft_grid));
-        b->thr_row = std::max<unsigned>(b->thr_row, fft_workgroup_threads(I.row_rpb, p->h_fft_grid));
+        b->thr_col = std::max<unsigned>(b->thr_col, grid_threads(p, I.col_np));
+        b->thr_row = std::max<unsigned>(b->thr_row, grid_threads(p, I.row_rpb));
         b->thr_ring = std::max<unsigned>(b->thr_ring, p->thr_ring);
-        b->thr_dct = std::max<unsigned>(b->thr_dct, fft_workgroup_threads(I.dct_dp, p->h_fft_dct));
+        b->thr_dct = std::max<unsigned>(b->thr_dct, d.dct_spec ? I.dct_dp * cfft_lanes(2 * d.M)
+                                                               : fft_workgroup_threads(I.dct_dp, p->h_fft_dct));
         b->lds_col = std::max(b->lds_col, fft_tile_lds(I.col_np, p->h_fft_grid));
         b->lds_row = std::max(b->lds_row, fft_tile_lds(I.row_rpb, p->h_fft_grid));
         b->lds_ring = std::max(b->lds_ring, p->lds_ring);
-        b->lds_dct = std::max(b->lds_dct, fft_tile_lds(I.dct_dp, p->h_fft_dct));
+        b->lds_dct = std::max(b->lds_dct, dct_tile_lds(p, I.dct_dp));
     }
 }
 

@@ -21,9 +21,13 @@
 
 namespace pat {
 
-constexpr int kCfftLanes = 64;
-constexpr int kCfftMax = 1024;   // longest compile-time length
+constexpr int kCfftLanes = 64;   // lanes of a one-wave transform
+constexpr int kCfftMax = 2048;   // longest compile-time length
 constexpr int kCfftMaxPasses = 12;
+
+// Lanes that transform one sequence of length n: one wave up to 1024, two
+// waves (one workgroup-wide barrier per pass) above.
+__host__ __device__ constexpr int cfft_lanes(int n) { return n <= 1024 ? kCfftLanes : 2 * kCfftLanes; }
 
 struct CPlan {
     int np;                       // passes (0: no plan)
@@ -38,12 +42,12 @@ __host__ __device__ constexpr int cbf_valu(int R)
     return R == 2 ? 4 : R == 3 ? 12 : R == 4 ? 16 : R == 6 ? 44 : R == 8 ? 60 : R == 9 ? 88 : 158;
 }
 
-// Cost of a pass of radix R over length n at 64 lanes: rounds of butterflies
-// (arithmetic, twiddle products, address work, LDS issue) plus a fixed cost
-// per pass (two barriers and an LDS round trip).
+// Cost of a pass of radix R over length n at cfft_lanes(n) lanes: rounds of
+// butterflies (arithmetic, twiddle products, address work, LDS issue) plus a
+// fixed cost per pass (two barriers and an LDS round trip).
 __host__ __device__ constexpr int cpass_cost(int n, int R, bool twiddled)
 {
-    const int rounds = (n / R + kCfftLanes - 1) / kCfftLanes;
+    const int rounds = (n / R + cfft_lanes(n) - 1) / cfft_lanes(n);
     return rounds * (cbf_valu(R) + (twiddled ? 4 * (R - 1) : 0) + 8 + R) + 40;
 }
 
@@ -63,8 +67,8 @@ __host__ __device__ constexpr CPlan make_cplan(int n)
     while (m % 2 == 0) { m /= 2; ++x; }
     while (m % 3 == 0) { m /= 3; ++y; }
     if (m != 1) return p;
-    int best[11][8] = {};
-    int choice[11][8] = {};
+    int best[12][8] = {};
+    int choice[12][8] = {};
     for (int i = 0; i <= x; ++i)
         for (int j = 0; j <= y; ++j) {
             choice[i][j] = -1;
@@ -73,7 +77,7 @@ __host__ __device__ constexpr CPlan make_cplan(int n)
             for (int c = 0; c < 7; ++c) {
                 if (A[c] > i || B[c] > j) continue;
                 const int R = RS[c];
-                if (((n / R + kCfftLanes - 1) / kCfftLanes) * R > 32) continue;
+                if (((n / R + cfft_lanes(n) - 1) / cfft_lanes(n)) * R > 32) continue;
                 if (best[i - A[c]][j - B[c]] >= (1 << 30)) continue;
                 const int v = best[i - A[c]][j - B[c]] + cpass_cost(n, R, true);
                 if (v < best[i][j]) { best[i][j] = v; choice[i][j] = c; }
@@ -101,11 +105,20 @@ __host__ __device__ constexpr CPlan make_cplan(int n)
     return p;
 }
 
-// Lengths with a compile-time transform (the switch in cfft_run).
+// One-wave lengths with a compile-time transform (the switch in cfft_run and
+// in the ring kernels).
 #define PAT_CFFT_LENGTHS(X)                                                                                   \
     X(2) X(3) X(4) X(6) X(8) X(9) X(12) X(16) X(18) X(24) X(27) X(32) X(36) X(48) X(54) X(64) X(72) X(81) \
     X(96) X(108) X(128) X(144) X(162) X(192) X(216) X(243) X(256) X(288) X(324) X(384) X(432) X(486) X(512) \
     X(576) X(648) X(729) X(768) X(864) X(972) X(1024)
+
+// Grid sides Ng with a compile-time transform (2D-FFT passes)
+#define PAT_GRID_LENGTHS(X) X(128) X(256) X(512) X(1024) X(2048)
+
+__host__ __device__ constexpr bool grid_len_ok(int n)
+{
+    return n == 128 || n == 256 || n == 512 || n == 1024 || n == 2048;
+}
 
 __host__ __device__ constexpr bool cfft_len_ok(int n)
 {
@@ -125,19 +138,21 @@ struct CPlanOf {
     static constexpr CPlan p = make_cplan(N);
 };
 
-// One pass; `active` lanes (wave 0) compute, every thread passes the barriers.
+// One pass; `active` lanes (lane = 0 .. cfft_lanes(N) - 1 of the sequence)
+// compute, every thread of the workgroup passes the barriers.
 template <int N, int R, int NS, int TWOFF, bool INV>
 __device__ __forceinline__ void cpass(float2* __restrict__ x, const float2* __restrict__ tw, bool active, int lane)
 {
+    constexpr int T = cfft_lanes(N);
     constexpr int NB = N / R;
-    constexpr int RND = (NB + kCfftLanes - 1) / kCfftLanes;
+    constexpr int RND = (NB + T - 1) / T;
     float2 v[RND][R];
     if (active) {
 #pragma unroll
         for (int i = 0; i < RND; ++i) {
-            const int j0 = lane + i * kCfftLanes;
+            const int j0 = lane + i * T;
             // the last round's idle lanes work on the last butterfly (results dropped)
-            const int j = (NB % kCfftLanes == 0 || i + 1 < RND) ? j0 : min(j0, NB - 1);
+            const int j = (NB % T == 0 || i + 1 < RND) ? j0 : min(j0, NB - 1);
             if constexpr (NS > 1) {
                 const int k = j % NS;
                 const float2* tp = tw + TWOFF + k * (R - 1);
@@ -159,8 +174,8 @@ __device__ __forceinline__ void cpass(float2* __restrict__ x, const float2* __re
     if (active) {
 #pragma unroll
         for (int i = 0; i < RND; ++i) {
-            const int j = lane + i * kCfftLanes;
-            if (NB % kCfftLanes == 0 || i + 1 < RND || j < NB) {
+            const int j = lane + i * T;
+            if (NB % T == 0 || i + 1 < RND || j < NB) {
                 const int k = j % NS;
                 const int dst = (j - k) * R + k;
 #pragma unroll
@@ -171,6 +186,7 @@ __device__ __forceinline__ void cpass(float2* __restrict__ x, const float2* __re
     __syncthreads();
 }
 
+// Passes S, S+1, ... of the length's plan
 template <int N, bool INV, int S>
 __device__ __forceinline__ void cfft_passes(float2* x, const float2* __restrict__ tw, bool active, int lane)
 {
@@ -183,13 +199,22 @@ __device__ __forceinline__ void cfft_passes(float2* x, const float2* __restrict_
 
 // In-place transform of x[0..N) in LDS (forward: e^{-2 pi i jk/N}, inverse:
 // e^{+2 pi i jk/N}, unnormalised); `tw` = the length's table.  Every thread of
-// the workgroup calls it (barriers); lanes 0..63 of wave 0 compute.
+// the workgroup calls it (barriers); `active` threads, lanes 0 ..
+// cfft_lanes(N) - 1 of the sequence, compute.
+template <int N, bool INV>
+__device__ __forceinline__ void cfft(float2* x, const float2* __restrict__ tw, int lane, bool active)
+{
+    static_assert(CPlanOf<N>::p.np > 0, "no compile-time plan for this length");
+    cfft_passes<N, INV, 0>(x, tw, active, lane);
+}
+
+// One-wave lengths, computed by lanes 0..63 of wave 0.
 template <int N, bool INV>
 __device__ __forceinline__ void cfft(float2* x, const float2* __restrict__ tw)
 {
-    static_assert(CPlanOf<N>::p.np > 0, "no compile-time plan for this length");
+    static_assert(cfft_lanes(N) == kCfftLanes, "one-wave lengths only");
     const int lane = threadIdx.x;
-    cfft_passes<N, INV, 0>(x, tw, lane < kCfftLanes, lane);
+    cfft<N, INV>(x, tw, lane, lane < kCfftLanes);
 }
 
 // Out-of-line instance (one per length and direction), for run-time dispatch.

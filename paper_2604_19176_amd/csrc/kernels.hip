@@ -129,6 +129,32 @@ struct IdxF {
 };
 
 // ---------------------------------------------------------------------------
+// The grid transforms (length Ng, `nseq` sequences at stride ld in LDS): with
+// a compile-time length (plans with grid_spec) sequence s is transformed by
+// threads s T .. s T + T - 1 (T = cfft_lanes(Ng)); else by the run-time plan.
+// ---------------------------------------------------------------------------
+template <bool INV>
+__device__ __forceinline__ void grid_fft(const PlanDev& d, float2* x, int ld, int nseq, const float2* tb)
+{
+    if (d.grid_spec) {
+        switch (d.Ng) {
+#define PAT_GRID_CASE(NG)                                                                        \
+    case NG: {                                                                                   \
+        constexpr int T = cfft_lanes(NG);                                                        \
+        const int sq = threadIdx.x / T;                                                          \
+        cfft<NG, INV>(x + (size_t)min(sq, nseq - 1) * ld, d.ctw + d.grid_ctw, threadIdx.x - sq * T, sq < nseq); \
+        break;                                                                                   \
+    }
+            PAT_GRID_LENGTHS(PAT_GRID_CASE)
+#undef PAT_GRID_CASE
+            default: break;
+        }
+    } else {
+        fft_lds<INV>(x, ld, nseq, d.ffts[d.fft_grid], tb);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // forward: column pass (FFT along y of real columns, packed in pairs)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void colpass_fwd_tile(const PlanDev& d, const WsLayout& L, const float* __restrict__ fb,
@@ -186,7 +212,7 @@ __device__ __forceinline__ void colpass_fwd_tile(const PlanDev& d, const WsLayou
         red[j0 + threadIdx.x] = sc * d.h2;
     }
     __syncthreads();
-    fft_lds<false>(sm, Ng, NP, d.ffts[d.fft_grid], tb);
+    grid_fft<false>(d, sm, Ng, NP, tb);
     fill_batched<4>(
         d.Hy * CT,
         [&](int e) {
@@ -233,7 +259,7 @@ __device__ __forceinline__ void rowpass_fwd_tile(const PlanDev& d, const WsLayou
         },
         [&](int, IdxVal iv) { sm[iv.i] = iv.v; });
     __syncthreads();
-    fft_lds<false>(sm, Ng, nr, d.ffts[d.fft_grid], tb);
+    grid_fft<false>(d, sm, Ng, nr, tb);
     fill_batched<4>(
         nr * Ng, [&](int e) { return sm[e]; }, [&](int e, float2 v) { G[(size_t)r0 * Ng + e] = v; });
 }
@@ -729,15 +755,19 @@ __device__ __forceinline__ void ring_fwd_spec_head(const PlanDev& d, const float
     __syncthreads();
     cfft<Pn, false>(buf, a.ctwR);
     // a_k = coef_k Q_k, Q_k = (Z_k + conj Z_{Pn-k})/2 - (i/2) w_{2Pn}^k (Z_k - conj Z_{Pn-k})
+    // (modes above K_n are zero: their evaluation is branched around, which
+    // skips the upper half of the synthesis input for rings with K_n < P/2)
     auto amode = [&](int k) {
-        const int kc = min(k, a.Kn);  // loads clamped into the ring's modes; k > K_n gives 0
-        const float2 zk = buf[kc];
-        const float2 zc = cconj(buf[kc == 0 ? 0 : Pn - kc]);
-        const float2 sm = cadd(zk, zc), df = csub(zk, zc);
-        const float2 t = cmul(a.uw[kc], df);
-        const float2 Q = make_float2(0.5f * (sm.x + t.y), 0.5f * (sm.y - t.x));
-        const float2 v = cmul(a.cf[kc], Q);
-        return k <= a.Kn ? v : make_float2(0.f, 0.f);
+        float2 v = make_float2(0.f, 0.f);
+        if (k <= a.Kn) {
+            const float2 zk = buf[k];
+            const float2 zc = cconj(buf[k == 0 ? 0 : Pn - k]);
+            const float2 sm = cadd(zk, zc), df = csub(zk, zc);
+            const float2 t = cmul(a.uw[k], df);
+            const float2 Q = make_float2(0.5f * (sm.x + t.y), 0.5f * (sm.y - t.x));
+            v = cmul(a.cf[k], Q);
+        }
+        return v;
     };
     const int Pf = d.fold_P, SH = Pf >> 1;
     // y_q = sum of a_k over k = q mod Pf, k <= K_n (in increasing k)
@@ -1248,6 +1278,170 @@ __device__ __forceinline__ void dct_tile(const PlanDev& d, const WsLayout& L, ch
 }
 
 // ---------------------------------------------------------------------------
+// The cosine transform with a compile-time length N2 = 2M (plans with
+// dct_spec): the same transform as dct_tile, one detector pair per sequence
+// of cfft_lanes(N2) lanes.  The zero-padded input is read from global memory
+// straight into the first pass's butterflies (that pass has Ns = 1 and no
+// twiddles), so the LDS is neither zero-filled nor staged; passes whose
+// inputs would all be padding skip their loads.  The adjoint's per-detector
+// data sums are taken over the samples lane by lane (in order), then across
+// the lanes by a fixed tree: one order for every launch shape.
+// ---------------------------------------------------------------------------
+// Sum over the `T` lanes of a sequence (lane = its index in the sequence),
+// returned to every lane; `slot` holds one float per wave of the workgroup.
+template <int T>
+__device__ __forceinline__ float seq_sum(float v, int lane, float* slot)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if constexpr (T == 64) {
+        return __shfl(v, 0, 64);
+    } else {
+        const int w = threadIdx.x >> 6;
+        if ((lane & 63) == 0) slot[w] = v;
+        __syncthreads();
+        const int w0 = w - (lane >> 6);  // first wave of the sequence
+        float t = 0.f;
+#pragma unroll
+        for (int k = 0; k < T / 64; ++k) t += slot[w0 + k];
+        __syncthreads();
+        return t;
+    }
+}
+
+template <int N2>
+__device__ __forceinline__ void dct_spec_tile(const PlanDev& d, const WsLayout& L, char* wb, float* __restrict__ gout,
+                                              const float* __restrict__ gin, int tile, int DP, int adj, int n_mass,
+                                              float2* sm, float* red_s, float* mass_s)
+{
+    constexpr int T = cfft_lanes(N2);
+    constexpr CPlan P = CPlanOf<N2>::p;
+    constexpr int R0 = P.rad[0], NB0 = N2 / R0, RND0 = (NB0 + T - 1) / T;
+    const int D = d.D, TT = d.T, NL = d.nlam;
+    float* hT = (float*)(wb + L.hdet);
+    float* red = (float*)(wb + L.red);
+    const int sq = threadIdx.x / T, lane = threadIdx.x - sq * T;
+    const int pair = tile * DP + sq;
+    const bool active = sq < DP && pair < (D + 1) / 2;
+    const int d0 = 2 * min(pair, (D + 1) / 2 - 1);
+    const int d1 = d0 + 1 < D ? d0 + 1 : d0;  // the partner of the last odd detector reads d0, weighted 0
+    const float w1 = d0 + 1 < D ? 1.f : 0.f;
+    // D even: every pair's two values sit at an 8-byte aligned address of each row
+    const bool pair2 = (D & 1) == 0;
+    float2* x = sm + (size_t)min(sq, DP - 1) * N2;
+    const float2* __restrict__ tw = d.ctw + d.dct_ctw;
+    if (!adj && threadIdx.x < 64) {
+        const float m = wave0_fixed_sum(red, n_mass);
+        if (threadIdx.x == 0) *mass_s = m;
+    }
+    const int nin = adj ? TT : NL;
+    // input position pos (1..nin) of the pair: g(d, pos-1) (adjoint) or hT[pos-1][d] (forward)
+    auto inp = [&](int pos) {
+        const int q = min(max(pos - 1, 0), nin - 1);
+        float re, im;
+        if (adj) {
+            re = gin[(size_t)d0 * TT + q];
+            im = gin[(size_t)d1 * TT + q];
+        } else if (pair2) {  // the pair's two values are adjacent in the row: one 8-byte load
+            const float2 v = *(const float2*)(hT + (size_t)q * D + d0);
+            re = v.x;
+            im = v.y;
+        } else {
+            const float* row = hT + (size_t)q * D;
+            re = row[d0];
+            im = row[d1];
+        }
+        const bool in = pos >= 1 && pos <= nin;
+        return make_float2(in ? re : 0.f, in ? w1 * im : 0.f);
+    };
+    if (active) {
+        float2 v[RND0][R0];
+#pragma unroll
+        for (int i = 0; i < RND0; ++i) {
+            const int j = (NB0 % T == 0 || i + 1 < RND0) ? lane + i * T : min(lane + i * T, NB0 - 1);
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                // inputs past position nin are the zero padding: a whole block of
+                // them needs no load
+                v[i][r] = (r * NB0 <= nin) ? inp(j + r * NB0) : make_float2(0.f, 0.f);
+            }
+            butterfly<R0, false>(v[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < RND0; ++i) {
+            const int j = lane + i * T;
+            if (NB0 % T == 0 || i + 1 < RND0 || j < NB0) {
+#pragma unroll
+                for (int r = 0; r < R0; ++r) x[j * R0 + r] = v[i][r];
+            }
+        }
+    }
+    if (adj) {
+        // data sums of the pair's detectors, for the endpoint term's transpose
+        float s0 = 0.f, s1 = 0.f;
+        if (active)
+            for (int q = lane; q < TT; q += T) {
+                s0 += gin[(size_t)d0 * TT + q];
+                s1 += gin[(size_t)d1 * TT + q];
+            }
+        s0 = seq_sum<T>(s0, lane, red_s);
+        s1 = seq_sum<T>(s1, lane, red_s);
+        if (active && lane == 0) {
+            red[d0] = s0;
+            if (d0 + 1 < D) red[d0 + 1] = s1;
+        }
+    }
+    __syncthreads();
+    cfft_passes<N2, false, 1>(x, tw, active, lane);
+    const float add = adj ? 0.f : d.kappa * *mass_s;
+    if (!active) return;  // no barrier follows
+    const int nout = adj ? NL : TT;
+    for (int q0 = 0; q0 < nout; q0 += 2 * T) {
+        float2 o[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int q = min(q0 + lane + u * T, nout - 1);
+            const float2 a = x[q + 1], c = x[N2 - q - 1];
+            o[u] = make_float2(0.5f * (a.x + c.x) + add, 0.5f * (a.y + c.y) + add);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int q = q0 + lane + u * T;
+            if (q < nout) {
+                if (adj) {
+                    float* row = hT + (size_t)q * D;
+                    if (pair2) {
+                        *(float2*)(row + d0) = make_float2(o[u].x, o[u].y);
+                    } else {
+                        row[d0] = o[u].x;
+                        if (d0 + 1 < D) row[d0 + 1] = o[u].y;
+                    }
+                } else {
+                    gout[(size_t)d0 * TT + q] = o[u].x;
+                    if (d0 + 1 < D) gout[(size_t)(d0 + 1) * TT + q] = o[u].y;
+                }
+            }
+        }
+    }
+}
+
+// Lengths 2M with a compile-time cosine transform
+#define PAT_DCT_LENGTHS(X) X(256) X(512) X(1024) X(2048)
+
+__device__ __forceinline__ void dct_run(const PlanDev& d, const WsLayout& L, char* wb, float* __restrict__ gout,
+                                        const float* __restrict__ gin, int tile, int DP, int adj, int n_mass,
+                                        float2* sm, float* red_s, float* mass_s)
+{
+    switch (2 * d.M) {
+#define PAT_DCT_CASE(N2) \
+    case N2: dct_spec_tile<N2>(d, L, wb, gout, gin, tile, DP, adj, n_mass, sm, red_s, mass_s); break;
+        PAT_DCT_LENGTHS(PAT_DCT_CASE)
+#undef PAT_DCT_CASE
+        default: break;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // adjoint: deterministic spread of the polar half-plane values onto G~ [Hy][Ng]
 // One lane owns one column; bands (footprint base rows) are swept in order and
 // an 8-row register window accumulates; band points are staged in LDS with
@@ -1537,7 +1731,7 @@ __device__ __forceinline__ void rowpass_adj_tile(const PlanDev& d, const WsLayou
         },
         [&](int e, float2 v) { sm[e] = v; });
     __syncthreads();
-    fft_lds<true>(sm, Ng, nr, d.ffts[d.fft_grid], tb);
+    grid_fft<true>(d, sm, Ng, nr, tb);
     const float rcpN = 1.0f / (float)N;
     fill_batched<4>(
         nr * N,
@@ -1594,7 +1788,7 @@ __device__ __forceinline__ void colpass_adj_tile(const PlanDev& d, const WsLayou
         },
         [&](int e, float2 v) { sm[e] = v; });
     __syncthreads();
-    fft_lds<true>(sm, Ng, NP, d.ffts[d.fft_grid], tb);
+    grid_fft<true>(d, sm, Ng, NP, tb);
     const float kt = d.kappa * d.h2 * *gsum_s;
     const float rcpCT = 1.0f / (float)CT;
     fill_batched<4>(
@@ -1852,6 +2046,22 @@ __global__ __launch_bounds__(1024) void k_dct_det(PlanDev d, WsLayout L, InstPtr
              item - b * ntile, DP, adj, n_mass, sm, red_s, &mass_s);
 }
 
+template <int N2>
+__global__ __launch_bounds__(1024) void k_dct_spec(PlanDev d, WsLayout L, InstPtrs wsp, float* __restrict__ gout,
+                                                   const float* __restrict__ gin, int DP, int adj, int n_mass, int batch)
+{
+    extern __shared__ float2 sm[];
+    __shared__ float red_s[16];
+    __shared__ float mass_s;
+    const int ntile = ((d.D + 1) / 2 + DP - 1) / DP;
+    const int item = xcd_item(blockIdx.x, ntile * batch);
+    if (item < 0) return;
+    const int b = item / ntile;
+    const size_t go = (size_t)b * d.D * d.T;
+    dct_spec_tile<N2>(d, L, wsp.ws + (size_t)b * wsp.stride, adj ? nullptr : gout + go, adj ? gin + go : nullptr,
+                      item - b * ntile, DP, adj, n_mass, sm, red_s, &mass_s);
+}
+
 // adj = 0: out[i] receives the data of instance i; adj = 1: in[i] is read.
 __global__ __launch_bounds__(1024) void k_dct_det_b(BatchDev bt, char* ws, float* const* __restrict__ out,
                                                     const float* const* __restrict__ in, int adj)
@@ -1863,8 +2073,12 @@ __global__ __launch_bounds__(1024) void k_dct_det_b(BatchDev bt, char* ws, float
     if (!batch_item(bt, kStDct, i, tile)) return;
     const BatchInst& I = bt.inst[i];
     const PlanDev d = I.d;
-    dct_tile(d, I.L, ws + I.ws_off, adj ? nullptr : out[i], adj ? in[i] : nullptr, tile, I.dct_dp, adj, d.N, sm,
-             red_s, &mass_s);
+    if (d.dct_spec)
+        dct_run(d, I.L, ws + I.ws_off, adj ? nullptr : out[i], adj ? in[i] : nullptr, tile, I.dct_dp, adj, d.N, sm,
+                red_s, &mass_s);
+    else
+        dct_tile(d, I.L, ws + I.ws_off, adj ? nullptr : out[i], adj ? in[i] : nullptr, tile, I.dct_dp, adj, d.N, sm,
+                 red_s, &mass_s);
 }
 
 // IB instances per workgroup: instances g*IB .. g*IB + IB - 1 of the batch; CB threads.

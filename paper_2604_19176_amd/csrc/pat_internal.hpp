@@ -121,7 +121,10 @@ struct PlanDev {
     int ring_spec;
     int syn_ctw;            // offset in ctw of the synthesis transform's table (length P/2)
     int syn_sw;             // offset in ctw of w_P^s = e^{-2 pi i s/P}, s = 0..P/2
-    int pad0;
+    int dct_spec;           // 1: cosine transform of compile-time length 2M (cfft.hpp)
+    int dct_ctw;            // offset in ctw of its table
+    int grid_spec;          // 1: 2D-FFT passes of compile-time length Ng (cfft.hpp)
+    int grid_ctw;           // offset in ctw of its table
     const int* ring_ctw;    // [nlam] offset in ctw of ring n's transform table (length Npsi(n)/2)
     const int* ring_uw;     // [nlam] offset in ctw of w_{Npsi(n)}^k, k = 0..Npsi(n)/2
     const float2* ctw;      // the tables (FP64-computed, FP32)
@@ -282,6 +285,11 @@ struct pat_plan {
     hipEvent_t ev[2][8];
     int ev_count[2];
 };
+
+namespace pat {
+// Threads of a 2D-FFT pass workgroup over `nseq` sequences of the plan's grid side.
+int grid_threads(const pat_plan* p, int nseq);
+}  // namespace pat
 
 // A heterogeneous batch (pat_batch_create).
 struct pat_batch {

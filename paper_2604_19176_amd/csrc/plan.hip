@@ -484,6 +484,12 @@ int fixed_fft_for(long n, FftDev* out, std::vector<float2>& tw)
 
 int fft_workgroup_threads(int nseq, const FftDev& fd) { return fft_threads(nseq, fd); }
 
+// Threads of a 2D-FFT pass workgroup over `nseq` sequences of the plan's grid side
+int grid_threads(const pat_plan* p, int nseq)
+{
+    return p->dev.grid_spec ? nseq * cfft_lanes(p->dev.Ng) : fft_threads(nseq, p->h_fft_grid);
+}
+
 // Dynamic LDS of the ring kernels: half-ring FFT buffer, synthesis buffers,
 // [D][RT] detector tile and four twiddle tables.
 static size_t ring_lds_bytes(const PlanDev& d, int RT)
@@ -505,22 +511,27 @@ int apply_launch(pat_plan* p, const LaunchCfg& c)
     auto fft_ok = [&](int v, size_t each, const FftDev& f, size_t fixed) {
         return v >= 1 && v <= 16 && v * each + fixed <= kLdsMax && fft_threads(v, f) <= 1024;
     };
+    auto grid_ok = [&](int v) {
+        if (!d.grid_spec) return fft_ok(v, sizeof(float2) * d.Ng, p->h_fft_grid, twb_bytes(p->h_fft_grid));
+        return v >= 1 && v <= 16 && v * sizeof(float2) * d.Ng + twb_bytes(p->h_fft_grid) <= kLdsMax &&
+               v * cfft_lanes(d.Ng) <= 1024;
+    };
     if (c.col_np < 1 || c.col_np > 16 || c.row_rpb < 1 || c.row_rpb > 16 || c.dct_dp < 1 || c.dct_dp > 16 ||
         c.ring_rt < 1 || c.ring_rt > 64 || !gather_shape_ok(c.gat_cb, c.gat_th, c.gat_ib) ||
         !spread_shape_ok(c.spr_cb, c.spr_th, c.spr_ib))
         return PAT_ERR_ARG;
-    if (!fft_ok(c.col_np, sizeof(float2) * d.Ng, p->h_fft_grid, twb_bytes(p->h_fft_grid)) ||
-        !fft_ok(c.row_rpb, sizeof(float2) * d.Ng, p->h_fft_grid, twb_bytes(p->h_fft_grid)) ||
-        !fft_ok(c.dct_dp, sizeof(float2) * 2 * d.M, p->h_fft_dct, twb_bytes(p->h_fft_dct)))
-        return PAT_ERR_UNSUPPORTED;
+    const bool dct_ok = d.dct_spec ? (c.dct_dp * sizeof(float2) * 2 * (size_t)d.M <= kLdsMax &&
+                                      c.dct_dp * cfft_lanes(2 * d.M) <= 1024)
+                                   : fft_ok(c.dct_dp, sizeof(float2) * 2 * d.M, p->h_fft_dct, twb_bytes(p->h_fft_dct));
+    if (!grid_ok(c.col_np) || !grid_ok(c.row_rpb) || !dct_ok) return PAT_ERR_UNSUPPORTED;
     const size_t lr = ring_lds_bytes(d, c.ring_rt);
     if (lr > kLdsMax) return PAT_ERR_UNSUPPORTED;
     p->cfg = c;
     p->cfg.spr_cap = 2 * c.spr_cb;
     p->lds_ring = lr;
-    p->thr_col = fft_threads(c.col_np, p->h_fft_grid);
-    p->thr_row = fft_threads(c.row_rpb, p->h_fft_grid);
-    p->thr_dct = fft_threads(c.dct_dp, p->h_fft_dct);
+    p->thr_col = grid_threads(p, c.col_np);
+    p->thr_row = grid_threads(p, c.row_rpb);
+    p->thr_dct = d.dct_spec ? c.dct_dp * cfft_lanes(2 * d.M) : fft_threads(c.dct_dp, p->h_fft_dct);
     p->n_col_tiles = (d.N + 2 * c.col_np - 1) / (2 * c.col_np);
     p->n_pair_tiles = ((d.D + 1) / 2 + c.dct_dp - 1) / c.dct_dp;
     return PAT_OK;
@@ -721,13 +732,13 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     // and of the synthesis prologue/epilogue twiddles w_P^s
     std::vector<float2> ctw;
     std::vector<int> ringCtw(nlam, 0), ringUw(nlam, 0);
+    std::map<int, int> tab_of, uw_of;
     d.ring_spec = 0;
     {
         const int SH = dv.P / 2;
         bool ok = !dv.dense && dv.P > 0 && d.syn_half && cfft_len_ok(SH);
         for (int n = 0; n < nlam && ok; ++n) ok = cfft_len_ok(ringN[n] / 2);
-        if (ok) {
-            std::map<int, int> tab_of, uw_of;
+        {
             auto add_cfft = [&](int L) {
                 auto it = tab_of.find(L);
                 if (it != tab_of.end()) return it->second;
@@ -755,17 +766,27 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
                 }
                 return o;
             };
-            d.syn_ctw = add_cfft(SH);
-            d.syn_sw = add_pow(dv.P, SH + 1);
-            for (int n = 0; n < nlam; ++n) {
-                const int Pn = ringN[n] / 2;
-                ringCtw[n] = add_cfft(Pn);
-                auto it = uw_of.find(Pn);
-                if (it == uw_of.end()) it = uw_of.emplace(Pn, add_pow(2 * Pn, Pn + 1)).first;
-                ringUw[n] = it->second;
+            if (ok) {
+                d.syn_ctw = add_cfft(SH);
+                d.syn_sw = add_pow(dv.P, SH + 1);
+                for (int n = 0; n < nlam; ++n) {
+                    const int Pn = ringN[n] / 2;
+                    ringCtw[n] = add_cfft(Pn);
+                    auto it = uw_of.find(Pn);
+                    if (it == uw_of.end()) it = uw_of.emplace(Pn, add_pow(2 * Pn, Pn + 1)).first;
+                    ringUw[n] = it->second;
+                }
+                d.ring_spec = 1;
+                p->thr_ring = kCfftLanes;
             }
-            d.ring_spec = 1;
-            p->thr_ring = kCfftLanes;
+            // the cosine transform: compile-time length 2M for the lengths the
+            // kernels instantiate
+            const int n2 = 2 * dv.M;
+            d.dct_spec = (n2 == 256 || n2 == 512 || n2 == 1024 || n2 == 2048) ? 1 : 0;
+            if (d.dct_spec) d.dct_ctw = add_cfft(n2);
+            // the 2D-FFT passes: compile-time grid side
+            d.grid_spec = grid_len_ok(Ng) ? 1 : 0;
+            if (d.grid_spec) d.grid_ctw = add_cfft(Ng);
         }
     }
     if (ctw.empty()) ctw.push_back(make_float2(0.f, 0.f));

@@ -31,7 +31,8 @@ struct SimDev {
     int D, T;               // detectors, time samples
     int rlo, nrow;          // box rows [rlo, rlo + nrow) read by the detectors' stencils
     int CT, RPB;            // columns per column-transform workgroup, rows per row-transform workgroup
-    double alpha;           // c dt / (M h): the phase c |k| j dt / (2 pi) = j alpha sqrt(mx^2 + my^2)
+    float a_hi, a_lo;       // alpha = c dt / (M h) as an unevaluated FP32 sum (FP64 on the host): the
+                            // phase c |k| j dt / (2 pi) = j alpha sqrt(mx^2 + my^2)
     const int2* mask_rows;  // [Ns]: image row i keeps columns jlo <= j < jhi (support disc)
     const int2* dix;        // [D]: box cell (x, y) of each detector's stencil sample at offset 0
     const float2* dfr;      // [D]: its fractional offsets (FP64-computed)
@@ -85,6 +86,36 @@ __global__ __launch_bounds__(1024) void k_sim_cols_fwd(SimDev s, const float2* _
     }
 }
 
+// The phase j alpha sqrt(mx^2 + my^2) reduced mod 1, in FP32 arithmetic with
+// error-free products (each quantity an unevaluated sum of two floats, as in
+// double-float arithmetic): q = mx^2 + my^2 is exact (q_hi + q_lo), the
+// square root is refined by one Newton step on its exact FMA residual, and
+// the products alpha s and j u are split exactly by FMA, so the fraction
+// returned is correct to about 2^-24 (a few cycles of phase would otherwise
+// lose their fraction's accuracy in FP32).
+__device__ __forceinline__ float sim_phase_frac(int mx, int my, int j, float a_hi, float a_lo)
+{
+    const unsigned q = (unsigned)(mx * mx + my * my);
+    const float q_hi = (float)q;
+    const float q_lo = (float)(int)(q - (unsigned)q_hi);  // exact: |q - q_hi| < 2^3 for q < 2^27
+    const float s = sqrtf(q_hi);
+    const float e = fmaf(-s, s, q_hi) + q_lo;             // q - s^2
+    const float sc = q == 0u ? 0.f : e * __builtin_amdgcn_rcpf(2.f * s);
+    // u = alpha (s + sc) = u_hi + u_lo
+    const float p = a_hi * s;
+    const float pe = fmaf(a_hi, s, -p);
+    const float t = pe + fmaf(a_hi, sc, a_lo * s);
+    const float u_hi = p + t;
+    const float u_lo = t - (u_hi - p);
+    // x = j u = P + L
+    const float J = (float)j;
+    const float P = J * u_hi;
+    const float L = fmaf(J, u_hi, -P) + J * u_lo;
+    float x = (P - floorf(P)) + L;
+    x -= floorf(x);
+    return x;
+}
+
 // Pair p of the chunk (time indices ja = 2 (pair0 + p) + 1, jb = ja + 1): the
 // inverse FFT along y of CT columns of F (cos(c|k|t_a) + i cos(c|k|t_b)),
 // rows [rlo, rlo + nrow) -> Wt [chunk][nrow][M]
@@ -101,11 +132,9 @@ __global__ __launch_bounds__(1024) void k_sim_cols_inv(SimDev s, const float2* _
         const int r = e / CT, cc = e - r * CT, c = c0 + min(cc, nc - 1);
         const float2 z = F[(size_t)r * M + c];
         const int mx = c < M / 2 ? c : c - M, my = r < M / 2 ? r : r - M;
-        const double u = s.alpha * sqrt((double)(mx * mx + my * my));
-        double xa = (double)ja * u, xb = (double)jb * u;
-        xa -= floor(xa);
-        xb -= floor(xb);
-        const float ca = cospif(2.0f * (float)xa), cb = has_b ? cospif(2.0f * (float)xb) : 0.f;
+        const float xa = sim_phase_frac(mx, my, ja, s.a_hi, s.a_lo);
+        const float xb = sim_phase_frac(mx, my, jb, s.a_hi, s.a_lo);
+        const float ca = cospif(2.0f * xa), cb = has_b ? cospif(2.0f * xb) : 0.f;
         sm[cc * M + r] = make_float2(z.x * ca - z.y * cb, z.y * ca + z.x * cb);
     }
     __syncthreads();
@@ -240,7 +269,11 @@ extern "C" int pat_sim_create(const pat_plan_desc* desc, pat_sim** out)
     d.off = (M - Ns) / 2;
     d.D = D;
     d.T = T;
-    d.alpha = desc->c * desc->dt / (M * h);
+    {
+        const double alpha = desc->c * desc->dt / (M * h);
+        d.a_hi = (float)alpha;
+        d.a_lo = (float)(alpha - (double)d.a_hi);
+    }
 
     // support mask per image row (FP64, as the reference decides it)
     std::vector<int2> mrows(Ns);

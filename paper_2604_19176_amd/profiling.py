@@ -96,11 +96,13 @@ def _counter(path, kernel):
 
 def scatter_factors(fetch_csv, write_csv, calib_bytes):
     """Known/counted bytes of the 8-byte scatter copy (largest dispatch) for
-    each counter, or None when the run has none."""
+    each counter, or None when the run has none.  It reads its source and a
+    4-byte index per 8-byte element (1.5 x calib_bytes) and writes calib_bytes
+    at scattered 8-byte addresses."""
     out = []
-    for path in (fetch_csv, write_csv):
+    for path, known in ((fetch_csv, 1.5 * calib_bytes), (write_csv, calib_bytes)):
         v = [float(r["Counter_Value"]) for r in _rows(path) if _short(r["Kernel_Name"]) == "k_scatter_copy"]
-        out.append(calib_bytes / (max(v) * 1024.0) if v and max(v) > 0 else None)
+        out.append(known / (max(v) * 1024.0) if v and max(v) > 0 else None)
     return {"fetch_scale": out[0], "write_scale": out[1]}
 
 

@@ -9,16 +9,18 @@
   network in float64 on the CPU gives the same loss, and its gradients measure
   the float32 network's own error (MIOpen convolutions, batch normalisation;
   reported, bounded at 1e-2).
-* Three Adam steps (learning rate 5e-4, the optimiser of Sec. 2.2.1) of two
-  identical float32 networks that differ only in the objective (library
-  kernels vs FP64 oracle) give the same losses (1e-4) and output images
-  within the learning rate (rel L2 <= 5e-4): Adam's first steps move each
-  parameter by about lr times the sign of its gradient, so the ~1e-6 relative
-  gradient difference of FP32 vs FP64 can flip the step of parameters whose
-  gradient is near zero, and the image then moves by up to the order of lr.
-  (Networks of different precision drift apart under these normalised first
-  steps whatever the objective, so the trajectory check holds the network
-  arithmetic fixed.)
+* Three gradient-descent steps of two identical float32 networks that differ
+  only in the objective (library kernels vs FP64 oracle) give the same losses
+  (1e-5) and output images (rel L2 1e-4).  The steps are plain gradient
+  descent, linear in the gradient, so the trajectories differ by the order of
+  the FP32-vs-FP64 gradient difference checked at step 0.  (Adam, the
+  optimiser of Sec. 2.2.1, moves each parameter in its first steps by about
+  the learning rate times the sign of its gradient, so the ~1e-6 gradient
+  difference flips the steps of parameters whose gradient is near zero and
+  moves the image by the order of the learning rate whatever the kernels do;
+  the Adam loop is checked by the objective-decrease test below.  Networks of
+  different precision drift apart likewise, so the trajectory check holds the
+  network arithmetic fixed.)
 * A short run lowers the objective; the U-Net has the layout of Sec. 2.2.1.
 """
 import numpy as np
@@ -126,20 +128,20 @@ def test_dip_steps_track_the_fp64_objective(torch_dev):
     assert float(la) == pytest.approx(float(lc), rel=1e-5)
     assert e_obj <= 1e-4
     assert e_net <= 1e-2
-    # (2) Adam trajectories of two identical float32 networks that differ only in the objective:
-    # the library's kernels vs the FP64 oracle.  Adam scales each parameter's step by the running
-    # RMS of its gradient, so in the first steps a parameter moves by about lr times the sign of
-    # its gradient: the ~1e-6 relative difference between the FP32 and FP64 objective gradients
-    # (checked at step 0 above) flips the steps of parameters whose gradient is near zero, which
-    # moves the output image by up to the order of lr.  The image bound is lr (5e-4); a wrong
-    # gradient moves the trajectories apart by orders of magnitude more.
-    lr = 5e-4
+    # (2) gradient-descent trajectories of two identical float32 networks that differ only in
+    # the objective: the library's kernels vs the FP64 oracle.  The step is linear in the
+    # gradient, so the trajectories stay within the order of the step-0 gradient difference
+    # (1e-4 bound); lr = 1e-6 moves the image by about 10 % over the three steps here, and a
+    # wrong operator gradient would move the trajectories apart by orders of magnitude more.
+    lr = 1e-6
     torch.manual_seed(4)
     net_a = UNet().cuda()
     net_b = UNet().cuda()
     net_b.load_state_dict(net_a.state_dict())
-    opt_a = torch.optim.Adam(net_a.parameters(), lr=lr)
-    opt_b = torch.optim.Adam(net_b.parameters(), lr=lr)
+    opt_a = torch.optim.SGD(net_a.parameters(), lr=lr)
+    opt_b = torch.optim.SGD(net_b.parameters(), lr=lr)
+    with torch.no_grad():
+        i0 = net_a(zg)[0, 0].cpu().double().numpy()
     for k in range(steps):
         opt_a.zero_grad()
         la = dip_objective(plan, net_a(zg)[0, 0].contiguous(), tg, lam, eps)
@@ -150,12 +152,13 @@ def test_dip_steps_track_the_fp64_objective(torch_dev):
         lb.backward()
         opt_b.step()
         print("step %d: loss library %.7e  oracle %.7e" % (k, float(la), float(lb)))
-        assert float(la) == pytest.approx(float(lb), rel=1e-4)
+        assert float(la) == pytest.approx(float(lb), rel=1e-5)
     with torch.no_grad():
         ia = net_a(zg)[0, 0].cpu().double().numpy()
         ib = net_b(zg)[0, 0].cpu().double().numpy()
-    print("image after %d steps: rel L2 %.2e" % (steps, _rel(ia, ib)))
-    assert _rel(ia, ib) <= lr
+    print("image after %d steps: moved %.2e, library vs oracle rel L2 %.2e" % (steps, _rel(ia, i0), _rel(ia, ib)))
+    assert _rel(ia, i0) >= 1e-2
+    assert _rel(ia, ib) <= 1e-4
     plan.close()
 
 
