@@ -192,7 +192,7 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
     prof_mark(p, 1, 2 + qa, st);
     {
         const int cb = c.spr_cb, ib = tile_ib(c.spr_ib, batch);
-        const int items = ((d.Ng + cb - 1) / cb) * spread_row_tiles(d.NB) * ((batch + ib - 1) / ib);
+        const int items = ((d.Ng + cb - 1) / cb) * d.spr_rows * ((batch + ib - 1) / ib);
         const dim3 grid(xcd_grid(items));
         const size_t lds = spread_lds(cb, ib);
         if (ib == 4) spread_launch_ib<4>(cb, grid, lds, st, d, p->ws, wsp, batch);
@@ -494,7 +494,7 @@ static void batch_layout(pat_batch* b)
         items[kStDct] = I.n_pair_tiles;
         items[kStSynFwd] = d.syn_dense ? syn_fwd_tiles(d) : 0;
         items[kStSynAdj] = d.syn_dense ? syn_adj_tiles(d) : 0;
-        items[kStSpread] = ((d.Ng + b->spr_cb - 1) / b->spr_cb) * spread_row_tiles(d.NB);
+        items[kStSpread] = ((d.Ng + b->spr_cb - 1) / b->spr_cb) * d.spr_rows;
         for (int s = 0; s < kNumStages; ++s)
             b->base[(size_t)s * (n + 1) + i + 1] = b->base[(size_t)s * (n + 1) + i] + items[s];
         // workgroup sizes from the tile shapes copied into the instance (a later

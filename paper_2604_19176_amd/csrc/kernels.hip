@@ -1538,6 +1538,43 @@ template <int IB, int CAP>
 __device__ __forceinline__ void spread_visit(const SpreadLds<IB>& S, int s0, int s1, int c0, int lane7,
                                              float2 (&acc)[IB][8])
 {
+    if constexpr (IB == 1) {
+        // one instance (small batches, where a tile's wave is often alone on
+        // its SIMD): the LDS reads of the next point, and the column of the
+        // one after, are issued before the current point's products (the same
+        // products in the same order)
+        if (s0 >= s1) return;
+        const int last = s1 - 1 - c0;
+        int e = s0 - c0;
+        float w = S.wx[(lane7 - S.bx[e]) * CAP + e];
+        float wy[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) wy[k] = S.wy[k * CAP + e];
+        float2 hv = S.h[e];
+        int bxn = S.bx[min(e + 1, last)];
+        for (int s = s0; s < s1; ++s) {
+            const int en = min(e + 1, last);
+            const int bx2 = S.bx[min(e + 2, last)];
+            const float wn = S.wx[(lane7 - bxn) * CAP + en];
+            float wyn[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) wyn[k] = S.wy[k * CAP + en];
+            const float2 hn = S.h[en];
+            const float2 t = cscale(hv, w);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                acc[0][k].x = fmaf(wy[k], t.x, acc[0][k].x);
+                acc[0][k].y = fmaf(wy[k], t.y, acc[0][k].y);
+            }
+            w = wn;
+            hv = hn;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) wy[k] = wyn[k];
+            bxn = bx2;
+            e = en;
+        }
+        return;
+    }
     for (int s = s0; s < s1; ++s) {
         const int e = s - c0;
         const int dx = lane7 - S.bx[e];
@@ -1560,10 +1597,12 @@ __device__ __forceinline__ void spread_visit(const SpreadLds<IB>& S, int s0, int
 // One tile of the spread for IB instances of one plan (wbs[b], b < nb, are the
 // instance workspaces; instances b >= nb are padding and neither read nor
 // written).  The workgroup has CB threads, one per column; CAP = 2 CB points
-// are staged per chunk.  Row tile rt sweeps bands [8 rt, 8 rt + 8) only and
-// writes their grid rows; the 7 rows after its last band are partial sums,
-// left in the tail region unless the tile is the last one (the adjoint row
-// pass adds them to the next tile's first rows).  CB is a compile-time
+// are staged per chunk.  Work row wr (d.spr_row[wr]) sweeps a run of bands:
+// a whole row tile rt, bands [8 rt, 8 rt + 8), writes their grid rows and
+// leaves its partial sums for the 7 rows after its last band in the tail
+// region unless it is the last row tile (the adjoint row pass adds them to the
+// next tile's first rows); a run of a split row tile writes every row it
+// touches, partial, to its rows of the slab region.  CB is a compile-time
 // constant so that every LDS access of the inner loops is an immediate offset
 // from one base address.
 template <int IB, int CB>
@@ -1573,13 +1612,17 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
     constexpr int CAP = 2 * CB;
     const int Ng = d.Ng, NB = d.NB;
     const int ncb = (Ng + CB - 1) / CB;
-    const int rb_ = tile / ncb, cb_ = tile - rb_ * ncb;
+    const int wr = tile / ncb, cb_ = tile - wr * ncb;
+    const int4 run = d.spr_row[wr];
+    const int band_lo = run.x, band_hi = run.y, rt = run.w;
+    const bool to_slab = run.z >= 0;
+    // the work row's output rows, from its first band on: grid or slab rows
     const float2* __restrict__ H[IB];
-    float2* Gt[IB];
+    float2* Ob[IB];
 #pragma unroll
     for (int b = 0; b < IB; ++b) {
         H[b] = (const float2*)(wbs[b] + L.polar);
-        Gt[b] = (float2*)(wbs[b] + L.grid);
+        Ob[b] = to_slab ? (float2*)(wbs[b] + L.slab) + (size_t)run.z * Ng : (float2*)(wbs[b] + L.grid) + (size_t)band_lo * Ng;
     }
     SpreadLds<IB> S;
     S.wx = sf;
@@ -1587,7 +1630,7 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
     S.bx = (int*)(sf + 16 * CAP);
     S.h = (float2*)(sf + 17 * CAP);  // CAP is even: 8-byte aligned
     int* rows = (int*)(sf + (size_t)CAP * (17 + 2 * IB));  // [3][CB + 10]
-    const int C0 = cb_ * CB, R0 = rb_ * kSpreadTh;
+    const int C0 = cb_ * CB;
     const int mx = C0 + threadIdx.x;
     const int lane7 = threadIdx.x + 7;
     const bool active = mx < Ng;
@@ -1596,7 +1639,6 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
     for (int b = 0; b < IB; ++b)
 #pragma unroll
         for (int k = 0; k < 8; ++k) acc[b][k] = make_float2(0.f, 0.f);
-    const int band_lo = R0, band_hi = min(NB - 1, R0 + kSpreadTh - 1);
     const int e0 = threadIdx.x, e1 = threadIdx.x + CB;
     // tile-relative footprint column of a staged point: the wrapped segment
     // (columns Ng-7 .. Ng-1 seen from a tile at column 0) is shifted by -Ng
@@ -1609,7 +1651,7 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
 #pragma unroll
         for (int b = 0; b < IB; ++b) h[b] = b < nb ? H[b][sl] : make_float2(0.f, 0.f);
     };
-    // band_lo <= band_hi always: there are ceil(NB / kSpreadTh) row tiles
+    // band_lo <= band_hi always (plan.hip, spread_runs)
     // Pipeline over bands (three LDS slots of CSR rows, slot of band r = (r - band_lo) % 3):
     // in the step of band rb, the CSR row of band rb+2 (fetched in the previous
     // step) is stored, the row of band rb+3 and the points of band rb+1 are
@@ -1669,11 +1711,11 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
             spread_visit<IB, CAP>(S, max(m.lo, c0), min(m.hi, c0 + cn), c0, lane7, acc);
             __syncthreads();
         }
-        // row rb has all of this tile's contributions
+        // row rb has all of this work row's contributions
         if (active) {
 #pragma unroll
             for (int b = 0; b < IB; ++b)
-                if (b < nb) Gt[b][(size_t)rb * Ng + mx] = acc[b][0];
+                if (b < nb) Ob[b][(size_t)(rb - band_lo) * Ng + mx] = acc[b][0];
         }
 #pragma unroll
         for (int b = 0; b < IB; ++b) {
@@ -1682,17 +1724,18 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
             acc[b][7] = make_float2(0.f, 0.f);
         }
     }
-    // the 7 rows after the tile's last band: complete after the plan's last band
-    // (rows NB .. Hy - 1), else partial sums for the tail region
-    const bool last = band_hi == NB - 1;
+    // the 7 rows after the last band: complete after the plan's last band (grid
+    // rows NB .. Hy - 1), partial sums for the tail region after a whole row
+    // tile's, slab rows after a run's
+    const bool own = to_slab || band_hi == NB - 1;
     if (active) {
 #pragma unroll
         for (int k = 0; k < 7; ++k) {
 #pragma unroll
             for (int b = 0; b < IB; ++b) {
                 if (b >= nb) continue;
-                if (last) Gt[b][(size_t)(band_hi + 1 + k) * Ng + mx] = acc[b][k];
-                else ((float2*)(wbs[b] + L.tail))[((size_t)rb_ * 7 + k) * Ng + mx] = acc[b][k];
+                if (own) Ob[b][(size_t)(band_hi - band_lo + 1 + k) * Ng + mx] = acc[b][k];
+                else ((float2*)(wbs[b] + L.tail))[((size_t)rt * 7 + k) * Ng + mx] = acc[b][k];
             }
         }
     }
@@ -1701,8 +1744,23 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
 // ---------------------------------------------------------------------------
 // adjoint: row pass (inverse FFT along x, crop to the N image columns)
 // ---------------------------------------------------------------------------
-// Grid row r = 8 q + k with q >= 1, k < 7 and 8 q < NB (a spread row tile q
-// exists) receives the tail left by spread row tile q - 1.
+// Grid row r = 8 q + k takes row tile q's part (its grid row, or, if the tile
+// was split into S runs, the slab rows of the runs that reach relative row k)
+// and, for q >= 1, k < 7 and 8 q < NB (a spread row tile q exists), row tile
+// q - 1's part at relative row k + 8 (its tail row, or its runs' slab rows).
+// Run j of a tile split S ways (w = 8 / S bands) holds relative rows
+// j w .. j w + w + 6 at slab rows s0 + 7 j + (relative row).  The terms are
+// added in one fixed order: (the tile's part, its runs in order) + (the
+// previous tile's part, its runs in order).
+
+// First and last run of a tile split 2^lg ways (lg >= 1) that reach relative
+// row x (0 .. 14): run j covers x when j w <= x <= j w + w + 6, w = 8 / 2^lg.
+__device__ __forceinline__ int2 split_runs_at(int lg, int x)
+{
+    const int w = kSpreadTh >> lg, a = x - w - 6;
+    return make_int2(a > 0 ? (a + w - 1) >> (3 - lg) : 0, min((1 << lg) - 1, x >> (3 - lg)));
+}
+
 __device__ __forceinline__ void rowpass_adj_tile(const PlanDev& d, const WsLayout& L, char* wb, int tile, int RPB,
                                                  float2* sm)
 {
@@ -1714,22 +1772,93 @@ __device__ __forceinline__ void rowpass_adj_tile(const PlanDev& d, const WsLayou
     const float2* tb = fft_twiddles_to_lds(sm + RPB * Ng, d.ffts[d.fft_grid], d.tw);
     static_assert(kSpreadTh == 8, "the tail lookup below divides by shifting");
     const float2* Tl = (const float2*)(wb + L.tail);
-    const float rcpNg = 1.0f / (float)Ng;
-    fill_batched<4>(
-        nr * Ng,
-        [&](int e) {
-            int rr, c;
-            fdivmod(e, Ng, rcpNg, rr, c);
-            const int r = r0 + rr, q = r >> 3, k = r & 7;
-            float2 v = Gt[(size_t)r0 * Ng + e];
-            if (q >= 1 && k < 7 && 8 * q < d.NB) {
-                const float2 t = Tl[((size_t)(q - 1) * 7 + k) * Ng + c];
-                v.x += t.x;
-                v.y += t.y;
+    const float2* Sl = (const float2*)(wb + L.slab);
+    // split entries of row tiles qa .. qa + 3 (the rows' tiles and the ones
+    // before; RPB <= 16), two per 64-bit word so that a lane picks its row's
+    // entry with shifts (no indexed private array)
+    const int qa = (r0 >> 3) - 1;
+    unsigned long long sp01 = 0, sp23 = 0;
+#pragma unroll
+    for (int t = 0; t < kSpreadSplitTiles; ++t) {  // constant indices only
+        const unsigned long long e = d.spr_head[t];
+        const int i = t - qa;
+        sp01 |= i == 0 ? e : (i == 1 ? e << 32 : 0ull);
+        sp23 |= i == 2 ? e : (i == 3 ? e << 32 : 0ull);
+    }
+    auto split_of = [&](int q) {  // q in qa .. qa + 3: (log2 of its runs, first slab row)
+        const int i = q - qa;
+        const unsigned e = (unsigned)(((i & 2) ? sp23 : sp01) >> (32 * (i & 1)));
+        return make_int2((int)(e & 15u), (int)(e >> 4));
+    };
+    // row by row (the row's case is uniform): a whole tile's row plus, if any,
+    // the tail row, four elements' loads per thread in flight; rows of split
+    // tiles sum up to kSpreadMaxRuns slab rows per part
+    constexpr int X = kSpreadMaxRuns;
+    for (int rr = 0; rr < nr; ++rr) {
+        const int r = r0 + rr, q = r >> 3, k = r & 7;
+        const bool tail = q >= 1 && k < 7 && 8 * q < d.NB;
+        const int2 so = split_of(q), st = tail ? split_of(q - 1) : make_int2(0, 0);
+        float2* dst = sm + (size_t)rr * Ng;
+        if (so.x == 0 && st.x == 0) {
+            const float2* __restrict__ gr = Gt + (size_t)r * Ng;
+            if (tail) {
+                const float2* __restrict__ tr = Tl + ((size_t)(q - 1) * 7 + k) * Ng;
+                fill_batched<4>(
+                    Ng,
+                    [&](int c) {
+                        const float2 a = gr[c], t = tr[c];
+                        return make_float2(a.x + t.x, a.y + t.y);
+                    },
+                    [&](int c, float2 v) { dst[c] = v; });
+            } else {
+                fill_batched<4>(Ng, [&](int c) { return gr[c]; }, [&](int c, float2 v) { dst[c] = v; });
             }
-            return v;
-        },
-        [&](int e, float2 v) { sm[e] = v; });
+            continue;
+        }
+        // the parts' rows: no own rows (the grid row, or the runs 0 .. nho of a
+        // split tile) and nt tail rows (the tail row, or the previous tile's runs
+        // jt.x .. jt.y); unused slots repeat the first row and are not added
+        const float2* po[X];
+        const float2* pt[X];
+        int no, nt;
+        if (so.x) {
+            no = split_runs_at(so.x, k).y + 1;
+#pragma unroll
+            for (int j = 0; j < X; ++j) po[j] = Sl + (size_t)(so.y + 7 * (j < no ? j : 0) + k) * Ng;
+        } else {
+            no = 1;
+#pragma unroll
+            for (int j = 0; j < X; ++j) po[j] = Gt + (size_t)r * Ng;
+        }
+        if (st.x) {
+            const int2 jt = split_runs_at(st.x, k + 8);
+            nt = jt.y - jt.x + 1;
+#pragma unroll
+            for (int j = 0; j < X; ++j) pt[j] = Sl + (size_t)(st.y + 7 * (jt.x + (j < nt ? j : 0)) + k + 8) * Ng;
+        } else {
+            nt = tail ? 1 : 0;
+#pragma unroll
+            for (int j = 0; j < X; ++j) pt[j] = tail ? Tl + ((size_t)(q - 1) * 7 + k) * Ng : po[0];
+        }
+        fill_batched<2>(
+            Ng,
+            [&](int c) {
+                float2 a[X], b[X];
+#pragma unroll
+                for (int j = 0; j < X; ++j) {
+                    a[j] = po[j][c];
+                    b[j] = pt[j][c];
+                }
+                float2 o = a[0], t = b[0];
+#pragma unroll
+                for (int j = 1; j < X; ++j) {
+                    if (j < no) o = make_float2(o.x + a[j].x, o.y + a[j].y);
+                    if (j < nt) t = make_float2(t.x + b[j].x, t.y + b[j].y);
+                }
+                return nt ? make_float2(o.x + t.x, o.y + t.y) : o;
+            },
+            [&](int c, float2 v) { dst[c] = v; });
+    }
     __syncthreads();
     grid_fft<true>(d, sm, Ng, nr, tb);
     const float rcpN = 1.0f / (float)N;
@@ -2082,11 +2211,13 @@ __global__ __launch_bounds__(1024) void k_dct_det_b(BatchDev bt, char* ws, float
 }
 
 // IB instances per workgroup: instances g*IB .. g*IB + IB - 1 of the batch; CB threads.
+// At IB = 4 the register budget is held to three waves per SIMD (168 VGPRs;
+// the kernel needs 170 unconstrained).
 template <int IB, int CB>
-__global__ __launch_bounds__(CB) void k_spread(PlanDev d, WsLayout L, InstPtrs wsp, int batch)
+__global__ __launch_bounds__(CB) __attribute__((amdgpu_waves_per_eu(IB == 4 ? 3 : 1))) void k_spread(PlanDev d, WsLayout L, InstPtrs wsp, int batch)
 {
     extern __shared__ float sf[];
-    const int per = ((d.Ng + CB - 1) / CB) * spread_row_tiles(d.NB);
+    const int per = ((d.Ng + CB - 1) / CB) * d.spr_rows;
     const int ngroups = (batch + IB - 1) / IB;
     const int item = xcd_item(blockIdx.x, per * ngroups);
     if (item < 0) return;

@@ -63,6 +63,12 @@ __host__ __device__ inline int fft_min_tps(const FftDev& d, int maxb = kFftMaxBu
     return t;
 }
 
+// Only the first kSpreadSplitTiles spread row tiles (around the spectrum's
+// origin, where the polar points crowd) may be split, into at most
+// kSpreadMaxRuns runs (see kSpreadTh below).
+constexpr int kSpreadSplitTiles = 16;
+constexpr int kSpreadMaxRuns = 4;
+
 struct PlanDev {
     // sizes
     int N;         // image side
@@ -96,6 +102,13 @@ struct PlanDev {
     const float4* bpt_geo;  // [npts]   (bx mod Ng as int bits, ring-order index as int bits, fx, fy)
     const float2* bpt_phase;// [npts]   pt_phase in band order
     const int* band_ptr;    // [NB][Ng + 1] CSR: first band-order slot with (r0, bx' >= bx)
+    // spread work rows (spread_runs): a row tile is swept whole, or as S runs of
+    // kSpreadTh / S bands each that write partial rows to the slab region
+    int spr_rows;           // work rows: the sum over row tiles of their runs
+    int slab_rows;          // rows of the slab region
+    const int4* spr_row;    // [spr_rows] (first band, last band, first slab row or -1 if whole, row tile)
+    // row tiles t < kSpreadSplitTiles: (first slab row of run 0) << 4 | log2 S (0: whole)
+    unsigned spr_head[kSpreadSplitTiles];
     // synthesis over detector angles theta_d = theta_0 + d dtheta
     int fold_P;             // P if dtheta = 2 pi s / P (P = 2^a3^b, gcd(s, P) = 1): fold k mod P, one FFT; else 0
     int fold_s;             // s: detector d is point s d of the P-point angular grid (s (D - 1) < P)
@@ -199,8 +212,20 @@ inline bool gather_shape_ok(int cb, int th, int ib)
 // tile's first 7 rows.  Every grid row is thus the sum of its bands from the
 // same 8-row block, then plus the sum of its bands from the block before: one
 // fixed order for every launch shape and batch.
+//
+// Near the spectrum's origin the polar points crowd, and a row tile's longest
+// lane (the visits of one column over its bands) is up to three times the
+// typical one; such row tiles are split into S = 2 or 4 runs of
+// kSpreadTh / S consecutive bands, each swept by its own workgroup, which
+// writes the kSpreadTh / S + 7 rows it touches to the slab region.  The
+// adjoint row pass then forms such a tile's rows as the sum of its runs'
+// partial rows, run by run in band order.  Which tiles are split, and into how
+// many runs, depends on the plan's points only (spread_runs in plan.hip), so
+// the order is still the same for every launch shape and batch.
 constexpr int kSpreadTh = 8;
 __host__ __device__ inline int spread_row_tiles(int NB) { return (NB + kSpreadTh - 1) / kSpreadTh; }
+// slab rows of one run of a row tile split into S runs
+__host__ __device__ inline int spread_run_rows(int S) { return kSpreadTh / S + 7; }
 inline bool spread_shape_ok(int cb, int th, int ib)
 {
     return cb >= 64 && cb <= 256 && cb % 64 == 0 && th == kSpreadTh && ib_ok(ib);
@@ -221,6 +246,7 @@ struct WsLayout {
     size_t polar;    // [npts]    float2   polar values: ring order (interpolation output), band order (spread input)
     size_t modes;    // [nlam][K+1] float2 mode coefficients (explicit detector angles only)
     size_t tail;     // [ceil(NB/8)][7][Ng] float2  spread: partial sums after each row tile's last band
+    size_t slab;     // [slab_rows][Ng] float2  spread: partial rows of the runs of split row tiles
     size_t red;      // small FP32 partial sums (mass / data sum)
     int n_red;       // number of partial sums
     size_t bytes;    // total per instance
@@ -234,7 +260,7 @@ enum BatchStage {
     kStGather,    // interpolation: ceil(Ng / gat_cb) x ceil(NB / gat_th) tiles
     kStRing,      // ring kernels: ceil(nlam / ring_rt) tiles
     kStDct,       // cosine transforms: ceil(ceil(D / 2) / dct_dp) tiles
-    kStSpread,    // spread: ceil(Ng / spr_cb) x ceil(NB / kSpreadTh) tiles
+    kStSpread,    // spread: ceil(Ng / spr_cb) x spr_rows tiles
     kStSynFwd,    // dense synthesis (explicit angles): ceil(nlam / 64) x ceil(D / 64) tiles, else 0
     kStSynAdj,    // its transpose: ceil(nlam / 64) x ceil(2 (K + 1) / 64) tiles, else 0
     kNumStages

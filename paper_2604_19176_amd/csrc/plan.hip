@@ -587,8 +587,9 @@ void layout_workspace(pat_plan* p)
     w.polar = o;  o += align256(sizeof(float2) * (size_t)d.npts);
     // explicit angles: mode coefficients a_k(n) (forward) / their adjoints, [nlam][K+1]
     w.modes = o;  o += d.syn_dense ? align256(sizeof(float2) * (size_t)d.nlam * d.Kp) : 0;
-    // spread: 7 partial rows per row tile
+    // spread: 7 partial rows per row tile; the partial rows of split row tiles' runs
     w.tail = o;   o += align256(sizeof(float2) * 7 * (size_t)d.Ng * spread_row_tiles(d.NB));
+    w.slab = o;   o += align256(sizeof(float2) * (size_t)d.slab_rows * d.Ng);
     // endpoint-term partial sums: one per image column (forward) or detector (adjoint)
     w.n_red = std::max(d.N, d.D);
     w.red = o;    o += align256(sizeof(float) * (size_t)w.n_red);
@@ -622,6 +623,71 @@ extern "C" int pat_bessel_jn_table(int kmax, double x, double* out)
     if (kmax < 0 || !out || !std::isfinite(x)) return PAT_ERR_ARG;
     bessel_jn_table(kmax, x, out);
     return PAT_OK;
+}
+
+// Spread work rows.  In band rb the lane of column c visits the points whose
+// footprint base column is c - 7 .. c (mod Ng); a row tile's longest lane,
+// summed over its bands, bounds its workgroup's time.  A row tile among the
+// first kSpreadSplitTiles whose longest lane exceeds kSpreadSplitFactor times
+// the median over the row tiles is split into the fewest runs S (2 or
+// kSpreadMaxRuns) that bring every run's longest lane under that limit, or
+// into kSpreadMaxRuns.  The last row tile, which writes the grid's final rows
+// itself, is never split.  Output: the work rows (first band, last band, first
+// slab row or -1, row tile), per row tile (S, first slab row), and the slab
+// rows in all.
+constexpr double kSpreadSplitFactor = 1.5;
+
+static void spread_runs(const std::vector<int>& bptr, int NB, int Ng, std::vector<int4>& rows,
+                        std::vector<int2>& split, int& slab_rows)
+{
+    const int nrt = spread_row_tiles(NB);
+    std::vector<int> vis((size_t)NB * Ng);
+    for (int r = 0; r < NB; ++r) {
+        const int* bp = &bptr[(size_t)r * (Ng + 1)];
+        for (int c = 0; c < Ng; ++c) {
+            int v = 0;
+            for (int dx = 0; dx < 8; ++dx) {
+                const int b = ((c - dx) % Ng + Ng) % Ng;
+                v += bp[b + 1] - bp[b];
+            }
+            vis[(size_t)r * Ng + c] = v;
+        }
+    }
+    auto longest = [&](int t, int S) {  // longest lane over the runs of row tile t split S ways
+        const int w = kSpreadTh / S, b0 = t * kSpreadTh, b1 = std::min(NB, b0 + kSpreadTh);
+        int best = 0;
+        for (int q = 0; q < S; ++q)
+            for (int c = 0; c < Ng; ++c) {
+                int v = 0;
+                for (int r = b0 + q * w; r < std::min(b1, b0 + (q + 1) * w); ++r) v += vis[(size_t)r * Ng + c];
+                best = std::max(best, v);
+            }
+        return best;
+    };
+    std::vector<int> whole(nrt);
+    for (int t = 0; t < nrt; ++t) whole[t] = longest(t, 1);
+    std::vector<int> srt(whole);
+    std::sort(srt.begin(), srt.end());
+    const double limit = kSpreadSplitFactor * srt[srt.size() / 2];
+    rows.clear();
+    split.assign(nrt, make_int2(1, -1));
+    slab_rows = 0;
+    for (int t = 0; t < nrt; ++t) {
+        const int b0 = t * kSpreadTh, b1 = std::min(NB, b0 + kSpreadTh) - 1;
+        int S = 1;
+        if (t + 1 < nrt && t < kSpreadSplitTiles)
+            while (S < kSpreadMaxRuns && longest(t, S) > limit) S *= 2;
+        if (S == 1) {
+            rows.push_back(make_int4(b0, b1, -1, t));
+            continue;
+        }
+        const int w = kSpreadTh / S;
+        split[t] = make_int2(S, slab_rows);
+        for (int q = 0; q < S; ++q) {
+            rows.push_back(make_int4(b0 + q * w, b0 + (q + 1) * w - 1, slab_rows, t));
+            slab_rows += spread_run_rows(S);
+        }
+    }
 }
 
 // Host part of plan creation; fills every table into `tb` and the PlanDev
@@ -861,6 +927,16 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
             bptr[(size_t)r * (Ng + 1) + Ng] = run;
         }
     }
+    std::vector<int4> sprRow;
+    std::vector<int2> sprSplit;
+    spread_runs(bptr, NB, Ng, sprRow, sprSplit, d.slab_rows);
+    d.spr_rows = (int)sprRow.size();
+    for (int t = 0; t < kSpreadSplitTiles; ++t) {
+        const int2 e = t < (int)sprSplit.size() ? sprSplit[t] : make_int2(1, -1);
+        int lg = 0;
+        while ((1 << lg) < e.x) ++lg;
+        d.spr_head[t] = e.x > 1 ? ((unsigned)e.y << 4) | (unsigned)lg : 0u;
+    }
 
     // --- synthesis over detector angles --------------------------------------
     // uniform arc: theta_d = theta_0 + d dtheta; explicit angles: the phases are
@@ -933,6 +1009,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     size_t o_post = tb.add(post), o_vhat = tb.add(vhat), o_syn = tb.add(syn_tab);
     size_t o_ffts = tb.add(ffts.descs), o_tw = tb.add(ffts.tw);
     size_t o_rctw = tb.add(ringCtw), o_ruw = tb.add(ringUw), o_ctw = tb.add(ctw);
+    size_t o_sprow = tb.add(sprRow);
     // store offsets in the pointer fields; relocated after the upload
     auto off = [](size_t o) { return (const void*)(uintptr_t)o; };
     d.deap = (const float*)off(o_deap);
@@ -956,6 +1033,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     d.ring_ctw = (const int*)off(o_rctw);
     d.ring_uw = (const int*)off(o_ruw);
     d.ctw = (const float2*)off(o_ctw);
+    d.spr_row = (const int4*)off(o_sprow);
     return PAT_OK;
 }
 
@@ -988,7 +1066,7 @@ extern "C" int pat_plan_create(const pat_plan_desc* desc, pat_plan** out)
     rel(d.deap); rel(d.mask_rows); rel(d.pt_phase); rel(d.ring_off); rel(d.ring_K);
     rel(d.ring_fft); rel(d.ring_twn); rel(d.ring_joff); rel(d.coef); rel(d.band_of); rel(d.bpt_geo); rel(d.bpt_phase);
     rel(d.band_ptr); rel(d.czt_post); rel(d.czt_vhat); rel(d.syn_tab); rel(d.ffts); rel(d.tw);
-    rel(d.ring_ctw); rel(d.ring_uw); rel(d.ctw);
+    rel(d.ring_ctw); rel(d.ring_uw); rel(d.ctw); rel(d.spr_row);
     p->desc = *desc;
     if (desc->det_theta) {  // the plan keeps its own copy of the angles
         p->det_theta = (double*)std::malloc(sizeof(double) * (size_t)desc->n_det);

@@ -14,6 +14,12 @@ the same run: the library's streaming copy k_stream_copy with the largest
 counter value (it reads and writes BYTES each).  The same factors for the
 library's 8-byte scatter copy k_scatter_copy over BYTES (the scattered-store
 pattern of the ring adjoint) are reported beside them.
+
+With `--rdreq <csv>`, a third pass counting the L2-to-memory read requests by
+size (`--pmc TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum
+TCC_EA0_RDREQ_sum`), the fetched bytes of each kernel are 32, 64 and 128 times
+its requests of each size instead of the scaled FETCH_SIZE; the same sum for
+k_stream_copy is reported against the bytes it is known to read.
 """
 from __future__ import annotations
 
@@ -106,12 +112,42 @@ def scatter_factors(fetch_csv, write_csv, calib_bytes):
     return {"fetch_scale": out[0], "write_scale": out[1]}
 
 
-def traffic(fetch_csv, write_csv, kernel, calib_bytes):
+RDREQ_SIZES = {"TCC_EA0_RDREQ_32B_sum": 32, "TCC_EA0_RDREQ_64B_sum": 64, "TCC_EA0_RDREQ_128B_sum": 128}
+
+
+def read_bytes_by_size(path):
+    """{(kernel, grid): [bytes of each dispatch]} from a request-size pass:
+    32, 64 and 128 bytes per counted request of each size."""
+    per = defaultdict(float)
+    key = {}
+    for r in _rows(path):
+        size = RDREQ_SIZES.get(r["Counter_Name"])
+        if size is None:
+            continue
+        d = (r["Dispatch_Id"], _short(r["Kernel_Name"]), _grid(r))
+        per[d] += size * float(r["Counter_Value"])
+        key[d] = (d[1], d[2])
+    out = defaultdict(list)
+    for d, v in per.items():
+        out[key[d]].append(v)
+    return out
+
+
+def _select(by_grid):
+    """The values at the most frequent grid among those of at least half the
+    largest grid (as _counter)."""
+    gmax = max(g for g in by_grid)
+    cand = {g: v for g, v in by_grid.items() if 2 * g >= gmax}
+    g = max(cand, key=lambda g: (len(cand[g]), g))
+    return cand[g]
+
+
+def traffic(fetch_csv, write_csv, kernel, calib_bytes, rdreq=None):
     f_kib, f_cal, nf = _counter(fetch_csv, kernel)
     w_kib, w_cal, nw = _counter(write_csv, kernel)
     sf = calib_bytes / (f_cal * 1024.0) if f_cal else 1.0
     sw = calib_bytes / (w_cal * 1024.0) if w_cal else 1.0
-    return {
+    out = {
         "kernel": kernel,
         "fetch_kib_per_launch_raw": f_kib, "write_kib_per_launch_raw": w_kib,
         "fetch_scale": sf, "write_scale": sw,
@@ -120,6 +156,12 @@ def traffic(fetch_csv, write_csv, kernel, calib_bytes):
         "calib_bytes": calib_bytes,
         "calib_fetch_kib": f_cal, "calib_write_kib": w_cal,
     }
+    if rdreq is not None:
+        v = _select({g: b for (k, g), b in rdreq.items() if k == kernel})
+        out["fetch_bytes_per_launch_scaled"] = out["fetch_bytes_per_launch"]
+        out["fetch_bytes_per_launch"] = sum(v) / len(v)
+        out["fetch_from"] = "request sizes"
+    return out
 
 
 # the device sources every kernel is compiled from
@@ -154,13 +196,18 @@ def main(argv=None):
     t.add_argument("--calib-bytes", type=float, required=True)
     t.add_argument("--batch", type=int, required=True)
     t.add_argument("--source", required=True)
+    t.add_argument("--rdreq")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats_table(a.trace, a.stats_csv))
     else:
+        rd = read_bytes_by_size(a.rdreq) if a.rdreq else None
         d = {"batch": a.batch, "kernels_hash": source_hash(a.source), "calib_bytes": a.calib_bytes,
              "scatter_copy_factors": scatter_factors(a.fetch, a.write, a.calib_bytes),
-             "kernels": {k: traffic(a.fetch, a.write, k, a.calib_bytes) for k in a.kernel}}
+             "kernels": {k: traffic(a.fetch, a.write, k, a.calib_bytes, rd) for k in a.kernel}}
+        if rd is not None:
+            cp = [v for (k, g), vs in rd.items() if k == "k_stream_copy" for v in vs]
+            d["copy_read_bytes_by_size"] = max(cp) if cp else None
         json.dump(d, sys.stdout, indent=1)
         print()
 
