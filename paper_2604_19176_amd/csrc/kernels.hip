@@ -1280,35 +1280,15 @@ __device__ __forceinline__ void dct_tile(const PlanDev& d, const WsLayout& L, ch
 // ---------------------------------------------------------------------------
 // The cosine transform with a compile-time length N2 = 2M (plans with
 // dct_spec): the same transform as dct_tile, one detector pair per sequence
-// of cfft_lanes(N2) lanes.  The zero-padded input is read from global memory
-// straight into the first pass's butterflies (that pass has Ns = 1 and no
-// twiddles), so the LDS is neither zero-filled nor staged; passes whose
-// inputs would all be padding skip their loads.  The adjoint's per-detector
-// data sums are taken over the samples lane by lane (in order), then across
-// the lanes by a fixed tree: one order for every launch shape.
+// of cfft_lanes(N2) lanes, DP pairs per workgroup.  The first pass (Ns = 1,
+// no twiddles) takes its inputs straight from memory, so the zero padding is
+// never stored, and blocks of it are never read.  The adjoint writes hT row
+// by row, the workgroup's pairs side by side.  The adjoint's per-detector data
+// sums are taken from the first pass's inputs, lane by lane in order, across
+// each wave's lanes by a fixed tree, then over the pair's waves in order (the
+// partial sums cross the barrier that precedes the second pass): one order
+// for every launch shape.
 // ---------------------------------------------------------------------------
-// Sum over the `T` lanes of a sequence (lane = its index in the sequence),
-// returned to every lane; `slot` holds one float per wave of the workgroup.
-template <int T>
-__device__ __forceinline__ float seq_sum(float v, int lane, float* slot)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    if constexpr (T == 64) {
-        return __shfl(v, 0, 64);
-    } else {
-        const int w = threadIdx.x >> 6;
-        if ((lane & 63) == 0) slot[w] = v;
-        __syncthreads();
-        const int w0 = w - (lane >> 6);  // first wave of the sequence
-        float t = 0.f;
-#pragma unroll
-        for (int k = 0; k < T / 64; ++k) t += slot[w0 + k];
-        __syncthreads();
-        return t;
-    }
-}
-
 template <int N2>
 __device__ __forceinline__ void dct_spec_tile(const PlanDev& d, const WsLayout& L, char* wb, float* __restrict__ gout,
                                               const float* __restrict__ gin, int tile, int DP, int adj, int n_mass,
@@ -1320,10 +1300,12 @@ __device__ __forceinline__ void dct_spec_tile(const PlanDev& d, const WsLayout& 
     const int D = d.D, TT = d.T, NL = d.nlam;
     float* hT = (float*)(wb + L.hdet);
     float* red = (float*)(wb + L.red);
+    const int npair = (D + 1) / 2;
+    const int p0 = tile * DP;               // the workgroup's first pair
+    const int npw = min(DP, npair - p0);    // and its number of pairs
     const int sq = threadIdx.x / T, lane = threadIdx.x - sq * T;
-    const int pair = tile * DP + sq;
-    const bool active = sq < DP && pair < (D + 1) / 2;
-    const int d0 = 2 * min(pair, (D + 1) / 2 - 1);
+    const bool active = sq < npw;
+    const int d0 = 2 * min(p0 + sq, npair - 1);
     const int d1 = d0 + 1 < D ? d0 + 1 : d0;  // the partner of the last odd detector reads d0, weighted 0
     const float w1 = d0 + 1 < D ? 1.f : 0.f;
     // D even: every pair's two values sit at an 8-byte aligned address of each row
@@ -1335,7 +1317,8 @@ __device__ __forceinline__ void dct_spec_tile(const PlanDev& d, const WsLayout& 
         if (threadIdx.x == 0) *mass_s = m;
     }
     const int nin = adj ? TT : NL;
-    // input position pos (1..nin) of the pair: g(d, pos-1) (adjoint) or hT[pos-1][d] (forward)
+    // input position pos (1..nin) of the pair: g(d, pos-1) (adjoint) or
+    // hT[pos-1][d] (forward); zero elsewhere
     auto inp = [&](int pos) {
         const int q = min(max(pos - 1, 0), nin - 1);
         float re, im;
@@ -1354,19 +1337,31 @@ __device__ __forceinline__ void dct_spec_tile(const PlanDev& d, const WsLayout& 
         const bool in = pos >= 1 && pos <= nin;
         return make_float2(in ? re : 0.f, in ? w1 * im : 0.f);
     };
+    // first pass (Ns = 1, no twiddles), fed from the inputs; inputs past
+    // position nin are the zero padding: a whole block of them needs no load.
+    // The adjoint's lanes sum the pair's data (for the endpoint term's
+    // transpose) from the same values.
+    float s0 = 0.f, s1 = 0.f;
+    float2 v[RND0][R0];
     if (active) {
-        float2 v[RND0][R0];
 #pragma unroll
         for (int i = 0; i < RND0; ++i) {
-            const int j = (NB0 % T == 0 || i + 1 < RND0) ? lane + i * T : min(lane + i * T, NB0 - 1);
+            const int j0 = lane + i * T;
+            const bool own = NB0 % T == 0 || i + 1 < RND0 || j0 < NB0;
+            // the last round's idle lanes work on the last butterfly (results dropped)
+            const int j = own ? j0 : NB0 - 1;
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
-                // inputs past position nin are the zero padding: a whole block of
-                // them needs no load
                 v[i][r] = (r * NB0 <= nin) ? inp(j + r * NB0) : make_float2(0.f, 0.f);
+                if (adj && own) {
+                    s0 += v[i][r].x;
+                    s1 += v[i][r].y;
+                }
             }
             butterfly<R0, false>(v[i]);
         }
+    }
+    if (active) {
 #pragma unroll
         for (int i = 0; i < RND0; ++i) {
             const int j = lane + i * T;
@@ -1376,50 +1371,72 @@ __device__ __forceinline__ void dct_spec_tile(const PlanDev& d, const WsLayout& 
             }
         }
     }
-    if (adj) {
-        // data sums of the pair's detectors, for the endpoint term's transpose
-        float s0 = 0.f, s1 = 0.f;
-        if (active)
-            for (int q = lane; q < TT; q += T) {
-                s0 += gin[(size_t)d0 * TT + q];
-                s1 += gin[(size_t)d1 * TT + q];
-            }
-        s0 = seq_sum<T>(s0, lane, red_s);
-        s1 = seq_sum<T>(s1, lane, red_s);
-        if (active && lane == 0) {
-            red[d0] = s0;
-            if (d0 + 1 < D) red[d0 + 1] = s1;
+    if (adj) {  // each wave's share of the sums, across its lanes by a fixed tree
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            s0 += __shfl_down(s0, o, 64);
+            s1 += __shfl_down(s1, o, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            red_s[2 * (threadIdx.x >> 6)] = s0;
+            red_s[2 * (threadIdx.x >> 6) + 1] = s1;
         }
     }
     __syncthreads();
+    if (adj && active && lane == 0) {  // the pair's waves in order
+        const int w0 = threadIdx.x >> 6;
+        float t0 = 0.f, t1 = 0.f;
+#pragma unroll
+        for (int k = 0; k < T / 64; ++k) {
+            t0 += red_s[2 * (w0 + k)];
+            t1 += red_s[2 * (w0 + k) + 1];
+        }
+        red[d0] = t0;
+        if (d0 + 1 < D) red[d0 + 1] = t1;
+    }
     cfft_passes<N2, false, 1>(x, tw, active, lane);
-    const float add = adj ? 0.f : d.kappa * *mass_s;
+    if (adj) {
+        // -> hT [nlam][D]: row by row, the workgroup's pairs side by side
+        const float rcp = 1.0f / (float)npw;
+        fill_batched<4>(
+            NL * npw,
+            [&](int e) {
+                int q, p;
+                fdivmod(e, npw, rcp, q, p);
+                const float2 a = sm[p * N2 + q + 1], c = sm[p * N2 + N2 - q - 1];
+                return make_float2(0.5f * (a.x + c.x), 0.5f * (a.y + c.y));
+            },
+            [&](int e, float2 o) {
+                int q, p;
+                fdivmod(e, npw, rcp, q, p);
+                const int a = 2 * (p0 + p);
+                float* row = hT + (size_t)q * D;
+                if (pair2) {
+                    *(float2*)(row + a) = o;
+                } else {
+                    row[a] = o.x;
+                    if (a + 1 < D) row[a + 1] = o.y;
+                }
+            });
+        return;
+    }
     if (!active) return;  // no barrier follows
-    const int nout = adj ? NL : TT;
-    for (int q0 = 0; q0 < nout; q0 += 2 * T) {
+    const float add = d.kappa * *mass_s;
+    // -> g [D][T]: contiguous along t
+    for (int q0 = 0; q0 < TT; q0 += 2 * T) {
         float2 o[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int q = min(q0 + lane + u * T, nout - 1);
+            const int q = min(q0 + lane + u * T, TT - 1);
             const float2 a = x[q + 1], c = x[N2 - q - 1];
             o[u] = make_float2(0.5f * (a.x + c.x) + add, 0.5f * (a.y + c.y) + add);
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int q = q0 + lane + u * T;
-            if (q < nout) {
-                if (adj) {
-                    float* row = hT + (size_t)q * D;
-                    if (pair2) {
-                        *(float2*)(row + d0) = make_float2(o[u].x, o[u].y);
-                    } else {
-                        row[d0] = o[u].x;
-                        if (d0 + 1 < D) row[d0 + 1] = o[u].y;
-                    }
-                } else {
-                    gout[(size_t)d0 * TT + q] = o[u].x;
-                    if (d0 + 1 < D) gout[(size_t)(d0 + 1) * TT + q] = o[u].y;
-                }
+            if (q < TT) {
+                gout[(size_t)d0 * TT + q] = o[u].x;
+                if (d0 + 1 < D) gout[(size_t)(d0 + 1) * TT + q] = o[u].y;
             }
         }
     }
@@ -2180,7 +2197,7 @@ __global__ __launch_bounds__(1024) void k_dct_spec(PlanDev d, WsLayout L, InstPt
                                                    const float* __restrict__ gin, int DP, int adj, int n_mass, int batch)
 {
     extern __shared__ float2 sm[];
-    __shared__ float red_s[16];
+    __shared__ float red_s[32];  // two per wave
     __shared__ float mass_s;
     const int ntile = ((d.D + 1) / 2 + DP - 1) / DP;
     const int item = xcd_item(blockIdx.x, ntile * batch);
