@@ -105,8 +105,8 @@ def algorithmic_bytes(info, geom, B):
         "gather": 16 * P + c8 * P + band_tab,               # band-order geometry and half-pixel phase
         "ring_fwd": ring_tab,
         "dct_fwd": 0, "dct_adj": 0,
-        "ring_adj": ring_tab + 4 * P + c8 * P,              # band-order slot and phase per point
-        "spread": 16 * P + band_tab,
+        "ring_adj": ring_tab + 4 * P,                       # band-order slot per point
+        "spread": 16 * P + c8 * P + band_tab,               # band-order geometry and half-pixel phase
         "rowpass_adj": 0, "colpass_adj": image_tab,
     }
     return {k: B * inst[k] + table[k] for k in inst}

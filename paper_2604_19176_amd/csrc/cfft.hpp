@@ -106,11 +106,15 @@ __host__ __device__ constexpr CPlan make_cplan(int n)
 }
 
 // One-wave lengths with a compile-time transform (the switch in cfft_run and
-// in the ring kernels).
-#define PAT_CFFT_LENGTHS(X)                                                                                   \
+// in the ring kernels), in two groups: the ring kernels are built once for the
+// lengths up to kCfftSplit and once for all of them, so that plans whose ring
+// and synthesis lengths are all short get the register budget of short ones.
+constexpr int kCfftSplit = 512;
+#define PAT_CFFT_LENGTHS_LO(X)                                                                                \
     X(2) X(3) X(4) X(6) X(8) X(9) X(12) X(16) X(18) X(24) X(27) X(32) X(36) X(48) X(54) X(64) X(72) X(81) \
-    X(96) X(108) X(128) X(144) X(162) X(192) X(216) X(243) X(256) X(288) X(324) X(384) X(432) X(486) X(512) \
-    X(576) X(648) X(729) X(768) X(864) X(972) X(1024)
+    X(96) X(108) X(128) X(144) X(162) X(192) X(216) X(243) X(256) X(288) X(324) X(384) X(432) X(486) X(512)
+#define PAT_CFFT_LENGTHS_HI(X) X(576) X(648) X(729) X(768) X(864) X(972) X(1024)
+#define PAT_CFFT_LENGTHS(X) PAT_CFFT_LENGTHS_LO(X) PAT_CFFT_LENGTHS_HI(X)
 
 // Grid sides Ng with a compile-time transform (2D-FFT passes)
 #define PAT_GRID_LENGTHS(X) X(128) X(256) X(512) X(1024) X(2048)
@@ -225,16 +229,24 @@ __device__ __forceinline__ void cfft_call(float2* x, const float2* __restrict__ 
 }
 
 // Run-time length: dispatch to the compile-time transform (n must satisfy
-// cfft_len_ok; the plan builder only selects such lengths).
-template <bool INV>
+// cfft_len_ok, and n <= kCfftSplit unless HI; the plan builder only selects
+// such lengths).
+template <bool INV, bool HI>
 __device__ __forceinline__ void cfft_run(float2* x, int n, const float2* __restrict__ tw)
 {
     switch (n) {
 #define PAT_CFFT_CASE_RUN(L) \
     case L: cfft_call<L, INV>(x, tw); break;
-        PAT_CFFT_LENGTHS(PAT_CFFT_CASE_RUN)
+        PAT_CFFT_LENGTHS_LO(PAT_CFFT_CASE_RUN)
+        default:
+            if constexpr (HI) {
+                switch (n) {
+                    PAT_CFFT_LENGTHS_HI(PAT_CFFT_CASE_RUN)
+                    default: break;
+                }
+            }
+            break;
 #undef PAT_CFFT_CASE_RUN
-        default: break;
     }
 }
 

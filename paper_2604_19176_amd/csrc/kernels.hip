@@ -16,7 +16,8 @@
 //   dct         : per detector: g(d, j) = sum_n hT[n][d] cos(pi n j / M) via one
 //                 complex FFT of length 2M for two detectors, + kappa * mass -> g [D][T]
 // Adjoint A* runs the exact transposes in reverse (dct, ring_adj or
-// syn_dense adjoint + ring_adj, spread, rowpass_adj, colpass_adj).  No
+// syn_dense adjoint + ring_adj, spread (which applies the conjugate half-pixel
+// phase as it stages each point), rowpass_adj, colpass_adj).  No
 // floating-point atomics anywhere: every sum has a fixed order, so results are
 // bitwise repeatable.
 #include "cfft.hpp"
@@ -274,9 +275,10 @@ __device__ __forceinline__ void rowpass_fwd_tile(const PlanDev& d, const WsLayou
 //            (one inverse FFT of length P after folding k mod P when
 //            dtheta = 2 pi / P, else Bluestein with two FFTs of length L),
 //            -> hT[n][d]  (real; the cosine transform over n follows)
-//   adjoint: the exact transpose, ending with the Hermitian fold and the
-//            conjugate half-pixel phase -> H, stored in band order for the
-//            spread (scattered writes here, contiguous reads there: reading
+//   adjoint: the exact transpose, ending with the Hermitian fold -> H,
+//            stored in band order for the spread, which applies the conjugate
+//            half-pixel phase as it stages each point from a band-order table
+//            (scattered writes here, contiguous reads there: reading
 //            H through each band-order point's ring index instead makes every
 //            wave-load of the spread touch tens of cache lines per instance,
 //            which costs the spread more than the scatter costs here).
@@ -676,7 +678,7 @@ __device__ __forceinline__ void ring_adj_tile(const PlanDev& d, const WsLayout& 
                 const float2 z2 = eb[m >> 1];
                 const float c = (m & 1) ? z2.y : z2.x;
                 const float2 Fh = make_float2(a + c, a - c);
-                return IdxVal{d.band_of[off + l], cmulc(Fh, d.pt_phase[off + l])};
+                return IdxVal{d.band_of[off + l], Fh};
             },
             [&](int, IdxVal iv) { Hb[iv.i] = iv.v; });
         __syncthreads();
@@ -754,26 +756,39 @@ __device__ __forceinline__ void ring_fwd_spec_head(const PlanDev& d, const float
     }
     __syncthreads();
     cfft<Pn, false>(buf, a.ctwR);
-    // a_k = coef_k Q_k, Q_k = (Z_k + conj Z_{Pn-k})/2 - (i/2) w_{2Pn}^k (Z_k - conj Z_{Pn-k})
-    // (modes above K_n are zero: their evaluation is branched around, which
-    // skips the upper half of the synthesis input for rings with K_n < P/2)
-    auto amode = [&](int k) {
-        float2 v = make_float2(0.f, 0.f);
-        if (k <= a.Kn) {
+    // a_k = coef_k Q_k for k <= K_n (zero above), in place of Z: the pair (k, Pn - k)
+    // shares sm = Z_k + conj Z_{Pn-k}, df = Z_k - conj Z_{Pn-k} and t = w_{2Pn}^k df,
+    //   Q_k = sm/2 - (i/2) t,  Q_{Pn-k} = conj(sm)/2 - (i/2) conj(t)
+    // (w_{2Pn}^{Pn-k} = -conj w_{2Pn}^k)
+    // (each lane reads and writes only its own pair's two slots)
+    if (act) {
+        constexpr int PAIRS = Pn / 2 + 1;  // k = 0 .. Pn/2
+#pragma unroll
+        for (int i = 0; i < (PAIRS + kCfftLanes - 1) / kCfftLanes; ++i) {
+            const int k0 = lane + i * kCfftLanes;
+            const int k = min(k0, PAIRS - 1);
+            const int kc = k == 0 ? 0 : Pn - k;
             const float2 zk = buf[k];
-            const float2 zc = cconj(buf[k == 0 ? 0 : Pn - k]);
+            const float2 zc = cconj(buf[kc]);
             const float2 sm = cadd(zk, zc), df = csub(zk, zc);
             const float2 t = cmul(a.uw[k], df);
-            const float2 Q = make_float2(0.5f * (sm.x + t.y), 0.5f * (sm.y - t.x));
-            v = cmul(a.cf[k], Q);
+            const float2 Q1 = make_float2(0.5f * (sm.x + t.y), 0.5f * (sm.y - t.x));
+            const float2 Q2 = make_float2(0.5f * (sm.x - t.y), 0.5f * (-sm.y - t.x));
+            const float2 c1 = a.cf[min(k, a.Kn)], c2 = a.cf[min(kc, a.Kn)];
+            const float2 v1 = k <= a.Kn ? cmul(c1, Q1) : make_float2(0.f, 0.f);
+            const float2 v2 = kc <= a.Kn ? cmul(c2, Q2) : make_float2(0.f, 0.f);
+            if (PAIRS % kCfftLanes == 0 || k0 < PAIRS) {
+                buf[k] = v1;
+                if (k != 0 && 2 * k != Pn) buf[kc] = v2;
+            }
         }
-        return v;
-    };
+    }
+    __syncthreads();
     const int Pf = d.fold_P, SH = Pf >> 1;
-    // y_q = sum of a_k over k = q mod Pf, k <= K_n (in increasing k)
+    // y_q = sum of a_k over k = q mod Pf, k < Pn (a_k = 0 above K_n), in increasing k
     auto mode = [&](int q) {
-        float2 y = amode(q);
-        for (int k = q + Pf; k <= a.Kn; k += Pf) y = cadd(y, amode(k));
+        float2 y = q < Pn ? buf[q] : make_float2(0.f, 0.f);
+        for (int k = q + Pf; k < Pn; k += Pf) y = cadd(y, buf[k]);
         return y;
     };
     const float2* __restrict__ sw = d.ctw + d.syn_sw;
@@ -818,6 +833,7 @@ __device__ __forceinline__ void ring_fwd_spec_tail(const PlanDev& d, const float
     __syncthreads();
 }
 
+template <bool HI>
 __device__ __forceinline__ void ring_fwd_spec_tile(const PlanDev& d, const WsLayout& L, char* wb, int n, float2* buf)
 {
     // one ring per workgroup: a loop over rings would keep every length's
@@ -830,11 +846,18 @@ __device__ __forceinline__ void ring_fwd_spec_tile(const PlanDev& d, const WsLay
     switch (Pn) {
 #define PAT_RING_FWD_HEAD(LEN) \
     case LEN: ring_fwd_spec_head<LEN>(d, Fp, a, buf, syn); break;
-        PAT_CFFT_LENGTHS(PAT_RING_FWD_HEAD)
+        PAT_CFFT_LENGTHS_LO(PAT_RING_FWD_HEAD)
+        default:
+            if constexpr (HI) {
+                switch (Pn) {
+                    PAT_CFFT_LENGTHS_HI(PAT_RING_FWD_HEAD)
+                    default: break;
+                }
+            }
+            break;
 #undef PAT_RING_FWD_HEAD
-        default: break;
     }
-    cfft_run<true>(syn, d.fold_P >> 1, d.ctw + d.syn_ctw);
+    cfft_run<true, HI>(syn, d.fold_P >> 1, d.ctw + d.syn_ctw);
     ring_fwd_spec_tail(d, syn, hT + (size_t)n * d.D);
 }
 
@@ -873,29 +896,48 @@ __device__ __forceinline__ void ring_adj_spec_head(const PlanDev& d, const float
 }
 
 template <int Pn>
-__device__ __forceinline__ void ring_adj_spec_tail(const PlanDev& d, const RingSpecArgs& a, const float2* syn,
+__device__ __forceinline__ void ring_adj_spec_tail(const PlanDev& d, const RingSpecArgs& a, float2* syn,
                                                    float2* buf, float2* Hb)
 {
     const int lane = threadIdx.x;
     const bool act = lane < kCfftLanes;
     const int Pf = d.fold_P, SH = Pf >> 1;
     const float2* __restrict__ sw = d.ctw + d.syn_sw;
-    // y~ at synthesis index k (< P) from the half-length transform Z = buf, then
-    // Q~_k = conj(coef_k) y~_k for k <= K_n (0 above)
+    // the ring points' band-order slots, for the stores at the end: loaded now,
+    // in flight during the transforms
+    constexpr int RO = (Pn + kCfftLanes - 1) / kCfftLanes;
+    int slot[RO];
+#pragma unroll
+    for (int i = 0; i < RO; ++i) slot[i] = d.band_of[a.off + min(lane + i * kCfftLanes, Pn - 1)];
+    // y~ at synthesis index q (0 <= q <= P/2) from the half-length transform Z,
+    // in place of Z (slot P/2 after it): the pair (s, SH - s) shares
+    // sm = Z_s + conj Z_{SH-s}, df = Z_s - conj Z_{SH-s}, t = w_P^s df,
+    //   y~_s = sm/2 - (i/2) t,  y~_{SH-s} = conj(sm)/2 - (i/2) conj(t),
+    // and y~_{SH} = Re Z_0 - Im Z_0; above P/2, y~_{P-q} = conj y~_q
+    // (each lane reads and writes only its own pair's slots)
+    float2* ys = syn;
+    if (act) {
+        const int PAIRS = SH / 2 + 1;  // s = 0 .. SH/2
+        for (int s = lane; s < PAIRS; s += kCfftLanes) {
+            const int sc = s == 0 ? 0 : SH - s;
+            const float2 zk = ys[s];
+            const float2 zc = cconj(ys[sc]);
+            const float2 sm = cadd(zk, zc), df = csub(zk, zc);
+            const float2 t = cmul(sw[s], df);
+            ys[s] = make_float2(0.5f * (sm.x + t.y), 0.5f * (sm.y - t.x));
+            if (s == 0) ys[SH] = make_float2(zc.x + zc.y, 0.f);
+            else if (2 * s != SH) ys[sc] = make_float2(0.5f * (sm.x - t.y), 0.5f * (-sm.y - t.x));
+        }
+    }
+    __syncthreads();
+    // Q~_k = conj(coef_k) y~_{k mod P} for k <= K_n (0 above)
     auto qmode = [&](int k) {
         const int kc = min(k, a.Kn);
         int kf = kc;  // synthesis index k mod Pf
         while (kf >= Pf) kf -= Pf;
         const bool hi = kf > SH;
-        const int s0 = hi ? Pf - kf : kf;
-        const float2 zk = syn[min(s0, SH - 1)];
-        const float2 zc = cconj(syn[s0 == 0 ? 0 : SH - s0]);
-        const float2 sm = cadd(zk, zc), df = csub(zk, zc);
-        const float2 t = cmul(sw[s0], df);
-        float2 y = make_float2(0.5f * (sm.x + t.y), 0.5f * (sm.y - t.x));
-        if (kf == SH) y = make_float2(zc.x + zc.y, 0.f);  // s0 = SH: zc = conj Z_0, y = Re Z_0 - Im Z_0
-        if (hi) y = cconj(y);
-        const float2 v = cmulc(y, a.cf[kc]);
+        const float2 y0 = ys[hi ? Pf - kf : kf];
+        const float2 v = cmulc(hi ? cconj(y0) : y0, a.cf[kc]);
         return k <= a.Kn ? v : make_float2(0.f, 0.f);
     };
     // input of the ring's half-length inverse transform at u: E + i O from the
@@ -931,9 +973,8 @@ __device__ __forceinline__ void ring_adj_spec_tail(const PlanDev& d, const RingS
     __syncthreads();
     cfft<Pn, true>(buf, a.ctwR);
     // q~(m): m = 2t -> Re z_t, m = 2t + 1 -> Im z_t;  F~_h(l) = (q~(l) + q~(l+Pn)) + i (q~(l) - q~(l+Pn)),
-    // times the conjugate half-pixel phase, stored in band order
+    // stored in band order (the spread applies the conjugate half-pixel phase)
     if (act) {
-        constexpr int RO = (Pn + kCfftLanes - 1) / kCfftLanes;
 #pragma unroll
         for (int i = 0; i < RO; ++i) {
             const int l0 = lane + i * kCfftLanes;
@@ -944,29 +985,35 @@ __device__ __forceinline__ void ring_adj_spec_tail(const PlanDev& d, const RingS
             const float2 z2 = buf[m >> 1];
             const float cv = (m & 1) ? z2.y : z2.x;
             const float2 Fh = make_float2(av + cv, av - cv);
-            const int slot = d.band_of[a.off + l];
-            const float2 v = cmulc(Fh, d.pt_phase[a.off + l]);
-            if (Pn % kCfftLanes == 0 || l0 < Pn) Hb[slot] = v;
+            if (Pn % kCfftLanes == 0 || l0 < Pn) Hb[slot[i]] = Fh;
         }
     }
     __syncthreads();
 }
 
+template <bool HI>
 __device__ __forceinline__ void ring_adj_spec_tile(const PlanDev& d, const WsLayout& L, char* wb, int n, float2* buf)
 {
     const float* hT = (const float*)(wb + L.hdet);  // [nlam][D]
     float2* Hb = (float2*)(wb + L.polar);
     float2* syn = buf + d.npsi_max / 2;  // the synthesis transform after the ring buffer
     ring_adj_spec_head(d, hT + (size_t)n * d.D, syn);
-    cfft_run<false>(syn, d.fold_P >> 1, d.ctw + d.syn_ctw);
+    cfft_run<false, HI>(syn, d.fold_P >> 1, d.ctw + d.syn_ctw);
     const RingSpecArgs a = ring_spec_args(d, n);
     const int Pn = d.ring_off[n + 1] - a.off;
     switch (Pn) {
 #define PAT_RING_ADJ_TAIL(LEN) \
     case LEN: ring_adj_spec_tail<LEN>(d, a, syn, buf, Hb); break;
-        PAT_CFFT_LENGTHS(PAT_RING_ADJ_TAIL)
+        PAT_CFFT_LENGTHS_LO(PAT_RING_ADJ_TAIL)
+        default:
+            if constexpr (HI) {
+                switch (Pn) {
+                    PAT_CFFT_LENGTHS_HI(PAT_RING_ADJ_TAIL)
+                    default: break;
+                }
+            }
+            break;
 #undef PAT_RING_ADJ_TAIL
-        default: break;
     }
 }
 
@@ -1535,9 +1582,10 @@ struct SpreadLds {
     float2* h;
 };
 
+// staged value: the point's H times the conjugate half-pixel phase ph
 template <int IB, int CAP>
 __device__ __forceinline__ void spread_stage(const SpreadLds<IB>& S, int e, float4 gq, int bx_rel,
-                                             const float2 (&h)[IB])
+                                             const float2 (&h)[IB], float2 ph)
 {
     float w[8];
     es_weights8(gq.z, w);
@@ -1547,8 +1595,11 @@ __device__ __forceinline__ void spread_stage(const SpreadLds<IB>& S, int e, floa
 #pragma unroll
     for (int k = 0; k < 8; ++k) S.wy[k * CAP + e] = w[k];
     S.bx[e] = bx_rel;
+    // explicit roundings: the same product in every instantiation of the tile
 #pragma unroll
-    for (int b = 0; b < IB; ++b) S.h[b * CAP + e] = h[b];
+    for (int b = 0; b < IB; ++b)
+        S.h[b * CAP + e] = make_float2(fmaf(h[b].x, ph.x, __fmul_rn(h[b].y, ph.y)),
+                                       fmaf(h[b].y, ph.x, -__fmul_rn(h[b].x, ph.y)));
 }
 
 template <int IB, int CAP>
@@ -1662,9 +1713,12 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
     auto rel = [&](const BandMeta& m, int idx, float4 gq) {
         return fbits(gq.x) - (idx < m.nA ? Ng : 0) - C0 + 7;
     };
-    auto fetch = [&](const BandMeta& m, int idx, float4& gq, float2 (&h)[IB]) {
+    // a point's geometry, half-pixel phase and values (the phase is applied
+    // when the point is staged, so that the loads stay in flight until then)
+    auto fetch = [&](const BandMeta& m, int idx, float4& gq, float2& ph, float2 (&h)[IB]) {
         const int sl = band_slot(m, idx);
         gq = d.bpt_geo[sl];
+        ph = d.bpt_phase[sl];
 #pragma unroll
         for (int b = 0; b < IB; ++b) h[b] = b < nb ? H[b][sl] : make_float2(0.f, 0.f);
     };
@@ -1677,6 +1731,7 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
     auto slot = [&](int r) { return rows + ((r - band_lo) % 3) * (CB + 10); };
     BandMeta nm;
     float4 ng0 = make_float4(0.f, 0.f, 0.f, 0.f), ng1 = ng0;
+    float2 np0 = make_float2(0.f, 0.f), np1 = np0;
     float2 nh0[IB], nh1[IB];
 #pragma unroll
     for (int b = 0; b < IB; ++b) nh0[b] = nh1[b] = make_float2(0.f, 0.f);
@@ -1693,24 +1748,25 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
     }
     __syncthreads();
     nm = band_meta(slot(band_lo), Ng, C0, CB, active);
-    if (e0 < nm.ntot) fetch(nm, e0, ng0, nh0);
-    if (e1 < nm.ntot) fetch(nm, e1, ng1, nh1);
+    if (e0 < nm.ntot) fetch(nm, e0, ng0, np0, nh0);
+    if (e1 < nm.ntot) fetch(nm, e1, ng1, np1, nh1);
     for (int rb = band_lo; rb <= band_hi; ++rb) {
         // slot of band rb+2 last held band rb-1, whose row was read two steps ago
         if (rb + 2 <= band_hi) band_row_store(slot(rb + 2), CB, rv);
         const BandMeta m = nm;
         const float4 g0 = ng0, g1 = ng1;
+        const float2 p0 = np0, p1 = np1;
         float2 h0[IB], h1[IB];
 #pragma unroll
         for (int b = 0; b < IB; ++b) { h0[b] = nh0[b]; h1[b] = nh1[b]; }
         // chunk 0 from registers
-        if (e0 < m.ntot) spread_stage<IB, CAP>(S, e0, g0, rel(m, e0, g0), h0);
-        if (e1 < m.ntot) spread_stage<IB, CAP>(S, e1, g1, rel(m, e1, g1), h1);
+        if (e0 < m.ntot) spread_stage<IB, CAP>(S, e0, g0, rel(m, e0, g0), h0, p0);
+        if (e1 < m.ntot) spread_stage<IB, CAP>(S, e1, g1, rel(m, e1, g1), h1, p1);
         __syncthreads();
         if (rb < band_hi) {  // band rb+1: its CSR row was stored one step ago
             nm = band_meta(slot(rb + 1), Ng, C0, CB, active);
-            if (e0 < nm.ntot) fetch(nm, e0, ng0, nh0);
-            if (e1 < nm.ntot) fetch(nm, e1, ng1, nh1);
+            if (e0 < nm.ntot) fetch(nm, e0, ng0, np0, nh0);
+            if (e1 < nm.ntot) fetch(nm, e1, ng1, np1, nh1);
         }
         if (rb + 3 <= band_hi) band_row_fetch(d, rb + 3, C0, CB, rv);
         spread_visit<IB, CAP>(S, m.lo, min(m.hi, CAP), 0, lane7, acc);
@@ -1720,9 +1776,9 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
             const int cn = min(CAP, m.ntot - c0);
             for (int e = threadIdx.x; e < cn; e += CB) {
                 float4 gq;
-                float2 hh[IB];
-                fetch(m, c0 + e, gq, hh);
-                spread_stage<IB, CAP>(S, e, gq, rel(m, c0 + e, gq), hh);
+                float2 ph, hh[IB];
+                fetch(m, c0 + e, gq, ph, hh);
+                spread_stage<IB, CAP>(S, e, gq, rel(m, c0 + e, gq), hh, ph);
             }
             __syncthreads();
             spread_visit<IB, CAP>(S, max(m.lo, c0), min(m.hi, c0 + cn), c0, lane7, acc);
@@ -2096,26 +2152,29 @@ __global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu
     if (!batch_item(bt, kStRing, i, tile)) return;
     const BatchInst& I = bt.inst[i];
     const PlanDev d = I.d;
-    if (d.ring_spec) ring_fwd_spec_tile(d, I.L, ws + I.ws_off, tile, sm);
+    if (d.ring_spec) ring_fwd_spec_tile<true>(d, I.L, ws + I.ws_off, tile, sm);
     else ring_fwd_tile(d, I.L, ws + I.ws_off, tile, I.ring_rt, sm);
 }
 
 // Ring kernels of plans with compile-time transforms: one wave and one ring
-// per workgroup (ring_rt does not apply), largest rings first.
+// per workgroup (ring_rt does not apply), largest rings first.  HI: built for
+// every compile-time length (else only for lengths up to kCfftSplit).
+template <bool HI>
 __global__ __launch_bounds__(kCfftLanes) void k_ring_fwd_spec(PlanDev d, WsLayout L, InstPtrs wsp, int batch)
 {
     extern __shared__ float2 sm[];
     int b, n;
     if (!ring_item<false>(blockIdx.x, d.nlam, batch, b, n)) return;
-    ring_fwd_spec_tile(d, L, wsp.ws + (size_t)b * wsp.stride, n, sm);
+    ring_fwd_spec_tile<HI>(d, L, wsp.ws + (size_t)b * wsp.stride, n, sm);
 }
 
+template <bool HI>
 __global__ __launch_bounds__(kCfftLanes) void k_ring_adj_spec(PlanDev d, WsLayout L, InstPtrs wsp, int batch)
 {
     extern __shared__ float2 sm[];
     int b, n;
     if (!ring_item<true>(blockIdx.x, d.nlam, batch, b, n)) return;
-    ring_adj_spec_tile(d, L, wsp.ws + (size_t)b * wsp.stride, n, sm);
+    ring_adj_spec_tile<HI>(d, L, wsp.ws + (size_t)b * wsp.stride, n, sm);
 }
 
 __global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_ring_adj(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
@@ -2133,7 +2192,7 @@ __global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu
     if (!batch_item(bt, kStRing, i, tile)) return;
     const BatchInst& I = bt.inst[i];
     const PlanDev d = I.d;
-    if (d.ring_spec) ring_adj_spec_tile(d, I.L, ws + I.ws_off, tile, sm);
+    if (d.ring_spec) ring_adj_spec_tile<true>(d, I.L, ws + I.ws_off, tile, sm);
     else ring_adj_tile(d, I.L, ws + I.ws_off, tile, I.ring_rt, sm);
 }
 

@@ -89,7 +89,6 @@ struct PlanDev {
     const float* deap;      // [N]: h / phihat(k - N/2), k = 0..N-1 (one factor per axis)
     const int2* mask_rows;  // [N]: row i keeps columns jlo <= j < jhi
     // polar points, ring order (ring n = 1..nlam occupies [ring_off[n-1], ring_off[n]))
-    const float2* pt_phase; // e^{-i pi (s_x + s_y)/Ng}  (half-pixel shift of cell-centred pixels)
     const int* ring_off;    // [nlam + 1]
     const int* ring_K;      // [nlam]   K_n: modes kept on ring n
     const int* ring_fft;    // [nlam]   FFT descriptor of Npsi(n)/2 (the ring's real transform)
@@ -100,7 +99,7 @@ struct PlanDev {
     // for the interpolation and the deterministic spread
     const int* band_of;     // [npts]   ring-order index -> band-order slot
     const float4* bpt_geo;  // [npts]   (bx mod Ng as int bits, ring-order index as int bits, fx, fy)
-    const float2* bpt_phase;// [npts]   pt_phase in band order
+    const float2* bpt_phase;// [npts]   e^{-i pi (s_x + s_y)/Ng} (half-pixel shift of cell-centred pixels)
     const int* band_ptr;    // [NB][Ng + 1] CSR: first band-order slot with (r0, bx' >= bx)
     // spread work rows (spread_runs): a row tile is swept whole, or as S runs of
     // kSpreadTh / S bands each that write partial rows to the slab region
@@ -132,6 +131,7 @@ struct PlanDev {
     // Npsi(n)/2 and the half-length synthesis P/2 have one (folded synthesis
     // of even length P, no explicit angles)
     int ring_spec;
+    int ring_spec_hi;       // 1: some ring or synthesis length exceeds kCfftSplit
     int syn_ctw;            // offset in ctw of the synthesis transform's table (length P/2)
     int syn_sw;             // offset in ctw of w_P^s = e^{-2 pi i s/P}, s = 0..P/2
     int dct_spec;           // 1: cosine transform of compile-time length 2M (cfft.hpp)
@@ -185,10 +185,10 @@ constexpr int kRingMaxThreads = 256;
 // Npsi_max and S.
 __host__ __device__ constexpr int ring_tw_slots(int n) { return 64 + (n + 63) / 64; }
 // With compile-time transforms: the ring buffer (Npsi_max/2 values), then the
-// synthesis transform's P/2.
+// synthesis transform's P/2 and one more slot (the adjoint's value at P/2).
 __host__ __device__ constexpr size_t ring_spec_lds_slots(int npsi_max, int S)
 {
-    return (size_t)(npsi_max / 2) + (size_t)(S / 2);
+    return (size_t)(npsi_max / 2) + (size_t)(S / 2) + 1;
 }
 __host__ __device__ constexpr size_t ring_lds_slots(int npsi_max, int S, int syn_half)
 {

@@ -800,10 +800,16 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     std::vector<int> ringCtw(nlam, 0), ringUw(nlam, 0);
     std::map<int, int> tab_of, uw_of;
     d.ring_spec = 0;
+    d.ring_spec_hi = 0;
     {
         const int SH = dv.P / 2;
         bool ok = !dv.dense && dv.P > 0 && d.syn_half && cfft_len_ok(SH);
         for (int n = 0; n < nlam && ok; ++n) ok = cfft_len_ok(ringN[n] / 2);
+        if (ok) {
+            int lmax = SH;
+            for (int n = 0; n < nlam; ++n) lmax = std::max(lmax, ringN[n] / 2);
+            d.ring_spec_hi = lmax > kCfftSplit;
+        }
         {
             auto add_cfft = [&](int L) {
                 auto it = tab_of.find(L);
@@ -1001,7 +1007,6 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
 
     // --- pack ---------------------------------------------------------------
     size_t o_deap = tb.add(deap), o_mask = tb.add(mask);
-    size_t o_phase = tb.add(phase);
     size_t o_roff = tb.add(ringOff), o_rk = tb.add(ringK), o_rfft = tb.add(ringFft), o_rj = tb.add(ringJoff);
     size_t o_rtwn = tb.add(ringTwn);
     size_t o_coef = tb.add(coef);
@@ -1014,7 +1019,6 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     auto off = [](size_t o) { return (const void*)(uintptr_t)o; };
     d.deap = (const float*)off(o_deap);
     d.mask_rows = (const int2*)off(o_mask);
-    d.pt_phase = (const float2*)off(o_phase);
     d.ring_off = (const int*)off(o_roff);
     d.ring_K = (const int*)off(o_rk);
     d.ring_fft = (const int*)off(o_rfft);
@@ -1063,7 +1067,7 @@ extern "C" int pat_plan_create(const pat_plan_desc* desc, pat_plan** out)
     char* base = (char*)mem;
     PlanDev& d = p->dev;
     auto rel = [&](auto& ptr) { ptr = (std::remove_reference_t<decltype(ptr)>)(base + (uintptr_t)ptr); };
-    rel(d.deap); rel(d.mask_rows); rel(d.pt_phase); rel(d.ring_off); rel(d.ring_K);
+    rel(d.deap); rel(d.mask_rows); rel(d.ring_off); rel(d.ring_K);
     rel(d.ring_fft); rel(d.ring_twn); rel(d.ring_joff); rel(d.coef); rel(d.band_of); rel(d.bpt_geo); rel(d.bpt_phase);
     rel(d.band_ptr); rel(d.czt_post); rel(d.czt_vhat); rel(d.syn_tab); rel(d.ffts); rel(d.tw);
     rel(d.ring_ctw); rel(d.ring_uw); rel(d.ctw); rel(d.spr_row);
