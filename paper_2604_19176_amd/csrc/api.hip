@@ -64,7 +64,7 @@ static int syn_adj_tiles(const PlanDev& d)
 // LDS of a cosine-transform tile (compile-time length: no twiddles in LDS)
 static size_t dct_tile_lds(const pat_plan* p, int dp)
 {
-    if (p->dev.dct_spec) return sizeof(float2) * (size_t)dp * 2 * p->dev.M;
+    if (p->dev.dct_spec) return sizeof(float2) * (size_t)dp * cfft_padded_len(2 * p->dev.M);
     return fft_tile_lds(dp, p->h_fft_dct);
 }
 

@@ -142,9 +142,20 @@ struct CPlanOf {
     static constexpr CPlan p = make_cplan(N);
 };
 
+// LDS slot of element i of a sequence: with PAD, one spare slot after every 16
+// elements, so that the stores of a radix-16 pass (stride 16 elements) and the
+// power-of-two strides of later passes fall on different banks.  A padded
+// sequence of length N takes cfft_padded_len(N) slots.
+template <bool PAD>
+__device__ __forceinline__ constexpr int cfft_slot(int i)
+{
+    return PAD ? i + (i >> 4) : i;
+}
+__host__ __device__ constexpr int cfft_padded_len(int n) { return n + n / 16; }
+
 // One pass; `active` lanes (lane = 0 .. cfft_lanes(N) - 1 of the sequence)
 // compute, every thread of the workgroup passes the barriers.
-template <int N, int R, int NS, int TWOFF, bool INV>
+template <int N, int R, int NS, int TWOFF, bool INV, bool PAD = false>
 __device__ __forceinline__ void cpass(float2* __restrict__ x, const float2* __restrict__ tw, bool active, int lane)
 {
     constexpr int T = cfft_lanes(N);
@@ -164,12 +175,12 @@ __device__ __forceinline__ void cpass(float2* __restrict__ x, const float2* __re
 #pragma unroll
                 for (int r = 1; r < R; ++r) w[r - 1] = tp[r - 1];
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[i][r] = x[j + r * NB];
+                for (int r = 0; r < R; ++r) v[i][r] = x[cfft_slot<PAD>(j + r * NB)];
 #pragma unroll
                 for (int r = 1; r < R; ++r) v[i][r] = INV ? cmulc(v[i][r], w[r - 1]) : cmul(v[i][r], w[r - 1]);
             } else {
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[i][r] = x[j + r * NB];
+                for (int r = 0; r < R; ++r) v[i][r] = x[cfft_slot<PAD>(j + r * NB)];
             }
             butterfly<R, INV>(v[i]);
         }
@@ -183,7 +194,7 @@ __device__ __forceinline__ void cpass(float2* __restrict__ x, const float2* __re
                 const int k = j % NS;
                 const int dst = (j - k) * R + k;
 #pragma unroll
-                for (int r = 0; r < R; ++r) x[dst + r * NS] = v[i][r];
+                for (int r = 0; r < R; ++r) x[cfft_slot<PAD>(dst + r * NS)] = v[i][r];
             }
         }
     }
@@ -191,13 +202,13 @@ __device__ __forceinline__ void cpass(float2* __restrict__ x, const float2* __re
 }
 
 // Passes S, S+1, ... of the length's plan
-template <int N, bool INV, int S>
+template <int N, bool INV, int S, bool PAD = false>
 __device__ __forceinline__ void cfft_passes(float2* x, const float2* __restrict__ tw, bool active, int lane)
 {
     constexpr CPlan P = CPlanOf<N>::p;
     if constexpr (S < P.np) {
-        cpass<N, P.rad[S], P.ns[S], P.twoff[S], INV>(x, tw, active, lane);
-        cfft_passes<N, INV, S + 1>(x, tw, active, lane);
+        cpass<N, P.rad[S], P.ns[S], P.twoff[S], INV, PAD>(x, tw, active, lane);
+        cfft_passes<N, INV, S + 1, PAD>(x, tw, active, lane);
     }
 }
 

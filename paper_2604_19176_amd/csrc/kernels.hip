@@ -1357,7 +1357,8 @@ __device__ __forceinline__ void dct_spec_tile(const PlanDev& d, const WsLayout& 
     const float w1 = d0 + 1 < D ? 1.f : 0.f;
     // D even: every pair's two values sit at an 8-byte aligned address of each row
     const bool pair2 = (D & 1) == 0;
-    float2* x = sm + (size_t)min(sq, DP - 1) * N2;
+    constexpr int NP2 = cfft_padded_len(N2);  // LDS slots per pair (padded sequence)
+    float2* x = sm + (size_t)min(sq, DP - 1) * NP2;
     const float2* __restrict__ tw = d.ctw + d.dct_ctw;
     if (!adj && threadIdx.x < 64) {
         const float m = wave0_fixed_sum(red, n_mass);
@@ -1414,7 +1415,7 @@ __device__ __forceinline__ void dct_spec_tile(const PlanDev& d, const WsLayout& 
             const int j = lane + i * T;
             if (NB0 % T == 0 || i + 1 < RND0 || j < NB0) {
 #pragma unroll
-                for (int r = 0; r < R0; ++r) x[j * R0 + r] = v[i][r];
+                for (int r = 0; r < R0; ++r) x[cfft_slot<true>(j * R0 + r)] = v[i][r];
             }
         }
     }
@@ -1441,7 +1442,7 @@ __device__ __forceinline__ void dct_spec_tile(const PlanDev& d, const WsLayout& 
         red[d0] = t0;
         if (d0 + 1 < D) red[d0 + 1] = t1;
     }
-    cfft_passes<N2, false, 1>(x, tw, active, lane);
+    cfft_passes<N2, false, 1, true>(x, tw, active, lane);
     if (adj) {
         // -> hT [nlam][D]: row by row, the workgroup's pairs side by side
         const float rcp = 1.0f / (float)npw;
@@ -1450,7 +1451,7 @@ __device__ __forceinline__ void dct_spec_tile(const PlanDev& d, const WsLayout& 
             [&](int e) {
                 int q, p;
                 fdivmod(e, npw, rcp, q, p);
-                const float2 a = sm[p * N2 + q + 1], c = sm[p * N2 + N2 - q - 1];
+                const float2 a = sm[p * NP2 + cfft_slot<true>(q + 1)], c = sm[p * NP2 + cfft_slot<true>(N2 - q - 1)];
                 return make_float2(0.5f * (a.x + c.x), 0.5f * (a.y + c.y));
             },
             [&](int e, float2 o) {
@@ -1475,7 +1476,7 @@ __device__ __forceinline__ void dct_spec_tile(const PlanDev& d, const WsLayout& 
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int q = min(q0 + lane + u * T, TT - 1);
-            const float2 a = x[q + 1], c = x[N2 - q - 1];
+            const float2 a = x[cfft_slot<true>(q + 1)], c = x[cfft_slot<true>(N2 - q - 1)];
             o[u] = make_float2(0.5f * (a.x + c.x) + add, 0.5f * (a.y + c.y) + add);
         }
 #pragma unroll

@@ -520,7 +520,7 @@ int apply_launch(pat_plan* p, const LaunchCfg& c)
         c.ring_rt < 1 || c.ring_rt > 64 || !gather_shape_ok(c.gat_cb, c.gat_th, c.gat_ib) ||
         !spread_shape_ok(c.spr_cb, c.spr_th, c.spr_ib))
         return PAT_ERR_ARG;
-    const bool dct_ok = d.dct_spec ? (c.dct_dp * sizeof(float2) * 2 * (size_t)d.M <= kLdsMax &&
+    const bool dct_ok = d.dct_spec ? (c.dct_dp * sizeof(float2) * (size_t)cfft_padded_len(2 * d.M) <= kLdsMax &&
                                       c.dct_dp * cfft_lanes(2 * d.M) <= 1024)
                                    : fft_ok(c.dct_dp, sizeof(float2) * 2 * d.M, p->h_fft_dct, twb_bytes(p->h_fft_dct));
     if (!grid_ok(c.col_np) || !grid_ok(c.row_rpb) || !dct_ok) return PAT_ERR_UNSUPPORTED;

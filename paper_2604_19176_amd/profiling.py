@@ -15,6 +15,10 @@ counter value (it reads and writes BYTES each).  The same factors for the
 library's 8-byte scatter copy k_scatter_copy over BYTES (the scattered-store
 pattern of the ring adjoint) are reported beside them.
 
+`python -m paper_2604_19176_amd.profiling counters <csv> --kernel NAME ...`
+prints, for each named kernel at its main launch grid, the mean of every
+counter of a `--pmc` pass per dispatch.
+
 With `--rdreq <csv>`, a third pass counting the L2-to-memory read requests by
 size (`--pmc TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum
 TCC_EA0_RDREQ_sum`), the fetched bytes of each kernel are 32, 64 and 128 times
@@ -183,6 +187,29 @@ def source_hash(path):
     return h.hexdigest()[:16]
 
 
+def counter_means(path, kernels):
+    """{kernel: {counter: mean per dispatch}} at each kernel's main grid (as _counter)."""
+    by = defaultdict(lambda: defaultdict(list))  # kernel -> grid -> [(dispatch, counter, value)]
+    for r in _rows(path):
+        k = _short(r["Kernel_Name"])
+        if k in kernels:
+            by[k][_grid(r)].append((r["Dispatch_Id"], r["Counter_Name"], float(r["Counter_Value"])))
+    out = {}
+    for k in kernels:
+        if k not in by:
+            continue
+        grids = {g: len({dsp for dsp, _, _ in v}) for g, v in by[k].items()}
+        gmax = max(grids)
+        g = max((g for g in grids if 2 * g >= gmax), key=lambda g: (grids[g], g))
+        acc = defaultdict(float)
+        for dsp, c, v in by[k][g]:
+            acc[c] += v
+        out[k] = {c: v / grids[g] for c, v in acc.items()}
+        out[k]["dispatches"] = grids[g]
+        out[k]["grid"] = g
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -197,9 +224,15 @@ def main(argv=None):
     t.add_argument("--batch", type=int, required=True)
     t.add_argument("--source", required=True)
     t.add_argument("--rdreq")
+    c = sub.add_parser("counters")
+    c.add_argument("csv")
+    c.add_argument("--kernel", required=True, nargs="+")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats_table(a.trace, a.stats_csv))
+    elif a.cmd == "counters":
+        json.dump(counter_means(a.csv, a.kernel), sys.stdout, indent=1)
+        print()
     else:
         rd = read_bytes_by_size(a.rdreq) if a.rdreq else None
         d = {"batch": a.batch, "kernels_hash": source_hash(a.source), "calib_bytes": a.calib_bytes,
