@@ -169,8 +169,21 @@ __device__ __forceinline__ void colpass_fwd_tile(const PlanDev& d, const WsLayou
     for (int e = threadIdx.x; e < NP * Ng; e += blockDim.x) sm[e] = make_float2(0.f, 0.f);
     __syncthreads();
     // the tile's columns, masked and deapodised, at rows centred in the padded
-    // column (batched, branch-free loads; columns past N read as zero)
+    // column (batched, branch-free loads; columns past N read as zero).
+    // Endpoint term: h^2 times the masked sum of each column, rows in
+    // kSumClasses classes (row i in class i mod kSumClasses), each summed in
+    // order, then the classes in order (independent of the workgroup size and
+    // of the tiling).  With kSumClasses x CT threads each thread's elements are
+    // one column's rows of one class, in order: the class sums are taken from
+    // the values loaded here; else a second loop reads the columns again.
     const float rcpCT = 1.0f / (float)CT;
+    const bool own_class = (int)blockDim.x == kSumClasses * CT;
+    float csum = 0.f;
+    struct Elt {
+        int i;
+        float v, raw;
+        bool in;
+    };
     fill_batched<4>(
         N * CT,
         [&](int e) {
@@ -179,16 +192,18 @@ __device__ __forceinline__ void colpass_fwd_tile(const PlanDev& d, const WsLayou
             const int j = j0 + jj, jc = min(j, N - 1);
             const int2 mr = d.mask_rows[i];
             const float fv = fb[(size_t)i * N + jc], di = d.deap[i], dj = d.deap[jc];
-            const float v = (j < N && j >= mr.x && j < mr.y) ? fv * di * dj : 0.f;
+            const bool in = j < N && j >= mr.x && j < mr.y;
+            const float v = in ? fv * di * dj : 0.f;
             int pos = i - N / 2;
             if (pos < 0) pos += Ng;
-            return IdxF{2 * ((jj >> 1) * Ng + pos) + (jj & 1), v};
+            return Elt{2 * ((jj >> 1) * Ng + pos) + (jj & 1), v, fv, in};
         },
-        [&](int, IdxF iv) { ((float*)sm)[iv.i] = iv.v; });
-    // endpoint term: h^2 times the masked sum of each column; rows in kSumClasses
-    // classes, each summed in order, then the classes in order (independent of
-    // the workgroup size and of the tiling).  Loads four rows ahead of the sum.
-    for (int t = threadIdx.x; t < kSumClasses * CT; t += blockDim.x) {
+        [&](int, Elt el) {
+            ((float*)sm)[el.i] = el.v;
+            csum = el.in ? csum + el.raw : csum;
+        });
+    if (own_class) red_s[threadIdx.x] = csum;  // class threadIdx.x / CT, column threadIdx.x % CT
+    for (int t = threadIdx.x; !own_class && t < kSumClasses * CT; t += blockDim.x) {
         const int jj = t % CT, c = t / CT, j = j0 + jj, jc = min(j, N - 1);
         float sc = 0.f;
         for (int i0 = c; i0 < N; i0 += 4 * kSumClasses) {
