@@ -115,6 +115,12 @@ constexpr int kCfftSplit = 512;
     X(96) X(108) X(128) X(144) X(162) X(192) X(216) X(243) X(256) X(288) X(324) X(384) X(432) X(486) X(512)
 #define PAT_CFFT_LENGTHS_HI(X) X(576) X(648) X(729) X(768) X(864) X(972) X(1024)
 #define PAT_CFFT_LENGTHS(X) PAT_CFFT_LENGTHS_LO(X) PAT_CFFT_LENGTHS_HI(X)
+// Two-wave lengths of the ring kernels (length group 2)
+#define PAT_CFFT_LENGTHS_HI2(X) X(1152) X(1296) X(1458) X(1536) X(1728) X(1944) X(2048)
+
+// Threads of a ring workgroup of length group G (0: lengths up to kCfftSplit,
+// 1: up to 1024, 2: up to 2048)
+__host__ __device__ constexpr int ring_spec_threads(int G) { return G == 2 ? 2 * kCfftLanes : kCfftLanes; }
 
 // Grid sides Ng with a compile-time transform (2D-FFT passes)
 #define PAT_GRID_LENGTHS(X) X(128) X(256) X(512) X(1024) X(2048)
@@ -128,6 +134,15 @@ __host__ __device__ constexpr bool cfft_len_ok(int n)
 {
 #define PAT_CFFT_CASE_OK(L) if (n == L) return true;
     PAT_CFFT_LENGTHS(PAT_CFFT_CASE_OK)
+#undef PAT_CFFT_CASE_OK
+    return false;
+}
+
+// A length of the ring kernels' two-wave group
+__host__ __device__ constexpr bool cfft_len2_ok(int n)
+{
+#define PAT_CFFT_CASE_OK(L) if (n == L) return true;
+    PAT_CFFT_LENGTHS_HI2(PAT_CFFT_CASE_OK)
 #undef PAT_CFFT_CASE_OK
     return false;
 }
@@ -232,32 +247,32 @@ __device__ __forceinline__ void cfft(float2* x, const float2* __restrict__ tw)
     cfft<N, INV>(x, tw, lane, lane < kCfftLanes);
 }
 
-// Out-of-line instance (one per length and direction), for run-time dispatch.
-template <int N, bool INV>
-__device__ __forceinline__ void cfft_call(float2* x, const float2* __restrict__ tw)
+// Run-time length of ring length group G, every thread of the workgroup
+// calling (the length's lanes, cfft_lanes(n), compute).
+template <bool INV, int G>
+__device__ __forceinline__ void cfft_run_wg(float2* x, int n, const float2* __restrict__ tw)
 {
-    cfft<N, INV>(x, tw);
-}
-
-// Run-time length: dispatch to the compile-time transform (n must satisfy
-// cfft_len_ok, and n <= kCfftSplit unless HI; the plan builder only selects
-// such lengths).
-template <bool INV, bool HI>
-__device__ __forceinline__ void cfft_run(float2* x, int n, const float2* __restrict__ tw)
-{
+    const int lane = threadIdx.x;
     switch (n) {
-#define PAT_CFFT_CASE_RUN(L) \
-    case L: cfft_call<L, INV>(x, tw); break;
-        PAT_CFFT_LENGTHS_LO(PAT_CFFT_CASE_RUN)
+#define PAT_CFFT_CASE_WG(L) \
+    case L: cfft<L, INV>(x, tw, lane, lane < cfft_lanes(L)); break;
+        PAT_CFFT_LENGTHS_LO(PAT_CFFT_CASE_WG)
         default:
-            if constexpr (HI) {
+            if constexpr (G >= 1) {
                 switch (n) {
-                    PAT_CFFT_LENGTHS_HI(PAT_CFFT_CASE_RUN)
-                    default: break;
+                    PAT_CFFT_LENGTHS_HI(PAT_CFFT_CASE_WG)
+                    default:
+                        if constexpr (G >= 2) {
+                            switch (n) {
+                                PAT_CFFT_LENGTHS_HI2(PAT_CFFT_CASE_WG)
+                                default: break;
+                            }
+                        }
+                        break;
                 }
             }
             break;
-#undef PAT_CFFT_CASE_RUN
+#undef PAT_CFFT_CASE_WG
     }
 }
 

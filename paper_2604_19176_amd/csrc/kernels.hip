@@ -744,20 +744,20 @@ __device__ __forceinline__ float2 syn_prologue(float2 y1, float2 y1m, float2 y2,
     return make_float2(E.x - O.y, E.y + O.x);
 }
 
-template <int Pn>
+template <int Pn, int T>
 __device__ __forceinline__ void ring_fwd_spec_head(const PlanDev& d, const float2* __restrict__ Fp,
                                                    const RingSpecArgs& a, float2* buf, float2* syn)
 {
     const int lane = threadIdx.x;
-    const bool act = lane < kCfftLanes;
+    const bool act = lane < T;
     // the ring's half-plane values packed as the real sequence q(m) = Re F + Im F
     // (m < Pn), Re F - Im F (m >= Pn), z(t) = q(2t) + i q(2t + 1)
     if (act) {
-        constexpr int RND = (Pn + kCfftLanes - 1) / kCfftLanes;
+        constexpr int RND = (Pn + T - 1) / T;
         float2 v[RND];
 #pragma unroll
         for (int i = 0; i < RND; ++i) {
-            const int t = min(lane + i * kCfftLanes, Pn - 1);
+            const int t = min(lane + i * T, Pn - 1);
             const int m0 = 2 * t, m1 = 2 * t + 1;
             const float2 F0 = Fp[a.off + (m0 < Pn ? m0 : m0 - Pn)];
             const float2 F1 = Fp[a.off + (m1 < Pn ? m1 : m1 - Pn)];
@@ -765,12 +765,12 @@ __device__ __forceinline__ void ring_fwd_spec_head(const PlanDev& d, const float
         }
 #pragma unroll
         for (int i = 0; i < RND; ++i) {
-            const int t = lane + i * kCfftLanes;
-            if (Pn % kCfftLanes == 0 || t < Pn) buf[t] = v[i];
+            const int t = lane + i * T;
+            if (Pn % T == 0 || t < Pn) buf[t] = v[i];
         }
     }
     __syncthreads();
-    cfft<Pn, false>(buf, a.ctwR);
+    cfft<Pn, false>(buf, a.ctwR, lane, lane < cfft_lanes(Pn));
     // a_k = coef_k Q_k for k <= K_n (zero above), in place of Z: the pair (k, Pn - k)
     // shares sm = Z_k + conj Z_{Pn-k}, df = Z_k - conj Z_{Pn-k} and t = w_{2Pn}^k df,
     //   Q_k = sm/2 - (i/2) t,  Q_{Pn-k} = conj(sm)/2 - (i/2) conj(t)
@@ -779,8 +779,8 @@ __device__ __forceinline__ void ring_fwd_spec_head(const PlanDev& d, const float
     if (act) {
         constexpr int PAIRS = Pn / 2 + 1;  // k = 0 .. Pn/2
 #pragma unroll
-        for (int i = 0; i < (PAIRS + kCfftLanes - 1) / kCfftLanes; ++i) {
-            const int k0 = lane + i * kCfftLanes;
+        for (int i = 0; i < (PAIRS + T - 1) / T; ++i) {
+            const int k0 = lane + i * T;
             const int k = min(k0, PAIRS - 1);
             const int kc = k == 0 ? 0 : Pn - k;
             const float2 zk = buf[k];
@@ -792,7 +792,7 @@ __device__ __forceinline__ void ring_fwd_spec_head(const PlanDev& d, const float
             const float2 c1 = a.cf[min(k, a.Kn)], c2 = a.cf[min(kc, a.Kn)];
             const float2 v1 = k <= a.Kn ? cmul(c1, Q1) : make_float2(0.f, 0.f);
             const float2 v2 = kc <= a.Kn ? cmul(c2, Q2) : make_float2(0.f, 0.f);
-            if (PAIRS % kCfftLanes == 0 || k0 < PAIRS) {
+            if (PAIRS % T == 0 || k0 < PAIRS) {
                 buf[k] = v1;
                 if (k != 0 && 2 * k != Pn) buf[kc] = v2;
             }
@@ -809,7 +809,7 @@ __device__ __forceinline__ void ring_fwd_spec_head(const PlanDev& d, const float
     const float2* __restrict__ sw = d.ctw + d.syn_sw;
     const int items = (SH + 1) >> 1;
     if (act) {
-        for (int s = lane; s < items; s += kCfftLanes) {
+        for (int s = lane; s < items; s += T) {
             if (s == 0) {
                 const float2 y0 = mode(0), yh = mode(SH), yq = mode(SH >> 1), y3 = mode(SH + (SH >> 1));
                 syn[0] = syn_prologue(y0, y0, yh, yh, sw[0]);
@@ -824,23 +824,24 @@ __device__ __forceinline__ void ring_fwd_spec_head(const PlanDev& d, const float
     __syncthreads();
 }
 
+template <int T>
 __device__ __forceinline__ void ring_fwd_spec_tail(const PlanDev& d, const float2* buf, float* hn)
 {
     const int lane = threadIdx.x;
-    if (lane < kCfftLanes) {
+    if (lane < T) {
         // detector q is point s q of the P-point grid: Re part at even, Im at odd points
-        for (int q0 = 0; q0 < d.D; q0 += 4 * kCfftLanes) {
+        for (int q0 = 0; q0 < d.D; q0 += 4 * T) {
             float v[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int q = min(q0 + lane + u * kCfftLanes, d.D - 1);
+                const int q = min(q0 + lane + u * T, d.D - 1);
                 const int j = q * d.fold_s;
                 const float2 z = buf[j >> 1];
                 v[u] = (j & 1) ? z.y : z.x;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int q = q0 + lane + u * kCfftLanes;
+                const int q = q0 + lane + u * T;
                 if (q < d.D) hn[q] = v[u];
             }
         }
@@ -848,7 +849,7 @@ __device__ __forceinline__ void ring_fwd_spec_tail(const PlanDev& d, const float
     __syncthreads();
 }
 
-template <bool HI>
+template <int G>
 __device__ __forceinline__ void ring_fwd_spec_tile(const PlanDev& d, const WsLayout& L, char* wb, int n, float2* buf)
 {
     // one ring per workgroup: a loop over rings would keep every length's
@@ -858,37 +859,46 @@ __device__ __forceinline__ void ring_fwd_spec_tile(const PlanDev& d, const WsLay
     float2* syn = buf + d.npsi_max / 2;  // the synthesis input after the ring buffer
     const RingSpecArgs a = ring_spec_args(d, n);
     const int Pn = d.ring_off[n + 1] - a.off;
+    constexpr int T = ring_spec_threads(G);
     switch (Pn) {
 #define PAT_RING_FWD_HEAD(LEN) \
-    case LEN: ring_fwd_spec_head<LEN>(d, Fp, a, buf, syn); break;
+    case LEN: ring_fwd_spec_head<LEN, T>(d, Fp, a, buf, syn); break;
         PAT_CFFT_LENGTHS_LO(PAT_RING_FWD_HEAD)
         default:
-            if constexpr (HI) {
+            if constexpr (G >= 1) {
                 switch (Pn) {
                     PAT_CFFT_LENGTHS_HI(PAT_RING_FWD_HEAD)
-                    default: break;
+                    default:
+                        if constexpr (G >= 2) {
+                            switch (Pn) {
+                                PAT_CFFT_LENGTHS_HI2(PAT_RING_FWD_HEAD)
+                                default: break;
+                            }
+                        }
+                        break;
                 }
             }
             break;
 #undef PAT_RING_FWD_HEAD
     }
-    cfft_run<true, HI>(syn, d.fold_P >> 1, d.ctw + d.syn_ctw);
-    ring_fwd_spec_tail(d, syn, hT + (size_t)n * d.D);
+    cfft_run_wg<true, G>(syn, d.fold_P >> 1, d.ctw + d.syn_ctw);
+    ring_fwd_spec_tail<T>(d, syn, hT + (size_t)n * d.D);
 }
 
+template <int T>
 __device__ __forceinline__ void ring_adj_spec_head(const PlanDev& d, const float* __restrict__ hn, float2* buf)
 {
     const int lane = threadIdx.x;
     const int SH = d.fold_P >> 1, fs = d.fold_s, D = d.D;
     // the detector values at points s q of the P-point grid (zero between), packed
     // as z(t) = h(2t) + i h(2t + 1)
-    if (lane < kCfftLanes) {
+    if (lane < T) {
         const float rcp_s = __builtin_amdgcn_rcpf((float)fs);
-        for (int t0 = 0; t0 < SH; t0 += 2 * kCfftLanes) {
+        for (int t0 = 0; t0 < SH; t0 += 2 * T) {
             float2 v[2];
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                const int t = min(t0 + lane + u * kCfftLanes, SH - 1);
+                const int t = min(t0 + lane + u * T, SH - 1);
                 float h[2];
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
@@ -902,7 +912,7 @@ __device__ __forceinline__ void ring_adj_spec_head(const PlanDev& d, const float
             }
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                const int t = t0 + lane + u * kCfftLanes;
+                const int t = t0 + lane + u * T;
                 if (t < SH) buf[t] = v[u];
             }
         }
@@ -910,20 +920,20 @@ __device__ __forceinline__ void ring_adj_spec_head(const PlanDev& d, const float
     __syncthreads();
 }
 
-template <int Pn>
+template <int Pn, int T>
 __device__ __forceinline__ void ring_adj_spec_tail(const PlanDev& d, const RingSpecArgs& a, float2* syn,
                                                    float2* buf, float2* Hb)
 {
     const int lane = threadIdx.x;
-    const bool act = lane < kCfftLanes;
+    const bool act = lane < T;
     const int Pf = d.fold_P, SH = Pf >> 1;
     const float2* __restrict__ sw = d.ctw + d.syn_sw;
     // the ring points' band-order slots, for the stores at the end: loaded now,
     // in flight during the transforms
-    constexpr int RO = (Pn + kCfftLanes - 1) / kCfftLanes;
+    constexpr int RO = (Pn + T - 1) / T;
     int slot[RO];
 #pragma unroll
-    for (int i = 0; i < RO; ++i) slot[i] = d.band_of[a.off + min(lane + i * kCfftLanes, Pn - 1)];
+    for (int i = 0; i < RO; ++i) slot[i] = d.band_of[a.off + min(lane + i * T, Pn - 1)];
     // y~ at synthesis index q (0 <= q <= P/2) from the half-length transform Z,
     // in place of Z (slot P/2 after it): the pair (s, SH - s) shares
     // sm = Z_s + conj Z_{SH-s}, df = Z_s - conj Z_{SH-s}, t = w_P^s df,
@@ -933,7 +943,7 @@ __device__ __forceinline__ void ring_adj_spec_tail(const PlanDev& d, const RingS
     float2* ys = syn;
     if (act) {
         const int PAIRS = SH / 2 + 1;  // s = 0 .. SH/2
-        for (int s = lane; s < PAIRS; s += kCfftLanes) {
+        for (int s = lane; s < PAIRS; s += T) {
             const int sc = s == 0 ? 0 : SH - s;
             const float2 zk = ys[s];
             const float2 zc = cconj(ys[sc]);
@@ -968,9 +978,9 @@ __device__ __forceinline__ void ring_adj_spec_tail(const PlanDev& d, const RingS
     constexpr int items = (Pn + 1) / 2;
     if (act) {
 #pragma unroll
-        for (int i = 0; i < (items + kCfftLanes - 1) / kCfftLanes; ++i) {
-            const int u = lane + i * kCfftLanes;
-            if (items % kCfftLanes != 0 && u >= items) break;
+        for (int i = 0; i < (items + T - 1) / T; ++i) {
+            const int u = lane + i * T;
+            if (items % T != 0 && u >= items) break;
             if (u == 0) {
                 const float2 q0 = qmode(0);
                 buf[0] = herm(0, q0, q0);
@@ -986,13 +996,13 @@ __device__ __forceinline__ void ring_adj_spec_tail(const PlanDev& d, const RingS
         }
     }
     __syncthreads();
-    cfft<Pn, true>(buf, a.ctwR);
+    cfft<Pn, true>(buf, a.ctwR, lane, lane < cfft_lanes(Pn));
     // q~(m): m = 2t -> Re z_t, m = 2t + 1 -> Im z_t;  F~_h(l) = (q~(l) + q~(l+Pn)) + i (q~(l) - q~(l+Pn)),
     // stored in band order (the spread applies the conjugate half-pixel phase)
     if (act) {
 #pragma unroll
         for (int i = 0; i < RO; ++i) {
-            const int l0 = lane + i * kCfftLanes;
+            const int l0 = lane + i * T;
             const int l = min(l0, Pn - 1);
             const float2 z1 = buf[l >> 1];
             const float av = (l & 1) ? z1.y : z1.x;
@@ -1000,31 +1010,39 @@ __device__ __forceinline__ void ring_adj_spec_tail(const PlanDev& d, const RingS
             const float2 z2 = buf[m >> 1];
             const float cv = (m & 1) ? z2.y : z2.x;
             const float2 Fh = make_float2(av + cv, av - cv);
-            if (Pn % kCfftLanes == 0 || l0 < Pn) Hb[slot[i]] = Fh;
+            if (Pn % T == 0 || l0 < Pn) Hb[slot[i]] = Fh;
         }
     }
     __syncthreads();
 }
 
-template <bool HI>
+template <int G>
 __device__ __forceinline__ void ring_adj_spec_tile(const PlanDev& d, const WsLayout& L, char* wb, int n, float2* buf)
 {
     const float* hT = (const float*)(wb + L.hdet);  // [nlam][D]
     float2* Hb = (float2*)(wb + L.polar);
     float2* syn = buf + d.npsi_max / 2;  // the synthesis transform after the ring buffer
-    ring_adj_spec_head(d, hT + (size_t)n * d.D, syn);
-    cfft_run<false, HI>(syn, d.fold_P >> 1, d.ctw + d.syn_ctw);
+    constexpr int T = ring_spec_threads(G);
+    ring_adj_spec_head<T>(d, hT + (size_t)n * d.D, syn);
+    cfft_run_wg<false, G>(syn, d.fold_P >> 1, d.ctw + d.syn_ctw);
     const RingSpecArgs a = ring_spec_args(d, n);
     const int Pn = d.ring_off[n + 1] - a.off;
     switch (Pn) {
 #define PAT_RING_ADJ_TAIL(LEN) \
-    case LEN: ring_adj_spec_tail<LEN>(d, a, syn, buf, Hb); break;
+    case LEN: ring_adj_spec_tail<LEN, T>(d, a, syn, buf, Hb); break;
         PAT_CFFT_LENGTHS_LO(PAT_RING_ADJ_TAIL)
         default:
-            if constexpr (HI) {
+            if constexpr (G >= 1) {
                 switch (Pn) {
                     PAT_CFFT_LENGTHS_HI(PAT_RING_ADJ_TAIL)
-                    default: break;
+                    default:
+                        if constexpr (G >= 2) {
+                            switch (Pn) {
+                                PAT_CFFT_LENGTHS_HI2(PAT_RING_ADJ_TAIL)
+                                default: break;
+                            }
+                        }
+                        break;
                 }
             }
             break;
@@ -2168,29 +2186,31 @@ __global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu
     if (!batch_item(bt, kStRing, i, tile)) return;
     const BatchInst& I = bt.inst[i];
     const PlanDev d = I.d;
-    if (d.ring_spec) ring_fwd_spec_tile<true>(d, I.L, ws + I.ws_off, tile, sm);
+    if (d.ring_spec && d.ring_spec_grp == 2) ring_fwd_spec_tile<2>(d, I.L, ws + I.ws_off, tile, sm);
+    else if (d.ring_spec) ring_fwd_spec_tile<1>(d, I.L, ws + I.ws_off, tile, sm);
     else ring_fwd_tile(d, I.L, ws + I.ws_off, tile, I.ring_rt, sm);
 }
 
-// Ring kernels of plans with compile-time transforms: one wave and one ring
-// per workgroup (ring_rt does not apply), largest rings first.  HI: built for
-// every compile-time length (else only for lengths up to kCfftSplit).
-template <bool HI>
-__global__ __launch_bounds__(kCfftLanes) void k_ring_fwd_spec(PlanDev d, WsLayout L, InstPtrs wsp, int batch)
+// Ring kernels of plans with compile-time transforms: one ring per workgroup
+// of ring_spec_threads(G) threads (ring_rt does not apply), largest rings
+// first.  Length group G (cfft.hpp): 0 up to kCfftSplit, 1 up to 1024 (one
+// wave), 2 up to 2048 (two waves).
+template <int G>
+__global__ __launch_bounds__(ring_spec_threads(G)) void k_ring_fwd_spec(PlanDev d, WsLayout L, InstPtrs wsp, int batch)
 {
     extern __shared__ float2 sm[];
     int b, n;
     if (!ring_item<false>(blockIdx.x, d.nlam, batch, b, n)) return;
-    ring_fwd_spec_tile<HI>(d, L, wsp.ws + (size_t)b * wsp.stride, n, sm);
+    ring_fwd_spec_tile<G>(d, L, wsp.ws + (size_t)b * wsp.stride, n, sm);
 }
 
-template <bool HI>
-__global__ __launch_bounds__(kCfftLanes) void k_ring_adj_spec(PlanDev d, WsLayout L, InstPtrs wsp, int batch)
+template <int G>
+__global__ __launch_bounds__(ring_spec_threads(G)) void k_ring_adj_spec(PlanDev d, WsLayout L, InstPtrs wsp, int batch)
 {
     extern __shared__ float2 sm[];
     int b, n;
     if (!ring_item<true>(blockIdx.x, d.nlam, batch, b, n)) return;
-    ring_adj_spec_tile<HI>(d, L, wsp.ws + (size_t)b * wsp.stride, n, sm);
+    ring_adj_spec_tile<G>(d, L, wsp.ws + (size_t)b * wsp.stride, n, sm);
 }
 
 __global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_ring_adj(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
@@ -2208,7 +2228,8 @@ __global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu
     if (!batch_item(bt, kStRing, i, tile)) return;
     const BatchInst& I = bt.inst[i];
     const PlanDev d = I.d;
-    if (d.ring_spec) ring_adj_spec_tile<true>(d, I.L, ws + I.ws_off, tile, sm);
+    if (d.ring_spec && d.ring_spec_grp == 2) ring_adj_spec_tile<2>(d, I.L, ws + I.ws_off, tile, sm);
+    else if (d.ring_spec) ring_adj_spec_tile<1>(d, I.L, ws + I.ws_off, tile, sm);
     else ring_adj_tile(d, I.L, ws + I.ws_off, tile, I.ring_rt, sm);
 }
 

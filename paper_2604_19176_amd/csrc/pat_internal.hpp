@@ -131,7 +131,7 @@ struct PlanDev {
     // Npsi(n)/2 and the half-length synthesis P/2 have one (folded synthesis
     // of even length P, no explicit angles)
     int ring_spec;
-    int ring_spec_hi;       // 1: some ring or synthesis length exceeds kCfftSplit
+    int ring_spec_grp;      // length group of the ring and synthesis lengths (cfft.hpp, ring_spec_threads)
     int syn_ctw;            // offset in ctw of the synthesis transform's table (length P/2)
     int syn_sw;             // offset in ctw of w_P^s = e^{-2 pi i s/P}, s = 0..P/2
     int dct_spec;           // 1: cosine transform of compile-time length 2M (cfft.hpp)

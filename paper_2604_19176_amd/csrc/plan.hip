@@ -800,15 +800,16 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     std::vector<int> ringCtw(nlam, 0), ringUw(nlam, 0);
     std::map<int, int> tab_of, uw_of;
     d.ring_spec = 0;
-    d.ring_spec_hi = 0;
+    d.ring_spec_grp = 0;
     {
         const int SH = dv.P / 2;
-        bool ok = !dv.dense && dv.P > 0 && d.syn_half && cfft_len_ok(SH);
-        for (int n = 0; n < nlam && ok; ++n) ok = cfft_len_ok(ringN[n] / 2);
+        auto len_ok = [](int L) { return cfft_len_ok(L) || cfft_len2_ok(L); };
+        bool ok = !dv.dense && dv.P > 0 && d.syn_half && len_ok(SH);
+        for (int n = 0; n < nlam && ok; ++n) ok = len_ok(ringN[n] / 2);
         if (ok) {
             int lmax = SH;
             for (int n = 0; n < nlam; ++n) lmax = std::max(lmax, ringN[n] / 2);
-            d.ring_spec_hi = lmax > kCfftSplit;
+            d.ring_spec_grp = lmax > 1024 ? 2 : (lmax > kCfftSplit ? 1 : 0);
         }
         {
             auto add_cfft = [&](int L) {
@@ -849,7 +850,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
                     ringUw[n] = it->second;
                 }
                 d.ring_spec = 1;
-                p->thr_ring = kCfftLanes;
+                p->thr_ring = ring_spec_threads(d.ring_spec_grp);
             }
             // the cosine transform: compile-time length 2M for the lengths the
             // kernels instantiate
