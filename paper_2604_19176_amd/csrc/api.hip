@@ -143,11 +143,13 @@ extern "C" int pat_forward(const pat_plan* p, const float* f, float* g, int batc
         const int rt = d.ring_spec ? 1 : c.ring_rt;  // compile-time ring kernels: one ring per workgroup
         const dim3 grid(xcd_grid((d.nlam + rt - 1) / rt * batch)), blk(p->thr_ring);
         if (d.ring_spec && d.ring_spec_grp == 2)
-            hipLaunchKernelGGL(k_ring_fwd_spec<2>, grid, blk, p->lds_ring, st, d, p->ws, wsp, batch);
+            hipLaunchKernelGGL((k_ring_fwd_spec<2, 1>), grid, blk, p->lds_ring, st, d, p->ws, wsp, batch);
         else if (d.ring_spec && d.ring_spec_grp == 1)
-            hipLaunchKernelGGL(k_ring_fwd_spec<1>, grid, blk, p->lds_ring, st, d, p->ws, wsp, batch);
+            hipLaunchKernelGGL((k_ring_fwd_spec<1, 1>), grid, blk, p->lds_ring, st, d, p->ws, wsp, batch);
+        else if (d.ring_spec && p->thr_ring == ring_spec_threads(0, 2))
+            hipLaunchKernelGGL((k_ring_fwd_spec<0, 2>), grid, blk, p->lds_ring, st, d, p->ws, wsp, batch);
         else if (d.ring_spec)
-            hipLaunchKernelGGL(k_ring_fwd_spec<0>, grid, blk, p->lds_ring, st, d, p->ws, wsp, batch);
+            hipLaunchKernelGGL((k_ring_fwd_spec<0, 1>), grid, blk, p->lds_ring, st, d, p->ws, wsp, batch);
         else hipLaunchKernelGGL(k_ring_fwd, grid, blk, p->lds_ring, st, d, p->ws, wsp, c.ring_rt, batch);
     }
     if ((rc = check_launch())) return rc;
@@ -191,11 +193,13 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
         const int rt = d.ring_spec ? 1 : c.ring_rt;
         const dim3 grid(xcd_grid((d.nlam + rt - 1) / rt * batch)), blk(p->thr_ring);
         if (d.ring_spec && d.ring_spec_grp == 2)
-            hipLaunchKernelGGL(k_ring_adj_spec<2>, grid, blk, p->lds_ring, st, d, p->ws, wsp, batch);
+            hipLaunchKernelGGL((k_ring_adj_spec<2, 1>), grid, blk, p->lds_ring, st, d, p->ws, wsp, batch);
         else if (d.ring_spec && d.ring_spec_grp == 1)
-            hipLaunchKernelGGL(k_ring_adj_spec<1>, grid, blk, p->lds_ring, st, d, p->ws, wsp, batch);
+            hipLaunchKernelGGL((k_ring_adj_spec<1, 1>), grid, blk, p->lds_ring, st, d, p->ws, wsp, batch);
+        else if (d.ring_spec && p->thr_ring == ring_spec_threads(0, 2))
+            hipLaunchKernelGGL((k_ring_adj_spec<0, 2>), grid, blk, p->lds_ring, st, d, p->ws, wsp, batch);
         else if (d.ring_spec)
-            hipLaunchKernelGGL(k_ring_adj_spec<0>, grid, blk, p->lds_ring, st, d, p->ws, wsp, batch);
+            hipLaunchKernelGGL((k_ring_adj_spec<0, 1>), grid, blk, p->lds_ring, st, d, p->ws, wsp, batch);
         else hipLaunchKernelGGL(k_ring_adj, grid, blk, p->lds_ring, st, d, p->ws, wsp, c.ring_rt, batch);
     }
     if ((rc = check_launch())) return rc;

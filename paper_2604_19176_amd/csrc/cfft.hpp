@@ -119,8 +119,8 @@ constexpr int kCfftSplit = 512;
 #define PAT_CFFT_LENGTHS_HI2(X) X(1152) X(1296) X(1458) X(1536) X(1728) X(1944) X(2048)
 
 // Threads of a ring workgroup of length group G (0: lengths up to kCfftSplit,
-// 1: up to 1024, 2: up to 2048)
-__host__ __device__ constexpr int ring_spec_threads(int G) { return G == 2 ? 2 * kCfftLanes : kCfftLanes; }
+// 1: up to 1024, 2: up to 2048), W waves per ring in the one-wave groups
+__host__ __device__ constexpr int ring_spec_threads(int G, int W = 1) { return G == 2 ? 2 * kCfftLanes : W * kCfftLanes; }
 
 // Grid sides Ng with a compile-time transform (2D-FFT passes)
 #define PAT_GRID_LENGTHS(X) X(128) X(256) X(512) X(1024) X(2048)
@@ -168,12 +168,13 @@ __device__ __forceinline__ constexpr int cfft_slot(int i)
 }
 __host__ __device__ constexpr int cfft_padded_len(int n) { return n + n / 16; }
 
-// One pass; `active` lanes (lane = 0 .. cfft_lanes(N) - 1 of the sequence)
-// compute, every thread of the workgroup passes the barriers.
-template <int N, int R, int NS, int TWOFF, bool INV, bool PAD = false>
+// One pass; `active` lanes (lane = 0 .. T - 1 of the sequence) compute,
+// every thread of the workgroup passes the barriers.  T >= cfft_lanes(N): the
+// same butterflies in the same order, spread over more lanes (the plan, and
+// so every result, depends on N only).
+template <int N, int R, int NS, int TWOFF, bool INV, bool PAD = false, int T = cfft_lanes(N)>
 __device__ __forceinline__ void cpass(float2* __restrict__ x, const float2* __restrict__ tw, bool active, int lane)
 {
-    constexpr int T = cfft_lanes(N);
     constexpr int NB = N / R;
     constexpr int RND = (NB + T - 1) / T;
     float2 v[RND][R];
@@ -217,25 +218,26 @@ __device__ __forceinline__ void cpass(float2* __restrict__ x, const float2* __re
 }
 
 // Passes S, S+1, ... of the length's plan
-template <int N, bool INV, int S, bool PAD = false>
+template <int N, bool INV, int S, bool PAD = false, int T = cfft_lanes(N)>
 __device__ __forceinline__ void cfft_passes(float2* x, const float2* __restrict__ tw, bool active, int lane)
 {
     constexpr CPlan P = CPlanOf<N>::p;
     if constexpr (S < P.np) {
-        cpass<N, P.rad[S], P.ns[S], P.twoff[S], INV, PAD>(x, tw, active, lane);
-        cfft_passes<N, INV, S + 1, PAD>(x, tw, active, lane);
+        cpass<N, P.rad[S], P.ns[S], P.twoff[S], INV, PAD, T>(x, tw, active, lane);
+        cfft_passes<N, INV, S + 1, PAD, T>(x, tw, active, lane);
     }
 }
 
 // In-place transform of x[0..N) in LDS (forward: e^{-2 pi i jk/N}, inverse:
 // e^{+2 pi i jk/N}, unnormalised); `tw` = the length's table.  Every thread of
-// the workgroup calls it (barriers); `active` threads, lanes 0 ..
-// cfft_lanes(N) - 1 of the sequence, compute.
-template <int N, bool INV>
+// the workgroup calls it (barriers); `active` threads, lanes 0 .. T - 1 of
+// the sequence (T >= cfft_lanes(N)), compute.
+template <int N, bool INV, int T = cfft_lanes(N)>
 __device__ __forceinline__ void cfft(float2* x, const float2* __restrict__ tw, int lane, bool active)
 {
     static_assert(CPlanOf<N>::p.np > 0, "no compile-time plan for this length");
-    cfft_passes<N, INV, 0>(x, tw, active, lane);
+    static_assert(T >= cfft_lanes(N), "at least the length's lanes");
+    cfft_passes<N, INV, 0, false, T>(x, tw, active, lane);
 }
 
 // One-wave lengths, computed by lanes 0..63 of wave 0.
@@ -247,15 +249,18 @@ __device__ __forceinline__ void cfft(float2* x, const float2* __restrict__ tw)
     cfft<N, INV>(x, tw, lane, lane < kCfftLanes);
 }
 
-// Run-time length of ring length group G, every thread of the workgroup
-// calling (the length's lanes, cfft_lanes(n), compute).
-template <bool INV, int G>
+// Lanes that transform a sequence of length n in a workgroup of T threads
+__host__ __device__ constexpr int cfft_wg_lanes(int n, int T) { return T > cfft_lanes(n) ? T : cfft_lanes(n); }
+
+// Run-time length of ring length group G in a workgroup of T threads, every
+// thread calling (cfft_wg_lanes(n, T) lanes compute).
+template <bool INV, int G, int T>
 __device__ __forceinline__ void cfft_run_wg(float2* x, int n, const float2* __restrict__ tw)
 {
     const int lane = threadIdx.x;
     switch (n) {
 #define PAT_CFFT_CASE_WG(L) \
-    case L: cfft<L, INV>(x, tw, lane, lane < cfft_lanes(L)); break;
+    case L: cfft<L, INV, cfft_wg_lanes(L, T)>(x, tw, lane, lane < cfft_wg_lanes(L, T)); break;
         PAT_CFFT_LENGTHS_LO(PAT_CFFT_CASE_WG)
         default:
             if constexpr (G >= 1) {

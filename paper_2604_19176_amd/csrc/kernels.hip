@@ -770,7 +770,7 @@ __device__ __forceinline__ void ring_fwd_spec_head(const PlanDev& d, const float
         }
     }
     __syncthreads();
-    cfft<Pn, false>(buf, a.ctwR, lane, lane < cfft_lanes(Pn));
+    cfft<Pn, false, cfft_wg_lanes(Pn, T)>(buf, a.ctwR, lane, lane < cfft_wg_lanes(Pn, T));
     // a_k = coef_k Q_k for k <= K_n (zero above), in place of Z: the pair (k, Pn - k)
     // shares sm = Z_k + conj Z_{Pn-k}, df = Z_k - conj Z_{Pn-k} and t = w_{2Pn}^k df,
     //   Q_k = sm/2 - (i/2) t,  Q_{Pn-k} = conj(sm)/2 - (i/2) conj(t)
@@ -849,7 +849,7 @@ __device__ __forceinline__ void ring_fwd_spec_tail(const PlanDev& d, const float
     __syncthreads();
 }
 
-template <int G>
+template <int G, int W>
 __device__ __forceinline__ void ring_fwd_spec_tile(const PlanDev& d, const WsLayout& L, char* wb, int n, float2* buf)
 {
     // one ring per workgroup: a loop over rings would keep every length's
@@ -859,7 +859,7 @@ __device__ __forceinline__ void ring_fwd_spec_tile(const PlanDev& d, const WsLay
     float2* syn = buf + d.npsi_max / 2;  // the synthesis input after the ring buffer
     const RingSpecArgs a = ring_spec_args(d, n);
     const int Pn = d.ring_off[n + 1] - a.off;
-    constexpr int T = ring_spec_threads(G);
+    constexpr int T = ring_spec_threads(G, W);
     switch (Pn) {
 #define PAT_RING_FWD_HEAD(LEN) \
     case LEN: ring_fwd_spec_head<LEN, T>(d, Fp, a, buf, syn); break;
@@ -881,7 +881,7 @@ __device__ __forceinline__ void ring_fwd_spec_tile(const PlanDev& d, const WsLay
             break;
 #undef PAT_RING_FWD_HEAD
     }
-    cfft_run_wg<true, G>(syn, d.fold_P >> 1, d.ctw + d.syn_ctw);
+    cfft_run_wg<true, G, T>(syn, d.fold_P >> 1, d.ctw + d.syn_ctw);
     ring_fwd_spec_tail<T>(d, syn, hT + (size_t)n * d.D);
 }
 
@@ -996,7 +996,7 @@ __device__ __forceinline__ void ring_adj_spec_tail(const PlanDev& d, const RingS
         }
     }
     __syncthreads();
-    cfft<Pn, true>(buf, a.ctwR, lane, lane < cfft_lanes(Pn));
+    cfft<Pn, true, cfft_wg_lanes(Pn, T)>(buf, a.ctwR, lane, lane < cfft_wg_lanes(Pn, T));
     // q~(m): m = 2t -> Re z_t, m = 2t + 1 -> Im z_t;  F~_h(l) = (q~(l) + q~(l+Pn)) + i (q~(l) - q~(l+Pn)),
     // stored in band order (the spread applies the conjugate half-pixel phase)
     if (act) {
@@ -1016,15 +1016,15 @@ __device__ __forceinline__ void ring_adj_spec_tail(const PlanDev& d, const RingS
     __syncthreads();
 }
 
-template <int G>
+template <int G, int W>
 __device__ __forceinline__ void ring_adj_spec_tile(const PlanDev& d, const WsLayout& L, char* wb, int n, float2* buf)
 {
     const float* hT = (const float*)(wb + L.hdet);  // [nlam][D]
     float2* Hb = (float2*)(wb + L.polar);
     float2* syn = buf + d.npsi_max / 2;  // the synthesis transform after the ring buffer
-    constexpr int T = ring_spec_threads(G);
+    constexpr int T = ring_spec_threads(G, W);
     ring_adj_spec_head<T>(d, hT + (size_t)n * d.D, syn);
-    cfft_run_wg<false, G>(syn, d.fold_P >> 1, d.ctw + d.syn_ctw);
+    cfft_run_wg<false, G, T>(syn, d.fold_P >> 1, d.ctw + d.syn_ctw);
     const RingSpecArgs a = ring_spec_args(d, n);
     const int Pn = d.ring_off[n + 1] - a.off;
     switch (Pn) {
@@ -2186,31 +2186,33 @@ __global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu
     if (!batch_item(bt, kStRing, i, tile)) return;
     const BatchInst& I = bt.inst[i];
     const PlanDev d = I.d;
-    if (d.ring_spec && d.ring_spec_grp == 2) ring_fwd_spec_tile<2>(d, I.L, ws + I.ws_off, tile, sm);
-    else if (d.ring_spec) ring_fwd_spec_tile<1>(d, I.L, ws + I.ws_off, tile, sm);
+    if (d.ring_spec && d.ring_spec_grp == 2) ring_fwd_spec_tile<2, 1>(d, I.L, ws + I.ws_off, tile, sm);
+    else if (d.ring_spec) ring_fwd_spec_tile<1, 1>(d, I.L, ws + I.ws_off, tile, sm);
     else ring_fwd_tile(d, I.L, ws + I.ws_off, tile, I.ring_rt, sm);
 }
 
 // Ring kernels of plans with compile-time transforms: one ring per workgroup
-// of ring_spec_threads(G) threads (ring_rt does not apply), largest rings
-// first.  Length group G (cfft.hpp): 0 up to kCfftSplit, 1 up to 1024 (one
-// wave), 2 up to 2048 (two waves).
-template <int G>
-__global__ __launch_bounds__(ring_spec_threads(G)) void k_ring_fwd_spec(PlanDev d, WsLayout L, InstPtrs wsp, int batch)
+// of ring_spec_threads(G, W) threads, largest rings first.  Length group G
+// (cfft.hpp): 0 up to kCfftSplit, 1 up to 1024 (one wave), 2 up to 2048 (two
+// waves); W waves per ring in the one-wave groups (the same arithmetic on
+// more lanes: small batches, where a ring's chain of phases is the critical
+// path).
+template <int G, int W>
+__global__ __launch_bounds__(ring_spec_threads(G, W)) void k_ring_fwd_spec(PlanDev d, WsLayout L, InstPtrs wsp, int batch)
 {
     extern __shared__ float2 sm[];
     int b, n;
     if (!ring_item<false>(blockIdx.x, d.nlam, batch, b, n)) return;
-    ring_fwd_spec_tile<G>(d, L, wsp.ws + (size_t)b * wsp.stride, n, sm);
+    ring_fwd_spec_tile<G, W>(d, L, wsp.ws + (size_t)b * wsp.stride, n, sm);
 }
 
-template <int G>
-__global__ __launch_bounds__(ring_spec_threads(G)) void k_ring_adj_spec(PlanDev d, WsLayout L, InstPtrs wsp, int batch)
+template <int G, int W>
+__global__ __launch_bounds__(ring_spec_threads(G, W)) void k_ring_adj_spec(PlanDev d, WsLayout L, InstPtrs wsp, int batch)
 {
     extern __shared__ float2 sm[];
     int b, n;
     if (!ring_item<true>(blockIdx.x, d.nlam, batch, b, n)) return;
-    ring_adj_spec_tile<G>(d, L, wsp.ws + (size_t)b * wsp.stride, n, sm);
+    ring_adj_spec_tile<G, W>(d, L, wsp.ws + (size_t)b * wsp.stride, n, sm);
 }
 
 __global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_ring_adj(PlanDev d, WsLayout L, InstPtrs wsp, int RT, int batch)
@@ -2228,8 +2230,8 @@ __global__ __launch_bounds__(kRingMaxThreads) __attribute__((amdgpu_waves_per_eu
     if (!batch_item(bt, kStRing, i, tile)) return;
     const BatchInst& I = bt.inst[i];
     const PlanDev d = I.d;
-    if (d.ring_spec && d.ring_spec_grp == 2) ring_adj_spec_tile<2>(d, I.L, ws + I.ws_off, tile, sm);
-    else if (d.ring_spec) ring_adj_spec_tile<1>(d, I.L, ws + I.ws_off, tile, sm);
+    if (d.ring_spec && d.ring_spec_grp == 2) ring_adj_spec_tile<2, 1>(d, I.L, ws + I.ws_off, tile, sm);
+    else if (d.ring_spec) ring_adj_spec_tile<1, 1>(d, I.L, ws + I.ws_off, tile, sm);
     else ring_adj_tile(d, I.L, ws + I.ws_off, tile, I.ring_rt, sm);
 }
 

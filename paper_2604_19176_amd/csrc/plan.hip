@@ -529,6 +529,9 @@ int apply_launch(pat_plan* p, const LaunchCfg& c)
     p->cfg = c;
     p->cfg.spr_cap = 2 * c.spr_cb;
     p->lds_ring = lr;
+    // compile-time ring kernels: ring_rt >= 2 gives the rings of the short-length
+    // group two waves each (the same arithmetic on more lanes)
+    if (d.ring_spec) p->thr_ring = ring_spec_threads(d.ring_spec_grp, d.ring_spec_grp == 0 && c.ring_rt >= 2 ? 2 : 1);
     p->thr_col = grid_threads(p, c.col_np);
     p->thr_row = grid_threads(p, c.row_rpb);
     p->thr_dct = d.dct_spec ? c.dct_dp * cfft_lanes(2 * d.M) : fft_threads(c.dct_dp, p->h_fft_dct);
