@@ -22,12 +22,16 @@
 namespace pat {
 
 constexpr int kCfftLanes = 64;   // lanes of a one-wave transform
-constexpr int kCfftMax = 2048;   // longest compile-time length
+constexpr int kCfftMax = 8192;   // longest compile-time length
 constexpr int kCfftMaxPasses = 12;
 
-// Lanes that transform one sequence of length n: one wave up to 1024, two
-// waves (one workgroup-wide barrier per pass) above.
-__host__ __device__ constexpr int cfft_lanes(int n) { return n <= 1024 ? kCfftLanes : 2 * kCfftLanes; }
+// Lanes that transform one sequence of length n: one wave up to 1024, then
+// one more wave per doubling (workgroup-wide barriers between passes), 16
+// elements per lane at 2048 .. 8192.
+__host__ __device__ constexpr int cfft_lanes(int n)
+{
+    return n <= 1024 ? kCfftLanes : (n <= 2048 ? 2 * kCfftLanes : (n <= 4096 ? 4 * kCfftLanes : 8 * kCfftLanes));
+}
 
 struct CPlan {
     int np;                       // passes (0: no plan)
@@ -67,8 +71,8 @@ __host__ __device__ constexpr CPlan make_cplan(int n)
     while (m % 2 == 0) { m /= 2; ++x; }
     while (m % 3 == 0) { m /= 3; ++y; }
     if (m != 1) return p;
-    int best[12][8] = {};
-    int choice[12][8] = {};
+    int best[14][9] = {};
+    int choice[14][9] = {};
     for (int i = 0; i <= x; ++i)
         for (int j = 0; j <= y; ++j) {
             choice[i][j] = -1;

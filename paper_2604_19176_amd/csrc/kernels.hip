@@ -1524,7 +1524,7 @@ __device__ __forceinline__ void dct_spec_tile(const PlanDev& d, const WsLayout& 
 }
 
 // Lengths 2M with a compile-time cosine transform
-#define PAT_DCT_LENGTHS(X) X(256) X(512) X(1024) X(2048)
+#define PAT_DCT_LENGTHS(X) X(256) X(512) X(1024) X(2048) X(4096) X(8192)
 
 __device__ __forceinline__ void dct_run(const PlanDev& d, const WsLayout& L, char* wb, float* __restrict__ gout,
                                         const float* __restrict__ gin, int tile, int DP, int adj, int n_mass,

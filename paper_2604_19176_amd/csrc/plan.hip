@@ -858,7 +858,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
             // the cosine transform: compile-time length 2M for the lengths the
             // kernels instantiate
             const int n2 = 2 * dv.M;
-            d.dct_spec = (n2 == 256 || n2 == 512 || n2 == 1024 || n2 == 2048) ? 1 : 0;
+            d.dct_spec = (n2 == 256 || n2 == 512 || n2 == 1024 || n2 == 2048 || n2 == 4096 || n2 == 8192) ? 1 : 0;
             if (d.dct_spec) d.dct_ctw = add_cfft(n2);
             // the 2D-FFT passes: compile-time grid side
             d.grid_spec = grid_len_ok(Ng) ? 1 : 0;

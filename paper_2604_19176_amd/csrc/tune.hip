@@ -25,7 +25,7 @@ const int kRingRt[] = {1, 2, 4};
 const int kDctDp[] = {1, 2, 4, 8};
 // (columns, rows or bands, instances per tile); a candidate whose LDS does not fit is skipped
 const int kGather[][3] = {{64, 8, 4}, {64, 16, 4}, {32, 8, 4}, {64, 4, 4}, {64, 16, 2}, {128, 16, 1},
-                          {64, 8, 1}, {128, 8, 2}, {64, 4, 1}, {32, 16, 4}};
+                          {64, 8, 1}, {128, 8, 2}, {64, 8, 2}, {32, 16, 4}};
 const int kSpread[][3] = {{256, 8, 4}, {192, 8, 4}, {128, 8, 4}, {256, 8, 2}, {128, 8, 2}, {192, 8, 1},
                           {128, 8, 1}, {256, 8, 1}, {64, 8, 4}, {64, 8, 1}};
 
