@@ -172,13 +172,48 @@ __device__ __forceinline__ constexpr int cfft_slot(int i)
 }
 __host__ __device__ constexpr int cfft_padded_len(int n) { return n + n / 16; }
 
-// One pass; `active` lanes (lane = 0 .. T - 1 of the sequence) compute,
-// every thread of the workgroup passes the barriers.  T >= cfft_lanes(N): the
-// same butterflies in the same order, spread over more lanes (the plan, and
-// so every result, depends on N only).
-template <int N, int R, int NS, int TWOFF, bool INV, bool PAD = false, int T = cfft_lanes(N)>
-__device__ __forceinline__ void cpass(float2* __restrict__ x, const float2* __restrict__ tw, bool active, int lane)
+// The twiddles of one pass for a lane's RND butterflies: w^{r k}, r = 1..R-1,
+// k = j mod NS (empty for the pass with NS = 1).
+template <int N, int R, int NS, int T>
+struct PassTw {
+    static constexpr int RND = (N / R + T - 1) / T;
+    float2 w[NS > 1 ? RND : 1][R - 1];
+};
+
+template <int N, int R, int NS, int TWOFF, int T>
+__device__ __forceinline__ void pass_tw_load(PassTw<N, R, NS, T>& pt, const float2* __restrict__ tw, bool active, int lane)
 {
+    constexpr int NB = N / R;
+    constexpr int RND = PassTw<N, R, NS, T>::RND;
+    if constexpr (NS > 1) {
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < RND; ++i) {
+                const int j0 = lane + i * T;
+                const int j = (NB % T == 0 || i + 1 < RND) ? j0 : min(j0, NB - 1);
+                const float2* tp = tw + TWOFF + (j % NS) * (R - 1);
+#pragma unroll
+                for (int r = 1; r < R; ++r) pt.w[i][r - 1] = tp[r - 1];
+            }
+        }
+    }
+}
+
+// Passes S, S+1, ... of the length's plan.  A pass's butterflies read their
+// inputs from LDS (one lane address plus immediate offsets), multiply by the
+// twiddles `cur` (loaded during the previous pass), and, before the barrier
+// that precedes their stores, the lane loads the next pass's twiddles, so
+// that their global-memory latency overlaps the store phase.  `active` lanes
+// (lane = 0 .. T - 1 of the sequence, T >= cfft_lanes(N)) compute, every
+// thread of the workgroup passes the barriers; more lanes run the same
+// butterflies in the same order (the plan, and so every result, depends on N
+// only).
+template <int N, bool INV, int S, bool PAD, int T>
+__device__ __forceinline__ void cfft_passes_tw(float2* __restrict__ x, const float2* __restrict__ tw, bool active,
+                                               int lane, const PassTw<N, CPlanOf<N>::p.rad[S], CPlanOf<N>::p.ns[S], T>& cur)
+{
+    constexpr CPlan P = CPlanOf<N>::p;
+    constexpr int R = P.rad[S], NS = P.ns[S];
     constexpr int NB = N / R;
     constexpr int RND = (NB + T - 1) / T;
     float2 v[RND][R];
@@ -188,47 +223,61 @@ __device__ __forceinline__ void cpass(float2* __restrict__ x, const float2* __re
             const int j0 = lane + i * T;
             // the last round's idle lanes work on the last butterfly (results dropped)
             const int j = (NB % T == 0 || i + 1 < RND) ? j0 : min(j0, NB - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = x[cfft_slot<PAD>(j + r * NB)];
             if constexpr (NS > 1) {
-                const int k = j % NS;
-                const float2* tp = tw + TWOFF + k * (R - 1);
-                float2 w[R - 1];
 #pragma unroll
-                for (int r = 1; r < R; ++r) w[r - 1] = tp[r - 1];
-#pragma unroll
-                for (int r = 0; r < R; ++r) v[i][r] = x[cfft_slot<PAD>(j + r * NB)];
-#pragma unroll
-                for (int r = 1; r < R; ++r) v[i][r] = INV ? cmulc(v[i][r], w[r - 1]) : cmul(v[i][r], w[r - 1]);
-            } else {
-#pragma unroll
-                for (int r = 0; r < R; ++r) v[i][r] = x[cfft_slot<PAD>(j + r * NB)];
+                for (int r = 1; r < R; ++r)
+                    v[i][r] = INV ? cmulc(v[i][r], cur.w[i][r - 1]) : cmul(v[i][r], cur.w[i][r - 1]);
             }
             butterfly<R, INV>(v[i]);
         }
     }
-    __syncthreads();
-    if (active) {
+    if constexpr (S + 1 < P.np) {
+        PassTw<N, P.rad[S + 1], P.ns[S + 1], T> nxt;
+        pass_tw_load<N, P.rad[S + 1], P.ns[S + 1], P.twoff[S + 1], T>(nxt, tw, active, lane);
+        __syncthreads();
+        if (active) {
 #pragma unroll
-        for (int i = 0; i < RND; ++i) {
-            const int j = lane + i * T;
-            if (NB % T == 0 || i + 1 < RND || j < NB) {
-                const int k = j % NS;
-                const int dst = (j - k) * R + k;
+            for (int i = 0; i < RND; ++i) {
+                const int j = lane + i * T;
+                if (NB % T == 0 || i + 1 < RND || j < NB) {
+                    const int k = j % NS;
+                    const int dst = (j - k) * R + k;
 #pragma unroll
-                for (int r = 0; r < R; ++r) x[cfft_slot<PAD>(dst + r * NS)] = v[i][r];
+                    for (int r = 0; r < R; ++r) x[cfft_slot<PAD>(dst + r * NS)] = v[i][r];
+                }
             }
         }
+        __syncthreads();
+        cfft_passes_tw<N, INV, S + 1, PAD, T>(x, tw, active, lane, nxt);
+    } else {
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < RND; ++i) {
+                const int j = lane + i * T;
+                if (NB % T == 0 || i + 1 < RND || j < NB) {
+                    const int k = j % NS;
+                    const int dst = (j - k) * R + k;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) x[cfft_slot<PAD>(dst + r * NS)] = v[i][r];
+                }
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
-// Passes S, S+1, ... of the length's plan
+// Passes S, S+1, ... of the length's plan (the twiddles of pass S loaded here)
 template <int N, bool INV, int S, bool PAD = false, int T = cfft_lanes(N)>
 __device__ __forceinline__ void cfft_passes(float2* x, const float2* __restrict__ tw, bool active, int lane)
 {
     constexpr CPlan P = CPlanOf<N>::p;
     if constexpr (S < P.np) {
-        cpass<N, P.rad[S], P.ns[S], P.twoff[S], INV, PAD, T>(x, tw, active, lane);
-        cfft_passes<N, INV, S + 1, PAD, T>(x, tw, active, lane);
+        PassTw<N, P.rad[S], P.ns[S], T> cur;
+        pass_tw_load<N, P.rad[S], P.ns[S], P.twoff[S], T>(cur, tw, active, lane);
+        cfft_passes_tw<N, INV, S, PAD, T>(x, tw, active, lane, cur);
     }
 }
 

@@ -1424,6 +1424,9 @@ __device__ __forceinline__ void dct_spec_tile(const PlanDev& d, const WsLayout& 
     // transpose) from the same values.
     float s0 = 0.f, s1 = 0.f;
     float2 v[RND0][R0];
+    // the second pass's twiddles, in flight with the inputs
+    PassTw<N2, P.rad[1], P.ns[1], T> tw1;
+    pass_tw_load<N2, P.rad[1], P.ns[1], P.twoff[1], T>(tw1, tw, active, lane);
     if (active) {
 #pragma unroll
         for (int i = 0; i < RND0; ++i) {
@@ -1475,7 +1478,7 @@ __device__ __forceinline__ void dct_spec_tile(const PlanDev& d, const WsLayout& 
         red[d0] = t0;
         if (d0 + 1 < D) red[d0 + 1] = t1;
     }
-    cfft_passes<N2, false, 1, true>(x, tw, active, lane);
+    cfft_passes_tw<N2, false, 1, true, T>(x, tw, active, lane, tw1);
     if (adj) {
         // -> hT [nlam][D]: row by row, the workgroup's pairs side by side
         const float rcp = 1.0f / (float)npw;
