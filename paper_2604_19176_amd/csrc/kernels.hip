@@ -1765,13 +1765,17 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
     // step) is stored, the row of band rb+3 and the points of band rb+1 are
     // fetched, and band rb (points fetched in the previous step) is staged and
     // visited.  Every global load is first waited for one step after it is issued.
+    // With one instance (small batches, registers to spare) the points are
+    // fetched two bands ahead instead (a second register set holds band rb+1):
+    // the band's CSR row is in LDS after the barrier of the step that stores it.
+    constexpr bool AHEAD2 = IB == 1;
     auto slot = [&](int r) { return rows + ((r - band_lo) % 3) * (CB + 10); };
-    BandMeta nm;
-    float4 ng0 = make_float4(0.f, 0.f, 0.f, 0.f), ng1 = ng0;
-    float2 np0 = make_float2(0.f, 0.f), np1 = np0;
-    float2 nh0[IB], nh1[IB];
+    BandMeta nm, qm;
+    float4 ng0 = make_float4(0.f, 0.f, 0.f, 0.f), ng1 = ng0, qg0 = ng0, qg1 = ng0;
+    float2 np0 = make_float2(0.f, 0.f), np1 = np0, qp0 = np0, qp1 = np0;
+    float2 nh0[IB], nh1[IB], qh0[IB], qh1[IB];
 #pragma unroll
-    for (int b = 0; b < IB; ++b) nh0[b] = nh1[b] = make_float2(0.f, 0.f);
+    for (int b = 0; b < IB; ++b) nh0[b] = nh1[b] = qh0[b] = qh1[b] = make_float2(0.f, 0.f);
     int rv[2] = {0, 0};  // CSR row in flight (band rb + 2 at the top of the step of band rb)
     {
         int v[2];
@@ -1787,6 +1791,11 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
     nm = band_meta(slot(band_lo), Ng, C0, CB, active);
     if (e0 < nm.ntot) fetch(nm, e0, ng0, np0, nh0);
     if (e1 < nm.ntot) fetch(nm, e1, ng1, np1, nh1);
+    if (AHEAD2 && band_lo + 1 <= band_hi) {
+        qm = band_meta(slot(band_lo + 1), Ng, C0, CB, active);
+        if (e0 < qm.ntot) fetch(qm, e0, qg0, qp0, qh0);
+        if (e1 < qm.ntot) fetch(qm, e1, qg1, qp1, qh1);
+    }
     for (int rb = band_lo; rb <= band_hi; ++rb) {
         // slot of band rb+2 last held band rb-1, whose row was read two steps ago
         if (rb + 2 <= band_hi) band_row_store(slot(rb + 2), CB, rv);
@@ -1800,7 +1809,13 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
         if (e0 < m.ntot) spread_stage<IB, CAP>(S, e0, g0, rel(m, e0, g0), h0, p0);
         if (e1 < m.ntot) spread_stage<IB, CAP>(S, e1, g1, rel(m, e1, g1), h1, p1);
         __syncthreads();
-        if (rb < band_hi) {  // band rb+1: its CSR row was stored one step ago
+        if constexpr (AHEAD2) {
+            if (rb + 2 <= band_hi) {  // band rb+2: its CSR row was stored at the top of this step
+                nm = band_meta(slot(rb + 2), Ng, C0, CB, active);
+                if (e0 < nm.ntot) fetch(nm, e0, ng0, np0, nh0);
+                if (e1 < nm.ntot) fetch(nm, e1, ng1, np1, nh1);
+            }
+        } else if (rb < band_hi) {  // band rb+1: its CSR row was stored one step ago
             nm = band_meta(slot(rb + 1), Ng, C0, CB, active);
             if (e0 < nm.ntot) fetch(nm, e0, ng0, np0, nh0);
             if (e1 < nm.ntot) fetch(nm, e1, ng1, np1, nh1);
@@ -1832,6 +1847,20 @@ __device__ __forceinline__ void spread_tile(const PlanDev& d, const WsLayout& L,
 #pragma unroll
             for (int k = 0; k < 7; ++k) acc[b][k] = acc[b][k + 1];
             acc[b][7] = make_float2(0.f, 0.f);
+        }
+        if constexpr (AHEAD2) {  // the set of band rb+1 is staged next; band rb+2's waits
+            const BandMeta tm = nm;
+            nm = qm;
+            qm = tm;
+            const float4 t0 = ng0, t1 = ng1;
+            ng0 = qg0; ng1 = qg1; qg0 = t0; qg1 = t1;
+            const float2 u0 = np0, u1 = np1;
+            np0 = qp0; np1 = qp1; qp0 = u0; qp1 = u1;
+#pragma unroll
+            for (int b = 0; b < IB; ++b) {
+                const float2 a0 = nh0[b], a1 = nh1[b];
+                nh0[b] = qh0[b]; nh1[b] = qh1[b]; qh0[b] = a0; qh1[b] = a1;
+            }
         }
     }
     // the 7 rows after the last band: complete after the plan's last band (grid
