@@ -975,23 +975,22 @@ __device__ __forceinline__ void ring_adj_spec_tail(const PlanDev& d, const RingS
         const float2 O = cmulc(csub(av, cv), a.uw[u]);
         return make_float2(E.x - O.y, E.y + O.x);
     };
+    // item u < (Pn + 1)/2 writes slots u and Pn - u; item 0 writes slot 0 and,
+    // for even Pn, slot Pn/2 (one path for every lane: no branch on u, the
+    // loads of all rounds can be issued together)
     constexpr int items = (Pn + 1) / 2;
     if (act) {
 #pragma unroll
         for (int i = 0; i < (items + T - 1) / T; ++i) {
-            const int u = lane + i * T;
-            if (items % T != 0 && u >= items) break;
-            if (u == 0) {
-                const float2 q0 = qmode(0);
-                buf[0] = herm(0, q0, q0);
-                if constexpr ((Pn & 1) == 0) {
-                    const float2 qh = qmode(Pn / 2);
-                    buf[Pn / 2] = herm(Pn / 2, qh, qh);
-                }
-            } else {
-                const float2 qa = qmode(u), qb = qmode(Pn - u);
-                buf[u] = herm(u, qa, qb);
-                buf[Pn - u] = herm(Pn - u, qb, qa);
+            const int u0 = lane + i * T;
+            const bool own = items % T == 0 || u0 < items;
+            const int u = min(u0, items - 1);
+            const int u2 = u == 0 ? ((Pn & 1) == 0 ? Pn / 2 : 0) : Pn - u;  // the second slot
+            const float2 qa = qmode(u), qb = qmode(u2);
+            const float2 ha = herm(u, qa, qb), hb = herm(u2, qb, u == 0 ? qb : qa);
+            if (own) {
+                buf[u] = ha;
+                if (u2 != 0) buf[u2] = hb;
             }
         }
     }
