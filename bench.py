@@ -424,7 +424,7 @@ def large_leg(args, np, torch, pat, dev):
                                "unit": "GB/s",
                                "frac": round(it_bytes * steps / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
-        "parity": parity, "launch": launch,
+        "parity": parity, "launch": launch, "split_batch": plan.split,
     }
     plan.close()
     return out
@@ -519,6 +519,8 @@ def bench_default(args):
         "kernels_ms_single": {k: round(v, 4) for k, v in kms1.items()},
         "kernels_hash": kernels_hash(),
         "launch": launch, "tuned": bool(args.tune),
+        # calls of at least this batch run as two half-batches on two streams (0: never)
+        "split_batch": {"batched": plan.split, "single": plan1.split},
         "cpu_baseline": cpu,
     }
     plan.close()

@@ -113,6 +113,12 @@ size_t pat_workspace_size(const pat_plan* plan, int batch);
 /* g = A f for `batch` images (1 <= batch <= max_batch).
  * f: device [batch][N][N] FP32 (read); g: device [batch][D][T] FP32 (written).
  * ws: device workspace of at least pat_workspace_size(plan, batch) bytes.
+ * The call enqueues its kernels and returns; they are ordered on `stream`.
+ * A call of at least the plan's split batch (pat_plan_set_split) runs the
+ * second half of its instances on a stream the plan owns, forked from and
+ * joined back to `stream` by events, so the call can still be recorded into a
+ * HIP graph from `stream`; calls sharing a plan from several host threads are
+ * serialised for that fork-launch-join sequence only.
  * Errors: PAT_ERR_ARG (null pointer, batch out of range), PAT_ERR_WORKSPACE,
  * PAT_ERR_HIP (launch failure). */
 int  pat_forward(const pat_plan* plan, const float* f, float* g, int batch,
@@ -265,6 +271,19 @@ typedef struct {
 int  pat_plan_get_launch(const pat_plan* plan, pat_launch* out);
 int  pat_plan_set_launch(pat_plan* plan, const pat_launch* cfg);
 
+/* Two-stream calls.  pat_forward / pat_adjoint calls of at least `min_batch`
+ * instances run instances [0, batch/2) on the caller's stream and the rest on
+ * a second stream of the plan, so that one half's kernels occupy the compute
+ * units the other half's last partial waves leave idle.  The outputs are
+ * bitwise those of one stream (every instance runs the same kernels and
+ * tiles).  min_batch 0 or 1 turns it off; the default is 64, and
+ * pat_autotune_plan times calls at its batch both ways and sets min_batch to
+ * that batch if two streams are faster, else to 0.  Calls under per-kernel
+ * timing (pat_profile_enable) always use one stream.
+ * Errors: PAT_ERR_ARG (NULL plan or pointer, min_batch < 0). */
+int  pat_plan_set_split(pat_plan* plan, int min_batch);
+int  pat_plan_get_split(const pat_plan* plan, int* min_batch);
+
 /* Heterogeneous batch: `count` instances, each with its own plan (grid size,
  * detector count and arc, time samples may all differ; a plan may appear
  * several times).  pat_batch_forward / pat_batch_adjoint evaluate every
@@ -308,11 +327,15 @@ int  pat_batch_get_launch(const pat_batch* batch, pat_launch* out);
 int  pat_batch_set_launch(pat_batch* batch, const pat_launch* cfg);
 
 /* Autotuner.  pat_autotune_plan times candidate launch shapes of `plan` at
- * `batch` instances (1 <= batch <= max_batch) on the null stream, choosing each stage's shape by its own measured kernel
- * time, applies the fastest, and records it in the JSON file cache_path
- * under a key made of the geometry, the batch and the device name; when that
- * key is already in the file the stored shapes are applied without timing
- * (an entry the shape checks now reject is tuned again and replaced).
+ * `batch` instances (1 <= batch <= max_batch) on the null stream, choosing
+ * each stage's shape by its own measured kernel time, applies the fastest,
+ * then times whole forward + adjoint calls on one stream and on two and sets
+ * the plan's split batch (pat_plan_set_split) to `batch` if two are at least
+ * 2 % faster, else to 0; it records shapes and split in the JSON file
+ * cache_path under a key made of the geometry, the batch and the device name.
+ * When that key is already in the file the stored shapes (and split, if the
+ * entry has one) are applied without timing (an entry the shape checks now
+ * reject is tuned again and replaced).
  * pat_autotune_batch does the same for a batch's interpolation and spread
  * shapes.  cache_path may be NULL (no cache).  Both allocate temporary device
  * buffers and synchronise: tuning calls, not for loops or graph capture.

@@ -26,6 +26,7 @@ from ._lib import (PatError, PAT_ERR_WORKSPACE, PAT_NOALLOC_SCRATCH_BYTES,  # no
                    pat_stream_copy,
                    pat_tv_grad, pat_pgd_update, pat_residual, pat_plan_derive, pat_bessel_jn_table,
                    pat_profile_enable, pat_profile_read, pat_launch, pat_plan_get_launch, pat_plan_set_launch,
+                   pat_plan_set_split, pat_plan_get_split,
                    pat_batch_create, pat_batch_destroy, pat_batch_workspace_size, pat_batch_forward,
                    pat_batch_adjoint, pat_batch_get_launch, pat_batch_set_launch, pat_autotune_plan,
                    pat_autotune_batch, pat_pd_dual_data, pat_pd_dual_tv, pat_pd_primal, pat_pd_change,
@@ -177,6 +178,16 @@ class PatPlan:
                 raise KeyError(k)
             setattr(c, k, int(v))
         pat_plan_set_launch(self.handle, c)
+
+    @property
+    def split(self) -> int:
+        """Smallest batch whose calls run as two half-batches on two streams (0: never)."""
+        return pat_plan_get_split(self.handle)
+
+    def set_split(self, min_batch: int):
+        """Calls of at least `min_batch` instances run half the batch on a second
+        stream of the plan (bitwise the same outputs); 0 turns it off."""
+        pat_plan_set_split(self.handle, min_batch)
 
     def autotune(self, batch: int | None = None, cache_path: str | None = None) -> dict:
         """Time candidate tile shapes at `batch` instances (default max_batch) and keep

@@ -87,6 +87,8 @@ def load():
         "pat_status_string": (ctypes.c_char_p, [ci]),
         "pat_plan_get_launch": (ci, [vp, P(pat_launch)]),
         "pat_plan_set_launch": (ci, [vp, P(pat_launch)]),
+        "pat_plan_set_split": (ci, [vp, ci]),
+        "pat_plan_get_split": (ci, [vp, P(ci)]),
         "pat_batch_create": (ci, [P(vp), ci, P(vp)]),
         "pat_batch_destroy": (None, [vp]),
         "pat_batch_workspace_size": (sz, [vp]),
@@ -214,6 +216,16 @@ def pat_plan_get_launch(plan) -> pat_launch:
 
 def pat_plan_set_launch(plan, cfg: pat_launch) -> None:
     _check(load().pat_plan_set_launch(plan, ctypes.byref(cfg)), "pat_plan_set_launch")
+
+
+def pat_plan_set_split(plan, min_batch: int) -> None:
+    _check(load().pat_plan_set_split(plan, int(min_batch)), "pat_plan_set_split")
+
+
+def pat_plan_get_split(plan) -> int:
+    v = ctypes.c_int()
+    _check(load().pat_plan_get_split(plan, ctypes.byref(v)), "pat_plan_get_split")
+    return v.value
 
 
 def pat_batch_create(plans) -> int:

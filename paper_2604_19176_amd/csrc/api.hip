@@ -110,12 +110,10 @@ static int validate(const pat_plan* p, const void* in, const void* out, int batc
     return PAT_OK;
 }
 
-extern "C" int pat_forward(const pat_plan* p, const float* f, float* g, int batch, void* ws, size_t ws_bytes,
-                           void* stream)
+// The forward's launches for `batch` instances on stream st (arguments checked)
+static int forward_run(const pat_plan* p, const float* f, float* g, int batch, void* ws, hipStream_t st)
 {
-    int rc = validate(p, f, g, batch, ws, ws_bytes);
-    if (rc != PAT_OK) return rc;
-    hipStream_t st = (hipStream_t)stream;
+    int rc = PAT_OK;
     const PlanDev& d = p->dev;
     const LaunchCfg& c = p->cfg;
     const InstPtrs wsp{(char*)ws, p->ws.bytes};
@@ -168,12 +166,10 @@ extern "C" int pat_forward(const pat_plan* p, const float* f, float* g, int batc
     return PAT_OK;
 }
 
-extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batch, void* ws, size_t ws_bytes,
-                           void* stream)
+// The adjoint's launches for `batch` instances on stream st (arguments checked)
+static int adjoint_run(const pat_plan* p, const float* g, float* f, int batch, void* ws, hipStream_t st)
 {
-    int rc = validate(p, g, f, batch, ws, ws_bytes);
-    if (rc != PAT_OK) return rc;
-    hipStream_t st = (hipStream_t)stream;
+    int rc = PAT_OK;
     const PlanDev& d = p->dev;
     const LaunchCfg& c = p->cfg;
     const InstPtrs wsp{(char*)ws, p->ws.bytes};
@@ -223,6 +219,75 @@ extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batc
                        d, p->ws, wsp, f, c.col_np, d.D);
     if ((rc = check_launch())) return rc;
     prof_mark(p, 1, 5 + qa, st);
+    return PAT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Two-stream calls.  A call of at least p->split_min instances (and not under
+// per-kernel timing, whose events time one stream's launches) runs instances
+// [0, h) on the caller's stream and [h, batch) on the plan's side stream,
+// h = batch / 2: the side stream waits for an event recorded on the caller's
+// stream, and the caller's stream waits for one recorded on the side stream
+// after its launches, so the call is ordered on the caller's stream as a
+// one-stream call is, and a graph captured from the caller's stream holds both
+// halves.  Each instance is computed by the same kernels with the same tiles
+// whichever half it is in, so the results are bitwise those of one stream.
+// ---------------------------------------------------------------------------
+template <class Run>
+static int split_run(const pat_plan* p, int batch, hipStream_t st, size_t in_each, size_t out_each, const float* in,
+                     float* out, void* ws, Run run)
+{
+    if (p->prof || p->split_min < 2 || batch < p->split_min || !p->side) return run(in, out, batch, ws, st);
+    const int h = batch / 2;
+    std::lock_guard<std::mutex> lk(*p->split_mu);
+    if (hipEventRecord(p->ev_fork, st) != hipSuccess || hipStreamWaitEvent(p->side, p->ev_fork, 0) != hipSuccess)
+        return PAT_ERR_HIP;
+    int rc = run(in + (size_t)h * in_each, out + (size_t)h * out_each, batch - h,
+                 (char*)ws + (size_t)h * p->ws.bytes, p->side);
+    if (rc == PAT_OK) rc = run(in, out, h, ws, st);
+    // the join is enqueued whatever the halves returned: the side stream
+    // never stays forked from the caller's (nor out of a capture)
+    const bool joined = hipEventRecord(p->ev_join, p->side) == hipSuccess &&
+                        hipStreamWaitEvent(st, p->ev_join, 0) == hipSuccess;
+    if (rc == PAT_OK && !joined) rc = PAT_ERR_HIP;
+    return rc;
+}
+
+extern "C" int pat_forward(const pat_plan* p, const float* f, float* g, int batch, void* ws, size_t ws_bytes,
+                           void* stream)
+{
+    const int rc = validate(p, f, g, batch, ws, ws_bytes);
+    if (rc != PAT_OK) return rc;
+    const PlanDev& d = p->dev;
+    return split_run(p, batch, (hipStream_t)stream, (size_t)d.N * d.N, (size_t)d.D * d.T, f, g, ws,
+                     [&](const float* fi, float* go, int nb, void* wsi, hipStream_t s) {
+                         return forward_run(p, fi, go, nb, wsi, s);
+                     });
+}
+
+extern "C" int pat_adjoint(const pat_plan* p, const float* g, float* f, int batch, void* ws, size_t ws_bytes,
+                           void* stream)
+{
+    const int rc = validate(p, g, f, batch, ws, ws_bytes);
+    if (rc != PAT_OK) return rc;
+    const PlanDev& d = p->dev;
+    return split_run(p, batch, (hipStream_t)stream, (size_t)d.D * d.T, (size_t)d.N * d.N, g, f, ws,
+                     [&](const float* gi, float* fo, int nb, void* wsi, hipStream_t s) {
+                         return adjoint_run(p, gi, fo, nb, wsi, s);
+                     });
+}
+
+extern "C" int pat_plan_set_split(pat_plan* p, int min_batch)
+{
+    if (!p || min_batch < 0) return PAT_ERR_ARG;
+    p->split_min = min_batch;
+    return PAT_OK;
+}
+
+extern "C" int pat_plan_get_split(const pat_plan* p, int* min_batch)
+{
+    if (!p || !min_batch) return PAT_ERR_ARG;
+    *min_batch = p->split_min;
     return PAT_OK;
 }
 

@@ -8,6 +8,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <vector>
 
 #include "../../include/pat.h"
@@ -20,6 +21,12 @@ constexpr int kEsWidth = 8;
 constexpr double kEsBeta = 2.30 * kEsWidth;
 
 constexpr int kMaxStages = 16;
+
+// Default for pat_plan_set_split: calls of at least this many instances run
+// as two half-batches on two streams, so that each half's kernels fill the
+// other's partly occupied last waves (below it the fork and join cost more
+// than that gains at 256^2; the autotuner measures it per plan and batch).
+constexpr int kSplitMinBatch = 64;
 
 // One complex FFT length n = 2^a 3^b: Stockham passes of radix 2, 3, 4, 6, 8, 9 or 16.
 struct FftDev {
@@ -310,6 +317,14 @@ struct pat_plan {
     int prof;
     hipEvent_t ev[2][8];
     int ev_count[2];
+    // two-stream calls (pat_plan_set_split): calls of at least split_min
+    // instances run their second half on `side`, forked from and joined to the
+    // caller's stream by ev_fork / ev_join; split_mu keeps one call's
+    // fork-launch-join sequence together when several host threads share the plan
+    int split_min;
+    hipStream_t side;
+    hipEvent_t ev_fork, ev_join;
+    std::mutex* split_mu;
 };
 
 namespace pat {

@@ -1092,6 +1092,16 @@ extern "C" int pat_plan_create(const pat_plan_desc* desc, pat_plan** out)
     p->dlam = dv.dlam;
     p->kappa = dv.kappa;
     layout_workspace(p);
+    // the second stream of two-stream calls (default priority, no implicit
+    // synchronisation with the null stream: the calls order it by events)
+    p->split_min = kSplitMinBatch;
+    p->split_mu = new (std::nothrow) std::mutex;
+    if (!p->split_mu || hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess) {
+        pat_plan_destroy(p);
+        return PAT_ERR_HIP;
+    }
     *out = p;
     return PAT_OK;
 }
@@ -1123,13 +1133,18 @@ extern "C" void pat_plan_destroy(pat_plan* p)
 {
     if (!p) return;
     (void)pat_profile_enable(p, 0);
-    if (p->table_mem) {
-        int cur = 0;
-        if (hipGetDevice(&cur) != hipSuccess) cur = p->device;
-        (void)hipSetDevice(p->device);
-        (void)hipFree(p->table_mem);
-        (void)hipSetDevice(cur);
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) cur = p->device;
+    (void)hipSetDevice(p->device);
+    if (p->side) {  // work still queued on it finishes first
+        (void)hipStreamSynchronize(p->side);
+        (void)hipStreamDestroy(p->side);
     }
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+    if (p->table_mem) (void)hipFree(p->table_mem);
+    (void)hipSetDevice(cur);
+    delete p->split_mu;
     std::free(p->det_theta);
     delete p;
 }

@@ -4,8 +4,10 @@
 // kernels, so one timed forward + adjoint per round measures a candidate of
 // every stage at once: round r sets the r-th candidate of each stage's list
 // (when it fits the LDS/thread limits), and each stage keeps the candidate with
-// its smallest kernel time.  Results are cached in a small JSON file, one entry
-// per geometry / batch / device.
+// its smallest kernel time.  Then whole calls at the tuned shapes are timed
+// on one stream and on two (pat_plan_set_split), and two are kept if faster.
+// Results are cached in a small JSON file, one entry per geometry / batch /
+// device.
 #include "pat_internal.hpp"
 
 #include <algorithm>
@@ -150,7 +152,9 @@ int cache_read(const char* path, std::string& text)
     return 1;
 }
 
-bool cache_lookup(const std::string& text, const std::string& key, pat_launch& c)
+// An entry's fields; `split` (the two-stream batch, pat_plan_set_split) is
+// read when the entry has it and left unchanged otherwise.
+bool cache_lookup(const std::string& text, const std::string& key, pat_launch& c, int* split = nullptr)
 {
     const std::string pat = "\"" + key + "\": {";
     const size_t at = text.find(pat);
@@ -164,10 +168,12 @@ bool cache_lookup(const std::string& text, const std::string& key, pat_launch& c
         if (q == std::string::npos) return false;
         if (std::sscanf(body.c_str() + q + f.size(), "%d", field_ptr(c, i)) != 1) return false;
     }
+    const size_t q = body.find("\"split\": ");
+    if (split && q != std::string::npos && std::sscanf(body.c_str() + q + 9, "%d", split) != 1) return false;
     return true;
 }
 
-bool cache_store(const char* path, const std::string& key, const pat_launch& c0)
+bool cache_store(const char* path, const std::string& key, const pat_launch& c0, int split = -1)
 {
     pat_launch c = c0;
     std::string text;
@@ -176,6 +182,7 @@ bool cache_store(const char* path, const std::string& key, const pat_launch& c0)
     int o = std::snprintf(entry, sizeof entry, "\"%s\": {", key.c_str());
     for (int i = 0; i < kNumFields; ++i)
         o += std::snprintf(entry + o, sizeof entry - o, "%s\"%s\": %d", i ? ", " : "", kFields[i], *field_ptr(c, i));
+    if (split >= 0) o += std::snprintf(entry + o, sizeof entry - o, ", \"split\": %d", split);
     std::snprintf(entry + o, sizeof entry - o, "}");
     const std::string pat = "\"" + key + "\": {";
     const size_t at = text.find(pat);
@@ -214,6 +221,41 @@ struct DevBufs {
     }
 };
 
+// Whole forward + adjoint calls at `batch`, one stream (t1) and two (t2):
+// the best of kSplitRounds alternating rounds of kSplitReps call pairs each,
+// in milliseconds per pair.  Leaves the plan's split setting as it found it.
+constexpr int kSplitRounds = 3, kSplitReps = 5;
+constexpr float kSplitGain = 0.98f;  // two streams kept only if at least 2 % faster
+
+int time_split(pat_plan* p, float* f, float* g, void* ws, size_t wsb, int batch, float& t1, float& t2)
+{
+    const int keep = p->split_min;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = PAT_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = PAT_ERR_HIP;
+    t1 = t2 = 3.0e38f;
+    for (int r = 0; r < kSplitRounds && rc == PAT_OK; ++r) {
+        for (int mode = 0; mode < 2 && rc == PAT_OK; ++mode) {
+            p->split_min = mode ? 2 : 0;
+            for (int k = -1; k < kSplitReps && rc == PAT_OK; ++k) {  // k = -1: warm-up
+                if (k == 0 && hipEventRecord(e0, nullptr) != hipSuccess) rc = PAT_ERR_HIP;
+                if (rc == PAT_OK) rc = pat_forward(p, f, g, batch, ws, wsb, nullptr);
+                if (rc == PAT_OK) rc = pat_adjoint(p, g, f, batch, ws, wsb, nullptr);
+            }
+            float ms = 0.f;
+            if (rc == PAT_OK && (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = PAT_ERR_HIP;
+            float& t = mode ? t2 : t1;
+            if (rc == PAT_OK) t = std::min(t, ms / kSplitReps);
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    p->split_min = keep;
+    return rc;
+}
+
 }  // namespace
 
 extern "C" int pat_autotune_plan(pat_plan* p, int batch, const char* cache_path)
@@ -228,7 +270,11 @@ extern "C" int pat_autotune_plan(pat_plan* p, int batch, const char* cache_path)
         if (rc < 0) return PAT_ERR_ARG;
         pat_launch c = def;
         // an entry the library no longer accepts (older shape rules) is re-tuned and replaced
-        if (rc > 0 && cache_lookup(text, key, c) && pat_plan_set_launch(p, &c) == PAT_OK) return PAT_OK;
+        int split = p->split_min;
+        if (rc > 0 && cache_lookup(text, key, c, &split) && pat_plan_set_launch(p, &c) == PAT_OK) {
+            p->split_min = split;
+            return PAT_OK;
+        }
     }
     const pat_plan_desc& dsc = p->desc;
     DevBufs bufs;
@@ -293,7 +339,12 @@ extern "C" int pat_autotune_plan(pat_plan* p, int batch, const char* cache_path)
         return rc;
     }
     if ((rc = pat_plan_set_launch(p, &best)) != PAT_OK) return rc;
-    if (cache_path && !cache_store(cache_path, key, best)) return PAT_ERR_ARG;
+    if (batch >= 2 && !p->prof) {  // two-stream calls at this batch: kept if faster
+        float t1 = 0.f, t2 = 0.f;
+        if ((rc = time_split(p, f, g, ws, wsb, batch, t1, t2)) != PAT_OK) return rc;
+        p->split_min = t2 < kSplitGain * t1 ? batch : 0;
+    }
+    if (cache_path && !cache_store(cache_path, key, best, p->split_min)) return PAT_ERR_ARG;
     return PAT_OK;
 }
 

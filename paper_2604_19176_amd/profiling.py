@@ -80,10 +80,19 @@ def stats_table(trace_csv, stats_csv=None, min_dispatches=5):
     return "\n".join(lines)
 
 
+def _main_grid(counts):
+    """The largest launch grid with at least three dispatches ({grid: count}):
+    the full-batch launches of bench.py's per-kernel timing, which run on one
+    stream (its timed steps may run as two half-batches with half the grid,
+    and its single-instance calls have smaller grids; with a cached tuning no
+    candidate shapes run)."""
+    many = [g for g, n in counts.items() if n >= 3]
+    return max(many) if many else max(counts)
+
+
 def _counter(path, kernel):
-    """Mean counter value over the dispatches of `kernel` at its most frequent
-    grid among the grids of at least half the largest one (the timed batched
-    launches, not the single-instance or untuned calls)."""
+    """Mean counter value over the dispatches of `kernel` at its main grid
+    (_main_grid)."""
     vals, calib = [], []
     for r in _rows(path):
         name = r["Kernel_Name"]
@@ -94,12 +103,10 @@ def _counter(path, kernel):
             calib.append(v)
     if not vals:
         raise SystemExit("kernel %s not found in %s" % (kernel, path))
-    gmax = max(g for g, _ in vals)
     count = defaultdict(int)
     for g, _ in vals:
-        if 2 * g >= gmax:
-            count[g] += 1
-    gsel = max(count, key=lambda g: (count[g], g))
+        count[g] += 1
+    gsel = _main_grid(count)
     kv = [v for g, v in vals if g == gsel]
     return sum(kv) / len(kv), (max(calib) if calib else None), len(kv)
 
@@ -138,12 +145,8 @@ def read_bytes_by_size(path):
 
 
 def _select(by_grid):
-    """The values at the most frequent grid among those of at least half the
-    largest grid (as _counter)."""
-    gmax = max(g for g in by_grid)
-    cand = {g: v for g, v in by_grid.items() if 2 * g >= gmax}
-    g = max(cand, key=lambda g: (len(cand[g]), g))
-    return cand[g]
+    """The values at the main grid (as _counter)."""
+    return by_grid[_main_grid({g: len(v) for g, v in by_grid.items()})]
 
 
 def traffic(fetch_csv, write_csv, kernel, calib_bytes, rdreq=None):
@@ -199,8 +202,7 @@ def counter_means(path, kernels):
         if k not in by:
             continue
         grids = {g: len({dsp for dsp, _, _ in v}) for g, v in by[k].items()}
-        gmax = max(grids)
-        g = max((g for g in grids if 2 * g >= gmax), key=lambda g: (grids[g], g))
+        g = _main_grid(grids)
         acc = defaultdict(float)
         for dsp, c, v in by[k][g]:
             acc[c] += v

@@ -251,10 +251,13 @@ def test_autotune_plan_writes_and_reuses_cache(torch_dev, tmp_path):
     assert len(entries) == 1
     (key, stored), = entries.items()
     assert "n=64" in key and "batch=4" in key
-    assert stored == chosen
+    # the shapes, and the two-stream batch the tuner timed (4: two streams won, 0: one)
+    split = stored.pop("split")
+    assert stored == chosen and split == plan.split and split in (0, 4)
     assert torch.equal(plan.forward(f), g0) and torch.equal(plan.adjoint(d), a0)
     plan2 = pat.PatPlan(geom, max_batch=4)
     assert plan2.autotune(batch=4, cache_path=cache) == chosen       # from the cache
+    assert plan2.split == split
     plan2.autotune(batch=1, cache_path=cache)                         # a second key
     assert len(json.load(open(cache))) == 2
     # an entry the shape checks now reject (another spread tile height) is tuned again and replaced
@@ -264,7 +267,8 @@ def test_autotune_plan_writes_and_reuses_cache(torch_dev, tmp_path):
         json.dump(stale, fh)
     plan3 = pat.PatPlan(geom, max_batch=4)
     again = plan3.autotune(batch=4, cache_path=cache)
-    assert again["spr_th"] == 8 and json.load(open(cache))[key] == again
+    renewed = json.load(open(cache))[key]
+    assert again["spr_th"] == 8 and renewed.pop("split") == plan3.split and renewed == again
     assert torch.equal(plan3.forward(f), g0) and torch.equal(plan3.adjoint(d), a0)
     plan.close()
     plan2.close()
