@@ -331,7 +331,7 @@ int  pat_batch_set_launch(pat_batch* batch, const pat_launch* cfg);
  * each stage's shape by its own measured kernel time, applies the fastest,
  * then times whole forward + adjoint calls on one stream and on two and sets
  * the plan's split batch (pat_plan_set_split) to `batch` if two are at least
- * 2 % faster, else to 0; it records shapes and split in the JSON file
+ * 1 % faster, else to 0; it records shapes and split in the JSON file
  * cache_path under a key made of the geometry, the batch and the device name.
  * When that key is already in the file the stored shapes (and split, if the
  * entry has one) are applied without timing (an entry the shape checks now

@@ -224,8 +224,8 @@ struct DevBufs {
 // Whole forward + adjoint calls at `batch`, one stream (t1) and two (t2):
 // the best of kSplitRounds alternating rounds of kSplitReps call pairs each,
 // in milliseconds per pair.  Leaves the plan's split setting as it found it.
-constexpr int kSplitRounds = 3, kSplitReps = 5;
-constexpr float kSplitGain = 0.98f;  // two streams kept only if at least 2 % faster
+constexpr int kSplitRounds = 4, kSplitReps = 8;
+constexpr float kSplitGain = 0.99f;  // two streams kept only if at least 1 % faster
 
 int time_split(pat_plan* p, float* f, float* g, void* ws, size_t wsb, int batch, float& t1, float& t2)
 {
