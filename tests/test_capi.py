@@ -199,6 +199,10 @@ def test_batch_and_tuner_entry_points_reject_null_arguments(patlib):
     cfg = patlib.pat_launch()
     assert lib.pat_plan_get_launch(None, ctypes.byref(cfg)) == -1
     assert lib.pat_plan_set_launch(None, ctypes.byref(cfg)) == -1
+    split = ctypes.c_int(-7)
+    assert lib.pat_plan_set_split(None, 2) == -1
+    assert lib.pat_plan_get_split(None, ctypes.byref(split)) == -1
+    assert split.value == -7
     out = ctypes.c_void_p()
     assert lib.pat_batch_create(None, 1, ctypes.byref(out)) == -1
     arr = (ctypes.c_void_p * 2)(None, None)
