@@ -58,3 +58,24 @@ def test_forward_noalloc_rejects_oversized_batch(torch_dev):
         pat.pat_forward_noalloc(plan.handle, f.data_ptr(), g.data_ptr(), B, _stream(torch))
     assert e.value.status == pat.PAT_ERR_WORKSPACE
     plan.close()
+
+
+def test_forward_noalloc_two_streams(torch_dev):
+    """A two-stream call on the library's array: its halves use disjoint
+    instance slices of it, and the output is bitwise the one-stream call's."""
+    torch = torch_dev
+    import paper_2604_19176_amd as pat
+    geom = config_geometry(2)
+    B = 6
+    print("noalloc two-stream case: N=%d batch %d" % (geom.n, B), flush=True)
+    f = torch.tensor(np.stack([make_phantom(geom.n, 20, 3, 4, 2300 + b) for b in range(B)]),
+                     dtype=torch.float32, device="cuda")
+    plan = pat.PatPlan(geom, max_batch=B)
+    plan.set_split(0)
+    ref = plan.forward(f).clone()
+    plan.set_split(2)
+    out = torch.full_like(ref, float("nan"))
+    pat.pat_forward_noalloc(plan.handle, f.data_ptr(), out.data_ptr(), B, _stream(torch))
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    plan.close()
