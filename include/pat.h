@@ -329,7 +329,8 @@ int  pat_batch_set_launch(pat_batch* batch, const pat_launch* cfg);
 /* Autotuner.  pat_autotune_plan times candidate launch shapes of `plan` at
  * `batch` instances (1 <= batch <= max_batch) on the null stream, choosing
  * each stage's shape by its own measured kernel time, applies the fastest,
- * then times whole forward + adjoint calls on one stream and on two and sets
+ * then times whole forward + adjoint calls on one stream and on two (each
+ * captured as a HIP graph on a stream of its own and replayed) and sets
  * the plan's split batch (pat_plan_set_split) to `batch` if two are at least
  * 1 % faster, else to 0; it records shapes and split in the JSON file
  * cache_path under a key made of the geometry, the batch and the device name.

@@ -222,36 +222,60 @@ struct DevBufs {
 };
 
 // Whole forward + adjoint calls at `batch`, one stream (t1) and two (t2):
-// the best of kSplitRounds alternating rounds of kSplitReps call pairs each,
-// in milliseconds per pair.  Leaves the plan's split setting as it found it.
+// each way, kSplitReps call pairs are captured into a HIP graph on a stream of
+// the tuner (so the host's launch rate does not enter), and the graph is
+// replayed in kSplitRounds alternating rounds; the best round, in
+// milliseconds per pair.  Leaves the plan's split setting as it found it.
 constexpr int kSplitRounds = 4, kSplitReps = 8;
 constexpr float kSplitGain = 0.99f;  // two streams kept only if at least 1 % faster
 
 int time_split(pat_plan* p, float* f, float* g, void* ws, size_t wsb, int batch, float& t1, float& t2)
 {
     const int keep = p->split_min;
+    hipStream_t cs = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipGraph_t gr[2] = {nullptr, nullptr};
+    hipGraphExec_t ex[2] = {nullptr, nullptr};
     int rc = PAT_OK;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = PAT_ERR_HIP;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess)
+        rc = PAT_ERR_HIP;
+    for (int mode = 0; mode < 2 && rc == PAT_OK; ++mode) {
+        p->split_min = mode ? 2 : 0;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            rc = PAT_ERR_HIP;
+            break;
+        }
+        for (int k = 0; k < kSplitReps && rc == PAT_OK; ++k) {
+            rc = pat_forward(p, f, g, batch, ws, wsb, cs);
+            if (rc == PAT_OK) rc = pat_adjoint(p, g, f, batch, ws, wsb, cs);
+        }
+        // the capture is ended whatever the calls returned
+        if (hipStreamEndCapture(cs, &gr[mode]) != hipSuccess && rc == PAT_OK) rc = PAT_ERR_HIP;
+        if (rc == PAT_OK && (hipGraphInstantiate(&ex[mode], gr[mode], nullptr, nullptr, 0) != hipSuccess ||
+                             hipGraphLaunch(ex[mode], cs) != hipSuccess))  // warm-up
+            rc = PAT_ERR_HIP;
+    }
     t1 = t2 = 3.0e38f;
     for (int r = 0; r < kSplitRounds && rc == PAT_OK; ++r) {
         for (int mode = 0; mode < 2 && rc == PAT_OK; ++mode) {
-            p->split_min = mode ? 2 : 0;
-            for (int k = -1; k < kSplitReps && rc == PAT_OK; ++k) {  // k = -1: warm-up
-                if (k == 0 && hipEventRecord(e0, nullptr) != hipSuccess) rc = PAT_ERR_HIP;
-                if (rc == PAT_OK) rc = pat_forward(p, f, g, batch, ws, wsb, nullptr);
-                if (rc == PAT_OK) rc = pat_adjoint(p, g, f, batch, ws, wsb, nullptr);
-            }
             float ms = 0.f;
-            if (rc == PAT_OK && (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            if (hipEventRecord(e0, cs) != hipSuccess || hipGraphLaunch(ex[mode], cs) != hipSuccess ||
+                hipEventRecord(e1, cs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
                 rc = PAT_ERR_HIP;
             float& t = mode ? t2 : t1;
             if (rc == PAT_OK) t = std::min(t, ms / kSplitReps);
         }
     }
+    if (cs) (void)hipStreamSynchronize(cs);
+    for (int mode = 0; mode < 2; ++mode) {
+        if (ex[mode]) (void)hipGraphExecDestroy(ex[mode]);
+        if (gr[mode]) (void)hipGraphDestroy(gr[mode]);
+    }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
+    if (cs) (void)hipStreamDestroy(cs);
     p->split_min = keep;
     return rc;
 }
