@@ -132,20 +132,27 @@ struct IdxF {
 // ---------------------------------------------------------------------------
 // The grid transforms (length Ng, `nseq` sequences at stride ld in LDS): with
 // a compile-time length (plans with grid_spec) sequence s is transformed by
-// threads s T .. s T + T - 1 (T = cfft_lanes(Ng)); else by the run-time plan.
+// threads s T .. s T + T - 1 (T = cfft_lanes(Ng), or twice that for `wide`
+// tiles of one sequence: the same butterflies in the same order on more
+// lanes); else by the run-time plan.
 // ---------------------------------------------------------------------------
+template <int NG, bool INV, int T>
+__device__ __forceinline__ void grid_cfft(const PlanDev& d, float2* x, int ld, int nseq)
+{
+    const int sq = threadIdx.x / T;
+    cfft<NG, INV, T>(x + (size_t)min(sq, nseq - 1) * ld, d.ctw + d.grid_ctw, threadIdx.x - sq * T, sq < nseq);
+}
+
 template <bool INV>
-__device__ __forceinline__ void grid_fft(const PlanDev& d, float2* x, int ld, int nseq, const float2* tb)
+__device__ __forceinline__ void grid_fft(const PlanDev& d, float2* x, int ld, int nseq, const float2* tb, bool wide)
 {
     if (d.grid_spec) {
         switch (d.Ng) {
 #define PAT_GRID_CASE(NG)                                                                        \
-    case NG: {                                                                                   \
-        constexpr int T = cfft_lanes(NG);                                                        \
-        const int sq = threadIdx.x / T;                                                          \
-        cfft<NG, INV>(x + (size_t)min(sq, nseq - 1) * ld, d.ctw + d.grid_ctw, threadIdx.x - sq * T, sq < nseq); \
-        break;                                                                                   \
-    }
+    case NG:                                                                                     \
+        if (wide) grid_cfft<NG, INV, 2 * cfft_lanes(NG)>(d, x, ld, nseq);                       \
+        else grid_cfft<NG, INV, cfft_lanes(NG)>(d, x, ld, nseq);                                 \
+        break;
             PAT_GRID_LENGTHS(PAT_GRID_CASE)
 #undef PAT_GRID_CASE
             default: break;
@@ -228,7 +235,7 @@ __device__ __forceinline__ void colpass_fwd_tile(const PlanDev& d, const WsLayou
         red[j0 + threadIdx.x] = sc * d.h2;
     }
     __syncthreads();
-    grid_fft<false>(d, sm, Ng, NP, tb);
+    grid_fft<false>(d, sm, Ng, NP, tb, NP == 1);
     fill_batched<4>(
         d.Hy * CT,
         [&](int e) {
@@ -275,7 +282,7 @@ __device__ __forceinline__ void rowpass_fwd_tile(const PlanDev& d, const WsLayou
         },
         [&](int, IdxVal iv) { sm[iv.i] = iv.v; });
     __syncthreads();
-    grid_fft<false>(d, sm, Ng, nr, tb);
+    grid_fft<false>(d, sm, Ng, nr, tb, RPB == 1);
     fill_batched<4>(
         nr * Ng, [&](int e) { return sm[e]; }, [&](int e, float2 v) { G[(size_t)r0 * Ng + e] = v; });
 }
@@ -1998,7 +2005,7 @@ __device__ __forceinline__ void rowpass_adj_tile(const PlanDev& d, const WsLayou
             [&](int c, float2 v) { dst[c] = v; });
     }
     __syncthreads();
-    grid_fft<true>(d, sm, Ng, nr, tb);
+    grid_fft<true>(d, sm, Ng, nr, tb, RPB == 1);
     const float rcpN = 1.0f / (float)N;
     fill_batched<4>(
         nr * N,
@@ -2055,7 +2062,7 @@ __device__ __forceinline__ void colpass_adj_tile(const PlanDev& d, const WsLayou
         },
         [&](int e, float2 v) { sm[e] = v; });
     __syncthreads();
-    grid_fft<true>(d, sm, Ng, NP, tb);
+    grid_fft<true>(d, sm, Ng, NP, tb, NP == 1);
     const float kt = d.kappa * d.h2 * *gsum_s;
     const float rcpCT = 1.0f / (float)CT;
     fill_batched<4>(

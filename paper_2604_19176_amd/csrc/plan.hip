@@ -485,9 +485,12 @@ int fixed_fft_for(long n, FftDev* out, std::vector<float2>& tw)
 int fft_workgroup_threads(int nseq, const FftDev& fd) { return fft_threads(nseq, fd); }
 
 // Threads of a 2D-FFT pass workgroup over `nseq` sequences of the plan's grid side
+// (compile-time lengths: a tile of one sequence gets twice the transform's
+// lanes, which shortens the single-instance chain; the kernels pass `wide`
+// to the transform when their tile has one sequence)
 int grid_threads(const pat_plan* p, int nseq)
 {
-    return p->dev.grid_spec ? nseq * cfft_lanes(p->dev.Ng) : fft_threads(nseq, p->h_fft_grid);
+    return p->dev.grid_spec ? (nseq == 1 ? 2 : nseq) * cfft_lanes(p->dev.Ng) : fft_threads(nseq, p->h_fft_grid);
 }
 
 // Dynamic LDS of the ring kernels: half-ring FFT buffer, synthesis buffers,
@@ -514,7 +517,7 @@ int apply_launch(pat_plan* p, const LaunchCfg& c)
     auto grid_ok = [&](int v) {
         if (!d.grid_spec) return fft_ok(v, sizeof(float2) * d.Ng, p->h_fft_grid, twb_bytes(p->h_fft_grid));
         return v >= 1 && v <= 16 && v * sizeof(float2) * d.Ng + twb_bytes(p->h_fft_grid) <= kLdsMax &&
-               v * cfft_lanes(d.Ng) <= 1024;
+               (v == 1 ? 2 : v) * cfft_lanes(d.Ng) <= 1024;
     };
     if (c.col_np < 1 || c.col_np > 16 || c.row_rpb < 1 || c.row_rpb > 16 || c.dct_dp < 1 || c.dct_dp > 16 ||
         c.ring_rt < 1 || c.ring_rt > 64 || !gather_shape_ok(c.gat_cb, c.gat_th, c.gat_ib) ||
