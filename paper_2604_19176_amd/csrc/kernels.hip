@@ -1918,21 +1918,10 @@ __device__ __forceinline__ void rowpass_adj_tile(const PlanDev& d, const WsLayou
     static_assert(kSpreadTh == 8, "the tail lookup below divides by shifting");
     const float2* Tl = (const float2*)(wb + L.tail);
     const float2* Sl = (const float2*)(wb + L.slab);
-    // split entries of row tiles qa .. qa + 3 (the rows' tiles and the ones
-    // before; RPB <= 16), two per 64-bit word so that a lane picks its row's
-    // entry with shifts (no indexed private array)
-    const int qa = (r0 >> 3) - 1;
-    unsigned long long sp01 = 0, sp23 = 0;
-#pragma unroll
-    for (int t = 0; t < kSpreadSplitTiles; ++t) {  // constant indices only
-        const unsigned long long e = d.spr_head[t];
-        const int i = t - qa;
-        sp01 |= i == 0 ? e : (i == 1 ? e << 32 : 0ull);
-        sp23 |= i == 2 ? e : (i == 3 ? e << 32 : 0ull);
-    }
-    auto split_of = [&](int q) {  // q in qa .. qa + 3: (log2 of its runs, first slab row)
-        const int i = q - qa;
-        const unsigned e = (unsigned)(((i & 2) ? sp23 : sp01) >> (32 * (i & 1)));
+    // a row tile's split entry (log2 of its runs, first slab row): q is
+    // uniform over the workgroup, so the entry is a scalar load
+    auto split_of = [&](int q) {
+        const unsigned e = d.spr_head[q];
         return make_int2((int)(e & 15u), (int)(e >> 4));
     };
     // row by row (the row's case is uniform): a whole tile's row plus, if any,

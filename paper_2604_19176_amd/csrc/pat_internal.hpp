@@ -113,8 +113,9 @@ struct PlanDev {
     int spr_rows;           // work rows: the sum over row tiles of their runs
     int slab_rows;          // rows of the slab region
     const int4* spr_row;    // [spr_rows] (first band, last band, first slab row or -1 if whole, row tile)
-    // row tiles t < kSpreadSplitTiles: (first slab row of run 0) << 4 | log2 S (0: whole)
-    unsigned spr_head[kSpreadSplitTiles];
+    // per row tile t (and zero for every t the adjoint row pass can name past
+    // the last): (first slab row of run 0) << 4 | log2 S, or 0 if swept whole
+    const unsigned* spr_head;
     // synthesis over detector angles theta_d = theta_0 + d dtheta
     int fold_P;             // P if dtheta = 2 pi s / P (P = 2^a3^b, gcd(s, P) = 1): fold k mod P, one FFT; else 0
     int fold_s;             // s: detector d is point s d of the P-point angular grid (s (D - 1) < P)

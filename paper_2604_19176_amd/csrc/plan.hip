@@ -633,17 +633,23 @@ extern "C" int pat_bessel_jn_table(int kmax, double x, double* out)
 
 // Spread work rows.  In band rb the lane of column c visits the points whose
 // footprint base column is c - 7 .. c (mod Ng); a row tile's longest lane,
-// summed over its bands, bounds its workgroup's time.  A row tile among the
-// first kSpreadSplitTiles whose longest lane exceeds kSpreadSplitFactor times
-// the median over the row tiles is split into the fewest runs S (2 or
-// kSpreadMaxRuns) that bring every run's longest lane under that limit, or
-// into kSpreadMaxRuns.  The last row tile, which writes the grid's final rows
-// itself, is never split.  Output: the work rows (first band, last band, first
-// slab row or -1, row tile), per row tile (S, first slab row), and the slab
-// rows in all.
+// summed over its bands, bounds its workgroup's time.  For batches: a row tile
+// among the first kSpreadSplitTiles whose longest lane exceeds
+// kSpreadSplitFactor times the median over the row tiles is split into the
+// fewest runs S (2 or kSpreadMaxRuns) that bring every run's longest lane
+// under that limit, or into kSpreadMaxRuns.  Plans for single instances
+// (max_batch 1), whose spread is one wave per tile and bound by each tile's
+// chain of bands, split every row tile whose longest lane exceeds
+// kSpreadSplitFactorSingle times the median: more, shorter work rows, at the
+// cost of the slab rows the adjoint row pass adds up.  The last row tile,
+// which writes the grid's final rows itself, is never split.  Output: the work
+// rows (first band, last band, first slab row or -1, row tile), per row tile
+// (S, first slab row), and the slab rows in all.  The split is a property of
+// the plan: every launch shape and batch size of a plan sums in its order.
 constexpr double kSpreadSplitFactor = 1.5;
+constexpr double kSpreadSplitFactorSingle = 0.5;
 
-static void spread_runs(const std::vector<int>& bptr, int NB, int Ng, std::vector<int4>& rows,
+static void spread_runs(const std::vector<int>& bptr, int NB, int Ng, bool single, std::vector<int4>& rows,
                         std::vector<int2>& split, int& slab_rows)
 {
     const int nrt = spread_row_tiles(NB);
@@ -674,14 +680,14 @@ static void spread_runs(const std::vector<int>& bptr, int NB, int Ng, std::vecto
     for (int t = 0; t < nrt; ++t) whole[t] = longest(t, 1);
     std::vector<int> srt(whole);
     std::sort(srt.begin(), srt.end());
-    const double limit = kSpreadSplitFactor * srt[srt.size() / 2];
+    const double limit = (single ? kSpreadSplitFactorSingle : kSpreadSplitFactor) * srt[srt.size() / 2];
     rows.clear();
     split.assign(nrt, make_int2(1, -1));
     slab_rows = 0;
     for (int t = 0; t < nrt; ++t) {
         const int b0 = t * kSpreadTh, b1 = std::min(NB, b0 + kSpreadTh) - 1;
         int S = 1;
-        if (t + 1 < nrt && t < kSpreadSplitTiles)
+        if (t + 1 < nrt && (single || t < kSpreadSplitTiles))
             while (S < kSpreadMaxRuns && longest(t, S) > limit) S *= 2;
         if (S == 1) {
             rows.push_back(make_int4(b0, b1, -1, t));
@@ -942,13 +948,15 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     }
     std::vector<int4> sprRow;
     std::vector<int2> sprSplit;
-    spread_runs(bptr, NB, Ng, sprRow, sprSplit, d.slab_rows);
+    spread_runs(bptr, NB, Ng, desc->max_batch == 1, sprRow, sprSplit, d.slab_rows);
     d.spr_rows = (int)sprRow.size();
-    for (int t = 0; t < kSpreadSplitTiles; ++t) {
-        const int2 e = t < (int)sprSplit.size() ? sprSplit[t] : make_int2(1, -1);
+    // the adjoint row pass looks up row tiles r / 8 and r / 8 - 1 of its grid rows r < Hy
+    std::vector<unsigned> sprHead((size_t)(d.Hy + 7) / 8 + 1, 0u);
+    for (size_t t = 0; t < sprSplit.size() && t < sprHead.size(); ++t) {
+        const int2 e = sprSplit[t];
         int lg = 0;
         while ((1 << lg) < e.x) ++lg;
-        d.spr_head[t] = e.x > 1 ? ((unsigned)e.y << 4) | (unsigned)lg : 0u;
+        sprHead[t] = e.x > 1 ? ((unsigned)e.y << 4) | (unsigned)lg : 0u;
     }
 
     // --- synthesis over detector angles --------------------------------------
@@ -1022,6 +1030,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     size_t o_ffts = tb.add(ffts.descs), o_tw = tb.add(ffts.tw);
     size_t o_rctw = tb.add(ringCtw), o_ruw = tb.add(ringUw), o_ctw = tb.add(ctw);
     size_t o_sprow = tb.add(sprRow);
+    size_t o_sphead = tb.add(sprHead);
     // store offsets in the pointer fields; relocated after the upload
     auto off = [](size_t o) { return (const void*)(uintptr_t)o; };
     d.deap = (const float*)off(o_deap);
@@ -1045,6 +1054,7 @@ static int build_tables(const pat_plan_desc* desc, const Derived& dv, pat_plan* 
     d.ring_uw = (const int*)off(o_ruw);
     d.ctw = (const float2*)off(o_ctw);
     d.spr_row = (const int4*)off(o_sprow);
+    d.spr_head = (const unsigned*)off(o_sphead);
     return PAT_OK;
 }
 
@@ -1077,7 +1087,7 @@ extern "C" int pat_plan_create(const pat_plan_desc* desc, pat_plan** out)
     rel(d.deap); rel(d.mask_rows); rel(d.ring_off); rel(d.ring_K);
     rel(d.ring_fft); rel(d.ring_twn); rel(d.ring_joff); rel(d.coef); rel(d.band_of); rel(d.bpt_geo); rel(d.bpt_phase);
     rel(d.band_ptr); rel(d.czt_post); rel(d.czt_vhat); rel(d.syn_tab); rel(d.ffts); rel(d.tw);
-    rel(d.ring_ctw); rel(d.ring_uw); rel(d.ctw); rel(d.spr_row);
+    rel(d.ring_ctw); rel(d.ring_uw); rel(d.ctw); rel(d.spr_row); rel(d.spr_head);
     p->desc = *desc;
     if (desc->det_theta) {  // the plan keeps its own copy of the angles
         p->det_theta = (double*)std::malloc(sizeof(double) * (size_t)desc->n_det);
