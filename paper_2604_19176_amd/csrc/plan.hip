@@ -641,13 +641,15 @@ extern "C" int pat_bessel_jn_table(int kmax, double x, double* out)
 // (max_batch 1), whose spread is one wave per tile and bound by each tile's
 // chain of bands, split every row tile whose longest lane exceeds
 // kSpreadSplitFactorSingle times the median: more, shorter work rows, at the
-// cost of the slab rows the adjoint row pass adds up.  The last row tile,
+// cost of the slab rows the adjoint row pass adds up, unless those would
+// exceed kSpreadSlabCapSingle bytes per instance (then the batched rule).  The last row tile,
 // which writes the grid's final rows itself, is never split.  Output: the work
 // rows (first band, last band, first slab row or -1, row tile), per row tile
 // (S, first slab row), and the slab rows in all.  The split is a property of
 // the plan: every launch shape and batch size of a plan sums in its order.
 constexpr double kSpreadSplitFactor = 1.5;
 constexpr double kSpreadSplitFactorSingle = 0.5;
+constexpr size_t kSpreadSlabCapSingle = 32u << 20;  // slab bytes per instance of a single-instance plan
 
 static void spread_runs(const std::vector<int>& bptr, int NB, int Ng, bool single, std::vector<int4>& rows,
                         std::vector<int2>& split, int& slab_rows)
@@ -681,14 +683,29 @@ static void spread_runs(const std::vector<int>& bptr, int NB, int Ng, bool singl
     std::vector<int> srt(whole);
     std::sort(srt.begin(), srt.end());
     const double limit = (single ? kSpreadSplitFactorSingle : kSpreadSplitFactor) * srt[srt.size() / 2];
+    // runs per row tile
+    std::vector<int> runs(nrt, 1);
+    long used = 0;  // slab rows
+    for (int t = 0; t + 1 < nrt; ++t) {
+        if (!single && t >= kSpreadSplitTiles) break;
+        int S = 1;
+        while (S < kSpreadMaxRuns && longest(t, S) > limit) S *= 2;
+        runs[t] = S;
+        if (S > 1) used += (long)S * spread_run_rows(S);
+    }
+    // a single-instance plan whose slab would exceed kSpreadSlabCapSingle
+    // bytes per instance takes the batched rule instead (splitting only part
+    // of the tiles leaves the unsplit ones as the longest chains)
+    if (single && used * (long)((size_t)Ng * sizeof(float2)) > (long)kSpreadSlabCapSingle) {
+        spread_runs(bptr, NB, Ng, false, rows, split, slab_rows);
+        return;
+    }
     rows.clear();
     split.assign(nrt, make_int2(1, -1));
     slab_rows = 0;
     for (int t = 0; t < nrt; ++t) {
         const int b0 = t * kSpreadTh, b1 = std::min(NB, b0 + kSpreadTh) - 1;
-        int S = 1;
-        if (t + 1 < nrt && (single || t < kSpreadSplitTiles))
-            while (S < kSpreadMaxRuns && longest(t, S) > limit) S *= 2;
+        const int S = runs[t];
         if (S == 1) {
             rows.push_back(make_int4(b0, b1, -1, t));
             continue;
