@@ -648,7 +648,7 @@ extern "C" int pat_bessel_jn_table(int kmax, double x, double* out)
 // (S, first slab row), and the slab rows in all.  The split is a property of
 // the plan: every launch shape and batch size of a plan sums in its order.
 constexpr double kSpreadSplitFactor = 1.5;
-constexpr double kSpreadSplitFactorSingle = 0.5;
+constexpr double kSpreadSplitFactorSingle = 0.7;
 constexpr size_t kSpreadSlabCapSingle = 32u << 20;  // slab bytes per instance of a single-instance plan
 
 static void spread_runs(const std::vector<int>& bptr, int NB, int Ng, bool single, std::vector<int4>& rows,
