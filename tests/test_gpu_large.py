@@ -65,6 +65,9 @@ def test_1024_forward_gaussian_closed_form(torch_dev):
     blobs = _large_blobs()
     f = render_phantom(PhantomSpec(blobs=blobs, cutoff_r=10.0), geom.n)
     plan = pat.PatPlan(geom)
+    # a single-instance plan's spread split never takes its workspace past the
+    # no-allocation entry point's array
+    assert plan.workspace_bytes(1) <= pat.PAT_NOALLOC_SCRATCH_BYTES
     g = plan.forward(torch.tensor(f, dtype=torch.float32, device="cuda")).cpu().double().numpy()
     plan.close()
     C = ref.discrete_gaussian_data(geom, oracle.sizes(geom), blobs)
