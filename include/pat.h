@@ -65,7 +65,11 @@ typedef struct {
     double c;                 /* constant speed of sound > 0                                          */
     double lambda_oversample; /* sigma_t >= 1 (2.0); radial frequency step dlam = pi/(M c dt)         */
     int    em_correction;     /* 1: add the rank-1 endpoint term kappa*h^2*sum(m f) (default 1)       */
-    int    max_batch;         /* capacity of the batch dimension (>= 1); sizes pat_workspace_size     */
+    int    max_batch;         /* capacity of the batch dimension (>= 1); sizes pat_workspace_size.
+                                 1 also selects the single-instance work split of the adjoint's
+                                 spread (more, shorter work rows while their partial rows take at
+                                 most 32 MiB per instance), so plans that differ only here may
+                                 differ in the last bits of A* g                                  */
     const double* det_theta;  /* NULL: the uniform arc above.  Else D explicit detector angles [rad],
                                  any order and spacing (gaps, several arcs, sparse elements), in host
                                  memory read only during pat_plan_create / pat_plan_derive (the plan
